@@ -1,0 +1,254 @@
+/* bayeslsh.h -- C ABI of libbayeslsh.so, BayesLSH candidate verification on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Satuluri & Parthasarathy, "Bayesian Locality Sensitive
+ * Hashing for Fast Similarity Search":
+ *   - the problem statement and output guarantees (Section 1),
+ *   - Algorithm 1 (BayesLSH: prune, else estimate until concentrated) and
+ *     Algorithm 2 (BayesLSH-Lite: prune with at most h hashes, then exact
+ *     similarity) of Section 3,
+ *   - the Jaccard (minhash, Beta prior; Section 4.1) and cosine (sign random
+ *     projections, uniform prior on r; Section 4.2) instantiations,
+ *   - the precomputation of minimum matches and the cache of concentration
+ *     decisions (Section 4.3).
+ *
+ * Conventions shared by every call
+ *   - Pointers are DEVICE pointers unless their name ends in _host.  The
+ *     caller owns all input and output memory.
+ *   - Calls that take `stream` (a hipStream_t passed as void*, NULL = the
+ *     default stream) only enqueue work and return; bayeslsh_sync() waits and
+ *     reports errors the kernels raised.
+ *   - Every call returns a blsh_status.  Nothing is thrown or aborted across
+ *     the ABI; on failure bayeslsh_last_error() returns a thread-local message.
+ *   - Arguments are validated on the host before anything is enqueued; an
+ *     invalid call enqueues nothing and leaves outputs untouched.
+ *   - A context (blsh_ctx) belongs to one device.  Calls on one context from
+ *     several host threads must be serialised by the caller.  Calls on
+ *     different streams of one context may overlap on the device only if
+ *     they do not share output buffers; they share the context's workspace
+ *     only through per-call slices, so overlapping calls must use separate
+ *     contexts.
+ */
+#ifndef BAYESLSH_H
+#define BAYESLSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BAYESLSH_VERSION 1
+
+typedef enum {
+  BLSH_OK = 0,
+  BLSH_EINVAL = -1,      /* invalid argument (shape, range, null pointer, layout) */
+  BLSH_ENOMEM = -2,      /* device allocation failed or workspace too small */
+  BLSH_EDEVICE = -3,     /* a HIP runtime call failed */
+  BLSH_ETRUNCATED = -4,  /* the accepted list overflowed acc_capacity (n_accepted holds the true count) */
+  BLSH_EBADID = -5,      /* a candidate referenced an object id >= n_obj (code byte 0xFF for that candidate) */
+  BLSH_EAGAIN = 1        /* serving: request not finished yet */
+} blsh_status;
+
+/* Similarity measures (Section 4). */
+typedef enum { BLSH_JACCARD = 0, BLSH_COSINE = 1 } blsh_measure;
+
+/* Per-candidate decision, stored in bits 7..6 of the code byte; bits 5..0 hold
+ * the level j at which the decision was taken (n = (j+1) k hashes compared).
+ * Code 0xFF marks a candidate with an out-of-range object id. */
+typedef enum {
+  BLSH_PRUNED = 0,       /* Pr[S >= t | M(m,n)] < epsilon                      (Alg. 1/2) */
+  BLSH_ACCEPT_CONC = 1,  /* Pr[|S - S_hat| < delta | M(m,n)] >= 1 - gamma      (Alg. 1)   */
+  BLSH_ACCEPT_NMAX = 2,  /* undecided when the signature ran out (n = n_max)   (Alg. 1)   */
+  BLSH_LITE_EXACT = 3    /* survived h hashes; exact similarity computed        (Alg. 2)   */
+} blsh_decision;
+
+/* Signature layouts. */
+typedef enum {
+  BLSH_OBJECT_MAJOR = 0, /* row per object: minhash uint32[n_obj][n_hashes];
+                            SRP uint32[n_obj][n_hashes/32] packed bits          */
+  BLSH_WORD_MAJOR = 1    /* SRP only: uint32[n_hashes/32][n_obj]; word w of all
+                            objects is contiguous (level-major slabs)          */
+} blsh_layout;
+
+/* Candidate kinds (Alg. 1/2 input C). */
+typedef enum {
+  BLSH_PAIRS = 0,        /* candidate c = (x[c], y[c]), c in [0, n_pairs)                    */
+  BLSH_QUERY_LISTS = 1,  /* list l = (query[l], cand[offsets[l] .. offsets[l+1])); candidate
+                            index c = position in cand                                       */
+  BLSH_ALL_PAIRS = 2     /* all i < j over [0, all_n), row-major: c = i*all_n - i(i+1)/2 + j-i-1 */
+} blsh_cand_kind;
+
+/* Vector kinds for exact similarity (Alg. 2) and signature generation. */
+typedef enum {
+  BLSH_DENSE = 0,        /* float dense[n_obj][dim], row-major                       */
+  BLSH_CSR = 1,          /* float values + uint32 indices (sorted, unique per row)   */
+  BLSH_SETS = 2          /* uint32 indices only (sorted, unique per row): binary sets */
+} blsh_vec_kind;
+
+/* Prior (Section 4.1: Beta(alpha, beta) for Jaccard; Section 4.2: uniform on
+ * r in [0.5, 1] for cosine).  Jaccard: alpha, beta must be integers >= 1 in
+ * this version.  Cosine: must be {1, 1} (the uniform prior). */
+typedef struct { double alpha, beta; } blsh_prior;
+
+typedef struct {
+  blsh_measure measure;
+  blsh_layout layout;
+  const uint32_t *data;
+  int64_t n_obj;
+  int32_t n_hashes;      /* hashes stored per object (SRP: multiple of 32)            */
+  int32_t n_max;         /* hashes verification may use, 0 = n_hashes; multiple of k   */
+} blsh_sigs;
+
+typedef struct {
+  blsh_cand_kind kind;
+  const uint32_t *x, *y;         /* PAIRS                     */
+  int64_t n_pairs;
+  const uint32_t *query;         /* QUERY_LISTS: [n_lists]     */
+  const int64_t *offsets;        /* QUERY_LISTS: [n_lists + 1] */
+  const uint32_t *cand;          /* QUERY_LISTS: [offsets[n_lists]] */
+  int64_t n_lists;
+  int64_t n_cand;                /* QUERY_LISTS: offsets[n_lists] (host copy of the total) */
+  int64_t all_n;                 /* ALL_PAIRS                 */
+} blsh_candidates;
+
+typedef struct {
+  blsh_vec_kind kind;
+  int64_t n_obj;
+  int64_t dim;                   /* DENSE: columns; CSR/SETS: index bound (indices < dim) */
+  const float *dense;            /* DENSE                     */
+  const int64_t *offsets;        /* CSR/SETS: [n_obj + 1]      */
+  const uint32_t *indices;       /* CSR/SETS                   */
+  const float *values;           /* CSR                        */
+} blsh_vectors;
+
+/* Outputs of a verification call.  Every field except m_debug is required.
+ *   code[c]      decision << 6 | level, one byte per candidate (fully overwritten)
+ *   acc_idx/val  the output set O, compacted in unspecified order: candidate
+ *                index and S_hat (Alg. 1) or the exact similarity (Alg. 2), fp32
+ *   n_accepted   device int64: true size of O even when it exceeds acc_capacity
+ *   m_debug      optional uint16 per candidate: m when the decision was taken */
+typedef struct {
+  uint8_t *code;
+  uint64_t *acc_idx;
+  float *acc_val;
+  int64_t acc_capacity;
+  int64_t *n_accepted;
+  uint16_t *m_debug;
+} blsh_result;
+
+typedef struct blsh_ctx blsh_ctx;
+
+/* ---------------- context ---------------- */
+
+/* Create a context on HIP device `device`.  The context owns the posterior
+ * table cache (host and device copies) and a survivor workspace that grows on
+ * demand (the growth synchronises the device).  Returns BLSH_EDEVICE if the
+ * device is absent. */
+int bayeslsh_create(blsh_ctx **out, int device);
+void bayeslsh_destroy(blsh_ctx *ctx);
+
+/* Wait for `stream`, then return (and clear) the first error a kernel of this
+ * context raised since the last sync: BLSH_ETRUNCATED, BLSH_EBADID, BLSH_EINVAL
+ * (empty set in bayeslsh_minhash_sigs), or BLSH_OK. */
+int bayeslsh_sync(blsh_ctx *ctx, void *stream);
+
+/* Thread-local description of the last failure of any call on this thread. */
+const char *bayeslsh_last_error(void);
+int bayeslsh_version(void);
+
+/* Kernel timing: when enabled, every kernel launch of the context is bracketed
+ * by HIP events on its stream.  bayeslsh_profile_read waits for the recorded
+ * events and returns, for kernels whose name contains `name_substr`, the total
+ * elapsed milliseconds and the number of launches since the last reset. */
+int bayeslsh_profile_enable(blsh_ctx *ctx, int enable);
+int bayeslsh_profile_reset(blsh_ctx *ctx);
+int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_ms_host, int64_t *launches_host);
+
+/* ---------------- posterior tables (host, FP64) ---------------- */
+
+/* Build (or fetch from the context's cache) the decision table of one
+ * parameter set and copy it out.  For each level j (n = (j+1) k, j < n_levels):
+ *   min_matches_host[j]  smallest m with Pr[S >= t | M(m,n)] >= epsilon, or n+1
+ *                        (minMatches of Section 4.3)
+ *   accept_host[j*words + w], words = (k*n_levels + 1 + 31)/32: bit m%32 of word
+ *                        m/32 set iff m >= min_matches[j] and
+ *                        Pr[|S - S_hat| < delta | M(m,n)] >= 1 - gamma
+ *                        (the cache of concentration results of Section 4.3)
+ * Jaccard probabilities use the Beta-binomial closed form (integer alpha,
+ * beta); cosine ones use Gauss-Legendre quadrature over the angle theta with
+ * r = 1 - theta/pi.  lite != 0 skips the concentration bits.  Either output
+ * pointer may be NULL.  min_margin_host (optional) receives the smallest
+ * distance of an evaluated probability from its threshold.  Host-only: ctx may
+ * be NULL (no GPU needed; the table is then built without caching). */
+int bayeslsh_posterior_table(blsh_ctx *ctx, blsh_measure measure, double t, double epsilon, double delta,
+                             double gamma, blsh_prior prior, int32_t k, int32_t n_levels, int32_t lite,
+                             int32_t *min_matches_host, uint32_t *accept_host, double *min_margin_host);
+
+/* ---------------- signature generation (Section 4) ---------------- */
+
+/* Minhash (Section 4.1): sigs[i][h] = min over e in set i of (a[h] e + b[h]) mod (2^31 - 1).
+ * sets: kind BLSH_SETS (indices sorted or not); a[h] in [1, 2^31-1), b[h] in
+ * [0, 2^31-1) (device arrays of n_hashes).  Output object-major uint32
+ * [n_obj][n_hashes].  An empty set gets 0xFFFFFFFF everywhere and makes the
+ * next bayeslsh_sync return BLSH_EINVAL. */
+int bayeslsh_minhash_sigs(blsh_ctx *ctx, const blsh_vectors *sets, const uint32_t *a, const uint32_t *b,
+                          int32_t n_hashes, uint32_t *sigs_out, void *stream);
+
+/* Sign random projections (Section 4.2): bit h of object i is 1 iff r_h . x_i >= 0,
+ * packed LSB-first (hash h -> word h/32, bit h%32) in `layout`.
+ *   DENSE vectors: planes = float R[dim][n_bits] (device); projections by an
+ *     FP32 MFMA product.
+ *   CSR vectors: planes = NULL; plane entries are generated on the fly:
+ *     g(term, h) = float(z), z from Box-Muller in FP64 on the Philox-4x32-10
+ *     words of counter (term, h/4, 0, 0) and key (seed lo32, seed hi32),
+ *     u_i = (w_i + 0.5)/2^32, (z0,z1) = BoxMuller(u0,u1), (z2,z3) = BoxMuller(u2,u3),
+ *     entry = z_{h mod 4}; projections accumulated in FP64.
+ * n_bits must be a multiple of 32 (DENSE: of 64). */
+int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *planes, int32_t n_bits,
+                      uint64_t seed, blsh_layout layout, uint32_t *bits_out, void *stream);
+
+/* ---------------- verification ---------------- */
+
+/* Algorithm 1 (BayesLSH).  For each candidate: compare k hashes at a time;
+ * prune when Pr[S >= t | M(m,n)] < epsilon; otherwise stop as soon as
+ * Pr[|S - S_hat| < delta | M(m,n)] >= 1 - gamma and emit S_hat; a candidate
+ * still undecided at n = n_max is emitted with its S_hat (ACCEPT_NMAX).
+ * S_hat: Jaccard (m+alpha-1)/(n+alpha+beta-2) clamped to [0,1]; cosine
+ * cos(pi (1 - max(0.5, m/n))).  Constraints: 0 < t, epsilon, delta, gamma < 1;
+ * k in {16, 32, 64}; n_max % k == 0; n_max/k <= 64.  SRP signatures may be
+ * OBJECT_MAJOR or WORD_MAJOR (WORD_MAJOR is the fast layout); minhash
+ * signatures must be OBJECT_MAJOR with n_hashes % 4 == 0. */
+int bayeslsh_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, double t,
+                    double epsilon, double delta, double gamma, blsh_prior prior, int32_t k,
+                    blsh_result *res, void *stream);
+
+/* Algorithm 2 (BayesLSH-Lite).  Prune as above using at most h hashes
+ * (h % k == 0, h <= n_max); survivors get their exact similarity from `exact`
+ * (cosine: DENSE or CSR, sums in FP64; Jaccard: SETS) and are emitted iff
+ * s > t, with s as acc_val.  Survivor codes are LITE_EXACT at level h/k - 1. */
+int bayeslsh_lite_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs,
+                         const blsh_vectors *exact, double t, double epsilon, blsh_prior prior, int32_t h,
+                         int32_t k, blsh_result *res, void *stream);
+
+/* Exhaustive comparator: every candidate compares all n_max hashes (no early
+ * exit, object-major rows read whole), then
+ *   mode REPLAY:      the decision sequence of Algorithm 1 is replayed on the
+ *                     per-level counts -> output identical to bayeslsh_verify;
+ *   mode REPLAY_LITE: the same for Algorithm 2 with budget h, then exact
+ *                     similarity on survivors -> identical to bayeslsh_lite_verify;
+ *   mode MLE:         the classical estimate m/n_max (cosine: r2c(m/n_max)),
+ *                     emitted iff >= t (Section 3; "LSH Approx" of Section 5.1);
+ *                     codes are ACCEPT_NMAX / PRUNED at level n_max/k - 1.
+ * `exact` and h are used by REPLAY_LITE only. */
+typedef enum { BLSH_REPLAY = 0, BLSH_REPLAY_LITE = 1, BLSH_MLE = 2 } blsh_exhaustive_mode;
+int bayeslsh_exhaustive_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs,
+                               const blsh_vectors *exact, double t, double epsilon, double delta,
+                               double gamma, blsh_prior prior, int32_t k, int32_t h,
+                               blsh_exhaustive_mode mode, blsh_result *res, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BAYESLSH_H */

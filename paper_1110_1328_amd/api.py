@@ -1,0 +1,330 @@
+"""Python binding of libbayeslsh.so: argument marshalling only.
+
+Functions carry the C names.  Device memory is held in torch tensors; each
+helper checks dtype, device and contiguity, fills the ctypes struct of the
+header with raw pointers, and calls the library on the current torch stream
+(or the stream passed in).  Every computation happens in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _abi as A
+from ._abi import (ACCEPT_CONC, ACCEPT_NMAX, ALL_PAIRS, COSINE, CSR, DENSE, JACCARD, LITE_EXACT, MLE,  # noqa: F401
+                   OBJECT_MAJOR, PAIRS, PRUNED, QUERY_LISTS, REPLAY, REPLAY_LITE, SETS, WORD_MAJOR)
+
+
+class BayesLSHError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (A.STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+def _lib():
+    return A.load()
+
+
+def _check(rc: int) -> int:
+    if rc != A.OK:
+        msg = _lib().bayeslsh_last_error()
+        raise BayesLSHError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _dev(t: torch.Tensor, dtype, name: str):
+    if t is None:
+        return None
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# ---------------------------------------------------------------------------
+# argument holders (keep the tensors alive next to their structs)
+# ---------------------------------------------------------------------------
+@dataclass
+class Signatures:
+    data: torch.Tensor
+    measure: int
+    layout: int
+    n_obj: int
+    n_hashes: int
+    n_max: int = 0
+
+    def struct(self):
+        _dev(self.data, torch.int32 if self.data.dtype == torch.int32 else torch.uint32, "signature data")
+        return A.Sigs(self.measure, self.layout, _p(self.data), self.n_obj, self.n_hashes, self.n_max)
+
+
+@dataclass
+class Candidates:
+    kind: int
+    x: torch.Tensor = None
+    y: torch.Tensor = None
+    query: torch.Tensor = None
+    offsets: torch.Tensor = None
+    cand: torch.Tensor = None
+    n_cand: int = 0
+    all_n: int = 0
+
+    @property
+    def count(self) -> int:
+        if self.kind == PAIRS:
+            return int(self.x.numel())
+        if self.kind == QUERY_LISTS:
+            return int(self.n_cand)
+        return self.all_n * (self.all_n - 1) // 2
+
+    def struct(self):
+        c = A.Candidates()
+        c.kind = self.kind
+        if self.kind == PAIRS:
+            _dev(self.x, torch.uint32, "x")
+            _dev(self.y, torch.uint32, "y")
+            if self.x.numel() != self.y.numel():
+                raise ValueError("x and y differ in length")
+            c.x, c.y, c.n_pairs = _p(self.x), _p(self.y), self.x.numel()
+        elif self.kind == QUERY_LISTS:
+            _dev(self.query, torch.uint32, "query")
+            _dev(self.offsets, torch.int64, "offsets")
+            _dev(self.cand, torch.uint32, "cand")
+            c.query, c.offsets, c.cand = _p(self.query), _p(self.offsets), _p(self.cand)
+            c.n_lists, c.n_cand = self.query.numel(), self.n_cand
+        else:
+            c.all_n = self.all_n
+        return c
+
+
+def pairs(x: torch.Tensor, y: torch.Tensor) -> Candidates:
+    return Candidates(PAIRS, x=x, y=y)
+
+
+def query_lists(query: torch.Tensor, offsets: torch.Tensor, cand: torch.Tensor, n_cand: int | None = None) -> Candidates:
+    return Candidates(QUERY_LISTS, query=query, offsets=offsets, cand=cand,
+                      n_cand=int(cand.numel()) if n_cand is None else int(n_cand))
+
+
+def all_pairs(n: int) -> Candidates:
+    return Candidates(ALL_PAIRS, all_n=int(n))
+
+
+@dataclass
+class Vectors:
+    kind: int
+    n_obj: int
+    dim: int
+    dense: torch.Tensor = None
+    offsets: torch.Tensor = None
+    indices: torch.Tensor = None
+    values: torch.Tensor = None
+
+    def struct(self):
+        if self.kind == DENSE:
+            _dev(self.dense, torch.float32, "dense")
+        else:
+            _dev(self.offsets, torch.int64, "offsets")
+            _dev(self.indices, torch.uint32, "indices")
+            if self.kind == CSR:
+                _dev(self.values, torch.float32, "values")
+        return A.Vectors(self.kind, self.n_obj, self.dim, _p(self.dense), _p(self.offsets), _p(self.indices),
+                         _p(self.values))
+
+
+def dense_vectors(x: torch.Tensor) -> Vectors:
+    return Vectors(DENSE, x.shape[0], x.shape[1], dense=x)
+
+
+def csr_vectors(offsets, indices, values, dim) -> Vectors:
+    return Vectors(CSR, offsets.numel() - 1, int(dim), offsets=offsets, indices=indices, values=values)
+
+
+def set_vectors(offsets, indices, dim) -> Vectors:
+    return Vectors(SETS, offsets.numel() - 1, int(dim), offsets=offsets, indices=indices)
+
+
+@dataclass
+class Result:
+    code: torch.Tensor
+    acc_idx: torch.Tensor
+    acc_val: torch.Tensor
+    n_accepted: torch.Tensor
+    m_debug: torch.Tensor = None
+    _s: object = field(default=None, repr=False)
+
+    def struct(self):
+        _dev(self.code, torch.uint8, "code")
+        _dev(self.acc_idx, torch.uint64, "acc_idx")
+        _dev(self.acc_val, torch.float32, "acc_val")
+        _dev(self.n_accepted, torch.int64, "n_accepted")
+        _dev(self.m_debug, torch.uint16, "m_debug")
+        return A.Result(_p(self.code), _p(self.acc_idx), _p(self.acc_val), self.acc_idx.numel(),
+                        _p(self.n_accepted), _p(self.m_debug))
+
+    def accepted(self):
+        """(idx, val) of the output set on the host, sorted by candidate index."""
+        n = min(int(self.n_accepted.item()), self.acc_idx.numel())
+        idx = self.acc_idx[:n].view(torch.int64).cpu().numpy()
+        val = self.acc_val[:n].cpu().numpy()
+        o = idx.argsort(kind="stable")
+        return idx[o], val[o]
+
+
+def make_result(n_cand: int, capacity: int, device="cuda", m_debug: bool = False) -> Result:
+    return Result(code=torch.empty(max(n_cand, 1), dtype=torch.uint8, device=device),
+                  acc_idx=torch.empty(max(capacity, 1), dtype=torch.int64, device=device).view(torch.uint64),
+                  acc_val=torch.empty(max(capacity, 1), dtype=torch.float32, device=device),
+                  n_accepted=torch.zeros(1, dtype=torch.int64, device=device),
+                  m_debug=(torch.empty(max(n_cand, 1), dtype=torch.int16, device=device).view(torch.uint16)
+                           if m_debug else None))
+
+
+def decode(code):
+    """code byte -> (decision, level); 0xFF marks a bad object id."""
+    return code >> 6, code & 63
+
+
+# ---------------------------------------------------------------------------
+# context and entry points (C names)
+# ---------------------------------------------------------------------------
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(_lib().bayeslsh_create(C.byref(h), device))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _lib().bayeslsh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bayeslsh_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def bayeslsh_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def bayeslsh_version() -> int:
+    return _lib().bayeslsh_version()
+
+
+def bayeslsh_sync(ctx: Context, stream=None) -> int:
+    return _check(_lib().bayeslsh_sync(ctx.handle, _stream(stream)))
+
+
+def bayeslsh_profile_enable(ctx: Context, enable: bool = True):
+    _check(_lib().bayeslsh_profile_enable(ctx.handle, int(enable)))
+
+
+def bayeslsh_profile_reset(ctx: Context):
+    _check(_lib().bayeslsh_profile_reset(ctx.handle))
+
+
+def bayeslsh_profile_read(ctx: Context, name: str):
+    ms, n = C.c_double(), C.c_int64()
+    _check(_lib().bayeslsh_profile_read(ctx.handle, name.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def bayeslsh_posterior_table(ctx, measure, t, epsilon, delta, gamma, prior=(1.0, 1.0), k=32, n_levels=8,
+                             lite=False):
+    """ctx may be None (host-only build, no GPU needed)."""
+    import numpy as np
+    words = (k * n_levels + 1 + 31) // 32
+    mm = np.zeros(n_levels, np.int32)
+    acc = np.zeros(n_levels * words, np.uint32)
+    margin = C.c_double()
+    _check(_lib().bayeslsh_posterior_table(ctx.handle if ctx is not None else None, measure, t, epsilon, delta, gamma, A.Prior(*prior), k,
+                                           n_levels, int(lite), mm.ctypes.data_as(C.c_void_p),
+                                           acc.ctypes.data_as(C.c_void_p), C.byref(margin)))
+    return mm, acc.reshape(n_levels, words), margin.value
+
+
+def bayeslsh_minhash_sigs(ctx: Context, sets: Vectors, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor,
+                          stream=None):
+    _dev(a, torch.uint32, "a")
+    _dev(b, torch.uint32, "b")
+    _dev(out, torch.uint32, "sigs_out")
+    if out.numel() < sets.n_obj * a.numel():
+        raise ValueError("sigs_out too small")
+    v = sets.struct()
+    _check(_lib().bayeslsh_minhash_sigs(ctx.handle, C.byref(v), _p(a), _p(b), a.numel(), _p(out), _stream(stream)))
+    return out
+
+
+def bayeslsh_srp_sigs(ctx: Context, vecs: Vectors, planes, n_bits: int, seed: int, layout: int, out: torch.Tensor,
+                      stream=None):
+    _dev(out, torch.uint32, "bits_out")
+    if planes is not None:
+        _dev(planes, torch.float32, "planes")
+    if out.numel() < vecs.n_obj * (n_bits // 32):
+        raise ValueError("bits_out too small")
+    v = vecs.struct()
+    _check(_lib().bayeslsh_srp_sigs(ctx.handle, C.byref(v), _p(planes), n_bits, seed, layout, _p(out),
+                                    _stream(stream)))
+    return out
+
+
+def _check_result_size(res: Result, cand: Candidates):
+    if res.code.numel() < cand.count:
+        raise ValueError("result.code holds %d bytes for %d candidates" % (res.code.numel(), cand.count))
+    if res.m_debug is not None and res.m_debug.numel() < cand.count:
+        raise ValueError("result.m_debug too small")
+
+
+def bayeslsh_verify(ctx: Context, cand: Candidates, sigs: Signatures, t, epsilon, delta, gamma, prior=(1.0, 1.0),
+                    k=32, res: Result = None, stream=None):
+    _check_result_size(res, cand)
+    cs, ss, rs = cand.struct(), sigs.struct(), res.struct()
+    _check(_lib().bayeslsh_verify(ctx.handle, C.byref(cs), C.byref(ss), t, epsilon, delta, gamma, A.Prior(*prior), k,
+                                  C.byref(rs), _stream(stream)))
+    return res
+
+
+def bayeslsh_lite_verify(ctx: Context, cand: Candidates, sigs: Signatures, exact: Vectors, t, epsilon,
+                         prior=(1.0, 1.0), h=128, k=32, res: Result = None, stream=None):
+    _check_result_size(res, cand)
+    cs, ss, vs, rs = cand.struct(), sigs.struct(), exact.struct(), res.struct()
+    _check(_lib().bayeslsh_lite_verify(ctx.handle, C.byref(cs), C.byref(ss), C.byref(vs), t, epsilon,
+                                       A.Prior(*prior), h, k, C.byref(rs), _stream(stream)))
+    return res
+
+
+def bayeslsh_exhaustive_verify(ctx: Context, cand: Candidates, sigs: Signatures, exact: Vectors | None, t, epsilon,
+                               delta, gamma, prior=(1.0, 1.0), k=32, h=0, mode=REPLAY, res: Result = None,
+                               stream=None):
+    _check_result_size(res, cand)
+    cs, ss, rs = cand.struct(), sigs.struct(), res.struct()
+    vs = exact.struct() if exact is not None else None
+    _check(_lib().bayeslsh_exhaustive_verify(ctx.handle, C.byref(cs), C.byref(ss),
+                                             C.byref(vs) if vs is not None else None, t, epsilon, delta, gamma,
+                                             A.Prior(*prior), k, h, mode, C.byref(rs), _stream(stream)))
+    return res

@@ -1,0 +1,500 @@
+// C ABI entry points: argument validation, table cache, workspace, dispatch.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "device_common.h"
+
+namespace blsh {
+
+// launchers (verify.hip, sigs.hip)
+int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool word_major, hipStream_t s);
+int launch_exhaustive(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s);
+int launch_zero(blsh_ctx *ctx, int64_t *p, int n, hipStream_t s);
+int launch_minhash(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *elems, int64_t n_sets, const uint32_t *a,
+                   const uint32_t *b, int n_hashes, uint32_t *out, hipStream_t s);
+int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *indices, const float *values,
+                      int64_t n_rows, int n_bits, uint64_t seed, bool word_major, uint32_t *out, hipStream_t s);
+int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim, const float *R, int n_bits,
+                     bool word_major, uint32_t *out, hipStream_t s);
+
+int launch_exact(blsh_ctx *ctx, const ExactArgs &e, const VerifyArgs &a, int64_t max_items, hipStream_t s);
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+LaunchScope::LaunchScope(blsh_ctx *c, hipStream_t s, const char *n) : ctx(c), stream(s), name(n), on(c && c->prof) {
+  if (on) {
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    hipEventRecord(a, stream);
+  }
+}
+LaunchScope::~LaunchScope() {
+  if (on) {
+    hipEventRecord(b, stream);
+    ctx->prof_pending.push_back({name, a, b});
+  }
+}
+
+int get_table(blsh_ctx *ctx, const TableKey &key, std::shared_ptr<HostTable> *host, const uint32_t **dev,
+              hipStream_t stream) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  auto it = ctx->host_tables.find(key);
+  std::shared_ptr<HostTable> ht;
+  if (it == ctx->host_tables.end()) {
+    ht = std::make_shared<HostTable>();
+    int rc = build_table(key, ht.get());
+    if (rc != BLSH_OK) return rc;
+    ctx->host_tables[key] = ht;
+  } else {
+    ht = it->second;
+  }
+  if (host) *host = ht;
+  if (dev) {
+    auto dt = ctx->dev_tables.find(key);
+    if (dt == ctx->dev_tables.end()) {
+      std::vector<uint32_t> img(kTabAccOff + size_t(ht->n_levels) * ht->words, 0u);
+      img[0] = uint32_t(ht->k);
+      img[1] = uint32_t(ht->n_levels);
+      img[2] = uint32_t(ht->words);
+      img[3] = uint32_t(key.measure);
+      std::memcpy(&img[4], &key.alpha, 8);
+      std::memcpy(&img[6], &key.beta, 8);
+      std::memcpy(&img[8], &key.t, 8);
+      for (int j = 0; j < ht->n_levels; ++j) img[kTabMinOff + j] = uint32_t(ht->min_matches[j]);
+      std::memcpy(&img[kTabAccOff], ht->accept.data(), ht->accept.size() * 4);
+      DevTable d;
+      d.words = img.size();
+      BLSH_HIP(hipMalloc(&d.ptr, d.words * 4));
+      BLSH_HIP(hipMemcpy(d.ptr, img.data(), d.words * 4, hipMemcpyHostToDevice));
+      dt = ctx->dev_tables.emplace(key, d).first;
+    }
+    *dev = dt->second.ptr;
+  }
+  (void)stream;
+  return BLSH_OK;
+}
+
+int ensure_workspace(blsh_ctx *ctx, size_t bytes) {
+  if (ctx->ws_bytes >= bytes) return BLSH_OK;
+  BLSH_HIP(hipDeviceSynchronize());
+  if (ctx->ws) hipFree(ctx->ws);
+  ctx->ws = nullptr;
+  ctx->ws_bytes = 0;
+  if (hipMalloc(&ctx->ws, bytes) != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(BLSH_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+  }
+  ctx->ws_bytes = bytes;
+  return BLSH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------
+static bool in01(double v) { return v > 0.0 && v < 1.0 && std::isfinite(v); }
+
+static int check_params(double t, double eps, double delta, double gamma, bool lite) {
+  if (!in01(t)) return fail(BLSH_EINVAL, "t must be in (0,1), got %g", t);
+  if (!in01(eps)) return fail(BLSH_EINVAL, "epsilon must be in (0,1), got %g", eps);
+  if (!lite && !in01(delta)) return fail(BLSH_EINVAL, "delta must be in (0,1), got %g", delta);
+  if (!lite && !in01(gamma)) return fail(BLSH_EINVAL, "gamma must be in (0,1), got %g", gamma);
+  return BLSH_OK;
+}
+
+static int check_prior(int measure, blsh_prior p) {
+  if (measure == BLSH_COSINE) {
+    if (p.alpha != 1.0 || p.beta != 1.0)
+      return fail(BLSH_EINVAL, "cosine uses the uniform prior on r in [0.5,1]: prior must be {1,1}");
+    return BLSH_OK;
+  }
+  if (!(p.alpha >= 1.0 && p.beta >= 1.0) || p.alpha != std::floor(p.alpha) || p.beta != std::floor(p.beta) ||
+      p.alpha > 1e6 || p.beta > 1e6)
+    return fail(BLSH_EINVAL, "Jaccard prior Beta(alpha,beta) needs integer alpha,beta >= 1 (got %g,%g)", p.alpha,
+                p.beta);
+  return BLSH_OK;
+}
+
+static int check_sigs(const blsh_sigs *s, int k, int *n_max_out, int *row_words) {
+  if (!s || !s->data) return fail(BLSH_EINVAL, "signatures: null");
+  if (s->measure != BLSH_JACCARD && s->measure != BLSH_COSINE) return fail(BLSH_EINVAL, "signatures: bad measure");
+  if (s->n_obj <= 0 || s->n_obj > 0xFFFFFFFFll) return fail(BLSH_EINVAL, "signatures: n_obj out of range");
+  if (s->n_hashes <= 0) return fail(BLSH_EINVAL, "signatures: n_hashes <= 0");
+  const int n_max = s->n_max ? s->n_max : s->n_hashes;
+  if (n_max > s->n_hashes || n_max <= 0) return fail(BLSH_EINVAL, "signatures: n_max > n_hashes");
+  if (k != 16 && k != 32 && k != 64) return fail(BLSH_EINVAL, "k must be 16, 32 or 64 (got %d)", k);
+  if (n_max % k) return fail(BLSH_EINVAL, "n_max (%d) must be a multiple of k (%d)", n_max, k);
+  if (n_max / k > kMaxLevels) return fail(BLSH_EINVAL, "n_max/k = %d levels exceeds %d", n_max / k, kMaxLevels);
+  if (s->measure == BLSH_COSINE) {
+    if (s->n_hashes % 32) return fail(BLSH_EINVAL, "SRP signatures: n_hashes must be a multiple of 32");
+    if (s->layout != BLSH_OBJECT_MAJOR && s->layout != BLSH_WORD_MAJOR) return fail(BLSH_EINVAL, "bad layout");
+    *row_words = s->n_hashes / 32;
+  } else {
+    if (s->layout != BLSH_OBJECT_MAJOR) return fail(BLSH_EINVAL, "minhash signatures must be OBJECT_MAJOR");
+    if (s->n_hashes % 4) return fail(BLSH_EINVAL, "minhash signatures: n_hashes must be a multiple of 4");
+    if (uintptr_t(s->data) & 15) return fail(BLSH_EINVAL, "minhash signatures must be 16-byte aligned");
+    *row_words = s->n_hashes;
+  }
+  *n_max_out = n_max;
+  return BLSH_OK;
+}
+
+static int check_cand(const blsh_candidates *c, int64_t *n_cand) {
+  if (!c) return fail(BLSH_EINVAL, "candidates: null");
+  switch (c->kind) {
+    case BLSH_PAIRS:
+      if (c->n_pairs < 0) return fail(BLSH_EINVAL, "candidates: n_pairs < 0");
+      if (c->n_pairs && (!c->x || !c->y)) return fail(BLSH_EINVAL, "candidates: null x/y");
+      *n_cand = c->n_pairs;
+      return BLSH_OK;
+    case BLSH_QUERY_LISTS:
+      if (c->n_lists < 0 || c->n_cand < 0) return fail(BLSH_EINVAL, "candidates: negative list sizes");
+      if (c->n_cand && (c->n_lists == 0 || !c->query || !c->offsets || !c->cand))
+        return fail(BLSH_EINVAL, "candidates: null list arrays");
+      *n_cand = c->n_cand;
+      return BLSH_OK;
+    case BLSH_ALL_PAIRS:
+      if (c->all_n < 0 || c->all_n > (1ll << 31)) return fail(BLSH_EINVAL, "candidates: all_n out of range");
+      *n_cand = c->all_n * (c->all_n - 1) / 2;
+      if (c->all_n < 2) *n_cand = 0;
+      return BLSH_OK;
+    default:
+      return fail(BLSH_EINVAL, "candidates: bad kind %d", int(c->kind));
+  }
+}
+
+static int check_result(const blsh_result *r) {
+  if (!r || !r->code || !r->n_accepted) return fail(BLSH_EINVAL, "result: code and n_accepted are required");
+  if (r->acc_capacity < 0) return fail(BLSH_EINVAL, "result: acc_capacity < 0");
+  if (r->acc_capacity > 0 && (!r->acc_idx || !r->acc_val)) return fail(BLSH_EINVAL, "result: null acc arrays");
+  return BLSH_OK;
+}
+
+static int check_exact(const blsh_vectors *v, int measure, int64_t n_obj) {
+  if (!v) return fail(BLSH_EINVAL, "exact vectors: null");
+  if (v->n_obj < n_obj) return fail(BLSH_EINVAL, "exact vectors: fewer objects than signatures");
+  if (measure == BLSH_JACCARD) {
+    if (v->kind != BLSH_SETS || !v->offsets || !v->indices)
+      return fail(BLSH_EINVAL, "Jaccard exact similarity needs SETS vectors");
+  } else if (v->kind == BLSH_DENSE) {
+    if (!v->dense || v->dim <= 0) return fail(BLSH_EINVAL, "dense vectors: null or dim <= 0");
+  } else if (v->kind == BLSH_CSR) {
+    if (!v->offsets || !v->indices || !v->values) return fail(BLSH_EINVAL, "CSR vectors: null arrays");
+  } else {
+    return fail(BLSH_EINVAL, "cosine exact similarity needs DENSE or CSR vectors");
+  }
+  return BLSH_OK;
+}
+
+static void fill_cand(VerifyArgs &a, const blsh_candidates *c) {
+  a.kind = c->kind;
+  a.x = c->x;
+  a.y = c->y;
+  a.query = c->query;
+  a.offsets = c->offsets;
+  a.cand = c->cand;
+  a.n_lists = c->n_lists;
+  a.all_n = c->all_n;
+}
+
+// Survivor queue slice layout inside the context workspace, sized for `chunk` candidates:
+//   [0, 64)                  q_n (int64) + padding
+//   [64, 64 + 8*chunk)       q_idx
+//   [.., + 8*chunk)          q_xy
+static constexpr int64_t kChunk = int64_t(1) << 26;
+
+struct Queue {
+  int64_t *n;
+  uint64_t *idx;
+  uint32_t *xy;
+};
+
+static int get_queue(blsh_ctx *ctx, int64_t chunk, Queue *q) {
+  const size_t bytes = 256 + size_t(chunk) * 16;
+  int rc = ensure_workspace(ctx, bytes);
+  if (rc) return rc;
+  char *base = static_cast<char *>(ctx->ws);
+  q->n = reinterpret_cast<int64_t *>(base);
+  q->idx = reinterpret_cast<uint64_t *>(base + 256);
+  q->xy = reinterpret_cast<uint32_t *>(base + 256 + size_t(chunk) * 8);
+  return BLSH_OK;
+}
+
+static void fill_exact(ExactArgs &e, const blsh_vectors *v, const Queue &q, double t) {
+  e.vec_kind = v->kind;
+  e.dense = v->dense;
+  e.dim = v->dim;
+  e.offsets = v->offsets;
+  e.indices = v->indices;
+  e.values = v->values;
+  e.q_idx = q.idx;
+  e.q_xy = q.xy;
+  e.q_n = q.n;
+  e.t = t;
+}
+
+// Shared driver of verify / lite / exhaustive.
+static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, const blsh_vectors *exact,
+                      double t, double eps, double delta, double gamma, blsh_prior prior, int k, int h,
+                      int exhaustive_mode /* -1: early-exit path */, blsh_result *res, void *stream) {
+  if (!ctx) return fail(BLSH_EINVAL, "null context");
+  const bool lite = exhaustive_mode == -1 ? (exact != nullptr) : exhaustive_mode == BLSH_REPLAY_LITE;
+  const bool tab_lite = lite || exhaustive_mode == BLSH_MLE;  // no concentration bits needed
+  int rc = check_params(t, eps, delta, gamma, tab_lite);
+  if (rc) return rc;
+  int n_max = 0, row_words = 0;
+  if ((rc = check_sigs(sigs, k, &n_max, &row_words))) return rc;
+  if ((rc = check_prior(sigs->measure, prior))) return rc;
+  int64_t n_cand = 0;
+  if ((rc = check_cand(cand, &n_cand))) return rc;
+  if ((rc = check_result(res))) return rc;
+  if (lite) {
+    if (h <= 0 || h % k || h > n_max) return fail(BLSH_EINVAL, "Lite: h (%d) must be a positive multiple of k <= n_max", h);
+    if ((rc = check_exact(exact, sigs->measure, sigs->n_obj))) return rc;
+  }
+  const bool exh = exhaustive_mode >= 0;
+  if (exh) {
+    if (sigs->measure == BLSH_COSINE) {
+      if (sigs->layout != BLSH_OBJECT_MAJOR) return fail(BLSH_EINVAL, "exhaustive: SRP signatures must be OBJECT_MAJOR");
+      if (n_max % 128 || n_max > 2048) return fail(BLSH_EINVAL, "exhaustive: SRP n_max must be a multiple of 128 <= 2048");
+      if (uintptr_t(sigs->data) & 15 || row_words % 4) return fail(BLSH_EINVAL, "exhaustive: rows must be 16-byte aligned");
+    } else if (n_max > 256) {
+      return fail(BLSH_EINVAL, "exhaustive: minhash n_max must be <= 256");
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n_levels = (lite ? h : n_max) / k;
+  TableKey key{int(sigs->measure), t, eps, tab_lite ? 0.0 : delta, tab_lite ? 0.0 : gamma, prior.alpha, prior.beta, k,
+               n_levels, tab_lite ? 1 : 0};
+  const uint32_t *dtab = nullptr;
+  if ((rc = get_table(ctx, key, nullptr, &dtab, s))) return rc;
+
+  VerifyArgs a{};
+  fill_cand(a, cand);
+  a.sig = sigs->data;
+  a.n_obj = sigs->n_obj;
+  a.row_words = row_words;
+  a.table = dtab;
+  a.n_levels = n_levels;
+  a.measure = sigs->measure;
+  a.code = res->code;
+  a.acc_idx = res->acc_idx;
+  a.acc_val = res->acc_val;
+  a.acc_cap = res->acc_capacity;
+  a.n_acc = res->n_accepted;
+  a.m_dbg = res->m_debug;
+  a.status = ctx->d_status;
+  a.mode = exh ? exhaustive_mode : 0;
+  a.count_levels = n_max / k;
+  a.t = t;
+  if ((rc = launch_zero(ctx, res->n_accepted, 1, s))) return fail(rc, "launch failed");
+  if (n_cand == 0) return BLSH_OK;
+  Queue q{};
+  const int64_t chunk = lite ? std::min<int64_t>(n_cand, kChunk) : n_cand;
+  if (lite && (rc = get_queue(ctx, chunk, &q))) return rc;
+  a.q_idx = q.idx;
+  a.q_xy = q.xy;
+  a.q_n = q.n;
+  ExactArgs e{};
+  if (lite) fill_exact(e, exact, q, t);
+  for (int64_t c0 = 0; c0 < n_cand; c0 += chunk) {
+    a.c_begin = c0;
+    a.c_end = std::min(n_cand, c0 + chunk);
+    if (lite && (rc = launch_zero(ctx, q.n, 1, s))) return fail(rc, "launch failed");
+    rc = exh ? launch_exhaustive(ctx, a, k, s)
+             : launch_verify(ctx, a, k, lite, sigs->measure == BLSH_COSINE && sigs->layout == BLSH_WORD_MAJOR, s);
+    if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;
+    if (lite && (rc = launch_exact(ctx, e, a, a.c_end - a.c_begin, s))) return fail(rc, "exact launch failed");
+  }
+  return BLSH_OK;
+}
+
+}  // namespace blsh
+
+using namespace blsh;
+
+extern "C" {
+
+const char *bayeslsh_last_error(void) { return g_err; }
+int bayeslsh_version(void) { return BAYESLSH_VERSION; }
+
+int bayeslsh_create(blsh_ctx **out, int device) {
+  if (!out) return fail(BLSH_EINVAL, "null output pointer");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(BLSH_EDEVICE, "no HIP device");
+  if (device < 0 || device >= n) return fail(BLSH_EINVAL, "device %d out of range", device);
+  BLSH_HIP(hipSetDevice(device));
+  auto *c = new (std::nothrow) blsh_ctx();
+  if (!c) return fail(BLSH_ENOMEM, "host allocation failed");
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  if (hipMalloc(&c->d_status, 256) != hipSuccess) {
+    delete c;
+    return fail(BLSH_ENOMEM, "status allocation failed");
+  }
+  if (hipMemset(c->d_status, 0, 256) != hipSuccess) {
+    hipFree(c->d_status);
+    delete c;
+    return fail(BLSH_EDEVICE, "status init failed");
+  }
+  *out = c;
+  return BLSH_OK;
+}
+
+void bayeslsh_destroy(blsh_ctx *ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  for (auto &kv : ctx->dev_tables) hipFree(kv.second.ptr);
+  for (auto &p : ctx->prof_pending) { hipEventDestroy(p.start); hipEventDestroy(p.stop); }
+  if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->d_status) hipFree(ctx->d_status);
+  delete ctx;
+}
+
+int bayeslsh_sync(blsh_ctx *ctx, void *stream) {
+  if (!ctx) return fail(BLSH_EINVAL, "null context");
+  BLSH_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  int32_t st = 0;
+  BLSH_HIP(hipMemcpy(&st, ctx->d_status, 4, hipMemcpyDeviceToHost));
+  if (st != 0) {
+    BLSH_HIP(hipMemset(ctx->d_status, 0, 4));
+    const char *what = st == BLSH_ETRUNCATED ? "accepted list overflowed acc_capacity"
+                       : st == BLSH_EBADID  ? "a candidate referenced an object id >= n_obj"
+                       : st == BLSH_EINVAL  ? "invalid input found on the device (empty set)"
+                                            : "device error";
+    return fail(st, "%s", what);
+  }
+  return BLSH_OK;
+}
+
+int bayeslsh_profile_enable(blsh_ctx *ctx, int enable) {
+  if (!ctx) return fail(BLSH_EINVAL, "null context");
+  ctx->prof = enable != 0;
+  return BLSH_OK;
+}
+
+int bayeslsh_profile_reset(blsh_ctx *ctx) {
+  if (!ctx) return fail(BLSH_EINVAL, "null context");
+  for (auto &p : ctx->prof_pending) {
+    hipEventSynchronize(p.stop);
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  ctx->prof_pending.clear();
+  ctx->prof_acc.clear();
+  return BLSH_OK;
+}
+
+int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_ms, int64_t *launches) {
+  if (!ctx || !name_substr) return fail(BLSH_EINVAL, "null argument");
+  for (auto &p : ctx->prof_pending) {
+    BLSH_HIP(hipEventSynchronize(p.stop));
+    float ms = 0.f;
+    BLSH_HIP(hipEventElapsedTime(&ms, p.start, p.stop));
+    auto &acc = ctx->prof_acc[p.name];
+    acc.first += ms;
+    acc.second += 1;
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  ctx->prof_pending.clear();
+  double tot = 0;
+  int64_t n = 0;
+  for (auto &kv : ctx->prof_acc)
+    if (kv.first.find(name_substr) != std::string::npos) { tot += kv.second.first; n += kv.second.second; }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = n;
+  return BLSH_OK;
+}
+
+int bayeslsh_posterior_table(blsh_ctx *ctx, blsh_measure measure, double t, double epsilon, double delta,
+                             double gamma, blsh_prior prior, int32_t k, int32_t n_levels, int32_t lite,
+                             int32_t *min_matches_host, uint32_t *accept_host, double *min_margin_host) {
+  int rc = check_params(t, epsilon, delta, gamma, lite != 0);
+  if (rc) return rc;
+  if (measure != BLSH_JACCARD && measure != BLSH_COSINE) return fail(BLSH_EINVAL, "bad measure");
+  if ((rc = check_prior(measure, prior))) return rc;
+  if (k <= 0 || k > 4096 || n_levels <= 0 || n_levels > kMaxLevels) return fail(BLSH_EINVAL, "bad k or n_levels");
+  TableKey key{int(measure), t, epsilon, lite ? 0.0 : delta, lite ? 0.0 : gamma, prior.alpha, prior.beta, k,
+               n_levels, lite ? 1 : 0};
+  std::shared_ptr<HostTable> ht;
+  if (ctx) {
+    if ((rc = get_table(ctx, key, &ht, nullptr, nullptr))) return rc;
+  } else {  // no context (e.g. a host without a GPU): build without caching
+    ht = std::make_shared<HostTable>();
+    if ((rc = build_table(key, ht.get()))) return rc;
+  }
+  if (min_matches_host) std::memcpy(min_matches_host, ht->min_matches.data(), 4 * ht->min_matches.size());
+  if (accept_host) std::memcpy(accept_host, ht->accept.data(), 4 * ht->accept.size());
+  if (min_margin_host) *min_margin_host = ht->min_margin;
+  return BLSH_OK;
+}
+
+int bayeslsh_minhash_sigs(blsh_ctx *ctx, const blsh_vectors *sets, const uint32_t *a, const uint32_t *b,
+                          int32_t n_hashes, uint32_t *sigs_out, void *stream) {
+  if (!ctx || !sets || !a || !b || !sigs_out) return fail(BLSH_EINVAL, "null argument");
+  if (sets->kind != BLSH_SETS || !sets->offsets || !sets->indices) return fail(BLSH_EINVAL, "minhash needs SETS vectors");
+  if (n_hashes <= 0 || n_hashes > 1024) return fail(BLSH_EINVAL, "n_hashes must be in [1, 1024]");
+  if (sets->n_obj <= 0) return BLSH_OK;
+  return launch_minhash(ctx, sets->offsets, sets->indices, sets->n_obj, a, b, n_hashes, sigs_out,
+                        static_cast<hipStream_t>(stream));
+}
+
+int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *planes, int32_t n_bits, uint64_t seed,
+                      blsh_layout layout, uint32_t *bits_out, void *stream) {
+  if (!ctx || !vecs || !bits_out) return fail(BLSH_EINVAL, "null argument");
+  if (n_bits <= 0 || n_bits % 32) return fail(BLSH_EINVAL, "n_bits must be a positive multiple of 32");
+  if (layout != BLSH_OBJECT_MAJOR && layout != BLSH_WORD_MAJOR) return fail(BLSH_EINVAL, "bad layout");
+  if (vecs->n_obj <= 0) return BLSH_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (vecs->kind == BLSH_DENSE) {
+    if (!vecs->dense || !planes) return fail(BLSH_EINVAL, "dense SRP needs vectors and planes");
+    if (uintptr_t(vecs->dense) & 15) return fail(BLSH_EINVAL, "dense vectors must be 16-byte aligned");
+    return launch_srp_dense(ctx, vecs->dense, vecs->n_obj, vecs->dim, planes, n_bits, layout == BLSH_WORD_MAJOR,
+                            bits_out, s);
+  }
+  if (vecs->kind == BLSH_CSR) {
+    if (!vecs->offsets || !vecs->indices || !vecs->values) return fail(BLSH_EINVAL, "CSR SRP needs offsets/indices/values");
+    if (planes) return fail(BLSH_EINVAL, "CSR SRP generates its planes: pass planes = NULL");
+    if (n_bits > 2048) return fail(BLSH_EINVAL, "CSR SRP: n_bits must be <= 2048");
+    return launch_srp_sparse(ctx, vecs->offsets, vecs->indices, vecs->values, vecs->n_obj, n_bits, seed,
+                             layout == BLSH_WORD_MAJOR, bits_out, s);
+  }
+  return fail(BLSH_EINVAL, "SRP needs DENSE or CSR vectors");
+}
+
+int bayeslsh_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, double t, double epsilon,
+                    double delta, double gamma, blsh_prior prior, int32_t k, blsh_result *res, void *stream) {
+  return run_verify(ctx, cand, sigs, nullptr, t, epsilon, delta, gamma, prior, k, 0, -1, res, stream);
+}
+
+int bayeslsh_lite_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, const blsh_vectors *exact,
+                         double t, double epsilon, blsh_prior prior, int32_t h, int32_t k, blsh_result *res,
+                         void *stream) {
+  if (!exact) return fail(BLSH_EINVAL, "Lite needs exact vectors");
+  return run_verify(ctx, cand, sigs, exact, t, epsilon, 0.5, 0.5, prior, k, h, -1, res, stream);
+}
+
+int bayeslsh_exhaustive_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs,
+                               const blsh_vectors *exact, double t, double epsilon, double delta, double gamma,
+                               blsh_prior prior, int32_t k, int32_t h, blsh_exhaustive_mode mode, blsh_result *res,
+                               void *stream) {
+  if (mode != BLSH_REPLAY && mode != BLSH_REPLAY_LITE && mode != BLSH_MLE) return fail(BLSH_EINVAL, "bad mode");
+  if (mode == BLSH_MLE) { delta = 0.5; gamma = 0.5; }
+  return run_verify(ctx, cand, sigs, mode == BLSH_REPLAY_LITE ? exact : nullptr, t, epsilon, delta, gamma, prior, k,
+                    h, int(mode), res, stream);
+}
+
+}  // extern "C"

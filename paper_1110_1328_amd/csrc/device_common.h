@@ -1,0 +1,208 @@
+// Device helpers for the gfx950 kernels (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace blsh {
+
+constexpr int kWave = 64;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Arguments shared by the verification kernels (passed by value).
+struct VerifyArgs {
+  // candidates
+  int32_t kind;
+  const uint32_t *x, *y;                 // PAIRS
+  const uint32_t *query;                 // QUERY_LISTS
+  const int64_t *offsets;
+  const uint32_t *cand;
+  int64_t n_lists;
+  int64_t all_n;                         // ALL_PAIRS
+  int64_t c_begin, c_end;                // candidate range of this launch
+  // signatures
+  const uint32_t *sig;
+  int64_t n_obj;
+  int32_t row_words;                     // object-major row length in 32-bit words
+  // decision table
+  const uint32_t *table;
+  int32_t n_levels;                      // levels run (n_max/k, or h/k for Lite)
+  int32_t measure;
+  // outputs
+  uint8_t *code;
+  uint64_t *acc_idx;
+  float *acc_val;
+  int64_t acc_cap;
+  int64_t *n_acc;
+  uint16_t *m_dbg;
+  // Lite survivors
+  uint64_t *q_idx;
+  uint32_t *q_xy;
+  int64_t *q_n;
+  int32_t *status;
+  // exhaustive
+  int32_t mode;                          // 0 replay, 1 replay-lite, 2 mle
+  int32_t count_levels;                  // levels compared in full (n_max/k)
+  double t;
+};
+
+// Arguments of the exact-similarity kernel (Lite survivors).
+struct ExactArgs {
+  int32_t vec_kind;
+  const float *dense;
+  int64_t dim;
+  const int64_t *offsets;
+  const uint32_t *indices;
+  const float *values;
+  const uint64_t *q_idx;
+  const uint32_t *q_xy;
+  const int64_t *q_n;
+  double t;
+};
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` in lanes below the calling lane.
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
+__device__ inline void raise_status(int32_t *status, int32_t code) {
+  if (status) atomicCAS(status, 0, code);
+}
+
+// Bijective remap of block ids so that each XCD (blocks are dealt round-robin
+// over the 8 XCDs) processes one contiguous range of tiles.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t xcd = b & 7, idx = b >> 3;
+  const int64_t per = nb >> 3, rem = nb & 7;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// Row-major decoding of the all-pairs index c -> (i, j), i < j < n.
+__device__ inline void all_pairs_decode(int64_t c, int64_t n, uint32_t &i_out, uint32_t &j_out) {
+  const double b = 2.0 * double(n) - 1.0;
+  int64_t i = int64_t((b - sqrt(b * b - 8.0 * double(c))) * 0.5);
+  if (i < 0) i = 0;
+  if (i > n - 2) i = n - 2;
+  auto start = [n](int64_t r) { return r * n - r * (r + 1) / 2; };
+  while (i > 0 && start(i) > c) --i;
+  while (i < n - 2 && start(i + 1) <= c) ++i;
+  i_out = uint32_t(i);
+  j_out = uint32_t(c - start(i) + i + 1);
+}
+
+// List containing candidate position c: the l with offsets[l] <= c < offsets[l+1].
+__device__ inline int64_t list_of(const int64_t *offsets, int64_t n_lists, int64_t c) {
+  int64_t lo = 0, hi = n_lists - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline bool fetch_candidate(const VerifyArgs &a, int64_t c, uint32_t &xi, uint32_t &yi) {
+  if (a.kind == BLSH_PAIRS) {
+    xi = __builtin_nontemporal_load(a.x + c);
+    yi = __builtin_nontemporal_load(a.y + c);
+  } else if (a.kind == BLSH_ALL_PAIRS) {
+    all_pairs_decode(c, a.all_n, xi, yi);
+  } else {
+    const int64_t l = list_of(a.offsets, a.n_lists, c);
+    xi = a.query[l];
+    yi = __builtin_nontemporal_load(a.cand + c);
+  }
+  return xi < a.n_obj && yi < a.n_obj;
+}
+
+// S_hat for an emitted pair (Section 3 eqn map; Section 4.1 Beta mode; Section 4.2 r2c(m/n)).
+__device__ inline float map_estimate(int measure, int m, int n, double alpha, double beta) {
+  if (measure == BLSH_JACCARD) {
+    double s = (m + alpha - 1.0) / (n + alpha + beta - 2.0);
+    s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+    return float(s);
+  }
+  double r = double(m) / double(n);
+  r = r < 0.5 ? 0.5 : r;
+  return float(cos(3.14159265358979323846 * (1.0 - r)));
+}
+
+__device__ inline double tab_f64(const uint32_t *tab, int w) {
+  return __hiloint2double(int(tab[w + 1]), int(tab[w]));
+}
+
+__device__ inline bool accept_bit(const uint32_t *tab, int words, int j, int m) {
+  return (tab[kTabAccOff + j * words + (m >> 5)] >> (m & 31)) & 1u;
+}
+
+// Wave-level compaction of (idx, val) into the accepted list; called in
+// converged control flow by every active lane of the wave.
+__device__ inline void emit_accepted(const VerifyArgs &a, bool pred, uint64_t idx, float val) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd((unsigned long long *)a.n_acc, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  if (pred) {
+    const unsigned long long pos = base + lanes_below(mask);
+    if (int64_t(pos) < a.acc_cap) {
+      a.acc_idx[pos] = idx;
+      a.acc_val[pos] = val;
+    } else {
+      raise_status(a.status, BLSH_ETRUNCATED);
+    }
+  }
+}
+
+// Wave-level compaction of Lite survivors into the exact-similarity queue.
+__device__ inline void push_survivor(const VerifyArgs &a, bool pred, uint64_t idx, uint32_t xi, uint32_t yi) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd((unsigned long long *)a.q_n, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  if (pred) {
+    const unsigned long long pos = base + lanes_below(mask);
+    a.q_idx[pos] = idx;
+    a.q_xy[2 * pos] = xi;
+    a.q_xy[2 * pos + 1] = yi;
+  }
+}
+
+// DPP lane permutations (GFX9 encodings).
+constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kDppRowMirror = 0x140;   // lane i <- 15 - i within a row of 16
+constexpr int kDppHalfMirror = 0x141;  // lane i <- 7 - i within each half row
+
+template <int CTRL>
+__device__ inline uint32_t dpp(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over aligned groups of G lanes (G in {1,2,4,8,16}); every lane of the
+// group receives the total.  All lanes of the wave must be active.
+template <int G>
+__device__ inline uint32_t group_sum(uint32_t v) {
+  if constexpr (G >= 2) v += dpp<kDppQuadXor1>(v);
+  if constexpr (G >= 4) v += dpp<kDppQuadXor2>(v);
+  if constexpr (G >= 8) v += dpp<kDppHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp<kDppRowMirror>(v);
+  return v;
+}
+
+// Broadcast lane (group base + S) within aligned groups of G lanes (G <= 16).
+template <int G, int S>
+__device__ inline uint32_t group_bcast(uint32_t v) {
+  constexpr int and_mask = 0x1F & ~(G - 1);
+  constexpr int pattern = and_mask | (S << 5);
+  return uint32_t(__builtin_amdgcn_ds_swizzle(int(v), pattern));
+}
+
+}  // namespace blsh

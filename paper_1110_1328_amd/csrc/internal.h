@@ -1,0 +1,105 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/bayeslsh.h"
+
+namespace blsh {
+
+constexpr int kMaxLevels = 64;
+
+// Thread-local error message; returns `code` for convenient `return fail(...)`.
+int fail(int code, const char *fmt, ...);
+
+#define BLSH_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::blsh::fail(BLSH_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Posterior decision table (Section 4.3): per level j, n = (j+1) k.
+// ---------------------------------------------------------------------------
+struct TableKey {
+  int measure;
+  double t, epsilon, delta, gamma, alpha, beta;
+  int k, n_levels, lite;
+  bool operator<(const TableKey &o) const {
+    return std::tie(measure, t, epsilon, delta, gamma, alpha, beta, k, n_levels, lite) <
+           std::tie(o.measure, o.t, o.epsilon, o.delta, o.gamma, o.alpha, o.beta, o.k, o.n_levels, o.lite);
+  }
+};
+
+struct HostTable {
+  int k = 0, n_levels = 0, n_max = 0, words = 0;
+  std::vector<int32_t> min_matches;   // [n_levels]
+  std::vector<uint32_t> accept;       // [n_levels][words]
+  double min_margin = 1.0;
+};
+
+// Device image of a table, read by every verify kernel into LDS.
+// Layout of the device buffer (32-bit words):
+//   [0] k  [1] n_levels  [2] words  [3] measure
+//   [4..5] alpha (double)  [6..7] beta (double)  [8..9] t (double)
+//   [16 .. 16+64)        min_matches
+//   [80 .. 80+L*words)   accept bits
+constexpr int kTabMinOff = 16;
+constexpr int kTabAccOff = 16 + kMaxLevels;
+
+int build_table(const TableKey &key, HostTable *out);  // host FP64, tables.cpp
+
+struct DevTable {
+  uint32_t *ptr = nullptr;
+  size_t words = 0;
+};
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t start, stop;
+};
+
+}  // namespace blsh
+
+struct blsh_ctx {
+  int device = 0;
+  int n_cu = 256;
+  std::mutex mu;
+  std::map<blsh::TableKey, std::shared_ptr<blsh::HostTable>> host_tables;
+  std::map<blsh::TableKey, blsh::DevTable> dev_tables;
+  // device status word: first error raised by a kernel (0 = none)
+  int32_t *d_status = nullptr;
+  // survivor workspace
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  // profiling
+  bool prof = false;
+  std::vector<blsh::ProfRec> prof_pending;
+  std::map<std::string, std::pair<double, int64_t>> prof_acc;
+};
+
+namespace blsh {
+int get_table(blsh_ctx *ctx, const TableKey &key, std::shared_ptr<HostTable> *host, const uint32_t **dev,
+              hipStream_t stream);
+int ensure_workspace(blsh_ctx *ctx, size_t bytes);
+
+// Launch helper with optional event bracketing.
+struct LaunchScope {
+  blsh_ctx *ctx;
+  hipStream_t stream;
+  const char *name;
+  hipEvent_t a{}, b{};
+  bool on;
+  LaunchScope(blsh_ctx *c, hipStream_t s, const char *n);
+  ~LaunchScope();
+};
+}  // namespace blsh

@@ -1,0 +1,234 @@
+// Signature generation kernels for gfx950 (Section 4 LSH families).
+//
+//   k_minhash          one wave per set, lanes over hash functions; each lane keeps
+//                      the running minimum of (a_h e + b_h) mod (2^31 - 1) over the
+//                      set's elements (Section 4.1).
+//   k_srp_sparse       one wave per sparse row, lanes over groups of 4 hashes; plane
+//                      entries come from Philox-4x32-10 + Box-Muller (FP64), the
+//                      projections accumulate in FP64, and the sign bits are packed
+//                      32 to a word with DPP (Section 4.2).
+//   k_srp_dense_mfma   dense rows times a Gaussian plane matrix on the matrix cores
+//                      (v_mfma_f32_32x32x2f32); each wave keeps 32 rows of X in
+//                      registers, the block stages a 32-plane slice of R in LDS, and
+//                      the sign of every accumulator is packed with a wave ballot.
+#include "device_common.h"
+
+namespace blsh {
+
+// ---------------------------------------------------------------------------
+// Minhash
+// ---------------------------------------------------------------------------
+template <int HPL>  // hashes per lane
+__global__ __launch_bounds__(256) void k_minhash(const int64_t *offsets, const uint32_t *elems, int64_t n_sets,
+                                                 const uint32_t *a, const uint32_t *b, int32_t n_hashes,
+                                                 uint32_t *out, int32_t *status) {
+  const int lane = lane_id();
+  const int64_t set = __builtin_amdgcn_readfirstlane(int(blockIdx.x)) * int64_t(4) + (threadIdx.x >> 6);
+  if (set >= n_sets) return;
+  constexpr uint64_t P = 2147483647ull;
+  uint64_t ah[HPL], bh[HPL];
+  uint32_t best[HPL];
+#pragma unroll
+  for (int i = 0; i < HPL; ++i) {
+    const int h = lane + kWave * i;
+    ah[i] = h < n_hashes ? a[h] : 0;
+    bh[i] = h < n_hashes ? b[h] : 0;
+    best[i] = 0xFFFFFFFFu;
+  }
+  const int64_t s = offsets[set], e = offsets[set + 1];
+  if (e <= s) raise_status(status, BLSH_EINVAL);
+  for (int64_t q = s; q < e; ++q) {
+    const uint64_t el = elems[q];
+#pragma unroll
+    for (int i = 0; i < HPL; ++i) {
+      uint64_t v = ah[i] * el + bh[i];
+      v = (v & P) + (v >> 31);
+      v = (v & P) + (v >> 31);
+      if (v >= P) v -= P;
+      best[i] = min(best[i], uint32_t(v));
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < HPL; ++i) {
+    const int h = lane + kWave * i;
+    if (h < n_hashes) out[size_t(set) * n_hashes + h] = best[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon et al., SC 2011) and the plane entries
+// ---------------------------------------------------------------------------
+__device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// The four plane entries for hashes 4q..4q+3 at coordinate `term`.
+__device__ inline void srp_gauss4(uint32_t term, uint32_t q, uint32_t k0, uint32_t k1, double g[4]) {
+  const uint4 w = philox4x32_10(make_uint4(term, q, 0u, 0u), k0, k1);
+  const double two32 = 4294967296.0, two_pi = 6.283185307179586476925286766559;
+  const double u0 = (double(w.x) + 0.5) / two32, u1 = (double(w.y) + 0.5) / two32;
+  const double u2 = (double(w.z) + 0.5) / two32, u3 = (double(w.w) + 0.5) / two32;
+  const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+  g[0] = double(float(r0 * cos(two_pi * u1)));
+  g[1] = double(float(r0 * sin(two_pi * u1)));
+  g[2] = double(float(r1 * cos(two_pi * u3)));
+  g[3] = double(float(r1 * sin(two_pi * u3)));
+}
+
+template <int G>
+__device__ inline uint32_t group_or(uint32_t v) {
+  if constexpr (G >= 2) v |= dpp<kDppQuadXor1>(v);
+  if constexpr (G >= 4) v |= dpp<kDppQuadXor2>(v);
+  if constexpr (G >= 8) v |= dpp<kDppHalfMirror>(v);
+  return v;
+}
+
+template <int QPL>  // quads (4 hashes) per lane
+__global__ __launch_bounds__(256) void k_srp_sparse(const int64_t *offsets, const uint32_t *indices,
+                                                    const float *values, int64_t n_rows, int32_t n_bits,
+                                                    uint32_t k0, uint32_t k1, int32_t word_major, uint32_t *out) {
+  const int lane = lane_id();
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= n_rows) return;  // wave-uniform
+  const int Q = n_bits / 4, W = n_bits / 32;
+  double acc[QPL][4];
+#pragma unroll
+  for (int i = 0; i < QPL; ++i)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[i][c] = 0.0;
+  const int64_t s = offsets[row], e = offsets[row + 1];
+  for (int64_t t = s; t < e; ++t) {
+    const uint32_t term = indices[t];
+    const double v = values[t];
+#pragma unroll
+    for (int i = 0; i < QPL; ++i) {
+      const int q = lane + kWave * i;
+      if (q < Q) {
+        double g[4];
+        srp_gauss4(term, uint32_t(q), k0, k1, g);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[i][c] += v * g[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < QPL; ++i) {
+    const int q = lane + kWave * i;
+    uint32_t nib = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) nib |= uint32_t(acc[i][c] >= 0.0) << c;
+    uint32_t word = group_or<8>(q < Q ? nib << (4 * (lane & 7)) : 0u);
+    const int w = q >> 3;
+    if ((lane & 7) == 0 && w < W) {
+      if (word_major) out[size_t(w) * n_rows + row] = word;
+      else out[size_t(row) * W + w] = word;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense SRP on the matrix cores
+// ---------------------------------------------------------------------------
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// X: [n_rows][D] fp32, R: [D][n_bits] fp32.  Block = 4 waves = 128 rows; the
+// D dimension is split between the two half-waves: lanes 0..31 cover
+// d in [0, D/2) and lanes 32..63 cover [D/2, D), so that each lane's A
+// operands are one contiguous half-row of X.
+template <int D>
+__global__ __launch_bounds__(256) void k_srp_dense_mfma(const float *X, int64_t n_rows, const float *R,
+                                                        int32_t n_bits, int32_t word_major, uint32_t *out) {
+  constexpr int HD = D / 2;
+  __shared__ float sR[D * 32];  // one 32-plane slice: sR[d*32 + j] = R[d][col0 + j]
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const int h = lane >> 5, i = lane & 31;
+  const int64_t row0 = int64_t(blockIdx.x) * 128 + wv * 32;
+  const int64_t my_row = row0 + i;
+  float xa[HD];
+  if (my_row < n_rows) {
+    const float4 *src = reinterpret_cast<const float4 *>(X + size_t(my_row) * D + h * HD);
+#pragma unroll
+    for (int q = 0; q < HD / 4; ++q) {
+      const float4 v = src[q];
+      xa[4 * q] = v.x; xa[4 * q + 1] = v.y; xa[4 * q + 2] = v.z; xa[4 * q + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < HD; ++q) xa[q] = 0.f;
+  }
+  const int W = n_bits / 32;
+  // row held in the result word by this lane (lanes 0..31): t = lane
+  const int t = lane & 31;
+  const int my_v = 4 * (t >> 3) + (t & 3), my_h = (t >> 2) & 1;
+  for (int tile = 0; tile < W; ++tile) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < D * 32; idx += 256) {
+      const int d = idx >> 5, j = idx & 31;
+      sR[idx] = R[size_t(d) * n_bits + tile * 32 + j];
+    }
+    __syncthreads();
+    floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < HD; ++s) {
+      const float bv = sR[(h * HD + s) * 32 + i];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[s], bv, acc, 0, 0, 0);
+    }
+    uint32_t word = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const uint64_t mk = __ballot(acc[v] >= 0.f);
+      if (my_v == v) word = my_h ? uint32_t(mk >> 32) : uint32_t(mk);
+    }
+    const int64_t r = row0 + t;
+    if (lane < 32 && r < n_rows) {
+      if (word_major) out[size_t(tile) * n_rows + r] = word;
+      else out[size_t(r) * W + tile] = word;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+int launch_minhash(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *elems, int64_t n_sets, const uint32_t *a,
+                   const uint32_t *b, int n_hashes, uint32_t *out, hipStream_t s) {
+  const int hpl = (n_hashes + kWave - 1) / kWave;
+  const int64_t nb = (n_sets + 3) / 4;
+  LaunchScope ls(ctx, s, "minhash_sigs");
+#define BLSH_MH(N) if (hpl <= N) { hipLaunchKernelGGL(k_minhash<N>, dim3(nb), dim3(256), 0, s, offsets, elems, n_sets, a, b, n_hashes, out, ctx->d_status); return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE; }
+  BLSH_MH(1) BLSH_MH(2) BLSH_MH(4) BLSH_MH(8) BLSH_MH(16)
+#undef BLSH_MH
+  return fail(BLSH_EINVAL, "minhash: n_hashes %d > 1024", n_hashes);
+}
+
+int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *indices, const float *values,
+                      int64_t n_rows, int n_bits, uint64_t seed, bool word_major, uint32_t *out, hipStream_t s) {
+  const int qpl = (n_bits / 4 + kWave - 1) / kWave;
+  const int64_t nb = (n_rows + 3) / 4;
+  const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+  LaunchScope ls(ctx, s, "srp_sparse");
+#define BLSH_SP(N) if (qpl <= N) { hipLaunchKernelGGL(k_srp_sparse<N>, dim3(nb), dim3(256), 0, s, offsets, indices, values, n_rows, n_bits, k0, k1, int(word_major), out); return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE; }
+  BLSH_SP(1) BLSH_SP(2) BLSH_SP(4) BLSH_SP(8)
+#undef BLSH_SP
+  return fail(BLSH_EINVAL, "srp (sparse): n_bits %d > 2048", n_bits);
+}
+
+int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim, const float *R, int n_bits,
+                     bool word_major, uint32_t *out, hipStream_t s) {
+  const int64_t nb = (n_rows + 127) / 128;
+  LaunchScope ls(ctx, s, "srp_dense_mfma");
+#define BLSH_DN(DD) if (dim == DD) { hipLaunchKernelGGL(k_srp_dense_mfma<DD>, dim3(nb), dim3(256), 0, s, X, n_rows, R, n_bits, int(word_major), out); return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE; }
+  BLSH_DN(32) BLSH_DN(64) BLSH_DN(128) BLSH_DN(256)
+#undef BLSH_DN
+  return fail(BLSH_EINVAL, "srp (dense): dim must be 32, 64, 128 or 256 (got %lld)", (long long)dim);
+}
+
+}  // namespace blsh

@@ -1,0 +1,215 @@
+// Host FP64 builder of the posterior decision tables (Section 4.3).
+//
+// For each level j (n = (j+1) k hashes compared) the table holds
+//   minMatches(n): the smallest m with Pr[S >= t | M(m,n)] >= epsilon, found by
+//                  binary search because that probability grows with m;
+//   accept bits:   for m >= minMatches(n), whether Pr[|S - S_hat| < delta | M(m,n)]
+//                  >= 1 - gamma (the cached concentration test).
+//
+// Jaccard (Section 4.1): the posterior is Beta(a, b), a = m + alpha,
+// b = n - m + beta.  With integer a, b the regularized incomplete beta is a
+// binomial tail, I_x(a, b) = Pr[Bin(a+b-1, x) >= a], so every probability is a
+// finite sum of binomial terms (the Beta-binomial closed form), summed in FP64
+// from log-space terms.
+//
+// Cosine (Section 4.2): with r = 1 - theta/pi the posterior density of the
+// angle is proportional to f(theta) = (1 - theta/pi)^m (theta/pi)^(n-m) on
+// [0, pi/2], and the events of interest are angle intervals: S >= t is
+// theta <= arccos(t), and |S - S_hat| < delta is
+// arccos(min(1, S_hat + delta)) < theta < arccos(max(0, S_hat - delta)).
+// Each probability is a ratio of integrals of f, computed by composite
+// Gauss-Legendre quadrature over the angle, in log space relative to the
+// peak of f so that no integral underflows.
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+#include "internal.h"
+
+namespace blsh {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// ---------------- Jaccard: binomial sums ----------------
+// Pr[Bin(N, x) <= c] for integer N >= 0, c, x in [0, 1].
+double binom_cdf(int N, int c, double x) {
+  if (c < 0) return 0.0;
+  if (c >= N) return 1.0;
+  if (x <= 0.0) return 1.0;
+  if (x >= 1.0) return 0.0;
+  const double lx = std::log(x), l1x = std::log1p(-x);
+  const double lgN = std::lgamma(N + 1.0);
+  // Sum whichever tail is shorter; all terms are positive.
+  const double mean = N * x;
+  if (c <= mean) {
+    double s = 0.0;
+    for (int j = 0; j <= c; ++j)
+      s += std::exp(lgN - std::lgamma(j + 1.0) - std::lgamma(N - j + 1.0) + j * lx + (N - j) * l1x);
+    return std::min(1.0, s);
+  }
+  double s = 0.0;
+  for (int j = c + 1; j <= N; ++j)
+    s += std::exp(lgN - std::lgamma(j + 1.0) - std::lgamma(N - j + 1.0) + j * lx + (N - j) * l1x);
+  return std::max(0.0, 1.0 - s);
+}
+
+// I_x(a, b) for integer a, b >= 1.
+double reg_inc_beta_int(int a, int b, double x) {
+  if (x <= 0.0) return 0.0;
+  if (x >= 1.0) return 1.0;
+  return 1.0 - binom_cdf(a + b - 1, a - 1, x);
+}
+
+struct Jaccard {
+  double t, delta, alpha, beta;
+  int ia, ib;
+  double prune_prob(int m, int n) const {   // 1 - I_t(m+alpha, n-m+beta)
+    const int a = m + ia, b = n - m + ib;
+    return binom_cdf(a + b - 1, a - 1, t);
+  }
+  double shat(int m, int n) const {
+    double s = (m + alpha - 1.0) / (n + alpha + beta - 2.0);
+    return std::min(1.0, std::max(0.0, s));
+  }
+  double concentration(int m, int n) const {
+    const int a = m + ia, b = n - m + ib;
+    const double s = shat(m, n);
+    const double hi = std::min(1.0, s + delta), lo = std::max(0.0, s - delta);
+    return reg_inc_beta_int(a, b, hi) - reg_inc_beta_int(a, b, lo);
+  }
+};
+
+// ---------------- Cosine: quadrature over the angle ----------------
+// 16-point Gauss-Legendre nodes/weights on [-1, 1] (positive half; symmetric).
+const double kGLx[8] = {0.0950125098376374401853193, 0.2816035507792589132304605, 0.4580167776572273863424194,
+                        0.6178762444026437484466718, 0.7554044083550030338951012, 0.8656312023878317438804679,
+                        0.9445750230732325760779884, 0.9894009349916499325961542};
+const double kGLw[8] = {0.1894506104550684962853967, 0.1826034150449235888667637, 0.1691565193950025381893121,
+                        0.1495959888165767320815017, 0.1246289712555338720524763, 0.0951585116824927848099251,
+                        0.0622535239386478928628438, 0.0271524594117540948517806};
+
+struct CosinePair {
+  int m, n;
+  double lmax, lo_eff, hi_eff;  // effective support of f on [0, pi/2]
+  double logf(double th) const {
+    double v = 0.0;
+    if (m) v += m * std::log1p(-th / kPi);
+    if (n - m) v += (th > 0.0) ? (n - m) * std::log(th / kPi) : -INFINITY;
+    return v;
+  }
+  CosinePair(int m_, int n_) : m(m_), n(n_) {
+    const double half = kPi / 2.0;
+    double peak = kPi * (1.0 - double(m) / n);
+    peak = std::min(half, std::max(0.0, peak));
+    lmax = logf(peak);
+    const double drop = 75.0;  // e^-75 ~ 3e-33 relative: negligible
+    // f is unimodal: bisection on each side for logf = lmax - drop
+    auto edge = [&](double in, double out) {
+      if (logf(out) >= lmax - drop) return out;
+      for (int it = 0; it < 80; ++it) {
+        double mid = 0.5 * (in + out);
+        if (logf(mid) >= lmax - drop) in = mid; else out = mid;
+      }
+      return out;
+    };
+    lo_eff = edge(peak, 0.0);
+    hi_eff = edge(peak, half);
+  }
+  // integral of f(theta) e^{-lmax} over [a, b] intersected with the support
+  double integral(double a, double b) const {
+    a = std::max(a, lo_eff);
+    b = std::min(b, hi_eff);
+    if (!(b > a)) return 0.0;
+    const double width = hi_eff - lo_eff;
+    int panels = int(std::ceil(96.0 * (b - a) / width)) + 2;
+    const double h = (b - a) / panels;
+    double s = 0.0;
+    for (int p = 0; p < panels; ++p) {
+      const double c = a + (p + 0.5) * h, r = 0.5 * h;
+      double ps = 0.0;
+      for (int q = 0; q < 8; ++q) {
+        ps += kGLw[q] * (std::exp(logf(c - r * kGLx[q]) - lmax) + std::exp(logf(c + r * kGLx[q]) - lmax));
+      }
+      s += ps * r;
+    }
+    return s;
+  }
+};
+
+struct Cosine {
+  double t, delta;
+  double prune_prob(int m, int n) const {
+    CosinePair f(m, n);
+    const double den = f.integral(0.0, kPi / 2.0);
+    return f.integral(0.0, std::acos(t)) / den;
+  }
+  double shat(int m, int n) const { return std::cos(kPi * (1.0 - std::max(0.5, double(m) / n))); }
+  double concentration(int m, int n) const {
+    CosinePair f(m, n);
+    const double den = f.integral(0.0, kPi / 2.0);
+    const double s = shat(m, n);
+    const double th_lo = std::acos(std::min(1.0, s + delta));
+    const double th_hi = std::min(kPi / 2.0, std::acos(std::max(0.0, s - delta)));
+    return f.integral(th_lo, th_hi) / den;
+  }
+};
+
+template <class Model>
+void build_level(const Model &mdl, const TableKey &key, int j, HostTable *out, double *margin) {
+  const int n = (j + 1) * key.k;
+  // minMatches(n): binary search for the first m with prune_prob >= epsilon.
+  int lo = 0, hi = n + 1;  // answer in [lo, hi]; hi = n+1 means "always prune"
+  while (lo < hi) {
+    int mid = (lo + hi) / 2;
+    if (mdl.prune_prob(mid, n) >= key.epsilon) hi = mid; else lo = mid + 1;
+  }
+  const int mm = lo;
+  out->min_matches[j] = mm;
+  double mg = 1.0;
+  if (mm <= n) mg = std::min(mg, std::fabs(mdl.prune_prob(mm, n) - key.epsilon));
+  if (mm > 0 && mm - 1 <= n) mg = std::min(mg, std::fabs(mdl.prune_prob(mm - 1, n) - key.epsilon));
+  if (!key.lite) {
+    for (int m = mm; m <= n; ++m) {
+      const double c = mdl.concentration(m, n);
+      mg = std::min(mg, std::fabs(c - (1.0 - key.gamma)));
+      if (c >= 1.0 - key.gamma) out->accept[size_t(j) * out->words + (m >> 5)] |= 1u << (m & 31);
+    }
+  }
+  *margin = mg;
+}
+
+template <class Model>
+void build_all(const Model &mdl, const TableKey &key, HostTable *out) {
+  std::vector<double> margins(key.n_levels, 1.0);
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nt = std::min<unsigned>(nt, key.n_levels);
+  std::vector<std::thread> th;
+  for (unsigned w = 0; w < nt; ++w)
+    th.emplace_back([&, w] {
+      for (int j = int(w); j < key.n_levels; j += int(nt)) build_level(mdl, key, j, out, &margins[j]);
+    });
+  for (auto &x : th) x.join();
+  out->min_margin = *std::min_element(margins.begin(), margins.end());
+}
+
+}  // namespace
+
+int build_table(const TableKey &key, HostTable *out) {
+  out->k = key.k;
+  out->n_levels = key.n_levels;
+  out->n_max = key.k * key.n_levels;
+  out->words = (out->n_max + 1 + 31) / 32;
+  out->min_matches.assign(key.n_levels, 0);
+  out->accept.assign(size_t(key.n_levels) * out->words, 0u);
+  if (key.measure == BLSH_JACCARD) {
+    Jaccard mdl{key.t, key.delta, key.alpha, key.beta, int(key.alpha), int(key.beta)};
+    build_all(mdl, key, out);
+  } else {
+    Cosine mdl{key.t, key.delta};
+    build_all(mdl, key, out);
+  }
+  return BLSH_OK;
+}
+
+}  // namespace blsh

@@ -1,0 +1,581 @@
+// Verification kernels for gfx950: Algorithm 1 (BayesLSH), Algorithm 2
+// (BayesLSH-Lite) and the exhaustive comparator.
+//
+// Every kernel walks the per-candidate loop of the algorithms: compare k
+// hashes, add the agreements to m, then look up the decision for (m, n) in the
+// precomputed table (minMatches and the concentration cache of Section 4.3).
+//
+//   k_verify_bits     sign-random-projection signatures (cosine); one lane per
+//                     candidate, 4 candidates per lane; level j reads k/32 words
+//                     per side (k = 16 reads half a word).  With the word-major
+//                     layout the words of one level form a dense slab (4 bytes
+//                     per object), so the gathers stay in L2.
+//   k_verify_minhash  minhash signatures (Jaccard); a group of k/4 lanes compares
+//                     one candidate's k hashes with one 16-byte load per lane and
+//                     per side, then sums the agreements with DPP; lane l owns
+//                     candidate l of the wave's tile of 64.
+//   k_exact_*         exact similarity on Lite survivors (one wave per pair).
+//   k_exhaustive_*    the comparator: all n_max hashes of both object-major rows,
+//                     per-level counts, prefix sums, then the decision sequence
+//                     of Algorithm 1/2 replayed (or the classical m/n estimate).
+#include "device_common.h"
+
+namespace blsh {
+
+// ---------------------------------------------------------------------------
+// SRP: one lane per candidate
+// ---------------------------------------------------------------------------
+template <int K, bool WORD_MAJOR>
+__device__ inline uint32_t level_agree_bits(const VerifyArgs &a, uint32_t xi, uint32_t yi, int j) {
+  if constexpr (K == 32) {
+    const uint32_t wx = WORD_MAJOR ? a.sig[size_t(j) * a.n_obj + xi] : a.sig[size_t(xi) * a.row_words + j];
+    const uint32_t wy = WORD_MAJOR ? a.sig[size_t(j) * a.n_obj + yi] : a.sig[size_t(yi) * a.row_words + j];
+    return 32u - __popc(wx ^ wy);
+  } else if constexpr (K == 64) {
+    const int w0 = 2 * j, w1 = 2 * j + 1;
+    uint32_t x0, x1, y0, y1;
+    if (WORD_MAJOR) {
+      x0 = a.sig[size_t(w0) * a.n_obj + xi];
+      x1 = a.sig[size_t(w1) * a.n_obj + xi];
+      y0 = a.sig[size_t(w0) * a.n_obj + yi];
+      y1 = a.sig[size_t(w1) * a.n_obj + yi];
+    } else {
+      x0 = a.sig[size_t(xi) * a.row_words + w0];
+      x1 = a.sig[size_t(xi) * a.row_words + w1];
+      y0 = a.sig[size_t(yi) * a.row_words + w0];
+      y1 = a.sig[size_t(yi) * a.row_words + w1];
+    }
+    return 64u - __popc(x0 ^ y0) - __popc(x1 ^ y1);
+  } else {  // K == 16
+    const int w = j >> 1;
+    const uint32_t wx = WORD_MAJOR ? a.sig[size_t(w) * a.n_obj + xi] : a.sig[size_t(xi) * a.row_words + w];
+    const uint32_t wy = WORD_MAJOR ? a.sig[size_t(w) * a.n_obj + yi] : a.sig[size_t(yi) * a.row_words + w];
+    const uint32_t d = ((wx ^ wy) >> ((j & 1) * 16)) & 0xFFFFu;
+    return 16u - __popc(d);
+  }
+}
+
+constexpr int kPPT = 4;        // candidates per lane (bits kernel)
+constexpr int kBlock = 256;
+
+template <int K, int KIND, bool LITE, bool WORD_MAJOR>
+__global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
+  __shared__ int s_min[kMaxLevels];
+  if (threadIdx.x < kMaxLevels)
+    s_min[threadIdx.x] = threadIdx.x < a.n_levels ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
+  __syncthreads();
+  const int L = a.n_levels;
+  const int words = int(a.table[2]);
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t c0 = a.c_begin + (tile * kBlock + threadIdx.x) * kPPT;
+  const bool any = c0 < a.c_end;
+
+  uint32_t xi[kPPT], yi[kPPT];
+  uint32_t alive = 0, bad = 0;
+  if (any) {
+    if (KIND == BLSH_PAIRS && c0 + kPPT <= a.c_end && ((uintptr_t(a.x + c0) | uintptr_t(a.y + c0)) & 15) == 0) {
+      const u32x4 vx = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.x + c0));
+      const u32x4 vy = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.y + c0));
+      xi[0] = vx.x; xi[1] = vx.y; xi[2] = vx.z; xi[3] = vx.w;
+      yi[0] = vy.x; yi[1] = vy.y; yi[2] = vy.z; yi[3] = vy.w;
+#pragma unroll
+      for (int p = 0; p < kPPT; ++p) {
+        if (xi[p] < a.n_obj && yi[p] < a.n_obj) alive |= 1u << p; else bad |= 1u << p;
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < kPPT; ++p) {
+        xi[p] = yi[p] = 0;
+        if (c0 + p < a.c_end) {
+          if (fetch_candidate(a, c0 + p, xi[p], yi[p])) alive |= 1u << p; else bad |= 1u << p;
+        }
+      }
+    }
+  }
+  uint32_t m[kPPT] = {0, 0, 0, 0};
+  uint8_t code[kPPT] = {0, 0, 0, 0};
+  uint32_t emit = 0;
+  for (int j = 0; j < L && alive; ++j) {
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p)
+      if (alive & (1u << p)) m[p] += level_agree_bits<K, WORD_MAJOR>(a, xi[p], yi[p], j);
+    const int mm = s_min[j];
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p) {
+      if (!(alive & (1u << p))) continue;
+      if (int(m[p]) < mm) {
+        code[p] = uint8_t((BLSH_PRUNED << 6) | j);
+        alive &= ~(1u << p);
+      } else if (!LITE && accept_bit(a.table, words, j, int(m[p]))) {
+        code[p] = uint8_t((BLSH_ACCEPT_CONC << 6) | j);
+        alive &= ~(1u << p);
+        emit |= 1u << p;
+      } else if (j == L - 1) {
+        code[p] = uint8_t(((LITE ? BLSH_LITE_EXACT : BLSH_ACCEPT_NMAX) << 6) | j);
+        alive &= ~(1u << p);
+        emit |= 1u << p;
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < kPPT; ++p)
+    if (bad & (1u << p)) code[p] = 0xFF;
+  if (bad) raise_status(a.status, BLSH_EBADID);
+
+  if (any) {
+    if (c0 + kPPT <= a.c_end && (uintptr_t(a.code + c0) & 3) == 0) {
+      const uint32_t packed = uint32_t(code[0]) | (uint32_t(code[1]) << 8) | (uint32_t(code[2]) << 16) |
+                              (uint32_t(code[3]) << 24);
+      __builtin_nontemporal_store(packed, reinterpret_cast<uint32_t *>(a.code + c0));
+    } else {
+#pragma unroll
+      for (int p = 0; p < kPPT; ++p)
+        if (c0 + p < a.c_end) a.code[c0 + p] = code[p];
+    }
+    if (a.m_dbg) {
+#pragma unroll
+      for (int p = 0; p < kPPT; ++p)
+        if (c0 + p < a.c_end) a.m_dbg[c0 + p] = uint16_t(m[p]);
+    }
+  }
+  // emission in converged control flow
+  if (__ballot(emit != 0) == 0) return;
+  const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
+#pragma unroll
+  for (int p = 0; p < kPPT; ++p) {
+    const bool e = (emit >> p) & 1u;
+    if (LITE) {
+      push_survivor(a, e, uint64_t(c0 + p), xi[p], yi[p]);
+    } else {
+      const int n = ((code[p] & 63) + 1) * K;
+      const float v = e ? map_estimate(a.measure, int(m[p]), n, alpha, beta) : 0.f;
+      emit_accepted(a, e, uint64_t(c0 + p), v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Minhash: a group of K/4 lanes per candidate
+// ---------------------------------------------------------------------------
+template <int G, int S>
+struct MinhashStep {
+  template <int K>
+  __device__ static inline void run(const VerifyArgs &a, uint32_t xi, uint32_t yi, uint32_t alive, int j, int r,
+                                    uint32_t &own) {
+    const uint32_t xs = group_bcast<G, S>(xi);
+    const uint32_t ys = group_bcast<G, S>(yi);
+    const uint32_t al = group_bcast<G, S>(alive);
+    uint32_t c = 0;
+    if (al) {
+      const uint4 hx = *reinterpret_cast<const uint4 *>(a.sig + size_t(xs) * a.row_words + j * K + 4 * r);
+      const uint4 hy = *reinterpret_cast<const uint4 *>(a.sig + size_t(ys) * a.row_words + j * K + 4 * r);
+      c = uint32_t(hx.x == hy.x) + uint32_t(hx.y == hy.y) + uint32_t(hx.z == hy.z) + uint32_t(hx.w == hy.w);
+    }
+    c = group_sum<G>(c);
+    if (r == S) own = c;
+    if constexpr (S + 1 < G) MinhashStep<G, S + 1>::template run<K>(a, xi, yi, alive, j, r, own);
+  }
+};
+
+template <int K, int KIND, bool LITE>
+__global__ __launch_bounds__(kBlock) void k_verify_minhash(VerifyArgs a) {
+  constexpr int G = K / 4;
+  __shared__ int s_min[kMaxLevels];
+  if (threadIdx.x < kMaxLevels)
+    s_min[threadIdx.x] = threadIdx.x < a.n_levels ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
+  __syncthreads();
+  const int L = a.n_levels;
+  const int words = int(a.table[2]);
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t c = a.c_begin + tile * kBlock + threadIdx.x;
+  const int lane = lane_id();
+  const int r = lane & (G - 1);
+  if (__ballot(c < a.c_end) == 0) return;  // whole wave past the end
+
+  uint32_t xi = 0, yi = 0, alive = 0;
+  bool bad = false;
+  if (c < a.c_end) {
+    if (fetch_candidate(a, c, xi, yi)) alive = 1; else { bad = true; xi = yi = 0; }
+  }
+  uint32_t m = 0;
+  uint8_t code = bad ? 0xFF : 0;
+  bool emit = false;
+  for (int j = 0; j < L; ++j) {
+    if (__ballot(alive != 0) == 0) break;
+    uint32_t own = 0;
+    MinhashStep<G, 0>::template run<K>(a, xi, yi, alive, j, r, own);
+    if (alive) {
+      m += own;
+      if (int(m) < s_min[j]) {
+        code = uint8_t((BLSH_PRUNED << 6) | j);
+        alive = 0;
+      } else if (!LITE && accept_bit(a.table, words, j, int(m))) {
+        code = uint8_t((BLSH_ACCEPT_CONC << 6) | j);
+        alive = 0;
+        emit = true;
+      } else if (j == L - 1) {
+        code = uint8_t(((LITE ? BLSH_LITE_EXACT : BLSH_ACCEPT_NMAX) << 6) | j);
+        alive = 0;
+        emit = true;
+      }
+    }
+  }
+  if (bad) raise_status(a.status, BLSH_EBADID);
+  if (c < a.c_end) {
+    a.code[c] = code;
+    if (a.m_dbg) a.m_dbg[c] = uint16_t(m);
+  }
+  if (LITE) {
+    push_survivor(a, emit, uint64_t(c), xi, yi);
+  } else {
+    const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
+    const float v = emit ? map_estimate(a.measure, int(m), ((code & 63) + 1) * K, alpha, beta) : 0.f;
+    emit_accepted(a, emit, uint64_t(c), v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact similarity on Lite survivors: one wave per queued pair
+// ---------------------------------------------------------------------------
+
+__device__ inline double wave_sum_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// position of key in sorted idx[0..n), or -1
+__device__ inline int64_t bsearch_u32(const uint32_t *idx, int64_t n, uint32_t key) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const uint32_t v = idx[mid];
+    if (v < key) lo = mid + 1; else hi = mid;
+  }
+  return (lo < n && idx[lo] == key) ? lo : -1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_exact(ExactArgs e, VerifyArgs a) {
+  const int lane = lane_id();
+  const int64_t n = *e.q_n;
+  const int64_t waves = int64_t(gridDim.x) * (kBlock / kWave);
+  for (int64_t q = int64_t(blockIdx.x) * (kBlock / kWave) + (threadIdx.x >> 6); q < n; q += waves) {
+    const uint32_t xi = e.q_xy[2 * q], yi = e.q_xy[2 * q + 1];
+    double s = 0.0;
+    if (e.vec_kind == BLSH_DENSE) {
+      const float *u = e.dense + size_t(xi) * e.dim, *v = e.dense + size_t(yi) * e.dim;
+      double nx = 0, ny = 0, dot = 0;
+      for (int64_t d = lane; d < e.dim; d += kWave) {
+        const double p = u[d], qv = v[d];
+        nx += p * p; ny += qv * qv; dot += p * qv;
+      }
+      nx = wave_sum_f64(nx); ny = wave_sum_f64(ny); dot = wave_sum_f64(dot);
+      s = (nx > 0 && ny > 0) ? dot / (sqrt(nx) * sqrt(ny)) : 0.0;
+    } else {
+      int64_t ax = e.offsets[xi], nxl = e.offsets[xi + 1] - ax;
+      int64_t ay = e.offsets[yi], nyl = e.offsets[yi + 1] - ay;
+      // iterate the shorter row, search the longer
+      int64_t as = ax, ns = nxl, al = ay, nl = nyl;
+      if (nxl > nyl) { as = ay; ns = nyl; al = ax; nl = nxl; }
+      if (e.vec_kind == BLSH_SETS) {
+        uint32_t inter = 0;
+        for (int64_t i = lane; i < ns; i += kWave) inter += bsearch_u32(e.indices + al, nl, e.indices[as + i]) >= 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) inter += __shfl_xor(inter, o);
+        const int64_t uni = nxl + nyl - int64_t(inter);
+        s = uni > 0 ? double(inter) / double(uni) : 0.0;
+      } else {
+        double nx = 0, ny = 0, dot = 0;
+        for (int64_t i = lane; i < nxl; i += kWave) { const double v = e.values[ax + i]; nx += v * v; }
+        for (int64_t i = lane; i < nyl; i += kWave) { const double v = e.values[ay + i]; ny += v * v; }
+        for (int64_t i = lane; i < ns; i += kWave) {
+          const int64_t pos = bsearch_u32(e.indices + al, nl, e.indices[as + i]);
+          if (pos >= 0) dot += double(e.values[as + i]) * double(e.values[al + pos]);
+        }
+        nx = wave_sum_f64(nx); ny = wave_sum_f64(ny); dot = wave_sum_f64(dot);
+        s = (nx > 0 && ny > 0) ? dot / (sqrt(nx) * sqrt(ny)) : 0.0;
+      }
+    }
+    if (lane == 0 && s > e.t) {
+      const unsigned long long pos = atomicAdd((unsigned long long *)a.n_acc, 1ull);
+      if (int64_t(pos) < a.acc_cap) {
+        a.acc_idx[pos] = e.q_idx[q];
+        a.acc_val[pos] = float(s);
+      } else {
+        raise_status(a.status, BLSH_ETRUNCATED);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exhaustive comparator
+// ---------------------------------------------------------------------------
+// Decision replay over cumulative counts: returns true when level j with m
+// agreements ends the per-candidate loop, and sets the decision.
+__device__ inline bool replay_decides(const VerifyArgs &a, const int *s_min, int words, int j, int m, int &dec) {
+  const int L = a.n_levels;
+  if (m < s_min[j]) { dec = BLSH_PRUNED; return true; }
+  if (a.mode == BLSH_REPLAY) {
+    if (accept_bit(a.table, words, j, m)) { dec = BLSH_ACCEPT_CONC; return true; }
+    if (j == L - 1) { dec = BLSH_ACCEPT_NMAX; return true; }
+  } else if (j == L - 1) {
+    dec = BLSH_LITE_EXACT;
+    return true;
+  }
+  return false;
+}
+
+// SRP rows of W words (W % 4 == 0, W <= 64): G = W/4 lanes per candidate, one
+// 16-byte load per lane and side; lane r holds words 4r..4r+3.
+template <int K, int G>
+__global__ __launch_bounds__(kBlock) void k_exhaustive_bits(VerifyArgs a) {
+  __shared__ int s_min[kMaxLevels];
+  if (threadIdx.x < kMaxLevels)
+    s_min[threadIdx.x] = threadIdx.x < a.n_levels ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
+  __syncthreads();
+  constexpr int PPW = kWave / G;            // candidates per wave step
+  constexpr int LPL = 128 / K;              // levels per lane
+  const int words = int(a.table[2]);
+  const int lane = lane_id(), r = lane % G, g = lane / G;
+  const int64_t wave = (xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / kWave;
+  const int64_t c = a.c_begin + wave * PPW + g;
+  const bool in = c < a.c_end;
+  uint32_t xi = 0, yi = 0;
+  bool ok = false;
+  if (in) ok = fetch_candidate(a, c, xi, yi);
+  // per-level agreement counts of this lane's 128 bits
+  uint32_t cnt[LPL];
+  uint32_t tot = 0;
+  if (ok && 4 * r < a.row_words) {
+    const uint4 hx = *reinterpret_cast<const uint4 *>(a.sig + size_t(xi) * a.row_words + 4 * r);
+    const uint4 hy = *reinterpret_cast<const uint4 *>(a.sig + size_t(yi) * a.row_words + 4 * r);
+    const uint32_t d[4] = {hx.x ^ hy.x, hx.y ^ hy.y, hx.z ^ hy.z, hx.w ^ hy.w};
+#pragma unroll
+    for (int q = 0; q < LPL; ++q) {
+      if constexpr (K == 16) cnt[q] = 16u - __popc((d[q >> 1] >> ((q & 1) * 16)) & 0xFFFFu);
+      else if constexpr (K == 32) cnt[q] = 32u - __popc(d[q]);
+      else cnt[q] = 64u - __popc(d[2 * q]) - __popc(d[2 * q + 1]);
+      tot += cnt[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < LPL; ++q) cnt[q] = 0;
+  }
+  // exclusive prefix of lane totals within the group
+  uint32_t incl = tot;
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    const uint32_t v = __shfl_up(incl, o, G);
+    if (r >= o) incl += v;
+  }
+  uint32_t run = incl - tot;
+  const int L = a.n_levels;
+  int dec = -1, dj = 0, dm = 0;
+  if (a.mode == BLSH_MLE) {
+    uint32_t total = __shfl(incl, g * G + G - 1);
+    dm = int(total);
+    dj = a.count_levels - 1;
+    dec = -2;  // resolved below by lane r == 0
+  } else {
+#pragma unroll
+    for (int q = 0; q < LPL; ++q) {
+      run += cnt[q];
+      const int j = r * LPL + q;
+      int d;
+      if (dec < 0 && j < L && replay_decides(a, s_min, words, j, int(run), d)) { dec = d; dj = j; dm = int(run); }
+    }
+  }
+  // first deciding lane of the group
+  const uint64_t has = __ballot(dec >= 0);
+  const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << (g * G);
+  const uint64_t mine = has & gmask;
+  const int first = mine ? __ffsll((unsigned long long)mine) - 1 : g * G;
+  const int fdec = __shfl(dec, first), fj = __shfl(dj, first), fm = __shfl(dm, first);
+  bool emit = false, surv = false;
+  float val = 0.f;
+  if (in && r == 0) {
+    uint8_t code;
+    if (!ok) {
+      code = 0xFF;
+      raise_status(a.status, BLSH_EBADID);
+    } else if (a.mode == BLSH_MLE) {
+      const int n = a.count_levels * K;
+      double s = double(fm) / n;
+      if (a.measure == BLSH_COSINE) s = cos(3.14159265358979323846 * (1.0 - s));
+      emit = s >= a.t;
+      val = float(s);
+      code = uint8_t(((emit ? BLSH_ACCEPT_NMAX : BLSH_PRUNED) << 6) | fj);
+    } else {
+      code = uint8_t((fdec << 6) | fj);
+      if (fdec == BLSH_ACCEPT_CONC || fdec == BLSH_ACCEPT_NMAX) {
+        emit = true;
+        val = map_estimate(a.measure, fm, (fj + 1) * K, tab_f64(a.table, 4), tab_f64(a.table, 6));
+      } else if (fdec == BLSH_LITE_EXACT) {
+        surv = true;
+      }
+    }
+    a.code[c] = code;
+    if (a.m_dbg) a.m_dbg[c] = uint16_t(fm);
+  }
+  if (a.mode == BLSH_REPLAY_LITE) push_survivor(a, surv, uint64_t(c), xi, yi);
+  else emit_accepted(a, emit, uint64_t(c), val);
+}
+
+// Minhash rows of H <= 256 hashes: one candidate per wave step, lane r holds
+// hashes 4r..4r+3; a wave-wide prefix gives the cumulative count at each level.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_exhaustive_minhash(VerifyArgs a) {
+  __shared__ int s_min[kMaxLevels];
+  if (threadIdx.x < kMaxLevels)
+    s_min[threadIdx.x] = threadIdx.x < a.n_levels ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
+  __syncthreads();
+  constexpr int LPG = K / 4;                 // lanes per level
+  const int words = int(a.table[2]);
+  const int lane = lane_id();
+  const int64_t wave = (xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / kWave;
+  const int64_t c = a.c_begin + wave;
+  if (c >= a.c_end) return;                  // wave-uniform
+  uint32_t xi = 0, yi = 0;
+  const bool ok = fetch_candidate(a, c, xi, yi);
+  uint32_t cnt = 0;
+  const int H = a.count_levels * K;
+  if (ok && 4 * lane < H) {
+    const uint4 hx = *reinterpret_cast<const uint4 *>(a.sig + size_t(xi) * a.row_words + 4 * lane);
+    const uint4 hy = *reinterpret_cast<const uint4 *>(a.sig + size_t(yi) * a.row_words + 4 * lane);
+    cnt = uint32_t(hx.x == hy.x) + uint32_t(hx.y == hy.y) + uint32_t(hx.z == hy.z) + uint32_t(hx.w == hy.w);
+  }
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t v = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += v;
+  }
+  const int L = a.n_levels;
+  int dec = -1, dj = 0, dm = 0;
+  const int j = lane / LPG;
+  if (a.mode != BLSH_MLE && (lane % LPG) == LPG - 1 && j < L) {
+    int d;
+    if (replay_decides(a, s_min, words, j, int(incl), d)) { dec = d; dj = j; dm = int(incl); }
+  }
+  const uint64_t has = __ballot(dec >= 0);
+  const int first = has ? __ffsll((unsigned long long)has) - 1 : 0;
+  const int fdec = __shfl(dec, first), fj = __shfl(dj, first), fm = __shfl(dm, first);
+  const uint32_t total = __shfl(incl, kWave - 1);
+  bool emit = false, surv = false;
+  float val = 0.f;
+  if (lane == 0) {
+    uint8_t code;
+    int mval = fm;
+    if (!ok) {
+      code = 0xFF;
+      raise_status(a.status, BLSH_EBADID);
+    } else if (a.mode == BLSH_MLE) {
+      const double s = double(total) / H;
+      emit = s >= a.t;
+      val = float(s);
+      mval = int(total);
+      code = uint8_t(((emit ? BLSH_ACCEPT_NMAX : BLSH_PRUNED) << 6) | (a.count_levels - 1));
+    } else {
+      code = uint8_t((fdec << 6) | fj);
+      if (fdec == BLSH_ACCEPT_CONC || fdec == BLSH_ACCEPT_NMAX) {
+        emit = true;
+        val = map_estimate(a.measure, fm, (fj + 1) * K, tab_f64(a.table, 4), tab_f64(a.table, 6));
+      } else if (fdec == BLSH_LITE_EXACT) {
+        surv = true;
+      }
+    }
+    a.code[c] = code;
+    if (a.m_dbg) a.m_dbg[c] = uint16_t(mval);
+  }
+  if (a.mode == BLSH_REPLAY_LITE) push_survivor(a, surv, uint64_t(c), xi, yi);
+  else emit_accepted(a, emit, uint64_t(c), val);
+}
+
+__global__ void k_zero_i64(int64_t *p, int n) {
+  if (int(threadIdx.x) < n) p[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline int64_t blocks_for(int64_t items, int64_t per_block) { return (items + per_block - 1) / per_block; }
+
+template <int K, bool LITE, bool WM>
+static int launch_bits_kind(const VerifyArgs &a, int64_t nb, hipStream_t s) {
+  switch (a.kind) {
+    case BLSH_PAIRS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_PAIRS, LITE, WM>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    case BLSH_QUERY_LISTS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_QUERY_LISTS, LITE, WM>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_verify_bits<K, BLSH_ALL_PAIRS, LITE, WM>), dim3(nb), dim3(kBlock), 0, s, a); break;
+  }
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+template <int K, bool LITE>
+static int launch_minhash_kind(const VerifyArgs &a, int64_t nb, hipStream_t s) {
+  switch (a.kind) {
+    case BLSH_PAIRS: hipLaunchKernelGGL((k_verify_minhash<K, BLSH_PAIRS, LITE>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    case BLSH_QUERY_LISTS: hipLaunchKernelGGL((k_verify_minhash<K, BLSH_QUERY_LISTS, LITE>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_verify_minhash<K, BLSH_ALL_PAIRS, LITE>), dim3(nb), dim3(kBlock), 0, s, a); break;
+  }
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool word_major, hipStream_t s) {
+  const int64_t n = a.c_end - a.c_begin;
+  if (n <= 0) return BLSH_OK;
+  if (a.measure == BLSH_COSINE) {
+    const int64_t nb = blocks_for(n, int64_t(kBlock) * kPPT);
+    LaunchScope ls(ctx, s, "verify_bits");
+#define BLSH_B(KK, LL, WW) if (k == KK && lite == LL && word_major == WW) return launch_bits_kind<KK, LL, WW>(a, nb, s);
+    BLSH_B(16, false, true) BLSH_B(16, true, true) BLSH_B(16, false, false) BLSH_B(16, true, false)
+    BLSH_B(32, false, true) BLSH_B(32, true, true) BLSH_B(32, false, false) BLSH_B(32, true, false)
+    BLSH_B(64, false, true) BLSH_B(64, true, true) BLSH_B(64, false, false) BLSH_B(64, true, false)
+#undef BLSH_B
+  } else {
+    const int64_t nb = blocks_for(n, kBlock);
+    LaunchScope ls(ctx, s, "verify_minhash");
+#define BLSH_M(KK, LL) if (k == KK && lite == LL) return launch_minhash_kind<KK, LL>(a, nb, s);
+    BLSH_M(16, false) BLSH_M(16, true) BLSH_M(32, false) BLSH_M(32, true) BLSH_M(64, false) BLSH_M(64, true)
+#undef BLSH_M
+  }
+  return fail(BLSH_EINVAL, "unsupported k=%d", k);
+}
+
+int launch_exhaustive(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s) {
+  const int64_t n = a.c_end - a.c_begin;
+  if (n <= 0) return BLSH_OK;
+  if (a.measure == BLSH_COSINE) {
+    const int G = (a.count_levels * k / 32) / 4;  // lanes per candidate: n_max bits, 128 per lane
+    LaunchScope ls(ctx, s, "exhaustive_bits");
+    const int64_t nb = blocks_for(n, int64_t(kBlock / G));
+#define BLSH_E(KK, GG) if (k == KK && G == GG) { hipLaunchKernelGGL((k_exhaustive_bits<KK, GG>), dim3(nb), dim3(kBlock), 0, s, a); return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE; }
+    BLSH_E(16, 1) BLSH_E(16, 2) BLSH_E(16, 4) BLSH_E(16, 8) BLSH_E(16, 16)
+    BLSH_E(32, 1) BLSH_E(32, 2) BLSH_E(32, 4) BLSH_E(32, 8) BLSH_E(32, 16)
+    BLSH_E(64, 1) BLSH_E(64, 2) BLSH_E(64, 4) BLSH_E(64, 8) BLSH_E(64, 16)
+#undef BLSH_E
+    return fail(BLSH_EINVAL, "exhaustive: unsupported signature width %d words", a.row_words);
+  }
+  LaunchScope ls(ctx, s, "exhaustive_minhash");
+  const int64_t nb = blocks_for(n, kBlock / kWave);
+  if (k == 16) hipLaunchKernelGGL((k_exhaustive_minhash<16>), dim3(nb), dim3(kBlock), 0, s, a);
+  else if (k == 32) hipLaunchKernelGGL((k_exhaustive_minhash<32>), dim3(nb), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_exhaustive_minhash<64>), dim3(nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+int launch_exact(blsh_ctx *ctx, const ExactArgs &e, const VerifyArgs &a, int64_t max_items, hipStream_t s) {
+  if (max_items <= 0) return BLSH_OK;
+  const int64_t nb = std::min<int64_t>(blocks_for(max_items, kBlock / kWave), int64_t(ctx->n_cu) * 8);
+  LaunchScope ls(ctx, s, "exact");
+  hipLaunchKernelGGL(k_exact, dim3(nb), dim3(kBlock), 0, s, e, a);
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+int launch_zero(blsh_ctx *ctx, int64_t *p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, p, n);
+  (void)ctx;
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+}  // namespace blsh

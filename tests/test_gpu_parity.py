@@ -1,0 +1,383 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Decisions, decision levels and match counts are compared bit for bit; S_hat
+and exact similarities within 1e-6 absolute.  Decision parity always runs on
+identical signature inputs (drawn by the seeded generators, or minhash
+signatures that are first shown to be bit-identical); SRP signature
+generation is checked separately against the FP64 oracle with the sign-flip
+rule (bits may differ only where |r . x| < 1e-5).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1110_1328_amd as P
+from oracle import reference as R
+from synth import generators as G
+
+from gpu_util import assert_same_as_oracle, csr_device, decode_result, down, sets_device, sigs_tensor, up
+
+pytestmark = pytest.mark.gpu
+
+T, EPS, DELTA, GAMMA = 0.7, 0.03, 0.05, 0.03
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    c = P.bayeslsh_create(0)
+    yield c
+    c.close()
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+def run_verify(ctx, cand, sigs, t=T, k=32, prior=(1.0, 1.0), cap=None, m_debug=True):
+    n = cand.count
+    res = P.make_result(n, cap if cap is not None else max(16, n), m_debug=m_debug)
+    P.bayeslsh_verify(ctx, cand, sigs, t, EPS, DELTA, GAMMA, prior, k, res)
+    P.bayeslsh_sync(ctx)
+    return res
+
+
+# ---------------------------------------------------------------------------
+# signatures
+# ---------------------------------------------------------------------------
+def test_minhash_signatures_bit_exact(ctx):
+    _flush("minhash sigs: 400 sets x 256 hashes")
+    sets = G.jaccard_sets(n_sets=400, vocab=100_000, n_groups=20, seed=G.SEED_BASE + 11)
+    a, b = G.minhash_coeffs(256, G.SEED_BASE + 12)
+    out = torch.empty(sets.n * 256, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_minhash_sigs(ctx, sets_device(sets), up(a), up(b), out)
+    P.bayeslsh_sync(ctx)
+    got = down(out).reshape(sets.n, 256)
+    want = R.minhash_signatures(sets.offsets, sets.elems, a, b)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("n_bits,layout", [(2048, P.WORD_MAJOR), (128, P.OBJECT_MAJOR), (96, P.WORD_MAJOR)])
+def test_sparse_srp_signatures_flip_rule(ctx, n_bits, layout):
+    _flush("sparse srp sigs: %d bits layout %d" % (n_bits, layout))
+    corpus = G.tfidf_corpus(n_docs=300, dim=1 << 20, seed=G.SEED_BASE + 21)
+    seed = 0x1234_5678_9ABC
+    W = n_bits // 32
+    out = torch.empty(corpus.n * W, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, csr_device(corpus), None, n_bits, seed, layout, out)
+    P.bayeslsh_sync(ctx)
+    got = down(out).reshape((W, corpus.n) if layout == P.WORD_MAJOR else (corpus.n, W))
+    if layout == P.WORD_MAJOR:
+        got = got.T
+    rows = np.arange(corpus.n, dtype=np.int64)
+    proj = R.srp_sparse_projections(corpus.offsets, corpus.indices, corpus.values, n_bits, seed, rows)
+    want = R.bits_from_projections(proj)
+    diff = np.unpackbits((got ^ want).view(np.uint8), bitorder="little").reshape(corpus.n, n_bits).astype(bool)
+    assert np.all(np.abs(proj[diff]) < 1e-5), np.abs(proj[diff]).max()
+    assert diff.sum() <= max(1, 1e-6 * diff.size)
+
+
+@pytest.mark.parametrize("d,n_bits,layout", [(256, 1024, P.WORD_MAJOR), (64, 64, P.OBJECT_MAJOR),
+                                             (128, 256, P.OBJECT_MAJOR)])
+def test_dense_srp_mfma_flip_rule(ctx, d, n_bits, layout):
+    _flush("dense srp sigs: d=%d bits=%d" % (d, n_bits))
+    mix = G.dense_mixture(n=5000 + 37, d=d, n_comp=50, seed=G.SEED_BASE + 31)   # ragged row tail
+    Rm = G.gaussian_planes(d, n_bits, G.SEED_BASE + 32)
+    W = n_bits // 32
+    out = torch.empty(mix.x.shape[0] * W, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(up(mix.x)), up(Rm), n_bits, 0, layout, out)
+    P.bayeslsh_sync(ctx)
+    n = mix.x.shape[0]
+    got = down(out).reshape((W, n) if layout == P.WORD_MAJOR else (n, W))
+    if layout == P.WORD_MAJOR:
+        got = got.T
+    proj = R.srp_dense_projections(mix.x, Rm)
+    want = R.bits_from_projections(proj)
+    diff = np.unpackbits((got ^ want).view(np.uint8), bitorder="little").reshape(n, n_bits).astype(bool)
+    assert np.all(np.abs(proj[diff]) < 1e-5), np.abs(proj[diff]).max()
+    assert diff.sum() <= max(1, 1e-6 * diff.size)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1
+# ---------------------------------------------------------------------------
+def _calib_pairs(measure, npairs, n_hashes, seed, lo=None):
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(lo if lo is not None else (0.5 if measure else 0.0), 1.0, npairs)
+    if measure == P.JACCARD:
+        return G.calibration_minhash(npairs, n_hashes, s, seed)
+    return G.pack_bits(G.calibration_bits(npairs, n_hashes, s, seed))
+
+
+@pytest.mark.parametrize("measure", [P.JACCARD, P.COSINE])
+@pytest.mark.parametrize("k", [16, 32, 64])
+def test_verify_pairs_bit_exact(ctx, measure, k):
+    """Pairs with similarities spread over the whole range; ragged count."""
+    n_hashes = 256 if measure == P.JACCARD else 1024
+    npairs = 20000 + 13
+    _flush("verify pairs measure=%d k=%d" % (measure, k))
+    sig = _calib_pairs(measure, npairs, n_hashes, 100 + k + measure)
+    rng = np.random.default_rng(7)
+    x = np.arange(0, 2 * npairs, 2, dtype=np.uint32)
+    y = x + 1
+    # mix in unrelated pairs and self pairs
+    sw = rng.random(npairs) < 0.3
+    y[sw] = rng.integers(0, 2 * npairs, sw.sum()).astype(np.uint32)
+    y[:5] = x[:5]
+    L = n_hashes // k
+    want = R.verify(x, y, measure, sig, k, L, T, EPS, DELTA, GAMMA)
+    layouts = [P.OBJECT_MAJOR] if measure == P.JACCARD else [P.WORD_MAJOR, P.OBJECT_MAJOR]
+    for layout in layouts:
+        res = run_verify(ctx, P.pairs(up(x), up(y)), sigs_tensor(sig, measure, layout), k=k)
+        assert_same_as_oracle(decode_result(res, npairs), want)
+    assert len(set(want["decision"].tolist())) == 3
+
+
+def test_verify_jaccard_workload_all_pairs(ctx):
+    """The Jaccard workload at full size: 2000 sets, all 1,999,000 pairs, 256
+    minhashes, k = 32, t = 0.7, Beta(1,1); explicit pairs give the same result."""
+    _flush("jaccard workload: 2000 sets all pairs")
+    sets = G.jaccard_sets()
+    a, b = G.minhash_coeffs(256, G.SEED_BASE + 101)
+    out = torch.empty(sets.n * 256, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_minhash_sigs(ctx, sets_device(sets), up(a), up(b), out)
+    P.bayeslsh_sync(ctx)
+    sig = R.minhash_signatures(sets.offsets, sets.elems, a, b)
+    np.testing.assert_array_equal(down(out).reshape(sets.n, 256), sig)   # identical inputs from here on
+    want = R.verify(None, None, P.JACCARD, sig, 32, 8, T, EPS, DELTA, GAMMA, all_n=sets.n)
+    S = P.Signatures(out, P.JACCARD, P.OBJECT_MAJOR, sets.n, 256)
+    res = run_verify(ctx, P.all_pairs(sets.n), S)
+    got = decode_result(res, len(want["decision"]))
+    assert_same_as_oracle(got, want)
+    x, y = R.all_pairs_xy(sets.n)
+    res2 = run_verify(ctx, P.pairs(up(x), up(y)), S)
+    assert_same_as_oracle(decode_result(res2, len(x)), want)
+    # planted near-duplicates are found
+    assert got["n_accepted"] >= 50
+
+
+def test_verify_query_lists(ctx):
+    _flush("verify query lists")
+    n_obj, n_hashes = 3000, 512
+    sig = _calib_pairs(P.COSINE, n_obj // 2, n_hashes, 5)
+    rng = np.random.default_rng(3)
+    lens = np.array([0, 1, 5, 64, 0, 1000, 333, 2], np.int64)
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    query = rng.integers(0, n_obj, len(lens)).astype(np.uint32)
+    cand = rng.integers(0, n_obj, offsets[-1]).astype(np.uint32)
+    cand[10:20] = query[3] ^ 1     # the query's calibration partner
+    qx = np.repeat(query, lens)
+    want = R.verify(qx, cand, P.COSINE, sig, 32, 16, 0.6, EPS, DELTA, GAMMA)
+    S = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR)
+    n = int(offsets[-1])
+    res = P.make_result(n, n, m_debug=True)
+    P.bayeslsh_verify(ctx, P.query_lists(up(query), up(offsets), up(cand)), S, 0.6, EPS, DELTA, GAMMA, (1, 1), 32, res)
+    P.bayeslsh_sync(ctx)
+    assert_same_as_oracle(decode_result(res, n), want)
+
+
+def test_verify_nonuniform_prior(ctx):
+    _flush("verify jaccard prior beta(2,3)")
+    npairs = 5000
+    sig = _calib_pairs(P.JACCARD, npairs, 128, 77)
+    x = np.arange(0, 2 * npairs, 2, dtype=np.uint32)
+    want = R.verify(x, x + 1, P.JACCARD, sig, 32, 4, 0.5, EPS, DELTA, GAMMA, alpha=2.0, beta=3.0)
+    res = run_verify(ctx, P.pairs(up(x), up(x + 1)), sigs_tensor(sig, P.JACCARD, P.OBJECT_MAJOR), t=0.5,
+                     prior=(2.0, 3.0))
+    assert_same_as_oracle(decode_result(res, npairs), want)
+
+
+def test_n_max_below_stored_hashes(ctx):
+    """A signature of 1024 bits verified with n_max = 256."""
+    npairs = 3000
+    sig = _calib_pairs(P.COSINE, npairs, 1024, 8)
+    x = np.arange(0, 2 * npairs, 2, dtype=np.uint32)
+    want = R.verify(x, x + 1, P.COSINE, sig, 32, 8, T, EPS, DELTA, GAMMA)
+    for layout in (P.WORD_MAJOR, P.OBJECT_MAJOR):
+        res = run_verify(ctx, P.pairs(up(x), up(x + 1)), sigs_tensor(sig, P.COSINE, layout, n_max=256))
+        assert_same_as_oracle(decode_result(res, npairs), want)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 and exact similarity
+# ---------------------------------------------------------------------------
+def test_lite_cosine_sparse(ctx):
+    _flush("lite cosine sparse")
+    corpus = G.tfidf_corpus(n_docs=3000, dim=1 << 16, mean_nnz=60, dup_frac=0.1, seed=G.SEED_BASE + 41)
+    x, y = G.sparse_band_candidates(corpus, n_bands=8, band_bits=5, seed=G.SEED_BASE + 42)
+    n = len(x)
+    # signatures: oracle SRP of the corpus (an input to both sides)
+    proj = R.srp_sparse_projections(corpus.offsets, corpus.indices, corpus.values, 256, 99,
+                                    np.arange(corpus.n, dtype=np.int64))
+    sig = R.bits_from_projections(proj)
+    want = R.verify(x, y, P.COSINE, sig, 32, 4, T, EPS, 0, 0, lite=True)
+    exact_fn = lambda a, b: R.exact_cosine_csr(corpus.offsets, corpus.indices, corpus.values, a, b)
+    want = R.lite_finish(want, exact_fn, x, y, T)
+    res = P.make_result(n, n, m_debug=True)
+    P.bayeslsh_lite_verify(ctx, P.pairs(up(x), up(y)), sigs_tensor(sig, P.COSINE, P.WORD_MAJOR), csr_device(corpus),
+                           T, EPS, (1, 1), 128, 32, res)
+    P.bayeslsh_sync(ctx)
+    got = decode_result(res, n)
+    assert_same_as_oracle(got, want, lite_exact=want["exact"])
+    assert got["n_accepted"] > 10 and (want["decision"] == R.DEC_LITE).sum() > got["n_accepted"]
+
+
+def test_lite_jaccard_sets_and_dense_cosine(ctx):
+    _flush("lite jaccard sets + dense cosine")
+    sets = G.jaccard_sets(n_sets=600, vocab=20000, n_groups=40, seed=G.SEED_BASE + 51)
+    a, b = G.minhash_coeffs(64, G.SEED_BASE + 52)
+    sig = R.minhash_signatures(sets.offsets, sets.elems, a, b)
+    x, y = R.all_pairs_xy(sets.n)
+    want = R.lite_finish(R.verify(x, y, P.JACCARD, sig, 32, 2, 0.5, EPS, 0, 0, lite=True),
+                         lambda p, q: R.exact_jaccard(sets.offsets, sets.elems, p, q), x, y, 0.5)
+    res = P.make_result(len(x), len(x), m_debug=True)
+    P.bayeslsh_lite_verify(ctx, P.all_pairs(sets.n), sigs_tensor(sig, P.JACCARD, P.OBJECT_MAJOR), sets_device(sets),
+                           0.5, EPS, (1, 1), 64, 32, res)
+    P.bayeslsh_sync(ctx)
+    assert_same_as_oracle(decode_result(res, len(x)), want, lite_exact=want["exact"])
+    # dense exact cosine
+    mix = G.dense_mixture(n=1500, d=256, n_comp=30, seed=G.SEED_BASE + 53)
+    Rm = G.gaussian_planes(256, 256, G.SEED_BASE + 54)
+    sig2 = R.bits_from_projections(R.srp_dense_projections(mix.x, Rm))
+    rng = np.random.default_rng(1)
+    x2 = rng.integers(0, 1500, 40000).astype(np.uint32)
+    y2 = rng.integers(0, 1500, 40000).astype(np.uint32)
+    same = mix.comp[x2] == mix.comp[y2]
+    assert same.sum() > 500
+    want2 = R.lite_finish(R.verify(x2, y2, P.COSINE, sig2, 32, 4, 0.8, EPS, 0, 0, lite=True),
+                          lambda p, q: R.exact_cosine_dense(mix.x, p, q), x2, y2, 0.8)
+    res2 = P.make_result(len(x2), len(x2), m_debug=True)
+    P.bayeslsh_lite_verify(ctx, P.pairs(up(x2), up(y2)), sigs_tensor(sig2, P.COSINE, P.WORD_MAJOR),
+                           P.dense_vectors(up(mix.x)), 0.8, EPS, (1, 1), 128, 32, res2)
+    P.bayeslsh_sync(ctx)
+    assert_same_as_oracle(decode_result(res2, len(x2)), want2, lite_exact=want2["exact"])
+
+
+# ---------------------------------------------------------------------------
+# exhaustive comparator
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("measure,k", [(P.JACCARD, 32), (P.COSINE, 32), (P.COSINE, 16), (P.COSINE, 64),
+                                       (P.JACCARD, 64)])
+def test_exhaustive_replay_equals_verify(ctx, measure, k):
+    _flush("exhaustive replay measure=%d k=%d" % (measure, k))
+    n_hashes = 256 if measure == P.JACCARD else 2048
+    npairs = 10000 + 3
+    sig = _calib_pairs(measure, npairs, n_hashes, 300 + k)
+    x = np.arange(0, 2 * npairs, 2, dtype=np.uint32)
+    L = min(64, n_hashes // k)
+    want = R.verify(x, x + 1, measure, sig, k, L, T, EPS, DELTA, GAMMA)
+    S = sigs_tensor(sig, measure, P.OBJECT_MAJOR, n_max=L * k)
+    res = P.make_result(npairs, npairs, m_debug=True)
+    P.bayeslsh_exhaustive_verify(ctx, P.pairs(up(x), up(x + 1)), S, None, T, EPS, DELTA, GAMMA, (1, 1), k, 0,
+                                 P.REPLAY, res)
+    P.bayeslsh_sync(ctx)
+    assert_same_as_oracle(decode_result(res, npairs), want)
+    # classical estimate over all n_max hashes
+    res = P.make_result(npairs, npairs, m_debug=True)
+    P.bayeslsh_exhaustive_verify(ctx, P.pairs(up(x), up(x + 1)), S, None, T, EPS, DELTA, GAMMA, (1, 1), k, 0,
+                                 P.MLE, res)
+    P.bayeslsh_sync(ctx)
+    got = decode_result(res, npairs)
+    mle = R.mle(x, x + 1, measure, sig, L * k, T)
+    np.testing.assert_array_equal(got["m"], mle["m"])
+    acc = np.flatnonzero(mle["accepted"])
+    np.testing.assert_array_equal(got["acc_idx"], acc)
+    np.testing.assert_allclose(got["acc_val"], mle["shat"][acc], atol=1e-6)
+
+
+def test_exhaustive_lite_replay(ctx):
+    corpus = G.tfidf_corpus(n_docs=2000, dim=1 << 16, mean_nnz=50, dup_frac=0.1, seed=G.SEED_BASE + 61)
+    x, y = G.sparse_band_candidates(corpus, n_bands=8, band_bits=4, seed=G.SEED_BASE + 62)
+    proj = R.srp_sparse_projections(corpus.offsets, corpus.indices, corpus.values, 512, 5,
+                                    np.arange(corpus.n, dtype=np.int64))
+    sig = R.bits_from_projections(proj)
+    want = R.lite_finish(R.verify(x, y, P.COSINE, sig, 32, 4, T, EPS, 0, 0, lite=True),
+                         lambda p, q: R.exact_cosine_csr(corpus.offsets, corpus.indices, corpus.values, p, q), x, y, T)
+    res = P.make_result(len(x), len(x), m_debug=True)
+    P.bayeslsh_exhaustive_verify(ctx, P.pairs(up(x), up(y)), sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR),
+                                 csr_device(corpus), T, EPS, 0.5, 0.5, (1, 1), 32, 128, P.REPLAY_LITE, res)
+    P.bayeslsh_sync(ctx)
+    assert_same_as_oracle(decode_result(res, len(x)), want, lite_exact=want["exact"])
+
+
+# ---------------------------------------------------------------------------
+# edge cases and error paths
+# ---------------------------------------------------------------------------
+def test_empty_and_tiny_inputs(ctx):
+    sig = _calib_pairs(P.COSINE, 4, 256, 1)
+    S = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR)
+    e = torch.empty(0, dtype=torch.int32, device="cuda").view(torch.uint32)
+    res = P.make_result(1, 4)
+    res.n_accepted.fill_(123)
+    P.bayeslsh_verify(ctx, P.pairs(e, e), S, T, EPS, DELTA, GAMMA, (1, 1), 32, res)
+    P.bayeslsh_sync(ctx)
+    assert int(res.n_accepted.item()) == 0
+    for n in (1, 2, 3, 5):
+        x = np.zeros(n, np.uint32)
+        y = np.arange(n, dtype=np.uint32) % 8
+        want = R.verify(x, y, P.COSINE, sig, 32, 8, T, EPS, DELTA, GAMMA)
+        got = decode_result(run_verify(ctx, P.pairs(up(x), up(y)), S), n)
+        assert_same_as_oracle(got, want)
+    res = P.make_result(1, 4)
+    P.bayeslsh_verify(ctx, P.all_pairs(1), S, T, EPS, DELTA, GAMMA, (1, 1), 32, res)
+    P.bayeslsh_sync(ctx)
+    assert int(res.n_accepted.item()) == 0
+
+
+def test_bad_object_ids_are_flagged(ctx):
+    sig = _calib_pairs(P.COSINE, 50, 256, 2)
+    S = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR)
+    x = np.arange(40, dtype=np.uint32)
+    y = x + 1
+    y[7] = 100          # out of range
+    x[20] = 1 << 31
+    res = P.make_result(40, 40)
+    P.bayeslsh_verify(ctx, P.pairs(up(x), up(y)), S, T, EPS, DELTA, GAMMA, (1, 1), 32, res)
+    with pytest.raises(P.BayesLSHError) as e:
+        P.bayeslsh_sync(ctx)
+    assert e.value.code == -5
+    code = res.code.cpu().numpy()
+    assert code[7] == 0xFF and code[20] == 0xFF
+    ok = np.setdiff1d(np.arange(40), [7, 20])
+    want = R.verify(x[ok], y[ok], P.COSINE, sig, 32, 8, T, EPS, DELTA, GAMMA)
+    np.testing.assert_array_equal(code[ok] >> 6, want["decision"])
+    P.bayeslsh_sync(ctx)  # cleared
+
+
+def test_truncation_reports_true_count(ctx):
+    npairs = 4000
+    sig = _calib_pairs(P.JACCARD, npairs, 128, 3, lo=0.9)
+    x = np.arange(0, 2 * npairs, 2, dtype=np.uint32)
+    want = R.verify(x, x + 1, P.JACCARD, sig, 32, 4, T, EPS, DELTA, GAMMA)
+    n_acc = int(((want["decision"] == 1) | (want["decision"] == 2)).sum())
+    assert n_acc > 100
+    res = P.make_result(npairs, 100)
+    P.bayeslsh_verify(ctx, P.pairs(up(x), up(x + 1)), sigs_tensor(sig, P.JACCARD, P.OBJECT_MAJOR), T, EPS, DELTA,
+                      GAMMA, (1, 1), 32, res)
+    with pytest.raises(P.BayesLSHError) as e:
+        P.bayeslsh_sync(ctx)
+    assert e.value.code == -4
+    assert int(res.n_accepted.item()) == n_acc
+    idx = down(res.acc_idx).astype(np.int64)
+    acc = set(np.flatnonzero((want["decision"] == 1) | (want["decision"] == 2)).tolist())
+    assert set(idx.tolist()) <= acc
+
+
+def test_invalid_arguments_rejected(ctx):
+    sig = _calib_pairs(P.COSINE, 10, 256, 4)
+    S = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR)
+    x = up(np.zeros(4, np.uint32))
+    res = P.make_result(4, 4)
+    bad = [dict(t=1.0), dict(k=24), dict(k=128), dict(prior=(2, 2)), dict(epsilon=0.0)]
+    for kw in bad:
+        a = dict(t=T, epsilon=EPS, k=32, prior=(1, 1))
+        a.update(kw)
+        with pytest.raises(P.BayesLSHError) as e:
+            P.bayeslsh_verify(ctx, P.pairs(x, x), S, a["t"], a["epsilon"], DELTA, GAMMA, a["prior"], a["k"], res)
+        assert e.value.code == -1
+    S2 = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR, n_max=96)     # not a multiple of k = 64
+    with pytest.raises(P.BayesLSHError):
+        P.bayeslsh_verify(ctx, P.pairs(x, x), S2, T, EPS, DELTA, GAMMA, (1, 1), 64, res)
+    with pytest.raises(P.BayesLSHError):   # Lite budget not a multiple of k
+        P.bayeslsh_lite_verify(ctx, P.pairs(x, x), S, P.dense_vectors(torch.zeros(10, 8, device="cuda")), T, EPS,
+                               (1, 1), 48, 32, res)

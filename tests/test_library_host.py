@@ -1,0 +1,96 @@
+"""Host-side checks of libbayeslsh.so that need no GPU: the exported symbols,
+the FP64 posterior-table builder against the oracle, and argument validation."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from oracle import posterior as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bayeslsh.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1110_1328_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1110_1328_amd import build
+        build.build()
+    return _abi.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1110_1328_amd import _abi
+    declared = _abi.header_symbols(HEADER)
+    assert len(declared) >= 14
+    for name in declared:
+        assert hasattr(lib, name), name
+    # and the binding declares a prototype for each
+    assert sorted(n for n, _, _ in _abi.PROTOTYPES) == declared
+    assert lib.bayeslsh_version() == 1
+
+
+TABLE_CASES = [
+    (0, 0.7, 32, 8, False, (1, 1)),     # Jaccard workload: t=0.7, 256 hashes, k=32
+    (0, 0.5, 16, 16, False, (1, 1)),
+    (0, 0.9, 64, 4, False, (1, 1)),
+    (0, 0.7, 32, 8, False, (2, 3)),     # non-uniform integer prior
+    (0, 0.3, 32, 8, True, (1, 1)),      # Lite (no concentration bits)
+    (1, 0.7, 32, 4, True, (1, 1)),      # cosine Lite, h = 128
+    (1, 0.8, 32, 32, False, (1, 1)),    # dense cosine, 1024 bits
+    (1, 0.5, 64, 16, False, (1, 1)),
+    (1, 0.9, 16, 16, False, (1, 1)),
+]
+
+
+@pytest.mark.parametrize("measure,t,k,L,lite,prior", TABLE_CASES)
+def test_posterior_table_matches_oracle(lib, measure, t, k, L, lite, prior):
+    import paper_1110_1328_amd as P
+    eps, delta, gamma = 0.03, 0.05, 0.03
+    mm, acc, margin = P.bayeslsh_posterior_table(None, measure, t, eps, delta, gamma, prior, k, L, lite)
+    memo = O.decision_memo(measure, t, eps, 0.0 if lite else delta, 0.0 if lite else gamma,
+                           float(prior[0]), float(prior[1]), k, L, not lite)
+    for j in range(L):
+        n = (j + 1) * k
+        surv = memo["survive"][j, :n + 1]
+        want = int(np.argmax(surv)) if surv.any() else n + 1
+        assert mm[j] == want, (j, mm[j], want)
+        if not lite:
+            bits = np.array([(int(acc[j, m >> 5]) >> (m & 31)) & 1 for m in range(n + 1)], np.uint8)
+            np.testing.assert_array_equal(bits, memo["accept"][j, :n + 1])
+    assert margin > 1e-9
+
+
+def test_posterior_table_rejects_bad_arguments(lib):
+    import paper_1110_1328_amd as P
+    from paper_1110_1328_amd.api import BayesLSHError
+    bad = [
+        dict(t=1.2), dict(t=0.0), dict(epsilon=0.0), dict(delta=1.0), dict(gamma=-0.1),
+        dict(measure=1, prior=(2.0, 1.0)),      # cosine needs the uniform prior
+        dict(prior=(1.5, 1.0)),                 # Jaccard prior must be integer
+        dict(prior=(0.5, 1.0)),
+        dict(n_levels=65), dict(k=0), dict(measure=7),
+    ]
+    for kw in bad:
+        args = dict(measure=0, t=0.7, epsilon=0.03, delta=0.05, gamma=0.03, prior=(1.0, 1.0), k=32, n_levels=4)
+        args.update(kw)
+        with pytest.raises(BayesLSHError) as e:
+            P.bayeslsh_posterior_table(None, args["measure"], args["t"], args["epsilon"], args["delta"],
+                                       args["gamma"], args["prior"], args["k"], args["n_levels"])
+        assert e.value.code == -1, kw
+
+
+def test_calls_without_a_context_fail_cleanly(lib):
+    from paper_1110_1328_amd import _abi
+    assert lib.bayeslsh_verify(None, None, None, 0.7, 0.03, 0.05, 0.03, _abi.Prior(1, 1), 32, None, None) == -1
+    assert b"context" in lib.bayeslsh_last_error()
+    assert lib.bayeslsh_sync(None, None) == -1
+    assert lib.bayeslsh_minhash_sigs(None, None, None, None, 0, None, None) == -1
+    h = C.c_void_p()
+    rc = lib.bayeslsh_create(C.byref(h), 0)
+    if rc == 0:   # a GPU is visible
+        lib.bayeslsh_destroy(h)
+    else:
+        assert rc == -3 and b"device" in lib.bayeslsh_last_error().lower()
