@@ -63,16 +63,16 @@ def build_workload(small: bool):
     return corpus, x, y
 
 
-def cpu_baseline(corpus, x, y, gpu_codes, n_objects=10_000):
-    """The oracle (plain C loop for Algorithm 2 + FP64 exact cosine) timed on the
-    candidates whose two objects both lie in the first `n_objects` ids; the
-    oracle computes its own 128-bit signatures for those objects.  Also returns
-    a parity check of the GPU codes on that sample."""
+def cpu_baseline(corpus, x, y, gpu_codes):
+    """The oracle (plain C loop of Algorithm 2 + FP64 exact cosine), timed over the
+    whole candidate set on the host's cores, on signatures the oracle computes
+    itself (the first h bits of every object; not timed, as the GPU's signature
+    generation is not in its step either).  Also compares its decisions with the
+    GPU codes on every candidate whose two objects have no near-zero projection
+    (only there can an FP32-vs-FP64 rounding flip a signature bit)."""
     from oracle import reference as R
     from oracle import posterior as OP
-    sel = np.flatnonzero((x < n_objects) & (y < n_objects))
-    sx, sy = x[sel], y[sel]
-    rows = np.arange(n_objects, dtype=np.int64)
+    rows = np.arange(corpus.n, dtype=np.int64)
     proj = R.srp_sparse_projections(corpus.offsets, corpus.indices, corpus.values, H, SRP_SEED, rows)
     sig = R.bits_from_projections(proj)
     OP.decision_memo(1, T, EPS, 0.0, 0.0, 1.0, 1.0, K, H // K, False)   # table, outside the timed region
@@ -80,20 +80,39 @@ def cpu_baseline(corpus, x, y, gpu_codes, n_objects=10_000):
     times = []
     for _ in range(3):
         t0 = time.perf_counter()
-        res = R.verify(sx, sy, 1, sig, K, H // K, T, EPS, 0.0, 0.0, lite=True)
+        res = R.verify(x, y, 1, sig, K, H // K, T, EPS, 0.0, 0.0, lite=True)
         res = R.lite_finish(res, lambda p, q: R.exact_cosine_csr(corpus.offsets, corpus.indices, corpus.values, p, q),
-                            sx, sy, T)
+                            x, y, T)
         times.append(time.perf_counter() - t0)
     dt = float(np.median(times))
-    # parity on the sample, on candidates whose objects have no near-zero projection
-    # (only there may an FP32-vs-FP64 sign flip make the GPU signature differ)
     fragile = np.any(np.abs(proj) < 1e-5, axis=1)
-    ok = ~(fragile[sx] | fragile[sy])
-    g = gpu_codes[sel]
-    parity = dict(sample=int(len(sel)), compared=int(ok.sum()),
-                  mismatches=int(np.sum((g[ok] >> 6) != res["decision"][ok]) + np.sum((g[ok] & 63) != res["level"][ok])))
-    return dict(value=len(sel) / dt, unit="pairs/s", cores=threads, kind="oracle",
-                sample="%d candidates with both ids < %d (median of 3 runs of %.2fs)" % (len(sel), n_objects, dt)), parity
+    ok = ~(fragile[x] | fragile[y])
+    g = gpu_codes
+    parity = dict(compared=int(ok.sum()), skipped_fragile=int((~ok).sum()),
+                  decision_mismatches=int(np.sum((g[ok] >> 6) != res["decision"][ok])),
+                  level_mismatches=int(np.sum((g[ok] & 63) != res["level"][ok])))
+    return dict(value=len(x) / dt, unit="pairs/s", cores=threads, kind="oracle",
+                sample="all %d candidates of the workload, median of 3 runs (%.2f s each)" % (len(x), dt)), parity, res
+
+
+def copy_calibration(n_bytes=1 << 30, reps=20):
+    """A plain device copy of known size (torch's copy kernel), for scaling rocprof
+    FETCH_SIZE/WRITE_SIZE and as the achievable-bandwidth reference."""
+    import torch
+    a = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    print(json.dumps({"copy_bytes_read": n_bytes, "copy_bytes_written": n_bytes, "ms": ms,
+                      "GBps_read_plus_write": 2 * n_bytes / ms / 1e6}), flush=True)
 
 
 def main():
@@ -103,6 +122,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--small", action="store_true", help="20k-document workload (quick check)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true", help="time a plain 1 GiB device copy and exit")
+    ap.add_argument("--gather", type=int, default=0, help="verify gather mode: 0 library default, 1 direct, 2 LDS cache")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -112,11 +133,16 @@ def main():
     import torch
     import paper_1110_1328_amd as P
 
+    if args.copy_calibration:
+        copy_calibration()
+        return
     log("generating workload")
     corpus, x, y = build_workload(args.small)
     n = len(x)
     log("corpus %d docs, %d nnz; %d candidates" % (corpus.n, len(corpus.indices), n))
     ctx = P.bayeslsh_create(0)
+    if args.gather:
+        P.bayeslsh_set_tuning(ctx, gather=args.gather)
     vec = P.csr_vectors(up(torch, corpus.offsets), up(torch, corpus.indices), up(torch, corpus.values), corpus.dim)
     xd, yd = up(torch, x), up(torch, y)
     W = N_BITS // 32
@@ -148,8 +174,6 @@ def main():
     for _ in range(args.warmup):
         step()
     P.bayeslsh_sync(ctx, stream)
-    P.bayeslsh_profile_enable(ctx, True)
-    P.bayeslsh_profile_reset(ctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -157,10 +181,18 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     P.bayeslsh_sync(ctx, stream)
+    ms_step = el * 1e3 / args.steps
+    # per-kernel durations: HIP events around each launch on the same stream, in a
+    # separate pass so that event creation does not enter the timed steps above
+    P.bayeslsh_profile_enable(ctx, True)
+    P.bayeslsh_profile_reset(ctx)
+    for _ in range(args.steps):
+        step()
+    P.bayeslsh_sync(ctx, stream)
     k_ms, k_n = P.bayeslsh_profile_read(ctx, "verify_bits")
+    k_name = "k_verify_bits (%s)" % ("LDS tile cache" if P.bayeslsh_get_tuning(ctx)["gather"] == 2 else "direct gathers")
     x_ms, x_n = P.bayeslsh_profile_read(ctx, "exact")
     P.bayeslsh_profile_enable(ctx, False)
-    ms_step = el * 1e3 / args.steps
     log("BayesLSH-Lite: %.3f ms/step (verify kernel %.3f ms, exact %.3f ms)" % (ms_step, k_ms / max(k_n, 1),
                                                                               x_ms / max(x_n, 1)))
     # exhaustive comparator
@@ -184,11 +216,17 @@ def main():
     same = same and np.array_equal(ia, ib) and np.array_equal(va, vb)
     dec, lvl = codes >> 6, codes & 63
     n_surv = int(np.sum(dec == 3))
-    # algorithmic bytes of the verify kernel: ids (8 B) + code (1 B) + per level reached
-    # both sides' chunk (2 x k/8 B) + one 16 B queue entry per survivor
-    alg_bytes = n * 9 + int(np.sum(lvl.astype(np.int64) + 1)) * 2 * (K // 8) + 16 * n_surv
+    # Algorithmic bytes of the verify kernel per launch.  HBM stream: candidate ids
+    # (8 B) + code (1 B) per candidate + one 16 B survivor-queue entry per survivor.
+    # The signature chunks (2 x k/8 B per level reached) are gathered from the
+    # word-major slabs (4 B x 100k objects per level), which stay in L2.
+    hbm_bytes = n * 9 + 16 * n_surv
+    gather_bytes = int(np.sum(lvl.astype(np.int64) + 1)) * 2 * (K // 8)
     k_avg_ms = k_ms / max(k_n, 1)
-    achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9
+    per_step = max(k_n, 1) / args.steps                 # verify launches per step (candidate chunks)
+    hbm_bytes = int(hbm_bytes / per_step)               # per launch
+    gather_bytes = int(gather_bytes / per_step)
+    achieved = hbm_bytes / (k_avg_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": n / (ms_step * 1e-3),
@@ -215,14 +253,16 @@ def main():
                        "same_output": same, "mode": "REPLAY_LITE, all 2048 bits per object"},
         "signature_ms": sig_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_verify_bits",
-                     "kernel_ms": k_avg_ms, "alg_bytes_per_launch": alg_bytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": k_name,
+                     "kernel_ms": k_avg_ms, "kernel_launches_timed": k_n, "hbm_bytes_per_launch": hbm_bytes,
+                     "l2_gather_bytes_per_launch": gather_bytes,
+                     "gather_inclusive_GBps": (hbm_bytes + gather_bytes) / (k_avg_ms * 1e-3) / 1e9},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        cb, parity = cpu_baseline(corpus, x, y, codes)
+        cb, parity, _ = cpu_baseline(corpus, x, y, codes)
         out["cpu_baseline"] = cb
-        out["sampled_parity"] = parity
+        out["full_size_parity"] = parity
         log("cpu baseline: %.3g pairs/s; parity %s" % (cb["value"], parity))
     ctx.close()
     print(json.dumps(out), flush=True)

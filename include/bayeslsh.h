@@ -166,6 +166,20 @@ int bayeslsh_profile_enable(blsh_ctx *ctx, int enable);
 int bayeslsh_profile_reset(blsh_ctx *ctx);
 int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_ms_host, int64_t *launches_host);
 
+/* Launch tuning of a context (callers that want a fixed configuration, and
+ * the autotuner).  Zero fields mean "library default".
+ *   gather: 1 = each lane gathers both signatures of its candidates directly;
+ *           2 = each block first gathers the level-0 words of the distinct
+ *               objects of its tile into an LDS hash table (pays off when
+ *               candidates arrive bucket-major, as LSH banding emits them).
+ *           Applies to SRP (cosine) verification; the result is identical. */
+typedef struct {
+  int32_t gather;
+  int32_t reserved[7];
+} blsh_tuning;
+int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *tuning_host);
+int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *tuning_host);
+
 /* ---------------- posterior tables (host, FP64) ---------------- */
 
 /* Build (or fetch from the context's cache) the decision table of one

@@ -46,6 +46,10 @@ class Result(C.Structure):
                 ("m_debug", p)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("gather", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
 # (name, restype, argtypes) for every symbol of the header
 PROTOTYPES = [
     ("bayeslsh_create", C.c_int, [C.POINTER(p), C.c_int]),
@@ -56,6 +60,8 @@ PROTOTYPES = [
     ("bayeslsh_profile_enable", C.c_int, [p, C.c_int]),
     ("bayeslsh_profile_reset", C.c_int, [p]),
     ("bayeslsh_profile_read", C.c_int, [p, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    ("bayeslsh_set_tuning", C.c_int, [p, C.POINTER(Tuning)]),
+    ("bayeslsh_get_tuning", C.c_int, [p, C.POINTER(Tuning)]),
     ("bayeslsh_posterior_table", C.c_int,
      [p, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, Prior, C.c_int32, C.c_int32, C.c_int32, p, p,
       C.POINTER(C.c_double)]),

@@ -58,6 +58,17 @@ def _p(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _cached(obj, build, *tensors):
+    """Rebuild the ctypes struct only when a tensor (or scalar field) changed."""
+    key = tuple(t.data_ptr() if isinstance(t, torch.Tensor) else t for t in tensors)
+    c = obj.__dict__.get("_cstruct")
+    if c is not None and c[0] == key:
+        return c[1]
+    st = build()
+    obj.__dict__["_cstruct"] = (key, st)
+    return st
+
+
 # ---------------------------------------------------------------------------
 # argument holders (keep the tensors alive next to their structs)
 # ---------------------------------------------------------------------------
@@ -71,6 +82,9 @@ class Signatures:
     n_max: int = 0
 
     def struct(self):
+        return _cached(self, self._build, self.data, self.measure, self.layout, self.n_obj, self.n_hashes, self.n_max)
+
+    def _build(self):
         _dev(self.data, torch.int32 if self.data.dtype == torch.int32 else torch.uint32, "signature data")
         return A.Sigs(self.measure, self.layout, _p(self.data), self.n_obj, self.n_hashes, self.n_max)
 
@@ -95,6 +109,10 @@ class Candidates:
         return self.all_n * (self.all_n - 1) // 2
 
     def struct(self):
+        return _cached(self, self._build, self.kind, self.x, self.y, self.query, self.offsets, self.cand, self.n_cand,
+                       self.all_n)
+
+    def _build(self):
         c = A.Candidates()
         c.kind = self.kind
         if self.kind == PAIRS:
@@ -138,6 +156,10 @@ class Vectors:
     values: torch.Tensor = None
 
     def struct(self):
+        return _cached(self, self._build, self.kind, self.n_obj, self.dim, self.dense, self.offsets, self.indices,
+                       self.values)
+
+    def _build(self):
         if self.kind == DENSE:
             _dev(self.dense, torch.float32, "dense")
         else:
@@ -171,6 +193,9 @@ class Result:
     _s: object = field(default=None, repr=False)
 
     def struct(self):
+        return _cached(self, self._build, self.code, self.acc_idx, self.acc_val, self.n_accepted, self.m_debug)
+
+    def _build(self):
         _dev(self.code, torch.uint8, "code")
         _dev(self.acc_idx, torch.uint64, "acc_idx")
         _dev(self.acc_val, torch.float32, "acc_val")
@@ -254,6 +279,18 @@ def bayeslsh_profile_read(ctx: Context, name: str):
     return ms.value, n.value
 
 
+def bayeslsh_set_tuning(ctx: Context, gather: int = 0):
+    t = A.Tuning()
+    t.gather = gather
+    _check(_lib().bayeslsh_set_tuning(ctx.handle, C.byref(t)))
+
+
+def bayeslsh_get_tuning(ctx: Context) -> dict:
+    t = A.Tuning()
+    _check(_lib().bayeslsh_get_tuning(ctx.handle, C.byref(t)))
+    return {"gather": t.gather}
+
+
 def bayeslsh_posterior_table(ctx, measure, t, epsilon, delta, gamma, prior=(1.0, 1.0), k=32, n_levels=8,
                              lite=False):
     """ctx may be None (host-only build, no GPU needed)."""
@@ -293,6 +330,17 @@ def bayeslsh_srp_sigs(ctx: Context, vecs: Vectors, planes, n_bits: int, seed: in
     return out
 
 
+_PRIORS = {}
+
+
+def _prior(prior):
+    prior = tuple(prior)
+    p = _PRIORS.get(prior)
+    if p is None:
+        p = _PRIORS[prior] = A.Prior(*prior)
+    return p
+
+
 def _check_result_size(res: Result, cand: Candidates):
     if res.code.numel() < cand.count:
         raise ValueError("result.code holds %d bytes for %d candidates" % (res.code.numel(), cand.count))
@@ -304,7 +352,7 @@ def bayeslsh_verify(ctx: Context, cand: Candidates, sigs: Signatures, t, epsilon
                     k=32, res: Result = None, stream=None):
     _check_result_size(res, cand)
     cs, ss, rs = cand.struct(), sigs.struct(), res.struct()
-    _check(_lib().bayeslsh_verify(ctx.handle, C.byref(cs), C.byref(ss), t, epsilon, delta, gamma, A.Prior(*prior), k,
+    _check(_lib().bayeslsh_verify(ctx.handle, C.byref(cs), C.byref(ss), t, epsilon, delta, gamma, _prior(prior), k,
                                   C.byref(rs), _stream(stream)))
     return res
 
@@ -314,7 +362,7 @@ def bayeslsh_lite_verify(ctx: Context, cand: Candidates, sigs: Signatures, exact
     _check_result_size(res, cand)
     cs, ss, vs, rs = cand.struct(), sigs.struct(), exact.struct(), res.struct()
     _check(_lib().bayeslsh_lite_verify(ctx.handle, C.byref(cs), C.byref(ss), C.byref(vs), t, epsilon,
-                                       A.Prior(*prior), h, k, C.byref(rs), _stream(stream)))
+                                       _prior(prior), h, k, C.byref(rs), _stream(stream)))
     return res
 
 

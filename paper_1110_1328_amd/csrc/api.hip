@@ -11,7 +11,7 @@ namespace blsh {
 // launchers (verify.hip, sigs.hip)
 int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool word_major, hipStream_t s);
 int launch_exhaustive(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s);
-int launch_zero(blsh_ctx *ctx, int64_t *p, int n, hipStream_t s);
+int launch_zero(blsh_ctx *ctx, int64_t *p, int64_t *q, hipStream_t s);
 int launch_minhash(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *elems, int64_t n_sets, const uint32_t *a,
                    const uint32_t *b, int n_hashes, uint32_t *out, hipStream_t s);
 int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *indices, const float *values,
@@ -206,26 +206,23 @@ static void fill_cand(VerifyArgs &a, const blsh_candidates *c) {
   a.all_n = c->all_n;
 }
 
-// Survivor queue slice layout inside the context workspace, sized for `chunk` candidates:
-//   [0, 64)                  q_n (int64) + padding
-//   [64, 64 + 8*chunk)       q_idx
-//   [.., + 8*chunk)          q_xy
-static constexpr int64_t kChunk = int64_t(1) << 26;
+// Survivor queue inside the context workspace, sized for `chunk` candidates:
+//   [0, 256)             q_n (int64) + padding
+//   [256, 256 + 4*chunk) q_rel (candidate index relative to the chunk start)
+static constexpr int64_t kChunk = int64_t(1) << 28;
 
 struct Queue {
   int64_t *n;
-  uint64_t *idx;
-  uint32_t *xy;
+  uint32_t *rel;
 };
 
 static int get_queue(blsh_ctx *ctx, int64_t chunk, Queue *q) {
-  const size_t bytes = 256 + size_t(chunk) * 16;
+  const size_t bytes = 256 + size_t(chunk) * 4;
   int rc = ensure_workspace(ctx, bytes);
   if (rc) return rc;
   char *base = static_cast<char *>(ctx->ws);
   q->n = reinterpret_cast<int64_t *>(base);
-  q->idx = reinterpret_cast<uint64_t *>(base + 256);
-  q->xy = reinterpret_cast<uint32_t *>(base + 256 + size_t(chunk) * 8);
+  q->rel = reinterpret_cast<uint32_t *>(base + 256);
   return BLSH_OK;
 }
 
@@ -236,8 +233,7 @@ static void fill_exact(ExactArgs &e, const blsh_vectors *v, const Queue &q, doub
   e.offsets = v->offsets;
   e.indices = v->indices;
   e.values = v->values;
-  e.q_idx = q.idx;
-  e.q_xy = q.xy;
+  e.q_rel = q.rel;
   e.q_n = q.n;
   e.t = t;
 }
@@ -296,20 +292,20 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   a.mode = exh ? exhaustive_mode : 0;
   a.count_levels = n_max / k;
   a.t = t;
-  if ((rc = launch_zero(ctx, res->n_accepted, 1, s))) return fail(rc, "launch failed");
-  if (n_cand == 0) return BLSH_OK;
+  if (n_cand == 0) return launch_zero(ctx, res->n_accepted, nullptr, s) ? fail(BLSH_EDEVICE, "launch failed") : BLSH_OK;
   Queue q{};
   const int64_t chunk = lite ? std::min<int64_t>(n_cand, kChunk) : n_cand;
   if (lite && (rc = get_queue(ctx, chunk, &q))) return rc;
-  a.q_idx = q.idx;
-  a.q_xy = q.xy;
+  a.q_rel = q.rel;
   a.q_n = q.n;
   ExactArgs e{};
   if (lite) fill_exact(e, exact, q, t);
   for (int64_t c0 = 0; c0 < n_cand; c0 += chunk) {
     a.c_begin = c0;
     a.c_end = std::min(n_cand, c0 + chunk);
-    if (lite && (rc = launch_zero(ctx, q.n, 1, s))) return fail(rc, "launch failed");
+    // one launch clears the output count (first chunk) and the survivor queue count
+    if ((c0 == 0 || lite) && (rc = launch_zero(ctx, c0 == 0 ? res->n_accepted : nullptr, lite ? q.n : nullptr, s)))
+      return fail(rc, "launch failed");
     rc = exh ? launch_exhaustive(ctx, a, k, s)
              : launch_verify(ctx, a, k, lite, sigs->measure == BLSH_COSINE && sigs->layout == BLSH_WORD_MAJOR, s);
     if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;
@@ -416,6 +412,19 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
     if (kv.first.find(name_substr) != std::string::npos) { tot += kv.second.first; n += kv.second.second; }
   if (total_ms) *total_ms = tot;
   if (launches) *launches = n;
+  return BLSH_OK;
+}
+
+int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
+  if (!ctx || !t) return fail(BLSH_EINVAL, "null argument");
+  if (t->gather < 0 || t->gather > 2) return fail(BLSH_EINVAL, "tuning.gather must be 0, 1 or 2");
+  ctx->tuning = *t;
+  return BLSH_OK;
+}
+
+int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *t) {
+  if (!ctx || !t) return fail(BLSH_EINVAL, "null argument");
+  *t = ctx->tuning;
   return BLSH_OK;
 }
 

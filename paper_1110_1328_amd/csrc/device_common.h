@@ -38,9 +38,8 @@ struct VerifyArgs {
   int64_t acc_cap;
   int64_t *n_acc;
   uint16_t *m_dbg;
-  // Lite survivors
-  uint64_t *q_idx;
-  uint32_t *q_xy;
+  // Lite survivors: candidate index relative to c_begin
+  uint32_t *q_rel;
   int64_t *q_n;
   int32_t *status;
   // exhaustive
@@ -57,8 +56,7 @@ struct ExactArgs {
   const int64_t *offsets;
   const uint32_t *indices;
   const float *values;
-  const uint64_t *q_idx;
-  const uint32_t *q_xy;
+  const uint32_t *q_rel;
   const int64_t *q_n;
   double t;
 };
@@ -159,20 +157,23 @@ __device__ inline void emit_accepted(const VerifyArgs &a, bool pred, uint64_t id
   }
 }
 
-// Wave-level compaction of Lite survivors into the exact-similarity queue.
-__device__ inline void push_survivor(const VerifyArgs &a, bool pred, uint64_t idx, uint32_t xi, uint32_t yi) {
+// Wave-level compaction of Lite survivors into the exact-similarity queue
+// (entries are candidate indices relative to the launch's c_begin).
+__device__ inline void push_survivor(const VerifyArgs &a, bool pred, int64_t c) {
   const uint64_t mask = __ballot(pred);
   if (mask == 0) return;
   const int leader = __ffsll((unsigned long long)mask) - 1;
   unsigned long long base = 0;
   if (lane_id() == leader) base = atomicAdd((unsigned long long *)a.q_n, (unsigned long long)__popcll(mask));
   base = __shfl(base, leader);
-  if (pred) {
-    const unsigned long long pos = base + lanes_below(mask);
-    a.q_idx[pos] = idx;
-    a.q_xy[2 * pos] = xi;
-    a.q_xy[2 * pos + 1] = yi;
-  }
+  if (pred) a.q_rel[base + lanes_below(mask)] = uint32_t(c - a.c_begin);
+}
+
+// Order this wave's LDS writes before its later LDS reads (and vice versa).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // DPP lane permutations (GFX9 encodings).

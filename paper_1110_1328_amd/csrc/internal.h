@@ -81,6 +81,8 @@ struct blsh_ctx {
   // survivor workspace
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  // tuning (bayeslsh_set_tuning)
+  blsh_tuning tuning{};
   // profiling
   bool prof = false;
   std::vector<blsh::ProfRec> prof_pending;

@@ -58,11 +58,52 @@ __device__ inline uint32_t level_agree_bits(const VerifyArgs &a, uint32_t xi, ui
 constexpr int kPPT = 4;        // candidates per lane (bits kernel)
 constexpr int kBlock = 256;
 
-template <int K, int KIND, bool LITE, bool WORD_MAJOR>
+// Level-0 agreement from words already held (LDS tile cache).
+template <int K>
+__device__ inline uint32_t agree_words(uint32_t x0, uint32_t x1, uint32_t y0, uint32_t y1, int j) {
+  if constexpr (K == 32) return 32u - __popc(x0 ^ y0);
+  else if constexpr (K == 64) return 64u - __popc(x0 ^ y0) - __popc(x1 ^ y1);
+  else return 16u - __popc(((x0 ^ y0) >> ((j & 1) * 16)) & 0xFFFFu);
+}
+
+// LDS tile cache of level-0 signature words.  A tile of kBlock*kPPT candidates
+// references at most 2*kBlock*kPPT distinct objects, half the table size, so
+// linear probing always finds the id or an empty slot.
+constexpr int kCacheBits = 12;
+constexpr int kCacheSlots = 1 << kCacheBits;
+constexpr uint32_t kEmptyTag = 0xFFFFFFFFu;   // never a valid id (n_obj <= 2^32 - 1)
+static_assert(kCacheSlots >= 2 * 256 * 4, "cache must hold twice the ids of a tile");
+
+__device__ inline int cache_insert(uint32_t *tag, uint32_t id) {
+  uint32_t h = (id * 2654435761u) >> (32 - kCacheBits);
+  for (int probe = 0; probe < kCacheSlots; ++probe) {
+    const uint32_t t = tag[h];
+    if (t == id) return int(h);
+    if (t == kEmptyTag) {
+      const uint32_t old = atomicCAS(&tag[h], kEmptyTag, id);
+      if (old == kEmptyTag || old == id) return int(h);
+    }
+    h = (h + 1) & (kCacheSlots - 1);
+  }
+  return -1;
+}
+
+// One lane per candidate, kPPT consecutive candidates per lane.  With LDSC the
+// block first gathers the level-0 word(s) of every distinct object of its tile
+// into an LDS hash table (one global gather per distinct object instead of two
+// per candidate), then compares level 0 from LDS; deeper levels gather from
+// global memory.
+template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool LDSC>
 __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
+  constexpr int LW = K == 64 ? 2 : 1;                       // words per level-0 chunk
   __shared__ int s_min[kMaxLevels];
+  __shared__ uint32_t s_tag[LDSC ? kCacheSlots : 1];
+  __shared__ uint32_t s_dat[LW][LDSC ? kCacheSlots : 1];
   if (threadIdx.x < kMaxLevels)
     s_min[threadIdx.x] = threadIdx.x < a.n_levels ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
+  if constexpr (LDSC) {
+    for (int i = threadIdx.x; i < kCacheSlots; i += kBlock) s_tag[i] = kEmptyTag;
+  }
   __syncthreads();
   const int L = a.n_levels;
   const int words = int(a.table[2]);
@@ -72,6 +113,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
 
   uint32_t xi[kPPT], yi[kPPT];
   uint32_t alive = 0, bad = 0;
+#pragma unroll
+  for (int p = 0; p < kPPT; ++p) xi[p] = yi[p] = 0;
   if (any) {
     if (KIND == BLSH_PAIRS && c0 + kPPT <= a.c_end && ((uintptr_t(a.x + c0) | uintptr_t(a.y + c0)) & 15) == 0) {
       const u32x4 vx = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.x + c0));
@@ -85,7 +128,6 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
     } else {
 #pragma unroll
       for (int p = 0; p < kPPT; ++p) {
-        xi[p] = yi[p] = 0;
         if (c0 + p < a.c_end) {
           if (fetch_candidate(a, c0 + p, xi[p], yi[p])) alive |= 1u << p; else bad |= 1u << p;
         }
@@ -95,27 +137,72 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
   uint32_t m[kPPT] = {0, 0, 0, 0};
   uint8_t code[kPPT] = {0, 0, 0, 0};
   uint32_t emit = 0;
-  for (int j = 0; j < L && alive; ++j) {
+  auto decide = [&](int p, int j) {
+    if (int(m[p]) < s_min[j]) {
+      code[p] = uint8_t((BLSH_PRUNED << 6) | j);
+      alive &= ~(1u << p);
+    } else if (!LITE && accept_bit(a.table, words, j, int(m[p]))) {
+      code[p] = uint8_t((BLSH_ACCEPT_CONC << 6) | j);
+      alive &= ~(1u << p);
+      emit |= 1u << p;
+    } else if (j == L - 1) {
+      code[p] = uint8_t(((LITE ? BLSH_LITE_EXACT : BLSH_ACCEPT_NMAX) << 6) | j);
+      alive &= ~(1u << p);
+      emit |= 1u << p;
+    }
+  };
+  int j0 = 0;
+  if constexpr (LDSC) {
+    // 1. insert every distinct id of the tile (consecutive equal ids are inserted once)
+    int sx[kPPT], sy[kPPT];
+    uint32_t prev = kEmptyTag;
+    int prev_slot = -1;
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p) {
+      sx[p] = sy[p] = -1;
+      if (alive & (1u << p)) {
+        sx[p] = xi[p] == prev ? prev_slot : cache_insert(s_tag, xi[p]);
+        prev = xi[p];
+        prev_slot = sx[p];
+        sy[p] = cache_insert(s_tag, yi[p]);
+      }
+    }
+    __syncthreads();
+    // 2. one gather per occupied slot
+    for (int i = threadIdx.x; i < kCacheSlots; i += kBlock) {
+      const uint32_t t = s_tag[i];
+      if (t != kEmptyTag) {
+#pragma unroll
+        for (int w = 0; w < LW; ++w)
+          s_dat[w][i] = WORD_MAJOR ? a.sig[size_t(w) * a.n_obj + t] : a.sig[size_t(t) * a.row_words + w];
+      }
+    }
+    __syncthreads();
+    // 3. level 0 (and level 1 for k = 16, which shares the word) from LDS
+    const int lds_levels = K == 16 ? 2 : 1;
+    for (int j = 0; j < lds_levels && j < L; ++j) {
+#pragma unroll
+      for (int p = 0; p < kPPT; ++p) {
+        if (!(alive & (1u << p))) continue;
+        if (sx[p] >= 0 && sy[p] >= 0) {
+          const uint32_t x0 = s_dat[0][sx[p]], y0 = s_dat[0][sy[p]];
+          const uint32_t x1 = LW == 2 ? s_dat[LW - 1][sx[p]] : 0u, y1 = LW == 2 ? s_dat[LW - 1][sy[p]] : 0u;
+          m[p] += agree_words<K>(x0, x1, y0, y1, j);
+        } else {
+          m[p] += level_agree_bits<K, WORD_MAJOR>(a, xi[p], yi[p], j);
+        }
+        decide(p, j);
+      }
+    }
+    j0 = lds_levels;
+  }
+  for (int j = j0; j < L && alive; ++j) {
 #pragma unroll
     for (int p = 0; p < kPPT; ++p)
       if (alive & (1u << p)) m[p] += level_agree_bits<K, WORD_MAJOR>(a, xi[p], yi[p], j);
-    const int mm = s_min[j];
 #pragma unroll
-    for (int p = 0; p < kPPT; ++p) {
-      if (!(alive & (1u << p))) continue;
-      if (int(m[p]) < mm) {
-        code[p] = uint8_t((BLSH_PRUNED << 6) | j);
-        alive &= ~(1u << p);
-      } else if (!LITE && accept_bit(a.table, words, j, int(m[p]))) {
-        code[p] = uint8_t((BLSH_ACCEPT_CONC << 6) | j);
-        alive &= ~(1u << p);
-        emit |= 1u << p;
-      } else if (j == L - 1) {
-        code[p] = uint8_t(((LITE ? BLSH_LITE_EXACT : BLSH_ACCEPT_NMAX) << 6) | j);
-        alive &= ~(1u << p);
-        emit |= 1u << p;
-      }
-    }
+    for (int p = 0; p < kPPT; ++p)
+      if (alive & (1u << p)) decide(p, j);
   }
 #pragma unroll
   for (int p = 0; p < kPPT; ++p)
@@ -145,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
   for (int p = 0; p < kPPT; ++p) {
     const bool e = (emit >> p) & 1u;
     if (LITE) {
-      push_survivor(a, e, uint64_t(c0 + p), xi[p], yi[p]);
+      push_survivor(a, e, c0 + p);
     } else {
       const int n = ((code[p] & 63) + 1) * K;
       const float v = e ? map_estimate(a.measure, int(m[p]), n, alpha, beta) : 0.f;
@@ -226,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_minhash(VerifyArgs a) {
     if (a.m_dbg) a.m_dbg[c] = uint16_t(m);
   }
   if (LITE) {
-    push_survivor(a, emit, uint64_t(c), xi, yi);
+    push_survivor(a, emit, c);
   } else {
     const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
     const float v = emit ? map_estimate(a.measure, int(m), ((code & 63) + 1) * K, alpha, beta) : 0.f;
@@ -255,12 +342,21 @@ __device__ inline int64_t bsearch_u32(const uint32_t *idx, int64_t n, uint32_t k
   return (lo < n && idx[lo] == key) ? lo : -1;
 }
 
+// One wave per queued pair.  Sparse rows: the longer row is staged in LDS
+// (when it has at most kExactLds entries) and every entry of the shorter row
+// is binary-searched in it; all sums are FP64.
+constexpr int kExactLds = 512;
+
 __global__ __launch_bounds__(kBlock) void k_exact(ExactArgs e, VerifyArgs a) {
-  const int lane = lane_id();
+  __shared__ uint32_t s_idx[kBlock / kWave][kExactLds];
+  __shared__ float s_val[kBlock / kWave][kExactLds];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
   const int64_t n = *e.q_n;
   const int64_t waves = int64_t(gridDim.x) * (kBlock / kWave);
-  for (int64_t q = int64_t(blockIdx.x) * (kBlock / kWave) + (threadIdx.x >> 6); q < n; q += waves) {
-    const uint32_t xi = e.q_xy[2 * q], yi = e.q_xy[2 * q + 1];
+  for (int64_t q = int64_t(blockIdx.x) * (kBlock / kWave) + w; q < n; q += waves) {
+    const int64_t c = a.c_begin + e.q_rel[q];
+    uint32_t xi, yi;
+    fetch_candidate(a, c, xi, yi);   // ids were range-checked before the pair was queued
     double s = 0.0;
     if (e.vec_kind == BLSH_DENSE) {
       const float *u = e.dense + size_t(xi) * e.dim, *v = e.dense + size_t(yi) * e.dim;
@@ -272,34 +368,61 @@ __global__ __launch_bounds__(kBlock) void k_exact(ExactArgs e, VerifyArgs a) {
       nx = wave_sum_f64(nx); ny = wave_sum_f64(ny); dot = wave_sum_f64(dot);
       s = (nx > 0 && ny > 0) ? dot / (sqrt(nx) * sqrt(ny)) : 0.0;
     } else {
-      int64_t ax = e.offsets[xi], nxl = e.offsets[xi + 1] - ax;
-      int64_t ay = e.offsets[yi], nyl = e.offsets[yi + 1] - ay;
-      // iterate the shorter row, search the longer
-      int64_t as = ax, ns = nxl, al = ay, nl = nyl;
-      if (nxl > nyl) { as = ay; ns = nyl; al = ax; nl = nxl; }
-      if (e.vec_kind == BLSH_SETS) {
-        uint32_t inter = 0;
-        for (int64_t i = lane; i < ns; i += kWave) inter += bsearch_u32(e.indices + al, nl, e.indices[as + i]) >= 0;
+      const int64_t ax = e.offsets[xi], nxl = e.offsets[xi + 1] - ax;
+      const int64_t ay = e.offsets[yi], nyl = e.offsets[yi + 1] - ay;
+      const bool x_long = nxl >= nyl;
+      const int64_t al = x_long ? ax : ay, nl = x_long ? nxl : nyl;
+      const int64_t as = x_long ? ay : ax, ns = x_long ? nyl : nxl;
+      const bool csr = e.vec_kind == BLSH_CSR;
+      const bool staged = nl <= kExactLds;
+      double n_long = 0.0, n_short = 0.0, dot = 0.0;
+      uint32_t inter = 0;
+      if (staged) {
+        for (int64_t i = lane; i < nl; i += kWave) {
+          s_idx[w][i] = e.indices[al + i];
+          if (csr) {
+            const float v = e.values[al + i];
+            s_val[w][i] = v;
+            n_long += double(v) * double(v);
+          }
+        }
+        wave_lds_sync();
+      } else if (csr) {
+        for (int64_t i = lane; i < nl; i += kWave) { const double v = e.values[al + i]; n_long += v * v; }
+      }
+      for (int64_t i = lane; i < ns; i += kWave) {
+        const uint32_t key = e.indices[as + i];
+        int64_t lo = 0, hi = nl;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          const uint32_t v = staged ? s_idx[w][mid] : e.indices[al + mid];
+          if (v < key) lo = mid + 1; else hi = mid;
+        }
+        const bool hit = lo < nl && (staged ? s_idx[w][lo] : e.indices[al + lo]) == key;
+        if (csr) {
+          const double vs = e.values[as + i];
+          n_short += vs * vs;
+          if (hit) dot += vs * double(staged ? s_val[w][lo] : e.values[al + lo]);
+        } else {
+          inter += hit;
+        }
+      }
+      if (csr) {
+        n_long = wave_sum_f64(n_long); n_short = wave_sum_f64(n_short); dot = wave_sum_f64(dot);
+        s = (n_long > 0 && n_short > 0) ? dot / (sqrt(x_long ? n_long : n_short) * sqrt(x_long ? n_short : n_long))
+                                        : 0.0;
+      } else {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) inter += __shfl_xor(inter, o);
         const int64_t uni = nxl + nyl - int64_t(inter);
         s = uni > 0 ? double(inter) / double(uni) : 0.0;
-      } else {
-        double nx = 0, ny = 0, dot = 0;
-        for (int64_t i = lane; i < nxl; i += kWave) { const double v = e.values[ax + i]; nx += v * v; }
-        for (int64_t i = lane; i < nyl; i += kWave) { const double v = e.values[ay + i]; ny += v * v; }
-        for (int64_t i = lane; i < ns; i += kWave) {
-          const int64_t pos = bsearch_u32(e.indices + al, nl, e.indices[as + i]);
-          if (pos >= 0) dot += double(e.values[as + i]) * double(e.values[al + pos]);
-        }
-        nx = wave_sum_f64(nx); ny = wave_sum_f64(ny); dot = wave_sum_f64(dot);
-        s = (nx > 0 && ny > 0) ? dot / (sqrt(nx) * sqrt(ny)) : 0.0;
       }
+      wave_lds_sync();   // the next pair may overwrite this wave's LDS rows
     }
     if (lane == 0 && s > e.t) {
       const unsigned long long pos = atomicAdd((unsigned long long *)a.n_acc, 1ull);
       if (int64_t(pos) < a.acc_cap) {
-        a.acc_idx[pos] = e.q_idx[q];
+        a.acc_idx[pos] = uint64_t(c);
         a.acc_val[pos] = float(s);
       } else {
         raise_status(a.status, BLSH_ETRUNCATED);
@@ -418,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_exhaustive_bits(VerifyArgs a) {
     a.code[c] = code;
     if (a.m_dbg) a.m_dbg[c] = uint16_t(fm);
   }
-  if (a.mode == BLSH_REPLAY_LITE) push_survivor(a, surv, uint64_t(c), xi, yi);
+  if (a.mode == BLSH_REPLAY_LITE) push_survivor(a, surv, c);
   else emit_accepted(a, emit, uint64_t(c), val);
 }
 
@@ -488,12 +611,13 @@ __global__ __launch_bounds__(kBlock) void k_exhaustive_minhash(VerifyArgs a) {
     a.code[c] = code;
     if (a.m_dbg) a.m_dbg[c] = uint16_t(mval);
   }
-  if (a.mode == BLSH_REPLAY_LITE) push_survivor(a, surv, uint64_t(c), xi, yi);
+  if (a.mode == BLSH_REPLAY_LITE) push_survivor(a, surv, c);
   else emit_accepted(a, emit, uint64_t(c), val);
 }
 
-__global__ void k_zero_i64(int64_t *p, int n) {
-  if (int(threadIdx.x) < n) p[threadIdx.x] = 0;
+__global__ void k_zero_i64(int64_t *p, int64_t *q) {
+  if (threadIdx.x == 0 && p) *p = 0;
+  if (threadIdx.x == 1 && q) *q = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -501,14 +625,19 @@ __global__ void k_zero_i64(int64_t *p, int n) {
 // ---------------------------------------------------------------------------
 static inline int64_t blocks_for(int64_t items, int64_t per_block) { return (items + per_block - 1) / per_block; }
 
-template <int K, bool LITE, bool WM>
+template <int K, bool LITE, bool WM, bool LC>
 static int launch_bits_kind(const VerifyArgs &a, int64_t nb, hipStream_t s) {
   switch (a.kind) {
-    case BLSH_PAIRS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_PAIRS, LITE, WM>), dim3(nb), dim3(kBlock), 0, s, a); break;
-    case BLSH_QUERY_LISTS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_QUERY_LISTS, LITE, WM>), dim3(nb), dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_verify_bits<K, BLSH_ALL_PAIRS, LITE, WM>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    case BLSH_PAIRS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_PAIRS, LITE, WM, LC>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    case BLSH_QUERY_LISTS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_QUERY_LISTS, LITE, WM, LC>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_verify_bits<K, BLSH_ALL_PAIRS, LITE, WM, LC>), dim3(nb), dim3(kBlock), 0, s, a); break;
   }
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+template <int K, bool LITE, bool WM>
+static int launch_bits_gather(const VerifyArgs &a, int64_t nb, bool lds_cache, hipStream_t s) {
+  return lds_cache ? launch_bits_kind<K, LITE, WM, true>(a, nb, s) : launch_bits_kind<K, LITE, WM, false>(a, nb, s);
 }
 
 template <int K, bool LITE>
@@ -526,8 +655,9 @@ int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool wor
   if (n <= 0) return BLSH_OK;
   if (a.measure == BLSH_COSINE) {
     const int64_t nb = blocks_for(n, int64_t(kBlock) * kPPT);
-    LaunchScope ls(ctx, s, "verify_bits");
-#define BLSH_B(KK, LL, WW) if (k == KK && lite == LL && word_major == WW) return launch_bits_kind<KK, LL, WW>(a, nb, s);
+    const bool lc = ctx->tuning.gather == 2;
+    LaunchScope ls(ctx, s, lc ? "verify_bits_ldscache" : "verify_bits");
+#define BLSH_B(KK, LL, WW) if (k == KK && lite == LL && word_major == WW) return launch_bits_gather<KK, LL, WW>(a, nb, lc, s);
     BLSH_B(16, false, true) BLSH_B(16, true, true) BLSH_B(16, false, false) BLSH_B(16, true, false)
     BLSH_B(32, false, true) BLSH_B(32, true, true) BLSH_B(32, false, false) BLSH_B(32, true, false)
     BLSH_B(64, false, true) BLSH_B(64, true, true) BLSH_B(64, false, false) BLSH_B(64, true, false)
@@ -566,14 +696,14 @@ int launch_exhaustive(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s) 
 
 int launch_exact(blsh_ctx *ctx, const ExactArgs &e, const VerifyArgs &a, int64_t max_items, hipStream_t s) {
   if (max_items <= 0) return BLSH_OK;
-  const int64_t nb = std::min<int64_t>(blocks_for(max_items, kBlock / kWave), int64_t(ctx->n_cu) * 8);
+  const int64_t nb = std::min<int64_t>(blocks_for(max_items, kBlock / kWave), int64_t(ctx->n_cu) * 2);
   LaunchScope ls(ctx, s, "exact");
   hipLaunchKernelGGL(k_exact, dim3(nb), dim3(kBlock), 0, s, e, a);
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
-int launch_zero(blsh_ctx *ctx, int64_t *p, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, p, n);
+int launch_zero(blsh_ctx *ctx, int64_t *p, int64_t *q, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, p, q);
   (void)ctx;
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }

@@ -133,6 +133,48 @@ def test_verify_pairs_bit_exact(ctx, measure, k):
     assert len(set(want["decision"].tolist())) == 3
 
 
+@pytest.mark.parametrize("k", [16, 32, 64])
+@pytest.mark.parametrize("lite", [False, True])
+def test_lds_tile_cache_matches(ctx, k, lite):
+    """The LDS tile-cache gather gives the same output as direct gathers and the
+    oracle, on bucket-major candidates (many repeated ids per tile) and on
+    random pairs (up to 2 distinct ids per candidate, the cache's worst case)."""
+    _flush("lds tile cache k=%d lite=%d" % (k, lite))
+    n_obj, n_hashes = 6000, 1024
+    sig = _calib_pairs(P.COSINE, n_obj // 2, n_hashes, 40 + k)
+    rng = np.random.default_rng(k)
+    # bucket-major: all pairs inside buckets of 20..80 members
+    xs, ys = [], []
+    for _ in range(40):
+        mem = np.sort(rng.choice(n_obj, rng.integers(20, 80), replace=False))
+        i, j = np.triu_indices(len(mem), 1)
+        xs.append(mem[i]); ys.append(mem[j])
+    xb, yb = np.concatenate(xs).astype(np.uint32), np.concatenate(ys).astype(np.uint32)
+    xr = rng.integers(0, n_obj, 30011).astype(np.uint32)
+    yr = rng.integers(0, n_obj, 30011).astype(np.uint32)
+    S = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR)
+    L = 4 if lite else n_hashes // k
+    for x, y in ((xb, yb), (xr, yr), (np.concatenate([xr, xb]), np.concatenate([yr, yb]))):
+        want = R.verify(x, y, P.COSINE, sig, k, L, T, EPS, DELTA, GAMMA, lite=lite)
+        outs = []
+        for g in (1, 2):
+            P.bayeslsh_set_tuning(ctx, gather=g)
+            res = P.make_result(len(x), len(x), m_debug=True)
+            if lite:
+                dense = P.dense_vectors(torch.ones(n_obj, 8, device="cuda"))
+                P.bayeslsh_lite_verify(ctx, P.pairs(up(x), up(y)), S, dense, T, EPS, (1, 1), L * k, k, res)
+            else:
+                P.bayeslsh_verify(ctx, P.pairs(up(x), up(y)), S, T, EPS, DELTA, GAMMA, (1, 1), k, res)
+            P.bayeslsh_sync(ctx)
+            got = decode_result(res, len(x))
+            np.testing.assert_array_equal(got["decision"], want["decision"])
+            np.testing.assert_array_equal(got["level"], want["level"])
+            np.testing.assert_array_equal(got["m"], want["m"])
+            outs.append(got)
+        np.testing.assert_array_equal(outs[0]["acc_idx"], outs[1]["acc_idx"])
+    P.bayeslsh_set_tuning(ctx, gather=0)
+
+
 def test_verify_jaccard_workload_all_pairs(ctx):
     """The Jaccard workload at full size: 2000 sets, all 1,999,000 pairs, 256
     minhashes, k = 32, t = 0.7, Beta(1,1); explicit pairs give the same result."""
