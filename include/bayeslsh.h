@@ -167,15 +167,31 @@ int bayeslsh_profile_reset(blsh_ctx *ctx);
 int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_ms_host, int64_t *launches_host);
 
 /* Launch tuning of a context (callers that want a fixed configuration, and
- * the autotuner).  Zero fields mean "library default".
+ * the autotuner).  Zero fields mean "library default".  The output is the same
+ * whatever the tuning, except through k (which bayeslsh_verify_batched may
+ * choose when called with k = 0).
  *   gather: 1 = each lane gathers both signatures of its candidates directly;
  *           2 = each block first gathers the level-0 words of the distinct
  *               objects of its tile into an LDS hash table (pays off when
  *               candidates arrive bucket-major, as LSH banding emits them).
- *           Applies to SRP (cosine) verification; the result is identical. */
+ *           Applies to SRP (cosine) bayeslsh_verify / lite_verify.
+ *   batch_inreg: batched calls run this many levels in registers before the
+ *           undecided candidates are compacted into a survivor queue.
+ *   batch_blocks_per_cu: persistent blocks per CU of the batched tile kernel.
+ *   batch_spill_cap: capacity of each survivor queue; a survivor that finds
+ *           the queue full keeps running in registers (same result).
+ *   last_batch_*: set by the library after each batched call (the autotuned
+ *           or given k, in-register levels and blocks per CU); ignored by
+ *           bayeslsh_set_tuning. */
 typedef struct {
   int32_t gather;
-  int32_t reserved[7];
+  int32_t batch_inreg;
+  int32_t batch_blocks_per_cu;
+  int32_t last_batch_k;
+  int32_t last_batch_inreg;
+  int32_t last_batch_blocks_per_cu;
+  int32_t batch_spill_cap;   /* batched: survivor-queue entries per measure (0 = min(n_cand, 2^24)) */
+  int32_t reserved;
 } blsh_tuning;
 int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *tuning_host);
 int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *tuning_host);
@@ -261,6 +277,34 @@ int bayeslsh_exhaustive_verify(blsh_ctx *ctx, const blsh_candidates *cand, const
                                const blsh_vectors *exact, double t, double epsilon, double delta,
                                double gamma, blsh_prior prior, int32_t k, int32_t h,
                                blsh_exhaustive_mode mode, blsh_result *res, void *stream);
+
+/* Batched verification (Algorithm 1) of many query lists in one call: list i
+ * verifies the candidates cand[offset .. offset+length) against its query
+ * object, under its own measure and threshold t, with shared epsilon, delta,
+ * gamma and Jaccard prior.  Lists use `jaccard_sigs` (minhash,
+ * OBJECT_MAJOR) or `cosine_sigs` (SRP, either layout); a set a batch does not
+ * use may be NULL.  Candidate index = position in cand, as for
+ * QUERY_LISTS; positions no list covers are left untouched.  At most 32
+ * distinct thresholds per call.
+ * Execution: one graph of persistent kernels (tile work queue, survivor
+ * compaction into a queue after `batch_inreg` levels, survivor drain).
+ * k = 16, 32 or 64 fixes the chunk size; k = 0 lets an autotuner pick k,
+ * the in-register levels and the grid by timing the candidates on this batch
+ * shape (cached per context) and writes the chosen k to *k_used_host (may be
+ * NULL).  k changes the check points of the algorithm and hence the output.
+ * Consecutive batched calls on one context must use the same stream (or be
+ * synchronised): they share the context's device-side batch descriptor. */
+typedef struct {
+  blsh_measure measure;
+  double t;
+  uint32_t query;
+  int64_t offset;
+  int64_t length;
+} blsh_list_desc;
+int bayeslsh_verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists_host, int64_t n_lists, const uint32_t *cand,
+                            int64_t n_cand, const blsh_sigs *jaccard_sigs, const blsh_sigs *cosine_sigs,
+                            double epsilon, double delta, double gamma, blsh_prior jaccard_prior, int32_t k,
+                            int32_t *k_used_host, blsh_result *res, void *stream);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,14 @@ class Result(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("gather", C.c_int32), ("reserved", C.c_int32 * 7)]
+    _fields_ = [("gather", C.c_int32), ("batch_inreg", C.c_int32), ("batch_blocks_per_cu", C.c_int32),
+                ("last_batch_k", C.c_int32), ("last_batch_inreg", C.c_int32),
+                ("last_batch_blocks_per_cu", C.c_int32), ("batch_spill_cap", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ListDesc(C.Structure):
+    _fields_ = [("measure", C.c_int), ("t", C.c_double), ("query", C.c_uint32), ("offset", C.c_int64),
+                ("length", C.c_int64)]
 
 
 # (name, restype, argtypes) for every symbol of the header
@@ -73,6 +80,9 @@ PROTOTYPES = [
     ("bayeslsh_lite_verify", C.c_int,
      [p, C.POINTER(Candidates), C.POINTER(Sigs), C.POINTER(Vectors), C.c_double, C.c_double, Prior, C.c_int32,
       C.c_int32, C.POINTER(Result), p]),
+    ("bayeslsh_verify_batched", C.c_int,
+     [p, C.POINTER(ListDesc), C.c_int64, p, C.c_int64, C.POINTER(Sigs), C.POINTER(Sigs), C.c_double, C.c_double,
+      C.c_double, Prior, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Result), p]),
     ("bayeslsh_exhaustive_verify", C.c_int,
      [p, C.POINTER(Candidates), C.POINTER(Sigs), C.POINTER(Vectors), C.c_double, C.c_double, C.c_double, C.c_double,
       Prior, C.c_int32, C.c_int32, C.c_int, C.POINTER(Result), p]),

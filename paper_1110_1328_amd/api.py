@@ -279,16 +279,59 @@ def bayeslsh_profile_read(ctx: Context, name: str):
     return ms.value, n.value
 
 
-def bayeslsh_set_tuning(ctx: Context, gather: int = 0):
+def bayeslsh_set_tuning(ctx: Context, gather: int = 0, batch_inreg: int = 0, batch_blocks_per_cu: int = 0,
+                        batch_spill_cap: int = 0):
     t = A.Tuning()
-    t.gather = gather
+    t.gather, t.batch_inreg, t.batch_blocks_per_cu, t.batch_spill_cap = gather, batch_inreg, batch_blocks_per_cu, batch_spill_cap
     _check(_lib().bayeslsh_set_tuning(ctx.handle, C.byref(t)))
 
 
 def bayeslsh_get_tuning(ctx: Context) -> dict:
     t = A.Tuning()
     _check(_lib().bayeslsh_get_tuning(ctx.handle, C.byref(t)))
-    return {"gather": t.gather}
+    return {name: getattr(t, name) for name, _ in A.Tuning._fields_ if name != "reserved"}
+
+
+LIST_DTYPE = None
+
+
+def list_descs(measure, t, query, offset, length):
+    """Host array of blsh_list_desc built from per-list columns (numpy, zero-copy into the call)."""
+    import numpy as np
+    global LIST_DTYPE
+    if LIST_DTYPE is None:
+        f = A.ListDesc
+        LIST_DTYPE = np.dtype({"names": ["measure", "t", "query", "offset", "length"],
+                               "formats": [np.int32, np.float64, np.uint32, np.int64, np.int64],
+                               "offsets": [f.measure.offset, f.t.offset, f.query.offset, f.offset.offset,
+                                           f.length.offset],
+                               "itemsize": C.sizeof(f)})
+    n = len(query)
+    arr = np.zeros(n, LIST_DTYPE)
+    arr["measure"], arr["t"], arr["query"], arr["offset"], arr["length"] = measure, t, query, offset, length
+    return arr
+
+
+def bayeslsh_verify_batched(ctx: Context, lists, cand: torch.Tensor, jaccard_sigs: Signatures | None,
+                            cosine_sigs: Signatures | None, epsilon, delta, gamma, prior=(1.0, 1.0), k=32,
+                            res: Result = None, stream=None) -> int:
+    """lists: array from list_descs().  Returns the k used (the autotuner's choice when k = 0)."""
+    import numpy as np
+    _dev(cand, torch.uint32, "cand")
+    lists = np.ascontiguousarray(lists)
+    if lists.dtype != LIST_DTYPE:
+        raise TypeError("lists must come from list_descs()")
+    if res.code.numel() < cand.numel():
+        raise ValueError("result.code smaller than cand")
+    js = jaccard_sigs.struct() if jaccard_sigs is not None else None
+    cs = cosine_sigs.struct() if cosine_sigs is not None else None
+    rs = res.struct()
+    k_used = C.c_int32(0)
+    _check(_lib().bayeslsh_verify_batched(ctx.handle, lists.ctypes.data_as(C.POINTER(A.ListDesc)), len(lists),
+                                          _p(cand), cand.numel(), C.byref(js) if js is not None else None,
+                                          C.byref(cs) if cs is not None else None, epsilon, delta, gamma,
+                                          _prior(prior), k, C.byref(k_used), C.byref(rs), _stream(stream)))
+    return k_used.value
 
 
 def bayeslsh_posterior_table(ctx, measure, t, epsilon, delta, gamma, prior=(1.0, 1.0), k=32, n_levels=8,

@@ -20,6 +20,10 @@ int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim,
                      bool word_major, uint32_t *out, hipStream_t s);
 
 int launch_exact(blsh_ctx *ctx, const ExactArgs &e, const VerifyArgs &a, int64_t max_items, hipStream_t s);
+int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
+                   const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
+                   blsh_prior prior, int32_t k, blsh_result *res, int32_t *k_used, hipStream_t s,
+                   int (*check_sigs_fn)(const blsh_sigs *, int, int *, int *));
 
 static thread_local char g_err[512] = "";
 
@@ -354,6 +358,7 @@ void bayeslsh_destroy(blsh_ctx *ctx) {
   hipDeviceSynchronize();
   for (auto &kv : ctx->dev_tables) hipFree(kv.second.ptr);
   for (auto &p : ctx->prof_pending) { hipEventDestroy(p.start); hipEventDestroy(p.stop); }
+  if (ctx->batch && ctx->batch_free) ctx->batch_free(ctx->batch);
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->d_status) hipFree(ctx->d_status);
   delete ctx;
@@ -418,7 +423,14 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
 int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
   if (!ctx || !t) return fail(BLSH_EINVAL, "null argument");
   if (t->gather < 0 || t->gather > 2) return fail(BLSH_EINVAL, "tuning.gather must be 0, 1 or 2");
-  ctx->tuning = *t;
+  if (t->batch_inreg < 0 || t->batch_inreg > kMaxLevels) return fail(BLSH_EINVAL, "tuning.batch_inreg out of range");
+  if (t->batch_blocks_per_cu < 0 || t->batch_blocks_per_cu > 32)
+    return fail(BLSH_EINVAL, "tuning.batch_blocks_per_cu must be in [0, 32]");
+  if (t->batch_spill_cap < 0) return fail(BLSH_EINVAL, "tuning.batch_spill_cap < 0");
+  ctx->tuning.gather = t->gather;
+  ctx->tuning.batch_spill_cap = t->batch_spill_cap;
+  ctx->tuning.batch_inreg = t->batch_inreg;
+  ctx->tuning.batch_blocks_per_cu = t->batch_blocks_per_cu;
   return BLSH_OK;
 }
 
@@ -494,6 +506,36 @@ int bayeslsh_lite_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_
                          void *stream) {
   if (!exact) return fail(BLSH_EINVAL, "Lite needs exact vectors");
   return run_verify(ctx, cand, sigs, exact, t, epsilon, 0.5, 0.5, prior, k, h, -1, res, stream);
+}
+
+int bayeslsh_verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand,
+                            int64_t n_cand, const blsh_sigs *jac, const blsh_sigs *cos, double epsilon, double delta,
+                            double gamma, blsh_prior prior, int32_t k, int32_t *k_used, blsh_result *res,
+                            void *stream) {
+  if (!ctx) return fail(BLSH_EINVAL, "null context");
+  int rc = check_params(0.5, epsilon, delta, gamma, false);
+  if (rc) return rc;
+  if (k != 0 && k != 16 && k != 32 && k != 64) return fail(BLSH_EINVAL, "k must be 0 (autotune), 16, 32 or 64");
+  if (n_lists < 0 || n_cand < 0 || n_cand > (int64_t(1) << 40)) return fail(BLSH_EINVAL, "bad list or candidate count");
+  if (n_lists > 0 && !lists) return fail(BLSH_EINVAL, "null list descriptors");
+  if (n_cand > 0 && !cand) return fail(BLSH_EINVAL, "null candidates");
+  if ((rc = check_result(res))) return rc;
+  if ((rc = check_prior(BLSH_JACCARD, prior))) return rc;
+  for (int64_t i = 0; i < n_lists; ++i) {
+    const blsh_list_desc &d = lists[i];
+    if (d.measure != BLSH_JACCARD && d.measure != BLSH_COSINE) return fail(BLSH_EINVAL, "list %lld: bad measure", (long long)i);
+    if (!in01(d.t)) return fail(BLSH_EINVAL, "list %lld: t must be in (0,1)", (long long)i);
+    if (d.offset < 0 || d.length < 0 || d.offset + d.length > n_cand)
+      return fail(BLSH_EINVAL, "list %lld: range outside [0, n_cand)", (long long)i);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n_lists == 0 || n_cand == 0) {
+    if (launch_zero(ctx, res->n_accepted, nullptr, s)) return fail(BLSH_EDEVICE, "launch failed");
+    if (k_used) *k_used = k;
+    return BLSH_OK;
+  }
+  return verify_batched(ctx, lists, n_lists, cand, n_cand, jac, cos, epsilon, delta, gamma, prior, k, res, k_used, s,
+                        check_sigs);
 }
 
 int bayeslsh_exhaustive_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs,

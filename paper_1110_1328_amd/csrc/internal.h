@@ -81,8 +81,11 @@ struct blsh_ctx {
   // survivor workspace
   void *ws = nullptr;
   size_t ws_bytes = 0;
-  // tuning (bayeslsh_set_tuning)
+  // tuning (bayeslsh_set_tuning; last_* fields report the last batched call)
   blsh_tuning tuning{};
+  // batched-call state (persistent buffers, captured graphs, autotune cache)
+  void *batch = nullptr;
+  void (*batch_free)(void *) = nullptr;
   // profiling
   bool prof = false;
   std::vector<blsh::ProfRec> prof_pending;
