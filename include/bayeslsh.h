@@ -306,6 +306,57 @@ int bayeslsh_verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists_host, int
                             double epsilon, double delta, double gamma, blsh_prior jaccard_prior, int32_t k,
                             int32_t *k_used_host, blsh_result *res, void *stream);
 
+/* ---------------- serving ---------------- */
+
+/* A serving loop answers similarity queries against a resident signature
+ * index: each request is a query object, its candidate ids (host memory) and a
+ * threshold t, verified with Algorithm 1 (epsilon, delta, gamma and k fixed at
+ * creation).  A scheduler thread (owned by the server) admits requests FIFO
+ * as long as an in-flight slot is free and their candidate ids fit in a device
+ * arena of mem_budget_bytes (4 bytes per candidate), then runs continuous
+ * batching: each device iteration verifies the next chunk of every admitted
+ * request (fair shares of max_batch_candidates) in one batched launch, so
+ * requests that arrive while others run join the next iteration.  A request
+ * completes when its last chunk's accepted pairs have been copied back; its
+ * output does not depend on the requests it was batched with.
+ * The server uses `ctx` exclusively until bayeslsh_server_destroy; the index
+ * signatures must stay valid meanwhile. */
+typedef struct {
+  size_t mem_budget_bytes;       /* device arena for candidate ids (admission limit) */
+  int32_t max_active;            /* requests admitted at once */
+  int32_t k;                     /* 16, 32 or 64 */
+  int64_t max_batch_candidates;  /* candidates per device iteration */
+  double epsilon, delta, gamma;
+  blsh_prior prior;              /* Jaccard prior (cosine: {1,1}) */
+} blsh_server_config;
+
+/* Result of a finished request.  The arrays are owned by the server and stay
+ * valid until bayeslsh_server_release.  acc_idx are positions in the
+ * request's candidate list (sorted order is not guaranteed).  Times are
+ * seconds on the server's clock (bayeslsh_server_clock). */
+typedef struct {
+  int64_t n_candidates;
+  int64_t n_accepted;
+  const uint64_t *acc_idx_host;
+  const float *acc_val_host;
+  double submit_time_s, admit_time_s, done_time_s;
+  int32_t status;
+} blsh_request_result;
+
+typedef struct blsh_server blsh_server;
+int bayeslsh_server_create(blsh_ctx *ctx, const blsh_sigs *index, const blsh_server_config *cfg, blsh_server **out);
+/* Copies the candidate ids; rejects ids >= n_obj (BLSH_EINVAL) and requests larger
+ * than the arena (BLSH_ENOMEM). */
+int bayeslsh_server_submit(blsh_server *srv, uint32_t query, const uint32_t *cand_host, int64_t n_cand, double t,
+                           int64_t *request_id);
+/* BLSH_OK (finished; *out filled), BLSH_EAGAIN (pending) or an error. */
+int bayeslsh_server_poll(blsh_server *srv, int64_t request_id, blsh_request_result *out);
+int bayeslsh_server_wait(blsh_server *srv, int64_t request_id, blsh_request_result *out);
+int bayeslsh_server_release(blsh_server *srv, int64_t request_id);
+int bayeslsh_server_stats(blsh_server *srv, int64_t *iterations_host, int64_t *pending_host, int64_t *active_host);
+double bayeslsh_server_clock(blsh_server *srv);
+void bayeslsh_server_destroy(blsh_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,18 @@ class ListDesc(C.Structure):
                 ("length", C.c_int64)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_size_t), ("max_active", C.c_int32), ("k", C.c_int32),
+                ("max_batch_candidates", C.c_int64), ("epsilon", C.c_double), ("delta", C.c_double),
+                ("gamma", C.c_double), ("prior", Prior)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("n_candidates", C.c_int64), ("n_accepted", C.c_int64), ("acc_idx_host", C.POINTER(C.c_uint64)),
+                ("acc_val_host", C.POINTER(C.c_float)), ("submit_time_s", C.c_double),
+                ("admit_time_s", C.c_double), ("done_time_s", C.c_double), ("status", C.c_int32)]
+
+
 # (name, restype, argtypes) for every symbol of the header
 PROTOTYPES = [
     ("bayeslsh_create", C.c_int, [C.POINTER(p), C.c_int]),
@@ -83,6 +95,14 @@ PROTOTYPES = [
     ("bayeslsh_verify_batched", C.c_int,
      [p, C.POINTER(ListDesc), C.c_int64, p, C.c_int64, C.POINTER(Sigs), C.POINTER(Sigs), C.c_double, C.c_double,
       C.c_double, Prior, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Result), p]),
+    ("bayeslsh_server_create", C.c_int, [p, C.POINTER(Sigs), C.POINTER(ServerConfig), C.POINTER(p)]),
+    ("bayeslsh_server_submit", C.c_int, [p, C.c_uint32, p, C.c_int64, C.c_double, C.POINTER(C.c_int64)]),
+    ("bayeslsh_server_poll", C.c_int, [p, C.c_int64, C.POINTER(RequestResult)]),
+    ("bayeslsh_server_wait", C.c_int, [p, C.c_int64, C.POINTER(RequestResult)]),
+    ("bayeslsh_server_release", C.c_int, [p, C.c_int64]),
+    ("bayeslsh_server_stats", C.c_int, [p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("bayeslsh_server_clock", C.c_double, [p]),
+    ("bayeslsh_server_destroy", None, [p]),
     ("bayeslsh_exhaustive_verify", C.c_int,
      [p, C.POINTER(Candidates), C.POINTER(Sigs), C.POINTER(Vectors), C.c_double, C.c_double, C.c_double, C.c_double,
       Prior, C.c_int32, C.c_int32, C.c_int, C.POINTER(Result), p]),

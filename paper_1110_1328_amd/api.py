@@ -419,3 +419,78 @@ def bayeslsh_exhaustive_verify(ctx: Context, cand: Candidates, sigs: Signatures,
                                              C.byref(vs) if vs is not None else None, t, epsilon, delta, gamma,
                                              A.Prior(*prior), k, h, mode, C.byref(rs), _stream(stream)))
     return res
+
+
+# ---------------------------------------------------------------------------
+# serving (bayeslsh_server_*)
+# ---------------------------------------------------------------------------
+class Server:
+    """Owns a blsh_server; the context passed in is used by the server alone."""
+
+    def __init__(self, ctx: Context, index: Signatures, mem_budget_bytes: int, max_active: int = 64, k: int = 32,
+                 max_batch_candidates: int = 1 << 24, epsilon=0.03, delta=0.05, gamma=0.03, prior=(1.0, 1.0)):
+        cfg = A.ServerConfig(mem_budget_bytes, max_active, k, max_batch_candidates, epsilon, delta, gamma,
+                             _prior(prior))
+        self._index = index
+        st = index.struct()
+        h = C.c_void_p()
+        _check(_lib().bayeslsh_server_create(ctx.handle, C.byref(st), C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+
+    def clock(self) -> float:
+        return _lib().bayeslsh_server_clock(self.handle)
+
+    def submit(self, query: int, cand, t: float) -> int:
+        import numpy as np
+        cand = np.ascontiguousarray(cand, dtype=np.uint32)
+        rid = C.c_int64()
+        _check(_lib().bayeslsh_server_submit(self.handle, int(query), cand.ctypes.data_as(C.c_void_p), len(cand),
+                                             float(t), C.byref(rid)))
+        return rid.value
+
+    @staticmethod
+    def _result(r: "A.RequestResult"):
+        import numpy as np
+        n = r.n_accepted
+        idx = np.ctypeslib.as_array(r.acc_idx_host, shape=(n,)).copy() if n else np.zeros(0, np.uint64)
+        val = np.ctypeslib.as_array(r.acc_val_host, shape=(n,)).copy() if n else np.zeros(0, np.float32)
+        o = np.argsort(idx, kind="stable")
+        return dict(n_candidates=r.n_candidates, acc_idx=idx[o].astype(np.int64), acc_val=val[o],
+                    submit=r.submit_time_s, admit=r.admit_time_s, done=r.done_time_s, status=r.status)
+
+    def poll(self, rid: int):
+        r = A.RequestResult()
+        rc = _lib().bayeslsh_server_poll(self.handle, rid, C.byref(r))
+        if rc == A.EAGAIN:
+            return None
+        _check(rc)
+        return self._result(r)
+
+    def wait(self, rid: int):
+        r = A.RequestResult()
+        _check(_lib().bayeslsh_server_wait(self.handle, rid, C.byref(r)))
+        return self._result(r)
+
+    def release(self, rid: int):
+        _check(_lib().bayeslsh_server_release(self.handle, rid))
+
+    def stats(self):
+        it, pe, ac = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_lib().bayeslsh_server_stats(self.handle, C.byref(it), C.byref(pe), C.byref(ac)))
+        return dict(iterations=it.value, pending=pe.value, active=ac.value)
+
+    def close(self):
+        if self.handle:
+            _lib().bayeslsh_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bayeslsh_server_create(ctx: Context, index: Signatures, **cfg) -> Server:
+    return Server(ctx, index, **cfg)

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbayeslsh.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["api.hip", "verify.hip", "sigs.hip", "batched.hip", "tables.cpp"]
+SOURCES = ["api.hip", "verify.hip", "sigs.hip", "batched.hip", "tables.cpp", "server.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
 # hipcc-only: no packed FP32 instructions in device code
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -30,8 +30,8 @@ def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip"] + COMMON + DEVICE + ["-c", path, "-o", obj]
-    else:
-        cmd = [HIPCC] + COMMON + ["-pthread", "-c", path, "-o", obj]
+    else:   # host-only C++ (HIP runtime API calls, no kernels)
+        cmd = [HIPCC] + COMMON + ["-D__HIP_PLATFORM_AMD__", "-pthread", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

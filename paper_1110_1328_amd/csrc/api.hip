@@ -152,6 +152,10 @@ static int check_sigs(const blsh_sigs *s, int k, int *n_max_out, int *row_words)
   return BLSH_OK;
 }
 
+int check_sigs_public(const blsh_sigs *s, int k, int *n_max_out, int *row_words) {
+  return check_sigs(s, k, n_max_out, row_words);
+}
+
 static int check_cand(const blsh_candidates *c, int64_t *n_cand) {
   if (!c) return fail(BLSH_EINVAL, "candidates: null");
   switch (c->kind) {
