@@ -353,7 +353,10 @@ int bayeslsh_server_submit(blsh_server *srv, uint32_t query, const uint32_t *can
 int bayeslsh_server_poll(blsh_server *srv, int64_t request_id, blsh_request_result *out);
 int bayeslsh_server_wait(blsh_server *srv, int64_t request_id, blsh_request_result *out);
 int bayeslsh_server_release(blsh_server *srv, int64_t request_id);
-int bayeslsh_server_stats(blsh_server *srv, int64_t *iterations_host, int64_t *pending_host, int64_t *active_host);
+/* Device iterations run, requests waiting and admitted now, and admission rounds
+ * that had to leave requests waiting for a slot or arena space.  Any pointer may be NULL. */
+int bayeslsh_server_stats(blsh_server *srv, int64_t *iterations_host, int64_t *pending_host, int64_t *active_host,
+                          int64_t *deferred_host);
 double bayeslsh_server_clock(blsh_server *srv);
 void bayeslsh_server_destroy(blsh_server *srv);
 

@@ -100,7 +100,8 @@ PROTOTYPES = [
     ("bayeslsh_server_poll", C.c_int, [p, C.c_int64, C.POINTER(RequestResult)]),
     ("bayeslsh_server_wait", C.c_int, [p, C.c_int64, C.POINTER(RequestResult)]),
     ("bayeslsh_server_release", C.c_int, [p, C.c_int64]),
-    ("bayeslsh_server_stats", C.c_int, [p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("bayeslsh_server_stats", C.c_int,
+     [p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("bayeslsh_server_clock", C.c_double, [p]),
     ("bayeslsh_server_destroy", None, [p]),
     ("bayeslsh_exhaustive_verify", C.c_int,

@@ -476,9 +476,9 @@ class Server:
         _check(_lib().bayeslsh_server_release(self.handle, rid))
 
     def stats(self):
-        it, pe, ac = C.c_int64(), C.c_int64(), C.c_int64()
-        _check(_lib().bayeslsh_server_stats(self.handle, C.byref(it), C.byref(pe), C.byref(ac)))
-        return dict(iterations=it.value, pending=pe.value, active=ac.value)
+        it, pe, ac, de = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_lib().bayeslsh_server_stats(self.handle, C.byref(it), C.byref(pe), C.byref(ac), C.byref(de)))
+        return dict(iterations=it.value, pending=pe.value, active=ac.value, deferred=de.value)
 
     def close(self):
         if self.handle:

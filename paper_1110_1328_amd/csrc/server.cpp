@@ -132,6 +132,7 @@ struct blsh_server {
   std::thread th;
   Clock::time_point t0;
   int64_t iterations = 0;
+  int64_t deferred = 0;   // admission rounds that left requests waiting (slots or memory)
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
 
@@ -241,6 +242,7 @@ void scheduler(blsh_server *S) {
         admitted.push_back(r);
         S->pending.pop_front();
       }
+      if (!S->pending.empty()) ++S->deferred;
     }
     for (Request *r : admitted) {
       if (r->n && hipMemcpyAsync(S->d_arena + r->arena_off, r->cand.data(), size_t(r->n) * 4, hipMemcpyHostToDevice,
@@ -404,10 +406,12 @@ int bayeslsh_server_release(blsh_server *srv, int64_t request_id) {
   return BLSH_OK;
 }
 
-int bayeslsh_server_stats(blsh_server *srv, int64_t *iterations_host, int64_t *pending_host, int64_t *active_host) {
+int bayeslsh_server_stats(blsh_server *srv, int64_t *iterations_host, int64_t *pending_host, int64_t *active_host,
+                          int64_t *deferred_host) {
   if (!srv) return fail(BLSH_EINVAL, "null server");
   std::lock_guard<std::mutex> lk(srv->mu);
   if (iterations_host) *iterations_host = srv->iterations;
+  if (deferred_host) *deferred_host = srv->deferred;
   if (pending_host) *pending_host = int64_t(srv->pending.size());
   if (active_host) {
     int64_t a = 0;
