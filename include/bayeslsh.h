@@ -306,6 +306,17 @@ int bayeslsh_verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists_host, int
                             double epsilon, double delta, double gamma, blsh_prior jaccard_prior, int32_t k,
                             int32_t *k_used_host, blsh_result *res, void *stream);
 
+/* Exhaustive comparator for a batch: the same lists, but every candidate
+ * compares all n_max hashes of its object-major row with the query's, and
+ * the decision sequence of Algorithm 1 is replayed on the per-level counts,
+ * so the output equals bayeslsh_verify_batched's at the same k (k required).
+ * Signatures must be OBJECT_MAJOR with 16-byte aligned rows; SRP n_max one of
+ * 128, 256, 512, 1024, 2048; minhash n_max a multiple of 64. */
+int bayeslsh_exhaustive_batched(blsh_ctx *ctx, const blsh_list_desc *lists_host, int64_t n_lists, const uint32_t *cand,
+                                int64_t n_cand, const blsh_sigs *jaccard_sigs, const blsh_sigs *cosine_sigs,
+                                double epsilon, double delta, double gamma, blsh_prior jaccard_prior, int32_t k,
+                                blsh_result *res, void *stream);
+
 /* ---------------- serving ---------------- */
 
 /* A serving loop answers similarity queries against a resident signature

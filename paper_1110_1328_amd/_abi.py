@@ -95,6 +95,9 @@ PROTOTYPES = [
     ("bayeslsh_verify_batched", C.c_int,
      [p, C.POINTER(ListDesc), C.c_int64, p, C.c_int64, C.POINTER(Sigs), C.POINTER(Sigs), C.c_double, C.c_double,
       C.c_double, Prior, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Result), p]),
+    ("bayeslsh_exhaustive_batched", C.c_int,
+     [p, C.POINTER(ListDesc), C.c_int64, p, C.c_int64, C.POINTER(Sigs), C.POINTER(Sigs), C.c_double, C.c_double,
+      C.c_double, Prior, C.c_int32, C.POINTER(Result), p]),
     ("bayeslsh_server_create", C.c_int, [p, C.POINTER(Sigs), C.POINTER(ServerConfig), C.POINTER(p)]),
     ("bayeslsh_server_submit", C.c_int, [p, C.c_uint32, p, C.c_int64, C.c_double, C.POINTER(C.c_int64)]),
     ("bayeslsh_server_poll", C.c_int, [p, C.c_int64, C.POINTER(RequestResult)]),

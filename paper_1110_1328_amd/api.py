@@ -421,6 +421,26 @@ def bayeslsh_exhaustive_verify(ctx: Context, cand: Candidates, sigs: Signatures,
     return res
 
 
+def bayeslsh_exhaustive_batched(ctx: Context, lists, cand: torch.Tensor, jaccard_sigs: Signatures | None,
+                                cosine_sigs: Signatures | None, epsilon, delta, gamma, prior=(1.0, 1.0), k=32,
+                                res: Result = None, stream=None):
+    import numpy as np
+    _dev(cand, torch.uint32, "cand")
+    lists = np.ascontiguousarray(lists)
+    if lists.dtype != LIST_DTYPE:
+        raise TypeError("lists must come from list_descs()")
+    if res.code.numel() < cand.numel():
+        raise ValueError("result.code smaller than cand")
+    js = jaccard_sigs.struct() if jaccard_sigs is not None else None
+    cs = cosine_sigs.struct() if cosine_sigs is not None else None
+    rs = res.struct()
+    _check(_lib().bayeslsh_exhaustive_batched(ctx.handle, lists.ctypes.data_as(C.POINTER(A.ListDesc)), len(lists),
+                                              _p(cand), cand.numel(), C.byref(js) if js is not None else None,
+                                              C.byref(cs) if cs is not None else None, epsilon, delta, gamma,
+                                              _prior(prior), k, C.byref(rs), _stream(stream)))
+    return res
+
+
 # ---------------------------------------------------------------------------
 # serving (bayeslsh_server_*)
 # ---------------------------------------------------------------------------

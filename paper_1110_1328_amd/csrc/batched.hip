@@ -398,6 +398,183 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
   }
 }
 
+// ---------------------------------------------------------------------------
+// exhaustive comparator over the same tiles: every candidate compares the
+// full n_max hashes of its row with the query's, and the decision sequence of
+// Algorithm 1 is replayed on the per-level counts (same output).
+// ---------------------------------------------------------------------------
+// first level in [j0, j1) at which the running count decides; updates m
+__device__ inline int replay_level(const uint32_t *tab, int words, int L, int j, int m, uint8_t &code) {
+  if (m < int(tab[kTabMinOff + j])) { code = uint8_t((BLSH_PRUNED << 6) | j); return 1; }
+  if (accept_bit(tab, words, j, m)) { code = uint8_t((BLSH_ACCEPT_CONC << 6) | j); return 2; }
+  if (j == L - 1) { code = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); return 2; }
+  return 0;
+}
+
+// SRP rows of W words: groups of G = W/4 lanes per candidate (one 16-byte load
+// per lane), exclusive prefix of lane totals, first deciding lane by ballot.
+template <int K, int G>
+__device__ void srp_tile_exhaustive(const BatchBlock &B, const BatchList &Ls, int64_t tile_in_list,
+                                    const uint32_t *tab, int L) {
+  constexpr int LPL = 128 / K;                 // levels per lane
+  constexpr int PER_BLOCK = kBBlock / G;
+  const SigView &S = B.sig[BLSH_COSINE];
+  const int words = int(tab[2]);
+  const int lane = lane_id(), r = lane % G, g = threadIdx.x / G, gw = lane / G;
+  const int64_t end = Ls.offset + Ls.length;
+  const uint32_t q = Ls.query;
+  const bool q_ok = q < S.n_obj;
+  uint4 hq = make_uint4(0, 0, 0, 0);
+  if (q_ok) hq = *reinterpret_cast<const uint4 *>(S.data + size_t(q) * S.row_words + 4 * r);
+  const int64_t t0 = Ls.offset + tile_in_list * kSrpTile;
+  for (int64_t c0 = t0; c0 < min(end, t0 + kSrpTile); c0 += PER_BLOCK) {
+    const int64_t c = c0 + g;
+    const bool in = c < end;
+    uint32_t y = 0;
+    bool ok = false;
+    if (in) {
+      y = B.cand[c];
+      ok = q_ok && y < S.n_obj;
+    }
+    uint32_t cnt[LPL], tot = 0;
+    if (ok) {
+      const uint4 hy = *reinterpret_cast<const uint4 *>(S.data + size_t(y) * S.row_words + 4 * r);
+      const uint32_t d[4] = {hq.x ^ hy.x, hq.y ^ hy.y, hq.z ^ hy.z, hq.w ^ hy.w};
+#pragma unroll
+      for (int qq = 0; qq < LPL; ++qq) {
+        if constexpr (K == 16) cnt[qq] = 16u - __popc((d[qq >> 1] >> ((qq & 1) * 16)) & 0xFFFFu);
+        else if constexpr (K == 32) cnt[qq] = 32u - __popc(d[qq]);
+        else cnt[qq] = 64u - __popc(d[2 * qq]) - __popc(d[2 * qq + 1]);
+        tot += cnt[qq];
+      }
+    } else {
+#pragma unroll
+      for (int qq = 0; qq < LPL; ++qq) cnt[qq] = 0;
+    }
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, G);
+      if (r >= o) incl += v;
+    }
+    uint32_t run = incl - tot;
+    int dec = 0, dm = 0;
+    uint8_t dcode = 0;
+#pragma unroll
+    for (int qq = 0; qq < LPL; ++qq) {
+      run += cnt[qq];
+      const int j = r * LPL + qq;
+      uint8_t cd;
+      if (!dec && ok && j < L) {
+        const int rr = replay_level(tab, words, L, j, int(run), cd);
+        if (rr) { dec = rr; dm = int(run); dcode = cd; }
+      }
+    }
+    const uint64_t has = __ballot(dec != 0);
+    const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << (gw * G);
+    const uint64_t mine = has & gmask;
+    const int first = mine ? __ffsll((unsigned long long)mine) - 1 : gw * G;
+    const int fdec = __shfl(dec, first), fm = __shfl(dm, first);
+    const uint32_t fcode = __shfl(uint32_t(dcode), first);
+    bool emit = false;
+    if (in && r == 0) {
+      B.code[c] = ok ? uint8_t(fcode) : uint8_t(0xFF);
+      if (B.m_dbg) B.m_dbg[c] = uint16_t(fm);
+      emit = ok && fdec == 2;
+      if (!ok) raise_status(B.status, BLSH_EBADID);
+    }
+    const float v = emit ? map_estimate(BLSH_COSINE, fm, ((fcode & 63) + 1) * K, 1.0, 1.0) : 0.f;
+    emit_block(B, emit, c, v);
+  }
+}
+
+// Minhash rows: groups of 16 lanes per candidate, 64 hashes (256 B) per pass;
+// per-level sums with DPP, then the levels replayed in order.
+template <int K>
+__device__ void minhash_tile_exhaustive(const BatchBlock &B, const BatchList &Ls, int64_t tile_in_list,
+                                        const uint32_t *tab, int L, int H) {
+  constexpr int G = 16;
+  constexpr int LPC = 64 / K;                  // levels per 64-hash chunk
+  constexpr int LL = K / 4;                    // lanes per level
+  constexpr int PER_BLOCK = kBBlock / G;
+  const SigView &S = B.sig[BLSH_JACCARD];
+  const int words = int(tab[2]);
+  const int lane = lane_id(), r = lane % G, g = threadIdx.x / G, gw = lane / G;
+  const int64_t end = Ls.offset + Ls.length;
+  const uint32_t q = Ls.query;
+  const bool q_ok = q < S.n_obj;
+  const int64_t t0 = Ls.offset + tile_in_list * kMhTile;
+  for (int64_t c0 = t0; c0 < min(end, t0 + kMhTile); c0 += PER_BLOCK) {
+    const int64_t c = c0 + g;
+    const bool in = c < end;
+    uint32_t y = 0;
+    bool ok = false;
+    if (in) {
+      y = B.cand[c];
+      ok = q_ok && y < S.n_obj;
+    }
+    int m = 0, dec = 0, dm = 0;
+    uint8_t dcode = 0;
+    for (int h0 = 0; h0 < H; h0 += 64) {
+      uint32_t cnt = 0;
+      if (ok) {
+        const uint4 hq = *reinterpret_cast<const uint4 *>(S.data + size_t(q) * S.row_words + h0 + 4 * r);
+        const uint4 hy = *reinterpret_cast<const uint4 *>(S.data + size_t(y) * S.row_words + h0 + 4 * r);
+        cnt = uint32_t(hq.x == hy.x) + uint32_t(hq.y == hy.y) + uint32_t(hq.z == hy.z) + uint32_t(hq.w == hy.w);
+      }
+      cnt = group_sum<LL>(cnt);
+#pragma unroll
+      for (int sl = 0; sl < LPC; ++sl) {
+        const uint32_t lev = __shfl(cnt, gw * G + sl * LL);
+        m += int(lev);
+        const int j = h0 / K + sl;
+        uint8_t cd;
+        if (!dec && ok && j < L) {
+          const int rr = replay_level(tab, words, L, j, m, cd);
+          if (rr) { dec = rr; dm = m; dcode = cd; }
+        }
+      }
+    }
+    bool emit = false;
+    if (in && r == 0) {
+      B.code[c] = ok ? dcode : uint8_t(0xFF);
+      if (B.m_dbg) B.m_dbg[c] = uint16_t(dm);
+      emit = ok && dec == 2;
+      if (!ok) raise_status(B.status, BLSH_EBADID);
+    }
+    const float v = emit ? map_estimate(BLSH_JACCARD, dm, ((dcode & 63) + 1) * K, B.alpha, B.beta) : 0.f;
+    emit_block(B, emit, c, v);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBBlock) void k_batch_exhaustive(const BatchBlock *__restrict__ Bp) {
+  const BatchBlock &B = *Bp;
+  __shared__ long long s_tile;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (long long)atomicAdd(&B.counters[0], 1ull);
+    __syncthreads();
+    const long long t = s_tile;
+    if (t >= B.n_tiles) break;
+    const int64_t l = list_of_tile(B.tile_prefix, B.n_lists, t);
+    const BatchList Ls = B.lists[l];
+    const uint32_t *tab = B.tables[Ls.table];
+    const int L = B.n_levels[Ls.table];
+    const int64_t tl = t - B.tile_prefix[l];
+    if (Ls.measure == BLSH_COSINE) {
+      const int W = L * K / 32;   // words compared: n_max bits
+      if (W == 4) srp_tile_exhaustive<K, 1>(B, Ls, tl, tab, L);
+      else if (W == 8) srp_tile_exhaustive<K, 2>(B, Ls, tl, tab, L);
+      else if (W == 16) srp_tile_exhaustive<K, 4>(B, Ls, tl, tab, L);
+      else if (W == 32) srp_tile_exhaustive<K, 8>(B, Ls, tl, tab, L);
+      else srp_tile_exhaustive<K, 16>(B, Ls, tl, tab, L);
+    } else {
+      minhash_tile_exhaustive<K>(B, Ls, tl, tab, L, L * K);
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_batch_reset(const BatchBlock *__restrict__ Bp) {
   const BatchBlock &B = *Bp;
   if (threadIdx.x < 3) B.counters[threadIdx.x] = 0;
@@ -420,8 +597,10 @@ struct BatchState {
   bool staged_valid = false;
   hipStream_t cap_stream{};
   struct GraphKey {
-    int k, grid1, grid2;
-    bool operator<(const GraphKey &o) const { return std::tie(k, grid1, grid2) < std::tie(o.k, o.grid1, o.grid2); }
+    int mode, k, grid1, grid2;
+    bool operator<(const GraphKey &o) const {
+      return std::tie(mode, k, grid1, grid2) < std::tie(o.mode, o.k, o.grid1, o.grid2);
+    }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
   struct Choice { int k, inreg, bpc; };
@@ -498,21 +677,25 @@ static int grow_spill(BatchState *b, int64_t cap) {
 }
 
 template <int K>
-static void launch_batch_kernels(BatchState *b, int grid1, int grid2, hipStream_t s) {
+static void launch_batch_kernels(BatchState *b, int mode, int grid1, int grid2, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, b->d_block);
+  if (mode == 1) {
+    hipLaunchKernelGGL(k_batch_exhaustive<K>, dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
+    return;
+  }
   hipLaunchKernelGGL(k_batch_phase1<K>, dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
   hipLaunchKernelGGL(k_batch_phase2<K>, dim3(grid2), dim3(kBBlock), 0, s, b->d_block);
 }
 
-static int get_graph(BatchState *b, int k, int grid1, int grid2, hipGraphExec_t *out) {
-  BatchState::GraphKey key{k, grid1, grid2};
+static int get_graph(BatchState *b, int mode, int k, int grid1, int grid2, hipGraphExec_t *out) {
+  BatchState::GraphKey key{mode, k, grid1, grid2};
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) { *out = it->second; return BLSH_OK; }
   hipGraph_t g;
   BLSH_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-  if (k == 16) launch_batch_kernels<16>(b, grid1, grid2, b->cap_stream);
-  else if (k == 32) launch_batch_kernels<32>(b, grid1, grid2, b->cap_stream);
-  else launch_batch_kernels<64>(b, grid1, grid2, b->cap_stream);
+  if (k == 16) launch_batch_kernels<16>(b, mode, grid1, grid2, b->cap_stream);
+  else if (k == 32) launch_batch_kernels<32>(b, mode, grid1, grid2, b->cap_stream);
+  else launch_batch_kernels<64>(b, mode, grid1, grid2, b->cap_stream);
   BLSH_HIP(hipStreamEndCapture(b->cap_stream, &g));
   hipGraphExec_t ex;
   hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -526,7 +709,7 @@ static int get_graph(BatchState *b, int k, int grid1, int grid2, hipGraphExec_t 
 int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
                    const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
                    blsh_prior prior, int32_t k, blsh_result *res, int32_t *k_used, hipStream_t s,
-                   int (*check_sigs_fn)(const blsh_sigs *, int, int *, int *)) {
+                   int (*check_sigs_fn)(const blsh_sigs *, int, int *, int *), int mode) {
   BatchState *b = nullptr;
   int rc = batch_state(ctx, &b);
   if (rc) return rc;
@@ -622,14 +805,14 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     const int grid1 = std::max(1, ctx->n_cu * bpc);
     const int grid2 = std::max(1, ctx->n_cu * 4);
     hipGraphExec_t ex;
-    if ((r2 = get_graph(b, kk, grid1, grid2, &ex))) return r2;
-    LaunchScope ls(ctx, s, "batched_graph");
+    if ((r2 = get_graph(b, mode, kk, grid1, grid2, &ex))) return r2;
+    LaunchScope ls(ctx, s, mode ? "batched_exhaustive_graph" : "batched_graph");
     BLSH_HIP(hipGraphLaunch(ex, s));
     return BLSH_OK;
   };
 
   BatchState::Choice ch{k ? k : 32, 2, 4};
-  if (k == 0) {
+  if (k == 0 && mode == 0) {
     // autotune key: batch shape (the choice is cached per context)
     std::vector<int64_t> key{n_lists, n_cand >> 16, int64_t(need[0]), int64_t(need[1]), n_max[0], n_max[1],
                              int64_t(ts.size())};

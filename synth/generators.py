@@ -447,3 +447,90 @@ def pack_bits(bits01: np.ndarray) -> np.ndarray:
     b = bits01.reshape(n, nb // 32, 32).astype(np.uint64)
     w = (b << np.arange(32, dtype=np.uint64)).sum(2)
     return w.astype(np.uint32)
+
+
+# ----------------------------------------------------------------------------
+# Large-scale variants (vectorised) for the batched and serving workloads
+# ----------------------------------------------------------------------------
+def jaccard_sets_large(n_sets=1_000_000, vocab=100_000, median=60.0, sigma=0.8, n_groups=50_000, group_size=5,
+                       frac_lo=0.1, frac_hi=0.4, seed=SEED_BASE + 5) -> SetCollection:
+    """The planted-group set collection at scale, drawn without per-set Python
+    loops.  Elements are drawn with replacement and deduplicated (at these
+    sizes a set loses an element with probability ~ size^2 / (2 vocab));
+    a member keeps each base element with probability 1 - f and replaces the
+    others by uniform ids (dropped if they collide with the base)."""
+    rng = _rng(seed)
+    sizes = np.maximum(1, np.rint(np.exp(math.log(median) + sigma * rng.standard_normal(n_sets)))).astype(np.int64)
+    sizes = np.minimum(sizes, vocab // 2)
+    pos = rng.permutation(n_sets)
+    group = np.full(n_sets, -1, np.int32)
+    is_base = np.zeros(n_sets, bool)
+    n_planted = n_groups * group_size
+    gpos = pos[:n_planted].reshape(n_groups, group_size)
+    group[gpos.ravel()] = np.repeat(np.arange(n_groups, dtype=np.int32), group_size)
+    is_base[gpos[:, 0]] = True
+    # independent rows: background sets and group bases
+    indep = np.concatenate([gpos[:, 0], pos[n_planted:]])
+    lens = sizes[indep]
+    owner = np.repeat(indep, lens)
+    el = rng.integers(0, vocab, size=int(lens.sum()), dtype=np.int64)
+    key = np.unique(owner.astype(np.int64) * vocab + el)
+    # members derived from their base
+    base_of = np.repeat(gpos[:, 0], group_size - 1)
+    members = gpos[:, 1:].ravel()
+    f = rng.uniform(frac_lo, frac_hi, size=len(members))
+    b_owner = key // vocab
+    b_elem = key - b_owner * vocab
+    b_start = np.searchsorted(b_owner, base_of, side="left")
+    b_end = np.searchsorted(b_owner, base_of, side="right")
+    m_len = b_end - b_start
+    m_owner = np.repeat(members, m_len)
+    idx = np.concatenate([np.arange(s, e) for s, e in zip(b_start, b_end)]) if len(members) else np.zeros(0, np.int64)
+    src = b_elem[idx]
+    keep = rng.random(len(idx)) >= np.repeat(f, m_len)
+    repl = rng.integers(0, vocab, size=len(idx), dtype=np.int64)
+    m_el = np.where(keep, src, repl)
+    m_key = np.unique(m_owner.astype(np.int64) * vocab + m_el)
+    # drop replaced ids that collided with a kept element (unique already merged them)
+    all_key = np.concatenate([key, m_key])
+    all_key.sort()
+    owner = all_key // vocab
+    elems = (all_key - owner * vocab).astype(np.uint32)
+    offsets = np.zeros(n_sets + 1, np.int64)
+    np.cumsum(np.bincount(owner, minlength=n_sets), out=offsets[1:])
+    return SetCollection(offsets, elems, group, is_base, vocab)
+
+
+def sorted_uniform_ids(n_obj: int, count: int, rng) -> np.ndarray:
+    """`count` ids uniform on [0, n_obj), returned sorted (repeats possible)."""
+    if count <= 0:
+        return np.zeros(0, np.uint32)
+    g = rng.exponential(size=count + 1)
+    c = np.cumsum(g)
+    return np.minimum((c[:-1] / c[-1] * n_obj).astype(np.int64), n_obj - 1).astype(np.uint32)
+
+
+def member_lists(n_lists, n_obj, len_lo_exp, len_hi_exp, related, member_frac=0.01, seed=SEED_BASE + 3,
+                 queries=None):
+    """Candidate lists of length floor(10^U(lo, hi)): a fraction `member_frac` from
+    the query's related objects (``related(q)``), the rest sorted uniform ids.
+    Returns (queries uint32, offsets int64, cand uint32)."""
+    rng = _rng(seed)
+    lens = np.floor(10.0 ** rng.uniform(len_lo_exp, len_hi_exp, size=n_lists)).astype(np.int64)
+    if queries is None:
+        queries = rng.integers(0, n_obj, size=n_lists).astype(np.uint32)
+    offsets = np.zeros(n_lists + 1, np.int64)
+    np.cumsum(lens, out=offsets[1:])
+    cand = np.empty(int(offsets[-1]), np.uint32)
+    for i in range(n_lists):
+        L = int(lens[i])
+        rel = np.asarray(related(int(queries[i])), dtype=np.int64)
+        n_rel = min(len(rel), int(round(member_frac * L)))
+        pick = rng.choice(rel, size=n_rel, replace=False) if n_rel else np.zeros(0, np.int64)
+        c = np.concatenate([pick.astype(np.uint32), sorted_uniform_ids(n_obj, L - n_rel, rng)])
+        c.sort()
+        cand[offsets[i]:offsets[i + 1]] = c
+    return queries, offsets, cand
+
+
+__all__ += ["jaccard_sets_large", "sorted_uniform_ids", "member_lists"]

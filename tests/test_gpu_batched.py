@@ -155,3 +155,17 @@ def test_batched_bad_query_and_invalid_lists(ctx, workload):
     with pytest.raises(P.BayesLSHError):   # a cosine list without cosine signatures
         P.bayeslsh_verify_batched(ctx, cos_only, up(w["cand"]), sigs_tensor(w["sj"], P.JACCARD, P.OBJECT_MAJOR), None,
                                   EPS, DELTA, GAMMA, (1, 1), 32, res)
+
+
+@pytest.mark.parametrize("k", [16, 32, 64])
+def test_exhaustive_batched_equals_batched(ctx, workload, k):
+    print("exhaustive batched k=%d" % k, flush=True)
+    w = workload
+    want = oracle_batched(w, k)
+    lists = P.list_descs(w["meas"], w["ts"], w["queries"], w["offsets"][:-1], w["lens"])
+    n = len(w["cand"])
+    res = P.make_result(n, n, m_debug=True)
+    P.bayeslsh_exhaustive_batched(ctx, lists, up(w["cand"]), sigs_tensor(w["sj"], P.JACCARD, P.OBJECT_MAJOR),
+                                  sigs_tensor(w["sc"], P.COSINE, P.OBJECT_MAJOR), EPS, DELTA, GAMMA, (1, 1), k, res)
+    P.bayeslsh_sync(ctx)
+    check(decode_result(res, n), want)
