@@ -123,7 +123,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="20k-document workload (quick check)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true", help="time a plain 1 GiB device copy and exit")
-    ap.add_argument("--gather", type=int, default=0, help="verify gather mode: 0 library default, 1 direct, 2 LDS cache")
+    ap.add_argument("--gather", type=int, default=0,
+                    help="verify gather mode: 0 library default, 1 direct, 2 LDS tile cache, 3 persistent LDS cache")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -190,7 +191,9 @@ def main():
         step()
     P.bayeslsh_sync(ctx, stream)
     k_ms, k_n = P.bayeslsh_profile_read(ctx, "verify_bits")
-    k_name = "k_verify_bits (%s)" % ("LDS tile cache" if P.bayeslsh_get_tuning(ctx)["gather"] == 2 else "direct gathers")
+    g = P.bayeslsh_get_tuning(ctx)["gather"]
+    k_name = {2: "k_verify_bits (LDS tile cache)", 3: "k_verify_bits_pc (persistent LDS cache)"}.get(
+        g, "k_verify_bits (direct gathers)")
     x_ms, x_n = P.bayeslsh_profile_read(ctx, "exact")
     P.bayeslsh_profile_enable(ctx, False)
     log("BayesLSH-Lite: %.3f ms/step (verify kernel %.3f ms, exact %.3f ms)" % (ms_step, k_ms / max(k_n, 1),

@@ -172,7 +172,10 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
  * choose when called with k = 0).
  *   gather: 1 = each lane gathers both signatures of its candidates directly;
  *           2 = each block first gathers the level-0 words of the distinct
- *               objects of its tile into an LDS hash table (pays off when
+ *               objects of its tile into an LDS hash table;
+ *           3 = persistent blocks own contiguous candidate ranges and keep a
+ *               direct-mapped LDS cache of the first three signature words of
+ *               recently seen objects across tiles (modes 2 and 3 pay off when
  *               candidates arrive bucket-major, as LSH banding emits them).
  *           Applies to SRP (cosine) bayeslsh_verify / lite_verify.
  *   batch_inreg: batched calls run this many levels in registers before the

@@ -426,7 +426,7 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
 
 int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
   if (!ctx || !t) return fail(BLSH_EINVAL, "null argument");
-  if (t->gather < 0 || t->gather > 2) return fail(BLSH_EINVAL, "tuning.gather must be 0, 1 or 2");
+  if (t->gather < 0 || t->gather > 3) return fail(BLSH_EINVAL, "tuning.gather must be 0, 1, 2 or 3");
   if (t->batch_inreg < 0 || t->batch_inreg > kMaxLevels) return fail(BLSH_EINVAL, "tuning.batch_inreg out of range");
   if (t->batch_blocks_per_cu < 0 || t->batch_blocks_per_cu > 32)
     return fail(BLSH_EINVAL, "tuning.batch_blocks_per_cu must be in [0, 32]");

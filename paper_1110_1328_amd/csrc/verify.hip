@@ -650,9 +650,12 @@ static int launch_minhash_kind(const VerifyArgs &a, int64_t nb, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
+int launch_verify_bits_cached(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool wm, hipStream_t s);
+
 int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool word_major, hipStream_t s) {
   const int64_t n = a.c_end - a.c_begin;
   if (n <= 0) return BLSH_OK;
+  if (a.measure == BLSH_COSINE && ctx->tuning.gather == 3) return launch_verify_bits_cached(ctx, a, k, lite, word_major, s);
   if (a.measure == BLSH_COSINE) {
     const int64_t nb = blocks_for(n, int64_t(kBlock) * kPPT);
     const bool lc = ctx->tuning.gather == 2;
@@ -696,7 +699,7 @@ int launch_exhaustive(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s) 
 
 int launch_exact(blsh_ctx *ctx, const ExactArgs &e, const VerifyArgs &a, int64_t max_items, hipStream_t s) {
   if (max_items <= 0) return BLSH_OK;
-  const int64_t nb = std::min<int64_t>(blocks_for(max_items, kBlock / kWave), int64_t(ctx->n_cu) * 2);
+  const int64_t nb = std::min<int64_t>(blocks_for(max_items, kBlock / kWave), int64_t(ctx->n_cu) * 16);
   LaunchScope ls(ctx, s, "exact");
   hipLaunchKernelGGL(k_exact, dim3(nb), dim3(kBlock), 0, s, e, a);
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;

@@ -136,9 +136,10 @@ def test_verify_pairs_bit_exact(ctx, measure, k):
 @pytest.mark.parametrize("k", [16, 32, 64])
 @pytest.mark.parametrize("lite", [False, True])
 def test_lds_tile_cache_matches(ctx, k, lite):
-    """The LDS tile-cache gather gives the same output as direct gathers and the
-    oracle, on bucket-major candidates (many repeated ids per tile) and on
-    random pairs (up to 2 distinct ids per candidate, the cache's worst case)."""
+    """The LDS tile cache (gather 2) and the persistent LDS cache (gather 3) give
+    the same output as direct gathers and the oracle, on bucket-major
+    candidates (many repeated ids per tile) and on random pairs (up to 2
+    distinct ids per candidate, the caches' worst case)."""
     _flush("lds tile cache k=%d lite=%d" % (k, lite))
     n_obj, n_hashes = 6000, 1024
     sig = _calib_pairs(P.COSINE, n_obj // 2, n_hashes, 40 + k)
@@ -157,7 +158,7 @@ def test_lds_tile_cache_matches(ctx, k, lite):
     for x, y in ((xb, yb), (xr, yr), (np.concatenate([xr, xb]), np.concatenate([yr, yb]))):
         want = R.verify(x, y, P.COSINE, sig, k, L, T, EPS, DELTA, GAMMA, lite=lite)
         outs = []
-        for g in (1, 2):
+        for g in (1, 2, 3):
             P.bayeslsh_set_tuning(ctx, gather=g)
             res = P.make_result(len(x), len(x), m_debug=True)
             if lite:
@@ -172,6 +173,7 @@ def test_lds_tile_cache_matches(ctx, k, lite):
             np.testing.assert_array_equal(got["m"], want["m"])
             outs.append(got)
         np.testing.assert_array_equal(outs[0]["acc_idx"], outs[1]["acc_idx"])
+        np.testing.assert_array_equal(outs[0]["acc_idx"], outs[2]["acc_idx"])
     P.bayeslsh_set_tuning(ctx, gather=0)
 
 
