@@ -123,8 +123,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="20k-document workload (quick check)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true", help="time a plain 1 GiB device copy and exit")
-    ap.add_argument("--gather", type=int, default=0,
-                    help="verify gather mode: 0 library default, 1 direct, 2 LDS tile cache, 3 persistent LDS cache")
+    ap.add_argument("--layout", choices=["prefix", "word-major"], default="prefix",
+                    help="SRP layout verified: object-major 128-bit rows (prefix) or word-major slabs of all bits")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -142,8 +142,6 @@ def main():
     n = len(x)
     log("corpus %d docs, %d nnz; %d candidates" % (corpus.n, len(corpus.indices), n))
     ctx = P.bayeslsh_create(0)
-    if args.gather:
-        P.bayeslsh_set_tuning(ctx, gather=args.gather)
     vec = P.csr_vectors(up(torch, corpus.offsets), up(torch, corpus.indices), up(torch, corpus.values), corpus.dim)
     xd, yd = up(torch, x), up(torch, y)
     W = N_BITS // 32
@@ -155,10 +153,19 @@ def main():
     P.bayeslsh_sync(ctx)
     sig_ms = (time.perf_counter() - t0) * 1e3
     P.bayeslsh_srp_sigs(ctx, vec, None, N_BITS, SRP_SEED, P.OBJECT_MAJOR, sig_om)
+    # Lite reads at most h bits: object-major rows of the first h bits (the plane of
+    # hash b does not depend on how many hashes are generated, so these are the
+    # first h bits of the full signatures)
+    sig_pf = torch.empty(corpus.n * (H // 32), dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, vec, None, H, SRP_SEED, P.OBJECT_MAJOR, sig_pf)
     P.bayeslsh_sync(ctx)
     log("signatures: %.1f ms for %d x %d bits" % (sig_ms, corpus.n, N_BITS))
     S_wm = P.Signatures(sig_wm, P.COSINE, P.WORD_MAJOR, corpus.n, N_BITS)
     S_om = P.Signatures(sig_om, P.COSINE, P.OBJECT_MAJOR, corpus.n, N_BITS)
+    S_pf = P.Signatures(sig_pf, P.COSINE, P.OBJECT_MAJOR, corpus.n, H)
+    S_run = S_pf if args.layout == "prefix" else S_wm
+    same_prefix = bool(torch.equal(sig_pf.view(torch.int32).view(corpus.n, H // 32),
+                                   sig_om.view(torch.int32).view(corpus.n, N_BITS // 32)[:, : H // 32]))
     cand = P.pairs(xd, yd)
     cap = max(1 << 20, n // 100)
     res = P.make_result(n, cap)
@@ -166,7 +173,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        P.bayeslsh_lite_verify(ctx, cand, S_wm, vec, T, EPS, (1.0, 1.0), H, K, res, stream)
+        P.bayeslsh_lite_verify(ctx, cand, S_run, vec, T, EPS, (1.0, 1.0), H, K, res, stream)
 
     def step_ex():
         P.bayeslsh_exhaustive_verify(ctx, cand, S_om, vec, T, EPS, 0.5, 0.5, (1.0, 1.0), K, H, P.REPLAY_LITE, res_ex,
@@ -191,13 +198,11 @@ def main():
         step()
     P.bayeslsh_sync(ctx, stream)
     k_ms, k_n = P.bayeslsh_profile_read(ctx, "verify_bits")
-    g = P.bayeslsh_get_tuning(ctx)["gather"]
-    k_name = {2: "k_verify_bits (LDS tile cache)", 3: "k_verify_bits_pc (persistent LDS cache)"}.get(
-        g, "k_verify_bits (direct gathers)")
-    x_ms, x_n = P.bayeslsh_profile_read(ctx, "exact")
+    k_name = ("k_verify_bits, object-major 128-bit rows (one 16-byte gather per side), fused Lite exact"
+              if args.layout == "prefix" else "k_verify_bits, word-major slabs, fused Lite exact")
+    x_ms, x_n = P.bayeslsh_profile_read(ctx, "exact")   # separate exact kernel (not used by this path)
     P.bayeslsh_profile_enable(ctx, False)
-    log("BayesLSH-Lite: %.3f ms/step (verify kernel %.3f ms, exact %.3f ms)" % (ms_step, k_ms / max(k_n, 1),
-                                                                              x_ms / max(x_n, 1)))
+    log("BayesLSH-Lite: %.3f ms/step (verify kernel %.3f ms)" % (ms_step, k_ms / max(k_n, 1)))
     # exhaustive comparator
     ex_steps = max(3, args.steps // 5)
     for _ in range(2):
@@ -220,10 +225,11 @@ def main():
     dec, lvl = codes >> 6, codes & 63
     n_surv = int(np.sum(dec == 3))
     # Algorithmic bytes of the verify kernel per launch.  HBM stream: candidate ids
-    # (8 B) + code (1 B) per candidate + one 16 B survivor-queue entry per survivor.
-    # The signature chunks (2 x k/8 B per level reached) are gathered from the
-    # word-major slabs (4 B x 100k objects per level), which stay in L2.
-    hbm_bytes = n * 9 + 16 * n_surv
+    # (8 B) and one code byte per candidate.  The signature bytes examined
+    # (2 x k/8 B per level reached) come from a 1.6 MB array (prefix layout) or
+    # 400 KB slabs (word-major) that stay in L2; the exact cosine of the rare
+    # survivors reads their two sparse rows (~2 x 100 x 8 B).
+    hbm_bytes = n * 9
     gather_bytes = int(np.sum(lvl.astype(np.int64) + 1)) * 2 * (K // 8)
     k_avg_ms = k_ms / max(k_n, 1)
     per_step = max(k_n, 1) / args.steps                 # verify launches per step (candidate chunks)
@@ -255,6 +261,7 @@ def main():
         "exhaustive": {"ms_per_step": ex_ms, "value": n / (ex_ms * 1e-3), "speedup": ex_ms / ms_step,
                        "same_output": same, "mode": "REPLAY_LITE, all 2048 bits per object"},
         "signature_ms": sig_ms,
+        "prefix_rows_equal_full_signature_prefix": same_prefix,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": k_name,
                      "kernel_ms": k_avg_ms, "kernel_launches_timed": k_n, "hbm_bytes_per_launch": hbm_bytes,

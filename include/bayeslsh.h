@@ -170,14 +170,12 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
  * the autotuner).  Zero fields mean "library default".  The output is the same
  * whatever the tuning, except through k (which bayeslsh_verify_batched may
  * choose when called with k = 0).
- *   gather: 1 = each lane gathers both signatures of its candidates directly;
- *           2 = each block first gathers the level-0 words of the distinct
- *               objects of its tile into an LDS hash table;
- *           3 = persistent blocks own contiguous candidate ranges and keep a
- *               direct-mapped LDS cache of the first three signature words of
- *               recently seen objects across tiles (modes 2 and 3 pay off when
- *               candidates arrive bucket-major, as LSH banding emits them).
- *           Applies to SRP (cosine) bayeslsh_verify / lite_verify.
+ *   gather: 1 = each lane gathers both signatures of its candidates directly
+ *           (the only SRP gather scheme; reserved for alternatives).
+ *           SRP signatures in OBJECT_MAJOR layout with rows of a multiple of
+ *           128 hashes, 16-byte aligned, are read 128 hashes at a time (one
+ *           16-byte gather per side serves the first 128/k levels), the fastest
+ *           layout when most pairs end within the first 128 hashes.
  *   batch_inreg: batched calls run this many levels in registers before the
  *           undecided candidates are compacted into a survivor queue.
  *   batch_blocks_per_cu: persistent blocks per CU of the batched tile kernel.

@@ -19,7 +19,7 @@ int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *ind
 int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim, const float *R, int n_bits,
                      bool word_major, uint32_t *out, hipStream_t s);
 
-int launch_exact(blsh_ctx *ctx, const ExactArgs &e, const VerifyArgs &a, int64_t max_items, hipStream_t s);
+int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStream_t s);
 int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
                    const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
                    blsh_prior prior, int32_t k, blsh_result *res, int32_t *k_used, hipStream_t s,
@@ -234,16 +234,13 @@ static int get_queue(blsh_ctx *ctx, int64_t chunk, Queue *q) {
   return BLSH_OK;
 }
 
-static void fill_exact(ExactArgs &e, const blsh_vectors *v, const Queue &q, double t) {
-  e.vec_kind = v->kind;
-  e.dense = v->dense;
-  e.dim = v->dim;
-  e.offsets = v->offsets;
-  e.indices = v->indices;
-  e.values = v->values;
-  e.q_rel = q.rel;
-  e.q_n = q.n;
-  e.t = t;
+static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
+  a.ex_kind = v->kind;
+  a.ex_dense = v->dense;
+  a.ex_dim = v->dim;
+  a.ex_offsets = v->offsets;
+  a.ex_indices = v->indices;
+  a.ex_values = v->values;
 }
 
 // Shared driver of verify / lite / exhaustive.
@@ -306,8 +303,9 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   if (lite && (rc = get_queue(ctx, chunk, &q))) return rc;
   a.q_rel = q.rel;
   a.q_n = q.n;
-  ExactArgs e{};
-  if (lite) fill_exact(e, exact, q, t);
+  if (lite) fill_exact(a, exact);
+  // the SRP early-exit kernel computes Lite exact similarities itself
+  const bool fused_exact = lite && exhaustive_mode == -1 && sigs->measure == BLSH_COSINE;
   for (int64_t c0 = 0; c0 < n_cand; c0 += chunk) {
     a.c_begin = c0;
     a.c_end = std::min(n_cand, c0 + chunk);
@@ -317,7 +315,7 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
     rc = exh ? launch_exhaustive(ctx, a, k, s)
              : launch_verify(ctx, a, k, lite, sigs->measure == BLSH_COSINE && sigs->layout == BLSH_WORD_MAJOR, s);
     if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;
-    if (lite && (rc = launch_exact(ctx, e, a, a.c_end - a.c_begin, s))) return fail(rc, "exact launch failed");
+    if (lite && !fused_exact && (rc = launch_exact(ctx, a, a.c_end - a.c_begin, s))) return fail(rc, "exact launch failed");
   }
   return BLSH_OK;
 }
@@ -426,7 +424,7 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
 
 int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
   if (!ctx || !t) return fail(BLSH_EINVAL, "null argument");
-  if (t->gather < 0 || t->gather > 3) return fail(BLSH_EINVAL, "tuning.gather must be 0, 1, 2 or 3");
+  if (t->gather < 0 || t->gather > 1) return fail(BLSH_EINVAL, "tuning.gather must be 0 or 1");
   if (t->batch_inreg < 0 || t->batch_inreg > kMaxLevels) return fail(BLSH_EINVAL, "tuning.batch_inreg out of range");
   if (t->batch_blocks_per_cu < 0 || t->batch_blocks_per_cu > 32)
     return fail(BLSH_EINVAL, "tuning.batch_blocks_per_cu must be in [0, 32]");

@@ -42,26 +42,26 @@ struct VerifyArgs {
   uint32_t *q_rel;
   int64_t *q_n;
   int32_t *status;
+  // exact similarity (Lite): the caller's vectors
+  int32_t ex_kind;
+  const float *ex_dense;
+  int64_t ex_dim;
+  const int64_t *ex_offsets;
+  const uint32_t *ex_indices;
+  const float *ex_values;
   // exhaustive
   int32_t mode;                          // 0 replay, 1 replay-lite, 2 mle
   int32_t count_levels;                  // levels compared in full (n_max/k)
   double t;
 };
 
-// Arguments of the exact-similarity kernel (Lite survivors).
-struct ExactArgs {
-  int32_t vec_kind;
-  const float *dense;
-  int64_t dim;
-  const int64_t *offsets;
-  const uint32_t *indices;
-  const float *values;
-  const uint32_t *q_rel;
-  const int64_t *q_n;
-  double t;
-};
-
 __device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline double wave_sum_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
 
 // Number of set bits of `mask` in lanes below the calling lane.
 __device__ inline uint32_t lanes_below(uint64_t mask) {

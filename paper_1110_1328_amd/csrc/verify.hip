@@ -58,52 +58,110 @@ __device__ inline uint32_t level_agree_bits(const VerifyArgs &a, uint32_t xi, ui
 constexpr int kPPT = 4;        // candidates per lane (bits kernel)
 constexpr int kBlock = 256;
 
-// Level-0 agreement from words already held (LDS tile cache).
+// agreement of level j from words already in registers (16-byte prefix)
 template <int K>
-__device__ inline uint32_t agree_words(uint32_t x0, uint32_t x1, uint32_t y0, uint32_t y1, int j) {
-  if constexpr (K == 32) return 32u - __popc(x0 ^ y0);
-  else if constexpr (K == 64) return 64u - __popc(x0 ^ y0) - __popc(x1 ^ y1);
-  else return 16u - __popc(((x0 ^ y0) >> ((j & 1) * 16)) & 0xFFFFu);
+__device__ inline uint32_t agree_from(const uint32_t *wx, const uint32_t *wy, int j) {
+  if constexpr (K == 32) return 32u - __popc(wx[j] ^ wy[j]);
+  else if constexpr (K == 64) return 64u - __popc(wx[2 * j] ^ wy[2 * j]) - __popc(wx[2 * j + 1] ^ wy[2 * j + 1]);
+  else return 16u - __popc(((wx[j >> 1] ^ wy[j >> 1]) >> ((j & 1) * 16)) & 0xFFFFu);
 }
 
-// LDS tile cache of level-0 signature words.  A tile of kBlock*kPPT candidates
-// references at most 2*kBlock*kPPT distinct objects, half the table size, so
-// linear probing always finds the id or an empty slot.
-constexpr int kCacheBits = 12;
-constexpr int kCacheSlots = 1 << kCacheBits;
-constexpr uint32_t kEmptyTag = 0xFFFFFFFFu;   // never a valid id (n_obj <= 2^32 - 1)
-static_assert(kCacheSlots >= 2 * 256 * 4, "cache must hold twice the ids of a tile");
+constexpr int kExactLds = 512;   // entries of the longer sparse row staged in LDS per wave
 
-__device__ inline int cache_insert(uint32_t *tag, uint32_t id) {
-  uint32_t h = (id * 2654435761u) >> (32 - kCacheBits);
-  for (int probe = 0; probe < kCacheSlots; ++probe) {
-    const uint32_t t = tag[h];
-    if (t == id) return int(h);
-    if (t == kEmptyTag) {
-      const uint32_t old = atomicCAS(&tag[h], kEmptyTag, id);
-      if (old == kEmptyTag || old == id) return int(h);
+// Exact similarity of one pair computed by the whole wave (Algorithm 2's
+// final step): cosine of dense rows or of sparse rows with sorted indices
+// (FP64 sums), or Jaccard of sorted sets (integer counts, one FP64 division).
+// Sparse: the longer row is staged in this wave's LDS rows when it fits and
+// every entry of the shorter row is binary-searched in it.
+__device__ double exact_wave(const VerifyArgs &a, uint32_t xi, uint32_t yi, uint32_t *s_idx, float *s_val) {
+  const int lane = lane_id();
+  if (a.ex_kind == BLSH_DENSE) {
+    const float *u = a.ex_dense + size_t(xi) * a.ex_dim, *v = a.ex_dense + size_t(yi) * a.ex_dim;
+    double nx = 0, ny = 0, dot = 0;
+    for (int64_t d = lane; d < a.ex_dim; d += kWave) {
+      const double p = u[d], q = v[d];
+      nx += p * p; ny += q * q; dot += p * q;
     }
-    h = (h + 1) & (kCacheSlots - 1);
+    nx = wave_sum_f64(nx); ny = wave_sum_f64(ny); dot = wave_sum_f64(dot);
+    return (nx > 0 && ny > 0) ? dot / (sqrt(nx) * sqrt(ny)) : 0.0;
   }
-  return -1;
+  const int64_t ax = a.ex_offsets[xi], nxl = a.ex_offsets[xi + 1] - ax;
+  const int64_t ay = a.ex_offsets[yi], nyl = a.ex_offsets[yi + 1] - ay;
+  const bool x_long = nxl >= nyl;
+  const int64_t al = x_long ? ax : ay, nl = x_long ? nxl : nyl;
+  const int64_t as = x_long ? ay : ax, ns = x_long ? nyl : nxl;
+  const bool csr = a.ex_kind == BLSH_CSR;
+  const bool staged = nl <= kExactLds;
+  double n_long = 0.0, n_short = 0.0, dot = 0.0;
+  uint32_t inter = 0;
+  if (staged) {
+    for (int64_t i = lane; i < nl; i += kWave) {
+      s_idx[i] = a.ex_indices[al + i];
+      if (csr) {
+        const float v = a.ex_values[al + i];
+        s_val[i] = v;
+        n_long += double(v) * double(v);
+      }
+    }
+    wave_lds_sync();
+  } else if (csr) {
+    for (int64_t i = lane; i < nl; i += kWave) { const double v = a.ex_values[al + i]; n_long += v * v; }
+  }
+  for (int64_t i = lane; i < ns; i += kWave) {
+    const uint32_t key = a.ex_indices[as + i];
+    int64_t lo = 0, hi = nl;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      const uint32_t v = staged ? s_idx[mid] : a.ex_indices[al + mid];
+      if (v < key) lo = mid + 1; else hi = mid;
+    }
+    const bool hit = lo < nl && (staged ? s_idx[lo] : a.ex_indices[al + lo]) == key;
+    if (csr) {
+      const double vs = a.ex_values[as + i];
+      n_short += vs * vs;
+      if (hit) dot += vs * double(staged ? s_val[lo] : a.ex_values[al + lo]);
+    } else {
+      inter += hit;
+    }
+  }
+  wave_lds_sync();   // the wave may stage another row next
+  if (csr) {
+    n_long = wave_sum_f64(n_long); n_short = wave_sum_f64(n_short); dot = wave_sum_f64(dot);
+    const double nx = x_long ? n_long : n_short, ny = x_long ? n_short : n_long;
+    return (nx > 0 && ny > 0) ? dot / (sqrt(nx) * sqrt(ny)) : 0.0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) inter += __shfl_xor(inter, o);
+  const int64_t uni = nxl + nyl - int64_t(inter);
+  return uni > 0 ? double(inter) / double(uni) : 0.0;
 }
 
-// One lane per candidate, kPPT consecutive candidates per lane.  With LDSC the
-// block first gathers the level-0 word(s) of every distinct object of its tile
-// into an LDS hash table (one global gather per distinct object instead of two
-// per candidate), then compares level 0 from LDS; deeper levels gather from
-// global memory.
-template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool LDSC>
+// Emission of one Lite survivor's exact similarity (called by lane 0).
+__device__ inline void emit_exact(const VerifyArgs &a, int64_t c, double s) {
+  if (s > a.t) {
+    const unsigned long long pos = atomicAdd((unsigned long long *)a.n_acc, 1ull);
+    if (int64_t(pos) < a.acc_cap) {
+      a.acc_idx[pos] = uint64_t(c);
+      a.acc_val[pos] = float(s);
+    } else {
+      raise_status(a.status, BLSH_ETRUNCATED);
+    }
+  }
+}
+
+// One lane per candidate, kPPT consecutive candidates per lane.
+//   PFX: object-major rows whose first 16 bytes (128 hashes) are loaded with one
+//        gather per side, so the first 128/K levels need no further round trip.
+//   LITE: survivors of the h-hash budget get their exact similarity right here,
+//        one survivor at a time by the whole wave (Algorithm 2).
+template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool PFX>
 __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
-  constexpr int LW = K == 64 ? 2 : 1;                       // words per level-0 chunk
+  constexpr int PL = PFX ? 128 / K : 0;   // levels served by the prefix
   __shared__ int s_min[kMaxLevels];
-  __shared__ uint32_t s_tag[LDSC ? kCacheSlots : 1];
-  __shared__ uint32_t s_dat[LW][LDSC ? kCacheSlots : 1];
+  __shared__ uint32_t s_eidx[LITE ? kBlock / kWave : 1][LITE ? kExactLds : 1];
+  __shared__ float s_eval[LITE ? kBlock / kWave : 1][LITE ? kExactLds : 1];
   if (threadIdx.x < kMaxLevels)
     s_min[threadIdx.x] = threadIdx.x < a.n_levels ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
-  if constexpr (LDSC) {
-    for (int i = threadIdx.x; i < kCacheSlots; i += kBlock) s_tag[i] = kEmptyTag;
-  }
   __syncthreads();
   const int L = a.n_levels;
   const int words = int(a.table[2]);
@@ -152,49 +210,26 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
     }
   };
   int j0 = 0;
-  if constexpr (LDSC) {
-    // 1. insert every distinct id of the tile (consecutive equal ids are inserted once)
-    int sx[kPPT], sy[kPPT];
-    uint32_t prev = kEmptyTag;
-    int prev_slot = -1;
+  if constexpr (PFX) {
+    uint32_t wx[kPPT][4], wy[kPPT][4];
 #pragma unroll
     for (int p = 0; p < kPPT; ++p) {
-      sx[p] = sy[p] = -1;
       if (alive & (1u << p)) {
-        sx[p] = xi[p] == prev ? prev_slot : cache_insert(s_tag, xi[p]);
-        prev = xi[p];
-        prev_slot = sx[p];
-        sy[p] = cache_insert(s_tag, yi[p]);
+        const u32x4 hx = *reinterpret_cast<const u32x4 *>(a.sig + size_t(xi[p]) * a.row_words);
+        const u32x4 hy = *reinterpret_cast<const u32x4 *>(a.sig + size_t(yi[p]) * a.row_words);
+        wx[p][0] = hx.x; wx[p][1] = hx.y; wx[p][2] = hx.z; wx[p][3] = hx.w;
+        wy[p][0] = hy.x; wy[p][1] = hy.y; wy[p][2] = hy.z; wy[p][3] = hy.w;
       }
     }
-    __syncthreads();
-    // 2. one gather per occupied slot
-    for (int i = threadIdx.x; i < kCacheSlots; i += kBlock) {
-      const uint32_t t = s_tag[i];
-      if (t != kEmptyTag) {
-#pragma unroll
-        for (int w = 0; w < LW; ++w)
-          s_dat[w][i] = WORD_MAJOR ? a.sig[size_t(w) * a.n_obj + t] : a.sig[size_t(t) * a.row_words + w];
-      }
-    }
-    __syncthreads();
-    // 3. level 0 (and level 1 for k = 16, which shares the word) from LDS
-    const int lds_levels = K == 16 ? 2 : 1;
-    for (int j = 0; j < lds_levels && j < L; ++j) {
+    for (int j = 0; j < PL && j < L && alive; ++j) {
 #pragma unroll
       for (int p = 0; p < kPPT; ++p) {
         if (!(alive & (1u << p))) continue;
-        if (sx[p] >= 0 && sy[p] >= 0) {
-          const uint32_t x0 = s_dat[0][sx[p]], y0 = s_dat[0][sy[p]];
-          const uint32_t x1 = LW == 2 ? s_dat[LW - 1][sx[p]] : 0u, y1 = LW == 2 ? s_dat[LW - 1][sy[p]] : 0u;
-          m[p] += agree_words<K>(x0, x1, y0, y1, j);
-        } else {
-          m[p] += level_agree_bits<K, WORD_MAJOR>(a, xi[p], yi[p], j);
-        }
+        m[p] += agree_from<K>(wx[p], wy[p], j);
         decide(p, j);
       }
     }
-    j0 = lds_levels;
+    j0 = PL;
   }
   for (int j = j0; j < L && alive; ++j) {
 #pragma unroll
@@ -227,13 +262,28 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
   }
   // emission in converged control flow
   if (__ballot(emit != 0) == 0) return;
-  const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
+  if constexpr (LITE) {
+    const int w = threadIdx.x / kWave;
+    const uint32_t c_lo = uint32_t(c0), c_hi = uint32_t(uint64_t(c0) >> 32);
 #pragma unroll
-  for (int p = 0; p < kPPT; ++p) {
-    const bool e = (emit >> p) & 1u;
-    if (LITE) {
-      push_survivor(a, e, c0 + p);
-    } else {
+    for (int p = 0; p < kPPT; ++p) {
+      uint64_t mask = __ballot((emit >> p) & 1u);
+      while (mask) {
+        const int l = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const uint32_t sx = __builtin_amdgcn_readlane(xi[p], l);
+        const uint32_t sy = __builtin_amdgcn_readlane(yi[p], l);
+        const int64_t c = int64_t(uint64_t(__builtin_amdgcn_readlane(c_lo, l)) |
+                                  (uint64_t(__builtin_amdgcn_readlane(c_hi, l)) << 32)) + p;
+        const double sim = exact_wave(a, sx, sy, s_eidx[w], s_eval[w]);
+        if (lane_id() == 0) emit_exact(a, c, sim);
+      }
+    }
+  } else {
+    const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p) {
+      const bool e = (emit >> p) & 1u;
       const int n = ((code[p] & 63) + 1) * K;
       const float v = e ? map_estimate(a.measure, int(m[p]), n, alpha, beta) : 0.f;
       emit_accepted(a, e, uint64_t(c0 + p), v);
@@ -325,109 +375,21 @@ __global__ __launch_bounds__(kBlock) void k_verify_minhash(VerifyArgs a) {
 // Exact similarity on Lite survivors: one wave per queued pair
 // ---------------------------------------------------------------------------
 
-__device__ inline double wave_sum_f64(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
 
-// position of key in sorted idx[0..n), or -1
-__device__ inline int64_t bsearch_u32(const uint32_t *idx, int64_t n, uint32_t key) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    const uint32_t v = idx[mid];
-    if (v < key) lo = mid + 1; else hi = mid;
-  }
-  return (lo < n && idx[lo] == key) ? lo : -1;
-}
 
-// One wave per queued pair.  Sparse rows: the longer row is staged in LDS
-// (when it has at most kExactLds entries) and every entry of the shorter row
-// is binary-searched in it; all sums are FP64.
-constexpr int kExactLds = 512;
-
-__global__ __launch_bounds__(kBlock) void k_exact(ExactArgs e, VerifyArgs a) {
+// One wave per queued pair (Lite survivors of the minhash and exhaustive paths).
+__global__ __launch_bounds__(kBlock) void k_exact(VerifyArgs a) {
   __shared__ uint32_t s_idx[kBlock / kWave][kExactLds];
   __shared__ float s_val[kBlock / kWave][kExactLds];
-  const int lane = lane_id(), w = threadIdx.x >> 6;
-  const int64_t n = *e.q_n;
+  const int w = threadIdx.x >> 6;
+  const int64_t n = *a.q_n;
   const int64_t waves = int64_t(gridDim.x) * (kBlock / kWave);
   for (int64_t q = int64_t(blockIdx.x) * (kBlock / kWave) + w; q < n; q += waves) {
-    const int64_t c = a.c_begin + e.q_rel[q];
+    const int64_t c = a.c_begin + a.q_rel[q];
     uint32_t xi, yi;
     fetch_candidate(a, c, xi, yi);   // ids were range-checked before the pair was queued
-    double s = 0.0;
-    if (e.vec_kind == BLSH_DENSE) {
-      const float *u = e.dense + size_t(xi) * e.dim, *v = e.dense + size_t(yi) * e.dim;
-      double nx = 0, ny = 0, dot = 0;
-      for (int64_t d = lane; d < e.dim; d += kWave) {
-        const double p = u[d], qv = v[d];
-        nx += p * p; ny += qv * qv; dot += p * qv;
-      }
-      nx = wave_sum_f64(nx); ny = wave_sum_f64(ny); dot = wave_sum_f64(dot);
-      s = (nx > 0 && ny > 0) ? dot / (sqrt(nx) * sqrt(ny)) : 0.0;
-    } else {
-      const int64_t ax = e.offsets[xi], nxl = e.offsets[xi + 1] - ax;
-      const int64_t ay = e.offsets[yi], nyl = e.offsets[yi + 1] - ay;
-      const bool x_long = nxl >= nyl;
-      const int64_t al = x_long ? ax : ay, nl = x_long ? nxl : nyl;
-      const int64_t as = x_long ? ay : ax, ns = x_long ? nyl : nxl;
-      const bool csr = e.vec_kind == BLSH_CSR;
-      const bool staged = nl <= kExactLds;
-      double n_long = 0.0, n_short = 0.0, dot = 0.0;
-      uint32_t inter = 0;
-      if (staged) {
-        for (int64_t i = lane; i < nl; i += kWave) {
-          s_idx[w][i] = e.indices[al + i];
-          if (csr) {
-            const float v = e.values[al + i];
-            s_val[w][i] = v;
-            n_long += double(v) * double(v);
-          }
-        }
-        wave_lds_sync();
-      } else if (csr) {
-        for (int64_t i = lane; i < nl; i += kWave) { const double v = e.values[al + i]; n_long += v * v; }
-      }
-      for (int64_t i = lane; i < ns; i += kWave) {
-        const uint32_t key = e.indices[as + i];
-        int64_t lo = 0, hi = nl;
-        while (lo < hi) {
-          const int64_t mid = (lo + hi) >> 1;
-          const uint32_t v = staged ? s_idx[w][mid] : e.indices[al + mid];
-          if (v < key) lo = mid + 1; else hi = mid;
-        }
-        const bool hit = lo < nl && (staged ? s_idx[w][lo] : e.indices[al + lo]) == key;
-        if (csr) {
-          const double vs = e.values[as + i];
-          n_short += vs * vs;
-          if (hit) dot += vs * double(staged ? s_val[w][lo] : e.values[al + lo]);
-        } else {
-          inter += hit;
-        }
-      }
-      if (csr) {
-        n_long = wave_sum_f64(n_long); n_short = wave_sum_f64(n_short); dot = wave_sum_f64(dot);
-        s = (n_long > 0 && n_short > 0) ? dot / (sqrt(x_long ? n_long : n_short) * sqrt(x_long ? n_short : n_long))
-                                        : 0.0;
-      } else {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) inter += __shfl_xor(inter, o);
-        const int64_t uni = nxl + nyl - int64_t(inter);
-        s = uni > 0 ? double(inter) / double(uni) : 0.0;
-      }
-      wave_lds_sync();   // the next pair may overwrite this wave's LDS rows
-    }
-    if (lane == 0 && s > e.t) {
-      const unsigned long long pos = atomicAdd((unsigned long long *)a.n_acc, 1ull);
-      if (int64_t(pos) < a.acc_cap) {
-        a.acc_idx[pos] = uint64_t(c);
-        a.acc_val[pos] = float(s);
-      } else {
-        raise_status(a.status, BLSH_ETRUNCATED);
-      }
-    }
+    const double sim = exact_wave(a, xi, yi, s_idx[w], s_val[w]);
+    if (lane_id() == 0) emit_exact(a, c, sim);
   }
 }
 
@@ -625,19 +587,20 @@ __global__ void k_zero_i64(int64_t *p, int64_t *q) {
 // ---------------------------------------------------------------------------
 static inline int64_t blocks_for(int64_t items, int64_t per_block) { return (items + per_block - 1) / per_block; }
 
-template <int K, bool LITE, bool WM, bool LC>
+template <int K, bool LITE, bool WM, bool PFX>
 static int launch_bits_kind(const VerifyArgs &a, int64_t nb, hipStream_t s) {
   switch (a.kind) {
-    case BLSH_PAIRS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_PAIRS, LITE, WM, LC>), dim3(nb), dim3(kBlock), 0, s, a); break;
-    case BLSH_QUERY_LISTS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_QUERY_LISTS, LITE, WM, LC>), dim3(nb), dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_verify_bits<K, BLSH_ALL_PAIRS, LITE, WM, LC>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    case BLSH_PAIRS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_PAIRS, LITE, WM, PFX>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    case BLSH_QUERY_LISTS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_QUERY_LISTS, LITE, WM, PFX>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_verify_bits<K, BLSH_ALL_PAIRS, LITE, WM, PFX>), dim3(nb), dim3(kBlock), 0, s, a); break;
   }
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
-template <int K, bool LITE, bool WM>
-static int launch_bits_gather(const VerifyArgs &a, int64_t nb, bool lds_cache, hipStream_t s) {
-  return lds_cache ? launch_bits_kind<K, LITE, WM, true>(a, nb, s) : launch_bits_kind<K, LITE, WM, false>(a, nb, s);
+template <int K, bool LITE>
+static int launch_bits_layout(const VerifyArgs &a, int64_t nb, bool wm, bool pfx, hipStream_t s) {
+  if (wm) return launch_bits_kind<K, LITE, true, false>(a, nb, s);
+  return pfx ? launch_bits_kind<K, LITE, false, true>(a, nb, s) : launch_bits_kind<K, LITE, false, false>(a, nb, s);
 }
 
 template <int K, bool LITE>
@@ -650,20 +613,16 @@ static int launch_minhash_kind(const VerifyArgs &a, int64_t nb, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
-int launch_verify_bits_cached(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool wm, hipStream_t s);
-
 int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool word_major, hipStream_t s) {
   const int64_t n = a.c_end - a.c_begin;
   if (n <= 0) return BLSH_OK;
-  if (a.measure == BLSH_COSINE && ctx->tuning.gather == 3) return launch_verify_bits_cached(ctx, a, k, lite, word_major, s);
   if (a.measure == BLSH_COSINE) {
     const int64_t nb = blocks_for(n, int64_t(kBlock) * kPPT);
-    const bool lc = ctx->tuning.gather == 2;
-    LaunchScope ls(ctx, s, lc ? "verify_bits_ldscache" : "verify_bits");
-#define BLSH_B(KK, LL, WW) if (k == KK && lite == LL && word_major == WW) return launch_bits_gather<KK, LL, WW>(a, nb, lc, s);
-    BLSH_B(16, false, true) BLSH_B(16, true, true) BLSH_B(16, false, false) BLSH_B(16, true, false)
-    BLSH_B(32, false, true) BLSH_B(32, true, true) BLSH_B(32, false, false) BLSH_B(32, true, false)
-    BLSH_B(64, false, true) BLSH_B(64, true, true) BLSH_B(64, false, false) BLSH_B(64, true, false)
+    // object-major rows of >= 128 hashes, 16-byte aligned: one 16-byte gather per side
+    const bool pfx = !word_major && a.row_words % 4 == 0 && (uintptr_t(a.sig) & 15) == 0;
+    LaunchScope ls(ctx, s, pfx ? "verify_bits_prefix" : "verify_bits");
+#define BLSH_B(KK, LL) if (k == KK && lite == LL) return launch_bits_layout<KK, LL>(a, nb, word_major, pfx, s);
+    BLSH_B(16, false) BLSH_B(16, true) BLSH_B(32, false) BLSH_B(32, true) BLSH_B(64, false) BLSH_B(64, true)
 #undef BLSH_B
   } else {
     const int64_t nb = blocks_for(n, kBlock);
@@ -697,11 +656,11 @@ int launch_exhaustive(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s) 
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
-int launch_exact(blsh_ctx *ctx, const ExactArgs &e, const VerifyArgs &a, int64_t max_items, hipStream_t s) {
+int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStream_t s) {
   if (max_items <= 0) return BLSH_OK;
   const int64_t nb = std::min<int64_t>(blocks_for(max_items, kBlock / kWave), int64_t(ctx->n_cu) * 16);
   LaunchScope ls(ctx, s, "exact");
-  hipLaunchKernelGGL(k_exact, dim3(nb), dim3(kBlock), 0, s, e, a);
+  hipLaunchKernelGGL(k_exact, dim3(nb), dim3(kBlock), 0, s, a);
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 

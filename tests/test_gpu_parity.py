@@ -135,16 +135,14 @@ def test_verify_pairs_bit_exact(ctx, measure, k):
 
 @pytest.mark.parametrize("k", [16, 32, 64])
 @pytest.mark.parametrize("lite", [False, True])
-def test_lds_tile_cache_matches(ctx, k, lite):
-    """The LDS tile cache (gather 2) and the persistent LDS cache (gather 3) give
-    the same output as direct gathers and the oracle, on bucket-major
-    candidates (many repeated ids per tile) and on random pairs (up to 2
-    distinct ids per candidate, the caches' worst case)."""
-    _flush("lds tile cache k=%d lite=%d" % (k, lite))
+def test_layouts_and_candidate_orders(ctx, k, lite):
+    """Word-major slabs, object-major rows (16-byte prefix gathers) and
+    object-major rows at an unaligned offset (word gathers) give the oracle's
+    output on bucket-major candidates and on random pairs."""
+    _flush("layouts k=%d lite=%d" % (k, lite))
     n_obj, n_hashes = 6000, 1024
     sig = _calib_pairs(P.COSINE, n_obj // 2, n_hashes, 40 + k)
     rng = np.random.default_rng(k)
-    # bucket-major: all pairs inside buckets of 20..80 members
     xs, ys = [], []
     for _ in range(40):
         mem = np.sort(rng.choice(n_obj, rng.integers(20, 80), replace=False))
@@ -153,28 +151,29 @@ def test_lds_tile_cache_matches(ctx, k, lite):
     xb, yb = np.concatenate(xs).astype(np.uint32), np.concatenate(ys).astype(np.uint32)
     xr = rng.integers(0, n_obj, 30011).astype(np.uint32)
     yr = rng.integers(0, n_obj, 30011).astype(np.uint32)
-    S = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR)
     L = 4 if lite else n_hashes // k
-    for x, y in ((xb, yb), (xr, yr), (np.concatenate([xr, xb]), np.concatenate([yr, yb]))):
+    dense = np.ones((n_obj, 8), np.float32)
+    dense[:, 0] = np.arange(n_obj)          # distinct rows: exact cosines < 1
+    dvec = P.dense_vectors(up(dense))
+    om = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
+    # object-major rows starting 4 bytes into the buffer: not 16-byte aligned
+    buf = torch.zeros(om.data.numel() + 1, dtype=torch.int32, device="cuda")
+    buf[1:] = om.data.view(torch.int32)
+    om_unaligned = P.Signatures(buf[1:].view(torch.uint32), P.COSINE, P.OBJECT_MAJOR, n_obj, n_hashes)
+    layouts = [sigs_tensor(sig, P.COSINE, P.WORD_MAJOR), om, om_unaligned]
+    for x, y in ((xb, yb), (xr, yr)):
         want = R.verify(x, y, P.COSINE, sig, k, L, T, EPS, DELTA, GAMMA, lite=lite)
-        outs = []
-        for g in (1, 2, 3):
-            P.bayeslsh_set_tuning(ctx, gather=g)
+        if lite:
+            want = R.lite_finish(want, lambda p_, q_: R.exact_cosine_dense(dense, p_, q_), x, y, T)
+        for S in layouts:
             res = P.make_result(len(x), len(x), m_debug=True)
             if lite:
-                dense = P.dense_vectors(torch.ones(n_obj, 8, device="cuda"))
-                P.bayeslsh_lite_verify(ctx, P.pairs(up(x), up(y)), S, dense, T, EPS, (1, 1), L * k, k, res)
+                P.bayeslsh_lite_verify(ctx, P.pairs(up(x), up(y)), S, dvec, T, EPS, (1, 1), L * k, k, res)
             else:
                 P.bayeslsh_verify(ctx, P.pairs(up(x), up(y)), S, T, EPS, DELTA, GAMMA, (1, 1), k, res)
             P.bayeslsh_sync(ctx)
             got = decode_result(res, len(x))
-            np.testing.assert_array_equal(got["decision"], want["decision"])
-            np.testing.assert_array_equal(got["level"], want["level"])
-            np.testing.assert_array_equal(got["m"], want["m"])
-            outs.append(got)
-        np.testing.assert_array_equal(outs[0]["acc_idx"], outs[1]["acc_idx"])
-        np.testing.assert_array_equal(outs[0]["acc_idx"], outs[2]["acc_idx"])
-    P.bayeslsh_set_tuning(ctx, gather=0)
+            assert_same_as_oracle(got, want, lite_exact=want["exact"] if lite else None)
 
 
 def test_verify_jaccard_workload_all_pairs(ctx):
