@@ -158,7 +158,7 @@ def test_layouts_and_candidate_orders(ctx, k, lite):
     om = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
     # object-major rows starting 4 bytes into the buffer: not 16-byte aligned
     buf = torch.zeros(om.data.numel() + 1, dtype=torch.int32, device="cuda")
-    buf[1:] = om.data.view(torch.int32)
+    buf[1:] = om.data.reshape(-1).view(torch.int32)
     om_unaligned = P.Signatures(buf[1:].view(torch.uint32), P.COSINE, P.OBJECT_MAJOR, n_obj, n_hashes)
     layouts = [sigs_tensor(sig, P.COSINE, P.WORD_MAJOR), om, om_unaligned]
     for x, y in ((xb, yb), (xr, yr)):
