@@ -58,12 +58,12 @@ __device__ inline uint32_t level_agree_bits(const VerifyArgs &a, uint32_t xi, ui
 constexpr int kPPT = 4;        // candidates per lane (bits kernel)
 constexpr int kBlock = 256;
 
-// agreement of level j from words already in registers (16-byte prefix)
+// agreement of level j from the XOR of the two 16-byte prefixes (in registers)
 template <int K>
-__device__ inline uint32_t agree_from(const uint32_t *wx, const uint32_t *wy, int j) {
-  if constexpr (K == 32) return 32u - __popc(wx[j] ^ wy[j]);
-  else if constexpr (K == 64) return 64u - __popc(wx[2 * j] ^ wy[2 * j]) - __popc(wx[2 * j + 1] ^ wy[2 * j + 1]);
-  else return 16u - __popc(((wx[j >> 1] ^ wy[j >> 1]) >> ((j & 1) * 16)) & 0xFFFFu);
+__device__ inline uint32_t agree_from_xor(const uint32_t *d, int j) {
+  if constexpr (K == 32) return 32u - __popc(d[j]);
+  else if constexpr (K == 64) return 64u - __popc(d[2 * j]) - __popc(d[2 * j + 1]);
+  else return 16u - __popc((d[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu);
 }
 
 constexpr int kExactLds = 512;   // entries of the longer sparse row staged in LDS per wave
@@ -155,7 +155,7 @@ __device__ inline void emit_exact(const VerifyArgs &a, int64_t c, double s) {
 //   LITE: survivors of the h-hash budget get their exact similarity right here,
 //        one survivor at a time by the whole wave (Algorithm 2).
 template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool PFX>
-__global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
+__global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
   constexpr int PL = PFX ? 128 / K : 0;   // levels served by the prefix
   __shared__ int s_min[kMaxLevels];
   __shared__ uint32_t s_eidx[LITE ? kBlock / kWave : 1][LITE ? kExactLds : 1];
@@ -211,21 +211,20 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
   };
   int j0 = 0;
   if constexpr (PFX) {
-    uint32_t wx[kPPT][4], wy[kPPT][4];
+    uint32_t d[kPPT][4];
 #pragma unroll
     for (int p = 0; p < kPPT; ++p) {
       if (alive & (1u << p)) {
         const u32x4 hx = *reinterpret_cast<const u32x4 *>(a.sig + size_t(xi[p]) * a.row_words);
         const u32x4 hy = *reinterpret_cast<const u32x4 *>(a.sig + size_t(yi[p]) * a.row_words);
-        wx[p][0] = hx.x; wx[p][1] = hx.y; wx[p][2] = hx.z; wx[p][3] = hx.w;
-        wy[p][0] = hy.x; wy[p][1] = hy.y; wy[p][2] = hy.z; wy[p][3] = hy.w;
+        d[p][0] = hx.x ^ hy.x; d[p][1] = hx.y ^ hy.y; d[p][2] = hx.z ^ hy.z; d[p][3] = hx.w ^ hy.w;
       }
     }
     for (int j = 0; j < PL && j < L && alive; ++j) {
 #pragma unroll
       for (int p = 0; p < kPPT; ++p) {
         if (!(alive & (1u << p))) continue;
-        m[p] += agree_from<K>(wx[p], wy[p], j);
+        m[p] += agree_from_xor<K>(d[p], j);
         decide(p, j);
       }
     }
