@@ -155,7 +155,7 @@ __device__ inline void emit_exact(const VerifyArgs &a, int64_t c, double s) {
 //   LITE: survivors of the h-hash budget get their exact similarity right here,
 //        one survivor at a time by the whole wave (Algorithm 2).
 template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool PFX>
-__global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
+__global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
   constexpr int PL = PFX ? 128 / K : 0;   // levels served by the prefix
   __shared__ int s_min[kMaxLevels];
   __shared__ uint32_t s_eidx[LITE ? kBlock / kWave : 1][LITE ? kExactLds : 1];
