@@ -211,14 +211,20 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
   };
   int j0 = 0;
   if constexpr (PFX) {
+    // all eight gathers are issued before any is consumed (object 0 stands in
+    // for candidates that are out of range or invalid; their result is unused)
+    u32x4 hx[kPPT], hy[kPPT];
+#pragma unroll
+    for (int p = 0; p < kPPT; ++p) {
+      const bool ok = (alive >> p) & 1u;
+      hx[p] = *reinterpret_cast<const u32x4 *>(a.sig + size_t(ok ? xi[p] : 0u) * a.row_words);
+      hy[p] = *reinterpret_cast<const u32x4 *>(a.sig + size_t(ok ? yi[p] : 0u) * a.row_words);
+    }
     uint32_t d[kPPT][4];
 #pragma unroll
     for (int p = 0; p < kPPT; ++p) {
-      if (alive & (1u << p)) {
-        const u32x4 hx = *reinterpret_cast<const u32x4 *>(a.sig + size_t(xi[p]) * a.row_words);
-        const u32x4 hy = *reinterpret_cast<const u32x4 *>(a.sig + size_t(yi[p]) * a.row_words);
-        d[p][0] = hx.x ^ hy.x; d[p][1] = hx.y ^ hy.y; d[p][2] = hx.z ^ hy.z; d[p][3] = hx.w ^ hy.w;
-      }
+      d[p][0] = hx[p].x ^ hy[p].x; d[p][1] = hx[p].y ^ hy[p].y;
+      d[p][2] = hx[p].z ^ hy[p].z; d[p][3] = hx[p].w ^ hy[p].w;
     }
     for (int j = 0; j < PL && j < L && alive; ++j) {
 #pragma unroll
