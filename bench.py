@@ -95,6 +95,26 @@ def cpu_baseline(corpus, x, y, gpu_codes):
                 sample="all %d candidates of the workload, median of 3 runs (%.2f s each)" % (len(x), dt)), parity, res
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "verify_bits_prefix_cosine_lite_100k_traffic.txt")
+KERNEL_SOURCES = ("paper_1110_1328_amd/csrc/verify.hip", "paper_1110_1328_amd/csrc/device_common.h")
+
+
+def measured_traffic():
+    """HBM bytes per verify launch from the committed FETCH_SIZE/WRITE_SIZE
+    counter runs (scaled by a plain copy's counters), or None when the kernel
+    sources have changed since those counters were taken."""
+    import hashlib
+    try:
+        kv = dict(l.split() for l in open(TRAFFIC_FILE) if l.strip())
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return int(kv["traffic_bytes_per_launch"]) if kv.get("kernel_source_sha256") == h.hexdigest() else None
+
+
 def copy_calibration(n_bytes=1 << 30, reps=20):
     """A plain device copy of known size (torch's copy kernel), for scaling rocprof
     FETCH_SIZE/WRITE_SIZE and as the achievable-bandwidth reference."""
@@ -263,7 +283,8 @@ def main():
         "signature_ms": sig_ms,
         "prefix_rows_equal_full_signature_prefix": same_prefix,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": k_name,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if args.layout == "prefix" else None, "kernel": k_name,
                      "kernel_ms": k_avg_ms, "kernel_launches_timed": k_n, "hbm_bytes_per_launch": hbm_bytes,
                      "l2_gather_bytes_per_launch": gather_bytes,
                      "gather_inclusive_GBps": (hbm_bytes + gather_bytes) / (k_avg_ms * 1e-3) / 1e9},
