@@ -135,6 +135,218 @@ def copy_calibration(n_bytes=1 << 30, reps=20):
                       "GBps_read_plus_write": 2 * n_bytes / ms / 1e6}), flush=True)
 
 
+def dense_index(torch, P, ctx, layouts):
+    """Dense cosine index: 1M x 256 unit vectors from a 1000-component Gaussian
+    mixture, 1024 SRP bits from the MFMA projection against Gaussian planes,
+    in each of the given layouts."""
+    from synth import generators as G
+    mix = G.dense_mixture(seed=G.SEED_BASE + 4)
+    planes = up(torch, G.gaussian_planes(256, 1024, G.SEED_BASE + 204))
+    xd = up(torch, mix.x)
+    sigs = []
+    for layout in layouts:
+        out = torch.empty(mix.x.shape[0] * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
+        P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), planes, 1024, 0, layout, out)
+        sigs.append(P.Signatures(out, P.COSINE, layout, mix.x.shape[0], 1024))
+    P.bayeslsh_sync(ctx)
+    del xd
+    return mix, sigs
+
+
+def groups_of(labels):
+    """related(q): the other objects with q's label (label < 0: none)."""
+    order = np.argsort(labels, kind="stable")
+    lab = labels[order]
+    starts = np.searchsorted(lab, labels, side="left")
+    ends = np.searchsorted(lab, labels, side="right")
+
+    def related(q):
+        if labels[q] < 0:
+            return np.zeros(0, np.int64)
+        m = order[starts[q]:ends[q]]
+        return m[m != q]
+    return related
+
+
+def run_batched(args, torch, P):
+    """4096 candidate lists (lengths 10^U(2,6)), measure ~ Bernoulli(1/2), t in
+    {0.5, 0.7, 0.9}; Jaccard lists against 1M minhash signatures (256 hashes),
+    cosine lists against the dense 1M x 1024-bit SRP index; one graph launch
+    with k, in-register levels and grid autotuned; the exhaustive batched
+    comparator at the chosen k must give the same output."""
+    from synth import generators as G
+    eps, delta, gamma = 0.03, 0.05, 0.03
+    ctx = P.bayeslsh_create(0)
+    log("jaccard index (1M sets, 256 minhashes)")
+    sets = G.jaccard_sets_large(seed=G.SEED_BASE + 5)
+    a, b = G.minhash_coeffs(256, G.SEED_BASE + 205)
+    sig_j = torch.empty(sets.n * 256, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_minhash_sigs(ctx, P.set_vectors(up(torch, sets.offsets), up(torch, sets.elems), sets.vocab),
+                            up(torch, a), up(torch, b), sig_j)
+    S_j = P.Signatures(sig_j, P.JACCARD, P.OBJECT_MAJOR, sets.n, 256)
+    log("cosine index (1M x 256 dense, 1024 SRP bits)")
+    # object-major rows: BayesLSH reads 128 hashes per gather, the comparator whole rows;
+    # the word-major layout (one slab per level) is timed beside it
+    mix, (S_c, S_c_wm) = dense_index(torch, P, ctx, (P.OBJECT_MAJOR, P.WORD_MAJOR))
+    n_lists = 4096
+    rng = np.random.default_rng(G.SEED_BASE + 3)
+    meas = rng.integers(0, 2, n_lists).astype(np.int32)
+    ts = rng.choice([0.5, 0.7, 0.9], n_lists)
+    log("lists")
+    qj, oj, cj = G.member_lists(int(np.sum(meas == 0)), sets.n, 2, 6, groups_of(sets.group), seed=G.SEED_BASE + 31)
+    qc, oc, cc = G.member_lists(int(np.sum(meas == 1)), mix.x.shape[0], 2, 6, groups_of(mix.comp),
+                                seed=G.SEED_BASE + 32)
+    cand = np.concatenate([cj, cc])
+    query = np.empty(n_lists, np.uint32)
+    offset = np.empty(n_lists, np.int64)
+    length = np.empty(n_lists, np.int64)
+    ij, ic = np.flatnonzero(meas == 0), np.flatnonzero(meas == 1)
+    query[ij], offset[ij], length[ij] = qj, oj[:-1], np.diff(oj)
+    query[ic], offset[ic], length[ic] = qc, oc[:-1] + len(cj), np.diff(oc)
+    lists = P.list_descs(meas, ts, query, offset, length)
+    n = len(cand)
+    log("%d lists, %d candidates (%d Jaccard, %d cosine)" % (n_lists, n, len(cj), len(cc)))
+    cand_d = up(torch, cand)
+    cap = 1 << 24
+    res = P.make_result(n, cap)
+    res_ex = P.make_result(n, cap)
+    stream = torch.cuda.current_stream()
+    k_used = P.bayeslsh_verify_batched(ctx, lists, cand_d, S_j, S_c, eps, delta, gamma, (1, 1), 0, res, stream)
+    P.bayeslsh_sync(ctx, stream)
+    tune = P.bayeslsh_get_tuning(ctx)
+    log("autotuned: k=%s inreg=%d blocks/CU=%d" % (k_used, tune["last_batch_inreg"], tune["last_batch_blocks_per_cu"]))
+
+    def timed(fn, steps):
+        for _ in range(2):
+            fn()
+        P.bayeslsh_sync(ctx, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        P.bayeslsh_sync(ctx, stream)
+        return el * 1e3 / steps
+
+    steps = max(3, args.steps // 5)
+    ms = timed(lambda: P.bayeslsh_verify_batched(ctx, lists, cand_d, S_j, S_c, eps, delta, gamma, (1, 1), k_used,
+                                                 res, stream), steps)
+    log("batched: %.3f ms" % ms)
+    # the same batch split by measure, at every k (where the time goes)
+    split = {}
+    r2 = P.make_result(n, cap)
+    for name, me in (("jaccard", 0), ("cosine", 1)):
+        sub = lists[meas == me]
+        split[name] = {}
+        for kk in (16, 32, 64):
+            split[name]["k%d" % kk] = timed(lambda: P.bayeslsh_verify_batched(
+                ctx, sub, cand_d, S_j if me == 0 else None, S_c if me == 1 else None, eps, delta, gamma, (1, 1),
+                kk, r2, stream), 3)
+            if me == 1:
+                split[name]["k%d_word_major" % kk] = timed(lambda: P.bayeslsh_verify_batched(
+                    ctx, sub, cand_d, None, S_c_wm, eps, delta, gamma, (1, 1), kk, r2, stream), 3)
+        split[name]["exhaustive_k%d" % k_used[me]] = timed(lambda: P.bayeslsh_exhaustive_batched(
+            ctx, sub, cand_d, S_j if me == 0 else None, S_c if me == 1 else None, eps, delta, gamma, (1, 1),
+            k_used, r2, stream), 2)
+        log("  %s: %s" % (name, ", ".join("%s %.2f ms" % kv for kv in split[name].items())))
+    del r2
+    ms_ex = timed(lambda: P.bayeslsh_exhaustive_batched(ctx, lists, cand_d, S_j, S_c, eps, delta, gamma, (1, 1),
+                                                        k_used, res_ex, stream), max(2, steps // 3))
+    log("exhaustive batched: %.3f ms" % ms_ex)
+    same = bool(torch.equal(res.code[:n], res_ex.code[:n]))
+    ia, va = res.accepted()
+    ib, vb = res_ex.accepted()
+    same = same and np.array_equal(ia, ib) and np.array_equal(va, vb)
+    codes = res.code[:n].cpu().numpy()
+    dec, lvl = codes >> 6, (codes & 63).astype(np.int64)
+    # algorithmic bytes: 4 B id + 1 B code per candidate, plus the candidate's
+    # signature chunk per level reached (the query's chunk is read once per tile)
+    per_level = np.where(np.repeat(meas, length) == 0, 4 * k_used[0], k_used[1] // 8)
+    alg = n * 5 + int(np.sum((lvl + 1) * per_level))
+    ctx.close()
+    return {
+        "metric": "candidate pairs verified/sec, batched BayesLSH vs exhaustive batched hash compare, same output",
+        "value": n / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": steps, "ms_per_step": ms,
+        "higher_is_better": True, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched: 4096 lists, lengths 10^U(2,6), measure ~ Bernoulli(1/2), t in {0.5,0.7,0.9}; "
+                               "Jaccard: 1M planted-group sets, 256 minhashes; cosine: 1M x 256 Gaussian-mixture "
+                               "vectors, 1024 SRP bits (object-major rows); eps=0.03, delta=0.05, gamma=0.03",
+                   "n_candidates": n, "n_jaccard": int(len(cj)), "n_cosine": int(len(cc)),
+                   "k_jaccard": k_used[0], "k_cosine": k_used[1], "inreg_levels": tune["last_batch_inreg"],
+                   "blocks_per_cu": tune["last_batch_blocks_per_cu"]},
+        "decisions": {"pruned": int(np.sum(dec == 0)), "accept_conc": int(np.sum(dec == 1)),
+                      "accept_nmax": int(np.sum(dec == 2)), "accepted_listed": int(len(ia))},
+        "exhaustive": {"ms_per_step": ms_ex, "value": n / (ms_ex * 1e-3), "speedup": ms_ex / ms,
+                       "same_output": same},
+        "algorithmic_bytes": alg, "algorithmic_GBps": alg / (ms * 1e-3) / 1e9,
+        "by_measure_ms": split,
+    }
+
+
+def run_serving(args, torch, P):
+    """Poisson arrivals of query objects against the dense cosine index
+    (candidate counts 10^U(3,6), t = 0.8): first all at once (saturated rate),
+    then at rho x that rate for rho in {0.5, 0.8, 0.95}; latency = arrival to
+    host-visible result."""
+    from synth import generators as G
+    ctx = P.bayeslsh_create(0)
+    log("cosine index (1M x 256 dense, 1024 SRP bits)")
+    mix, (S,) = dense_index(torch, P, ctx, (P.WORD_MAJOR,))
+    nq = args.queries
+    log("%d queries" % nq)
+    rng = np.random.default_rng(G.SEED_BASE + 6)
+    queries = rng.integers(0, mix.x.shape[0], nq).astype(np.uint32)
+    q, off, cand = G.member_lists(nq, mix.x.shape[0], 3, 6, groups_of(mix.comp), seed=G.SEED_BASE + 61,
+                                  queries=queries)
+    lens = np.diff(off)
+    total = int(off[-1])
+    log("%d candidates" % total)
+    srv = P.Server(ctx, S, mem_budget_bytes=2 << 30, max_active=64, k=32, max_batch_candidates=1 << 24)
+
+    def run(gaps):
+        ids = []
+        t0 = time.perf_counter()
+        for i in range(nq):
+            if gaps is not None:
+                due = t0 + gaps[i]
+                while time.perf_counter() < due:
+                    pass
+            ids.append(srv.submit(int(q[i]), cand[off[i]:off[i + 1]], 0.8))
+        out = [srv.wait(r) for r in ids]
+        el = time.perf_counter() - t0
+        for r in ids:
+            srv.release(r)
+        lat = np.array([o["done"] - o["submit"] for o in out])
+        return el, lat, out
+
+    run(None)                                            # warm (graphs, tables)
+    el, lat, out0 = run(None)
+    sat_qps = nq / el
+    res = {"saturated": {"queries_per_s": sat_qps, "pairs_per_s": total / el,
+                         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}}
+    log("saturated: %.0f q/s, %.3g pairs/s" % (sat_qps, total / el))
+    for rho in (0.5, 0.8, 0.95):
+        gaps = np.cumsum(np.random.default_rng(int(rho * 100)).exponential(1.0 / (rho * sat_qps), nq))
+        el, lat, out = run(gaps)
+        same = all(np.array_equal(a["acc_idx"], b["acc_idx"]) and np.array_equal(a["acc_val"], b["acc_val"])
+                   for a, b in zip(out0, out))
+        res["rho_%.2f" % rho] = {"queries_per_s": nq / el, "pairs_per_s": total / el,
+                                 "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "same_results": same}
+        log("rho %.2f: p50 %.2f ms p99 %.2f ms" % (rho, res["rho_%.2f" % rho]["p50_ms"], res["rho_%.2f" % rho]["p99_ms"]))
+    st = srv.stats()
+    srv.close()
+    ctx.close()
+    return {"metric": "serving: candidate pairs verified/sec and query latency", "unit": "pairs/s",
+            "value": res["saturated"]["pairs_per_s"], "n_gpus": 1, "data": "synthetic", "dtype": "u32",
+            "config": {"workload": "serving: %d queries against 1M x 1024-bit dense cosine index, candidates "
+                                   "10^U(3,6) per query (1%% from the query's mixture component), t=0.8, k=32, "
+                                   "max_active=64, 2 GiB arena" % nq, "n_candidates": total,
+                       "mean_candidates": float(lens.mean())},
+            "latency": res, "server_stats": st}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +357,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="time a plain 1 GiB device copy and exit")
     ap.add_argument("--layout", choices=["prefix", "word-major"], default="prefix",
                     help="SRP layout verified: object-major 128-bit rows (prefix) or word-major slabs of all bits")
+    ap.add_argument("--workload", choices=["lite", "batched", "serving"], default="lite",
+                    help="lite: the cosine BayesLSH-Lite line (default); batched: 4096 mixed query lists in one "
+                         "graph launch vs the exhaustive batched comparator; serving: Poisson arrivals against the "
+                         "dense cosine index, p50/p99 latency")
+    ap.add_argument("--queries", type=int, default=10000, help="serving: number of queries")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -156,6 +373,12 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args, torch, P)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(run_serving(args, torch, P)), flush=True)
         return
     log("generating workload")
     corpus, x, y = build_workload(args.small)

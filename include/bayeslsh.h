@@ -169,7 +169,7 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
 /* Launch tuning of a context (callers that want a fixed configuration, and
  * the autotuner).  Zero fields mean "library default".  The output is the same
  * whatever the tuning, except through k (which bayeslsh_verify_batched may
- * choose when called with k = 0).
+ * choose when called with a k of 0).
  *   gather: 1 = each lane gathers both signatures of its candidates directly
  *           (the only SRP gather scheme; reserved for alternatives).
  *           SRP signatures in OBJECT_MAJOR layout with rows of a multiple of
@@ -178,21 +178,22 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
  *           layout when most pairs end within the first 128 hashes.
  *   batch_inreg: batched calls run this many levels in registers before the
  *           undecided candidates are compacted into a survivor queue.
- *   batch_blocks_per_cu: persistent blocks per CU of the batched tile kernel.
+ *   batch_blocks_per_cu: blocks per CU of the batched tile kernel (4 waves
+ *           each; every wave runs a contiguous range of tiles).
  *   batch_spill_cap: capacity of each survivor queue; a survivor that finds
  *           the queue full keeps running in registers (same result).
  *   last_batch_*: set by the library after each batched call (the autotuned
- *           or given k, in-register levels and blocks per CU); ignored by
- *           bayeslsh_set_tuning. */
+ *           or given k of each measure, in-register levels and blocks per
+ *           CU); ignored by bayeslsh_set_tuning. */
 typedef struct {
   int32_t gather;
   int32_t batch_inreg;
   int32_t batch_blocks_per_cu;
-  int32_t last_batch_k;
+  int32_t last_batch_k_jaccard;
   int32_t last_batch_inreg;
   int32_t last_batch_blocks_per_cu;
   int32_t batch_spill_cap;   /* batched: survivor-queue entries per measure (0 = min(n_cand, 2^24)) */
-  int32_t reserved;
+  int32_t last_batch_k_cosine;
 } blsh_tuning;
 int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *tuning_host);
 int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *tuning_host);
@@ -283,16 +284,19 @@ int bayeslsh_exhaustive_verify(blsh_ctx *ctx, const blsh_candidates *cand, const
  * verifies the candidates cand[offset .. offset+length) against its query
  * object, under its own measure and threshold t, with shared epsilon, delta,
  * gamma and Jaccard prior.  Lists use `jaccard_sigs` (minhash,
- * OBJECT_MAJOR) or `cosine_sigs` (SRP, either layout); a set a batch does not
- * use may be NULL.  Candidate index = position in cand, as for
- * QUERY_LISTS; positions no list covers are left untouched.  At most 32
- * distinct thresholds per call.
- * Execution: one graph of persistent kernels (tile work queue, survivor
- * compaction into a queue after `batch_inreg` levels, survivor drain).
- * k = 16, 32 or 64 fixes the chunk size; k = 0 lets an autotuner pick k,
- * the in-register levels and the grid by timing the candidates on this batch
- * shape (cached per context) and writes the chosen k to *k_used_host (may be
- * NULL).  k changes the check points of the algorithm and hence the output.
+ * OBJECT_MAJOR) or `cosine_sigs` (SRP, either layout; OBJECT_MAJOR rows of a
+ * multiple of 128 hashes, 16-byte aligned, are read 128 hashes per gather);
+ * a set a batch does not use may be NULL.  Candidate index = position in
+ * cand, as for QUERY_LISTS; positions no list covers are left untouched.  At
+ * most 32 distinct thresholds per call.
+ * Execution: one graph of kernels on a fixed grid (every wave runs a
+ * contiguous range of tiles; candidates undecided after `batch_inreg` levels
+ * are compacted into a survivor queue, which a second kernel drains).
+ * k_jaccard and k_cosine (16, 32 or 64) fix each measure's chunk size; 0 lets
+ * an autotuner pick it, and then also the in-register levels and the grid,
+ * by timing this batch shape (cached per context).  The k used are written to
+ * k_used_host[0] (Jaccard) and k_used_host[1] (cosine); k_used_host may be
+ * NULL.  k changes the check points of the algorithm and hence the output.
  * Consecutive batched calls on one context must use the same stream (or be
  * synchronised): they share the context's device-side batch descriptor. */
 typedef struct {
@@ -304,19 +308,20 @@ typedef struct {
 } blsh_list_desc;
 int bayeslsh_verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists_host, int64_t n_lists, const uint32_t *cand,
                             int64_t n_cand, const blsh_sigs *jaccard_sigs, const blsh_sigs *cosine_sigs,
-                            double epsilon, double delta, double gamma, blsh_prior jaccard_prior, int32_t k,
-                            int32_t *k_used_host, blsh_result *res, void *stream);
+                            double epsilon, double delta, double gamma, blsh_prior jaccard_prior, int32_t k_jaccard,
+                            int32_t k_cosine, int32_t *k_used_host, blsh_result *res, void *stream);
 
 /* Exhaustive comparator for a batch: the same lists, but every candidate
  * compares all n_max hashes of its object-major row with the query's, and
  * the decision sequence of Algorithm 1 is replayed on the per-level counts,
- * so the output equals bayeslsh_verify_batched's at the same k (k required).
+ * so the output equals bayeslsh_verify_batched's at the same k pair (both
+ * required for the measures the batch uses).
  * Signatures must be OBJECT_MAJOR with 16-byte aligned rows; SRP n_max one of
  * 128, 256, 512, 1024, 2048; minhash n_max a multiple of 64. */
 int bayeslsh_exhaustive_batched(blsh_ctx *ctx, const blsh_list_desc *lists_host, int64_t n_lists, const uint32_t *cand,
                                 int64_t n_cand, const blsh_sigs *jaccard_sigs, const blsh_sigs *cosine_sigs,
-                                double epsilon, double delta, double gamma, blsh_prior jaccard_prior, int32_t k,
-                                blsh_result *res, void *stream);
+                                double epsilon, double delta, double gamma, blsh_prior jaccard_prior,
+                                int32_t k_jaccard, int32_t k_cosine, blsh_result *res, void *stream);
 
 /* ---------------- serving ---------------- */
 

@@ -48,8 +48,9 @@ class Result(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("gather", C.c_int32), ("batch_inreg", C.c_int32), ("batch_blocks_per_cu", C.c_int32),
-                ("last_batch_k", C.c_int32), ("last_batch_inreg", C.c_int32),
-                ("last_batch_blocks_per_cu", C.c_int32), ("batch_spill_cap", C.c_int32), ("reserved", C.c_int32)]
+                ("last_batch_k_jaccard", C.c_int32), ("last_batch_inreg", C.c_int32),
+                ("last_batch_blocks_per_cu", C.c_int32), ("batch_spill_cap", C.c_int32),
+                ("last_batch_k_cosine", C.c_int32)]
 
 
 class ListDesc(C.Structure):
@@ -94,10 +95,10 @@ PROTOTYPES = [
       C.c_int32, C.POINTER(Result), p]),
     ("bayeslsh_verify_batched", C.c_int,
      [p, C.POINTER(ListDesc), C.c_int64, p, C.c_int64, C.POINTER(Sigs), C.POINTER(Sigs), C.c_double, C.c_double,
-      C.c_double, Prior, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Result), p]),
+      C.c_double, Prior, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Result), p]),
     ("bayeslsh_exhaustive_batched", C.c_int,
      [p, C.POINTER(ListDesc), C.c_int64, p, C.c_int64, C.POINTER(Sigs), C.POINTER(Sigs), C.c_double, C.c_double,
-      C.c_double, Prior, C.c_int32, C.POINTER(Result), p]),
+      C.c_double, Prior, C.c_int32, C.c_int32, C.POINTER(Result), p]),
     ("bayeslsh_server_create", C.c_int, [p, C.POINTER(Sigs), C.POINTER(ServerConfig), C.POINTER(p)]),
     ("bayeslsh_server_submit", C.c_int, [p, C.c_uint32, p, C.c_int64, C.c_double, C.POINTER(C.c_int64)]),
     ("bayeslsh_server_poll", C.c_int, [p, C.c_int64, C.POINTER(RequestResult)]),

@@ -289,7 +289,7 @@ def bayeslsh_set_tuning(ctx: Context, gather: int = 0, batch_inreg: int = 0, bat
 def bayeslsh_get_tuning(ctx: Context) -> dict:
     t = A.Tuning()
     _check(_lib().bayeslsh_get_tuning(ctx.handle, C.byref(t)))
-    return {name: getattr(t, name) for name, _ in A.Tuning._fields_ if name != "reserved"}
+    return {name: getattr(t, name) for name, _ in A.Tuning._fields_}
 
 
 LIST_DTYPE = None
@@ -312,10 +312,18 @@ def list_descs(measure, t, query, offset, length):
     return arr
 
 
+def _k_pair(k):
+    """k: one value for both measures or a (k_jaccard, k_cosine) pair; 0 = autotune."""
+    if isinstance(k, (tuple, list)):
+        return int(k[0]), int(k[1])
+    return int(k), int(k)
+
+
 def bayeslsh_verify_batched(ctx: Context, lists, cand: torch.Tensor, jaccard_sigs: Signatures | None,
                             cosine_sigs: Signatures | None, epsilon, delta, gamma, prior=(1.0, 1.0), k=32,
-                            res: Result = None, stream=None) -> int:
-    """lists: array from list_descs().  Returns the k used (the autotuner's choice when k = 0)."""
+                            res: Result = None, stream=None) -> tuple:
+    """lists: array from list_descs(); k: int or (k_jaccard, k_cosine), 0 = autotune.
+    Returns the (k_jaccard, k_cosine) used."""
     import numpy as np
     _dev(cand, torch.uint32, "cand")
     lists = np.ascontiguousarray(lists)
@@ -326,12 +334,13 @@ def bayeslsh_verify_batched(ctx: Context, lists, cand: torch.Tensor, jaccard_sig
     js = jaccard_sigs.struct() if jaccard_sigs is not None else None
     cs = cosine_sigs.struct() if cosine_sigs is not None else None
     rs = res.struct()
-    k_used = C.c_int32(0)
+    k_used = (C.c_int32 * 2)()
+    kj, kc = _k_pair(k)
     _check(_lib().bayeslsh_verify_batched(ctx.handle, lists.ctypes.data_as(C.POINTER(A.ListDesc)), len(lists),
                                           _p(cand), cand.numel(), C.byref(js) if js is not None else None,
                                           C.byref(cs) if cs is not None else None, epsilon, delta, gamma,
-                                          _prior(prior), k, C.byref(k_used), C.byref(rs), _stream(stream)))
-    return k_used.value
+                                          _prior(prior), kj, kc, k_used, C.byref(rs), _stream(stream)))
+    return int(k_used[0]), int(k_used[1])
 
 
 def bayeslsh_posterior_table(ctx, measure, t, epsilon, delta, gamma, prior=(1.0, 1.0), k=32, n_levels=8,
@@ -434,10 +443,11 @@ def bayeslsh_exhaustive_batched(ctx: Context, lists, cand: torch.Tensor, jaccard
     js = jaccard_sigs.struct() if jaccard_sigs is not None else None
     cs = cosine_sigs.struct() if cosine_sigs is not None else None
     rs = res.struct()
+    kj, kc = _k_pair(k)
     _check(_lib().bayeslsh_exhaustive_batched(ctx.handle, lists.ctypes.data_as(C.POINTER(A.ListDesc)), len(lists),
                                               _p(cand), cand.numel(), C.byref(js) if js is not None else None,
                                               C.byref(cs) if cs is not None else None, epsilon, delta, gamma,
-                                              _prior(prior), k, C.byref(rs), _stream(stream)))
+                                              _prior(prior), kj, kc, C.byref(rs), _stream(stream)))
     return res
 
 

@@ -22,7 +22,7 @@ int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim,
 int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStream_t s);
 int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
                    const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
-                   blsh_prior prior, int32_t k, blsh_result *res, int32_t *k_used, hipStream_t s,
+                   blsh_prior prior, int32_t kj, int32_t kc, blsh_result *res, int32_t *k_used, hipStream_t s,
                    int (*check_sigs_fn)(const blsh_sigs *, int, int *, int *), int mode);
 
 static thread_local char g_err[512] = "";
@@ -512,13 +512,13 @@ int bayeslsh_lite_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_
 
 static int batched_common(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand,
                           int64_t n_cand, const blsh_sigs *jac, const blsh_sigs *cos, double epsilon, double delta,
-                          double gamma, blsh_prior prior, int32_t k, int32_t *k_used, blsh_result *res, void *stream,
-                          int mode) {
+                          double gamma, blsh_prior prior, int32_t kj, int32_t kc, int32_t *k_used, blsh_result *res,
+                          void *stream, int mode) {
   if (!ctx) return fail(BLSH_EINVAL, "null context");
   int rc = check_params(0.5, epsilon, delta, gamma, false);
   if (rc) return rc;
-  if (k != 0 && k != 16 && k != 32 && k != 64) return fail(BLSH_EINVAL, "k must be 0 (autotune), 16, 32 or 64");
-  if (mode == 1 && k == 0) return fail(BLSH_EINVAL, "the exhaustive comparator needs an explicit k");
+  for (int32_t k : {kj, kc})
+    if (k != 0 && k != 16 && k != 32 && k != 64) return fail(BLSH_EINVAL, "k must be 0 (autotune), 16, 32 or 64");
   if (n_lists < 0 || n_cand < 0 || n_cand > (int64_t(1) << 40)) return fail(BLSH_EINVAL, "bad list or candidate count");
   if (n_lists > 0 && !lists) return fail(BLSH_EINVAL, "null list descriptors");
   if (n_cand > 0 && !cand) return fail(BLSH_EINVAL, "null candidates");
@@ -530,11 +530,15 @@ static int batched_common(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_
     if (!in01(d.t)) return fail(BLSH_EINVAL, "list %lld: t must be in (0,1)", (long long)i);
     if (d.offset < 0 || d.length < 0 || d.offset + d.length > n_cand)
       return fail(BLSH_EINVAL, "list %lld: range outside [0, n_cand)", (long long)i);
+    if (mode == 1 && (d.measure == BLSH_JACCARD ? kj : kc) == 0)
+      return fail(BLSH_EINVAL, "the exhaustive comparator needs an explicit k for every measure it runs");
   }
   if (mode == 1) {
     for (const blsh_sigs *sg : {jac, cos}) {
       if (!sg) continue;
       int nm = 0, rw = 0;
+      const int32_t k = sg->measure == BLSH_JACCARD ? kj : kc;
+      if (k == 0) continue;   // no list of this measure (checked above)
       if ((rc = check_sigs(sg, k, &nm, &rw))) return rc;
       if (sg->layout != BLSH_OBJECT_MAJOR || (uintptr_t(sg->data) & 15) || rw % 4)
         return fail(BLSH_EINVAL, "exhaustive: object-major, 16-byte aligned rows required");
@@ -547,27 +551,27 @@ static int batched_common(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (n_lists == 0 || n_cand == 0) {
     if (launch_zero(ctx, res->n_accepted, nullptr, s)) return fail(BLSH_EDEVICE, "launch failed");
-    if (k_used) *k_used = k;
+    if (k_used) { k_used[0] = kj; k_used[1] = kc; }
     return BLSH_OK;
   }
-  return verify_batched(ctx, lists, n_lists, cand, n_cand, jac, cos, epsilon, delta, gamma, prior, k, res, k_used, s,
-                        check_sigs, mode);
+  return verify_batched(ctx, lists, n_lists, cand, n_cand, jac, cos, epsilon, delta, gamma, prior, kj, kc, res, k_used,
+                        s, check_sigs, mode);
 }
 
 int bayeslsh_verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand,
                             int64_t n_cand, const blsh_sigs *jac, const blsh_sigs *cos, double epsilon, double delta,
-                            double gamma, blsh_prior prior, int32_t k, int32_t *k_used, blsh_result *res,
-                            void *stream) {
-  return batched_common(ctx, lists, n_lists, cand, n_cand, jac, cos, epsilon, delta, gamma, prior, k, k_used, res,
+                            double gamma, blsh_prior prior, int32_t kj, int32_t kc, int32_t *k_used,
+                            blsh_result *res, void *stream) {
+  return batched_common(ctx, lists, n_lists, cand, n_cand, jac, cos, epsilon, delta, gamma, prior, kj, kc, k_used, res,
                         stream, 0);
 }
 
 int bayeslsh_exhaustive_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand,
                                 int64_t n_cand, const blsh_sigs *jac, const blsh_sigs *cos, double epsilon,
-                                double delta, double gamma, blsh_prior prior, int32_t k, blsh_result *res,
-                                void *stream) {
-  return batched_common(ctx, lists, n_lists, cand, n_cand, jac, cos, epsilon, delta, gamma, prior, k, nullptr, res,
-                        stream, 1);
+                                double delta, double gamma, blsh_prior prior, int32_t kj, int32_t kc,
+                                blsh_result *res, void *stream) {
+  return batched_common(ctx, lists, n_lists, cand, n_cand, jac, cos, epsilon, delta, gamma, prior, kj, kc, nullptr,
+                        res, stream, 1);
 }
 
 int bayeslsh_exhaustive_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs,

@@ -1,36 +1,41 @@
 // Batched verification of many query lists of uneven lengths in one
 // graph-launched pair of persistent kernels (Algorithm 1 per candidate).
 //
-// Phase 1 (k_batch_phase1): persistent blocks pull tiles from a device work
-//   counter.  A tile is 1024 consecutive candidates of one SRP list (one lane
-//   per 4 candidates) or 256 of one minhash list (a group of k/4 lanes per
-//   candidate, lane l of a wave owning candidate l).  The query's words are
-//   loaded once per tile.  Each list carries its own measure and threshold,
-//   hence its own decision table.  A candidate still undecided after
-//   `inreg_levels` levels is spilled to a per-measure survivor queue
-//   (wavefront ballot compaction); when the queue is full it simply continues
-//   in registers.
+// Phase 1 (k_batch_phase1): the batch is cut into wave tiles -- 256
+//   consecutive candidates of one SRP list (4 per lane) or 64 of one minhash
+//   list (lane l owns candidate l, a group of k/4 lanes compares each
+//   candidate's k hashes) -- and every wave of the fixed grid runs one
+//   contiguous range of tiles (no work counter, no block barrier).  The
+//   query's hashes are wave-uniform.  Each list carries its own measure and
+//   threshold, hence its own decision table, and each measure its own k.  A
+//   candidate still undecided after `inreg_levels` levels (SRP object-major
+//   rows: at least the 128 hashes one 16-byte load brings) is spilled to a
+//   per-measure survivor queue (wavefront ballot compaction); when the queue
+//   is full it simply continues in registers.
 // Phase 2 (k_batch_phase2): persistent blocks drain the survivor queues with
 //   every lane busy: one lane per SRP survivor, one group of k/4 lanes per
 //   minhash survivor, running the remaining levels.
 //
 // Both kernels read all their arguments from one device-resident BatchBlock,
 // so the graph that holds [reset, phase 1, phase 2] is captured once per
-// (k, grid) and replayed for any batch: each call only refreshes the block.
+// (k pair, grid) and replayed for any batch: each call only refreshes the block.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <set>
+#include <utility>
 
 #include "device_common.h"
 
 namespace blsh {
 
 constexpr int kMaxBatchTables = 64;
-constexpr int kSrpTile = 1024;     // candidates per SRP tile (256 lanes x 4)
-constexpr int kMhTile = 256;       // candidates per minhash tile (one per lane)
 constexpr int kBBlock = 256;
+constexpr int kSrpTile = 256;      // phase 1: candidates per SRP wave tile (64 lanes x 4)
+constexpr int kMhTile = 64;        // phase 1: candidates per minhash wave tile (one per lane)
+constexpr int kExSrpTile = 1024;   // comparator: candidates per SRP block tile
+constexpr int kExMhTile = 256;     // comparator: candidates per minhash block tile
 
 struct BatchList {
   int64_t offset;
@@ -74,6 +79,40 @@ struct BatchBlock {
 // z = list index, w = m | level << 16 (level = next level to run).
 __device__ inline uint4 spill_entry(int64_t pos, uint32_t list, uint32_t m, uint32_t next_level) {
   return make_uint4(uint32_t(pos), uint32_t(uint64_t(pos) >> 32), list, m | (next_level << 16));
+}
+
+// Read-only data (signatures, tables, list descriptors: nothing the kernels
+// write) read through the constant address space, so that a wave-uniform
+// address becomes one scalar load.
+template <typename T>
+__device__ inline T ld_uniform(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)(p);
+}
+
+__device__ inline BatchList ld_list(const BatchList *p) {
+  BatchList r;
+  r.offset = ld_uniform(&p->offset);
+  r.length = ld_uniform(&p->length);
+  r.query = ld_uniform(&p->query);
+  r.measure = ld_uniform(&p->measure);
+  r.table = ld_uniform(&p->table);
+  r.pad = 0;
+  return r;
+}
+
+// Static split of T tiles over the waves of the grid: wave w runs the tiles
+// [w T / W, (w+1) T / W).
+__device__ inline void wave_range(int64_t T, int64_t &begin, int64_t &end) {
+  const int64_t W = int64_t(gridDim.x) * (kBBlock / kWave);
+  const int64_t w = int64_t(blockIdx.x) * (kBBlock / kWave) +
+                    int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
+  begin = w * T / W;
+  end = (w + 1) * T / W;
+}
+
+template <int G, int... S>
+__device__ inline void group_bcast_all(uint32_t v, uint32_t *out, std::integer_sequence<int, S...>) {
+  ((out[S] = group_bcast<G, S>(v)), ...);
 }
 
 __device__ inline void emit_block(const BatchBlock &B, bool pred, int64_t idx, float val) {
@@ -120,144 +159,190 @@ __device__ inline uint32_t srp_level_word_agree(const SigView &s, uint32_t q, ui
 }
 
 // ---------------------------------------------------------------------------
-// phase 1: tiles
+// phase 1: wave tiles
 // ---------------------------------------------------------------------------
+// agreement of level j from the XOR of two 128-bit prefixes
 template <int K>
-__device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_id, int64_t tile_in_list,
-                         const int *s_min, const uint32_t *tab, int L) {
-  const SigView &S = B.sig[BLSH_COSINE];
-  const int words = int(tab[2]);
-  const int64_t base = Ls.offset + tile_in_list * kSrpTile;
+__device__ inline uint32_t prefix_agree(const uint32_t *d, int j) {
+  if constexpr (K == 32) return 32u - __popc(d[j]);
+  else if constexpr (K == 64) return 64u - __popc(d[2 * j]) - __popc(d[2 * j + 1]);
+  else return 16u - __popc((d[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu);
+}
+
+// 256 consecutive candidates of one SRP list: candidate base + 64 p + lane.
+template <int K>
+__device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_id, int64_t base,
+                         const uint32_t *tab, int L) {
+  constexpr int P = kSrpTile / kWave;
+  constexpr int PL = 128 / K;          // levels held by a 128-bit prefix
+  const SigView S = B.sig[BLSH_COSINE];
+  const int words = int(ld_uniform(tab + 2));
+  const int lane = lane_id();
   const int64_t end = Ls.offset + Ls.length;
-  const int64_t c0 = base + int64_t(threadIdx.x) * 4;
   const uint32_t q = Ls.query;
   const bool q_ok = q < S.n_obj;
-  uint32_t y[4] = {0, 0, 0, 0};
-  uint32_t alive = 0, bad = 0;
+  // object-major rows that a 16-byte load can start: one gather per side
+  // serves the first 128 hashes
+  const bool pfx = !S.word_major && (S.row_words & 3) == 0 && (uintptr_t(S.data) & 15) == 0;
+  uint32_t y[P], alive = 0, bad = 0, in = 0;
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    if (c0 + p < end) {
-      y[p] = __builtin_nontemporal_load(B.cand + c0 + p);
-      if (q_ok && y[p] < S.n_obj) alive |= 1u << p; else bad |= 1u << p;
+  for (int p = 0; p < P; ++p) {
+    const int64_t c = base + p * kWave + lane;
+    y[p] = 0;
+    if (c < end) {
+      in |= 1u << p;
+      y[p] = __builtin_nontemporal_load(B.cand + c);
+      if (q_ok && y[p] < S.n_obj) alive |= 1u << p; else { bad |= 1u << p; y[p] = 0; }
     }
   }
-  uint32_t m[4] = {0, 0, 0, 0};
-  uint8_t code[4] = {0, 0, 0, 0};
-  uint32_t emit = 0;
-  const int J = min(L, B.inreg_levels);
+  uint32_t m[P], emit = 0;
+  uint8_t code[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) { m[p] = 0; code[p] = 0; }
+  auto decide = [&](int p, int j) {
+    if (int(m[p]) < int(ld_uniform(tab + kTabMinOff + j))) {
+      code[p] = uint8_t((BLSH_PRUNED << 6) | j);
+      alive &= ~(1u << p);
+    } else if (accept_bit(tab, words, j, int(m[p]))) {
+      code[p] = uint8_t((BLSH_ACCEPT_CONC << 6) | j);
+      alive &= ~(1u << p);
+      emit |= 1u << p;
+    } else if (j == L - 1) {
+      code[p] = uint8_t((BLSH_ACCEPT_NMAX << 6) | j);
+      alive &= ~(1u << p);
+      emit |= 1u << p;
+    }
+  };
+  auto word_levels = [&](int j0, int j1) {
+    for (int j = j0; j < j1 && __ballot(alive != 0); ++j) {
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        if (alive & (1u << p)) m[p] += srp_level_word_agree<K>(S, q, y[p], j);
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        if (alive & (1u << p)) decide(p, j);
+    }
+  };
+  const int J = min(L, max(B.inreg_levels, pfx ? PL : 0));
   int j = 0;
-  for (; j < J && alive; ++j) {
+  if (pfx && __ballot(alive != 0)) {
+    // all gathers issued before any is consumed; a lane without a live
+    // candidate reads the query's own row
+    const u32x4 hq = ld_uniform(reinterpret_cast<const u32x4 *>(S.data + size_t(q) * S.row_words));
+    u32x4 hy[P];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
-      if (alive & (1u << p)) m[p] += srp_level_word_agree<K>(S, q, y[p], j);
+    for (int p = 0; p < P; ++p)
+      hy[p] = *reinterpret_cast<const u32x4 *>(S.data + size_t((alive >> p) & 1u ? y[p] : q) * S.row_words);
+    uint32_t d[P][4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      if (!(alive & (1u << p))) continue;
-      if (int(m[p]) < s_min[j]) { code[p] = uint8_t((BLSH_PRUNED << 6) | j); alive &= ~(1u << p); }
-      else if (accept_bit(tab, words, j, int(m[p]))) { code[p] = uint8_t((BLSH_ACCEPT_CONC << 6) | j); alive &= ~(1u << p); emit |= 1u << p; }
-      else if (j == L - 1) { code[p] = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); alive &= ~(1u << p); emit |= 1u << p; }
+    for (int p = 0; p < P; ++p) {
+      d[p][0] = hq.x ^ hy[p].x; d[p][1] = hq.y ^ hy[p].y;
+      d[p][2] = hq.z ^ hy[p].z; d[p][3] = hq.w ^ hy[p].w;
     }
+    const int JP = min(J, PL);
+#pragma unroll
+    for (int jj = 0; jj < PL; ++jj) {   // unrolled: d is indexed by constants
+      if (jj < JP && __ballot(alive != 0)) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          if (!(alive & (1u << p))) continue;
+          m[p] += prefix_agree<K>(d[p], jj);
+          decide(p, jj);
+        }
+      }
+    }
+    j = JP;
   }
+  word_levels(j, J);
   // spill what is still undecided; what cannot be spilled continues here
   uint32_t kept = 0;
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < P; ++p) {
     const bool want = (alive >> p) & 1u;
-    const bool ok = spill_push(B, BLSH_COSINE, want, spill_entry(c0 + p, uint32_t(list_id), m[p], uint32_t(J)));
+    const bool ok = spill_push(B, BLSH_COSINE, want,
+                               spill_entry(base + p * kWave + lane, uint32_t(list_id), m[p], uint32_t(J)));
     if (want && !ok) kept |= 1u << p;
   }
   alive = kept;
-  for (j = J; j < L && alive; ++j) {
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-      if (alive & (1u << p)) m[p] += srp_level_word_agree<K>(S, q, y[p], j);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      if (!(alive & (1u << p))) continue;
-      if (int(m[p]) < s_min[j]) { code[p] = uint8_t((BLSH_PRUNED << 6) | j); alive &= ~(1u << p); }
-      else if (accept_bit(tab, words, j, int(m[p]))) { code[p] = uint8_t((BLSH_ACCEPT_CONC << 6) | j); alive &= ~(1u << p); emit |= 1u << p; }
-      else if (j == L - 1) { code[p] = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); alive &= ~(1u << p); emit |= 1u << p; }
-    }
-  }
+  word_levels(J, L);
   if (bad) raise_status(B.status, BLSH_EBADID);
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    if (c0 + p >= end) continue;
-    B.code[c0 + p] = (bad >> p) & 1u ? uint8_t(0xFF) : code[p];
-    if (B.m_dbg) B.m_dbg[c0 + p] = uint16_t(m[p]);
+  for (int p = 0; p < P; ++p) {
+    if (!((in >> p) & 1u)) continue;
+    const int64_t c = base + p * kWave + lane;
+    B.code[c] = (bad >> p) & 1u ? uint8_t(0xFF) : code[p];
+    if (B.m_dbg) B.m_dbg[c] = uint16_t(m[p]);
   }
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < P; ++p) {
     const bool e = (emit >> p) & 1u;
     const float v = e ? map_estimate(BLSH_COSINE, int(m[p]), ((code[p] & 63) + 1) * K, 1.0, 1.0) : 0.f;
-    emit_block(B, e, c0 + p, v);
+    emit_block(B, e, base + p * kWave + lane, v);
   }
 }
 
-template <int G, int S>
-struct BatchMhStep {
-  template <int K>
-  __device__ static inline void run(const SigView &sv, uint4 hq, uint32_t y, uint32_t alive, int j, int r,
-                                    uint32_t &own) {
-    const uint32_t ys = group_bcast<G, S>(y);
-    const uint32_t al = group_bcast<G, S>(alive);
-    uint32_t c = 0;
-    if (al) {
-      const uint4 hy = *reinterpret_cast<const uint4 *>(sv.data + size_t(ys) * sv.row_words + j * K + 4 * r);
-      c = uint32_t(hq.x == hy.x) + uint32_t(hq.y == hy.y) + uint32_t(hq.z == hy.z) + uint32_t(hq.w == hy.w);
-    }
-    c = group_sum<G>(c);
-    if (r == S) own = c;
-    if constexpr (S + 1 < G) BatchMhStep<G, S + 1>::template run<K>(sv, hq, y, alive, j, r, own);
-  }
-};
-
+// 64 consecutive candidates of one minhash list: lane l owns candidate base + l;
+// the group of G = k/4 lanes holding a candidate compares the k hashes of each
+// of its G members in turn (lane r holds hashes 4r..4r+3 of the level), with
+// the group's rows loaded before any comparison.
 template <int K>
-__device__ void minhash_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_id, int64_t tile_in_list,
-                             const int *s_min, const uint32_t *tab, int L) {
+__device__ void minhash_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_id, int64_t base,
+                             const uint32_t *tab, int L) {
   constexpr int G = K / 4;
-  const SigView &S = B.sig[BLSH_JACCARD];
-  const int words = int(tab[2]);
+  constexpr int CH = G < 8 ? G : 8;      // rows in flight per pass
+  const SigView S = B.sig[BLSH_JACCARD];
+  const int words = int(ld_uniform(tab + 2));
   const int64_t end = Ls.offset + Ls.length;
-  const int64_t c = Ls.offset + tile_in_list * kMhTile + threadIdx.x;
   const int lane = lane_id(), r = lane & (G - 1);
+  const int64_t c = base + lane;
   const uint32_t q = Ls.query;
   const bool q_ok = q < S.n_obj;
-  uint32_t y = 0, alive = 0;
-  bool bad = false;
-  if (c < end) {
+  const bool in = c < end;
+  uint32_t y = 0;
+  bool alive = false, bad = false;
+  if (in) {
     y = __builtin_nontemporal_load(B.cand + c);
-    if (q_ok && y < S.n_obj) alive = 1; else { bad = true; y = 0; }
+    if (q_ok && y < S.n_obj) alive = true; else bad = true;
   }
   uint32_t m = 0;
   uint8_t code = 0;
   bool emit = false;
-  const int J = min(L, B.inreg_levels);
   auto level = [&](int j) {
-    uint4 hq = make_uint4(0, 0, 0, 0);
-    if (q_ok) hq = *reinterpret_cast<const uint4 *>(S.data + size_t(q) * S.row_words + j * K + 4 * r);
+    // a lane whose candidate is decided (or invalid) reads the query's row
+    const uint32_t yv = alive ? y : q;
+    uint32_t ys[G];
+    group_bcast_all<G>(yv, ys, std::make_integer_sequence<int, G>{});
+    const size_t col = size_t(j) * K + 4 * r;
+    const uint4 hq = *reinterpret_cast<const uint4 *>(S.data + size_t(q) * S.row_words + col);
     uint32_t own = 0;
-    BatchMhStep<G, 0>::template run<K>(S, hq, y, alive, j, r, own);
+#pragma unroll
+    for (int s0 = 0; s0 < G; s0 += CH) {
+      uint4 hy[CH];
+#pragma unroll
+      for (int s = 0; s < CH; ++s)
+        hy[s] = *reinterpret_cast<const uint4 *>(S.data + size_t(ys[s0 + s]) * S.row_words + col);
+#pragma unroll
+      for (int s = 0; s < CH; ++s) {
+        uint32_t cnt = uint32_t(hq.x == hy[s].x) + uint32_t(hq.y == hy[s].y) + uint32_t(hq.z == hy[s].z) +
+                       uint32_t(hq.w == hy[s].w);
+        cnt = group_sum<G>(cnt);
+        if (r == s0 + s) own = cnt;
+      }
+    }
     if (alive) {
       m += own;
-      if (int(m) < s_min[j]) { code = uint8_t((BLSH_PRUNED << 6) | j); alive = 0; }
-      else if (accept_bit(tab, words, j, int(m))) { code = uint8_t((BLSH_ACCEPT_CONC << 6) | j); alive = 0; emit = true; }
-      else if (j == L - 1) { code = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); alive = 0; emit = true; }
+      if (int(m) < int(ld_uniform(tab + kTabMinOff + j))) { code = uint8_t((BLSH_PRUNED << 6) | j); alive = false; }
+      else if (accept_bit(tab, words, j, int(m))) { code = uint8_t((BLSH_ACCEPT_CONC << 6) | j); alive = false; emit = true; }
+      else if (j == L - 1) { code = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); alive = false; emit = true; }
     }
   };
-  for (int j = 0; j < J; ++j) {
-    if (__ballot(alive != 0) == 0) break;
-    level(j);
-  }
-  const bool want = alive != 0;
-  const bool ok = spill_push(B, BLSH_JACCARD, want, spill_entry(c, uint32_t(list_id), m, uint32_t(J)));
-  if (ok) alive = 0;
-  for (int j = J; j < L; ++j) {
-    if (__ballot(alive != 0) == 0) break;
-    level(j);
-  }
+  const int J = min(L, B.inreg_levels);
+  for (int j = 0; j < J && __ballot(alive); ++j) level(j);
+  const bool ok = spill_push(B, BLSH_JACCARD, alive, spill_entry(c, uint32_t(list_id), m, uint32_t(J)));
+  if (ok) alive = false;
+  for (int j = J; j < L && __ballot(alive); ++j) level(j);
   if (bad) raise_status(B.status, BLSH_EBADID);
-  if (c < end) {
+  if (in) {
     B.code[c] = bad ? uint8_t(0xFF) : code;
     if (B.m_dbg) B.m_dbg[c] = uint16_t(m);
   }
@@ -265,45 +350,45 @@ __device__ void minhash_tile(const BatchBlock &B, const BatchList &Ls, int32_t l
   emit_block(B, emit, c, v);
 }
 
+// Index of the list holding tile t (the last l with prefix[l] <= t).
 __device__ inline int64_t list_of_tile(const int64_t *prefix, int64_t n_lists, int64_t t) {
   int64_t lo = 0, hi = n_lists - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+    if (ld_uniform(prefix + mid) <= t) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
-template <int K>
+template <int KJ, int KC>
 __global__ __launch_bounds__(kBBlock) void k_batch_phase1(const BatchBlock *__restrict__ Bp) {
   const BatchBlock &B = *Bp;
-  __shared__ int s_min[kMaxLevels];
-  __shared__ long long s_tile;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = (long long)atomicAdd(&B.counters[0], 1ull);
-    __syncthreads();
-    const long long t = s_tile;
-    if (t >= B.n_tiles) break;
-    const int64_t l = list_of_tile(B.tile_prefix, B.n_lists, t);
-    const BatchList Ls = B.lists[l];
-    const uint32_t *tab = B.tables[Ls.table];
-    const int L = B.n_levels[Ls.table];
-    if (threadIdx.x < kMaxLevels) s_min[threadIdx.x] = int(threadIdx.x) < L ? int(tab[kTabMinOff + threadIdx.x]) : 0x7fffffff;
-    __syncthreads();
-    if (Ls.measure == BLSH_COSINE) srp_tile<K>(B, Ls, int32_t(l), t - B.tile_prefix[l], s_min, tab, L);
-    else minhash_tile<K>(B, Ls, int32_t(l), t - B.tile_prefix[l], s_min, tab, L);
-    __syncthreads();
+  int64_t t0, t1;
+  wave_range(B.n_tiles, t0, t1);
+  if (t0 >= t1) return;
+  int64_t l = list_of_tile(B.tile_prefix, B.n_lists, t0);
+  int64_t first = ld_uniform(B.tile_prefix + l), next = ld_uniform(B.tile_prefix + l + 1);
+  for (int64_t t = t0; t < t1; ++t) {
+    while (t >= next) {   // empty lists have no tiles
+      ++l;
+      first = next;
+      next = ld_uniform(B.tile_prefix + l + 1);
+    }
+    const BatchList Ls = ld_list(B.lists + l);
+    const uint32_t *tab = ld_uniform(B.tables + Ls.table);
+    const int L = ld_uniform(B.n_levels + Ls.table);
+    if (Ls.measure == BLSH_COSINE) srp_tile<KC>(B, Ls, int32_t(l), Ls.offset + (t - first) * kSrpTile, tab, L);
+    else minhash_tile<KJ>(B, Ls, int32_t(l), Ls.offset + (t - first) * kMhTile, tab, L);
   }
 }
 
 // ---------------------------------------------------------------------------
 // phase 2: spilled survivors
 // ---------------------------------------------------------------------------
-template <int K>
+template <int KJ, int KC>
 __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__restrict__ Bp) {
-  constexpr int G = K / 4;
+  constexpr int G = KJ / 4;
   const BatchBlock &B = *Bp;
-  const int lane = lane_id();
   // SRP survivors: one lane each
   {
     const int64_t n = min<int64_t>(int64_t(B.counters[1 + BLSH_COSINE]), B.spill_cap);
@@ -330,7 +415,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
         q = Ls.query;
         yv = B.cand[pos];
         for (; j < L; ++j) {
-          m += srp_level_word_agree<K>(S, q, yv, j);
+          m += srp_level_word_agree<KC>(S, q, yv, j);
           if (int(m) < int(tab[kTabMinOff + j])) { code = uint8_t((BLSH_PRUNED << 6) | j); break; }
           if (accept_bit(tab, words, j, int(m))) { code = uint8_t((BLSH_ACCEPT_CONC << 6) | j); emit = true; break; }
           if (j == L - 1) { code = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); emit = true; break; }
@@ -338,7 +423,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
         B.code[pos] = code;
         if (B.m_dbg) B.m_dbg[pos] = uint16_t(m);
       }
-      const float v = emit ? map_estimate(BLSH_COSINE, int(m), ((code & 63) + 1) * K, 1.0, 1.0) : 0.f;
+      const float v = emit ? map_estimate(BLSH_COSINE, int(m), ((code & 63) + 1) * KC, 1.0, 1.0) : 0.f;
       emit_block(B, emit, pos, v);
     }
   }
@@ -374,8 +459,8 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
       while (__ballot(alive) != 0) {
         uint32_t c = 0;
         if (alive) {
-          const uint4 hq = *reinterpret_cast<const uint4 *>(S.data + size_t(q) * S.row_words + j * K + 4 * r);
-          const uint4 hy = *reinterpret_cast<const uint4 *>(S.data + size_t(yv) * S.row_words + j * K + 4 * r);
+          const uint4 hq = *reinterpret_cast<const uint4 *>(S.data + size_t(q) * S.row_words + j * KJ + 4 * r);
+          const uint4 hy = *reinterpret_cast<const uint4 *>(S.data + size_t(yv) * S.row_words + j * KJ + 4 * r);
           c = uint32_t(hq.x == hy.x) + uint32_t(hq.y == hy.y) + uint32_t(hq.z == hy.z) + uint32_t(hq.w == hy.w);
         }
         c = group_sum<G>(c);
@@ -392,7 +477,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
         if (B.m_dbg) B.m_dbg[pos] = uint16_t(m);
       }
       const bool e = emit && r == 0;
-      const float v = e ? map_estimate(BLSH_JACCARD, int(m), ((code & 63) + 1) * K, B.alpha, B.beta) : 0.f;
+      const float v = e ? map_estimate(BLSH_JACCARD, int(m), ((code & 63) + 1) * KJ, B.alpha, B.beta) : 0.f;
       emit_block(B, e, pos, v);
     }
   }
@@ -426,8 +511,8 @@ __device__ void srp_tile_exhaustive(const BatchBlock &B, const BatchList &Ls, in
   const bool q_ok = q < S.n_obj;
   uint4 hq = make_uint4(0, 0, 0, 0);
   if (q_ok) hq = *reinterpret_cast<const uint4 *>(S.data + size_t(q) * S.row_words + 4 * r);
-  const int64_t t0 = Ls.offset + tile_in_list * kSrpTile;
-  for (int64_t c0 = t0; c0 < min(end, t0 + kSrpTile); c0 += PER_BLOCK) {
+  const int64_t t0 = Ls.offset + tile_in_list * kExSrpTile;
+  for (int64_t c0 = t0; c0 < min(end, t0 + kExSrpTile); c0 += PER_BLOCK) {
     const int64_t c = c0 + g;
     const bool in = c < end;
     uint32_t y = 0;
@@ -503,8 +588,8 @@ __device__ void minhash_tile_exhaustive(const BatchBlock &B, const BatchList &Ls
   const int64_t end = Ls.offset + Ls.length;
   const uint32_t q = Ls.query;
   const bool q_ok = q < S.n_obj;
-  const int64_t t0 = Ls.offset + tile_in_list * kMhTile;
-  for (int64_t c0 = t0; c0 < min(end, t0 + kMhTile); c0 += PER_BLOCK) {
+  const int64_t t0 = Ls.offset + tile_in_list * kExMhTile;
+  for (int64_t c0 = t0; c0 < min(end, t0 + kExMhTile); c0 += PER_BLOCK) {
     const int64_t c = c0 + g;
     const bool in = c < end;
     uint32_t y = 0;
@@ -547,31 +632,35 @@ __device__ void minhash_tile_exhaustive(const BatchBlock &B, const BatchList &Ls
   }
 }
 
-template <int K>
+// Block b of the fixed grid runs the block tiles [b T / NB, (b+1) T / NB).
+template <int KJ, int KC>
 __global__ __launch_bounds__(kBBlock) void k_batch_exhaustive(const BatchBlock *__restrict__ Bp) {
   const BatchBlock &B = *Bp;
-  __shared__ long long s_tile;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = (long long)atomicAdd(&B.counters[0], 1ull);
-    __syncthreads();
-    const long long t = s_tile;
-    if (t >= B.n_tiles) break;
-    const int64_t l = list_of_tile(B.tile_prefix, B.n_lists, t);
-    const BatchList Ls = B.lists[l];
-    const uint32_t *tab = B.tables[Ls.table];
-    const int L = B.n_levels[Ls.table];
-    const int64_t tl = t - B.tile_prefix[l];
-    if (Ls.measure == BLSH_COSINE) {
-      const int W = L * K / 32;   // words compared: n_max bits
-      if (W == 4) srp_tile_exhaustive<K, 1>(B, Ls, tl, tab, L);
-      else if (W == 8) srp_tile_exhaustive<K, 2>(B, Ls, tl, tab, L);
-      else if (W == 16) srp_tile_exhaustive<K, 4>(B, Ls, tl, tab, L);
-      else if (W == 32) srp_tile_exhaustive<K, 8>(B, Ls, tl, tab, L);
-      else srp_tile_exhaustive<K, 16>(B, Ls, tl, tab, L);
-    } else {
-      minhash_tile_exhaustive<K>(B, Ls, tl, tab, L, L * K);
+  const int64_t T = B.n_tiles, NB = gridDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * T / NB, t1 = (int64_t(blockIdx.x) + 1) * T / NB;
+  if (t0 >= t1) return;
+  int64_t l = list_of_tile(B.tile_prefix, B.n_lists, t0);
+  int64_t first = ld_uniform(B.tile_prefix + l), next = ld_uniform(B.tile_prefix + l + 1);
+  for (int64_t t = t0; t < t1; ++t) {
+    while (t >= next) {
+      ++l;
+      first = next;
+      next = ld_uniform(B.tile_prefix + l + 1);
     }
-    __syncthreads();
+    const BatchList Ls = ld_list(B.lists + l);
+    const uint32_t *tab = ld_uniform(B.tables + Ls.table);
+    const int L = ld_uniform(B.n_levels + Ls.table);
+    const int64_t tl = t - first;
+    if (Ls.measure == BLSH_COSINE) {
+      const int W = L * KC / 32;   // words compared: n_max bits
+      if (W == 4) srp_tile_exhaustive<KC, 1>(B, Ls, tl, tab, L);
+      else if (W == 8) srp_tile_exhaustive<KC, 2>(B, Ls, tl, tab, L);
+      else if (W == 16) srp_tile_exhaustive<KC, 4>(B, Ls, tl, tab, L);
+      else if (W == 32) srp_tile_exhaustive<KC, 8>(B, Ls, tl, tab, L);
+      else srp_tile_exhaustive<KC, 16>(B, Ls, tl, tab, L);
+    } else {
+      minhash_tile_exhaustive<KJ>(B, Ls, tl, tab, L, L * KJ);
+    }
   }
 }
 
@@ -597,29 +686,29 @@ struct BatchState {
   bool staged_valid = false;
   hipStream_t cap_stream{};
   struct GraphKey {
-    int mode, k, grid1, grid2;
+    int mode, kj, kc, grid1, grid2;
     bool operator<(const GraphKey &o) const {
-      return std::tie(mode, k, grid1, grid2) < std::tie(o.mode, o.k, o.grid1, o.grid2);
+      return std::tie(mode, kj, kc, grid1, grid2) < std::tie(o.mode, o.kj, o.kc, o.grid1, o.grid2);
     }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
-  struct Choice { int k, inreg, bpc; };
+  struct Choice { int kj, kc, inreg, bpc; };
   std::map<std::vector<int64_t>, Choice> tuned;
 };
 
 static void batch_free(BatchState *b) {
   if (!b) return;
-  for (auto &g : b->graphs) hipGraphExecDestroy(g.second);
-  if (b->d_block) hipFree(b->d_block);
-  if (b->h_block) hipHostFree(b->h_block);
-  if (b->d_lists) hipFree(b->d_lists);
-  if (b->h_lists) hipHostFree(b->h_lists);
-  if (b->d_prefix) hipFree(b->d_prefix);
-  if (b->h_prefix) hipHostFree(b->h_prefix);
-  if (b->d_counters) hipFree(b->d_counters);
-  for (auto *p : b->d_spill) if (p) hipFree(p);
-  if (b->staged_valid) hipEventDestroy(b->staged);
-  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  if (b->d_block) (void)hipFree(b->d_block);
+  if (b->h_block) (void)hipHostFree(b->h_block);
+  if (b->d_lists) (void)hipFree(b->d_lists);
+  if (b->h_lists) (void)hipHostFree(b->h_lists);
+  if (b->d_prefix) (void)hipFree(b->d_prefix);
+  if (b->h_prefix) (void)hipHostFree(b->h_prefix);
+  if (b->d_counters) (void)hipFree(b->d_counters);
+  for (auto *p : b->d_spill) if (p) (void)hipFree(p);
+  if (b->staged_valid) (void)hipEventDestroy(b->staged);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;
 }
 
@@ -648,10 +737,10 @@ static int batch_state(blsh_ctx *ctx, BatchState **out) {
 static int grow_lists(BatchState *b, int64_t n_lists) {
   if (b->lists_cap >= n_lists) return BLSH_OK;
   BLSH_HIP(hipDeviceSynchronize());
-  if (b->d_lists) hipFree(b->d_lists);
-  if (b->h_lists) hipHostFree(b->h_lists);
-  if (b->d_prefix) hipFree(b->d_prefix);
-  if (b->h_prefix) hipHostFree(b->h_prefix);
+  if (b->d_lists) (void)hipFree(b->d_lists);
+  if (b->h_lists) (void)hipHostFree(b->h_lists);
+  if (b->d_prefix) (void)hipFree(b->d_prefix);
+  if (b->h_prefix) (void)hipHostFree(b->h_prefix);
   b->d_lists = b->h_lists = nullptr;
   b->d_prefix = b->h_prefix = nullptr;
   b->lists_cap = 0;
@@ -668,7 +757,7 @@ static int grow_lists(BatchState *b, int64_t n_lists) {
 static int grow_spill(BatchState *b, int64_t cap) {
   if (b->spill_cap >= cap) return BLSH_OK;
   BLSH_HIP(hipDeviceSynchronize());
-  for (auto *&p : b->d_spill) { if (p) hipFree(p); p = nullptr; }
+  for (auto *&p : b->d_spill) { if (p) (void)hipFree(p); p = nullptr; }
   b->spill_cap = 0;
   for (auto *&p : b->d_spill)
     if (hipMalloc(&p, size_t(cap) * sizeof(uint4)) != hipSuccess) return fail(BLSH_ENOMEM, "spill buffers");
@@ -676,30 +765,37 @@ static int grow_spill(BatchState *b, int64_t cap) {
   return BLSH_OK;
 }
 
-template <int K>
+template <int KJ, int KC>
 static void launch_batch_kernels(BatchState *b, int mode, int grid1, int grid2, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, b->d_block);
   if (mode == 1) {
-    hipLaunchKernelGGL(k_batch_exhaustive<K>, dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
+    hipLaunchKernelGGL((k_batch_exhaustive<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
     return;
   }
-  hipLaunchKernelGGL(k_batch_phase1<K>, dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
-  hipLaunchKernelGGL(k_batch_phase2<K>, dim3(grid2), dim3(kBBlock), 0, s, b->d_block);
+  hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
+  hipLaunchKernelGGL((k_batch_phase2<KJ, KC>), dim3(grid2), dim3(kBBlock), 0, s, b->d_block);
 }
 
-static int get_graph(BatchState *b, int mode, int k, int grid1, int grid2, hipGraphExec_t *out) {
-  BatchState::GraphKey key{mode, k, grid1, grid2};
+template <int KJ>
+static void launch_batch_kernels_kc(BatchState *b, int kc, int mode, int grid1, int grid2, hipStream_t s) {
+  if (kc == 16) launch_batch_kernels<KJ, 16>(b, mode, grid1, grid2, s);
+  else if (kc == 32) launch_batch_kernels<KJ, 32>(b, mode, grid1, grid2, s);
+  else launch_batch_kernels<KJ, 64>(b, mode, grid1, grid2, s);
+}
+
+static int get_graph(BatchState *b, int mode, int kj, int kc, int grid1, int grid2, hipGraphExec_t *out) {
+  BatchState::GraphKey key{mode, kj, kc, grid1, grid2};
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) { *out = it->second; return BLSH_OK; }
   hipGraph_t g;
   BLSH_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-  if (k == 16) launch_batch_kernels<16>(b, mode, grid1, grid2, b->cap_stream);
-  else if (k == 32) launch_batch_kernels<32>(b, mode, grid1, grid2, b->cap_stream);
-  else launch_batch_kernels<64>(b, mode, grid1, grid2, b->cap_stream);
+  if (kj == 16) launch_batch_kernels_kc<16>(b, kc, mode, grid1, grid2, b->cap_stream);
+  else if (kj == 32) launch_batch_kernels_kc<32>(b, kc, mode, grid1, grid2, b->cap_stream);
+  else launch_batch_kernels_kc<64>(b, kc, mode, grid1, grid2, b->cap_stream);
   BLSH_HIP(hipStreamEndCapture(b->cap_stream, &g));
   hipGraphExec_t ex;
   hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(BLSH_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
   b->graphs[key] = ex;
   *out = ex;
@@ -708,13 +804,13 @@ static int get_graph(BatchState *b, int mode, int k, int grid1, int grid2, hipGr
 
 int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
                    const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
-                   blsh_prior prior, int32_t k, blsh_result *res, int32_t *k_used, hipStream_t s,
+                   blsh_prior prior, int32_t kj, int32_t kc, blsh_result *res, int32_t *k_used, hipStream_t s,
                    int (*check_sigs_fn)(const blsh_sigs *, int, int *, int *), int mode) {
   BatchState *b = nullptr;
   int rc = batch_state(ctx, &b);
   if (rc) return rc;
-  // --- tables per (measure, t) ---
-  std::vector<int> ks = k ? std::vector<int>{k} : std::vector<int>{16, 32, 64};
+  // --- tables per (measure, t); each measure has its own k ---
+  const int k_given[2] = {kj, kc};
   int n_max[2] = {0, 0}, row_words[2] = {0, 0};
   const blsh_sigs *sv[2] = {jac, cos};
   bool need[2] = {false, false};
@@ -723,6 +819,7 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     if (!need[me]) continue;
     if (!sv[me]) return fail(BLSH_EINVAL, "a list needs %s signatures", me ? "cosine" : "Jaccard");
     if (sv[me]->measure != me) return fail(BLSH_EINVAL, "signature set has the wrong measure");
+    const std::vector<int> ks = k_given[me] ? std::vector<int>{k_given[me]} : std::vector<int>{16, 32, 64};
     for (int kk : ks)
       if ((rc = check_sigs_fn(sv[me], kk, &n_max[me], &row_words[me]))) return rc;
   }
@@ -734,6 +831,7 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
   // --- work decomposition (does not depend on k) ---
   if ((rc = grow_lists(b, n_lists))) return rc;
   if (b->staged_valid) BLSH_HIP(hipEventSynchronize(b->staged));   // previous call's staging copies are done
+  const int64_t srp_tile = mode ? kExSrpTile : kSrpTile, mh_tile = mode ? kExMhTile : kMhTile;
   int64_t tiles = 0;
   b->h_prefix[0] = 0;
   for (int64_t i = 0; i < n_lists; ++i) {
@@ -745,7 +843,7 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     bl.measure = d.measure;
     bl.table = int32_t(std::lower_bound(ts.begin(), ts.end(), d.t) - ts.begin()) * 2 + (d.measure == BLSH_COSINE);
     bl.pad = 0;
-    const int64_t tsz = d.measure == BLSH_COSINE ? kSrpTile : kMhTile;
+    const int64_t tsz = d.measure == BLSH_COSINE ? srp_tile : mh_tile;
     tiles += (d.length + tsz - 1) / tsz;
     b->h_prefix[i + 1] = tiles;
   }
@@ -754,7 +852,12 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
                                 : std::max<int64_t>(1024, std::min<int64_t>(n_cand, int64_t(1) << 24));
   if ((rc = grow_spill(b, spill_cap))) return rc;
 
-  auto prepare = [&](int kk, int inreg) -> int {
+  auto prepare = [&](int kkj, int kkc, int inreg) -> int {
+    const int kk[2] = {kkj, kkc};
+    // the pinned staging block is read by the copy enqueued by the previous
+    // prepare (the autotuner enqueues several per call): wait for that copy
+    // before rewriting the block
+    BLSH_HIP(hipEventSynchronize(b->staged));
     BatchBlock &B = *b->h_block;
     std::memset(&B, 0, sizeof(B));
     B.lists = b->d_lists;
@@ -769,8 +872,8 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     for (size_t ti = 0; ti < ts.size(); ++ti)
       for (int me = 0; me < 2; ++me) {
         if (!need[me]) continue;
-        const int L = n_max[me] / kk;
-        TableKey key{me, ts[ti], eps, delta, gamma, me ? 1.0 : prior.alpha, me ? 1.0 : prior.beta, kk, L, 0};
+        const int L = n_max[me] / kk[me];
+        TableKey key{me, ts[ti], eps, delta, gamma, me ? 1.0 : prior.alpha, me ? 1.0 : prior.beta, kk[me], L, 0};
         const uint32_t *dt = nullptr;
         int r2 = get_table(ctx, key, nullptr, &dt, s);
         if (r2) return r2;
@@ -799,55 +902,84 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
   BLSH_HIP(hipMemcpyAsync(b->d_lists, b->h_lists, n_lists * sizeof(BatchList), hipMemcpyHostToDevice, s));
   BLSH_HIP(hipMemcpyAsync(b->d_prefix, b->h_prefix, (n_lists + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
 
-  auto run = [&](int kk, int inreg, int bpc) -> int {
-    int r2 = prepare(kk, inreg);
+  auto run = [&](const BatchState::Choice &c) -> int {
+    int r2 = prepare(c.kj, c.kc, c.inreg);
     if (r2) return r2;
-    const int grid1 = std::max(1, ctx->n_cu * bpc);
+    const int grid1 = std::max(1, ctx->n_cu * c.bpc);
     const int grid2 = std::max(1, ctx->n_cu * 4);
     hipGraphExec_t ex;
-    if ((r2 = get_graph(b, mode, kk, grid1, grid2, &ex))) return r2;
+    if ((r2 = get_graph(b, mode, c.kj, c.kc, grid1, grid2, &ex))) return r2;
     LaunchScope ls(ctx, s, mode ? "batched_exhaustive_graph" : "batched_graph");
     BLSH_HIP(hipGraphLaunch(ex, s));
     return BLSH_OK;
   };
 
-  BatchState::Choice ch{k ? k : 32, 2, 4};
-  if (k == 0 && mode == 0) {
-    // autotune key: batch shape (the choice is cached per context)
+  // k of a measure no list uses is irrelevant: 32
+  BatchState::Choice ch{kj ? kj : 32, kc ? kc : 32, 2, 8};
+  if ((kj == 0 || kc == 0) && mode == 0) {
+    // autotune (cached per context and batch shape): each free k in turn with
+    // the other fixed (the two measures' tiles share the grid but not their
+    // work), then in-register levels x blocks per CU at the chosen pair
     std::vector<int64_t> key{n_lists, n_cand >> 16, int64_t(need[0]), int64_t(need[1]), n_max[0], n_max[1],
-                             int64_t(ts.size())};
+                             int64_t(ts.size()), kj, kc};
     auto it = b->tuned.find(key);
     if (it != b->tuned.end()) {
       ch = it->second;
     } else {
-      hipEvent_t e0, e1;
-      BLSH_HIP(hipEventCreate(&e0));
-      BLSH_HIP(hipEventCreate(&e1));
+      struct EventPair {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~EventPair() {
+          for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+        }
+      } ev;
+      BLSH_HIP(hipEventCreate(&ev.e[0]));
+      BLSH_HIP(hipEventCreate(&ev.e[1]));
+      hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
+      auto time_of = [&](const BatchState::Choice &c, float *ms) -> int {
+        int r2 = run(c);                                   // warm (tables, graph)
+        if (r2) return r2;
+        BLSH_HIP(hipEventRecord(e0, s));
+        if ((r2 = run(c))) return r2;
+        BLSH_HIP(hipEventRecord(e1, s));
+        BLSH_HIP(hipEventSynchronize(e1));
+        BLSH_HIP(hipEventElapsedTime(ms, e0, e1));
+        return BLSH_OK;
+      };
+      for (int me = 0; me < 2; ++me) {
+        if (k_given[me] || !need[me]) continue;
+        float best = 1e30f;
+        BatchState::Choice pick = ch;
+        for (int kk : {16, 32, 64}) {
+          BatchState::Choice c = ch;
+          (me ? c.kc : c.kj) = kk;
+          float ms = 0.f;
+          if ((rc = time_of(c, &ms))) return rc;
+          if (ms < best) { best = ms; pick = c; }
+        }
+        ch = pick;
+      }
       float best = 1e30f;
-      for (int kk : {16, 32, 64})
-        for (int inreg : {1, 2, 4})
-          for (int bpc : {2, 4, 8}) {
-            if ((rc = run(kk, inreg, bpc))) return rc;      // warm (tables, graph)
-            BLSH_HIP(hipEventRecord(e0, s));
-            if ((rc = run(kk, inreg, bpc))) return rc;
-            BLSH_HIP(hipEventRecord(e1, s));
-            BLSH_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            BLSH_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; ch = BatchState::Choice{kk, inreg, bpc}; }
-          }
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      BatchState::Choice pick = ch;
+      for (int inreg : {1, 2, 4})
+        for (int bpc : {2, 4, 8}) {
+          BatchState::Choice c = ch;
+          c.inreg = inreg;
+          c.bpc = bpc;
+          float ms = 0.f;
+          if ((rc = time_of(c, &ms))) return rc;
+          if (ms < best) { best = ms; pick = c; }
+        }
+      ch = pick;
       b->tuned[key] = ch;
     }
-  } else {
-    ch.k = k;
   }
   if (ctx->tuning.batch_inreg > 0) ch.inreg = ctx->tuning.batch_inreg;
   if (ctx->tuning.batch_blocks_per_cu > 0) ch.bpc = ctx->tuning.batch_blocks_per_cu;
-  if ((rc = run(ch.k, ch.inreg, ch.bpc))) return rc;
-  if (k_used) *k_used = ch.k;
-  ctx->tuning.last_batch_k = ch.k;
+  if ((rc = run(ch))) return rc;
+  if (k_used) { k_used[0] = ch.kj; k_used[1] = ch.kc; }
+  ctx->tuning.last_batch_k_jaccard = ch.kj;
+  ctx->tuning.last_batch_k_cosine = ch.kc;
   ctx->tuning.last_batch_inreg = ch.inreg;
   ctx->tuning.last_batch_blocks_per_cu = ch.bpc;
   return BLSH_OK;

@@ -117,6 +117,17 @@ __device__ inline bool fetch_candidate(const VerifyArgs &a, int64_t c, uint32_t 
   return xi < a.n_obj && yi < a.n_obj;
 }
 
+// cos(x) for x in [0, pi/2] from its Taylor series through x^24 (truncation
+// below (pi/2)^26 / 26! < 2e-21), in Horner form: a few registers, no range
+// reduction.
+__device__ inline double cos_quarter(double x) {
+  const double x2 = x * x;
+  double c = 1.0;
+#pragma unroll
+  for (int i = 12; i >= 1; --i) c = 1.0 - c * x2 / double((2 * i - 1) * (2 * i));
+  return c;
+}
+
 // S_hat for an emitted pair (Section 3 eqn map; Section 4.1 Beta mode; Section 4.2 r2c(m/n)).
 __device__ inline float map_estimate(int measure, int m, int n, double alpha, double beta) {
   if (measure == BLSH_JACCARD) {
@@ -126,7 +137,7 @@ __device__ inline float map_estimate(int measure, int m, int n, double alpha, do
   }
   double r = double(m) / double(n);
   r = r < 0.5 ? 0.5 : r;
-  return float(cos(3.14159265358979323846 * (1.0 - r)));
+  return float(cos_quarter(3.14159265358979323846 * (1.0 - r)));   // r2c: cos(pi (1 - r)), r in [0.5, 1]
 }
 
 __device__ inline double tab_f64(const uint32_t *tab, int w) {

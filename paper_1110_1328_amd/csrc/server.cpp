@@ -37,7 +37,7 @@
 namespace blsh {
 int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
                    const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
-                   blsh_prior prior, int32_t k, blsh_result *res, int32_t *k_used, hipStream_t s,
+                   blsh_prior prior, int32_t kj, int32_t kc, blsh_result *res, int32_t *k_used, hipStream_t s,
                    int (*check_sigs_fn)(const blsh_sigs *, int, int *, int *), int mode);
 int check_sigs_public(const blsh_sigs *s, int k, int *n_max_out, int *row_words);
 }  // namespace blsh
@@ -184,7 +184,8 @@ int launch_iteration(blsh_server *S, Iteration &it, std::vector<Request *> &act)
   const blsh_sigs *jac = S->index.measure == BLSH_JACCARD ? &S->index : nullptr;
   const blsh_sigs *cos = S->index.measure == BLSH_COSINE ? &S->index : nullptr;
   int rc = verify_batched(S->ctx, it.lists.data(), int64_t(it.lists.size()), S->d_arena, S->arena.cap, jac, cos,
-                          S->cfg.epsilon, S->cfg.delta, S->cfg.gamma, S->cfg.prior, S->cfg.k, &res, nullptr, S->stream,
+                          S->cfg.epsilon, S->cfg.delta, S->cfg.gamma, S->cfg.prior, S->cfg.k, S->cfg.k, &res, nullptr,
+                          S->stream,
                           check_sigs_public, 0);
   if (rc) return rc;
   if (hipEventRecord(it.done, S->stream) != hipSuccess) return BLSH_EDEVICE;

@@ -49,6 +49,8 @@ def workload():
 
 
 def oracle_batched(w, k):
+    """k: one value for both measures or (k_jaccard, k_cosine)."""
+    kj, kc = (k, k) if isinstance(k, int) else k
     n = len(w["cand"])
     dec = np.zeros(n, np.uint8)
     lvl = np.zeros(n, np.int16)
@@ -59,6 +61,7 @@ def oracle_batched(w, k):
         if s == e:
             continue
         sig = w["sj"] if w["meas"][i] == 0 else w["sc"]
+        k = kj if w["meas"][i] == 0 else kc
         L = (256 if w["meas"][i] == 0 else 1024) // k
         x = np.full(e - s, w["queries"][i], np.uint32)
         r = R.verify(x, w["cand"][s:e], int(w["meas"][i]), sig, k, L, float(w["ts"][i]), EPS, DELTA, GAMMA)
@@ -86,15 +89,20 @@ def check(got, want):
     np.testing.assert_allclose(got["acc_val"], want["shat"][acc], atol=1e-6)
 
 
-@pytest.mark.parametrize("k", [16, 32, 64])
+@pytest.mark.parametrize("k", [16, 32, 64, (16, 64), (64, 16)])
 def test_batched_matches_oracle(ctx, workload, k):
-    print("batched k=%d" % k, flush=True)
+    """Every k (one per measure or a pair), word-major and object-major
+    cosine signatures (the latter read 128 hashes per gather), several
+    in-register depths before the survivor queue."""
+    print("batched k=%s" % (k,), flush=True)
     want = oracle_batched(workload, k)
-    for inreg in (1, 3, 64):
-        P.bayeslsh_set_tuning(ctx, batch_inreg=inreg, batch_blocks_per_cu=2)
-        kk, got = run_batched(ctx, workload, k)
-        assert kk == k
-        check(got, want)
+    kp = (k, k) if isinstance(k, int) else k
+    for layout in (P.WORD_MAJOR, P.OBJECT_MAJOR):
+        for inreg in (1, 3, 64):
+            P.bayeslsh_set_tuning(ctx, batch_inreg=inreg, batch_blocks_per_cu=2)
+            kk, got = run_batched(ctx, workload, k, layout=layout)
+            assert kk == kp
+            check(got, want)
     P.bayeslsh_set_tuning(ctx)
     assert len(set(want["decision"].tolist())) == 3
 
@@ -125,12 +133,15 @@ def test_batched_graph_replays(ctx, workload):
 def test_batched_autotune(ctx, workload):
     print("batched autotune", flush=True)
     kk, got = run_batched(ctx, workload, 0)
-    assert kk in (16, 32, 64)
+    assert kk[0] in (16, 32, 64) and kk[1] in (16, 32, 64)
     t = P.bayeslsh_get_tuning(ctx)
-    assert t["last_batch_k"] == kk and t["last_batch_inreg"] in (1, 2, 4)
+    assert (t["last_batch_k_jaccard"], t["last_batch_k_cosine"]) == kk and t["last_batch_inreg"] in (1, 2, 4)
     check(got, oracle_batched(workload, kk))
     kk2, _ = run_batched(ctx, workload, 0)   # cached choice: same k
     assert kk2 == kk
+    kk3, got3 = run_batched(ctx, workload, (32, 0))   # Jaccard fixed, cosine tuned
+    assert kk3[0] == 32 and kk3[1] in (16, 32, 64)
+    check(got3, oracle_batched(workload, kk3))
 
 
 def test_batched_bad_query_and_invalid_lists(ctx, workload):
@@ -157,9 +168,9 @@ def test_batched_bad_query_and_invalid_lists(ctx, workload):
                                   EPS, DELTA, GAMMA, (1, 1), 32, res)
 
 
-@pytest.mark.parametrize("k", [16, 32, 64])
+@pytest.mark.parametrize("k", [16, 32, 64, (16, 64)])
 def test_exhaustive_batched_equals_batched(ctx, workload, k):
-    print("exhaustive batched k=%d" % k, flush=True)
+    print("exhaustive batched k=%s" % (k,), flush=True)
     w = workload
     want = oracle_batched(w, k)
     lists = P.list_descs(w["meas"], w["ts"], w["queries"], w["offsets"][:-1], w["lens"])
