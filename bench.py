@@ -135,19 +135,28 @@ def copy_calibration(n_bytes=1 << 30, reps=20):
                       "GBps_read_plus_write": 2 * n_bytes / ms / 1e6}), flush=True)
 
 
-def dense_index(torch, P, ctx, layouts):
+def dense_index(torch, P, ctx, layouts, prefix=False):
     """Dense cosine index: 1M x 256 unit vectors from a 1000-component Gaussian
     mixture, 1024 SRP bits from the MFMA projection against Gaussian planes,
-    in each of the given layouts."""
+    in each of the given layouts; with prefix=True each set also carries the
+    16 B/object array of hashes 0..127 (the first 128 plane columns), checked
+    against the object-major rows when those are built."""
     from synth import generators as G
     mix = G.dense_mixture(seed=G.SEED_BASE + 4)
     planes = up(torch, G.gaussian_planes(256, 1024, G.SEED_BASE + 204))
     xd = up(torch, mix.x)
+    n = mix.x.shape[0]
+    pfx = None
+    if prefix:
+        pfx = torch.empty(n * 4, dtype=torch.int32, device="cuda").view(torch.uint32)
+        P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), planes[:, :128].contiguous(), 128, 0, P.OBJECT_MAJOR, pfx)
     sigs = []
     for layout in layouts:
-        out = torch.empty(mix.x.shape[0] * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
+        out = torch.empty(n * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
         P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), planes, 1024, 0, layout, out)
-        sigs.append(P.Signatures(out, P.COSINE, layout, mix.x.shape[0], 1024))
+        if pfx is not None and layout == P.OBJECT_MAJOR:
+            assert torch.equal(out.view(torch.int32).view(n, 32)[:, :4], pfx.view(torch.int32).view(n, 4))
+        sigs.append(P.Signatures(out, P.COSINE, layout, n, 1024, prefix=pfx))
     P.bayeslsh_sync(ctx)
     del xd
     return mix, sigs
@@ -185,9 +194,12 @@ def run_batched(args, torch, P):
                             up(torch, a), up(torch, b), sig_j)
     S_j = P.Signatures(sig_j, P.JACCARD, P.OBJECT_MAJOR, sets.n, 256)
     log("cosine index (1M x 256 dense, 1024 SRP bits)")
-    # object-major rows: BayesLSH reads 128 hashes per gather, the comparator whole rows;
-    # the word-major layout (one slab per level) is timed beside it
-    mix, (S_c, S_c_wm) = dense_index(torch, P, ctx, (P.OBJECT_MAJOR, P.WORD_MAJOR))
+    # BayesLSH: word-major slabs (one per level) plus the 16 B/object prefix array,
+    # so one gather serves the first 128 hashes; the comparator reads whole
+    # object-major rows (also timed for BayesLSH, and word-major without the prefix)
+    mix, (S_c, S_c_om) = dense_index(torch, P, ctx, (P.WORD_MAJOR, P.OBJECT_MAJOR), prefix=True)
+    S_c_wm = P.Signatures(S_c.data, P.COSINE, P.WORD_MAJOR, S_c.n_obj, 1024)
+    S_c_om = P.Signatures(S_c_om.data, P.COSINE, P.OBJECT_MAJOR, S_c_om.n_obj, 1024)
     n_lists = 4096
     rng = np.random.default_rng(G.SEED_BASE + 3)
     meas = rng.integers(0, 2, n_lists).astype(np.int32)
@@ -243,15 +255,21 @@ def run_batched(args, torch, P):
             split[name]["k%d" % kk] = timed(lambda: P.bayeslsh_verify_batched(
                 ctx, sub, cand_d, S_j if me == 0 else None, S_c if me == 1 else None, eps, delta, gamma, (1, 1),
                 kk, r2, stream), 3)
+            P.bayeslsh_set_tuning(ctx, batch_inreg=64)      # every level in registers, no survivor queue
+            split[name]["k%d_inreg_all" % kk] = timed(lambda: P.bayeslsh_verify_batched(
+                ctx, sub, cand_d, S_j if me == 0 else None, S_c if me == 1 else None, eps, delta, gamma, (1, 1),
+                kk, r2, stream), 3)
+            P.bayeslsh_set_tuning(ctx)
             if me == 1:
-                split[name]["k%d_word_major" % kk] = timed(lambda: P.bayeslsh_verify_batched(
-                    ctx, sub, cand_d, None, S_c_wm, eps, delta, gamma, (1, 1), kk, r2, stream), 3)
+                for lname, Sl in (("word_major", S_c_wm), ("object_major", S_c_om)):
+                    split[name]["k%d_%s" % (kk, lname)] = timed(lambda: P.bayeslsh_verify_batched(
+                        ctx, sub, cand_d, None, Sl, eps, delta, gamma, (1, 1), kk, r2, stream), 3)
         split[name]["exhaustive_k%d" % k_used[me]] = timed(lambda: P.bayeslsh_exhaustive_batched(
-            ctx, sub, cand_d, S_j if me == 0 else None, S_c if me == 1 else None, eps, delta, gamma, (1, 1),
+            ctx, sub, cand_d, S_j if me == 0 else None, S_c_om if me == 1 else None, eps, delta, gamma, (1, 1),
             k_used, r2, stream), 2)
         log("  %s: %s" % (name, ", ".join("%s %.2f ms" % kv for kv in split[name].items())))
     del r2
-    ms_ex = timed(lambda: P.bayeslsh_exhaustive_batched(ctx, lists, cand_d, S_j, S_c, eps, delta, gamma, (1, 1),
+    ms_ex = timed(lambda: P.bayeslsh_exhaustive_batched(ctx, lists, cand_d, S_j, S_c_om, eps, delta, gamma, (1, 1),
                                                         k_used, res_ex, stream), max(2, steps // 3))
     log("exhaustive batched: %.3f ms" % ms_ex)
     same = bool(torch.equal(res.code[:n], res_ex.code[:n]))
@@ -271,7 +289,7 @@ def run_batched(args, torch, P):
         "higher_is_better": True, "dtype": "u32", "data": "synthetic",
         "config": {"workload": "batched: 4096 lists, lengths 10^U(2,6), measure ~ Bernoulli(1/2), t in {0.5,0.7,0.9}; "
                                "Jaccard: 1M planted-group sets, 256 minhashes; cosine: 1M x 256 Gaussian-mixture "
-                               "vectors, 1024 SRP bits (object-major rows); eps=0.03, delta=0.05, gamma=0.03",
+                               "vectors, 1024 SRP bits (word-major + 128-bit prefix array; the comparator reads object-major rows); eps=0.03, delta=0.05, gamma=0.03",
                    "n_candidates": n, "n_jaccard": int(len(cj)), "n_cosine": int(len(cc)),
                    "k_jaccard": k_used[0], "k_cosine": k_used[1], "inreg_levels": tune["last_batch_inreg"],
                    "blocks_per_cu": tune["last_batch_blocks_per_cu"]},
@@ -292,7 +310,7 @@ def run_serving(args, torch, P):
     from synth import generators as G
     ctx = P.bayeslsh_create(0)
     log("cosine index (1M x 256 dense, 1024 SRP bits)")
-    mix, (S,) = dense_index(torch, P, ctx, (P.WORD_MAJOR,))
+    mix, (S,) = dense_index(torch, P, ctx, (P.WORD_MAJOR,), prefix=True)
     nq = args.queries
     log("%d queries" % nq)
     rng = np.random.default_rng(G.SEED_BASE + 6)

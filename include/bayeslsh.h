@@ -99,6 +99,14 @@ typedef struct {
   int64_t n_obj;
   int32_t n_hashes;      /* hashes stored per object (SRP: multiple of 32)            */
   int32_t n_max;         /* hashes verification may use, 0 = n_hashes; multiple of k   */
+  const uint32_t *prefix; /* SRP, optional (NULL = none): hashes 0..127 of every object
+                             again, object-major, 4 words per object, 16-byte aligned
+                             (n_hashes >= 128).  The verification kernels then read a
+                             candidate's first 128 hashes with one 16-byte gather from
+                             this 16 B/object array, and later hashes from `data`.  The
+                             caller keeps it equal to the first 128 hashes of `data`
+                             (bayeslsh_srp_sigs with n_bits = 128 and the same seed or
+                             the first 128 plane columns writes it).                  */
 } blsh_sigs;
 
 typedef struct {

@@ -28,7 +28,7 @@ class Prior(C.Structure):
 
 class Sigs(C.Structure):
     _fields_ = [("measure", C.c_int), ("layout", C.c_int), ("data", p), ("n_obj", C.c_int64),
-                ("n_hashes", C.c_int32), ("n_max", C.c_int32)]
+                ("n_hashes", C.c_int32), ("n_max", C.c_int32), ("prefix", p)]
 
 
 class Candidates(C.Structure):

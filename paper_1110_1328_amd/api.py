@@ -80,13 +80,20 @@ class Signatures:
     n_obj: int
     n_hashes: int
     n_max: int = 0
+    prefix: torch.Tensor = None   # SRP: optional [n_obj][4] words = hashes 0..127 of every object
 
     def struct(self):
-        return _cached(self, self._build, self.data, self.measure, self.layout, self.n_obj, self.n_hashes, self.n_max)
+        return _cached(self, self._build, self.data, self.measure, self.layout, self.n_obj, self.n_hashes, self.n_max,
+                       self.prefix)
 
     def _build(self):
         _dev(self.data, torch.int32 if self.data.dtype == torch.int32 else torch.uint32, "signature data")
-        return A.Sigs(self.measure, self.layout, _p(self.data), self.n_obj, self.n_hashes, self.n_max)
+        if self.prefix is not None:
+            _dev(self.prefix, torch.int32 if self.prefix.dtype == torch.int32 else torch.uint32, "signature prefix")
+            if self.prefix.numel() < 4 * self.n_obj:
+                raise ValueError("signature prefix holds %d words for %d objects" % (self.prefix.numel(), self.n_obj))
+        return A.Sigs(self.measure, self.layout, _p(self.data), self.n_obj, self.n_hashes, self.n_max,
+                      _p(self.prefix))
 
 
 @dataclass

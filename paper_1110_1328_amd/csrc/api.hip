@@ -141,8 +141,11 @@ static int check_sigs(const blsh_sigs *s, int k, int *n_max_out, int *row_words)
   if (s->measure == BLSH_COSINE) {
     if (s->n_hashes % 32) return fail(BLSH_EINVAL, "SRP signatures: n_hashes must be a multiple of 32");
     if (s->layout != BLSH_OBJECT_MAJOR && s->layout != BLSH_WORD_MAJOR) return fail(BLSH_EINVAL, "bad layout");
+    if (s->prefix && (s->n_hashes < 128 || (uintptr_t(s->prefix) & 15)))
+      return fail(BLSH_EINVAL, "SRP prefix: needs n_hashes >= 128 and 16-byte alignment");
     *row_words = s->n_hashes / 32;
   } else {
+    if (s->prefix) return fail(BLSH_EINVAL, "a prefix array is for SRP signatures only");
     if (s->layout != BLSH_OBJECT_MAJOR) return fail(BLSH_EINVAL, "minhash signatures must be OBJECT_MAJOR");
     if (s->n_hashes % 4) return fail(BLSH_EINVAL, "minhash signatures: n_hashes must be a multiple of 4");
     if (uintptr_t(s->data) & 15) return fail(BLSH_EINVAL, "minhash signatures must be 16-byte aligned");
@@ -284,6 +287,16 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   a.sig = sigs->data;
   a.n_obj = sigs->n_obj;
   a.row_words = row_words;
+  // first 128 hashes in one 16-byte gather: the caller's prefix array, or
+  // object-major rows that a 16-byte load can start
+  if (sigs->measure == BLSH_COSINE && sigs->prefix) {
+    a.pfx = sigs->prefix;
+    a.pfx_stride = 4;
+  } else if (sigs->measure == BLSH_COSINE && sigs->layout == BLSH_OBJECT_MAJOR && row_words % 4 == 0 &&
+             (uintptr_t(sigs->data) & 15) == 0) {
+    a.pfx = sigs->data;
+    a.pfx_stride = row_words;
+  }
   a.table = dtab;
   a.n_levels = n_levels;
   a.measure = sigs->measure;

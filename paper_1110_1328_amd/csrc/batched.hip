@@ -36,6 +36,7 @@ constexpr int kSrpTile = 256;      // phase 1: candidates per SRP wave tile (64 
 constexpr int kMhTile = 64;        // phase 1: candidates per minhash wave tile (one per lane)
 constexpr int kExSrpTile = 1024;   // comparator: candidates per SRP block tile
 constexpr int kExMhTile = 256;     // comparator: candidates per minhash block tile
+constexpr int kSpillShards = 8;    // survivor queue slices per measure, each with its own counter
 
 struct BatchList {
   int64_t offset;
@@ -51,6 +52,8 @@ struct SigView {
   int64_t n_obj;
   int32_t row_words;
   int32_t word_major;
+  const uint32_t *pfx;          // SRP: hashes 0..127 of object i at pfx + i * pfx_stride, or null
+  int64_t pfx_stride;
 };
 
 struct BatchBlock {
@@ -69,7 +72,7 @@ struct BatchBlock {
   int64_t *n_acc;
   uint16_t *m_dbg;
   int32_t *status;
-  unsigned long long *counters; // [0] tile counter, [1] spill count Jaccard, [2] spill count cosine
+  unsigned long long *counters; // [1 + measure * kSpillShards + shard]: survivor count of a queue slice
   uint4 *spill[2];
   int64_t spill_cap;
   int32_t inreg_levels;
@@ -133,19 +136,42 @@ __device__ inline void emit_block(const BatchBlock &B, bool pred, int64_t idx, f
   }
 }
 
-// Reserve spill slots for the lanes with `pred`; returns whether this lane got one.
-__device__ inline bool spill_push(const BatchBlock &B, int meas, bool pred, uint4 e) {
-  const uint64_t mask = __ballot(pred);
-  if (mask == 0) return false;
-  const int leader = __ffsll((unsigned long long)mask) - 1;
+// Survivor queue of a measure: kSpillShards slices of spill_cap / kSpillShards
+// entries, slice = blockIdx mod kSpillShards, so the reservations of the grid
+// spread over several counters.  One tile's survivors (bit p of `want`: the
+// lane's candidate p) take one atomic; returns the bits whose entry was stored
+// (the others found the slice full and continue in registers).  Called by all
+// lanes of the wave.
+template <int P>
+__device__ inline uint32_t spill_tile(const BatchBlock &B, int meas, uint32_t want, const uint4 *e) {
+  uint64_t mask[P];
+  uint32_t total = 0;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    mask[p] = __ballot((want >> p) & 1u);
+    total += uint32_t(__popcll(mask[p]));
+  }
+  if (total == 0) return 0;
+  const int shard = int(blockIdx.x) & (kSpillShards - 1);
   unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd(&B.counters[1 + meas], (unsigned long long)__popcll(mask));
-  base = __shfl(base, leader);
-  if (!pred) return false;
-  const unsigned long long pos = base + lanes_below(mask);
-  if (int64_t(pos) >= B.spill_cap) return false;
-  B.spill[meas][pos] = e;
-  return true;
+  if (lane_id() == 0) base = atomicAdd(&B.counters[1 + meas * kSpillShards + shard], (unsigned long long)total);
+  base = (unsigned long long)__shfl((long long)base, 0);
+  const int64_t cap = B.spill_cap / kSpillShards;
+  uint4 *slice = B.spill[meas] + shard * cap;
+  uint32_t stored = 0;
+  uint64_t off = base;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if ((want >> p) & 1u) {
+      const int64_t pos = int64_t(off + lanes_below(mask[p]));
+      if (pos < cap) {
+        slice[pos] = e[p];
+        stored |= 1u << p;
+      }
+    }
+    off += __popcll(mask[p]);
+  }
+  return stored;
 }
 
 template <int K>
@@ -181,9 +207,9 @@ __device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_
   const int64_t end = Ls.offset + Ls.length;
   const uint32_t q = Ls.query;
   const bool q_ok = q < S.n_obj;
-  // object-major rows that a 16-byte load can start: one gather per side
-  // serves the first 128 hashes
-  const bool pfx = !S.word_major && (S.row_words & 3) == 0 && (uintptr_t(S.data) & 15) == 0;
+  // a prefix view (the caller's prefix array, or object-major rows that a
+  // 16-byte load can start): one gather per side serves the first 128 hashes
+  const bool pfx = S.pfx != nullptr;
   uint32_t y[P], alive = 0, bad = 0, in = 0;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
@@ -228,11 +254,11 @@ __device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_
   if (pfx && __ballot(alive != 0)) {
     // all gathers issued before any is consumed; a lane without a live
     // candidate reads the query's own row
-    const u32x4 hq = ld_uniform(reinterpret_cast<const u32x4 *>(S.data + size_t(q) * S.row_words));
+    const u32x4 hq = ld_uniform(reinterpret_cast<const u32x4 *>(S.pfx + size_t(q) * S.pfx_stride));
     u32x4 hy[P];
 #pragma unroll
     for (int p = 0; p < P; ++p)
-      hy[p] = *reinterpret_cast<const u32x4 *>(S.data + size_t((alive >> p) & 1u ? y[p] : q) * S.row_words);
+      hy[p] = *reinterpret_cast<const u32x4 *>(S.pfx + size_t((alive >> p) & 1u ? y[p] : q) * S.pfx_stride);
     uint32_t d[P][4];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -255,15 +281,12 @@ __device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_
   }
   word_levels(j, J);
   // spill what is still undecided; what cannot be spilled continues here
-  uint32_t kept = 0;
+  if (J < L) {
+    uint4 e[P];
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const bool want = (alive >> p) & 1u;
-    const bool ok = spill_push(B, BLSH_COSINE, want,
-                               spill_entry(base + p * kWave + lane, uint32_t(list_id), m[p], uint32_t(J)));
-    if (want && !ok) kept |= 1u << p;
+    for (int p = 0; p < P; ++p) e[p] = spill_entry(base + p * kWave + lane, uint32_t(list_id), m[p], uint32_t(J));
+    alive &= ~spill_tile<P>(B, BLSH_COSINE, alive, e);
   }
-  alive = kept;
   word_levels(J, L);
   if (bad) raise_status(B.status, BLSH_EBADID);
 #pragma unroll
@@ -338,8 +361,10 @@ __device__ void minhash_tile(const BatchBlock &B, const BatchList &Ls, int32_t l
   };
   const int J = min(L, B.inreg_levels);
   for (int j = 0; j < J && __ballot(alive); ++j) level(j);
-  const bool ok = spill_push(B, BLSH_JACCARD, alive, spill_entry(c, uint32_t(list_id), m, uint32_t(J)));
-  if (ok) alive = false;
+  if (J < L) {
+    const uint4 e = spill_entry(c, uint32_t(list_id), m, uint32_t(J));
+    if (spill_tile<1>(B, BLSH_JACCARD, alive ? 1u : 0u, &e)) alive = false;
+  }
   for (int j = J; j < L && __ballot(alive); ++j) level(j);
   if (bad) raise_status(B.status, BLSH_EBADID);
   if (in) {
@@ -390,8 +415,10 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
   constexpr int G = KJ / 4;
   const BatchBlock &B = *Bp;
   // SRP survivors: one lane each
-  {
-    const int64_t n = min<int64_t>(int64_t(B.counters[1 + BLSH_COSINE]), B.spill_cap);
+  const int64_t cap = B.spill_cap / kSpillShards;
+  for (int shard = 0; shard < kSpillShards; ++shard) {
+    const int64_t n = min<int64_t>(int64_t(B.counters[1 + BLSH_COSINE * kSpillShards + shard]), cap);
+    const uint4 *slice = B.spill[BLSH_COSINE] + shard * cap;
     const SigView &S = B.sig[BLSH_COSINE];
     const int64_t stride = int64_t(gridDim.x) * kBBlock;
     for (int64_t i0 = int64_t(blockIdx.x) * kBBlock; i0 < n; i0 += stride) {
@@ -404,7 +431,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
       uint8_t code = 0;
       bool emit = false;
       if (act) {
-        const uint4 e = B.spill[BLSH_COSINE][i];
+        const uint4 e = slice[i];
         pos = int64_t(uint64_t(e.x) | (uint64_t(e.y) << 32));
         const BatchList Ls = B.lists[e.z];
         tab = B.tables[Ls.table];
@@ -428,8 +455,9 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
     }
   }
   // minhash survivors: one group of G lanes each
-  {
-    const int64_t n = min<int64_t>(int64_t(B.counters[1 + BLSH_JACCARD]), B.spill_cap);
+  for (int shard = 0; shard < kSpillShards; ++shard) {
+    const int64_t n = min<int64_t>(int64_t(B.counters[1 + BLSH_JACCARD * kSpillShards + shard]), cap);
+    const uint4 *slice = B.spill[BLSH_JACCARD] + shard * cap;
     const SigView &S = B.sig[BLSH_JACCARD];
     constexpr int PER_BLOCK = kBBlock / G;
     const int g = threadIdx.x / G, r = threadIdx.x % G;
@@ -442,7 +470,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
       int j = 0, L = 0, words = 0;
       const uint32_t *tab = nullptr;
       if (act) {
-        const uint4 e = B.spill[BLSH_JACCARD][i];
+        const uint4 e = slice[i];
         pos = int64_t(uint64_t(e.x) | (uint64_t(e.y) << 32));
         const BatchList Ls = B.lists[e.z];
         tab = B.tables[Ls.table];
@@ -666,8 +694,8 @@ __global__ __launch_bounds__(kBBlock) void k_batch_exhaustive(const BatchBlock *
 
 __global__ void k_batch_reset(const BatchBlock *__restrict__ Bp) {
   const BatchBlock &B = *Bp;
-  if (threadIdx.x < 3) B.counters[threadIdx.x] = 0;
-  if (threadIdx.x == 3) *B.n_acc = 0;
+  if (threadIdx.x < 1 + 2 * kSpillShards) B.counters[threadIdx.x] = 0;
+  if (threadIdx.x == 63) *B.n_acc = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -867,7 +895,11 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     B.cand = cand;
     for (int me = 0; me < 2; ++me) {
       if (!need[me]) continue;
-      B.sig[me] = SigView{sv[me]->data, sv[me]->n_obj, row_words[me], sv[me]->layout == BLSH_WORD_MAJOR ? 1 : 0};
+      const blsh_sigs &g = *sv[me];
+      const bool om_rows = g.layout == BLSH_OBJECT_MAJOR && row_words[me] % 4 == 0 && (uintptr_t(g.data) & 15) == 0;
+      const uint32_t *pfx = me == BLSH_COSINE ? (g.prefix ? g.prefix : (om_rows ? g.data : nullptr)) : nullptr;
+      B.sig[me] = SigView{g.data, g.n_obj, row_words[me], g.layout == BLSH_WORD_MAJOR ? 1 : 0, pfx,
+                          g.prefix ? 4 : int64_t(row_words[me])};
     }
     for (size_t ti = 0; ti < ts.size(); ++ti)
       for (int me = 0; me < 2; ++me) {
@@ -961,7 +993,7 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
       }
       float best = 1e30f;
       BatchState::Choice pick = ch;
-      for (int inreg : {1, 2, 4})
+      for (int inreg : {1, 2, 4, kMaxLevels})   // kMaxLevels: every level in registers, no queue
         for (int bpc : {2, 4, 8}) {
           BatchState::Choice c = ch;
           c.inreg = inreg;

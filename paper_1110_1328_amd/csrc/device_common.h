@@ -27,6 +27,8 @@ struct VerifyArgs {
   const uint32_t *sig;
   int64_t n_obj;
   int32_t row_words;                     // object-major row length in 32-bit words
+  const uint32_t *pfx;                   // hashes 0..127 of object i at pfx + i * pfx_stride (16 B), or null
+  int32_t pfx_stride;
   // decision table
   const uint32_t *table;
   int32_t n_levels;                      // levels run (n_max/k, or h/k for Lite)

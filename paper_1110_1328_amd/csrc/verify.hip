@@ -150,8 +150,10 @@ __device__ inline void emit_exact(const VerifyArgs &a, int64_t c, double s) {
 }
 
 // One lane per candidate, kPPT consecutive candidates per lane.
-//   PFX: object-major rows whose first 16 bytes (128 hashes) are loaded with one
-//        gather per side, so the first 128/K levels need no further round trip.
+//   PFX: the first 128 hashes of each side are loaded with one 16-byte gather
+//        (from the caller's prefix array or the start of object-major rows), so
+//        the first 128/K levels need no further round trip; later levels read
+//        `sig` in its own layout.
 //   LITE: survivors of the h-hash budget get their exact similarity right here,
 //        one survivor at a time by the whole wave (Algorithm 2).
 template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool PFX>
@@ -217,8 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
 #pragma unroll
     for (int p = 0; p < kPPT; ++p) {
       const bool ok = (alive >> p) & 1u;
-      hx[p] = *reinterpret_cast<const u32x4 *>(a.sig + size_t(ok ? xi[p] : 0u) * a.row_words);
-      hy[p] = *reinterpret_cast<const u32x4 *>(a.sig + size_t(ok ? yi[p] : 0u) * a.row_words);
+      hx[p] = *reinterpret_cast<const u32x4 *>(a.pfx + size_t(ok ? xi[p] : 0u) * a.pfx_stride);
+      hy[p] = *reinterpret_cast<const u32x4 *>(a.pfx + size_t(ok ? yi[p] : 0u) * a.pfx_stride);
     }
     uint32_t d[kPPT][4];
 #pragma unroll
@@ -604,7 +606,7 @@ static int launch_bits_kind(const VerifyArgs &a, int64_t nb, hipStream_t s) {
 
 template <int K, bool LITE>
 static int launch_bits_layout(const VerifyArgs &a, int64_t nb, bool wm, bool pfx, hipStream_t s) {
-  if (wm) return launch_bits_kind<K, LITE, true, false>(a, nb, s);
+  if (wm) return pfx ? launch_bits_kind<K, LITE, true, true>(a, nb, s) : launch_bits_kind<K, LITE, true, false>(a, nb, s);
   return pfx ? launch_bits_kind<K, LITE, false, true>(a, nb, s) : launch_bits_kind<K, LITE, false, false>(a, nb, s);
 }
 
@@ -623,8 +625,8 @@ int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool wor
   if (n <= 0) return BLSH_OK;
   if (a.measure == BLSH_COSINE) {
     const int64_t nb = blocks_for(n, int64_t(kBlock) * kPPT);
-    // object-major rows of >= 128 hashes, 16-byte aligned: one 16-byte gather per side
-    const bool pfx = !word_major && a.row_words % 4 == 0 && (uintptr_t(a.sig) & 15) == 0;
+    // the first 128 hashes in one 16-byte gather per side where a prefix view exists
+    const bool pfx = a.pfx != nullptr;
     LaunchScope ls(ctx, s, pfx ? "verify_bits_prefix" : "verify_bits");
 #define BLSH_B(KK, LL) if (k == KK && lite == LL) return launch_bits_layout<KK, LL>(a, nb, word_major, pfx, s);
     BLSH_B(16, false) BLSH_B(16, true) BLSH_B(32, false) BLSH_B(32, true) BLSH_B(64, false) BLSH_B(64, true)

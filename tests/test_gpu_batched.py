@@ -69,14 +69,28 @@ def oracle_batched(w, k):
     return dict(decision=dec, level=lvl, m=mm, shat=sh)
 
 
+PREFIX = "word-major + prefix array"
+
+
+def cosine_sigs(w, layout):
+    """The cosine signature set in a layout, or word-major slabs with a
+    separate 16 B/object array of hashes 0..127 (layout PREFIX)."""
+    if layout == PREFIX:
+        S = sigs_tensor(w["sc"], P.COSINE, P.WORD_MAJOR)
+        return P.Signatures(S.data, P.COSINE, P.WORD_MAJOR, S.n_obj, S.n_hashes,
+                            prefix=up(np.ascontiguousarray(w["sc"][:, :4])))
+    return sigs_tensor(w["sc"], P.COSINE, layout)
+
+
 def run_batched(ctx, w, k, layout=P.WORD_MAJOR):
     lists = P.list_descs(w["meas"], w["ts"], w["queries"], w["offsets"][:-1], w["lens"])
     cand = up(w["cand"])
     n = len(w["cand"])
     res = P.make_result(n, n, m_debug=True)
-    kk = P.bayeslsh_verify_batched(ctx, lists, cand, sigs_tensor(w["sj"], P.JACCARD, P.OBJECT_MAJOR),
-                                   sigs_tensor(w["sc"], P.COSINE, layout), EPS, DELTA, GAMMA, (1, 1), k, res)
-    P.bayeslsh_sync(ctx)
+    Sj, Sc = sigs_tensor(w["sj"], P.JACCARD, P.OBJECT_MAJOR), cosine_sigs(w, layout)
+    kk = P.bayeslsh_verify_batched(ctx, lists, cand, Sj, Sc, EPS, DELTA, GAMMA, (1, 1), k, res)
+    P.bayeslsh_sync(ctx)   # the signature tensors stay referenced until the work is done
+    del Sj, Sc
     return kk, decode_result(res, n)
 
 
@@ -91,13 +105,13 @@ def check(got, want):
 
 @pytest.mark.parametrize("k", [16, 32, 64, (16, 64), (64, 16)])
 def test_batched_matches_oracle(ctx, workload, k):
-    """Every k (one per measure or a pair), word-major and object-major
-    cosine signatures (the latter read 128 hashes per gather), several
-    in-register depths before the survivor queue."""
+    """Every k (one per measure or a pair); word-major, object-major (read
+    128 hashes per gather) and word-major with a prefix array for the cosine
+    signatures; several in-register depths before the survivor queue."""
     print("batched k=%s" % (k,), flush=True)
     want = oracle_batched(workload, k)
     kp = (k, k) if isinstance(k, int) else k
-    for layout in (P.WORD_MAJOR, P.OBJECT_MAJOR):
+    for layout in (P.WORD_MAJOR, P.OBJECT_MAJOR, PREFIX):
         for inreg in (1, 3, 64):
             P.bayeslsh_set_tuning(ctx, batch_inreg=inreg, batch_blocks_per_cu=2)
             kk, got = run_batched(ctx, workload, k, layout=layout)
@@ -135,7 +149,7 @@ def test_batched_autotune(ctx, workload):
     kk, got = run_batched(ctx, workload, 0)
     assert kk[0] in (16, 32, 64) and kk[1] in (16, 32, 64)
     t = P.bayeslsh_get_tuning(ctx)
-    assert (t["last_batch_k_jaccard"], t["last_batch_k_cosine"]) == kk and t["last_batch_inreg"] in (1, 2, 4)
+    assert (t["last_batch_k_jaccard"], t["last_batch_k_cosine"]) == kk and t["last_batch_inreg"] in (1, 2, 4, 64)
     check(got, oracle_batched(workload, kk))
     kk2, _ = run_batched(ctx, workload, 0)   # cached choice: same k
     assert kk2 == kk
@@ -151,8 +165,9 @@ def test_batched_bad_query_and_invalid_lists(ctx, workload):
     lists = P.list_descs(w["meas"], w["ts"], w["queries"], w["offsets"][:-1], w["lens"])
     n = len(w["cand"])
     res = P.make_result(n, n)
-    P.bayeslsh_verify_batched(ctx, lists, up(w["cand"]), sigs_tensor(w["sj"], P.JACCARD, P.OBJECT_MAJOR),
-                              sigs_tensor(w["sc"], P.COSINE, P.WORD_MAJOR), EPS, DELTA, GAMMA, (1, 1), 32, res)
+    cand = up(w["cand"])
+    Sj, Sc = sigs_tensor(w["sj"], P.JACCARD, P.OBJECT_MAJOR), sigs_tensor(w["sc"], P.COSINE, P.WORD_MAJOR)
+    P.bayeslsh_verify_batched(ctx, lists, cand, Sj, Sc, EPS, DELTA, GAMMA, (1, 1), 32, res)
     with pytest.raises(P.BayesLSHError) as e:
         P.bayeslsh_sync(ctx)
     assert e.value.code == -5
@@ -176,7 +191,8 @@ def test_exhaustive_batched_equals_batched(ctx, workload, k):
     lists = P.list_descs(w["meas"], w["ts"], w["queries"], w["offsets"][:-1], w["lens"])
     n = len(w["cand"])
     res = P.make_result(n, n, m_debug=True)
-    P.bayeslsh_exhaustive_batched(ctx, lists, up(w["cand"]), sigs_tensor(w["sj"], P.JACCARD, P.OBJECT_MAJOR),
-                                  sigs_tensor(w["sc"], P.COSINE, P.OBJECT_MAJOR), EPS, DELTA, GAMMA, (1, 1), k, res)
+    cand = up(w["cand"])
+    Sj, Sc = sigs_tensor(w["sj"], P.JACCARD, P.OBJECT_MAJOR), sigs_tensor(w["sc"], P.COSINE, P.OBJECT_MAJOR)
+    P.bayeslsh_exhaustive_batched(ctx, lists, cand, Sj, Sc, EPS, DELTA, GAMMA, (1, 1), k, res)
     P.bayeslsh_sync(ctx)
     check(decode_result(res, n), want)

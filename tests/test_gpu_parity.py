@@ -136,9 +136,10 @@ def test_verify_pairs_bit_exact(ctx, measure, k):
 @pytest.mark.parametrize("k", [16, 32, 64])
 @pytest.mark.parametrize("lite", [False, True])
 def test_layouts_and_candidate_orders(ctx, k, lite):
-    """Word-major slabs, object-major rows (16-byte prefix gathers) and
-    object-major rows at an unaligned offset (word gathers) give the oracle's
-    output on bucket-major candidates and on random pairs."""
+    """Word-major slabs, object-major rows (16-byte prefix gathers),
+    object-major rows at an unaligned offset (word gathers), and either of the
+    last two with a separate prefix array give the oracle's output on
+    bucket-major candidates and on random pairs."""
     _flush("layouts k=%d lite=%d" % (k, lite))
     n_obj, n_hashes = 6000, 1024
     sig = _calib_pairs(P.COSINE, n_obj // 2, n_hashes, 40 + k)
@@ -160,7 +161,12 @@ def test_layouts_and_candidate_orders(ctx, k, lite):
     buf = torch.zeros(om.data.numel() + 1, dtype=torch.int32, device="cuda")
     buf[1:] = om.data.reshape(-1).view(torch.int32)
     om_unaligned = P.Signatures(buf[1:].view(torch.uint32), P.COSINE, P.OBJECT_MAJOR, n_obj, n_hashes)
-    layouts = [sigs_tensor(sig, P.COSINE, P.WORD_MAJOR), om, om_unaligned]
+    # a separate 16 B/object prefix array (hashes 0..127) beside either layout
+    pfx = up(np.ascontiguousarray(sig[:, :4]))
+    wm = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR)
+    wm_pfx = P.Signatures(wm.data, P.COSINE, P.WORD_MAJOR, n_obj, n_hashes, prefix=pfx)
+    om_unaligned_pfx = P.Signatures(om_unaligned.data, P.COSINE, P.OBJECT_MAJOR, n_obj, n_hashes, prefix=pfx)
+    layouts = [wm, om, om_unaligned, wm_pfx, om_unaligned_pfx]
     for x, y in ((xb, yb), (xr, yr)):
         want = R.verify(x, y, P.COSINE, sig, k, L, T, EPS, DELTA, GAMMA, lite=lite)
         if lite:
@@ -417,6 +423,16 @@ def test_invalid_arguments_rejected(ctx):
         a.update(kw)
         with pytest.raises(P.BayesLSHError) as e:
             P.bayeslsh_verify(ctx, P.pairs(x, x), S, a["t"], a["epsilon"], DELTA, GAMMA, a["prior"], a["k"], res)
+        assert e.value.code == -1
+    # prefix arrays: SRP only, 16-byte aligned, n_hashes >= 128
+    pbuf = torch.zeros(4 * 10 + 1, dtype=torch.int32, device="cuda")
+    bad_sigs = [P.Signatures(S.data, P.COSINE, P.WORD_MAJOR, 10, 256, prefix=pbuf[1:].view(torch.uint32)),
+                P.Signatures(S.data, P.COSINE, P.WORD_MAJOR, 10, 96, prefix=pbuf[:40].view(torch.uint32)),
+                P.Signatures(up(np.zeros((10, 128), np.uint32)), P.JACCARD, P.OBJECT_MAJOR, 10, 128,
+                             prefix=pbuf[:40].view(torch.uint32))]
+    for Sb in bad_sigs:
+        with pytest.raises(P.BayesLSHError) as e:
+            P.bayeslsh_verify(ctx, P.pairs(x, x), Sb, T, EPS, DELTA, GAMMA, (1, 1), 32, res)
         assert e.value.code == -1
     S2 = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR, n_max=96)     # not a multiple of k = 64
     with pytest.raises(P.BayesLSHError):
