@@ -188,8 +188,9 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
  *           undecided candidates are compacted into a survivor queue.
  *   batch_blocks_per_cu: blocks per CU of the batched tile kernel (4 waves
  *           each; every wave runs a contiguous range of tiles).
- *   batch_spill_cap: capacity of each survivor queue; a survivor that finds
- *           the queue full keeps running in registers (same result).
+ *   batch_spill_cap: entries of each measure's survivor queue, split evenly
+ *           into one region per wave of the tile kernel; a survivor that finds
+ *           its wave's region full keeps running in registers (same result).
  *   last_batch_*: set by the library after each batched call (the autotuned
  *           or given k of each measure, in-register levels and blocks per
  *           CU); ignored by bayeslsh_set_tuning. */

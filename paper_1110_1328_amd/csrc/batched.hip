@@ -1,23 +1,24 @@
 // Batched verification of many query lists of uneven lengths in one
 // graph-launched pair of persistent kernels (Algorithm 1 per candidate).
 //
-// Phase 1 (k_batch_phase1): the batch is cut into wave tiles -- 256
-//   consecutive candidates of one SRP list (4 per lane) or 64 of one minhash
-//   list (lane l owns candidate l, a group of k/4 lanes compares each
-//   candidate's k hashes) -- and every wave of the fixed grid runs one
-//   contiguous range of tiles (no work counter, no block barrier).  The
+// Phase 1 (k_batch_phase1, one launch per measure): the batch is cut into
+//   wave tiles -- 256 consecutive candidates of one SRP list (4 per lane) or
+//   64 of one minhash list (lane l owns candidate l, a group of k/4 lanes
+//   compares each candidate's k hashes) -- and every wave of the fixed grid
+//   runs one contiguous range of tiles (no work counter, no block barrier),
+//   each XCD an eighth of every list (L2 locality of sorted ids).  The
 //   query's hashes are wave-uniform.  Each list carries its own measure and
 //   threshold, hence its own decision table, and each measure its own k.  A
 //   candidate still undecided after `inreg_levels` levels (SRP object-major
-//   rows: at least the 128 hashes one 16-byte load brings) is spilled to a
-//   per-measure survivor queue (wavefront ballot compaction); when the queue
-//   is full it simply continues in registers.
+//   rows: at least the 128 hashes one 16-byte load brings) is spilled to the
+//   wave's own region of the measure's survivor queue (ballot compaction, no
+//   atomics); when the region is full it simply continues in registers.
 // Phase 2 (k_batch_phase2): persistent blocks drain the survivor queues with
 //   every lane busy: one lane per SRP survivor, one group of k/4 lanes per
 //   minhash survivor, running the remaining levels.
 //
-// Both kernels read all their arguments from one device-resident BatchBlock,
-// so the graph that holds [reset, phase 1, phase 2] is captured once per
+// The kernels read all their arguments from one device-resident BatchBlock,
+// so the graph that holds [reset, phase 1 x 2, phase 2] is captured once per
 // (k pair, grid) and replayed for any batch: each call only refreshes the block.
 #include <algorithm>
 #include <chrono>
@@ -36,7 +37,7 @@ constexpr int kSrpTile = 256;      // phase 1: candidates per SRP wave tile (64 
 constexpr int kMhTile = 64;        // phase 1: candidates per minhash wave tile (one per lane)
 constexpr int kExSrpTile = 1024;   // comparator: candidates per SRP block tile
 constexpr int kExMhTile = 256;     // comparator: candidates per minhash block tile
-constexpr int kSpillShards = 8;    // survivor queue slices per measure, each with its own counter
+constexpr int kXcds = 8;           // phase 1: list tiles split in kXcds position ranges, one per XCD
 
 struct BatchList {
   int64_t offset;
@@ -58,7 +59,10 @@ struct SigView {
 
 struct BatchBlock {
   const BatchList *lists;
-  const int64_t *tile_prefix;   // [n_lists + 1]
+  // phase 1: [2 measures][kXcds][n_lists + 1], slice (me, x) counts the
+  // tiles [x n_t / kXcds, (x+1) n_t / kXcds) of each list of measure me (n_t
+  // tiles); comparator: [n_lists + 1]
+  const int64_t *tile_prefix;
   int64_t n_lists, n_tiles;
   const uint32_t *cand;
   SigView sig[2];               // [BLSH_JACCARD], [BLSH_COSINE]
@@ -72,9 +76,11 @@ struct BatchBlock {
   int64_t *n_acc;
   uint16_t *m_dbg;
   int32_t *status;
-  unsigned long long *counters; // [1 + measure * kSpillShards + shard]: survivor count of a queue slice
-  uint4 *spill[2];
-  int64_t spill_cap;
+  unsigned long long *counters; // unused (kept zero)
+  uint4 *spill[2];               // survivor queue per measure: spill_region entries per phase-1 wave
+  uint32_t *spill_count[2];     // entries each phase-1 wave stored in its region
+  int64_t spill_region;
+  int32_t spill_waves;          // waves of the phase-1 grid
   int32_t inreg_levels;
 };
 
@@ -103,16 +109,6 @@ __device__ inline BatchList ld_list(const BatchList *p) {
   return r;
 }
 
-// Static split of T tiles over the waves of the grid: wave w runs the tiles
-// [w T / W, (w+1) T / W).
-__device__ inline void wave_range(int64_t T, int64_t &begin, int64_t &end) {
-  const int64_t W = int64_t(gridDim.x) * (kBBlock / kWave);
-  const int64_t w = int64_t(blockIdx.x) * (kBBlock / kWave) +
-                    int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
-  begin = w * T / W;
-  end = (w + 1) * T / W;
-}
-
 template <int G, int... S>
 __device__ inline void group_bcast_all(uint32_t v, uint32_t *out, std::integer_sequence<int, S...>) {
   ((out[S] = group_bcast<G, S>(v)), ...);
@@ -136,40 +132,28 @@ __device__ inline void emit_block(const BatchBlock &B, bool pred, int64_t idx, f
   }
 }
 
-// Survivor queue of a measure: kSpillShards slices of spill_cap / kSpillShards
-// entries, slice = blockIdx mod kSpillShards, so the reservations of the grid
-// spread over several counters.  One tile's survivors (bit p of `want`: the
-// lane's candidate p) take one atomic; returns the bits whose entry was stored
-// (the others found the slice full and continue in registers).  Called by all
-// lanes of the wave.
+// Survivor queue of a measure: phase-1 wave w owns the entries
+// [w R, (w+1) R) (R = spill_region) and keeps its fill `n` in a register, so
+// spilling takes a ballot and no atomic.  Bit p of `want`: the lane's
+// candidate p; returns the bits whose entry was stored (the others found the
+// region full and continue in registers).  Called by all lanes of the wave.
 template <int P>
-__device__ inline uint32_t spill_tile(const BatchBlock &B, int meas, uint32_t want, const uint4 *e) {
-  uint64_t mask[P];
-  uint32_t total = 0;
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    mask[p] = __ballot((want >> p) & 1u);
-    total += uint32_t(__popcll(mask[p]));
-  }
-  if (total == 0) return 0;
-  const int shard = int(blockIdx.x) & (kSpillShards - 1);
-  unsigned long long base = 0;
-  if (lane_id() == 0) base = atomicAdd(&B.counters[1 + meas * kSpillShards + shard], (unsigned long long)total);
-  base = (unsigned long long)__shfl((long long)base, 0);
-  const int64_t cap = B.spill_cap / kSpillShards;
-  uint4 *slice = B.spill[meas] + shard * cap;
+__device__ inline uint32_t spill_tile(const BatchBlock &B, int meas, int64_t wave, uint32_t &n, uint32_t want,
+                                      const uint4 *e) {
+  const int64_t R = B.spill_region;
+  uint4 *region = B.spill[meas] + wave * R;
   uint32_t stored = 0;
-  uint64_t off = base;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
+    const uint64_t mask = __ballot((want >> p) & 1u);
     if ((want >> p) & 1u) {
-      const int64_t pos = int64_t(off + lanes_below(mask[p]));
-      if (pos < cap) {
-        slice[pos] = e[p];
+      const int64_t pos = int64_t(n) + lanes_below(mask);
+      if (pos < R) {
+        region[pos] = e[p];
         stored |= 1u << p;
       }
     }
-    off += __popcll(mask[p]);
+    n = uint32_t(min<int64_t>(R, int64_t(n) + __popcll(mask)));
   }
   return stored;
 }
@@ -198,7 +182,7 @@ __device__ inline uint32_t prefix_agree(const uint32_t *d, int j) {
 // 256 consecutive candidates of one SRP list: candidate base + 64 p + lane.
 template <int K>
 __device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_id, int64_t base,
-                         const uint32_t *tab, int L) {
+                         const uint32_t *tab, int L, int64_t wave, uint32_t &n_spill) {
   constexpr int P = kSrpTile / kWave;
   constexpr int PL = 128 / K;          // levels held by a 128-bit prefix
   const SigView S = B.sig[BLSH_COSINE];
@@ -285,7 +269,7 @@ __device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_
     uint4 e[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) e[p] = spill_entry(base + p * kWave + lane, uint32_t(list_id), m[p], uint32_t(J));
-    alive &= ~spill_tile<P>(B, BLSH_COSINE, alive, e);
+    alive &= ~spill_tile<P>(B, BLSH_COSINE, wave, n_spill, alive, e);
   }
   word_levels(J, L);
   if (bad) raise_status(B.status, BLSH_EBADID);
@@ -310,7 +294,7 @@ __device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_
 // the group's rows loaded before any comparison.
 template <int K>
 __device__ void minhash_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_id, int64_t base,
-                             const uint32_t *tab, int L) {
+                             const uint32_t *tab, int L, int64_t wave, uint32_t &n_spill) {
   constexpr int G = K / 4;
   constexpr int CH = G < 8 ? G : 8;      // rows in flight per pass
   const SigView S = B.sig[BLSH_JACCARD];
@@ -363,7 +347,7 @@ __device__ void minhash_tile(const BatchBlock &B, const BatchList &Ls, int32_t l
   for (int j = 0; j < J && __ballot(alive); ++j) level(j);
   if (J < L) {
     const uint4 e = spill_entry(c, uint32_t(list_id), m, uint32_t(J));
-    if (spill_tile<1>(B, BLSH_JACCARD, alive ? 1u : 0u, &e)) alive = false;
+    if (spill_tile<1>(B, BLSH_JACCARD, wave, n_spill, alive ? 1u : 0u, &e)) alive = false;
   }
   for (int j = J; j < L && __ballot(alive); ++j) level(j);
   if (bad) raise_status(B.status, BLSH_EBADID);
@@ -385,26 +369,54 @@ __device__ inline int64_t list_of_tile(const int64_t *prefix, int64_t n_lists, i
   return lo;
 }
 
+// The tiles [t0, t1) of slice x, run in order by one wave.
 template <int KJ, int KC>
-__global__ __launch_bounds__(kBBlock) void k_batch_phase1(const BatchBlock *__restrict__ Bp) {
-  const BatchBlock &B = *Bp;
-  int64_t t0, t1;
-  wave_range(B.n_tiles, t0, t1);
-  if (t0 >= t1) return;
-  int64_t l = list_of_tile(B.tile_prefix, B.n_lists, t0);
-  int64_t first = ld_uniform(B.tile_prefix + l), next = ld_uniform(B.tile_prefix + l + 1);
+__device__ inline void phase1_range(const BatchBlock &B, int x, const int64_t *prefix, int64_t t0, int64_t t1,
+                                    int64_t wave, uint32_t &n_spill_j, uint32_t &n_spill_c) {
+  int64_t l = list_of_tile(prefix, B.n_lists, t0);
+  int64_t first = ld_uniform(prefix + l), next = ld_uniform(prefix + l + 1);
   for (int64_t t = t0; t < t1; ++t) {
-    while (t >= next) {   // empty lists have no tiles
+    while (t >= next) {   // lists with no tiles in this slice
       ++l;
       first = next;
-      next = ld_uniform(B.tile_prefix + l + 1);
+      next = ld_uniform(prefix + l + 1);
     }
     const BatchList Ls = ld_list(B.lists + l);
     const uint32_t *tab = ld_uniform(B.tables + Ls.table);
     const int L = ld_uniform(B.n_levels + Ls.table);
-    if (Ls.measure == BLSH_COSINE) srp_tile<KC>(B, Ls, int32_t(l), Ls.offset + (t - first) * kSrpTile, tab, L);
-    else minhash_tile<KJ>(B, Ls, int32_t(l), Ls.offset + (t - first) * kMhTile, tab, L);
+    const int64_t tsz = Ls.measure == BLSH_COSINE ? kSrpTile : kMhTile;
+    const int64_t tile = (int64_t(x) * ((Ls.length + tsz - 1) / tsz)) / kXcds + (t - first);
+    if (Ls.measure == BLSH_COSINE)
+      srp_tile<KC>(B, Ls, int32_t(l), Ls.offset + tile * kSrpTile, tab, L, wave, n_spill_c);
+    else
+      minhash_tile<KJ>(B, Ls, int32_t(l), Ls.offset + tile * kMhTile, tab, L, wave, n_spill_j);
   }
+}
+
+// Blocks are dealt round-robin over the XCDs (block b runs on XCD b mod 8),
+// each with its own L2.  Phase 1 gives the blocks of XCD x the x-th eighth
+// (by position) of every list's tiles: lists hold sorted candidate ids, so an
+// XCD touches about an eighth of the signature rows and its L2 holds them.
+// Within an XCD every wave runs a contiguous range of that XCD's tiles.  One
+// launch runs the lists of one measure (`meas`), so the streaming minhash rows
+// do not evict the SRP rows from L2.
+template <int KJ, int KC>
+__global__ __launch_bounds__(kBBlock) void k_batch_phase1(const BatchBlock *__restrict__ Bp, int meas) {
+  const BatchBlock &B = *Bp;
+  const int x = int(blockIdx.x) % kXcds;
+  const int64_t nbx = (int64_t(gridDim.x) - x + kXcds - 1) / kXcds;      // blocks on this XCD (grid >= kXcds)
+  const int64_t wx = int64_t(blockIdx.x / kXcds) * (kBBlock / kWave) +
+                     int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
+  const int64_t Wx = nbx * (kBBlock / kWave);
+  const int64_t *prefix = B.tile_prefix + int64_t(meas * kXcds + x) * (B.n_lists + 1);
+  const int64_t Tx = ld_uniform(prefix + B.n_lists);
+  const int64_t t0 = wx * Tx / Wx, t1 = (wx + 1) * Tx / Wx;
+  const int64_t wave = int64_t(blockIdx.x) * (kBBlock / kWave) +
+                       int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
+  uint32_t n_spill_j = 0, n_spill_c = 0;
+  if (t0 < t1) phase1_range<KJ, KC>(B, x, prefix, t0, t1, wave, n_spill_j, n_spill_c);
+  if (lane_id() == 0)   // every wave of the grid reports its fill, 0 included
+    B.spill_count[meas][wave] = meas == BLSH_COSINE ? n_spill_c : n_spill_j;
 }
 
 // ---------------------------------------------------------------------------
@@ -414,14 +426,14 @@ template <int KJ, int KC>
 __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__restrict__ Bp) {
   constexpr int G = KJ / 4;
   const BatchBlock &B = *Bp;
+  // block b drains the regions of phase-1 waves b, b + grid, ...
+  const int64_t R = B.spill_region;
   // SRP survivors: one lane each
-  const int64_t cap = B.spill_cap / kSpillShards;
-  for (int shard = 0; shard < kSpillShards; ++shard) {
-    const int64_t n = min<int64_t>(int64_t(B.counters[1 + BLSH_COSINE * kSpillShards + shard]), cap);
-    const uint4 *slice = B.spill[BLSH_COSINE] + shard * cap;
+  for (int64_t w = blockIdx.x; w < B.spill_waves; w += gridDim.x) {
+    const int64_t n = B.spill_count[BLSH_COSINE][w];
+    const uint4 *slice = B.spill[BLSH_COSINE] + w * R;
     const SigView &S = B.sig[BLSH_COSINE];
-    const int64_t stride = int64_t(gridDim.x) * kBBlock;
-    for (int64_t i0 = int64_t(blockIdx.x) * kBBlock; i0 < n; i0 += stride) {
+    for (int64_t i0 = 0; i0 < n; i0 += kBBlock) {
       const int64_t i = i0 + threadIdx.x;
       bool act = i < n;
       int64_t pos = 0;
@@ -455,14 +467,13 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
     }
   }
   // minhash survivors: one group of G lanes each
-  for (int shard = 0; shard < kSpillShards; ++shard) {
-    const int64_t n = min<int64_t>(int64_t(B.counters[1 + BLSH_JACCARD * kSpillShards + shard]), cap);
-    const uint4 *slice = B.spill[BLSH_JACCARD] + shard * cap;
+  for (int64_t w = blockIdx.x; w < B.spill_waves; w += gridDim.x) {
+    const int64_t n = B.spill_count[BLSH_JACCARD][w];
+    const uint4 *slice = B.spill[BLSH_JACCARD] + w * R;
     const SigView &S = B.sig[BLSH_JACCARD];
     constexpr int PER_BLOCK = kBBlock / G;
     const int g = threadIdx.x / G, r = threadIdx.x % G;
-    const int64_t stride = int64_t(gridDim.x) * PER_BLOCK;
-    for (int64_t i0 = int64_t(blockIdx.x) * PER_BLOCK; i0 < n; i0 += stride) {
+    for (int64_t i0 = 0; i0 < n; i0 += PER_BLOCK) {
       const int64_t i = i0 + g;
       const bool act = i < n;
       int64_t pos = 0;
@@ -694,8 +705,7 @@ __global__ __launch_bounds__(kBBlock) void k_batch_exhaustive(const BatchBlock *
 
 __global__ void k_batch_reset(const BatchBlock *__restrict__ Bp) {
   const BatchBlock &B = *Bp;
-  if (threadIdx.x < 1 + 2 * kSpillShards) B.counters[threadIdx.x] = 0;
-  if (threadIdx.x == 63) *B.n_acc = 0;
+  if (threadIdx.x == 0) *B.n_acc = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -710,6 +720,8 @@ struct BatchState {
   unsigned long long *d_counters = nullptr;
   uint4 *d_spill[2] = {nullptr, nullptr};
   int64_t spill_cap = 0;
+  uint32_t *d_spill_count = nullptr;    // [2][spill_waves_cap]
+  int64_t spill_waves_cap = 0;
   hipEvent_t staged{};
   bool staged_valid = false;
   hipStream_t cap_stream{};
@@ -735,6 +747,7 @@ static void batch_free(BatchState *b) {
   if (b->h_prefix) (void)hipHostFree(b->h_prefix);
   if (b->d_counters) (void)hipFree(b->d_counters);
   for (auto *p : b->d_spill) if (p) (void)hipFree(p);
+  if (b->d_spill_count) (void)hipFree(b->d_spill_count);
   if (b->staged_valid) (void)hipEventDestroy(b->staged);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;
@@ -775,10 +788,23 @@ static int grow_lists(BatchState *b, int64_t n_lists) {
   const int64_t cap = std::max<int64_t>(n_lists, 1024);
   if (hipMalloc(&b->d_lists, cap * sizeof(BatchList)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void **>(&b->h_lists), cap * sizeof(BatchList), hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(&b->d_prefix, (cap + 1) * sizeof(int64_t)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void **>(&b->h_prefix), (cap + 1) * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+      hipMalloc(&b->d_prefix, 2 * kXcds * (cap + 1) * sizeof(int64_t)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&b->h_prefix), 2 * kXcds * (cap + 1) * sizeof(int64_t),
+                    hipHostMallocDefault) != hipSuccess)
     return fail(BLSH_ENOMEM, "list buffers");
   b->lists_cap = cap;
+  return BLSH_OK;
+}
+
+static int grow_spill_counts(BatchState *b, int64_t waves) {
+  if (b->spill_waves_cap >= waves) return BLSH_OK;
+  BLSH_HIP(hipDeviceSynchronize());
+  if (b->d_spill_count) (void)hipFree(b->d_spill_count);
+  b->d_spill_count = nullptr;
+  b->spill_waves_cap = 0;
+  if (hipMalloc(&b->d_spill_count, size_t(2 * waves) * sizeof(uint32_t)) != hipSuccess)
+    return fail(BLSH_ENOMEM, "spill counts");
+  b->spill_waves_cap = waves;
   return BLSH_OK;
 }
 
@@ -800,7 +826,8 @@ static void launch_batch_kernels(BatchState *b, int mode, int grid1, int grid2, 
     hipLaunchKernelGGL((k_batch_exhaustive<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
     return;
   }
-  hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
+  hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block, int(BLSH_COSINE));
+  hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block, int(BLSH_JACCARD));
   hipLaunchKernelGGL((k_batch_phase2<KJ, KC>), dim3(grid2), dim3(kBBlock), 0, s, b->d_block);
 }
 
@@ -860,8 +887,10 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
   if ((rc = grow_lists(b, n_lists))) return rc;
   if (b->staged_valid) BLSH_HIP(hipEventSynchronize(b->staged));   // previous call's staging copies are done
   const int64_t srp_tile = mode ? kExSrpTile : kSrpTile, mh_tile = mode ? kExMhTile : kMhTile;
+  // tile prefix sums: one array (comparator) or one per (measure, XCD slice)
+  const int n_slices = mode ? 1 : 2 * kXcds;
   int64_t tiles = 0;
-  b->h_prefix[0] = 0;
+  for (int x = 0; x < n_slices; ++x) b->h_prefix[int64_t(x) * (n_lists + 1)] = 0;
   for (int64_t i = 0; i < n_lists; ++i) {
     const blsh_list_desc &d = lists[i];
     BatchList &bl = b->h_lists[i];
@@ -872,15 +901,24 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     bl.table = int32_t(std::lower_bound(ts.begin(), ts.end(), d.t) - ts.begin()) * 2 + (d.measure == BLSH_COSINE);
     bl.pad = 0;
     const int64_t tsz = d.measure == BLSH_COSINE ? srp_tile : mh_tile;
-    tiles += (d.length + tsz - 1) / tsz;
-    b->h_prefix[i + 1] = tiles;
+    const int64_t nt = (d.length + tsz - 1) / tsz;
+    tiles += nt;
+    for (int x = 0; x < n_slices; ++x) {
+      int64_t *px = b->h_prefix + int64_t(x) * (n_lists + 1);
+      if (mode) {
+        px[i + 1] = px[i] + nt;
+      } else {
+        const int me = x / kXcds, xs = x % kXcds;
+        px[i + 1] = px[i] + (me == d.measure ? (int64_t(xs + 1) * nt) / kXcds - (int64_t(xs) * nt) / kXcds : 0);
+      }
+    }
   }
   const int64_t spill_cap = ctx->tuning.batch_spill_cap > 0
                                 ? int64_t(ctx->tuning.batch_spill_cap)
                                 : std::max<int64_t>(1024, std::min<int64_t>(n_cand, int64_t(1) << 24));
   if ((rc = grow_spill(b, spill_cap))) return rc;
 
-  auto prepare = [&](int kkj, int kkc, int inreg) -> int {
+  auto prepare = [&](int kkj, int kkc, int inreg, int grid1) -> int {
     const int kk[2] = {kkj, kkc};
     // the pinned staging block is read by the copy enqueued by the previous
     // prepare (the autotuner enqueues several per call): wait for that copy
@@ -924,7 +962,10 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     B.counters = b->d_counters;
     B.spill[0] = b->d_spill[0];
     B.spill[1] = b->d_spill[1];
-    B.spill_cap = spill_cap;
+    B.spill_waves = grid1 * (kBBlock / kWave);
+    B.spill_region = spill_cap / B.spill_waves;
+    B.spill_count[0] = b->d_spill_count;
+    B.spill_count[1] = b->d_spill_count + B.spill_waves;
     B.inreg_levels = inreg;
     BLSH_HIP(hipMemcpyAsync(b->d_block, b->h_block, sizeof(BatchBlock), hipMemcpyHostToDevice, s));
     // the pinned staging may be rewritten by the next call once these copies ran
@@ -932,12 +973,14 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     return BLSH_OK;
   };
   BLSH_HIP(hipMemcpyAsync(b->d_lists, b->h_lists, n_lists * sizeof(BatchList), hipMemcpyHostToDevice, s));
-  BLSH_HIP(hipMemcpyAsync(b->d_prefix, b->h_prefix, (n_lists + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  BLSH_HIP(hipMemcpyAsync(b->d_prefix, b->h_prefix, n_slices * (n_lists + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                          s));
 
   auto run = [&](const BatchState::Choice &c) -> int {
-    int r2 = prepare(c.kj, c.kc, c.inreg);
+    const int grid1 = std::max(kXcds, ctx->n_cu * c.bpc);   // phase 1 needs a block on every XCD slice
+    int r2 = grow_spill_counts(b, int64_t(grid1) * (kBBlock / kWave));
     if (r2) return r2;
-    const int grid1 = std::max(1, ctx->n_cu * c.bpc);
+    if ((r2 = prepare(c.kj, c.kc, c.inreg, grid1))) return r2;
     const int grid2 = std::max(1, ctx->n_cu * 4);
     hipGraphExec_t ex;
     if ((r2 = get_graph(b, mode, c.kj, c.kc, grid1, grid2, &ex))) return r2;
