@@ -156,8 +156,10 @@ __device__ inline void emit_exact(const VerifyArgs &a, int64_t c, double s) {
 //        `sig` in its own layout.
 //   LITE: survivors of the h-hash budget get their exact similarity right here,
 //        one survivor at a time by the whole wave (Algorithm 2).
+// (8 waves per SIMD: the register bound costs a few bytes of spill in the
+// rarely taken exact-similarity path and keeps more gathers in flight)
 template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool PFX>
-__global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
+__global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
   constexpr int PL = PFX ? 128 / K : 0;   // levels served by the prefix
   __shared__ int s_min[kMaxLevels];
   __shared__ uint32_t s_eidx[LITE ? kBlock / kWave : 1][LITE ? kExactLds : 1];
@@ -270,18 +272,24 @@ __global__ __launch_bounds__(kBlock) void k_verify_bits(VerifyArgs a) {
   // emission in converged control flow
   if (__ballot(emit != 0) == 0) return;
   if constexpr (LITE) {
+    // the survivors' ids are fetched again (wave-uniform, rare) rather than
+    // kept in registers through the exact-similarity code
     const int w = threadIdx.x / kWave;
-    const uint32_t c_lo = uint32_t(c0), c_hi = uint32_t(uint64_t(c0) >> 32);
+    const int64_t wave_c0 = a.c_begin + (tile * kBlock + int64_t(w) * kWave) * kPPT;
 #pragma unroll
     for (int p = 0; p < kPPT; ++p) {
       uint64_t mask = __ballot((emit >> p) & 1u);
       while (mask) {
         const int l = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1;
-        const uint32_t sx = __builtin_amdgcn_readlane(xi[p], l);
-        const uint32_t sy = __builtin_amdgcn_readlane(yi[p], l);
-        const int64_t c = int64_t(uint64_t(__builtin_amdgcn_readlane(c_lo, l)) |
-                                  (uint64_t(__builtin_amdgcn_readlane(c_hi, l)) << 32)) + p;
+        const int64_t c = wave_c0 + int64_t(l) * kPPT + p;
+        uint32_t sx, sy;
+        if constexpr (KIND == BLSH_PAIRS) {
+          sx = a.x[c];
+          sy = a.y[c];
+        } else {
+          fetch_candidate(a, c, sx, sy);
+        }
         const double sim = exact_wave(a, sx, sy, s_eidx[w], s_eval[w]);
         if (lane_id() == 0) emit_exact(a, c, sim);
       }
