@@ -88,8 +88,9 @@ typedef enum {
 } blsh_vec_kind;
 
 /* Prior (Section 4.1: Beta(alpha, beta) for Jaccard; Section 4.2: uniform on
- * r in [0.5, 1] for cosine).  Jaccard: alpha, beta must be integers >= 1 in
- * this version.  Cosine: must be {1, 1} (the uniform prior). */
+ * r in [0.5, 1] for cosine).  Jaccard: 0 < alpha, beta <= 1e6 (integers use
+ * the exact Beta-binomial closed form, other values the continued fraction of
+ * the incomplete beta; see bayeslsh_fit_prior).  Cosine: must be {1, 1}. */
 typedef struct { double alpha, beta; } blsh_prior;
 
 typedef struct {
@@ -218,7 +219,8 @@ int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *tuning_host);
  *                        Pr[|S - S_hat| < delta | M(m,n)] >= 1 - gamma
  *                        (the cache of concentration results of Section 4.3)
  * Jaccard probabilities use the Beta-binomial closed form (integer alpha,
- * beta); cosine ones use Gauss-Legendre quadrature over the angle theta with
+ * beta) or the continued fraction of the regularized incomplete beta (other
+ * alpha, beta); cosine ones use Gauss-Legendre quadrature over the angle theta with
  * r = 1 - theta/pi.  lite != 0 skips the concentration bits.  Either output
  * pointer may be NULL.  min_margin_host (optional) receives the smallest
  * distance of an evaluated probability from its threshold.  Host-only: ctx may
@@ -272,6 +274,24 @@ int bayeslsh_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs 
 int bayeslsh_lite_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs,
                          const blsh_vectors *exact, double t, double epsilon, blsh_prior prior, int32_t h,
                          int32_t k, blsh_result *res, void *stream);
+
+/* Exact similarity of every candidate (the quantity Algorithm 2 computes for
+ * its survivors): Jaccard |A n B| / |A u B| of SETS vectors, cosine of DENSE
+ * or CSR vectors with sums in FP64.  sim_out: device double[n_cand], one value
+ * per candidate index; a candidate with an id >= n_obj gets NaN and makes the
+ * next bayeslsh_sync return BLSH_EBADID.  Used to draw the similarity sample
+ * that bayeslsh_fit_prior turns into a prior. */
+int bayeslsh_exact_similarity(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_vectors *vecs,
+                              double *sim_out, void *stream);
+
+/* Learned Jaccard prior (Section 4.1): Beta(alpha, beta) fitted to a random
+ * sample of candidate-pair similarities s_1..s_r (host array) by the method
+ * of moments: with the sample mean m and variance v = sum (s_i - m)^2 / r,
+ *   alpha = m (m (1 - m) / v - 1),  beta = (1 - m) (m (1 - m) / v - 1).
+ * When no Beta has these moments (r < 2, v = 0 or v >= m (1 - m)) or the fit
+ * exceeds 1e6, the uniform prior {1, 1} is written and *uniform_host (may be
+ * NULL) is set to 1.  Host-only; BLSH_EINVAL if a value is outside [0, 1]. */
+int bayeslsh_fit_prior(const double *sim_host, int64_t r, blsh_prior *prior_out, int32_t *uniform_host);
 
 /* Exhaustive comparator: every candidate compares all n_max hashes (no early
  * exit, object-major rows read whole), then

@@ -77,6 +77,28 @@ def jaccard_concentration(m: int, n: int, delta: float, alpha: float = 1.0, beta
     return float(betainc(a, b, hi) - betainc(a, b, lo))
 
 
+def fit_beta_moments(sims) -> tuple[float, float, bool]:
+    """Learned Jaccard prior (Section 4.1): the Beta(alpha, beta) whose mean and
+    variance equal the sample mean and the sample variance (sum of squared
+    deviations divided by the sample size).  With mean s and variance v,
+    alpha = s (s(1-s)/v - 1) and beta = (1-s)(s(1-s)/v - 1).  Returns
+    (alpha, beta, fell_back): no Beta has the sample's moments when fewer than
+    two values are given, v = 0 or v >= s(1-s), and a fit above 1e6 is beyond
+    the tables' range; all of these give the uniform prior (1, 1)."""
+    x = np.asarray(sims, dtype=np.float64)
+    if x.size < 2:
+        return 1.0, 1.0, True
+    s = float(x.mean())
+    v = float(((x - s) ** 2).mean())
+    if not (v > 0.0) or not (v < s * (1.0 - s)):
+        return 1.0, 1.0, True
+    c = s * (1.0 - s) / v - 1.0
+    a, b = s * c, (1.0 - s) * c
+    if not (0.0 < a <= 1e6 and 0.0 < b <= 1e6):
+        return 1.0, 1.0, True
+    return a, b, False
+
+
 # --------------------------------------------------------------------------
 # Cosine, uniform prior on r in [0.5, 1]  (Section 4.2)
 # --------------------------------------------------------------------------

@@ -425,6 +425,30 @@ def bayeslsh_lite_verify(ctx: Context, cand: Candidates, sigs: Signatures, exact
     return res
 
 
+def bayeslsh_exact_similarity(ctx: Context, cand: Candidates, vecs: Vectors, out: torch.Tensor = None,
+                              stream=None) -> torch.Tensor:
+    """Exact similarity of every candidate (FP64 device tensor of cand.count)."""
+    if out is None:
+        out = torch.empty(max(cand.count, 1), dtype=torch.float64, device="cuda")
+    _dev(out, torch.float64, "sim_out")
+    if out.numel() < cand.count:
+        raise ValueError("sim_out too small")
+    cs, vs = cand.struct(), vecs.struct()
+    _check(_lib().bayeslsh_exact_similarity(ctx.handle, C.byref(cs), C.byref(vs), _p(out), _stream(stream)))
+    return out
+
+
+def bayeslsh_fit_prior(sims) -> tuple:
+    """Method-of-moments Beta prior from a host sample of similarities:
+    returns ((alpha, beta), fell_back_to_uniform)."""
+    import numpy as np
+    s = np.ascontiguousarray(sims, dtype=np.float64)
+    pr = A.Prior()
+    uni = C.c_int32(0)
+    _check(_lib().bayeslsh_fit_prior(s.ctypes.data_as(C.c_void_p), len(s), C.byref(pr), C.byref(uni)))
+    return (pr.alpha, pr.beta), bool(uni.value)
+
+
 def bayeslsh_exhaustive_verify(ctx: Context, cand: Candidates, sigs: Signatures, exact: Vectors | None, t, epsilon,
                                delta, gamma, prior=(1.0, 1.0), k=32, h=0, mode=REPLAY, res: Result = None,
                                stream=None):

@@ -20,6 +20,7 @@ int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim,
                      bool word_major, uint32_t *out, hipStream_t s);
 
 int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStream_t s);
+int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s);
 int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
                    const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
                    blsh_prior prior, int32_t kj, int32_t kc, blsh_result *res, int32_t *k_used, hipStream_t s,
@@ -121,9 +122,8 @@ static int check_prior(int measure, blsh_prior p) {
       return fail(BLSH_EINVAL, "cosine uses the uniform prior on r in [0.5,1]: prior must be {1,1}");
     return BLSH_OK;
   }
-  if (!(p.alpha >= 1.0 && p.beta >= 1.0) || p.alpha != std::floor(p.alpha) || p.beta != std::floor(p.beta) ||
-      p.alpha > 1e6 || p.beta > 1e6)
-    return fail(BLSH_EINVAL, "Jaccard prior Beta(alpha,beta) needs integer alpha,beta >= 1 (got %g,%g)", p.alpha,
+  if (!(p.alpha > 0.0 && p.beta > 0.0) || !(p.alpha <= 1e6 && p.beta <= 1e6))
+    return fail(BLSH_EINVAL, "Jaccard prior Beta(alpha,beta) needs 0 < alpha, beta <= 1e6 (got %g,%g)", p.alpha,
                 p.beta);
   return BLSH_OK;
 }
@@ -585,6 +585,64 @@ int bayeslsh_exhaustive_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int6
                                 blsh_result *res, void *stream) {
   return batched_common(ctx, lists, n_lists, cand, n_cand, jac, cos, epsilon, delta, gamma, prior, kj, kc, nullptr,
                         res, stream, 1);
+}
+
+int bayeslsh_exact_similarity(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_vectors *vecs,
+                              double *sim_out, void *stream) {
+  if (!ctx) return fail(BLSH_EINVAL, "null context");
+  int64_t n_cand = 0;
+  int rc = check_cand(cand, &n_cand);
+  if (rc) return rc;
+  if (!vecs) return fail(BLSH_EINVAL, "exact vectors: null");
+  if ((rc = check_exact(vecs, vecs->kind == BLSH_SETS ? BLSH_JACCARD : BLSH_COSINE, 0))) return rc;
+  if (vecs->n_obj <= 0 || vecs->n_obj > 0xFFFFFFFFll) return fail(BLSH_EINVAL, "exact vectors: n_obj out of range");
+  if (n_cand > 0 && !sim_out) return fail(BLSH_EINVAL, "sim_out: null");
+  VerifyArgs a{};
+  fill_cand(a, cand);
+  fill_exact(a, vecs);
+  a.n_obj = vecs->n_obj;
+  a.status = ctx->d_status;
+  a.c_begin = 0;
+  a.c_end = n_cand;
+  return launch_exact_pairs(ctx, a, sim_out, static_cast<hipStream_t>(stream)) ? fail(BLSH_EDEVICE, "launch failed")
+                                                                                : BLSH_OK;
+}
+
+int bayeslsh_fit_prior(const double *sim_host, int64_t r, blsh_prior *prior_out, int32_t *uniform_host) {
+  if (!prior_out) return fail(BLSH_EINVAL, "prior_out: null");
+  if (r < 0 || (r > 0 && !sim_host)) return fail(BLSH_EINVAL, "bad sample");
+  // Section 4.1, method of moments: sample mean and (population) variance
+  double mean = 0.0;
+  for (int64_t i = 0; i < r; ++i) {
+    if (!(sim_host[i] >= 0.0 && sim_host[i] <= 1.0)) return fail(BLSH_EINVAL, "similarity %lld outside [0,1]", (long long)i);
+    mean += sim_host[i];
+  }
+  bool uniform = r < 2;
+  double alpha = 1.0, beta = 1.0;
+  if (!uniform) {
+    mean /= double(r);
+    double var = 0.0;
+    for (int64_t i = 0; i < r; ++i) var += (sim_host[i] - mean) * (sim_host[i] - mean);
+    var /= double(r);
+    const double spread = mean * (1.0 - mean);
+    // no Beta has these moments (or only one with parameters past the table
+    // builder's range): keep the uniform prior
+    if (!(var > 0.0) || !(var < spread)) {
+      uniform = true;
+    } else {
+      const double common = spread / var - 1.0;
+      alpha = mean * common;
+      beta = (1.0 - mean) * common;
+      if (!(alpha > 0.0 && beta > 0.0 && alpha <= 1e6 && beta <= 1e6)) {
+        uniform = true;
+        alpha = beta = 1.0;
+      }
+    }
+  }
+  prior_out->alpha = alpha;
+  prior_out->beta = beta;
+  if (uniform_host) *uniform_host = uniform ? 1 : 0;
+  return BLSH_OK;
 }
 
 int bayeslsh_exhaustive_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs,

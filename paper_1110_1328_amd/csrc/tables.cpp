@@ -10,7 +10,10 @@
 // b = n - m + beta.  With integer a, b the regularized incomplete beta is a
 // binomial tail, I_x(a, b) = Pr[Bin(a+b-1, x) >= a], so every probability is a
 // finite sum of binomial terms (the Beta-binomial closed form), summed in FP64
-// from log-space terms.
+// from log-space terms.  A learned prior (real alpha, beta > 0, fitted by the
+// method of moments of Section 4.1) uses the continued fraction of I_x(a, b)
+// instead, evaluated by the modified Lentz method, on the side of the mean
+// where it converges fast (the other side through I_x(a,b) = 1 - I_{1-x}(b,a)).
 //
 // Cosine (Section 4.2): with r = 1 - theta/pi the posterior density of the
 // angle is proportional to f(theta) = (1 - theta/pi)^m (theta/pi)^(n-m) on
@@ -61,10 +64,57 @@ double reg_inc_beta_int(int a, int b, double x) {
   return 1.0 - binom_cdf(a + b - 1, a - 1, x);
 }
 
+// Continued fraction of I_x(a, b) (real a, b > 0):
+//   I_x(a,b) = x^a (1-x)^b / (a B(a,b)) / F,  F = 1 + d1 / (1 + d2 / (1 + ...)),
+//   d_{2i+1} = -(a+i)(a+b+i) x / ((a+2i)(a+2i+1)),  d_{2i} = i(b-i) x / ((a+2i-1)(a+2i)),
+// with F evaluated by the modified Lentz method; accurate where
+// x < (a+1)/(a+b+2).
+double inc_beta_cf(double a, double b, double x) {
+  const double tiny = 1e-300, eps = 1e-16;
+  double f = 1.0, C = 1.0, D = 0.0;
+  for (int j = 1; j <= 20000; ++j) {
+    double dj;
+    if (j & 1) {
+      const double i = (j - 1) / 2;
+      dj = -(a + i) * (a + b + i) * x / ((a + 2.0 * i) * (a + 2.0 * i + 1.0));
+    } else {
+      const double i = j / 2;
+      dj = i * (b - i) * x / ((a + 2.0 * i - 1.0) * (a + 2.0 * i));
+    }
+    D = 1.0 + dj * D;
+    if (std::fabs(D) < tiny) D = tiny;
+    D = 1.0 / D;
+    C = 1.0 + dj / C;
+    if (std::fabs(C) < tiny) C = tiny;
+    const double step = C * D;
+    f *= step;
+    if (std::fabs(step - 1.0) < eps) break;
+  }
+  const double lpre = a * std::log(x) + b * std::log1p(-x) - std::log(a) -
+                      (std::lgamma(a) + std::lgamma(b) - std::lgamma(a + b));
+  return std::exp(lpre) / f;
+}
+
+// I_x(a, b) and its complement 1 - I_x(a, b), each without cancellation.
+double reg_inc_beta(double a, double b, double x) {
+  if (x <= 0.0) return 0.0;
+  if (x >= 1.0) return 1.0;
+  if (x < (a + 1.0) / (a + b + 2.0)) return inc_beta_cf(a, b, x);
+  return 1.0 - inc_beta_cf(b, a, 1.0 - x);
+}
+double reg_inc_beta_upper(double a, double b, double x) {
+  if (x <= 0.0) return 1.0;
+  if (x >= 1.0) return 0.0;
+  if (x < (a + 1.0) / (a + b + 2.0)) return 1.0 - inc_beta_cf(a, b, x);
+  return inc_beta_cf(b, a, 1.0 - x);
+}
+
 struct Jaccard {
   double t, delta, alpha, beta;
   int ia, ib;
+  bool integer;   // alpha, beta integers: exact binomial sums
   double prune_prob(int m, int n) const {   // 1 - I_t(m+alpha, n-m+beta)
+    if (!integer) return reg_inc_beta_upper(m + alpha, n - m + beta, t);
     const int a = m + ia, b = n - m + ib;
     return binom_cdf(a + b - 1, a - 1, t);
   }
@@ -73,9 +123,13 @@ struct Jaccard {
     return std::min(1.0, std::max(0.0, s));
   }
   double concentration(int m, int n) const {
-    const int a = m + ia, b = n - m + ib;
     const double s = shat(m, n);
     const double hi = std::min(1.0, s + delta), lo = std::max(0.0, s - delta);
+    if (!integer) {
+      const double a = m + alpha, b = n - m + beta;
+      return reg_inc_beta(a, b, hi) - reg_inc_beta(a, b, lo);
+    }
+    const int a = m + ia, b = n - m + ib;
     return reg_inc_beta_int(a, b, hi) - reg_inc_beta_int(a, b, lo);
   }
 };
@@ -203,7 +257,9 @@ int build_table(const TableKey &key, HostTable *out) {
   out->min_matches.assign(key.n_levels, 0);
   out->accept.assign(size_t(key.n_levels) * out->words, 0u);
   if (key.measure == BLSH_JACCARD) {
-    Jaccard mdl{key.t, key.delta, key.alpha, key.beta, int(key.alpha), int(key.beta)};
+    const bool integer = key.alpha == std::floor(key.alpha) && key.beta == std::floor(key.beta) && key.alpha >= 1.0 &&
+                         key.beta >= 1.0;
+    Jaccard mdl{key.t, key.delta, key.alpha, key.beta, int(key.alpha), int(key.beta), integer};
     build_all(mdl, key, out);
   } else {
     Cosine mdl{key.t, key.delta};

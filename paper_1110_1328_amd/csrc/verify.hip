@@ -408,6 +408,27 @@ __global__ __launch_bounds__(kBlock) void k_exact(VerifyArgs a) {
   }
 }
 
+// Exact similarity of every candidate in [c_begin, c_end), one wave per pair,
+// written to out[c] in FP64 (bad ids: NaN and BLSH_EBADID).
+__global__ __launch_bounds__(kBlock) void k_exact_pairs(VerifyArgs a, double *out) {
+  __shared__ uint32_t s_idx[kBlock / kWave][kExactLds];
+  __shared__ float s_val[kBlock / kWave][kExactLds];
+  const int w = threadIdx.x >> 6;
+  const int64_t waves = int64_t(gridDim.x) * (kBlock / kWave);
+  for (int64_t c = a.c_begin + int64_t(blockIdx.x) * (kBlock / kWave) + w; c < a.c_end; c += waves) {
+    uint32_t xi, yi;
+    if (!fetch_candidate(a, c, xi, yi)) {
+      if (lane_id() == 0) {
+        out[c] = __builtin_nan("");
+        raise_status(a.status, BLSH_EBADID);
+      }
+      continue;
+    }
+    const double sim = exact_wave(a, xi, yi, s_idx[w], s_val[w]);
+    if (lane_id() == 0) out[c] = sim;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Exhaustive comparator
 // ---------------------------------------------------------------------------
@@ -676,6 +697,15 @@ int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStrea
   const int64_t nb = std::min<int64_t>(blocks_for(max_items, kBlock / kWave), int64_t(ctx->n_cu) * 16);
   LaunchScope ls(ctx, s, "exact");
   hipLaunchKernelGGL(k_exact, dim3(nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s) {
+  const int64_t n = a.c_end - a.c_begin;
+  if (n <= 0) return BLSH_OK;
+  const int64_t nb = std::min<int64_t>(blocks_for(n, kBlock / kWave), int64_t(ctx->n_cu) * 16);
+  LaunchScope ls(ctx, s, "exact_pairs");
+  hipLaunchKernelGGL(k_exact_pairs, dim3(nb), dim3(kBlock), 0, s, a, out);
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 

@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import paper_1110_1328_amd as P
+from oracle import posterior as O
 from oracle import reference as R
 from synth import generators as G
 
@@ -440,3 +441,69 @@ def test_invalid_arguments_rejected(ctx):
     with pytest.raises(P.BayesLSHError):   # Lite budget not a multiple of k
         P.bayeslsh_lite_verify(ctx, P.pairs(x, x), S, P.dense_vectors(torch.zeros(10, 8, device="cuda")), T, EPS,
                                (1, 1), 48, 32, res)
+
+
+def test_exact_similarity_matches_oracle(ctx):
+    """bayeslsh_exact_similarity: Jaccard of sets, cosine of CSR and dense rows,
+    against the oracle's FP64 brute force; a bad id gives NaN and EBADID."""
+    _flush("exact similarity")
+    rng = np.random.default_rng(33)
+    sets = G.jaccard_sets(n_sets=400, n_groups=20, seed=G.SEED_BASE + 41)
+    corpus = G.tfidf_corpus(n_docs=3000, seed=G.SEED_BASE + 42)
+    mix = G.dense_mixture(n=2000, d=96, n_comp=20, seed=G.SEED_BASE + 43)
+    cases = [(sets_device(sets), sets.n, lambda x, y: R.exact_jaccard(sets.offsets, sets.elems, x, y)),
+             (csr_device(corpus), corpus.n,
+              lambda x, y: R.exact_cosine_csr(corpus.offsets, corpus.indices, corpus.values, x, y)),
+             (P.dense_vectors(up(mix.x)), mix.x.shape[0], lambda x, y: R.exact_cosine_dense(mix.x, x, y))]
+    for vecs, n_obj, ref in cases:
+        x = rng.integers(0, n_obj, 5003).astype(np.uint32)
+        y = rng.integers(0, n_obj, 5003).astype(np.uint32)
+        x[:10] = y[:10]                                    # self pairs: similarity 1
+        got = down(P.bayeslsh_exact_similarity(ctx, P.pairs(up(x), up(y)), vecs))[:len(x)]
+        P.bayeslsh_sync(ctx)
+        np.testing.assert_allclose(got, ref(x, y), atol=1e-6, rtol=0)
+        lq = up(np.array([0, 2], np.uint32))
+        off = up(np.array([0, 3, 5], np.int64))
+        cl = up(y[:5])
+        got_l = down(P.bayeslsh_exact_similarity(ctx, P.query_lists(lq, off, cl, 5), vecs))[:5]
+        P.bayeslsh_sync(ctx)
+        np.testing.assert_allclose(got_l, ref(np.array([0, 0, 0, 2, 2], np.uint32), y[:5]), atol=1e-6, rtol=0)
+    xb = up(np.array([0, sets.n], np.uint32))
+    out = P.bayeslsh_exact_similarity(ctx, P.pairs(xb, up(np.array([1, 2], np.uint32))), sets_device(sets))
+    with pytest.raises(P.BayesLSHError) as e:
+        P.bayeslsh_sync(ctx)
+    assert e.value.code == -5
+    o = down(out)
+    assert np.isfinite(o[0]) and np.isnan(o[1])
+
+
+def test_learned_prior_pipeline(ctx):
+    """Section 4.1's learned prior end to end on the Jaccard workload: exact
+    similarities of a random sample of candidate pairs on the GPU, the
+    method-of-moments Beta fit, then Algorithm 1 over all 1,999,000 pairs with
+    that (real-valued) prior -- against the oracle run at the oracle's own fit."""
+    _flush("learned prior pipeline")
+    sets = G.jaccard_sets()
+    a, b = G.minhash_coeffs(256, G.SEED_BASE + 101)
+    out = torch.empty(sets.n * 256, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_minhash_sigs(ctx, sets_device(sets), up(a), up(b), out)
+    P.bayeslsh_sync(ctx)
+    sig = R.minhash_signatures(sets.offsets, sets.elems, a, b)
+    np.testing.assert_array_equal(down(out).reshape(sets.n, 256), sig)
+    # candidates: all pairs; the sample: random positions among them
+    xa, ya = R.all_pairs_xy(sets.n)
+    pick = G.subsample_pairs(len(xa), 20000, G.SEED_BASE + 44)
+    xs, ys = xa[pick], ya[pick]
+    sims = down(P.bayeslsh_exact_similarity(ctx, P.pairs(up(xs), up(ys)), sets_device(sets)))[:len(xs)]
+    P.bayeslsh_sync(ctx)
+    want_sims = R.exact_jaccard(sets.offsets, sets.elems, xs, ys)
+    np.testing.assert_allclose(sims, want_sims, atol=1e-12, rtol=0)
+    (alpha, beta), fell = P.bayeslsh_fit_prior(sims)
+    wa, wb, wfell = O.fit_beta_moments(want_sims)
+    assert not fell and not wfell
+    assert alpha == pytest.approx(wa, rel=1e-9) and beta == pytest.approx(wb, rel=1e-9)
+    assert (alpha, beta) != (1.0, 1.0)
+    want = R.verify(None, None, P.JACCARD, sig, 32, 8, T, EPS, DELTA, GAMMA, alpha=wa, beta=wb, all_n=sets.n)
+    S = P.Signatures(out, P.JACCARD, P.OBJECT_MAJOR, sets.n, 256)
+    res = run_verify(ctx, P.all_pairs(sets.n), S, prior=(alpha, beta))
+    assert_same_as_oracle(decode_result(res, len(want["decision"])), want)

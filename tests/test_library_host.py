@@ -38,6 +38,10 @@ TABLE_CASES = [
     (0, 0.9, 64, 4, False, (1, 1)),
     (0, 0.7, 32, 8, False, (2, 3)),     # non-uniform integer prior
     (0, 0.3, 32, 8, True, (1, 1)),      # Lite (no concentration bits)
+    (0, 0.7, 32, 8, False, (0.37, 2.9)),  # learned (real) priors: continued fraction
+    (0, 0.5, 16, 16, False, (2.5, 7.25)),
+    (0, 0.9, 64, 4, False, (0.8, 0.6)),
+    (0, 0.3, 32, 8, True, (1.7, 4.2)),
     (1, 0.7, 32, 4, True, (1, 1)),      # cosine Lite, h = 128
     (1, 0.8, 32, 32, False, (1, 1)),    # dense cosine, 1024 bits
     (1, 0.5, 64, 16, False, (1, 1)),
@@ -69,8 +73,9 @@ def test_posterior_table_rejects_bad_arguments(lib):
     bad = [
         dict(t=1.2), dict(t=0.0), dict(epsilon=0.0), dict(delta=1.0), dict(gamma=-0.1),
         dict(measure=1, prior=(2.0, 1.0)),      # cosine needs the uniform prior
-        dict(prior=(1.5, 1.0)),                 # Jaccard prior must be integer
-        dict(prior=(0.5, 1.0)),
+        dict(prior=(0.0, 1.0)),                 # Jaccard prior: 0 < alpha, beta <= 1e6
+        dict(prior=(1.0, -2.0)),
+        dict(prior=(2e6, 1.0)),
         dict(n_levels=65), dict(k=0), dict(measure=7),
     ]
     for kw in bad:
@@ -94,3 +99,20 @@ def test_calls_without_a_context_fail_cleanly(lib):
         lib.bayeslsh_destroy(h)
     else:
         assert rc == -3 and b"device" in lib.bayeslsh_last_error().lower()
+
+
+def test_fit_prior_matches_oracle(lib):
+    """bayeslsh_fit_prior (Section 4.1, method of moments) against the oracle's
+    fit, including the cases that fall back to the uniform prior."""
+    import paper_1110_1328_amd as P
+    from paper_1110_1328_amd.api import BayesLSHError
+    rng = np.random.default_rng(5)
+    samples = [rng.beta(2.0, 5.0, 5000), rng.beta(0.4, 3.0, 777), rng.uniform(0.2, 0.9, 31), [0.2, 0.4],
+               [0.3, 0.3, 0.3], [0.0, 1.0], [0.7], [], [0.5 - 1e-5, 0.5 + 1e-5]]
+    for smp in samples:
+        (a, b), fell = P.bayeslsh_fit_prior(smp)
+        wa, wb, wfell = O.fit_beta_moments(smp)
+        assert fell == wfell
+        assert a == pytest.approx(wa, rel=1e-12) and b == pytest.approx(wb, rel=1e-12)
+    with pytest.raises(BayesLSHError):
+        P.bayeslsh_fit_prior([0.3, 1.5])

@@ -393,3 +393,57 @@ def test_mle_estimate():
     out = R.mle(x, y, 0, sig, 64, 0.5)
     want = [(sig[i] == sig[j]).mean() for i, j in zip(x, y)]
     np.testing.assert_allclose(out["shat"], want)
+
+
+# ---------------------------------------------------------------------------
+# Learned prior (Section 4.1): method of moments, and the posterior with real
+# Beta parameters
+# ---------------------------------------------------------------------------
+def test_fit_beta_moments_hand_example():
+    """{0.2, 0.4}: mean 3/10, variance 1/100, so s(1-s)/v - 1 = 20 and
+    Beta(6, 14) (worked by hand in exact fractions)."""
+    mean = Fraction(3, 10)
+    var = (Fraction(1, 10) ** 2 + Fraction(1, 10) ** 2) / 2
+    c = mean * (1 - mean) / var - 1
+    assert (mean * c, (1 - mean) * c) == (6, 14)
+    a, b, fell = P.fit_beta_moments([0.2, 0.4])
+    assert not fell
+    assert a == pytest.approx(6.0, rel=1e-12) and b == pytest.approx(14.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.37, 2.9), (2.0, 5.0), (7.5, 0.8), (40.0, 60.0)])
+def test_fit_beta_moments_inverts_the_beta_moments(alpha, beta):
+    """A two-point sample {mu - sd, mu + sd} has mean mu and variance sd^2; with
+    the Beta's own moments mu = a/(a+b), sd^2 = ab/((a+b)^2 (a+b+1)) the fit
+    returns (a, b)."""
+    mu = alpha / (alpha + beta)
+    sd = math.sqrt(alpha * beta / ((alpha + beta) ** 2 * (alpha + beta + 1.0)))
+    a, b, fell = P.fit_beta_moments([mu - sd, mu + sd])
+    assert not fell
+    assert a == pytest.approx(alpha, rel=1e-10) and b == pytest.approx(beta, rel=1e-10)
+
+
+def test_fit_beta_moments_large_sample_and_degenerate_cases():
+    rng = np.random.default_rng(17)
+    a, b, fell = P.fit_beta_moments(rng.beta(2.0, 5.0, 200_000))
+    assert not fell and abs(a - 2.0) < 0.05 and abs(b - 5.0) < 0.12
+    for bad in ([0.4], [0.3, 0.3, 0.3], [0.0, 1.0], [0.0, 0.0, 1.0, 1.0]):
+        assert P.fit_beta_moments(bad) == (1.0, 1.0, True), bad
+    # a sample too concentrated for the tables' range falls back too
+    assert P.fit_beta_moments([0.5 - 1e-5, 0.5 + 1e-5])[2]
+
+
+@pytest.mark.parametrize("m,n,alpha,beta,t", [(3, 32, 0.37, 2.9, 0.7), (20, 64, 2.5, 7.25, 0.5),
+                                              (60, 64, 0.8, 0.6, 0.9), (0, 16, 1.7, 4.2, 0.3)])
+def test_jaccard_posterior_with_real_prior(m, n, alpha, beta, t):
+    """Real (learned) Beta parameters: the prune and concentration
+    probabilities equal the regularized incomplete beta of the posterior
+    Beta(m + alpha, n - m + beta) at 50 digits."""
+    mpmath.mp.dps = 50
+    a, b = mpmath.mpf(m) + mpmath.mpf(alpha), mpmath.mpf(n - m) + mpmath.mpf(beta)
+    want = 1 - mpmath.betainc(a, b, 0, mpmath.mpf(t), regularized=True)
+    assert P.jaccard_prune_prob(m, n, t, alpha, beta) == pytest.approx(float(want), rel=1e-10, abs=1e-15)
+    s = P.jaccard_map(m, n, alpha, beta)
+    lo, hi = max(0.0, s - 0.05), min(1.0, s + 0.05)
+    want_c = mpmath.betainc(a, b, mpmath.mpf(lo), mpmath.mpf(hi), regularized=True)
+    assert P.jaccard_concentration(m, n, 0.05, alpha, beta) == pytest.approx(float(want_c), rel=1e-10, abs=1e-15)
