@@ -284,6 +284,23 @@ int bayeslsh_lite_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_
 int bayeslsh_exact_similarity(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_vectors *vecs,
                               double *sim_out, void *stream);
 
+/* LSH banding candidate generation (Section 2): the first n_bands * band_bits
+ * bits of each object's sign-random-projection signature (`band_sigs`, an
+ * SRP set drawn independently of the verification bits; either layout) are
+ * cut into n_bands band keys of band_bits bits; two objects whose keys are
+ * equal in some band form a candidate pair, emitted once, in the first band
+ * where they collide.  max_bucket > 0 keeps only the first max_bucket members
+ * (by id) of each bucket.  Output order: band by band, buckets by increasing
+ * key, then (x, y) with x < y in row-major order of the bucket's members --
+ * the bucket-major order the verification kernels read best.  x_out, y_out:
+ * device uint32[capacity].  *n_pairs_host receives the number of pairs; the
+ * call waits for `stream`.  More pairs than capacity: the first `capacity` are
+ * written and BLSH_ETRUNCATED is returned.  Uses the context workspace
+ * (about 8 * n_obj * (n_bands + 4) bytes). */
+int bayeslsh_band_candidates(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t n_bands, int32_t band_bits,
+                             int32_t max_bucket, uint32_t *x_out, uint32_t *y_out, int64_t capacity,
+                             int64_t *n_pairs_host, void *stream);
+
 /* Learned Jaccard prior (Section 4.1): Beta(alpha, beta) fitted to a random
  * sample of candidate-pair similarities s_1..s_r (host array) by the method
  * of moments: with the sample mean m and variance v = sum (s_i - m)^2 / r,

@@ -290,3 +290,47 @@ def exact_jaccard(offsets, elems, x, y):
     out = np.empty(len(x), np.float64)
     lib().exact_jaccard(_ptr(offsets), _ptr(elems), _ptr(x), _ptr(y), len(x), _ptr(out))
     return out
+
+
+# ---------------------------------------------------------------------------
+# LSH banding candidate generation (Section 2), plain Python
+# ---------------------------------------------------------------------------
+def band_keys(bits_words, n_bands, band_bits):
+    """Key of band j of every object: its bits j*b .. j*b+b-1 (LSB-first packed
+    words, bit h in word h // 32 at position h % 32), as an integer."""
+    w = np.asarray(bits_words, dtype=np.uint64)
+    n = w.shape[0]
+    keys = np.zeros((n, n_bands), np.int64)
+    for j in range(n_bands):
+        for t in range(band_bits):
+            h = j * band_bits + t
+            bit = (w[:, h // 32] >> np.uint64(h % 32)) & np.uint64(1)
+            keys[:, j] |= bit.astype(np.int64) << t
+    return keys
+
+
+def band_candidates(bits_words, n_bands, band_bits, max_bucket=0):
+    """Objects whose keys agree in some band are candidates; a pair is listed
+    once, in the first band where its keys agree.  Order: band by band,
+    buckets by increasing key, members by increasing id, pairs (i, j) of a
+    bucket's members in row-major order (i < j).  max_bucket > 0 keeps the
+    first max_bucket members of each bucket."""
+    keys = band_keys(bits_words, n_bands, band_bits)
+    n = keys.shape[0]
+    xs, ys = [], []
+    for j in range(n_bands):
+        buckets = {}
+        for i in range(n):
+            buckets.setdefault(int(keys[i, j]), []).append(i)
+        for key in sorted(buckets):
+            mem = buckets[key]
+            if max_bucket:
+                mem = mem[:max_bucket]
+            for a in range(len(mem)):
+                for b in range(a + 1, len(mem)):
+                    x, y = mem[a], mem[b]
+                    if any(keys[x, jj] == keys[y, jj] for jj in range(j)):
+                        continue
+                    xs.append(x)
+                    ys.append(y)
+    return np.array(xs, np.uint32), np.array(ys, np.uint32)

@@ -438,6 +438,29 @@ def bayeslsh_exact_similarity(ctx: Context, cand: Candidates, vecs: Vectors, out
     return out
 
 
+def bayeslsh_band_candidates(ctx: Context, band_sigs: Signatures, n_bands: int, band_bits: int, capacity: int,
+                             max_bucket: int = 0, x_out: torch.Tensor = None, y_out: torch.Tensor = None,
+                             stream=None):
+    """LSH banding on the device.  Returns (x, y, n_pairs, truncated): uint32
+    device tensors of `capacity` entries, the first min(n_pairs, capacity) valid."""
+    if x_out is None:
+        x_out = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda").view(torch.uint32)
+    if y_out is None:
+        y_out = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda").view(torch.uint32)
+    _dev(x_out, torch.uint32, "x_out")
+    _dev(y_out, torch.uint32, "y_out")
+    if x_out.numel() < capacity or y_out.numel() < capacity:
+        raise ValueError("outputs smaller than capacity")
+    st = band_sigs.struct()
+    n = C.c_int64(0)
+    rc = _lib().bayeslsh_band_candidates(ctx.handle, C.byref(st), n_bands, band_bits, max_bucket, _p(x_out), _p(y_out),
+                                         capacity, C.byref(n), _stream(stream))
+    if rc == A.ETRUNCATED:
+        return x_out, y_out, n.value, True
+    _check(rc)
+    return x_out, y_out, n.value, False
+
+
 def bayeslsh_fit_prior(sims) -> tuple:
     """Method-of-moments Beta prior from a host sample of similarities:
     returns ((alpha, beta), fell_back_to_uniform)."""

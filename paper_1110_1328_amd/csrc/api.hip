@@ -21,6 +21,9 @@ int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim,
 
 int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStream_t s);
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s);
+int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t row_words, bool word_major,
+                    int32_t n_bands, int32_t band_bits, int32_t max_bucket, uint32_t *x_out, uint32_t *y_out,
+                    int64_t capacity, int64_t *n_pairs, hipStream_t s);
 int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
                    const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
                    blsh_prior prior, int32_t kj, int32_t kc, blsh_result *res, int32_t *k_used, hipStream_t s,
@@ -606,6 +609,28 @@ int bayeslsh_exact_similarity(blsh_ctx *ctx, const blsh_candidates *cand, const 
   a.c_end = n_cand;
   return launch_exact_pairs(ctx, a, sim_out, static_cast<hipStream_t>(stream)) ? fail(BLSH_EDEVICE, "launch failed")
                                                                                 : BLSH_OK;
+}
+
+int bayeslsh_band_candidates(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t n_bands, int32_t band_bits,
+                             int32_t max_bucket, uint32_t *x_out, uint32_t *y_out, int64_t capacity,
+                             int64_t *n_pairs_host, void *stream) {
+  if (!ctx) return fail(BLSH_EINVAL, "null context");
+  if (!n_pairs_host) return fail(BLSH_EINVAL, "n_pairs_host: null");
+  *n_pairs_host = 0;
+  const blsh_sigs *g = band_sigs;
+  if (!g || !g->data) return fail(BLSH_EINVAL, "band signatures: null");
+  if (g->measure != BLSH_COSINE) return fail(BLSH_EINVAL, "banding takes sign-random-projection bits");
+  if (g->layout != BLSH_OBJECT_MAJOR && g->layout != BLSH_WORD_MAJOR) return fail(BLSH_EINVAL, "bad layout");
+  if (g->n_obj <= 0 || g->n_obj > 0xFFFFFFFFll) return fail(BLSH_EINVAL, "band signatures: n_obj out of range");
+  if (g->n_hashes <= 0 || g->n_hashes % 32) return fail(BLSH_EINVAL, "band signatures: n_hashes must be a multiple of 32");
+  if (band_bits < 1 || band_bits > 32 || n_bands < 1 || n_bands > 64)
+    return fail(BLSH_EINVAL, "banding: 1 <= band_bits <= 32 and 1 <= n_bands <= 64");
+  if (int64_t(n_bands) * band_bits > g->n_hashes)
+    return fail(BLSH_EINVAL, "banding: n_bands * band_bits (%d) > n_hashes (%d)", n_bands * band_bits, g->n_hashes);
+  if (max_bucket < 0 || capacity < 0) return fail(BLSH_EINVAL, "banding: negative max_bucket or capacity");
+  if (capacity > 0 && (!x_out || !y_out)) return fail(BLSH_EINVAL, "banding: null outputs");
+  return band_candidates(ctx, g->data, g->n_obj, g->n_hashes / 32, g->layout == BLSH_WORD_MAJOR, n_bands, band_bits,
+                         max_bucket, x_out, y_out, capacity, n_pairs_host, static_cast<hipStream_t>(stream));
 }
 
 int bayeslsh_fit_prior(const double *sim_host, int64_t r, blsh_prior *prior_out, int32_t *uniform_host) {

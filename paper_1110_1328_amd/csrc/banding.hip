@@ -1,0 +1,211 @@
+// LSH banding candidate generation (Section 2): the hashes of an object are
+// cut into n_bands bands of band_bits sign-random-projection bits each, and
+// objects whose band key is equal in some band become a candidate pair.  A
+// pair is emitted once, in the first band where its two keys are equal.
+//
+// Per band, on the device:
+//   keys      every object's key of every band (band-major for the sort,
+//             object-major for the first-band test), from the packed bits;
+//   sort      (key, id) pairs by key, stable (rocPRIM radix sort), so each
+//             bucket lists its members by increasing id;
+//   bounds    the bucket [start, end) of every sorted position;
+//   count     one wave per member row p: partners q in (p, end), kept when no
+//             earlier band has equal keys -> kept pairs per row;
+//   scan      exclusive prefix of the row counts (rocPRIM) -> output offsets;
+//   emit      the same walk writes (x, y) = (ids[p], ids[q]) at the row's
+//             offset plus the lane's ballot rank, so the output order is band
+//             by band, bucket by increasing key, row by increasing id, partner
+//             by increasing id (x < y).
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "device_common.h"
+
+namespace blsh {
+
+constexpr int kBandBlock = 256;
+
+// Key of band j of object i: bits [j b, j b + b) of its signature (LSB-first).
+__global__ __launch_bounds__(kBandBlock) void k_band_keys(const uint32_t *sig, int64_t n_obj, int32_t row_words,
+                                                          int32_t word_major, int32_t n_bands, int32_t band_bits,
+                                                          uint32_t *keys_bm, uint32_t *keys_om) {
+  const int64_t i = int64_t(blockIdx.x) * kBandBlock + threadIdx.x;
+  if (i >= n_obj) return;
+  const uint32_t mask = band_bits == 32 ? 0xFFFFFFFFu : ((1u << band_bits) - 1u);
+  auto word = [&](int w) -> uint32_t {
+    return word_major ? sig[size_t(w) * n_obj + i] : sig[size_t(i) * row_words + w];
+  };
+  for (int j = 0; j < n_bands; ++j) {
+    const int o = j * band_bits, w = o >> 5, sh = o & 31;
+    uint32_t v = word(w) >> sh;
+    if (sh + band_bits > 32) v |= word(w + 1) << (32 - sh);
+    v &= mask;
+    keys_bm[size_t(j) * n_obj + i] = v;
+    keys_om[size_t(i) * n_bands + j] = v;
+  }
+}
+
+__global__ void k_iota(uint32_t *ids, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) ids[i] = uint32_t(i);
+}
+
+// [start, end) of the bucket of every sorted position (the thread at a bucket
+// start walks its bucket).
+__global__ __launch_bounds__(kBandBlock) void k_bucket_bounds(const uint32_t *skeys, int64_t n, uint32_t *bstart,
+                                                              uint32_t *bend) {
+  const int64_t p = int64_t(blockIdx.x) * kBandBlock + threadIdx.x;
+  if (p >= n || (p > 0 && skeys[p] == skeys[p - 1])) return;
+  int64_t e = p + 1;
+  while (e < n && skeys[e] == skeys[p]) ++e;
+  for (int64_t q = p; q < e; ++q) {
+    bstart[q] = uint32_t(p);
+    bend[q] = uint32_t(e);
+  }
+}
+
+struct BandArgs {
+  const uint32_t *sids;      // sorted ids of this band
+  const uint32_t *bstart, *bend;
+  const uint32_t *keys_om;   // [n_obj][n_bands]
+  int64_t n_obj;
+  int32_t n_bands, band;
+  int32_t max_bucket;        // 0: every member; else the first max_bucket members of a bucket
+  int64_t *row_count;        // count pass
+  const int64_t *row_off;    // emit pass
+  const int64_t *base;       // emit pass: output offset of this band
+  uint32_t *x_out, *y_out;
+  int64_t capacity;
+};
+
+// One wave per member row p.  EMIT = false counts the kept pairs of the row;
+// EMIT = true writes them in order.
+template <bool EMIT>
+__global__ __launch_bounds__(kBandBlock) void k_band_pairs(BandArgs a) {
+  const int lane = lane_id();
+  const int64_t waves = int64_t(gridDim.x) * (kBandBlock / kWave);
+  const int64_t w0 = int64_t(blockIdx.x) * (kBandBlock / kWave) +
+                     int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
+  const int64_t out0 = EMIT ? *a.base : 0;
+  for (int64_t p = w0; p < a.n_obj; p += waves) {
+    const int64_t s = a.bstart[p];
+    int64_t e = a.bend[p];
+    int64_t kept = 0;
+    if (a.max_bucket > 0) e = min<int64_t>(e, s + a.max_bucket);
+    if (p + 1 < e) {
+      const uint32_t x = a.sids[p];
+      const uint32_t *kx = a.keys_om + size_t(x) * a.n_bands;
+      const int64_t off = EMIT ? out0 + a.row_off[p] : 0;
+      for (int64_t q0 = p + 1; q0 < e; q0 += kWave) {
+        const int64_t q = q0 + lane;
+        bool keep = false;
+        uint32_t y = 0;
+        if (q < e) {
+          y = a.sids[q];
+          const uint32_t *ky = a.keys_om + size_t(y) * a.n_bands;
+          keep = true;
+          for (int j = 0; j < a.band; ++j)   // collided in an earlier band: emitted there
+            if (kx[j] == ky[j]) { keep = false; break; }
+        }
+        const uint64_t mask = __ballot(keep);
+        if (EMIT && keep) {
+          const int64_t pos = off + kept + int64_t(lanes_below(mask));
+          if (pos < a.capacity) {
+            a.x_out[pos] = x;
+            a.y_out[pos] = y;
+          }
+        }
+        kept += __popcll(mask);
+      }
+    }
+    if (!EMIT && lane == 0) a.row_count[p] = kept;
+  }
+}
+
+// base += (pairs of this band) = row_off[n-1] + row_count[n-1]
+__global__ void k_band_advance(int64_t *base, const int64_t *row_off, const int64_t *row_count, int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && n > 0) *base += row_off[n - 1] + row_count[n - 1];
+}
+
+__global__ void k_band_zero(int64_t *base) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *base = 0;
+}
+
+static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t row_words, bool word_major,
+                    int32_t n_bands, int32_t band_bits, int32_t max_bucket, uint32_t *x_out, uint32_t *y_out,
+                    int64_t capacity, int64_t *n_pairs, hipStream_t s) {
+  const size_t n = size_t(n_obj);
+  // rocPRIM temporary storage sizes
+  size_t sort_tmp = 0, scan_tmp = 0;
+  if (rocprim::radix_sort_pairs(nullptr, sort_tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                (const uint32_t *)nullptr, (uint32_t *)nullptr, n, 0, unsigned(band_bits), s) !=
+          hipSuccess ||
+      rocprim::exclusive_scan(nullptr, scan_tmp, (const int64_t *)nullptr, (int64_t *)nullptr, int64_t(0), n,
+                              rocprim::plus<int64_t>(), s) != hipSuccess)
+    return fail(BLSH_EDEVICE, "banding: temporary storage query failed");
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
+  const size_t o_kbm = take(n * n_bands * 4), o_kom = take(n * n_bands * 4), o_ids = take(n * 4),
+               o_skeys = take(n * 4), o_sids = take(n * 4), o_bs = take(n * 4), o_be = take(n * 4),
+               o_cnt = take(n * 8), o_off = take(n * 8), o_base = take(256), o_tmp = take(std::max(sort_tmp, scan_tmp));
+  int rc = ensure_workspace(ctx, off);
+  if (rc) return rc;
+  char *ws = static_cast<char *>(ctx->ws);
+  uint32_t *keys_bm = reinterpret_cast<uint32_t *>(ws + o_kbm), *keys_om = reinterpret_cast<uint32_t *>(ws + o_kom);
+  uint32_t *ids = reinterpret_cast<uint32_t *>(ws + o_ids), *skeys = reinterpret_cast<uint32_t *>(ws + o_skeys);
+  uint32_t *sids = reinterpret_cast<uint32_t *>(ws + o_sids);
+  uint32_t *bstart = reinterpret_cast<uint32_t *>(ws + o_bs), *bend = reinterpret_cast<uint32_t *>(ws + o_be);
+  int64_t *row_count = reinterpret_cast<int64_t *>(ws + o_cnt), *row_off = reinterpret_cast<int64_t *>(ws + o_off);
+  int64_t *base = reinterpret_cast<int64_t *>(ws + o_base);
+  void *tmp = ws + o_tmp;
+
+  LaunchScope ls(ctx, s, "band_candidates");
+  const unsigned nb = unsigned((n + kBandBlock - 1) / kBandBlock);
+  hipLaunchKernelGGL(k_band_keys, dim3(nb), dim3(kBandBlock), 0, s, sig, n_obj, row_words, int(word_major), n_bands,
+                     band_bits, keys_bm, keys_om);
+  hipLaunchKernelGGL(k_iota, dim3(nb), dim3(kBandBlock), 0, s, ids, n_obj);
+  hipLaunchKernelGGL(k_band_zero, dim3(1), dim3(64), 0, s, base);
+  const unsigned pair_blocks = unsigned(std::min<int64_t>(int64_t(ctx->n_cu) * 8, (n_obj + 3) / 4 + 1));
+  for (int j = 0; j < n_bands; ++j) {
+    size_t t1 = sort_tmp;
+    if (rocprim::radix_sort_pairs(tmp, t1, keys_bm + size_t(j) * n, skeys, ids, sids, n, 0, unsigned(band_bits),
+                                  s) != hipSuccess)
+      return fail(BLSH_EDEVICE, "banding: radix sort failed");
+    hipLaunchKernelGGL(k_bucket_bounds, dim3(nb), dim3(kBandBlock), 0, s, skeys, n_obj, bstart, bend);
+    BandArgs a{};
+    a.sids = sids;
+    a.bstart = bstart;
+    a.bend = bend;
+    a.keys_om = keys_om;
+    a.n_obj = n_obj;
+    a.n_bands = n_bands;
+    a.band = j;
+    a.max_bucket = max_bucket;
+    a.row_count = row_count;
+    a.row_off = row_off;
+    a.base = base;
+    a.x_out = x_out;
+    a.y_out = y_out;
+    a.capacity = capacity;
+    hipLaunchKernelGGL(k_band_pairs<false>, dim3(pair_blocks), dim3(kBandBlock), 0, s, a);
+    size_t t2 = scan_tmp;
+    if (rocprim::exclusive_scan(tmp, t2, row_count, row_off, int64_t(0), n, rocprim::plus<int64_t>(), s) !=
+        hipSuccess)
+      return fail(BLSH_EDEVICE, "banding: scan failed");
+    hipLaunchKernelGGL(k_band_pairs<true>, dim3(pair_blocks), dim3(kBandBlock), 0, s, a);
+    hipLaunchKernelGGL(k_band_advance, dim3(1), dim3(64), 0, s, base, row_off, row_count, n_obj);
+  }
+  BLSH_HIP(hipMemcpyAsync(n_pairs, base, 8, hipMemcpyDeviceToHost, s));
+  BLSH_HIP(hipStreamSynchronize(s));
+  if (hipGetLastError() != hipSuccess) return fail(BLSH_EDEVICE, "banding: launch failed");
+  return *n_pairs > capacity ? fail(BLSH_ETRUNCATED, "banding: %lld pairs, capacity %lld", (long long)*n_pairs,
+                                    (long long)capacity)
+                             : BLSH_OK;
+}
+
+}  // namespace blsh

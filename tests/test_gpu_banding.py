@@ -1,0 +1,71 @@
+"""GPU parity of LSH banding candidate generation (bayeslsh_band_candidates)
+against the oracle's plain banding: the same pairs in the same order."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1110_1328_amd as P
+from oracle import reference as R
+from synth import generators as G
+
+from gpu_util import down, sigs_tensor, up
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    c = P.bayeslsh_create(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def bits():
+    """Sign bits of a clustered point set (64 bits): buckets of uneven size."""
+    mix = G.dense_mixture(n=3000, d=64, n_comp=30, seed=G.SEED_BASE + 61)
+    planes = G.gaussian_planes(64, 64, G.SEED_BASE + 62)
+    return G.pack_bits((mix.x.astype(np.float64) @ planes >= 0).astype(np.uint8))
+
+
+def run(ctx, S, nb, b, cap, max_bucket=0):
+    x, y, n, trunc = P.bayeslsh_band_candidates(ctx, S, nb, b, cap, max_bucket=max_bucket)
+    k = min(n, cap)
+    return down(x)[:k], down(y)[:k], n, trunc
+
+
+@pytest.mark.parametrize("nb,b,max_bucket", [(8, 8, 0), (5, 11, 0), (8, 8, 5), (4, 16, 0)])
+def test_banding_matches_oracle(ctx, bits, nb, b, max_bucket):
+    """Both layouts; band keys that straddle a 32-bit word (b = 11); a bucket cap."""
+    print("banding nb=%d b=%d max_bucket=%d" % (nb, b, max_bucket), flush=True)
+    wx, wy = R.band_candidates(bits, nb, b, max_bucket)
+    assert len(wx) > 1000
+    for layout in (P.OBJECT_MAJOR, P.WORD_MAJOR):
+        S = sigs_tensor(bits, P.COSINE, layout)
+        gx, gy, n, trunc = run(ctx, S, nb, b, len(wx) + 100, max_bucket)
+        assert n == len(wx) and not trunc
+        np.testing.assert_array_equal(gx, wx)
+        np.testing.assert_array_equal(gy, wy)
+
+
+def test_banding_truncation_empty_and_invalid(ctx, bits):
+    print("banding truncation", flush=True)
+    wx, wy = R.band_candidates(bits, 8, 8)
+    S = sigs_tensor(bits, P.COSINE, P.OBJECT_MAJOR)
+    half = len(wx) // 2
+    gx, gy, n, trunc = run(ctx, S, 8, 8, half)
+    assert trunc and n == len(wx)
+    np.testing.assert_array_equal(gx, wx[:half])
+    np.testing.assert_array_equal(gy, wy[:half])
+    # distinct random 32-bit keys in a single band: no pair
+    rnd = np.random.default_rng(3).integers(0, 2 ** 32, size=(500, 1), dtype=np.uint64).astype(np.uint32)
+    _, _, n0, _ = run(ctx, sigs_tensor(rnd, P.COSINE, P.OBJECT_MAJOR), 1, 32, 16)
+    assert n0 == len(R.band_candidates(rnd, 1, 32)[0])
+    for nb, b in ((0, 8), (8, 0), (8, 33), (9, 8)):     # 9 x 8 bits > 64 stored bits
+        with pytest.raises(P.BayesLSHError) as e:
+            run(ctx, S, nb, b, 16)
+        assert e.value.code == -1
+    mh = sigs_tensor(np.zeros((10, 64), np.uint32), P.JACCARD, P.OBJECT_MAJOR)
+    with pytest.raises(P.BayesLSHError):
+        run(ctx, mh, 4, 8, 16)

@@ -447,3 +447,47 @@ def test_jaccard_posterior_with_real_prior(m, n, alpha, beta, t):
     lo, hi = max(0.0, s - 0.05), min(1.0, s + 0.05)
     want_c = mpmath.betainc(a, b, mpmath.mpf(lo), mpmath.mpf(hi), regularized=True)
     assert P.jaccard_concentration(m, n, 0.05, alpha, beta) == pytest.approx(float(want_c), rel=1e-10, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# LSH banding (Section 2)
+# ---------------------------------------------------------------------------
+def test_banding_against_brute_force():
+    """Every pair whose keys agree in some band is listed exactly once, in its
+    first agreeing band, in bucket-major order; no other pair is listed."""
+    rng = np.random.default_rng(8)
+    n, nb, b = 300, 6, 3
+    bits = G.pack_bits(rng.integers(0, 2, size=(n, 32), dtype=np.uint8))
+    x, y = R.band_candidates(bits, nb, b)
+    keys = np.zeros((n, nb), np.int64)
+    for i in range(n):                      # keys by hand, one bit at a time
+        for j in range(nb):
+            for t in range(b):
+                h = j * b + t
+                keys[i, j] |= ((int(bits[i, h // 32]) >> (h % 32)) & 1) << t
+    first = {}
+    for i in range(n):
+        for k in range(i + 1, n):
+            eq = np.flatnonzero(keys[i] == keys[k])
+            if len(eq):
+                first[(i, k)] = int(eq[0])
+    got = list(zip(x.tolist(), y.tolist()))
+    assert len(got) == len(set(got)) == len(first)
+    assert set(got) == set(first)
+    # order: band of first agreement, then key, then (x, y)
+    order = [(first[p], keys[p[0], first[p]], p[0], p[1]) for p in got]
+    assert order == sorted(order)
+
+
+@pytest.mark.parametrize("r", [0.6, 0.8])
+def test_banding_collision_probability(r):
+    """Section 2: with l bands of b bits, a pair whose bits agree independently
+    with probability r becomes a candidate with probability 1 - (1 - r^b)^l."""
+    rng = np.random.default_rng(int(r * 100))
+    n_pairs, nb, b = 3000, 8, 6
+    bits = G.pack_bits(G.calibration_bits(n_pairs, 64, np.full(n_pairs, r), int(r * 1000)))
+    x, y = R.band_candidates(bits, nb, b, max_bucket=0)
+    planted = np.sum((x % 2 == 0) & (y == x + 1))
+    p = 1.0 - (1.0 - r ** b) ** nb
+    sd = math.sqrt(n_pairs * p * (1 - p))
+    assert abs(planted - n_pairs * p) < 4 * sd + 1, (planted, n_pairs * p)
