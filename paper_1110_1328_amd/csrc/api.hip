@@ -21,6 +21,7 @@ int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim,
 
 int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStream_t s);
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s);
+int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, hipStream_t s);
 int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t row_words, bool word_major,
                     int32_t n_bands, int32_t band_bits, int32_t max_bucket, uint32_t *x_out, uint32_t *y_out,
                     int64_t capacity, int64_t *n_pairs, hipStream_t s);
@@ -221,22 +222,26 @@ static void fill_cand(VerifyArgs &a, const blsh_candidates *c) {
 }
 
 // Survivor queue inside the context workspace, sized for `chunk` candidates:
-//   [0, 256)             q_n (int64) + padding
-//   [256, 256 + 4*chunk) q_rel (candidate index relative to the chunk start)
+//   [0, 256)                       q_n (int64) + padding
+//   [256, 256 + 4*chunk)           q_rel (candidate index relative to the chunk start)
+//   [256 + 4*chunk, 256 + 8*chunk) q_m (m | next level << 16; SRP tail only)
 static constexpr int64_t kChunk = int64_t(1) << 28;
+static constexpr int64_t kExhChunk = int64_t(1) << 24;
 
 struct Queue {
   int64_t *n;
   uint32_t *rel;
+  uint32_t *m;
 };
 
-static int get_queue(blsh_ctx *ctx, int64_t chunk, Queue *q) {
-  const size_t bytes = 256 + size_t(chunk) * 4;
+static int get_queue(blsh_ctx *ctx, int64_t chunk, bool with_m, Queue *q) {
+  const size_t bytes = 256 + size_t(chunk) * (with_m ? 8 : 4);
   int rc = ensure_workspace(ctx, bytes);
   if (rc) return rc;
   char *base = static_cast<char *>(ctx->ws);
   q->n = reinterpret_cast<int64_t *>(base);
   q->rel = reinterpret_cast<uint32_t *>(base + 256);
+  q->m = with_m ? reinterpret_cast<uint32_t *>(base + 256 + size_t(chunk) * 4) : nullptr;
   return BLSH_OK;
 }
 
@@ -315,9 +320,16 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   a.t = t;
   if (n_cand == 0) return launch_zero(ctx, res->n_accepted, nullptr, s) ? fail(BLSH_EDEVICE, "launch failed") : BLSH_OK;
   Queue q{};
-  const int64_t chunk = lite ? std::min<int64_t>(n_cand, kChunk) : n_cand;
-  if (lite && (rc = get_queue(ctx, chunk, &q))) return rc;
+  // SRP Algorithm 1 with a prefix view: candidates undecided after the first
+  // 128 hashes are queued and finished by a second kernel with every lane busy
+  const bool tail = !exh && !lite && sigs->measure == BLSH_COSINE && a.pfx != nullptr && 128 / k < n_levels;
+  const bool queued = lite || tail;
+  // launches are chunked so that no grid exceeds 2^32 work-items (the
+  // dispatch's grid size): the comparator runs up to 64 lanes per candidate
+  const int64_t chunk = std::min<int64_t>(n_cand, exh ? kExhChunk : kChunk);
+  if (queued && (rc = get_queue(ctx, chunk, tail, &q))) return rc;
   a.q_rel = q.rel;
+  a.q_m = q.m;
   a.q_n = q.n;
   if (lite) fill_exact(a, exact);
   // the SRP early-exit kernel computes Lite exact similarities itself
@@ -326,10 +338,11 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
     a.c_begin = c0;
     a.c_end = std::min(n_cand, c0 + chunk);
     // one launch clears the output count (first chunk) and the survivor queue count
-    if ((c0 == 0 || lite) && (rc = launch_zero(ctx, c0 == 0 ? res->n_accepted : nullptr, lite ? q.n : nullptr, s)))
+    if ((c0 == 0 || queued) && (rc = launch_zero(ctx, c0 == 0 ? res->n_accepted : nullptr, queued ? q.n : nullptr, s)))
       return fail(rc, "launch failed");
-    rc = exh ? launch_exhaustive(ctx, a, k, s)
-             : launch_verify(ctx, a, k, lite, sigs->measure == BLSH_COSINE && sigs->layout == BLSH_WORD_MAJOR, s);
+    const bool wm = sigs->measure == BLSH_COSINE && sigs->layout == BLSH_WORD_MAJOR;
+    rc = exh ? launch_exhaustive(ctx, a, k, s) : launch_verify(ctx, a, k, lite, wm, s);
+    if (!rc && tail) rc = launch_verify_tail(ctx, a, k, wm, s);
     if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;
     if (lite && !fused_exact && (rc = launch_exact(ctx, a, a.c_end - a.c_begin, s))) return fail(rc, "exact launch failed");
   }

@@ -40,8 +40,11 @@ struct VerifyArgs {
   int64_t acc_cap;
   int64_t *n_acc;
   uint16_t *m_dbg;
-  // Lite survivors: candidate index relative to c_begin
+  // survivor queue: candidate index relative to c_begin (Lite survivors, and
+  // SRP candidates undecided after the 128-hash prefix when q_m is set: then
+  // q_m holds m | next level << 16 for the tail kernel)
   uint32_t *q_rel;
+  uint32_t *q_m;
   int64_t *q_n;
   int32_t *status;
   // exact similarity (Lite): the caller's vectors
@@ -180,6 +183,33 @@ __device__ inline void push_survivor(const VerifyArgs &a, bool pred, int64_t c) 
   if (lane_id() == leader) base = atomicAdd((unsigned long long *)a.q_n, (unsigned long long)__popcll(mask));
   base = __shfl(base, leader);
   if (pred) a.q_rel[base + lanes_below(mask)] = uint32_t(c - a.c_begin);
+}
+
+// Wave-level compaction of a lane's P candidates (bit p of `want`: candidate
+// c0 + p, with mj[p] = m | next level << 16) into the survivor queue with one
+// atomic per wave.
+template <int P>
+__device__ inline void push_survivors(const VerifyArgs &a, uint32_t want, int64_t c0, const uint32_t *mj) {
+  uint64_t mask[P];
+  uint32_t total = 0;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    mask[p] = __ballot((want >> p) & 1u);
+    total += uint32_t(__popcll(mask[p]));
+  }
+  if (total == 0) return;
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd((unsigned long long *)a.q_n, (unsigned long long)total);
+  base = (unsigned long long)__shfl((long long)base, 0);
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if ((want >> p) & 1u) {
+      const unsigned long long pos = base + lanes_below(mask[p]);
+      a.q_rel[pos] = uint32_t(c0 + p - a.c_begin);
+      a.q_m[pos] = mj[p];
+    }
+    base += __popcll(mask[p]);
+  }
 }
 
 // Order this wave's LDS writes before its later LDS reads (and vice versa).

@@ -239,6 +239,17 @@ __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
       }
     }
     j0 = PL;
+    if constexpr (!LITE) {
+      if (a.q_m && j0 < L) {
+        // still undecided after the prefix: to the queue, finished by k_verify_tail
+        // with every lane busy (the code written below is overwritten there)
+        uint32_t mj[kPPT];
+#pragma unroll
+        for (int p = 0; p < kPPT; ++p) mj[p] = m[p] | (uint32_t(j0) << 16);
+        push_survivors<kPPT>(a, alive, c0, mj);
+        alive = 0;
+      }
+    }
   }
   for (int j = j0; j < L && alive; ++j) {
 #pragma unroll
@@ -405,6 +416,82 @@ __global__ __launch_bounds__(kBlock) void k_exact(VerifyArgs a) {
     fetch_candidate(a, c, xi, yi);   // ids were range-checked before the pair was queued
     const double sim = exact_wave(a, xi, yi, s_idx[w], s_val[w]);
     if (lane_id() == 0) emit_exact(a, c, sim);
+  }
+}
+
+// Algorithm 1 for the SRP candidates queued after the 128-hash prefix: one
+// lane per survivor, from its next level on; object-major rows are read 128
+// hashes per 16-byte load, word-major slabs one level at a time.
+// Decision of level j for running count m; true when the pair is decided.
+__device__ inline bool tail_decide(const VerifyArgs &a, const int *s_min, int words, int L, int j, uint32_t m,
+                                   uint8_t &code, bool &emit) {
+  if (int(m) < s_min[j]) { code = uint8_t((BLSH_PRUNED << 6) | j); return true; }
+  if (accept_bit(a.table, words, j, int(m))) { code = uint8_t((BLSH_ACCEPT_CONC << 6) | j); emit = true; return true; }
+  if (j == L - 1) { code = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); emit = true; return true; }
+  return false;
+}
+
+template <int K, bool WM>
+__global__ __launch_bounds__(kBlock) void k_verify_tail(VerifyArgs a) {
+  __shared__ int s_min[kMaxLevels];
+  if (threadIdx.x < kMaxLevels)
+    s_min[threadIdx.x] = threadIdx.x < a.n_levels ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
+  __syncthreads();
+  const int L = a.n_levels;
+  const int words = int(a.table[2]);
+  const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
+  const int64_t n = *a.q_n;
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t i0 = int64_t(blockIdx.x) * kBlock; i0 < n; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    int64_t c = 0;
+    uint32_t m = 0;
+    uint8_t code = 0;
+    bool emit = false;
+    if (i < n) {
+      c = a.c_begin + a.q_rel[i];
+      const uint32_t e = a.q_m[i];
+      m = e & 0xFFFFu;
+      int j = int(e >> 16);
+      uint32_t x, y;
+      if (a.kind == BLSH_PAIRS) {
+        x = a.x[c];
+        y = a.y[c];
+      } else {
+        fetch_candidate(a, c, x, y);
+      }
+      bool done = false;
+      if constexpr (WM) {
+        for (; j < L && !done; ++j) {
+          m += level_agree_bits<K, true>(a, x, y, j);
+          done = tail_decide(a, s_min, words, L, j, m, code, emit);
+        }
+      } else {
+        constexpr int LPC = 128 / K;   // levels per 16-byte chunk
+        while (j < L && !done) {
+          const int ch = j / LPC;
+          const u32x4 hx = *reinterpret_cast<const u32x4 *>(a.sig + size_t(x) * a.row_words + 4 * ch);
+          const u32x4 hy = *reinterpret_cast<const u32x4 *>(a.sig + size_t(y) * a.row_words + 4 * ch);
+          const uint32_t d[4] = {hx.x ^ hy.x, hx.y ^ hy.y, hx.z ^ hy.z, hx.w ^ hy.w};
+          for (; j < L && j < (ch + 1) * LPC && !done; ++j) {
+            // level within the chunk picked by selects (a register array
+            // indexed at run time would go to scratch)
+            const int jj = j - ch * LPC;
+            auto w = [d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3]](int q) {
+              return q == 0 ? d0 : q == 1 ? d1 : q == 2 ? d2 : d3;
+            };
+            if constexpr (K == 32) m += 32u - __popc(w(jj));
+            else if constexpr (K == 64) m += 64u - __popc(w(2 * jj)) - __popc(w(2 * jj + 1));
+            else m += 16u - __popc((w(jj >> 1) >> ((jj & 1) * 16)) & 0xFFFFu);
+            done = tail_decide(a, s_min, words, L, j, m, code, emit);
+          }
+        }
+      }
+      a.code[c] = code;
+      if (a.m_dbg) a.m_dbg[c] = uint16_t(m);
+    }
+    const float v = emit ? map_estimate(a.measure, int(m), ((code & 63) + 1) * K, alpha, beta) : 0.f;
+    emit_accepted(a, emit, uint64_t(c), v);
   }
 }
 
@@ -698,6 +785,20 @@ int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStrea
   LaunchScope ls(ctx, s, "exact");
   hipLaunchKernelGGL(k_exact, dim3(nb), dim3(kBlock), 0, s, a);
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, hipStream_t s) {
+  const int64_t nb = int64_t(ctx->n_cu) * 16;
+  LaunchScope ls(ctx, s, "verify_tail");
+#define BLSH_T(KK)                                                                                  \
+  if (k == KK) {                                                                                    \
+    if (word_major) hipLaunchKernelGGL((k_verify_tail<KK, true>), dim3(nb), dim3(kBlock), 0, s, a);  \
+    else hipLaunchKernelGGL((k_verify_tail<KK, false>), dim3(nb), dim3(kBlock), 0, s, a);           \
+    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                                \
+  }
+  BLSH_T(16) BLSH_T(32) BLSH_T(64)
+#undef BLSH_T
+  return fail(BLSH_EINVAL, "unsupported k=%d", k);
 }
 
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s) {

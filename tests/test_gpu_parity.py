@@ -350,6 +350,64 @@ def test_exhaustive_lite_replay(ctx):
     assert_same_as_oracle(decode_result(res, len(x)), want, lite_exact=want["exact"])
 
 
+def test_chunked_launches_past_two_to_the_28(ctx):
+    """A candidate list longer than one verify launch (2^28 candidates) and
+    than many comparator launches: the prefix verify with its survivor tail
+    and the full-signature replay give the same codes and accepted set, and a
+    seeded sample of positions (both sides of each launch boundary included)
+    matches the oracle."""
+    npairs, n_hashes, k = 4096, 1024, 32
+    n = (1 << 28) + (1 << 24) + 77
+    _flush("chunked launches n=%d" % n)
+    sig = _calib_pairs(P.COSINE, npairs, n_hashes, 909)
+    n_obj = 2 * npairs
+    # candidate i: planted pair (2j, 2j+1) with j = i * 2654435761 mod 4096, or
+    # every 7th an unrelated object as y
+    i = torch.arange(n, dtype=torch.int64, device="cuda")
+    x64 = 2 * ((i * 2654435761) % npairs)
+    y64 = torch.where(i % 7 == 0, (i * 40503) % n_obj, x64 + 1)
+    del i
+    x = x64.to(torch.int32).view(torch.uint32)
+    y = y64.to(torch.int32).view(torch.uint32)
+    del x64, y64
+    cand = P.pairs(x, y)
+    wm_pfx = P.Signatures(sigs_tensor(sig, P.COSINE, P.WORD_MAJOR).data, P.COSINE, P.WORD_MAJOR, n_obj, n_hashes,
+                          prefix=up(np.ascontiguousarray(sig[:, :4])))
+    om = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
+    cap = n
+    rv = P.make_result(n, cap)
+    P.bayeslsh_verify(ctx, cand, wm_pfx, T, EPS, DELTA, GAMMA, (1, 1), k, rv)
+    re = P.make_result(n, cap)
+    P.bayeslsh_exhaustive_verify(ctx, cand, om, None, T, EPS, DELTA, GAMMA, (1, 1), k, 0, P.REPLAY, re)
+    P.bayeslsh_sync(ctx)
+    assert torch.equal(rv.code, re.code)
+    na = int(rv.n_accepted.item())
+    assert na == int(re.n_accepted.item()) and 0 < na <= cap
+    ia, pa = torch.sort(rv.acc_idx[:na].view(torch.int64))
+    ib, pb = torch.sort(re.acc_idx[:na].view(torch.int64))
+    assert torch.equal(ia, ib)
+    assert float((rv.acc_val[:na][pa] - re.acc_val[:na][pb]).abs().max()) <= 1e-6
+    del ib, pb, re
+    # seeded sample against the oracle
+    rng = np.random.default_rng(910)
+    edges = np.array([(1 << 24) * c + d for c in range(1, 17) for d in (-1, 0)] + [(1 << 28) - 1, 1 << 28, n - 1])
+    pos = np.unique(np.concatenate([rng.integers(0, n, 20000), edges]))
+    pos_t = torch.from_numpy(pos).cuda()
+    xs = 2 * ((pos * 2654435761) % npairs)
+    ys = np.where(pos % 7 == 0, (pos * 40503) % n_obj, xs + 1)
+    xs, ys = xs.astype(np.uint32), ys.astype(np.uint32)
+    want = R.verify(xs, ys, P.COSINE, sig, k, n_hashes // k, T, EPS, DELTA, GAMMA)
+    code = rv.code[pos_t].cpu().numpy()
+    np.testing.assert_array_equal(code >> 6, want["decision"])
+    np.testing.assert_array_equal(code & 63, want["level"])
+    hit = torch.searchsorted(ia, pos_t).clamp(max=na - 1)
+    found = (ia[hit] == pos_t).cpu().numpy()
+    acc = (want["decision"] == R.DEC_CONC) | (want["decision"] == R.DEC_NMAX)
+    np.testing.assert_array_equal(found, acc)
+    vals = rv.acc_val[:na][pa][hit].cpu().numpy()
+    np.testing.assert_allclose(vals[acc], want["shat"][acc], atol=1e-6, rtol=0)
+
+
 # ---------------------------------------------------------------------------
 # edge cases and error paths
 # ---------------------------------------------------------------------------
