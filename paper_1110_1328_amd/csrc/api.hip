@@ -22,6 +22,9 @@ int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim,
 int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStream_t s);
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s);
 int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, hipStream_t s);
+int launch_zero_slices(blsh_ctx *ctx, int64_t *cnt, hipStream_t s);
+int launch_acc_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t *nxt_cnt, int64_t *nxt_total, bool last,
+                     hipStream_t s);
 int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t row_words, bool word_major,
                     int32_t n_bands, int32_t band_bits, int32_t max_bucket, uint32_t *x_out, uint32_t *y_out,
                     int64_t capacity, int64_t *n_pairs, hipStream_t s);
@@ -221,27 +224,51 @@ static void fill_cand(VerifyArgs &a, const blsh_candidates *c) {
   a.all_n = c->all_n;
 }
 
-// Survivor queue inside the context workspace, sized for `chunk` candidates:
-//   [0, 256)                       q_n (int64) + padding
-//   [256, 256 + 4*chunk)           q_rel (candidate index relative to the chunk start)
-//   [256 + 4*chunk, 256 + 8*chunk) q_m (m | next level << 16; SRP tail only)
+// Buffers of one verify call, for launches of at most `chunk` candidates.
+// Counters (the context's slice buffer), kCntStride int64 apart:
+//   [0, S)           staging counts, set 0
+//   [S, 2S)          staging counts, set 1
+//   [2S, 3S)         survivor-queue counts
+//   3S, 3S + 1       running accepted count of set 0, set 1
+// Context workspace:
+//   q_rel [, q_m]    kSlices survivor-queue slices of q_cap entries: a launch
+//                    of n candidates puts at most ceil((n + 1024) / kSlices) +
+//                    256 entries in one slice (every kernel's waves take at most
+//                    256 candidates and its blocks at most 1024, and wave w
+//                    uses slice w % kSlices), so a slice never overflows
+//   st_rel, st_val   kSlices accepted-pair staging slices of st_cap entries
 static constexpr int64_t kChunk = int64_t(1) << 28;
 static constexpr int64_t kExhChunk = int64_t(1) << 24;
+static constexpr int64_t kStageDefault = int64_t(1) << 24;
+static constexpr size_t kSliceBufWords = (size_t(3) * kSlices + 2) * kCntStride;
 
-struct Queue {
-  int64_t *n;
-  uint32_t *rel;
-  uint32_t *m;
+struct Workspace {
+  int64_t *cnt;   // the context's counter buffer
+  uint32_t *q_rel, *q_m;
+  int64_t q_cap;
+  uint32_t *st_rel;
+  float *st_val;
+  int64_t st_cap;
 };
 
-static int get_queue(blsh_ctx *ctx, int64_t chunk, bool with_m, Queue *q) {
-  const size_t bytes = 256 + size_t(chunk) * (with_m ? 8 : 4);
-  int rc = ensure_workspace(ctx, bytes);
+static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static int get_workspace(blsh_ctx *ctx, int64_t chunk, bool queue, bool with_m, Workspace *w) {
+  const int64_t S = kSlices;
+  w->q_cap = queue ? (chunk + 1024 + S - 1) / S + 256 : 0;
+  const int64_t stage = ctx->tuning.acc_stage_cap > 0 ? int64_t(ctx->tuning.acc_stage_cap) : kStageDefault;
+  w->st_cap = (std::min<int64_t>(chunk, stage) + S - 1) / S;
+  const size_t q_bytes = align256(size_t(S) * w->q_cap * 4);
+  const size_t st_bytes = align256(size_t(S) * w->st_cap * 4);
+  int rc = ensure_workspace(ctx, q_bytes * (with_m ? 2 : 1) + 2 * st_bytes);
   if (rc) return rc;
-  char *base = static_cast<char *>(ctx->ws);
-  q->n = reinterpret_cast<int64_t *>(base);
-  q->rel = reinterpret_cast<uint32_t *>(base + 256);
-  q->m = with_m ? reinterpret_cast<uint32_t *>(base + 256 + size_t(chunk) * 4) : nullptr;
+  w->cnt = ctx->d_slices;
+  char *p = static_cast<char *>(ctx->ws);
+  w->q_rel = queue ? reinterpret_cast<uint32_t *>(p) : nullptr;
+  w->q_m = queue && with_m ? reinterpret_cast<uint32_t *>(p + q_bytes) : nullptr;
+  p += q_bytes * (with_m ? 2 : 1);
+  w->st_rel = reinterpret_cast<uint32_t *>(p);
+  w->st_val = reinterpret_cast<float *>(p + st_bytes);
   return BLSH_OK;
 }
 
@@ -319,33 +346,49 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   a.count_levels = n_max / k;
   a.t = t;
   if (n_cand == 0) return launch_zero(ctx, res->n_accepted, nullptr, s) ? fail(BLSH_EDEVICE, "launch failed") : BLSH_OK;
-  Queue q{};
   // SRP Algorithm 1 with a prefix view: candidates undecided after the first
   // 128 hashes are queued and finished by a second kernel with every lane busy
   const bool tail = !exh && !lite && sigs->measure == BLSH_COSINE && a.pfx != nullptr && 128 / k < n_levels;
-  const bool queued = lite || tail;
+  // the SRP early-exit kernel computes Lite exact similarities itself
+  const bool fused_exact = lite && exhaustive_mode == -1 && sigs->measure == BLSH_COSINE;
+  const bool queued = (lite && !fused_exact) || tail;
   // launches are chunked so that no grid exceeds 2^32 work-items (the
   // dispatch's grid size): the comparator runs up to 64 lanes per candidate
   const int64_t chunk = std::min<int64_t>(n_cand, exh ? kExhChunk : kChunk);
-  if (queued && (rc = get_queue(ctx, chunk, tail, &q))) return rc;
-  a.q_rel = q.rel;
-  a.q_m = q.m;
-  a.q_n = q.n;
+  Workspace w{};
+  if ((rc = get_workspace(ctx, chunk, queued, tail, &w))) return rc;
+  a.q_rel = w.q_rel;
+  a.q_m = w.q_m;
+  a.q_cnt = w.cnt + size_t(2) * kSlices * kCntStride;
+  a.q_cap = w.q_cap;
+  a.st_rel = w.st_rel;
+  a.st_val = w.st_val;
+  a.st_cap = w.st_cap;
   if (lite) fill_exact(a, exact);
-  // the SRP early-exit kernel computes Lite exact similarities itself
-  const bool fused_exact = lite && exhaustive_mode == -1 && sigs->measure == BLSH_COSINE;
+  // the counters of the next set are zero unless an earlier call stopped
+  // before its last flush
+  if (ctx->slices_dirty) {
+    if ((rc = launch_zero_slices(ctx, w.cnt, s))) return fail(rc, "launch failed");
+    ctx->slices_dirty = false;
+  }
+  auto set_cnt = [&](int set) { return w.cnt + size_t(set) * kSlices * kCntStride; };
+  auto set_total = [&](int set) { return w.cnt + (size_t(3) * kSlices + set) * kCntStride; };
   for (int64_t c0 = 0; c0 < n_cand; c0 += chunk) {
     a.c_begin = c0;
     a.c_end = std::min(n_cand, c0 + chunk);
-    // one launch clears the output count (first chunk) and the survivor queue count
-    if ((c0 == 0 || queued) && (rc = launch_zero(ctx, c0 == 0 ? res->n_accepted : nullptr, queued ? q.n : nullptr, s)))
-      return fail(rc, "launch failed");
+    const int cur = ctx->slice_set, nxt = cur ^ 1;
+    a.acc_cnt = set_cnt(cur);
+    a.acc_total = set_total(cur);
     const bool wm = sigs->measure == BLSH_COSINE && sigs->layout == BLSH_WORD_MAJOR;
+    ctx->slices_dirty = true;
     rc = exh ? launch_exhaustive(ctx, a, k, s) : launch_verify(ctx, a, k, lite, wm, s);
     if (!rc && tail) rc = launch_verify_tail(ctx, a, k, wm, s);
+    if (!rc && queued && !tail) rc = launch_exact(ctx, a, a.c_end - a.c_begin, s);
+    if (!rc) rc = launch_acc_flush(ctx, a, set_cnt(nxt), set_total(nxt), a.c_end == n_cand, s);
     if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;
-    if (lite && !fused_exact && (rc = launch_exact(ctx, a, a.c_end - a.c_begin, s))) return fail(rc, "exact launch failed");
+    ctx->slice_set = nxt;
   }
+  ctx->slices_dirty = false;
   return BLSH_OK;
 }
 
@@ -379,6 +422,18 @@ int bayeslsh_create(blsh_ctx **out, int device) {
     delete c;
     return fail(BLSH_EDEVICE, "status init failed");
   }
+  if (hipMalloc(&c->d_slices, kSliceBufWords * sizeof(int64_t)) != hipSuccess) {
+    hipFree(c->d_status);
+    delete c;
+    return fail(BLSH_ENOMEM, "counter allocation failed");
+  }
+  if (hipMemset(c->d_slices, 0, kSliceBufWords * sizeof(int64_t)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    hipFree(c->d_slices);
+    hipFree(c->d_status);
+    delete c;
+    return fail(BLSH_EDEVICE, "counter init failed");
+  }
   *out = c;
   return BLSH_OK;
 }
@@ -392,6 +447,7 @@ void bayeslsh_destroy(blsh_ctx *ctx) {
   if (ctx->batch && ctx->batch_free) ctx->batch_free(ctx->batch);
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->d_status) hipFree(ctx->d_status);
+  if (ctx->d_slices) hipFree(ctx->d_slices);
   delete ctx;
 }
 
@@ -458,7 +514,9 @@ int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
   if (t->batch_blocks_per_cu < 0 || t->batch_blocks_per_cu > 32)
     return fail(BLSH_EINVAL, "tuning.batch_blocks_per_cu must be in [0, 32]");
   if (t->batch_spill_cap < 0) return fail(BLSH_EINVAL, "tuning.batch_spill_cap < 0");
+  if (t->acc_stage_cap < 0) return fail(BLSH_EINVAL, "tuning.acc_stage_cap < 0");
   ctx->tuning.gather = t->gather;
+  ctx->tuning.acc_stage_cap = t->acc_stage_cap;
   ctx->tuning.batch_spill_cap = t->batch_spill_cap;
   ctx->tuning.batch_inreg = t->batch_inreg;
   ctx->tuning.batch_blocks_per_cu = t->batch_blocks_per_cu;

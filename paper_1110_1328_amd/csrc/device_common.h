@@ -42,10 +42,22 @@ struct VerifyArgs {
   uint16_t *m_dbg;
   // survivor queue: candidate index relative to c_begin (Lite survivors, and
   // SRP candidates undecided after the 128-hash prefix when q_m is set: then
-  // q_m holds m | next level << 16 for the tail kernel)
+  // q_m holds m | next level << 16 for the tail kernel).  kSlices slices of
+  // q_cap entries; the count of slice s is q_cnt[s * kCntStride].
   uint32_t *q_rel;
   uint32_t *q_m;
-  int64_t *q_n;
+  int64_t *q_cnt;
+  int64_t q_cap;
+  // accepted-pair staging: kSlices slices of st_cap entries (index relative to
+  // c_begin, value), counts at acc_cnt[s * kCntStride], appended to the
+  // caller's list by k_acc_flush; entries that find their slice full go to the
+  // list directly.  Positions in the list come from the running count
+  // *acc_total; the last flush of a call stores it to *n_acc.
+  int64_t *acc_cnt;
+  uint32_t *st_rel;
+  float *st_val;
+  int64_t st_cap;
+  int64_t *acc_total;
   int32_t *status;
   // exact similarity (Lite): the caller's vectors
   int32_t ex_kind;
@@ -61,6 +73,18 @@ struct VerifyArgs {
 };
 
 __device__ inline int lane_id() { return __lane_id(); }
+
+// Device-scope atomics on one address (or one cache line) serialise at the
+// memory side, about 12 ns apiece on MI355X; spread over counters on lines of
+// their own they run concurrently.  Queue and staging counts are therefore
+// split into kSlices slices, 256 bytes apart, and a wave uses the slice of its
+// launch-wide wave number.
+constexpr int kSlices = 256;
+constexpr int kCntStride = 32;   // int64 words between slice counters (256 B)
+
+__device__ inline int wave_slice() {
+  return __builtin_amdgcn_readfirstlane(int((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kSlices - 1)));
+}
 
 __device__ inline double wave_sum_f64(double v) {
 #pragma unroll
@@ -153,14 +177,13 @@ __device__ inline bool accept_bit(const uint32_t *tab, int words, int j, int m) 
   return (tab[kTabAccOff + j * words + (m >> 5)] >> (m & 31)) & 1u;
 }
 
-// Wave-level compaction of (idx, val) into the accepted list; called in
-// converged control flow by every active lane of the wave.
-__device__ inline void emit_accepted(const VerifyArgs &a, bool pred, uint64_t idx, float val) {
+// Accepted list, direct: one atomic on the running count per call.
+__device__ inline void emit_direct(const VerifyArgs &a, bool pred, uint64_t idx, float val) {
   const uint64_t mask = __ballot(pred);
   if (mask == 0) return;
   const int leader = __ffsll((unsigned long long)mask) - 1;
   unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd((unsigned long long *)a.n_acc, (unsigned long long)__popcll(mask));
+  if (lane_id() == leader) base = atomicAdd((unsigned long long *)a.acc_total, (unsigned long long)__popcll(mask));
   base = __shfl(base, leader);
   if (pred) {
     const unsigned long long pos = base + lanes_below(mask);
@@ -173,16 +196,50 @@ __device__ inline void emit_accepted(const VerifyArgs &a, bool pred, uint64_t id
   }
 }
 
+// Wave-level compaction of (idx, val) into the wave's staging slice (the
+// caller's list for entries past the slice's capacity); called in converged
+// control flow by every active lane.
+__device__ inline void emit_accepted(const VerifyArgs &a, bool pred, uint64_t idx, float val) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return;
+  {
+    const int s = wave_slice();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader)
+      base = atomicAdd((unsigned long long *)(a.acc_cnt + s * kCntStride), (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader);
+    const unsigned long long pos = base + lanes_below(mask);
+    if (pred && int64_t(pos) < a.st_cap) {
+      a.st_rel[size_t(s) * a.st_cap + pos] = uint32_t(idx - uint64_t(a.c_begin));
+      a.st_val[size_t(s) * a.st_cap + pos] = val;
+      pred = false;
+    }
+  }
+  emit_direct(a, pred, idx, val);
+}
+
+// Position of a wave's `total` new entries in its survivor-queue slice (valid
+// in every lane); the queue is sized so that a slice never overflows, and an
+// entry past q_cap would be dropped with BLSH_EDEVICE raised.
+__device__ inline int64_t queue_reserve(const VerifyArgs &a, int s, uint32_t total, int leader) {
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd((unsigned long long *)(a.q_cnt + s * kCntStride), (unsigned long long)total);
+  return int64_t(__shfl(base, leader));
+}
+
 // Wave-level compaction of Lite survivors into the exact-similarity queue
 // (entries are candidate indices relative to the launch's c_begin).
 __device__ inline void push_survivor(const VerifyArgs &a, bool pred, int64_t c) {
   const uint64_t mask = __ballot(pred);
   if (mask == 0) return;
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd((unsigned long long *)a.q_n, (unsigned long long)__popcll(mask));
-  base = __shfl(base, leader);
-  if (pred) a.q_rel[base + lanes_below(mask)] = uint32_t(c - a.c_begin);
+  const int s = wave_slice();
+  const int64_t base = queue_reserve(a, s, uint32_t(__popcll(mask)), __ffsll((unsigned long long)mask) - 1);
+  if (pred) {
+    const int64_t pos = base + lanes_below(mask);
+    if (pos < a.q_cap) a.q_rel[size_t(s) * a.q_cap + pos] = uint32_t(c - a.c_begin);
+    else raise_status(a.status, BLSH_EDEVICE);
+  }
 }
 
 // Wave-level compaction of a lane's P candidates (bit p of `want`: candidate
@@ -198,15 +255,20 @@ __device__ inline void push_survivors(const VerifyArgs &a, uint32_t want, int64_
     total += uint32_t(__popcll(mask[p]));
   }
   if (total == 0) return;
-  unsigned long long base = 0;
-  if (lane_id() == 0) base = atomicAdd((unsigned long long *)a.q_n, (unsigned long long)total);
-  base = (unsigned long long)__shfl((long long)base, 0);
+  const int s = wave_slice();
+  int64_t base = queue_reserve(a, s, total, 0);
+  uint32_t *rel = a.q_rel + size_t(s) * a.q_cap;
+  uint32_t *qm = a.q_m + size_t(s) * a.q_cap;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     if ((want >> p) & 1u) {
-      const unsigned long long pos = base + lanes_below(mask[p]);
-      a.q_rel[pos] = uint32_t(c0 + p - a.c_begin);
-      a.q_m[pos] = mj[p];
+      const int64_t pos = base + lanes_below(mask[p]);
+      if (pos < a.q_cap) {
+        rel[pos] = uint32_t(c0 + p - a.c_begin);
+        qm[pos] = mj[p];
+      } else {
+        raise_status(a.status, BLSH_EDEVICE);
+      }
     }
     base += __popcll(mask[p]);
   }

@@ -78,6 +78,14 @@ struct blsh_ctx {
   std::map<blsh::TableKey, blsh::DevTable> dev_tables;
   // device status word: first error raised by a kernel (0 = none)
   int32_t *d_status = nullptr;
+  // counters of the single-call verification paths: two sets of staging
+  // slice counts (launches alternate between them; slice_set names the next
+  // one, whose counts and running count are zero between calls), the queue
+  // slice counts, the two running accepted counts; slices_dirty: a call
+  // stopped before its last flush
+  int64_t *d_slices = nullptr;
+  int slice_set = 0;
+  bool slices_dirty = false;
   // survivor workspace
   void *ws = nullptr;
   size_t ws_bytes = 0;

@@ -136,16 +136,23 @@ __device__ double exact_wave(const VerifyArgs &a, uint32_t xi, uint32_t yi, uint
   return uni > 0 ? double(inter) / double(uni) : 0.0;
 }
 
-// Emission of one Lite survivor's exact similarity (called by lane 0).
+// Emission of one Lite survivor's exact similarity (called by lane 0): into
+// the wave's staging slice, or the caller's list when that is full.
 __device__ inline void emit_exact(const VerifyArgs &a, int64_t c, double s) {
-  if (s > a.t) {
-    const unsigned long long pos = atomicAdd((unsigned long long *)a.n_acc, 1ull);
-    if (int64_t(pos) < a.acc_cap) {
-      a.acc_idx[pos] = uint64_t(c);
-      a.acc_val[pos] = float(s);
-    } else {
-      raise_status(a.status, BLSH_ETRUNCATED);
-    }
+  if (!(s > a.t)) return;
+  const int sl = wave_slice();
+  const unsigned long long spos = atomicAdd((unsigned long long *)(a.acc_cnt + sl * kCntStride), 1ull);
+  if (int64_t(spos) < a.st_cap) {
+    a.st_rel[size_t(sl) * a.st_cap + spos] = uint32_t(c - a.c_begin);
+    a.st_val[size_t(sl) * a.st_cap + spos] = float(s);
+    return;
+  }
+  const unsigned long long pos = atomicAdd((unsigned long long *)a.acc_total, 1ull);
+  if (int64_t(pos) < a.acc_cap) {
+    a.acc_idx[pos] = uint64_t(c);
+    a.acc_val[pos] = float(s);
+  } else {
+    raise_status(a.status, BLSH_ETRUNCATED);
   }
 }
 
@@ -404,14 +411,19 @@ __global__ __launch_bounds__(kBlock) void k_verify_minhash(VerifyArgs a) {
 
 
 // One wave per queued pair (Lite survivors of the minhash and exhaustive paths).
+// The grid holds a multiple of kSlices waves: wave g serves queue slice
+// g % kSlices together with the other waves of that slice.
 __global__ __launch_bounds__(kBlock) void k_exact(VerifyArgs a) {
   __shared__ uint32_t s_idx[kBlock / kWave][kExactLds];
   __shared__ float s_val[kBlock / kWave][kExactLds];
   const int w = threadIdx.x >> 6;
-  const int64_t n = *a.q_n;
-  const int64_t waves = int64_t(gridDim.x) * (kBlock / kWave);
-  for (int64_t q = int64_t(blockIdx.x) * (kBlock / kWave) + w; q < n; q += waves) {
-    const int64_t c = a.c_begin + a.q_rel[q];
+  const int64_t g = int64_t(blockIdx.x) * (kBlock / kWave) + w;
+  const int sl = int(g % kSlices);
+  const int64_t parts = int64_t(gridDim.x) * (kBlock / kWave) / kSlices;
+  const int64_t n = min(a.q_cnt[sl * kCntStride], a.q_cap);
+  const uint32_t *rel = a.q_rel + size_t(sl) * a.q_cap;
+  for (int64_t q = g / kSlices; q < n; q += parts) {
+    const int64_t c = a.c_begin + rel[q];
     uint32_t xi, yi;
     fetch_candidate(a, c, xi, yi);   // ids were range-checked before the pair was queued
     const double sim = exact_wave(a, xi, yi, s_idx[w], s_val[w]);
@@ -440,17 +452,22 @@ __global__ __launch_bounds__(kBlock) void k_verify_tail(VerifyArgs a) {
   const int L = a.n_levels;
   const int words = int(a.table[2]);
   const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
-  const int64_t n = *a.q_n;
-  const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t i0 = int64_t(blockIdx.x) * kBlock; i0 < n; i0 += stride) {
+  // the grid is a multiple of kSlices blocks: block b serves queue slice
+  // b % kSlices together with the other blocks of that slice
+  const int sl = int(blockIdx.x % kSlices);
+  const int64_t n = min(a.q_cnt[sl * kCntStride], a.q_cap);
+  const uint32_t *rel = a.q_rel + size_t(sl) * a.q_cap;
+  const uint32_t *qm = a.q_m + size_t(sl) * a.q_cap;
+  const int64_t stride = int64_t(gridDim.x / kSlices) * kBlock;
+  for (int64_t i0 = int64_t(blockIdx.x / kSlices) * kBlock; i0 < n; i0 += stride) {
     const int64_t i = i0 + threadIdx.x;
     int64_t c = 0;
     uint32_t m = 0;
     uint8_t code = 0;
     bool emit = false;
     if (i < n) {
-      c = a.c_begin + a.q_rel[i];
-      const uint32_t e = a.q_m[i];
+      c = a.c_begin + rel[i];
+      const uint32_t e = qm[i];
       m = e & 0xFFFFu;
       int j = int(e >> 16);
       uint32_t x, y;
@@ -705,6 +722,70 @@ __global__ void k_zero_i64(int64_t *p, int64_t *q) {
   if (threadIdx.x == 1 && q) *q = 0;
 }
 
+// Clears every counter of the single-call paths (both staging-count sets and
+// running counts, the queue counts): one block of kSlices threads.  Only
+// needed after a call that stopped before its last flush.
+__global__ void k_zero_slices(int64_t *cnt) {
+  for (int i = 0; i < 3; ++i) cnt[(size_t(i) * kSlices + threadIdx.x) * kCntStride] = 0;
+  if (threadIdx.x < 2) cnt[(size_t(3) * kSlices + threadIdx.x) * kCntStride] = 0;
+}
+
+// After each launch (chunk), one block per staging slice, no atomics: every
+// block reads the kSlices counts of the launch's staging set (a.acc_cnt) and
+// the running count (*a.acc_total), and block s copies slice s to the
+// caller's list after the slices before it.  The next launch uses the other
+// set (nxt_cnt, *nxt_total): block 0 clears its counts and stores the new
+// running count there, or 0 and *n_acc on the call's last launch.  Block s
+// also clears queue count s.
+__global__ __launch_bounds__(kBlock) void k_acc_flush(VerifyArgs a, int64_t *nxt_cnt, int64_t *nxt_total, int last) {
+  static_assert(kSlices == kBlock, "one staging slice per thread of a block");
+  __shared__ int64_t s_cnt[kSlices];
+  __shared__ int64_t s_base, s_total;
+  const int t = threadIdx.x, sl = blockIdx.x;
+  int64_t c = min(a.acc_cnt[size_t(t) * kCntStride], a.st_cap);
+  // inclusive scan of the slice counts across the block (wave scan, then
+  // the four wave totals)
+  int64_t v = c;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t u = __shfl_up(v, o);
+    if (lane_id() >= o) v += u;
+  }
+  s_cnt[t] = v;
+  __syncthreads();
+  int64_t before = 0;
+  for (int w = 0; w < (t >> 6); ++w) before += s_cnt[w * kWave + kWave - 1];
+  __syncthreads();
+  s_cnt[t] = before + v - c;   // exclusive prefix
+  if (t == kSlices - 1) s_total = before + v;
+  if (t == 0) s_base = *a.acc_total;
+  __syncthreads();
+  const int64_t n = min(a.acc_cnt[size_t(sl) * kCntStride], a.st_cap);
+  const int64_t base = s_base + s_cnt[sl];
+  const uint32_t *rel = a.st_rel + size_t(sl) * a.st_cap;
+  const float *val = a.st_val + size_t(sl) * a.st_cap;
+  bool trunc = false;
+  for (int64_t i = t; i < n; i += kBlock) {
+    const int64_t pos = base + i;
+    if (pos < a.acc_cap) {
+      a.acc_idx[pos] = uint64_t(a.c_begin) + rel[i];
+      a.acc_val[pos] = val[i];
+    } else {
+      trunc = true;
+    }
+  }
+  if (trunc) raise_status(a.status, BLSH_ETRUNCATED);
+  if (t == 0 && a.q_cnt) a.q_cnt[size_t(sl) * kCntStride] = 0;
+  if (sl == 0) {
+    nxt_cnt[size_t(t) * kCntStride] = 0;
+    if (t == 0) {
+      const int64_t total = s_base + s_total;
+      *nxt_total = last ? 0 : total;
+      if (last) *a.n_acc = total;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -779,16 +860,21 @@ int launch_exhaustive(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s) 
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
+// Grids of the queue consumers: a multiple of kSlices waves (k_exact) or
+// blocks (k_verify_tail), at least one per slice.
+static inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
 int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStream_t s) {
   if (max_items <= 0) return BLSH_OK;
-  const int64_t nb = std::min<int64_t>(blocks_for(max_items, kBlock / kWave), int64_t(ctx->n_cu) * 16);
+  const int64_t nb = round_up(std::min<int64_t>(blocks_for(max_items, kBlock / kWave), int64_t(ctx->n_cu) * 16),
+                              kSlices / (kBlock / kWave));
   LaunchScope ls(ctx, s, "exact");
   hipLaunchKernelGGL(k_exact, dim3(nb), dim3(kBlock), 0, s, a);
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
 int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, hipStream_t s) {
-  const int64_t nb = int64_t(ctx->n_cu) * 16;
+  const int64_t nb = round_up(int64_t(ctx->n_cu) * 16, kSlices);
   LaunchScope ls(ctx, s, "verify_tail");
 #define BLSH_T(KK)                                                                                  \
   if (k == KK) {                                                                                    \
@@ -807,6 +893,19 @@ int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStrea
   const int64_t nb = std::min<int64_t>(blocks_for(n, kBlock / kWave), int64_t(ctx->n_cu) * 16);
   LaunchScope ls(ctx, s, "exact_pairs");
   hipLaunchKernelGGL(k_exact_pairs, dim3(nb), dim3(kBlock), 0, s, a, out);
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+int launch_zero_slices(blsh_ctx *ctx, int64_t *cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_slices, dim3(1), dim3(kSlices), 0, s, cnt);
+  (void)ctx;
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+int launch_acc_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t *nxt_cnt, int64_t *nxt_total, bool last,
+                     hipStream_t s) {
+  LaunchScope ls(ctx, s, "acc_flush");
+  hipLaunchKernelGGL(k_acc_flush, dim3(kSlices), dim3(kBlock), 0, s, a, nxt_cnt, nxt_total, int(last));
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 

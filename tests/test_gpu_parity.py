@@ -408,6 +408,74 @@ def test_chunked_launches_past_two_to_the_28(ctx):
     np.testing.assert_allclose(vals[acc], want["shat"][acc], atol=1e-6, rtol=0)
 
 
+STAGE_SLICES = 256   # staging slices of the library: acc_stage_cap = 256 leaves one entry per slice
+
+
+def test_accepted_staging_overflow(ctx):
+    """With one staging entry per slice almost every accepted pair takes the
+    direct path: Algorithm 1 (SRP with and without the survivor tail, minhash),
+    Lite (fused SRP exact, minhash exact queue) and the comparator still give
+    the oracle's output, and truncation still reports the true count."""
+    _flush("staging overflow")
+    P.bayeslsh_set_tuning(ctx, acc_stage_cap=STAGE_SLICES)
+    try:
+        npairs = 30000 + 7
+        for measure, n_hashes in ((P.COSINE, 1024), (P.JACCARD, 256)):
+            sig = _calib_pairs(measure, npairs, n_hashes, 77 + measure)
+            x = np.arange(0, 2 * npairs, 2, dtype=np.uint32)
+            y = x + 1
+            L = n_hashes // 32
+            want = R.verify(x, y, measure, sig, 32, L, T, EPS, DELTA, GAMMA)
+            layouts = [P.OBJECT_MAJOR] if measure == P.JACCARD else [P.OBJECT_MAJOR, P.WORD_MAJOR]
+            for layout in layouts:   # cosine object-major: prefix kernel + tail
+                res = run_verify(ctx, P.pairs(up(x), up(y)), sigs_tensor(sig, measure, layout))
+                assert_same_as_oracle(decode_result(res, npairs), want)
+            S = sigs_tensor(sig, measure, P.OBJECT_MAJOR, n_max=L * 32)
+            res = P.make_result(npairs, npairs, m_debug=True)
+            P.bayeslsh_exhaustive_verify(ctx, P.pairs(up(x), up(y)), S, None, T, EPS, DELTA, GAMMA, (1, 1), 32, 0,
+                                         P.REPLAY, res)
+            P.bayeslsh_sync(ctx)
+            assert_same_as_oracle(decode_result(res, npairs), want)
+            n_acc = int(((want["decision"] == R.DEC_CONC) | (want["decision"] == R.DEC_NMAX)).sum())
+            assert n_acc > 10 * STAGE_SLICES
+            res = P.make_result(npairs, n_acc // 3)
+            P.bayeslsh_verify(ctx, P.pairs(up(x), up(y)), sigs_tensor(sig, measure, P.OBJECT_MAJOR), T, EPS, DELTA,
+                              GAMMA, (1, 1), 32, res)
+            with pytest.raises(P.BayesLSHError) as e:
+                P.bayeslsh_sync(ctx)
+            assert e.value.code == -4
+            assert int(res.n_accepted.item()) == n_acc
+        # Lite: fused SRP exact and the minhash exact queue
+        n_obj = 4000
+        sig = _calib_pairs(P.COSINE, n_obj // 2, 512, 78, lo=0.6)
+        dense = np.random.default_rng(79).standard_normal((n_obj, 16)).astype(np.float32)
+        dense[1::2] = dense[0::2] + 0.05 * dense[1::2]
+        x = np.arange(0, n_obj, 2, dtype=np.uint32)
+        y = x + 1
+        want = R.lite_finish(R.verify(x, y, P.COSINE, sig, 32, 4, 0.5, EPS, 0, 0, lite=True),
+                             lambda p, q: R.exact_cosine_dense(dense, p, q), x, y, 0.5)
+        assert want["accepted"].sum() > 10 * STAGE_SLICES // 8
+        res = P.make_result(len(x), len(x), m_debug=True)
+        P.bayeslsh_lite_verify(ctx, P.pairs(up(x), up(y)), sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR),
+                               P.dense_vectors(up(dense)), 0.5, EPS, (1, 1), 128, 32, res)
+        P.bayeslsh_sync(ctx)
+        assert_same_as_oracle(decode_result(res, len(x)), want, lite_exact=want["exact"])
+        sets = G.jaccard_sets(n_sets=1200, vocab=20_000, n_groups=200, seed=G.SEED_BASE + 80)
+        a, b = G.minhash_coeffs(128, G.SEED_BASE + 81)
+        msig = R.minhash_signatures(sets.offsets, sets.elems, a, b)
+        i, j = np.triu_indices(300, 1)
+        x, y = i.astype(np.uint32), j.astype(np.uint32)
+        want = R.lite_finish(R.verify(x, y, P.JACCARD, msig, 32, 2, 0.3, EPS, 0, 0, lite=True),
+                             lambda p, q: R.exact_jaccard(sets.offsets, sets.elems, p, q), x, y, 0.3)
+        res = P.make_result(len(x), len(x), m_debug=True)
+        P.bayeslsh_lite_verify(ctx, P.pairs(up(x), up(y)), sigs_tensor(msig, P.JACCARD, P.OBJECT_MAJOR),
+                               sets_device(sets), 0.3, EPS, (1, 1), 64, 32, res)
+        P.bayeslsh_sync(ctx)
+        assert_same_as_oracle(decode_result(res, len(x)), want, lite_exact=want["exact"])
+    finally:
+        P.bayeslsh_set_tuning(ctx)
+
+
 # ---------------------------------------------------------------------------
 # edge cases and error paths
 # ---------------------------------------------------------------------------
