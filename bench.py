@@ -369,7 +369,7 @@ def run_serving(args, torch, P):
 
 def run_dense(args, torch, P):
     """Dense cosine estimation: 1M x 256 Gaussian-mixture vectors, 1024 SRP bits
-    (word-major + prefix array) for verification; candidates from GPU LSH
+    (object-major rows + prefix array) for verification; candidates from GPU LSH
     banding (16 bands x 12 bits of an independent 192-bit projection); then
     Algorithm 1 (t = 0.8, eps = gamma = 0.03, delta = 0.05, k = 32, n_max = 1024)
     over every candidate, against the exhaustive REPLAY comparator (object-major
@@ -380,9 +380,9 @@ def run_dense(args, torch, P):
     t, eps, delta, gamma, k = 0.8, 0.03, 0.05, 0.03, 32
     ctx = P.bayeslsh_create(0)
     log("dense index (1M x 256, 1024 verification bits)")
-    mix, (S_wm, S_om) = dense_index(torch, P, ctx, (P.WORD_MAJOR, P.OBJECT_MAJOR), prefix=True)
+    mix, (S_pfx,) = dense_index(torch, P, ctx, (P.OBJECT_MAJOR,), prefix=True)
     n_obj = mix.x.shape[0]
-    S_om = P.Signatures(S_om.data, P.COSINE, P.OBJECT_MAJOR, n_obj, 1024)
+    S_om = P.Signatures(S_pfx.data, P.COSINE, P.OBJECT_MAJOR, n_obj, 1024)
     band_planes = up(torch, G.gaussian_planes(256, 192, G.SEED_BASE + 104))
     band_sig = torch.empty(n_obj * 6, dtype=torch.int32, device="cuda").view(torch.uint32)
     xd = up(torch, mix.x)
@@ -417,7 +417,7 @@ def run_dense(args, torch, P):
         P.bayeslsh_sync(ctx, stream)
         return el * 1e3 / steps
 
-    ms = timed(lambda: P.bayeslsh_verify(ctx, cand, S_wm, t, eps, delta, gamma, (1, 1), k, res, stream), 5)
+    ms = timed(lambda: P.bayeslsh_verify(ctx, cand, S_pfx, t, eps, delta, gamma, (1, 1), k, res, stream), 5)
     log("BayesLSH: %.3f ms (%.3g pairs/s)" % (ms, n / ms * 1e3))
     ms_ex = timed(lambda: P.bayeslsh_exhaustive_verify(ctx, cand, S_om, None, t, eps, delta, gamma, (1, 1), k, 0,
                                                        P.REPLAY, res_ex, stream), 2)

@@ -21,7 +21,7 @@ int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim,
 
 int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStream_t s);
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s);
-int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, hipStream_t s);
+int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, int words, hipStream_t s);
 int launch_zero_slices(blsh_ctx *ctx, int64_t *cnt, hipStream_t s);
 int launch_acc_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t *nxt_cnt, int64_t *nxt_total, bool last,
                      hipStream_t s);
@@ -382,7 +382,7 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
     const bool wm = sigs->measure == BLSH_COSINE && sigs->layout == BLSH_WORD_MAJOR;
     ctx->slices_dirty = true;
     rc = exh ? launch_exhaustive(ctx, a, k, s) : launch_verify(ctx, a, k, lite, wm, s);
-    if (!rc && tail) rc = launch_verify_tail(ctx, a, k, wm, s);
+    if (!rc && tail) rc = launch_verify_tail(ctx, a, k, wm, (n_levels * k + 1 + 31) / 32, s);
     if (!rc && queued && !tail) rc = launch_exact(ctx, a, a.c_end - a.c_begin, s);
     if (!rc) rc = launch_acc_flush(ctx, a, set_cnt(nxt), set_total(nxt), a.c_end == n_cand, s);
     if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;

@@ -432,26 +432,34 @@ __global__ __launch_bounds__(kBlock) void k_exact(VerifyArgs a) {
 }
 
 // Algorithm 1 for the SRP candidates queued after the 128-hash prefix: one
-// lane per survivor, from its next level on; object-major rows are read 128
-// hashes per 16-byte load, word-major slabs one level at a time.
-// Decision of level j for running count m; true when the pair is decided.
-__device__ inline bool tail_decide(const VerifyArgs &a, const int *s_min, int words, int L, int j, uint32_t m,
-                                   uint8_t &code, bool &emit) {
-  if (int(m) < s_min[j]) { code = uint8_t((BLSH_PRUNED << 6) | j); return true; }
-  if (accept_bit(a.table, words, j, int(m))) { code = uint8_t((BLSH_ACCEPT_CONC << 6) | j); emit = true; return true; }
-  if (j == L - 1) { code = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); emit = true; return true; }
-  return false;
+// lane per queued pair, from its next level on.  On object-major rows a step
+// loads the next two 16-byte chunks of both sides, every load issued before
+// any is used, so one round trip serves 256 / K levels; on word-major slabs,
+// where every word is a gather of its own, a step loads one level's words.
+// minMatches and the accept bits sit in LDS (the decision of a level costs no
+// memory round trip).
+// Agreeing hashes of level q of the 8 loaded words (q < 256 / K; q is a
+// constant after unrolling, so every word index is too).
+template <int K>
+__device__ inline uint32_t agree_at(const uint32_t (&d)[8], int q) {
+  if constexpr (K == 32) return 32u - __popc(d[q]);
+  else if constexpr (K == 64) return 64u - __popc(d[2 * q]) - __popc(d[2 * q + 1]);
+  else return 16u - __popc((d[q >> 1] >> ((q & 1) * 16)) & 0xFFFFu);
 }
 
 template <int K, bool WM>
 __global__ __launch_bounds__(kBlock) void k_verify_tail(VerifyArgs a) {
+  extern __shared__ uint32_t s_acc[];   // n_levels * words accept-bit words
   __shared__ int s_min[kMaxLevels];
-  if (threadIdx.x < kMaxLevels)
-    s_min[threadIdx.x] = threadIdx.x < a.n_levels ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
-  __syncthreads();
   const int L = a.n_levels;
   const int words = int(a.table[2]);
+  if (threadIdx.x < kMaxLevels)
+    s_min[threadIdx.x] = threadIdx.x < L ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
+  for (int i = threadIdx.x; i < L * words; i += kBlock) s_acc[i] = a.table[kTabAccOff + i];
+  __syncthreads();
   const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
+  constexpr int kStepWords = WM ? (K == 64 ? 2 : 1) : 8;   // words of each side per step
+  constexpr int kStepLevels = kStepWords * 32 / K;
   // the grid is a multiple of kSlices blocks: block b serves queue slice
   // b % kSlices together with the other blocks of that slice
   const int sl = int(blockIdx.x % kSlices);
@@ -478,31 +486,53 @@ __global__ __launch_bounds__(kBlock) void k_verify_tail(VerifyArgs a) {
         fetch_candidate(a, c, x, y);
       }
       bool done = false;
-      if constexpr (WM) {
-        for (; j < L && !done; ++j) {
-          m += level_agree_bits<K, true>(a, x, y, j);
-          done = tail_decide(a, s_min, words, L, j, m, code, emit);
+      while (!done) {
+        // words [w0, w0 + 8) of both sides (w0: first word of level j; a
+        // 16-byte chunk boundary for rows)
+        int w0 = j * K / 32;
+        if constexpr (!WM) w0 &= ~3;
+        const int base = w0 * 32 / K;   // level of the first loaded hashes
+        const int avail = min(kStepWords, a.row_words - w0);
+        uint32_t d[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if constexpr (WM) {
+          uint32_t hx[kStepWords], hy[kStepWords];
+#pragma unroll
+          for (int u = 0; u < kStepWords; ++u) {
+            hx[u] = a.sig[size_t(w0 + u) * a.n_obj + x];
+            hy[u] = a.sig[size_t(w0 + u) * a.n_obj + y];
+          }
+#pragma unroll
+          for (int u = 0; u < kStepWords; ++u) d[u] = hx[u] ^ hy[u];
+        } else {
+          const u32x4 hx0 = *reinterpret_cast<const u32x4 *>(a.sig + size_t(x) * a.row_words + w0);
+          const u32x4 hy0 = *reinterpret_cast<const u32x4 *>(a.sig + size_t(y) * a.row_words + w0);
+          u32x4 hx1 = hx0, hy1 = hy0;
+          if (avail > 4) {
+            hx1 = *reinterpret_cast<const u32x4 *>(a.sig + size_t(x) * a.row_words + w0 + 4);
+            hy1 = *reinterpret_cast<const u32x4 *>(a.sig + size_t(y) * a.row_words + w0 + 4);
+          }
+          d[0] = hx0.x ^ hy0.x; d[1] = hx0.y ^ hy0.y; d[2] = hx0.z ^ hy0.z; d[3] = hx0.w ^ hy0.w;
+          d[4] = hx1.x ^ hy1.x; d[5] = hx1.y ^ hy1.y; d[6] = hx1.z ^ hy1.z; d[7] = hx1.w ^ hy1.w;
         }
-      } else {
-        constexpr int LPC = 128 / K;   // levels per 16-byte chunk
-        while (j < L && !done) {
-          const int ch = j / LPC;
-          const u32x4 hx = *reinterpret_cast<const u32x4 *>(a.sig + size_t(x) * a.row_words + 4 * ch);
-          const u32x4 hy = *reinterpret_cast<const u32x4 *>(a.sig + size_t(y) * a.row_words + 4 * ch);
-          const uint32_t d[4] = {hx.x ^ hy.x, hx.y ^ hy.y, hx.z ^ hy.z, hx.w ^ hy.w};
-          for (; j < L && j < (ch + 1) * LPC && !done; ++j) {
-            // level within the chunk picked by selects (a register array
-            // indexed at run time would go to scratch)
-            const int jj = j - ch * LPC;
-            auto w = [d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3]](int q) {
-              return q == 0 ? d0 : q == 1 ? d1 : q == 2 ? d2 : d3;
-            };
-            if constexpr (K == 32) m += 32u - __popc(w(jj));
-            else if constexpr (K == 64) m += 64u - __popc(w(2 * jj)) - __popc(w(2 * jj + 1));
-            else m += 16u - __popc((w(jj >> 1) >> ((jj & 1) * 16)) & 0xFFFFu);
-            done = tail_decide(a, s_min, words, L, j, m, code, emit);
+        const int q0 = j - base, qn = min(L - base, avail * 32 / K);
+#pragma unroll
+        for (int q = 0; q < kStepLevels; ++q) {
+          if (q >= q0 && q < qn && !done) {
+            m += agree_at<K>(d, q);
+            const int jj = base + q;
+            if (int(m) < s_min[jj]) {
+              code = uint8_t((BLSH_PRUNED << 6) | jj);
+              done = true;
+            } else if ((s_acc[jj * words + (m >> 5)] >> (m & 31)) & 1u) {
+              code = uint8_t((BLSH_ACCEPT_CONC << 6) | jj);
+              emit = done = true;
+            } else if (jj == L - 1) {
+              code = uint8_t((BLSH_ACCEPT_NMAX << 6) | jj);
+              emit = done = true;
+            }
           }
         }
+        j = base + qn;
       }
       a.code[c] = code;
       if (a.m_dbg) a.m_dbg[c] = uint16_t(m);
@@ -873,14 +903,16 @@ int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStrea
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
-int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, hipStream_t s) {
+// words: accept-bit words per level of the launch's table (LDS of the tail).
+int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, int words, hipStream_t s) {
   const int64_t nb = round_up(int64_t(ctx->n_cu) * 16, kSlices);
+  const size_t lds = size_t(a.n_levels) * words * 4;
   LaunchScope ls(ctx, s, "verify_tail");
-#define BLSH_T(KK)                                                                                  \
-  if (k == KK) {                                                                                    \
-    if (word_major) hipLaunchKernelGGL((k_verify_tail<KK, true>), dim3(nb), dim3(kBlock), 0, s, a);  \
-    else hipLaunchKernelGGL((k_verify_tail<KK, false>), dim3(nb), dim3(kBlock), 0, s, a);           \
-    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                                \
+#define BLSH_T(KK)                                                                                    \
+  if (k == KK) {                                                                                      \
+    if (word_major) hipLaunchKernelGGL((k_verify_tail<KK, true>), dim3(nb), dim3(kBlock), lds, s, a);  \
+    else hipLaunchKernelGGL((k_verify_tail<KK, false>), dim3(nb), dim3(kBlock), lds, s, a);           \
+    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                                  \
   }
   BLSH_T(16) BLSH_T(32) BLSH_T(64)
 #undef BLSH_T
