@@ -165,17 +165,27 @@ __device__ inline void emit_exact(const VerifyArgs &a, int64_t c, double s) {
 //        one survivor at a time by the whole wave (Algorithm 2).
 // (8 waves per SIMD: the register bound costs a few bytes of spill in the
 // rarely taken exact-similarity path and keeps more gathers in flight)
+// The accept bits of the first kLdsAccLevels levels are staged in LDS (a
+// global table load per level and candidate would double the kernel's memory
+// instructions); later levels read the table.
+constexpr int kLdsAccLevels = 8;
+constexpr int kMaxAccWords = (64 * kMaxLevels + 1 + 31) / 32;
+
 template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool PFX>
 __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
   constexpr int PL = PFX ? 128 / K : 0;   // levels served by the prefix
   __shared__ int s_min[kMaxLevels];
+  __shared__ uint32_t s_acc[LITE ? 1 : kLdsAccLevels * kMaxAccWords];
   __shared__ uint32_t s_eidx[LITE ? kBlock / kWave : 1][LITE ? kExactLds : 1];
   __shared__ float s_eval[LITE ? kBlock / kWave : 1][LITE ? kExactLds : 1];
-  if (threadIdx.x < kMaxLevels)
-    s_min[threadIdx.x] = threadIdx.x < a.n_levels ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
-  __syncthreads();
   const int L = a.n_levels;
   const int words = int(a.table[2]);
+  if (threadIdx.x < kMaxLevels)
+    s_min[threadIdx.x] = threadIdx.x < L ? int(a.table[kTabMinOff + threadIdx.x]) : 0x7fffffff;
+  if constexpr (!LITE) {
+    for (int i = threadIdx.x; i < min(L, kLdsAccLevels) * words; i += kBlock) s_acc[i] = a.table[kTabAccOff + i];
+  }
+  __syncthreads();
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t c0 = a.c_begin + (tile * kBlock + threadIdx.x) * kPPT;
   const bool any = c0 < a.c_end;
@@ -210,7 +220,8 @@ __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
     if (int(m[p]) < s_min[j]) {
       code[p] = uint8_t((BLSH_PRUNED << 6) | j);
       alive &= ~(1u << p);
-    } else if (!LITE && accept_bit(a.table, words, j, int(m[p]))) {
+    } else if (!LITE && (j < kLdsAccLevels ? (s_acc[j * words + (m[p] >> 5)] >> (m[p] & 31)) & 1u
+                                            : accept_bit(a.table, words, j, int(m[p])))) {
       code[p] = uint8_t((BLSH_ACCEPT_CONC << 6) | j);
       alive &= ~(1u << p);
       emit |= 1u << p;
