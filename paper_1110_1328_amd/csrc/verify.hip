@@ -171,8 +171,18 @@ __device__ inline void emit_exact(const VerifyArgs &a, int64_t c, double s) {
 constexpr int kLdsAccLevels = 8;
 constexpr int kMaxAccWords = (64 * kMaxLevels + 1 + 31) / 32;
 
-template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool PFX>
+// Queue entries of the tail: m | next level << 16, or, with kDecidedBit, m |
+// level << 16 of a candidate already accepted inside the prefix (the tail only
+// emits it).
+constexpr uint32_t kDecidedBit = 1u << 31;
+
+//   TAIL (PFX, not LITE): only the prefix levels run here; every candidate
+//        still undecided after them, and every one accepted inside them, goes
+//        to the survivor queue, and k_verify_tail finishes and emits them (this
+//        kernel then carries no emission code: fewer registers, no spills).
+template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool PFX, bool TAIL = false>
 __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
+  static_assert(!TAIL || (PFX && !LITE), "the tail split follows the prefix");
   constexpr int PL = PFX ? 128 / K : 0;   // levels served by the prefix
   __shared__ int s_min[kMaxLevels];
   __shared__ uint32_t s_acc[LITE ? 1 : kLdsAccLevels * kMaxAccWords];
@@ -235,12 +245,15 @@ __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
   if constexpr (PFX) {
     // all eight gathers are issued before any is consumed (object 0 stands in
     // for candidates that are out of range or invalid; their result is unused)
+    // (address: one 32 x 32 -> 64-bit multiply-add per gather)
     u32x4 hx[kPPT], hy[kPPT];
+    const char *pb = reinterpret_cast<const char *>(a.pfx);
+    const uint32_t sb = uint32_t(a.pfx_stride) * 4u;
 #pragma unroll
     for (int p = 0; p < kPPT; ++p) {
-      const bool ok = (alive >> p) & 1u;
-      hx[p] = *reinterpret_cast<const u32x4 *>(a.pfx + size_t(ok ? xi[p] : 0u) * a.pfx_stride);
-      hy[p] = *reinterpret_cast<const u32x4 *>(a.pfx + size_t(ok ? yi[p] : 0u) * a.pfx_stride);
+      const uint32_t ok = 0u - ((alive >> p) & 1u);
+      hx[p] = *reinterpret_cast<const u32x4 *>(pb + uint64_t(xi[p] & ok) * sb);
+      hy[p] = *reinterpret_cast<const u32x4 *>(pb + uint64_t(yi[p] & ok) * sb);
     }
     uint32_t d[kPPT][4];
 #pragma unroll
@@ -257,16 +270,18 @@ __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
       }
     }
     j0 = PL;
-    if constexpr (!LITE) {
-      if (a.q_m && j0 < L) {
-        // still undecided after the prefix: to the queue, finished by k_verify_tail
-        // with every lane busy (the code written below is overwritten there)
-        uint32_t mj[kPPT];
+    if constexpr (TAIL) {
+      // still undecided after the prefix, or accepted inside it: to the
+      // queue, finished by k_verify_tail with every lane busy (the code
+      // written below is overwritten there)
+      uint32_t mj[kPPT];
 #pragma unroll
-        for (int p = 0; p < kPPT; ++p) mj[p] = m[p] | (uint32_t(j0) << 16);
-        push_survivors<kPPT>(a, alive, c0, mj);
-        alive = 0;
-      }
+      for (int p = 0; p < kPPT; ++p)
+        mj[p] = (alive >> p) & 1u ? m[p] | (uint32_t(j0) << 16)
+                                  : m[p] | (uint32_t(code[p] & 63) << 16) | kDecidedBit;
+      push_survivors<kPPT>(a, alive | emit, c0, mj);
+      alive = 0;
+      emit = 0;
     }
   }
   for (int j = j0; j < L && alive; ++j) {
@@ -298,6 +313,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
         if (c0 + p < a.c_end) a.m_dbg[c0 + p] = uint16_t(m[p]);
     }
   }
+  if constexpr (TAIL) return;
   // emission in converged control flow
   if (__ballot(emit != 0) == 0) return;
   if constexpr (LITE) {
@@ -488,15 +504,18 @@ __global__ __launch_bounds__(kBlock) void k_verify_tail(VerifyArgs a) {
       c = a.c_begin + rel[i];
       const uint32_t e = qm[i];
       m = e & 0xFFFFu;
-      int j = int(e >> 16);
-      uint32_t x, y;
-      if (a.kind == BLSH_PAIRS) {
+      int j = int((e >> 16) & 0x7FFFu);
+      bool done = false;
+      uint32_t x = 0, y = 0;
+      if (e & kDecidedBit) {   // accepted inside the prefix: emit only
+        code = uint8_t((BLSH_ACCEPT_CONC << 6) | j);
+        emit = done = true;
+      } else if (a.kind == BLSH_PAIRS) {
         x = a.x[c];
         y = a.y[c];
       } else {
         fetch_candidate(a, c, x, y);
       }
-      bool done = false;
       while (!done) {
         // words [w0, w0 + 8) of both sides (w0: first word of level j; a
         // 16-byte chunk boundary for rows)
@@ -832,18 +851,24 @@ __global__ __launch_bounds__(kBlock) void k_acc_flush(VerifyArgs a, int64_t *nxt
 // ---------------------------------------------------------------------------
 static inline int64_t blocks_for(int64_t items, int64_t per_block) { return (items + per_block - 1) / per_block; }
 
-template <int K, bool LITE, bool WM, bool PFX>
+template <int K, bool LITE, bool WM, bool PFX, bool TAIL = false>
 static int launch_bits_kind(const VerifyArgs &a, int64_t nb, hipStream_t s) {
   switch (a.kind) {
-    case BLSH_PAIRS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_PAIRS, LITE, WM, PFX>), dim3(nb), dim3(kBlock), 0, s, a); break;
-    case BLSH_QUERY_LISTS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_QUERY_LISTS, LITE, WM, PFX>), dim3(nb), dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_verify_bits<K, BLSH_ALL_PAIRS, LITE, WM, PFX>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    case BLSH_PAIRS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_PAIRS, LITE, WM, PFX, TAIL>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    case BLSH_QUERY_LISTS: hipLaunchKernelGGL((k_verify_bits<K, BLSH_QUERY_LISTS, LITE, WM, PFX, TAIL>), dim3(nb), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_verify_bits<K, BLSH_ALL_PAIRS, LITE, WM, PFX, TAIL>), dim3(nb), dim3(kBlock), 0, s, a); break;
   }
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
+// tail: the prefix kernel hands every candidate not pruned inside the prefix
+// to the survivor queue (a.q_m set; not Lite)
 template <int K, bool LITE>
-static int launch_bits_layout(const VerifyArgs &a, int64_t nb, bool wm, bool pfx, hipStream_t s) {
+static int launch_bits_layout(const VerifyArgs &a, int64_t nb, bool wm, bool pfx, bool tail, hipStream_t s) {
+  if constexpr (!LITE) {
+    if (tail) return wm ? launch_bits_kind<K, false, true, true, true>(a, nb, s)
+                        : launch_bits_kind<K, false, false, true, true>(a, nb, s);
+  }
   if (wm) return pfx ? launch_bits_kind<K, LITE, true, true>(a, nb, s) : launch_bits_kind<K, LITE, true, false>(a, nb, s);
   return pfx ? launch_bits_kind<K, LITE, false, true>(a, nb, s) : launch_bits_kind<K, LITE, false, false>(a, nb, s);
 }
@@ -865,8 +890,9 @@ int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool wor
     const int64_t nb = blocks_for(n, int64_t(kBlock) * kPPT);
     // the first 128 hashes in one 16-byte gather per side where a prefix view exists
     const bool pfx = a.pfx != nullptr;
+    const bool tail = pfx && !lite && a.q_m != nullptr;
     LaunchScope ls(ctx, s, pfx ? "verify_bits_prefix" : "verify_bits");
-#define BLSH_B(KK, LL) if (k == KK && lite == LL) return launch_bits_layout<KK, LL>(a, nb, word_major, pfx, s);
+#define BLSH_B(KK, LL) if (k == KK && lite == LL) return launch_bits_layout<KK, LL>(a, nb, word_major, pfx, tail, s);
     BLSH_B(16, false) BLSH_B(16, true) BLSH_B(32, false) BLSH_B(32, true) BLSH_B(64, false) BLSH_B(64, true)
 #undef BLSH_B
   } else {
