@@ -192,8 +192,9 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
  *   batch_spill_cap: entries of each measure's survivor queue, split evenly
  *           into one region per wave of the tile kernel; a survivor that finds
  *           its wave's region full keeps running in registers (same result).
- *   acc_stage_cap: entries of the accepted-pair staging of the single-call
- *           paths (verify, Lite, exhaustive).  Accepted pairs are first
+ *   acc_stage_cap: entries of the accepted-pair staging (single-call paths:
+ *           verify, Lite, exhaustive; batched calls: at most 2^20).  Accepted
+ *           pairs are first
  *           gathered into 256 slices with counters on separate cache lines
  *           (one counter serialises every wave's atomic) and appended to the
  *           caller's list after each launch; a pair that finds its slice full
@@ -210,7 +211,7 @@ typedef struct {
   int32_t last_batch_blocks_per_cu;
   int32_t batch_spill_cap;   /* batched: survivor-queue entries per measure (0 = min(n_cand, 2^24)) */
   int32_t last_batch_k_cosine;
-  int32_t acc_stage_cap;     /* verify/lite/exhaustive: accepted-pair staging entries (0 = 2^24) */
+  int32_t acc_stage_cap;     /* accepted-pair staging entries (0 = 2^24 single-call, 2^20 batched) */
 } blsh_tuning;
 int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *tuning_host);
 int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *tuning_host);

@@ -38,6 +38,7 @@ constexpr int kMhTile = 64;        // phase 1: candidates per minhash wave tile 
 constexpr int kExSrpTile = 1024;   // comparator: candidates per SRP block tile
 constexpr int kExMhTile = 256;     // comparator: candidates per minhash block tile
 constexpr int kXcds = 8;           // phase 1: list tiles split in kXcds position ranges, one per XCD
+constexpr int64_t kBatchStage = 4096;   // accepted-pair staging entries per slice
 
 struct BatchList {
   int64_t offset;
@@ -76,7 +77,15 @@ struct BatchBlock {
   int64_t *n_acc;
   uint16_t *m_dbg;
   int32_t *status;
-  unsigned long long *counters; // unused (kept zero)
+  // accepted-pair staging (as in the single-call paths): kSlices slices of
+  // st_cap entries, counts at acc_cnt[s * kCntStride], appended to the list by
+  // k_batch_flush; entries past a slice's capacity go to the list directly at
+  // positions from the running count *acc_total
+  int64_t *acc_cnt;
+  uint64_t *st_idx;
+  float *st_val;
+  int64_t st_cap;
+  int64_t *acc_total;
   uint4 *spill[2];               // survivor queue per measure: spill_region entries per phase-1 wave
   uint32_t *spill_count[2];     // entries each phase-1 wave stored in its region
   int64_t spill_region;
@@ -114,12 +123,30 @@ __device__ inline void group_bcast_all(uint32_t v, uint32_t *out, std::integer_s
   ((out[S] = group_bcast<G, S>(v)), ...);
 }
 
+// Wave-level compaction of accepted pairs into the wave's staging slice (the
+// list itself past the slice's capacity); called by all lanes of the wave.
 __device__ inline void emit_block(const BatchBlock &B, bool pred, int64_t idx, float val) {
-  const uint64_t mask = __ballot(pred);
+  uint64_t mask = __ballot(pred);
   if (mask == 0) return;
+  {
+    const int sl = wave_slice();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader)
+      base = atomicAdd((unsigned long long *)(B.acc_cnt + sl * kCntStride), (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader);
+    const unsigned long long pos = base + lanes_below(mask);
+    if (pred && int64_t(pos) < B.st_cap) {
+      B.st_idx[size_t(sl) * B.st_cap + pos] = uint64_t(idx);
+      B.st_val[size_t(sl) * B.st_cap + pos] = val;
+      pred = false;
+    }
+    mask = __ballot(pred);
+    if (mask == 0) return;
+  }
   const int leader = __ffsll((unsigned long long)mask) - 1;
   unsigned long long base = 0;
-  if (lane_id() == leader) base = atomicAdd((unsigned long long *)B.n_acc, (unsigned long long)__popcll(mask));
+  if (lane_id() == leader) base = atomicAdd((unsigned long long *)B.acc_total, (unsigned long long)__popcll(mask));
   base = __shfl(base, leader);
   if (pred) {
     const unsigned long long pos = base + lanes_below(mask);
@@ -703,9 +730,56 @@ __global__ __launch_bounds__(kBBlock) void k_batch_exhaustive(const BatchBlock *
   }
 }
 
+// Clears the running count and the staging counts: one block of kSlices
+// threads.
 __global__ void k_batch_reset(const BatchBlock *__restrict__ Bp) {
   const BatchBlock &B = *Bp;
-  if (threadIdx.x == 0) *B.n_acc = 0;
+  B.acc_cnt[threadIdx.x * kCntStride] = 0;
+  if (threadIdx.x == 0) *B.acc_total = 0;
+}
+
+// Appends the staging slices to the accepted list, one block per slice, no
+// atomics: every block scans the kSlices counts, block s copies slice s after
+// the slices before it and after the entries written directly; block 0
+// stores the final count to *n_acc (which no block reads).
+__global__ __launch_bounds__(kBBlock) void k_batch_flush(const BatchBlock *__restrict__ Bp) {
+  static_assert(kSlices == kBBlock, "one staging slice per thread of a block");
+  const BatchBlock &B = *Bp;
+  __shared__ int64_t s_cnt[kSlices];
+  __shared__ int64_t s_base, s_total;
+  const int t = threadIdx.x, sl = blockIdx.x;
+  const int64_t c = min(B.acc_cnt[size_t(t) * kCntStride], B.st_cap);
+  int64_t v = c;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t u = __shfl_up(v, o);
+    if (lane_id() >= o) v += u;
+  }
+  s_cnt[t] = v;
+  __syncthreads();
+  int64_t before = 0;
+  for (int w = 0; w < (t >> 6); ++w) before += s_cnt[w * kWave + kWave - 1];
+  __syncthreads();
+  s_cnt[t] = before + v - c;
+  if (t == kSlices - 1) s_total = before + v;
+  if (t == 0) s_base = *B.acc_total;
+  __syncthreads();
+  const int64_t n = min(B.acc_cnt[size_t(sl) * kCntStride], B.st_cap);
+  const int64_t base = s_base + s_cnt[sl];
+  const uint64_t *idx = B.st_idx + size_t(sl) * B.st_cap;
+  const float *val = B.st_val + size_t(sl) * B.st_cap;
+  bool trunc = false;
+  for (int64_t i = t; i < n; i += kBBlock) {
+    const int64_t pos = base + i;
+    if (pos < B.acc_cap) {
+      B.acc_idx[pos] = idx[i];
+      B.acc_val[pos] = val[i];
+    } else {
+      trunc = true;
+    }
+  }
+  if (trunc) raise_status(B.status, BLSH_ETRUNCATED);
+  if (sl == 0 && t == 0) *B.n_acc = s_base + s_total;
 }
 
 // ---------------------------------------------------------------------------
@@ -717,7 +791,11 @@ struct BatchState {
   BatchList *d_lists = nullptr, *h_lists = nullptr;
   int64_t *d_prefix = nullptr, *h_prefix = nullptr;
   int64_t lists_cap = 0;
-  unsigned long long *d_counters = nullptr;
+  // staging: kSlices counters (kCntStride apart), the running count, then
+  // kSlices x kBatchStage entries
+  int64_t *d_stage_cnt = nullptr;
+  uint64_t *d_st_idx = nullptr;
+  float *d_st_val = nullptr;
   uint4 *d_spill[2] = {nullptr, nullptr};
   int64_t spill_cap = 0;
   uint32_t *d_spill_count = nullptr;    // [2][spill_waves_cap]
@@ -745,7 +823,9 @@ static void batch_free(BatchState *b) {
   if (b->h_lists) (void)hipHostFree(b->h_lists);
   if (b->d_prefix) (void)hipFree(b->d_prefix);
   if (b->h_prefix) (void)hipHostFree(b->h_prefix);
-  if (b->d_counters) (void)hipFree(b->d_counters);
+  if (b->d_stage_cnt) (void)hipFree(b->d_stage_cnt);
+  if (b->d_st_idx) (void)hipFree(b->d_st_idx);
+  if (b->d_st_val) (void)hipFree(b->d_st_val);
   for (auto *p : b->d_spill) if (p) (void)hipFree(p);
   if (b->d_spill_count) (void)hipFree(b->d_spill_count);
   if (b->staged_valid) (void)hipEventDestroy(b->staged);
@@ -761,7 +841,9 @@ static int batch_state(blsh_ctx *ctx, BatchState **out) {
     if (!b) return fail(BLSH_ENOMEM, "host allocation failed");
     if (hipMalloc(&b->d_block, sizeof(BatchBlock)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&b->h_block), sizeof(BatchBlock), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(&b->d_counters, 256) != hipSuccess ||
+        hipMalloc(&b->d_stage_cnt, (size_t(kSlices) + 1) * kCntStride * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&b->d_st_idx, size_t(kSlices) * kBatchStage * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&b->d_st_val, size_t(kSlices) * kBatchStage * sizeof(float)) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
       batch_free(b);
@@ -821,14 +903,15 @@ static int grow_spill(BatchState *b, int64_t cap) {
 
 template <int KJ, int KC>
 static void launch_batch_kernels(BatchState *b, int mode, int grid1, int grid2, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, b->d_block);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kSlices), 0, s, b->d_block);
   if (mode == 1) {
     hipLaunchKernelGGL((k_batch_exhaustive<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
-    return;
+  } else {
+    hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block, int(BLSH_COSINE));
+    hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block, int(BLSH_JACCARD));
+    hipLaunchKernelGGL((k_batch_phase2<KJ, KC>), dim3(grid2), dim3(kBBlock), 0, s, b->d_block);
   }
-  hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block, int(BLSH_COSINE));
-  hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block, int(BLSH_JACCARD));
-  hipLaunchKernelGGL((k_batch_phase2<KJ, KC>), dim3(grid2), dim3(kBBlock), 0, s, b->d_block);
+  hipLaunchKernelGGL(k_batch_flush, dim3(kSlices), dim3(kBBlock), 0, s, b->d_block);
 }
 
 template <int KJ>
@@ -959,7 +1042,13 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     B.n_acc = res->n_accepted;
     B.m_dbg = res->m_debug;
     B.status = ctx->d_status;
-    B.counters = b->d_counters;
+    B.acc_cnt = b->d_stage_cnt;
+    B.acc_total = b->d_stage_cnt + size_t(kSlices) * kCntStride;
+    B.st_idx = b->d_st_idx;
+    B.st_val = b->d_st_val;
+    B.st_cap = ctx->tuning.acc_stage_cap > 0
+                   ? std::min<int64_t>(kBatchStage, std::max<int64_t>(1, ctx->tuning.acc_stage_cap / kSlices))
+                   : kBatchStage;
     B.spill[0] = b->d_spill[0];
     B.spill[1] = b->d_spill[1];
     B.spill_waves = grid1 * (kBBlock / kWave);

@@ -132,6 +132,31 @@ def test_batched_spill_overflow_and_layout(ctx, workload):
     P.bayeslsh_set_tuning(ctx)
 
 
+def test_batched_staging_overflow(ctx, workload):
+    """One staging entry per slice: nearly every accepted pair takes the
+    direct path into the list; the output is still the oracle's, for the
+    batched path and the exhaustive batched comparator."""
+    print("batched staging overflow", flush=True)
+    want = oracle_batched(workload, 32)
+    n_acc = int(((want["decision"] == 1) | (want["decision"] == 2)).sum())
+    assert n_acc > 4 * 256
+    P.bayeslsh_set_tuning(ctx, acc_stage_cap=256)
+    try:
+        _, got = run_batched(ctx, workload, 32, layout=P.OBJECT_MAJOR)
+        check(got, want)
+        lists = P.list_descs(workload["meas"], workload["ts"], workload["queries"], workload["offsets"][:-1],
+                             workload["lens"])
+        n = len(workload["cand"])
+        res = P.make_result(n, n, m_debug=True)
+        Sj = sigs_tensor(workload["sj"], P.JACCARD, P.OBJECT_MAJOR)
+        Sc = sigs_tensor(workload["sc"], P.COSINE, P.OBJECT_MAJOR)
+        P.bayeslsh_exhaustive_batched(ctx, lists, up(workload["cand"]), Sj, Sc, EPS, DELTA, GAMMA, (1, 1), 32, res)
+        P.bayeslsh_sync(ctx)
+        check(decode_result(res, n), want)
+    finally:
+        P.bayeslsh_set_tuning(ctx)
+
+
 def test_batched_graph_replays(ctx, workload):
     """The captured graph replayed several times with eager work and syncs in
     between: every replay matches the oracle."""
