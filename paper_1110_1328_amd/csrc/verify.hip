@@ -245,15 +245,25 @@ __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
   if constexpr (PFX) {
     // all eight gathers are issued before any is consumed (object 0 stands in
     // for candidates that are out of range or invalid; their result is unused)
-    // (address: one 32 x 32 -> 64-bit multiply-add per gather)
+    // (address: one 32 x 32 -> 64-bit multiply-add per gather).  A lane's
+    // consecutive candidates usually share x (bucket-major rows, query
+    // lists): its x prefix is then reused rather than gathered again, and a
+    // wave in which no lane needs it skips the load.
     u32x4 hx[kPPT], hy[kPPT];
     const char *pb = reinterpret_cast<const char *>(a.pfx);
     const uint32_t sb = uint32_t(a.pfx_stride) * 4u;
+    uint32_t ex[kPPT];
 #pragma unroll
     for (int p = 0; p < kPPT; ++p) {
       const uint32_t ok = 0u - ((alive >> p) & 1u);
-      hx[p] = *reinterpret_cast<const u32x4 *>(pb + uint64_t(xi[p] & ok) * sb);
+      ex[p] = xi[p] & ok;
       hy[p] = *reinterpret_cast<const u32x4 *>(pb + uint64_t(yi[p] & ok) * sb);
+    }
+    hx[0] = *reinterpret_cast<const u32x4 *>(pb + uint64_t(ex[0]) * sb);
+#pragma unroll
+    for (int p = 1; p < kPPT; ++p) {
+      hx[p] = hx[p - 1];
+      if (ex[p] != ex[p - 1]) hx[p] = *reinterpret_cast<const u32x4 *>(pb + uint64_t(ex[p]) * sb);
     }
     uint32_t d[kPPT][4];
 #pragma unroll
