@@ -461,6 +461,70 @@ def run_dense(args, torch, P):
     }
 
 
+def run_sweep(args, torch, P):
+    """Synthetic analogs of the paper's experiments on the cosine tf-idf
+    workload (100k documents, 16-band LSH candidates, 2048 SRP bits): exact
+    similarity of every candidate as ground truth ("LSH"), the classical
+    estimate over all hashes ("LSH Approx"), the pruning curve, gamma / delta /
+    epsilon varied one at a time around 0.05 at t = 0.7 (time, recall, mean
+    error, fraction of errors > 0.05), and BayesLSH vs BayesLSH-Lite by
+    threshold."""
+    from paper_1110_1328_amd import experiments as E
+    corpus, x, y = build_workload(args.small)
+    n = len(x)
+    log("sweep workload: %d docs, %d candidates" % (corpus.n, n))
+    ctx = P.bayeslsh_create(0)
+    vec = P.csr_vectors(up(torch, corpus.offsets), up(torch, corpus.indices), up(torch, corpus.values), corpus.dim)
+    cand = P.pairs(up(torch, x), up(torch, y))
+    W = N_BITS // 32
+    sig_om = torch.empty(corpus.n * W, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, vec, None, N_BITS, SRP_SEED, P.OBJECT_MAJOR, sig_om)
+    sig_pf = torch.empty(corpus.n * (H // 32), dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, vec, None, H, SRP_SEED, P.OBJECT_MAJOR, sig_pf)
+    P.bayeslsh_sync(ctx)
+    S = P.Signatures(sig_om, P.COSINE, P.OBJECT_MAJOR, corpus.n, N_BITS)
+    S_pf = P.Signatures(sig_pf, P.COSINE, P.OBJECT_MAJOR, corpus.n, H)
+    stream = torch.cuda.current_stream()
+    truth, exact_ms = E.exact_truth(ctx, cand, vec, stream)
+    log("exact similarity of every candidate (LSH): %.1f ms" % exact_ms)
+    approx = E.lsh_approx(ctx, cand, S, truth, T, K, stream=stream)
+    log("LSH Approx: %.2f ms, recall %.4f, mean error %.4f" % (approx["ms"], approx["recall"], approx["mean_error"]))
+    # the paper's defaults: epsilon = gamma = 0.03, delta = 0.05
+    res = P.make_result(n, n)
+    ms = E._timed(ctx, lambda: P.bayeslsh_verify(ctx, cand, S, T, 0.03, 0.05, 0.03, (1.0, 1.0), K, res, stream),
+                  max(3, args.steps // 10), stream)
+    q = E.quality(*E.accepted_mask(res, n), truth, T)
+    curve = E.pruning_curve(res.code[:n], K, N_BITS // K)
+    log("BayesLSH t=%.1f: %.2f ms, recall %.4f, mean error %.4f" % (T, ms, q["recall"], q["mean_error"]))
+    res_l = P.make_result(n, n)
+    P.bayeslsh_lite_verify(ctx, cand, S_pf, vec, T, 0.03, (1.0, 1.0), H, K, res_l, stream)
+    P.bayeslsh_sync(ctx, stream)
+    curve_lite = E.pruning_curve(res_l.code[:n], K, H // K)
+    sweep = E.parameter_sweep(ctx, cand, S, truth, T, K, stream=stream)
+    for r in sweep:
+        log("vary %-7s %.2f: %.2f ms, recall %.4f, mean error %.4f, errors > 0.05: %.4f" % (
+            r["vary"], r["value"], r["ms"], r["recall"], r["mean_error"], r["frac_error_gt"]))
+    by_t = E.threshold_sweep(ctx, cand, S, S_pf, vec, truth, (0.5, 0.6, 0.7, 0.8, 0.9), K, H, stream=stream)
+    for r in by_t:
+        log("t=%.1f: BayesLSH %.2f ms (recall %.4f), Lite %.2f ms (recall %.4f)" % (
+            r["t"], r["bayeslsh_ms"], r["bayeslsh_recall"], r["lite_ms"], r["lite_recall"]))
+    ctx.close()
+    return {
+        "metric": "candidate pairs verified/sec, BayesLSH vs exhaustive hash compare, same output",
+        "value": n / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "ms_per_step": ms, "higher_is_better": True,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "experiment analogs: %d tf-idf documents, %d 16-band LSH candidates, 2048 SRP bits, "
+                               "cosine t=%.1f, k=%d; Algorithm 1 at epsilon=gamma=0.03, delta=0.05" % (corpus.n, n, T, K)},
+        "quality": q,
+        "lsh_exact_ms": exact_ms,
+        "lsh_approx": approx,
+        "pruning_curve": [[nh, f] for nh, f in curve],
+        "pruning_curve_lite": [[nh, f] for nh, f in curve_lite],
+        "parameter_sweep": sweep,
+        "by_threshold": by_t,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -471,11 +535,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="time a plain 1 GiB device copy and exit")
     ap.add_argument("--layout", choices=["prefix", "word-major"], default="prefix",
                     help="SRP layout verified: object-major 128-bit rows (prefix) or word-major slabs of all bits")
-    ap.add_argument("--workload", choices=["lite", "batched", "serving", "dense"], default="lite",
+    ap.add_argument("--workload", choices=["lite", "batched", "serving", "dense", "sweep"], default="lite",
                     help="lite: the cosine BayesLSH-Lite line (default); batched: 4096 mixed query lists in one "
                          "graph launch vs the exhaustive batched comparator; serving: Poisson arrivals against the "
                          "dense cosine index, p50/p99 latency; dense: GPU LSH banding of 1M dense vectors then "
-                         "Algorithm 1 over all ~2e9 candidates")
+                         "Algorithm 1 over all ~2e9 candidates; sweep: the paper's experiments on the tf-idf "
+                         "workload (pruning curve, gamma/delta/epsilon, BayesLSH vs Lite by threshold)")
     ap.add_argument("--queries", type=int, default=10000, help="serving: number of queries")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -497,6 +562,9 @@ def main():
         return
     if args.workload == "dense":
         print(json.dumps(run_dense(args, torch, P)), flush=True)
+        return
+    if args.workload == "sweep":
+        print(json.dumps(run_sweep(args, torch, P)), flush=True)
         return
     log("generating workload")
     corpus, x, y = build_workload(args.small)
