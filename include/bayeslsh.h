@@ -152,8 +152,11 @@ typedef struct blsh_ctx blsh_ctx;
 /* ---------------- context ---------------- */
 
 /* Create a context on HIP device `device`.  The context owns the posterior
- * table cache (host and device copies) and a survivor workspace that grows on
- * demand (the growth synchronises the device).  Returns BLSH_EDEVICE if the
+ * table cache (host and device copies), a survivor workspace that grows on
+ * demand (the growth synchronises the device) and the counters of the
+ * accepted-pair staging.  Calls on one context share these: calls that may
+ * run at the same time on the device (different streams) need different
+ * contexts; calls queued on one stream are fine.  Returns BLSH_EDEVICE if the
  * device is absent. */
 int bayeslsh_create(blsh_ctx **out, int device);
 void bayeslsh_destroy(blsh_ctx *ctx);
