@@ -691,6 +691,14 @@ def main():
                        "same_output": same, "mode": "REPLAY_LITE, all 2048 bits per object"},
         "signature_ms": sig_ms,
         "prefix_rows_equal_full_signature_prefix": same_prefix,
+        # the paper's own speedups, for context only (other hardware, whole
+        # pipeline including candidate generation, real datasets)
+        "paper_context": {
+            "speedup_over_baselines": "typically 2x-20x (abstract; Section 5)",
+            "speedup_over_lsh_approx": "tf-idf cosine 2.0x-3.0x, binary Jaccard 2.8x-4.2x, binary cosine 1.2x "
+                                       "(Table 2, time summed over thresholds)",
+            "hardware": "single-threaded C/C++, dual-socket dual-core 2.3 GHz Opteron, 8 GB RAM (Section 5)",
+        },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if args.layout == "prefix" else None, "kernel": k_name,
