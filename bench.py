@@ -694,7 +694,7 @@ def main():
         # the paper's own speedups, for context only (other hardware, whole
         # pipeline including candidate generation, real datasets)
         "paper_context": {
-            "speedup_over_baselines": "typically 2x-20x (abstract; Section 5)",
+            "speedup_over_baselines": "2x-20x in most comparisons (abstract; Section 5)",
             "speedup_over_lsh_approx": "tf-idf cosine 2.0x-3.0x, binary Jaccard 2.8x-4.2x, binary cosine 1.2x "
                                        "(Table 2, time summed over thresholds)",
             "hardware": "single-threaded C/C++, dual-socket dual-core 2.3 GHz Opteron, 8 GB RAM (Section 5)",
