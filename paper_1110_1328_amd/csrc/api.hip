@@ -231,7 +231,8 @@ static void fill_cand(VerifyArgs &a, const blsh_candidates *c) {
 //   [2S, 3S)         survivor-queue counts
 //   3S, 3S + 1       running accepted count of set 0, set 1
 // Context workspace:
-//   q_rel [, q_m]    kSlices survivor-queue slices of q_cap entries: a launch
+//   q_rel [, q_m]    kSlices survivor-queue slices of q_cap entries (q_m: the
+//                    SRP tail's m | level << 16 beside each index): a launch
 //                    of n candidates puts at most ceil((n + 1024) / kSlices) +
 //                    256 entries in one slice (every kernel's waves take at most
 //                    256 candidates and its blocks at most 1024, and wave w

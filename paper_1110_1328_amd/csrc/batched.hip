@@ -17,9 +17,13 @@
 //   every lane busy: one lane per SRP survivor, one group of k/4 lanes per
 //   minhash survivor, running the remaining levels.
 //
+// Accepted pairs are staged in slices (as in the single-call paths) and
+// appended to the caller's list by k_batch_flush at the end of the batch.
+//
 // The kernels read all their arguments from one device-resident BatchBlock,
-// so the graph that holds [reset, phase 1 x 2, phase 2] is captured once per
-// (k pair, grid) and replayed for any batch: each call only refreshes the block.
+// so the graph that holds [reset, phase 1 x 2, phase 2, flush] is captured
+// once per (k pair, grid) and replayed for any batch: each call only refreshes
+// the block.
 #include <algorithm>
 #include <chrono>
 #include <cmath>

@@ -9,7 +9,11 @@
 //                     candidate, 4 candidates per lane; level j reads k/32 words
 //                     per side (k = 16 reads half a word).  With the word-major
 //                     layout the words of one level form a dense slab (4 bytes
-//                     per object), so the gathers stay in L2.
+//                     per object), so the gathers stay in L2.  With a prefix
+//                     view the first 128 hashes come in one 16-byte gather per
+//                     side; in Algorithm 1 the candidates left after them go to
+//                     a survivor queue for k_verify_tail.
+//   k_verify_tail     Algorithm 1 past the prefix, one lane per queued pair.
 //   k_verify_minhash  minhash signatures (Jaccard); a group of k/4 lanes compares
 //                     one candidate's k hashes with one 16-byte load per lane and
 //                     per side, then sums the agreements with DPP; lane l owns
@@ -18,6 +22,12 @@
 //   k_exhaustive_*    the comparator: all n_max hashes of both object-major rows,
 //                     per-level counts, prefix sums, then the decision sequence
 //                     of Algorithm 1/2 replayed (or the classical m/n estimate).
+//   k_acc_flush       the accepted pairs staged in slices during a launch,
+//                     appended to the caller's list.
+//
+// Survivor queues and the accepted-pair staging are split into slices whose
+// counters sit on separate cache lines (device-common helpers): one counter
+// for a whole launch would serialise every wave's atomic.
 #include "device_common.h"
 
 namespace blsh {
