@@ -218,12 +218,36 @@ def test_verify_query_lists(ctx):
     cand[10:20] = query[3] ^ 1     # the query's calibration partner
     qx = np.repeat(query, lens)
     want = R.verify(qx, cand, P.COSINE, sig, 32, 16, 0.6, EPS, DELTA, GAMMA)
-    S = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR)
     n = int(offsets[-1])
-    res = P.make_result(n, n, m_debug=True)
-    P.bayeslsh_verify(ctx, P.query_lists(up(query), up(offsets), up(cand)), S, 0.6, EPS, DELTA, GAMMA, (1, 1), 32, res)
-    P.bayeslsh_sync(ctx)
-    assert_same_as_oracle(decode_result(res, n), want)
+    wm = sigs_tensor(sig, P.COSINE, P.WORD_MAJOR)
+    # word-major (levels in registers), object-major rows (prefix kernel and
+    # survivor tail), word-major with a prefix array (tail on slabs)
+    layouts = [wm, sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR),
+               P.Signatures(wm.data, P.COSINE, P.WORD_MAJOR, n_obj, n_hashes,
+                            prefix=up(np.ascontiguousarray(sig[:, :4])))]
+    for S in layouts:
+        res = P.make_result(n, n, m_debug=True)
+        P.bayeslsh_verify(ctx, P.query_lists(up(query), up(offsets), up(cand)), S, 0.6, EPS, DELTA, GAMMA, (1, 1),
+                          32, res)
+        P.bayeslsh_sync(ctx)
+        assert_same_as_oracle(decode_result(res, n), want)
+
+
+def test_verify_all_pairs_cosine_tail(ctx):
+    """ALL_PAIRS (the candidate index decoded from the triangle) through the
+    prefix kernel and the survivor tail, with a ragged last launch tile."""
+    _flush("verify all pairs cosine (tail)")
+    n_obj, n_hashes = 1203, 1024
+    sig = _calib_pairs(P.COSINE, (n_obj + 1) // 2, n_hashes, 6)[:n_obj]
+    want = R.verify(None, None, P.COSINE, sig, 32, n_hashes // 32, 0.7, EPS, DELTA, GAMMA, all_n=n_obj)
+    n = n_obj * (n_obj - 1) // 2
+    for layout in (P.OBJECT_MAJOR, P.WORD_MAJOR):
+        res = P.make_result(n, n, m_debug=True)
+        P.bayeslsh_verify(ctx, P.all_pairs(n_obj), sigs_tensor(sig, P.COSINE, layout), 0.7, EPS, DELTA, GAMMA,
+                          (1, 1), 32, res)
+        P.bayeslsh_sync(ctx)
+        assert_same_as_oracle(decode_result(res, n), want)
+    assert len(set(want["decision"].tolist())) == 3
 
 
 def test_verify_nonuniform_prior(ctx):
