@@ -370,7 +370,8 @@ def run_serving(args, torch, P):
 def run_dense(args, torch, P):
     """Dense cosine estimation: 1M x 256 Gaussian-mixture vectors, 1024 SRP bits
     (object-major rows + prefix array) for verification; candidates from GPU LSH
-    banding (16 bands x 12 bits of an independent 192-bit projection); then
+    banding (16 bands x 12 bits of an independent 192-bit projection, each
+    bucket's pairs listed by 16 x 16 tiles of its members); then
     Algorithm 1 (t = 0.8, eps = gamma = 0.03, delta = 0.05, k = 32, n_max = 1024)
     over every candidate, against the exhaustive REPLAY comparator (object-major
     rows) with the same output.  A random sample of the candidates is checked
@@ -395,7 +396,7 @@ def run_dense(args, torch, P):
     yo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, _, n, trunc = P.bayeslsh_band_candidates(ctx, S_band, 16, 12, cap, x_out=xo, y_out=yo)
+    _, _, n, trunc = P.bayeslsh_band_candidates(ctx, S_band, 16, 12, cap, x_out=xo, y_out=yo, order_tile=16)
     band_ms = (time.perf_counter() - t0) * 1e3
     assert not trunc, n
     log("banding: %d candidates in %.1f ms" % (n, band_ms))
@@ -449,8 +450,9 @@ def run_dense(args, torch, P):
         "value": n / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "ms_per_step": ms, "higher_is_better": True,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": "dense cosine estimation: 1M x 256 Gaussian-mixture vectors (1000 components), 1024 SRP "
-                               "bits, GPU LSH banding 16 x 12 bits on an independent 192-bit projection, Algorithm 1 "
-                               "t=0.8, eps=gamma=0.03, delta=0.05, k=32, n_max=1024",
+                               "bits, GPU LSH banding 16 x 12 bits on an independent 192-bit projection (pairs of a "
+                               "bucket in 16 x 16 tiles), Algorithm 1 t=0.8, eps=gamma=0.03, delta=0.05, k=32, "
+                               "n_max=1024",
                    "n_candidates": n, "banding_ms": band_ms, "banding_pairs_per_s": n / (band_ms * 1e-3)},
         "decisions": {"pruned": dec_counts[0], "accept_conc": dec_counts[1], "accept_nmax": dec_counts[2],
                       "mean_level": lvl_mean, "accepted_listed": int(len(ia))},

@@ -302,15 +302,20 @@ int bayeslsh_exact_similarity(blsh_ctx *ctx, const blsh_candidates *cand, const 
  * equal in some band form a candidate pair, emitted once, in the first band
  * where they collide.  max_bucket > 0 keeps only the first max_bucket members
  * (by id) of each bucket.  Output order: band by band, buckets by increasing
- * key, then (x, y) with x < y in row-major order of the bucket's members --
- * the bucket-major order the verification kernels read best.  x_out, y_out:
+ * key, then the pairs (x, y), x < y, of the bucket's members (by id):
+ * order_tile = 0, row-major over member positions; order_tile = 16, by 16 x 16
+ * tiles of member positions (tile rows, then tile columns, row-major inside a
+ * tile), so that a run of 256 candidates touches about 32 objects -- the
+ * order the verification kernels read best.  x_out, y_out:
  * device uint32[capacity].  *n_pairs_host receives the number of pairs; the
  * call waits for `stream`.  More pairs than capacity: the first `capacity` are
- * written and BLSH_ETRUNCATED is returned.  Uses the context workspace
- * (about 8 * n_obj * (n_bands + 4) bytes). */
+ * written and BLSH_ETRUNCATED is returned; order_tile other than 0 or 16
+ * gives BLSH_EINVAL.  Uses the context workspace (about 8 * n_obj * (n_bands
+ * + 6) bytes) and, with tiles, a context buffer of 16 bytes per tile of the
+ * largest band. */
 int bayeslsh_band_candidates(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t n_bands, int32_t band_bits,
-                             int32_t max_bucket, uint32_t *x_out, uint32_t *y_out, int64_t capacity,
-                             int64_t *n_pairs_host, void *stream);
+                             int32_t max_bucket, int32_t order_tile, uint32_t *x_out, uint32_t *y_out,
+                             int64_t capacity, int64_t *n_pairs_host, void *stream);
 
 /* Learned Jaccard prior (Section 4.1): Beta(alpha, beta) fitted to a random
  * sample of candidate-pair similarities s_1..s_r (host array) by the method

@@ -309,12 +309,14 @@ def band_keys(bits_words, n_bands, band_bits):
     return keys
 
 
-def band_candidates(bits_words, n_bands, band_bits, max_bucket=0):
+def band_candidates(bits_words, n_bands, band_bits, max_bucket=0, tile=0):
     """Objects whose keys agree in some band are candidates; a pair is listed
     once, in the first band where its keys agree.  Order: band by band,
-    buckets by increasing key, members by increasing id, pairs (i, j) of a
-    bucket's members in row-major order (i < j).  max_bucket > 0 keeps the
-    first max_bucket members of each bucket."""
+    buckets by increasing key, members by increasing id; the pairs (a, b),
+    a < b, of a bucket's member positions in row-major order (tile = 0), or
+    (tile = T > 0) by T x T tiles -- tile rows a // T, then tile columns
+    b // T, then row-major inside the tile.  max_bucket > 0 keeps the first
+    max_bucket members of each bucket."""
     keys = band_keys(bits_words, n_bands, band_bits)
     n = keys.shape[0]
     xs, ys = [], []
@@ -326,11 +328,13 @@ def band_candidates(bits_words, n_bands, band_bits, max_bucket=0):
             mem = buckets[key]
             if max_bucket:
                 mem = mem[:max_bucket]
-            for a in range(len(mem)):
-                for b in range(a + 1, len(mem)):
-                    x, y = mem[a], mem[b]
-                    if any(keys[x, jj] == keys[y, jj] for jj in range(j)):
-                        continue
-                    xs.append(x)
-                    ys.append(y)
+            pos = [(a, b) for a in range(len(mem)) for b in range(a + 1, len(mem))]
+            if tile:
+                pos.sort(key=lambda ab: (ab[0] // tile, ab[1] // tile, ab[0], ab[1]))
+            for a, b in pos:
+                x, y = mem[a], mem[b]
+                if any(keys[x, jj] == keys[y, jj] for jj in range(j)):
+                    continue
+                xs.append(x)
+                ys.append(y)
     return np.array(xs, np.uint32), np.array(ys, np.uint32)

@@ -95,7 +95,7 @@ PROTOTYPES = [
       C.c_int32, C.POINTER(Result), p]),
     ("bayeslsh_exact_similarity", C.c_int, [p, C.POINTER(Candidates), C.POINTER(Vectors), p, p]),
     ("bayeslsh_fit_prior", C.c_int, [p, C.c_int64, C.POINTER(Prior), C.POINTER(C.c_int32)]),
-    ("bayeslsh_band_candidates", C.c_int, [p, C.POINTER(Sigs), C.c_int32, C.c_int32, C.c_int32, p, p, C.c_int64,
+    ("bayeslsh_band_candidates", C.c_int, [p, C.POINTER(Sigs), C.c_int32, C.c_int32, C.c_int32, C.c_int32, p, p, C.c_int64,
                                            C.POINTER(C.c_int64), p]),
     ("bayeslsh_verify_batched", C.c_int,
      [p, C.POINTER(ListDesc), C.c_int64, p, C.c_int64, C.POINTER(Sigs), C.POINTER(Sigs), C.c_double, C.c_double,

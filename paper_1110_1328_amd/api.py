@@ -441,9 +441,10 @@ def bayeslsh_exact_similarity(ctx: Context, cand: Candidates, vecs: Vectors, out
 
 def bayeslsh_band_candidates(ctx: Context, band_sigs: Signatures, n_bands: int, band_bits: int, capacity: int,
                              max_bucket: int = 0, x_out: torch.Tensor = None, y_out: torch.Tensor = None,
-                             stream=None):
+                             stream=None, order_tile: int = 0):
     """LSH banding on the device.  Returns (x, y, n_pairs, truncated): uint32
-    device tensors of `capacity` entries, the first min(n_pairs, capacity) valid."""
+    device tensors of `capacity` entries, the first min(n_pairs, capacity) valid.
+    order_tile: 0 (row-major pairs per bucket) or 16 (16 x 16 tiles)."""
     if x_out is None:
         x_out = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda").view(torch.uint32)
     if y_out is None:
@@ -454,8 +455,8 @@ def bayeslsh_band_candidates(ctx: Context, band_sigs: Signatures, n_bands: int, 
         raise ValueError("outputs smaller than capacity")
     st = band_sigs.struct()
     n = C.c_int64(0)
-    rc = _lib().bayeslsh_band_candidates(ctx.handle, C.byref(st), n_bands, band_bits, max_bucket, _p(x_out), _p(y_out),
-                                         capacity, C.byref(n), _stream(stream))
+    rc = _lib().bayeslsh_band_candidates(ctx.handle, C.byref(st), n_bands, band_bits, max_bucket, order_tile,
+                                         _p(x_out), _p(y_out), capacity, C.byref(n), _stream(stream))
     if rc == A.ETRUNCATED:
         return x_out, y_out, n.value, True
     _check(rc)

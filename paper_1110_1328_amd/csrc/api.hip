@@ -26,8 +26,8 @@ int launch_zero_slices(blsh_ctx *ctx, int64_t *cnt, hipStream_t s);
 int launch_acc_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t *nxt_cnt, int64_t *nxt_total, bool last,
                      hipStream_t s);
 int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t row_words, bool word_major,
-                    int32_t n_bands, int32_t band_bits, int32_t max_bucket, uint32_t *x_out, uint32_t *y_out,
-                    int64_t capacity, int64_t *n_pairs, hipStream_t s);
+                    int32_t n_bands, int32_t band_bits, int32_t max_bucket, int32_t tile, uint32_t *x_out,
+                    uint32_t *y_out, int64_t capacity, int64_t *n_pairs, hipStream_t s);
 int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
                    const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
                    blsh_prior prior, int32_t kj, int32_t kc, blsh_result *res, int32_t *k_used, hipStream_t s,
@@ -449,6 +449,7 @@ void bayeslsh_destroy(blsh_ctx *ctx) {
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->d_status) hipFree(ctx->d_status);
   if (ctx->d_slices) hipFree(ctx->d_slices);
+  if (ctx->tile_buf) hipFree(ctx->tile_buf);
   delete ctx;
 }
 
@@ -684,8 +685,8 @@ int bayeslsh_exact_similarity(blsh_ctx *ctx, const blsh_candidates *cand, const 
 }
 
 int bayeslsh_band_candidates(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t n_bands, int32_t band_bits,
-                             int32_t max_bucket, uint32_t *x_out, uint32_t *y_out, int64_t capacity,
-                             int64_t *n_pairs_host, void *stream) {
+                             int32_t max_bucket, int32_t order_tile, uint32_t *x_out, uint32_t *y_out,
+                             int64_t capacity, int64_t *n_pairs_host, void *stream) {
   if (!ctx) return fail(BLSH_EINVAL, "null context");
   if (!n_pairs_host) return fail(BLSH_EINVAL, "n_pairs_host: null");
   *n_pairs_host = 0;
@@ -700,9 +701,11 @@ int bayeslsh_band_candidates(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t 
   if (int64_t(n_bands) * band_bits > g->n_hashes)
     return fail(BLSH_EINVAL, "banding: n_bands * band_bits (%d) > n_hashes (%d)", n_bands * band_bits, g->n_hashes);
   if (max_bucket < 0 || capacity < 0) return fail(BLSH_EINVAL, "banding: negative max_bucket or capacity");
+  if (order_tile != 0 && order_tile != 16) return fail(BLSH_EINVAL, "banding: order_tile must be 0 or 16");
   if (capacity > 0 && (!x_out || !y_out)) return fail(BLSH_EINVAL, "banding: null outputs");
   return band_candidates(ctx, g->data, g->n_obj, g->n_hashes / 32, g->layout == BLSH_WORD_MAJOR, n_bands, band_bits,
-                         max_bucket, x_out, y_out, capacity, n_pairs_host, static_cast<hipStream_t>(stream));
+                         max_bucket, order_tile, x_out, y_out, capacity, n_pairs_host,
+                         static_cast<hipStream_t>(stream));
 }
 
 int bayeslsh_fit_prior(const double *sim_host, int64_t r, blsh_prior *prior_out, int32_t *uniform_host) {

@@ -16,6 +16,7 @@
 //             offset plus the lane's ballot rank, so the output order is band
 //             by band, bucket by increasing key, row by increasing id, partner
 //             by increasing id (x < y).
+#include <algorithm>
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -124,6 +125,133 @@ __global__ __launch_bounds__(kBandBlock) void k_band_pairs(BandArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tiled emission order: the upper triangle of a bucket's member positions cut
+// into kTile x kTile tiles, listed by tile row, then tile column, each tile
+// row-major -- a run of 256 candidates then touches about 2 kTile objects
+// instead of one row's ~256, which the verification kernels' L1 reuses.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 16;   // 16 x 16 = 256 pair positions: one wave, 4 per lane
+
+// flag[p] = 1 where p starts a bucket
+__global__ __launch_bounds__(kBandBlock) void k_start_flags(const uint32_t *bstart, int64_t n, uint32_t *flag) {
+  const int64_t p = int64_t(blockIdx.x) * kBandBlock + threadIdx.x;
+  if (p < n) flag[p] = bstart[p] == uint32_t(p) ? 1u : 0u;
+}
+
+// meta[0] = number of buckets (after the exclusive scan of the flags)
+__global__ void k_count_buckets(const uint32_t *flag, const uint32_t *bidx, int64_t n, int64_t *meta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) meta[0] = n > 0 ? int64_t(bidx[n - 1]) + flag[n - 1] : 0;
+}
+
+// Bucket b (starting at position p): its start, its member count (capped at
+// max_bucket) and its number of tiles nT (nT + 1) / 2, nT = ceil(len / kTile).
+__global__ __launch_bounds__(kBandBlock) void k_bucket_tiles(const uint32_t *bstart, const uint32_t *bend,
+                                                             const uint32_t *bidx, int64_t n, int32_t max_bucket,
+                                                             uint32_t *bpos, uint32_t *blen, int64_t *ntile) {
+  const int64_t p = int64_t(blockIdx.x) * kBandBlock + threadIdx.x;
+  if (p >= n || bstart[p] != uint32_t(p)) return;
+  const uint32_t b = bidx[p];
+  uint32_t len = bend[p] - uint32_t(p);
+  if (max_bucket > 0) len = min(len, uint32_t(max_bucket));
+  bpos[b] = uint32_t(p);
+  blen[b] = len;
+  const int64_t nt = len >= 2 ? (int64_t(len) + kTile - 1) / kTile : 0;
+  ntile[b] = nt * (nt + 1) / 2;
+}
+
+// meta[1] = number of tiles of the band
+__global__ void k_count_tiles(const int64_t *toff, const int64_t *ntile, int64_t nb, int64_t *meta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) meta[1] = nb > 0 ? toff[nb - 1] + ntile[nb - 1] : 0;
+}
+
+struct TileArgs {
+  const uint32_t *sids;      // sorted ids of this band
+  const uint32_t *keys_om;   // [n_obj][n_bands]
+  int32_t n_bands, band;
+  const uint32_t *bpos, *blen;
+  const int64_t *toff;       // first tile of each bucket
+  int64_t n_buckets, n_tiles;
+  int64_t *tcnt;             // count pass: kept pairs per tile
+  const int64_t *tcoff;      // emit pass: their exclusive prefix
+  const int64_t *base;       // emit pass: output offset of this band
+  uint32_t *x_out, *y_out;
+  int64_t capacity;
+};
+
+// One wave per tile: lane l holds the tile's pair positions 4l .. 4l + 3
+// (row-major), so lanes, then a lane's four slots, are in output order.
+template <bool EMIT>
+__global__ __launch_bounds__(kBandBlock) void k_band_tiles(TileArgs a) {
+  const int lane = lane_id();
+  const int64_t waves = int64_t(gridDim.x) * (kBandBlock / kWave);
+  const int64_t w0 = int64_t(blockIdx.x) * (kBandBlock / kWave) +
+                     int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
+  const int64_t out0 = EMIT ? *a.base : 0;
+  for (int64_t t = w0; t < a.n_tiles; t += waves) {
+    // bucket: the last b with toff[b] <= t
+    int64_t lo = 0, hi = a.n_buckets - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) / 2;
+      if (a.toff[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int64_t lt = t - a.toff[lo];
+    const int64_t len = a.blen[lo];
+    const int64_t nt = (len + kTile - 1) / kTile;
+    // tile (ta, tb), tb >= ta: rows before ta hold S(ta) = ta nt - ta (ta - 1) / 2 tiles
+    auto S = [nt](int64_t r) { return r * nt - r * (r - 1) / 2; };
+    const double q2 = double(2 * nt + 1);
+    int64_t ta = int64_t((q2 - sqrt(max(0.0, q2 * q2 - 8.0 * double(lt)))) / 2.0);
+    ta = max<int64_t>(0, min(ta, nt - 1));
+    while (ta > 0 && S(ta) > lt) --ta;
+    while (ta + 1 < nt && S(ta + 1) <= lt) ++ta;
+    const int64_t tb = ta + (lt - S(ta));
+    const int64_t p0 = a.bpos[lo];
+    const int64_t ar = ta * kTile + (4 * lane) / kTile;   // the lane's row (same for its 4 slots)
+    bool keep[4];
+    uint32_t xs = 0, ys[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t cr = tb * kTile + (4 * lane + i) % kTile;
+      keep[i] = ar < cr && cr < len;
+      if (keep[i]) {
+        xs = a.sids[p0 + ar];
+        ys[i] = a.sids[p0 + cr];
+        const uint32_t *kx = a.keys_om + size_t(xs) * a.n_bands;
+        const uint32_t *ky = a.keys_om + size_t(ys[i]) * a.n_bands;
+        for (int j = 0; j < a.band; ++j)   // collided in an earlier band: emitted there
+          if (kx[j] == ky[j]) { keep[i] = false; break; }
+      }
+    }
+    uint64_t mask[4];
+    int64_t total = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      mask[i] = __ballot(keep[i]);
+      total += __popcll(mask[i]);
+    }
+    if (!EMIT) {
+      if (lane == 0) a.tcnt[t] = total;
+    } else {
+      int64_t rank = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) rank += lanes_below(mask[i]);
+      const int64_t off = out0 + a.tcoff[t];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (keep[i]) {
+          const int64_t pos = off + rank;
+          if (pos < a.capacity) {
+            a.x_out[pos] = xs;
+            a.y_out[pos] = ys[i];
+          }
+          ++rank;
+        }
+      }
+    }
+  }
+}
+
 // base += (pairs of this band) = row_off[n-1] + row_count[n-1]
 __global__ void k_band_advance(int64_t *base, const int64_t *row_off, const int64_t *row_count, int64_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && n > 0) *base += row_off[n - 1] + row_count[n - 1];
@@ -135,24 +263,42 @@ __global__ void k_band_zero(int64_t *base) {
 
 static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+static int ensure_tile_buf(blsh_ctx *ctx, size_t bytes) {
+  if (ctx->tile_bytes >= bytes) return BLSH_OK;
+  BLSH_HIP(hipDeviceSynchronize());
+  if (ctx->tile_buf) (void)hipFree(ctx->tile_buf);
+  ctx->tile_buf = nullptr;
+  ctx->tile_bytes = 0;
+  const size_t want = std::max(bytes, size_t(1) << 20);
+  if (hipMalloc(&ctx->tile_buf, want) != hipSuccess) return fail(BLSH_ENOMEM, "banding: tile buffer of %zu bytes", want);
+  ctx->tile_bytes = want;
+  return BLSH_OK;
+}
+
 int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t row_words, bool word_major,
-                    int32_t n_bands, int32_t band_bits, int32_t max_bucket, uint32_t *x_out, uint32_t *y_out,
-                    int64_t capacity, int64_t *n_pairs, hipStream_t s) {
+                    int32_t n_bands, int32_t band_bits, int32_t max_bucket, int32_t tile, uint32_t *x_out,
+                    uint32_t *y_out, int64_t capacity, int64_t *n_pairs, hipStream_t s) {
+  if (tile != 0 && tile != kTile) return fail(BLSH_EINVAL, "banding: order_tile must be 0 or %d", kTile);
   const size_t n = size_t(n_obj);
   // rocPRIM temporary storage sizes
-  size_t sort_tmp = 0, scan_tmp = 0;
+  size_t sort_tmp = 0, scan_tmp = 0, flag_tmp = 0;
   if (rocprim::radix_sort_pairs(nullptr, sort_tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                                 (const uint32_t *)nullptr, (uint32_t *)nullptr, n, 0, unsigned(band_bits), s) !=
           hipSuccess ||
       rocprim::exclusive_scan(nullptr, scan_tmp, (const int64_t *)nullptr, (int64_t *)nullptr, int64_t(0), n,
-                              rocprim::plus<int64_t>(), s) != hipSuccess)
+                              rocprim::plus<int64_t>(), s) != hipSuccess ||
+      rocprim::exclusive_scan(nullptr, flag_tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr, uint32_t(0), n,
+                              rocprim::plus<uint32_t>(), s) != hipSuccess)
     return fail(BLSH_EDEVICE, "banding: temporary storage query failed");
-  // workspace layout
+  // workspace layout (row order: row counts and offsets; tiled order: the
+  // same two int64 arrays hold tile counts and offsets per bucket)
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
   const size_t o_kbm = take(n * n_bands * 4), o_kom = take(n * n_bands * 4), o_ids = take(n * 4),
                o_skeys = take(n * 4), o_sids = take(n * 4), o_bs = take(n * 4), o_be = take(n * 4),
-               o_cnt = take(n * 8), o_off = take(n * 8), o_base = take(256), o_tmp = take(std::max(sort_tmp, scan_tmp));
+               o_cnt = take(n * 8), o_off = take(n * 8), o_base = take(256),
+               o_flag = take(tile ? n * 4 : 0), o_bidx = take(tile ? n * 4 : 0), o_bpos = take(tile ? n * 4 : 0),
+               o_blen = take(tile ? n * 4 : 0), o_tmp = take(std::max({sort_tmp, scan_tmp, flag_tmp}));
   int rc = ensure_workspace(ctx, off);
   if (rc) return rc;
   char *ws = static_cast<char *>(ctx->ws);
@@ -162,6 +308,9 @@ int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t r
   uint32_t *bstart = reinterpret_cast<uint32_t *>(ws + o_bs), *bend = reinterpret_cast<uint32_t *>(ws + o_be);
   int64_t *row_count = reinterpret_cast<int64_t *>(ws + o_cnt), *row_off = reinterpret_cast<int64_t *>(ws + o_off);
   int64_t *base = reinterpret_cast<int64_t *>(ws + o_base);
+  int64_t *meta = base + 4;   // tiled order: bucket and tile totals of a band
+  uint32_t *flag = reinterpret_cast<uint32_t *>(ws + o_flag), *bidx = reinterpret_cast<uint32_t *>(ws + o_bidx);
+  uint32_t *bpos = reinterpret_cast<uint32_t *>(ws + o_bpos), *blen = reinterpret_cast<uint32_t *>(ws + o_blen);
   void *tmp = ws + o_tmp;
 
   LaunchScope ls(ctx, s, "band_candidates");
@@ -177,6 +326,64 @@ int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t r
                                   s) != hipSuccess)
       return fail(BLSH_EDEVICE, "banding: radix sort failed");
     hipLaunchKernelGGL(k_bucket_bounds, dim3(nb), dim3(kBandBlock), 0, s, skeys, n_obj, bstart, bend);
+    if (tile) {
+      // buckets: index by a scan of start flags, then each bucket's tile count
+      hipLaunchKernelGGL(k_start_flags, dim3(nb), dim3(kBandBlock), 0, s, bstart, n_obj, flag);
+      size_t t2 = flag_tmp;
+      if (rocprim::exclusive_scan(tmp, t2, flag, bidx, uint32_t(0), n, rocprim::plus<uint32_t>(), s) != hipSuccess)
+        return fail(BLSH_EDEVICE, "banding: scan failed");
+      hipLaunchKernelGGL(k_count_buckets, dim3(1), dim3(64), 0, s, flag, bidx, n_obj, meta);
+      hipLaunchKernelGGL(k_bucket_tiles, dim3(nb), dim3(kBandBlock), 0, s, bstart, bend, bidx, n_obj, max_bucket,
+                         bpos, blen, row_count);
+      int64_t n_buckets = 0;
+      BLSH_HIP(hipMemcpyAsync(&n_buckets, meta, 8, hipMemcpyDeviceToHost, s));
+      BLSH_HIP(hipStreamSynchronize(s));
+      size_t t3 = scan_tmp;
+      if (rocprim::exclusive_scan(tmp, t3, row_count, row_off, int64_t(0), size_t(n_buckets),
+                                  rocprim::plus<int64_t>(), s) != hipSuccess)
+        return fail(BLSH_EDEVICE, "banding: scan failed");
+      hipLaunchKernelGGL(k_count_tiles, dim3(1), dim3(64), 0, s, row_off, row_count, n_buckets, meta);
+      int64_t n_tiles = 0;
+      BLSH_HIP(hipMemcpyAsync(&n_tiles, meta + 1, 8, hipMemcpyDeviceToHost, s));
+      BLSH_HIP(hipStreamSynchronize(s));
+      if (n_tiles == 0) continue;
+      // per-tile counts and offsets, and the scan's temporary storage
+      size_t tile_tmp = 0;
+      if (rocprim::exclusive_scan(nullptr, tile_tmp, (const int64_t *)nullptr, (int64_t *)nullptr, int64_t(0),
+                                  size_t(n_tiles), rocprim::plus<int64_t>(), s) != hipSuccess)
+        return fail(BLSH_EDEVICE, "banding: temporary storage query failed");
+      const size_t tb = align256(size_t(n_tiles) * 8);
+      if ((rc = ensure_tile_buf(ctx, 2 * tb + tile_tmp))) return rc;
+      int64_t *tcnt = static_cast<int64_t *>(ctx->tile_buf);
+      int64_t *tcoff = reinterpret_cast<int64_t *>(static_cast<char *>(ctx->tile_buf) + tb);
+      void *ttmp = static_cast<char *>(ctx->tile_buf) + 2 * tb;
+      TileArgs ta{};
+      ta.sids = sids;
+      ta.keys_om = keys_om;
+      ta.n_bands = n_bands;
+      ta.band = j;
+      ta.bpos = bpos;
+      ta.blen = blen;
+      ta.toff = row_off;
+      ta.n_buckets = n_buckets;
+      ta.n_tiles = n_tiles;
+      ta.tcnt = tcnt;
+      ta.tcoff = tcoff;
+      ta.base = base;
+      ta.x_out = x_out;
+      ta.y_out = y_out;
+      ta.capacity = capacity;
+      const unsigned tile_blocks =
+          unsigned(std::min<int64_t>(int64_t(ctx->n_cu) * 8, (n_tiles + kBandBlock / kWave - 1) / (kBandBlock / kWave)));
+      hipLaunchKernelGGL(k_band_tiles<false>, dim3(tile_blocks), dim3(kBandBlock), 0, s, ta);
+      size_t t4 = tile_tmp;
+      if (rocprim::exclusive_scan(ttmp, t4, tcnt, tcoff, int64_t(0), size_t(n_tiles), rocprim::plus<int64_t>(), s) !=
+          hipSuccess)
+        return fail(BLSH_EDEVICE, "banding: scan failed");
+      hipLaunchKernelGGL(k_band_tiles<true>, dim3(tile_blocks), dim3(kBandBlock), 0, s, ta);
+      hipLaunchKernelGGL(k_band_advance, dim3(1), dim3(64), 0, s, base, tcoff, tcnt, n_tiles);
+      continue;
+    }
     BandArgs a{};
     a.sids = sids;
     a.bstart = bstart;

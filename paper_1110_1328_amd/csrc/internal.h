@@ -89,6 +89,9 @@ struct blsh_ctx {
   // survivor workspace
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  // banding: per-tile counts and offsets of the tiled emission order
+  void *tile_buf = nullptr;
+  size_t tile_bytes = 0;
   // tuning (bayeslsh_set_tuning; last_* fields report the last batched call)
   blsh_tuning tuning{};
   // batched-call state (persistent buffers, captured graphs, autotune cache)

@@ -29,35 +29,42 @@ def bits():
     return G.pack_bits((mix.x.astype(np.float64) @ planes >= 0).astype(np.uint8))
 
 
-def run(ctx, S, nb, b, cap, max_bucket=0):
-    x, y, n, trunc = P.bayeslsh_band_candidates(ctx, S, nb, b, cap, max_bucket=max_bucket)
+def run(ctx, S, nb, b, cap, max_bucket=0, tile=0):
+    x, y, n, trunc = P.bayeslsh_band_candidates(ctx, S, nb, b, cap, max_bucket=max_bucket, order_tile=tile)
     k = min(n, cap)
     return down(x)[:k], down(y)[:k], n, trunc
 
 
-@pytest.mark.parametrize("nb,b,max_bucket", [(8, 8, 0), (5, 11, 0), (8, 8, 5), (4, 16, 0)])
-def test_banding_matches_oracle(ctx, bits, nb, b, max_bucket):
-    """Both layouts; band keys that straddle a 32-bit word (b = 11); a bucket cap."""
-    print("banding nb=%d b=%d max_bucket=%d" % (nb, b, max_bucket), flush=True)
-    wx, wy = R.band_candidates(bits, nb, b, max_bucket)
+@pytest.mark.parametrize("tile", [0, 16])
+@pytest.mark.parametrize("nb,b,max_bucket", [(8, 8, 0), (5, 11, 0), (8, 8, 5), (4, 16, 0), (3, 5, 40)])
+def test_banding_matches_oracle(ctx, bits, nb, b, max_bucket, tile):
+    """Both layouts; band keys that straddle a 32-bit word (b = 11); bucket
+    caps (a single tile per bucket, and caps that are not a multiple of the
+    tile); row-major and tiled orders."""
+    print("banding nb=%d b=%d max_bucket=%d tile=%d" % (nb, b, max_bucket, tile), flush=True)
+    wx, wy = R.band_candidates(bits, nb, b, max_bucket, tile=tile)
     assert len(wx) > 1000
     for layout in (P.OBJECT_MAJOR, P.WORD_MAJOR):
         S = sigs_tensor(bits, P.COSINE, layout)
-        gx, gy, n, trunc = run(ctx, S, nb, b, len(wx) + 100, max_bucket)
+        gx, gy, n, trunc = run(ctx, S, nb, b, len(wx) + 100, max_bucket, tile)
         assert n == len(wx) and not trunc
         np.testing.assert_array_equal(gx, wx)
         np.testing.assert_array_equal(gy, wy)
 
 
-def test_banding_truncation_empty_and_invalid(ctx, bits):
-    print("banding truncation", flush=True)
-    wx, wy = R.band_candidates(bits, 8, 8)
+@pytest.mark.parametrize("tile", [0, 16])
+def test_banding_truncation_empty_and_invalid(ctx, bits, tile):
+    print("banding truncation tile=%d" % tile, flush=True)
+    wx, wy = R.band_candidates(bits, 8, 8, tile=tile)
     S = sigs_tensor(bits, P.COSINE, P.OBJECT_MAJOR)
     half = len(wx) // 2
-    gx, gy, n, trunc = run(ctx, S, 8, 8, half)
+    gx, gy, n, trunc = run(ctx, S, 8, 8, half, tile=tile)
     assert trunc and n == len(wx)
     np.testing.assert_array_equal(gx, wx[:half])
     np.testing.assert_array_equal(gy, wy[:half])
+    with pytest.raises(P.BayesLSHError) as e:
+        run(ctx, S, 8, 8, 16, tile=8)
+    assert e.value.code == -1
     # distinct random 32-bit keys in a single band: no pair
     rnd = np.random.default_rng(3).integers(0, 2 ** 32, size=(500, 1), dtype=np.uint64).astype(np.uint32)
     _, _, n0, _ = run(ctx, sigs_tensor(rnd, P.COSINE, P.OBJECT_MAJOR), 1, 32, 16)

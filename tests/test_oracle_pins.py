@@ -479,6 +479,34 @@ def test_banding_against_brute_force():
     assert order == sorted(order)
 
 
+def test_banding_tiled_order():
+    """The tiled order lists exactly the row-major order's pairs of each band
+    and bucket, rearranged: for member positions (a, b) of one bucket, by tile
+    row a // T, tile column b // T, then (a, b)."""
+    rng = np.random.default_rng(9)
+    n, nb, b, T = 400, 4, 2, 3
+    bits = G.pack_bits(rng.integers(0, 2, size=(n, 32), dtype=np.uint8))
+    x0, y0 = R.band_candidates(bits, nb, b)
+    x1, y1 = R.band_candidates(bits, nb, b, tile=T)
+    assert sorted(zip(x0.tolist(), y0.tolist())) == sorted(zip(x1.tolist(), y1.tolist()))
+    keys = R.band_keys(bits, nb, b)
+    # by hand: band of first agreement, bucket key, positions among the bucket's members
+    def band_of(p):
+        return int(np.flatnonzero(keys[p[0]] == keys[p[1]])[0])
+    members = {}
+    for j in range(nb):
+        for i in range(n):
+            members.setdefault((j, int(keys[i, j])), []).append(i)
+    order = []
+    for p in zip(x1.tolist(), y1.tolist()):
+        j = band_of(p)
+        mem = members[(j, int(keys[p[0], j]))]
+        a, c = mem.index(p[0]), mem.index(p[1])
+        order.append((j, int(keys[p[0], j]), a // T, c // T, a, c))
+    assert order == sorted(order)
+    assert any(o[2] != o[3] for o in order) and any(o[2] == o[3] for o in order)
+
+
 @pytest.mark.parametrize("r", [0.6, 0.8])
 def test_banding_collision_probability(r):
     """Section 2: with l bands of b bits, a pair whose bits agree independently
