@@ -11,7 +11,7 @@ namespace blsh {
 // launchers (verify.hip, sigs.hip)
 int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool word_major, hipStream_t s);
 int launch_exhaustive(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s);
-int launch_zero(blsh_ctx *ctx, int64_t *p, int64_t *q, hipStream_t s);
+int launch_zero(blsh_ctx *ctx, int64_t *p, hipStream_t s);
 int launch_minhash(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *elems, int64_t n_sets, const uint32_t *a,
                    const uint32_t *b, int n_hashes, uint32_t *out, hipStream_t s);
 int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *indices, const float *values,
@@ -346,12 +346,15 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   a.mode = exh ? exhaustive_mode : 0;
   a.count_levels = n_max / k;
   a.t = t;
-  if (n_cand == 0) return launch_zero(ctx, res->n_accepted, nullptr, s) ? fail(BLSH_EDEVICE, "launch failed") : BLSH_OK;
+  if (n_cand == 0) return launch_zero(ctx, res->n_accepted, s) ? fail(BLSH_EDEVICE, "launch failed") : BLSH_OK;
   // SRP Algorithm 1 with a prefix view: candidates undecided after the first
   // 128 hashes are queued and finished by a second kernel with every lane busy
   const bool tail = !exh && !lite && sigs->measure == BLSH_COSINE && a.pfx != nullptr && 128 / k < n_levels;
-  // the SRP early-exit kernel computes Lite exact similarities itself
-  const bool fused_exact = lite && exhaustive_mode == -1 && sigs->measure == BLSH_COSINE;
+  // Lite exact similarities of SRP survivors: with a prefix view the
+  // early-exit kernel queues the survivors for k_exact (it then needs no
+  // exact-similarity code: fewer registers, no LDS rows, and its waves never
+  // wait on one survivor's sparse gathers); otherwise it computes them itself
+  const bool fused_exact = lite && exhaustive_mode == -1 && sigs->measure == BLSH_COSINE && a.pfx == nullptr;
   const bool queued = (lite && !fused_exact) || tail;
   // launches are chunked so that no grid exceeds 2^32 work-items (the
   // dispatch's grid size): the comparator runs up to 64 lanes per candidate
@@ -639,7 +642,7 @@ static int batched_common(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (n_lists == 0 || n_cand == 0) {
-    if (launch_zero(ctx, res->n_accepted, nullptr, s)) return fail(BLSH_EDEVICE, "launch failed");
+    if (launch_zero(ctx, res->n_accepted, s)) return fail(BLSH_EDEVICE, "launch failed");
     if (k_used) { k_used[0] = kj; k_used[1] = kc; }
     return BLSH_OK;
   }

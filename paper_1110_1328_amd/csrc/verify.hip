@@ -172,7 +172,8 @@ __device__ inline void emit_exact(const VerifyArgs &a, int64_t c, double s) {
 //        the first 128/K levels need no further round trip; later levels read
 //        `sig` in its own layout.
 //   LITE: survivors of the h-hash budget get their exact similarity right here,
-//        one survivor at a time by the whole wave (Algorithm 2).
+//        one survivor at a time by the whole wave (Algorithm 2), or, with
+//        TAIL, from k_exact after this kernel.
 // (8 waves per SIMD: the register bound costs a few bytes of spill in the
 // rarely taken exact-similarity path and keeps more gathers in flight)
 // The accept bits of the first kLdsAccLevels levels are staged in LDS (a
@@ -186,18 +187,21 @@ constexpr int kMaxAccWords = (64 * kMaxLevels + 1 + 31) / 32;
 // emits it).
 constexpr uint32_t kDecidedBit = 1u << 31;
 
-//   TAIL (PFX, not LITE): only the prefix levels run here; every candidate
-//        still undecided after them, and every one accepted inside them, goes
-//        to the survivor queue, and k_verify_tail finishes and emits them (this
-//        kernel then carries no emission code: fewer registers, no spills).
+//   TAIL (PFX): a second kernel finishes the work (this kernel then carries
+//        no emission code: fewer registers, no spills).  Not LITE: only the
+//        prefix levels run here; every candidate still undecided after them,
+//        and every one accepted inside them, goes to the survivor queue, and
+//        k_verify_tail finishes and emits them.  LITE: the survivors of the h
+//        hashes go to the exact-similarity queue for k_exact.
 template <int K, int KIND, bool LITE, bool WORD_MAJOR, bool PFX, bool TAIL = false>
 __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
-  static_assert(!TAIL || (PFX && !LITE), "the tail split follows the prefix");
+  static_assert(!TAIL || PFX, "the split follows the prefix");
+  constexpr bool FUSED = LITE && !TAIL;   // Lite exact similarity in this kernel
   constexpr int PL = PFX ? 128 / K : 0;   // levels served by the prefix
   __shared__ int s_min[kMaxLevels];
   __shared__ uint32_t s_acc[LITE ? 1 : kLdsAccLevels * kMaxAccWords];
-  __shared__ uint32_t s_eidx[LITE ? kBlock / kWave : 1][LITE ? kExactLds : 1];
-  __shared__ float s_eval[LITE ? kBlock / kWave : 1][LITE ? kExactLds : 1];
+  __shared__ uint32_t s_eidx[FUSED ? kBlock / kWave : 1][FUSED ? kExactLds : 1];
+  __shared__ float s_eval[FUSED ? kBlock / kWave : 1][FUSED ? kExactLds : 1];
   const int L = a.n_levels;
   const int words = int(a.table[2]);
   if (threadIdx.x < kMaxLevels)
@@ -290,7 +294,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
       }
     }
     j0 = PL;
-    if constexpr (TAIL) {
+    if constexpr (TAIL && !LITE) {
       // still undecided after the prefix, or accepted inside it: to the
       // queue, finished by k_verify_tail with every lane busy (the code
       // written below is overwritten there)
@@ -333,7 +337,13 @@ __global__ __launch_bounds__(kBlock, 8) void k_verify_bits(VerifyArgs a) {
         if (c0 + p < a.c_end) a.m_dbg[c0 + p] = uint16_t(m[p]);
     }
   }
-  if constexpr (TAIL) return;
+  if constexpr (TAIL) {
+    if constexpr (LITE) {
+#pragma unroll
+      for (int p = 0; p < kPPT; ++p) push_survivor(a, (emit >> p) & 1u, c0 + p);
+    }
+    return;
+  }
   // emission in converged control flow
   if (__ballot(emit != 0) == 0) return;
   if constexpr (LITE) {
@@ -797,9 +807,8 @@ __global__ __launch_bounds__(kBlock) void k_exhaustive_minhash(VerifyArgs a) {
   else emit_accepted(a, emit, uint64_t(c), val);
 }
 
-__global__ void k_zero_i64(int64_t *p, int64_t *q) {
-  if (threadIdx.x == 0 && p) *p = 0;
-  if (threadIdx.x == 1 && q) *q = 0;
+__global__ void k_zero_i64(int64_t *p) {
+  if (threadIdx.x == 0) *p = 0;
 }
 
 // Clears every counter of the single-call paths (both staging-count sets and
@@ -881,14 +890,13 @@ static int launch_bits_kind(const VerifyArgs &a, int64_t nb, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
-// tail: the prefix kernel hands every candidate not pruned inside the prefix
-// to the survivor queue (a.q_m set; not Lite)
+// tail: the prefix kernel hands the rest of the work to a second kernel
+// through the survivor queue (Algorithm 1: a.q_m set, k_verify_tail; Lite:
+// a.q_rel set, k_exact)
 template <int K, bool LITE>
 static int launch_bits_layout(const VerifyArgs &a, int64_t nb, bool wm, bool pfx, bool tail, hipStream_t s) {
-  if constexpr (!LITE) {
-    if (tail) return wm ? launch_bits_kind<K, false, true, true, true>(a, nb, s)
-                        : launch_bits_kind<K, false, false, true, true>(a, nb, s);
-  }
+  if (tail) return wm ? launch_bits_kind<K, LITE, true, true, true>(a, nb, s)
+                      : launch_bits_kind<K, LITE, false, true, true>(a, nb, s);
   if (wm) return pfx ? launch_bits_kind<K, LITE, true, true>(a, nb, s) : launch_bits_kind<K, LITE, true, false>(a, nb, s);
   return pfx ? launch_bits_kind<K, LITE, false, true>(a, nb, s) : launch_bits_kind<K, LITE, false, false>(a, nb, s);
 }
@@ -910,7 +918,7 @@ int launch_verify(blsh_ctx *ctx, const VerifyArgs &a, int k, bool lite, bool wor
     const int64_t nb = blocks_for(n, int64_t(kBlock) * kPPT);
     // the first 128 hashes in one 16-byte gather per side where a prefix view exists
     const bool pfx = a.pfx != nullptr;
-    const bool tail = pfx && !lite && a.q_m != nullptr;
+    const bool tail = pfx && (lite ? a.q_rel != nullptr : a.q_m != nullptr);
     LaunchScope ls(ctx, s, pfx ? "verify_bits_prefix" : "verify_bits");
 #define BLSH_B(KK, LL) if (k == KK && lite == LL) return launch_bits_layout<KK, LL>(a, nb, word_major, pfx, tail, s);
     BLSH_B(16, false) BLSH_B(16, true) BLSH_B(32, false) BLSH_B(32, true) BLSH_B(64, false) BLSH_B(64, true)
@@ -998,8 +1006,8 @@ int launch_acc_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t *nxt_cnt, int64
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
-int launch_zero(blsh_ctx *ctx, int64_t *p, int64_t *q, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, p, q);
+int launch_zero(blsh_ctx *ctx, int64_t *p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, p);
   (void)ctx;
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }

@@ -438,8 +438,9 @@ STAGE_SLICES = 256   # staging slices of the library: acc_stage_cap = 256 leaves
 def test_accepted_staging_overflow(ctx):
     """With one staging entry per slice almost every accepted pair takes the
     direct path: Algorithm 1 (SRP with and without the survivor tail, minhash),
-    Lite (fused SRP exact, minhash exact queue) and the comparator still give
-    the oracle's output, and truncation still reports the true count."""
+    Lite (SRP survivors queued for the exact kernel, minhash exact queue) and
+    the comparator still give the oracle's output, and truncation still
+    reports the true count."""
     _flush("staging overflow")
     P.bayeslsh_set_tuning(ctx, acc_stage_cap=STAGE_SLICES)
     try:
