@@ -308,7 +308,9 @@ def run_serving(args, torch, P):
     """Poisson arrivals of query objects against the dense cosine index
     (candidate counts 10^U(3,6), t = 0.8): first all at once (saturated rate),
     then at rho x that rate for rho in {0.5, 0.8, 0.95}; latency = arrival to
-    host-visible result."""
+    host-visible result.  Then the same requests submitted from device memory
+    (candidate ids resident on the GPU, no host copy of them): saturated and at
+    rho = 0.95 of that rate."""
     from synth import generators as G
     ctx = P.bayeslsh_create(0)
     log("cosine index (1M x 256 dense, 1024 SRP bits)")
@@ -324,6 +326,8 @@ def run_serving(args, torch, P):
     log("%d candidates" % total)
     srv = P.Server(ctx, S, mem_budget_bytes=2 << 30, max_active=64, k=32, max_batch_candidates=1 << 24)
 
+    dcand = None
+
     def run(gaps):
         ids = []
         t0 = time.perf_counter()
@@ -332,7 +336,11 @@ def run_serving(args, torch, P):
                 due = t0 + gaps[i]
                 while time.perf_counter() < due:
                     pass
-            ids.append(srv.submit(int(q[i]), cand[off[i]:off[i + 1]], 0.8))
+            if dcand is None:
+                ids.append(srv.submit(int(q[i]), cand[off[i]:off[i + 1]], 0.8))
+            else:
+                ids.append(srv.submit_device(int(q[i]), dcand[off[i]:off[i + 1]], 0.8))
+        run.submit_s = time.perf_counter() - t0              # when the client had submitted everything
         out = [srv.wait(r) for r in ids]
         el = time.perf_counter() - t0
         for r in ids:
@@ -344,7 +352,8 @@ def run_serving(args, torch, P):
     el, lat, out0 = run(None)
     sat_qps = nq / el
     res = {"saturated": {"queries_per_s": sat_qps, "pairs_per_s": total / el,
-                         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}}
+                         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                         "client_submit_s": run.submit_s, "elapsed_s": el}}
     log("saturated: %.0f q/s, %.3g pairs/s" % (sat_qps, total / el))
     for rho in (0.5, 0.8, 0.95):
         gaps = np.cumsum(np.random.default_rng(int(rho * 100)).exponential(1.0 / (rho * sat_qps), nq))
@@ -355,6 +364,29 @@ def run_serving(args, torch, P):
                                  "p50_ms": float(np.percentile(lat, 50) * 1e3),
                                  "p99_ms": float(np.percentile(lat, 99) * 1e3), "same_results": same}
         log("rho %.2f: p50 %.2f ms p99 %.2f ms" % (rho, res["rho_%.2f" % rho]["p50_ms"], res["rho_%.2f" % rho]["p99_ms"]))
+    # the same requests with candidate ids already resident on the device
+    dcand = up(torch, cand)
+    run(None)
+    el, lat, out = run(None)
+    dev_qps = nq / el
+    same = all(np.array_equal(a["acc_idx"], b["acc_idx"]) and np.array_equal(a["acc_val"], b["acc_val"])
+               for a, b in zip(out0, out))
+    res["device_saturated"] = {"queries_per_s": dev_qps, "pairs_per_s": total / el,
+                               "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                               "p99_ms": float(np.percentile(lat, 99) * 1e3), "same_results": same,
+                               "client_submit_s": run.submit_s, "elapsed_s": el}
+    log("device submit, saturated: %.0f q/s, %.3g pairs/s" % (dev_qps, total / el))
+    gaps = np.cumsum(np.random.default_rng(95).exponential(1.0 / (0.95 * dev_qps), nq))
+    el, lat, out = run(gaps)
+    same = all(np.array_equal(a["acc_idx"], b["acc_idx"]) and np.array_equal(a["acc_val"], b["acc_val"])
+               for a, b in zip(out0, out))
+    res["device_rho_0.95"] = {"queries_per_s": nq / el, "pairs_per_s": total / el,
+                              "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                              "p99_ms": float(np.percentile(lat, 99) * 1e3), "same_results": same,
+                              "client_submit_s": run.submit_s, "elapsed_s": el}
+    log("device submit, rho 0.95: p50 %.2f ms p99 %.2f ms" % (res["device_rho_0.95"]["p50_ms"],
+                                                               res["device_rho_0.95"]["p99_ms"]))
+    dcand = None
     st = srv.stats()
     srv.close()
     ctx.close()

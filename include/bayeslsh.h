@@ -428,6 +428,19 @@ int bayeslsh_server_create(blsh_ctx *ctx, const blsh_sigs *index, const blsh_ser
  * than the arena (BLSH_ENOMEM). */
 int bayeslsh_server_submit(blsh_server *srv, uint32_t query, const uint32_t *cand_host, int64_t n_cand, double t,
                            int64_t *request_id);
+/* As bayeslsh_server_submit for candidate ids already in device memory (for
+ * instance from bayeslsh_band_candidates): nothing is copied on the host; the
+ * server copies them device to device into its arena when it admits the
+ * request, so cand_dev must stay valid and unchanged until the request is
+ * finished (poll/wait report it).  Ids are checked on the device only: a
+ * candidate with an id >= n_obj is never accepted, the other candidates are
+ * verified as usual, and the request finishes with status BLSH_EBADID (its
+ * accepted list still holds the valid candidates' results).  A query id >=
+ * n_obj is rejected here (BLSH_EINVAL); requests larger than the arena:
+ * BLSH_ENOMEM.  Any pending status of `ctx` is cleared when the server is
+ * created. */
+int bayeslsh_server_submit_device(blsh_server *srv, uint32_t query, const uint32_t *cand_dev, int64_t n_cand,
+                                  double t, int64_t *request_id);
 /* BLSH_OK (finished; *out filled), BLSH_EAGAIN (pending) or an error. */
 int bayeslsh_server_poll(blsh_server *srv, int64_t request_id, blsh_request_result *out);
 int bayeslsh_server_wait(blsh_server *srv, int64_t request_id, blsh_request_result *out);

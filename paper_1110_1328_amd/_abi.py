@@ -105,6 +105,7 @@ PROTOTYPES = [
       C.c_double, Prior, C.c_int32, C.c_int32, C.POINTER(Result), p]),
     ("bayeslsh_server_create", C.c_int, [p, C.POINTER(Sigs), C.POINTER(ServerConfig), C.POINTER(p)]),
     ("bayeslsh_server_submit", C.c_int, [p, C.c_uint32, p, C.c_int64, C.c_double, C.POINTER(C.c_int64)]),
+    ("bayeslsh_server_submit_device", C.c_int, [p, C.c_uint32, p, C.c_int64, C.c_double, C.POINTER(C.c_int64)]),
     ("bayeslsh_server_poll", C.c_int, [p, C.c_int64, C.POINTER(RequestResult)]),
     ("bayeslsh_server_wait", C.c_int, [p, C.c_int64, C.POINTER(RequestResult)]),
     ("bayeslsh_server_release", C.c_int, [p, C.c_int64]),

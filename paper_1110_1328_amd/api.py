@@ -518,6 +518,7 @@ class Server:
         cfg = A.ServerConfig(mem_budget_bytes, max_active, k, max_batch_candidates, epsilon, delta, gamma,
                              _prior(prior))
         self._index = index
+        self._held = {}   # device candidate arrays of requests submitted from the device
         st = index.struct()
         h = C.c_void_p()
         _check(_lib().bayeslsh_server_create(ctx.handle, C.byref(st), C.byref(cfg), C.byref(h)))
@@ -535,6 +536,16 @@ class Server:
                                              float(t), C.byref(rid)))
         return rid.value
 
+    def submit_device(self, query: int, cand: torch.Tensor, t: float) -> int:
+        """Candidate ids already on the device (uint32 tensor): no host copy.
+        The tensor is held until release()."""
+        _dev(cand, torch.uint32, "cand")
+        rid = C.c_int64()
+        _check(_lib().bayeslsh_server_submit_device(self.handle, int(query), _p(cand), int(cand.numel()), float(t),
+                                                    C.byref(rid)))
+        self._held[rid.value] = cand
+        return rid.value
+
     @staticmethod
     def _result(r: "A.RequestResult"):
         import numpy as np
@@ -550,16 +561,20 @@ class Server:
         rc = _lib().bayeslsh_server_poll(self.handle, rid, C.byref(r))
         if rc == A.EAGAIN:
             return None
-        _check(rc)
+        if rc != A.EBADID:   # finished with bad device ids: the result says so in "status"
+            _check(rc)
         return self._result(r)
 
     def wait(self, rid: int):
         r = A.RequestResult()
-        _check(_lib().bayeslsh_server_wait(self.handle, rid, C.byref(r)))
+        rc = _lib().bayeslsh_server_wait(self.handle, rid, C.byref(r))
+        if rc != A.EBADID:
+            _check(rc)
         return self._result(r)
 
     def release(self, rid: int):
         _check(_lib().bayeslsh_server_release(self.handle, rid))
+        self._held.pop(rid, None)
 
     def stats(self):
         it, pe, ac, de = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()

@@ -52,7 +52,8 @@ struct Request {
   int64_t id;
   uint32_t query;
   double t;
-  std::vector<uint32_t> cand;       // host copy
+  std::vector<uint32_t> cand;       // host copy (host submission)
+  const uint32_t *d_src = nullptr;  // caller's device array (device submission)
   int64_t n;
   int64_t arena_off = -1;           // in uint32 units
   int64_t issued = 0, finished = 0; // candidates launched / completed
@@ -60,6 +61,7 @@ struct Request {
   std::vector<float> acc_val;
   double t_submit = 0, t_admit = 0, t_done = 0;
   int status = BLSH_OK;
+  bool bad_id = false;              // a device-submitted id >= n_obj was seen
   bool done = false;
 };
 
@@ -193,10 +195,37 @@ int launch_iteration(blsh_server *S, Iteration &it, std::vector<Request *> &act)
   return BLSH_OK;
 }
 
-int finish_iteration(blsh_server *S, Iteration &it) {
+// Device-submitted ids are checked by the kernels only: a bad id gets code
+// 0xFF and raises the context's status word (first error wins).  The word is
+// shared by both in-flight iterations, so it only says that some iteration may
+// hold a bad id; which request it belongs to is read from this iteration's own
+// codes.  It is cleared only when no other iteration is in flight, so an error
+// raised by the overlapping iteration is seen when that one finishes.
+int check_device_ids(blsh_server *S, Iteration &it, bool other_busy) {
+  bool dev = false;
+  for (const Slice &sl : it.slices) dev |= sl.r->d_src != nullptr;
+  if (!dev) return BLSH_OK;
+  int32_t st = 0;
+  if (hipMemcpy(&st, S->ctx->d_status, 4, hipMemcpyDeviceToHost) != hipSuccess) return BLSH_EDEVICE;
+  if (st == BLSH_OK) return BLSH_OK;
+  std::vector<uint8_t> code;
+  for (const Slice &sl : it.slices) {
+    if (!sl.r->d_src || sl.r->bad_id) continue;
+    code.resize(size_t(sl.len));
+    if (hipMemcpy(code.data(), it.d_code + sl.r->arena_off + sl.begin, size_t(sl.len), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return BLSH_EDEVICE;
+    sl.r->bad_id = std::find(code.begin(), code.end(), uint8_t(0xFF)) != code.end();
+  }
+  if (!other_busy && hipMemset(S->ctx->d_status, 0, 4) != hipSuccess) return BLSH_EDEVICE;
+  return BLSH_OK;
+}
+
+int finish_iteration(blsh_server *S, Iteration &it, bool other_busy) {
   if (!it.busy) return BLSH_OK;
   it.busy = false;
   if (hipEventSynchronize(it.done) != hipSuccess) return BLSH_EDEVICE;
+  if (int rc = check_device_ids(S, it, other_busy)) return rc;
   int64_t n = 0;
   if (hipMemcpy(&n, it.d_n_acc, 8, hipMemcpyDeviceToHost) != hipSuccess) return BLSH_EDEVICE;
   if (n > it.acc_cap) return BLSH_ETRUNCATED;
@@ -246,10 +275,13 @@ void scheduler(blsh_server *S) {
       if (!S->pending.empty()) ++S->deferred;
     }
     for (Request *r : admitted) {
-      if (r->n && hipMemcpyAsync(S->d_arena + r->arena_off, r->cand.data(), size_t(r->n) * 4, hipMemcpyHostToDevice,
-                                 S->stream) != hipSuccess) {
-        S->fatal = BLSH_EDEVICE;
-      }
+      const hipError_t e =
+          r->n == 0 ? hipSuccess
+          : r->d_src ? hipMemcpyAsync(S->d_arena + r->arena_off, r->d_src, size_t(r->n) * 4, hipMemcpyDeviceToDevice,
+                                      S->stream)
+                     : hipMemcpyAsync(S->d_arena + r->arena_off, r->cand.data(), size_t(r->n) * 4,
+                                      hipMemcpyHostToDevice, S->stream);
+      if (e != hipSuccess) S->fatal = BLSH_EDEVICE;
       act.push_back(r);
     }
     // launch the next iteration, then retire the previous one
@@ -257,8 +289,8 @@ void scheduler(blsh_server *S) {
     int rc = BLSH_OK;
     if (!nx.busy) rc = launch_iteration(S, nx, act);
     Iteration &pv = S->iters[cur ^ 1];
-    if (rc == BLSH_OK) rc = finish_iteration(S, pv);
-    if (rc == BLSH_OK && !nx.busy) rc = finish_iteration(S, nx);   // nothing new was launched: drain
+    if (rc == BLSH_OK) rc = finish_iteration(S, pv, nx.busy);
+    if (rc == BLSH_OK && !nx.busy) rc = finish_iteration(S, nx, false);   // nothing new was launched: drain
     cur ^= 1;
     ++S->iterations;
     // completions
@@ -269,7 +301,7 @@ void scheduler(blsh_server *S) {
       for (Request *r : act) {
         if (S->fatal != BLSH_OK || r->finished >= r->n) {
           r->done = true;
-          r->status = S->fatal;
+          r->status = S->fatal != BLSH_OK ? S->fatal : r->bad_id ? BLSH_EBADID : BLSH_OK;
           r->t_done = S->now();
           S->arena.release(r->arena_off, r->n);
           std::vector<uint32_t>().swap(r->cand);
@@ -311,6 +343,7 @@ int bayeslsh_server_create(blsh_ctx *ctx, const blsh_sigs *index, const blsh_ser
   S->index = *index;
   S->cfg = *cfg;
   BLSH_HIP(hipSetDevice(ctx->device));
+  BLSH_HIP(hipMemset(ctx->d_status, 0, 4));   // the server owns the context from here on
   BLSH_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
   const int64_t words = int64_t(cfg->mem_budget_bytes / 4);
   if (hipMalloc(&S->d_arena, size_t(words) * 4) != hipSuccess) {
@@ -355,6 +388,28 @@ int bayeslsh_server_submit(blsh_server *srv, uint32_t query, const uint32_t *can
   r->t = t;
   r->n = n_cand;
   r->cand.assign(cand_host, cand_host + n_cand);
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (srv->fatal != BLSH_OK) return fail(srv->fatal, "server failed earlier");
+  r->id = srv->next_id++;
+  r->t_submit = srv->now();
+  *request_id = r->id;
+  srv->pending.push_back(r.get());
+  srv->all[r->id] = std::move(r);
+  srv->cv_work.notify_one();
+  return BLSH_OK;
+}
+
+int bayeslsh_server_submit_device(blsh_server *srv, uint32_t query, const uint32_t *cand_dev, int64_t n_cand,
+                                  double t, int64_t *request_id) {
+  if (!srv || !request_id || n_cand < 0 || (n_cand > 0 && !cand_dev)) return fail(BLSH_EINVAL, "bad argument");
+  if (!(t > 0 && t < 1)) return fail(BLSH_EINVAL, "t must be in (0,1)");
+  if (n_cand > srv->arena.cap) return fail(BLSH_ENOMEM, "request of %lld candidates exceeds the memory budget", (long long)n_cand);
+  if (int64_t(query) >= srv->index.n_obj) return fail(BLSH_EINVAL, "query id %u >= n_obj", query);
+  auto r = std::make_unique<Request>();
+  r->query = query;
+  r->t = t;
+  r->n = n_cand;
+  r->d_src = cand_dev;
   std::lock_guard<std::mutex> lk(srv->mu);
   if (srv->fatal != BLSH_OK) return fail(srv->fatal, "server failed earlier");
   r->id = srv->next_id++;

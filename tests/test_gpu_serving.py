@@ -11,7 +11,7 @@ import paper_1110_1328_amd as P
 from oracle import reference as R
 from synth import generators as G
 
-from gpu_util import sigs_tensor
+from gpu_util import sigs_tensor, up
 
 pytestmark = pytest.mark.gpu
 EPS, DELTA, GAMMA = 0.03, 0.05, 0.03
@@ -98,6 +98,62 @@ def test_serving_poisson_arrivals_and_limits(index):
         with pytest.raises(P.BayesLSHError):
             srv.submit(0, np.array([index.shape[0]], np.uint32), 0.8)      # id out of range
         assert srv.stats()["iterations"] > 0
+    finally:
+        srv.close()
+        ctx.close()
+
+
+def test_serving_device_submit_equals_host_and_oracle(index):
+    """Candidate ids submitted from device memory give the same output as the
+    same request submitted from the host, mixed in one stream of requests; a
+    device request with ids >= n_obj finishes with BLSH_EBADID, its other
+    candidates verified as usual, and does not mark the requests after it."""
+    print("serving device submit", flush=True)
+    ctx = P.bayeslsh_create(0)
+    S = sigs_tensor(index, P.COSINE, P.WORD_MAJOR)
+    n_obj = index.shape[0]
+    srv = P.Server(ctx, S, mem_budget_bytes=2 << 20, max_active=6, k=32, max_batch_candidates=1 << 15)
+    try:
+        reqs = make_requests(n_obj, 40, 7)
+        reqs.append((3, np.zeros(0, np.uint32), 0.8))                        # empty request
+        dev = [up(c.astype(np.uint32)) for _, c, _ in reqs]
+        ids = []
+        for i, (q, c, t) in enumerate(reqs):                                  # interleave host and device
+            ids.append((srv.submit(q, c, t), srv.submit_device(q, dev[i], t)))
+        for (rh, rd), (q, c, t) in zip(ids, reqs):
+            a, b = srv.wait(rh), srv.wait(rd)
+            assert a["status"] == 0 and b["status"] == 0
+            np.testing.assert_array_equal(a["acc_idx"], b["acc_idx"])
+            np.testing.assert_array_equal(a["acc_val"], b["acc_val"])
+            acc, sh = oracle_request(index, q, c, t)
+            np.testing.assert_array_equal(b["acc_idx"], acc)
+            np.testing.assert_allclose(b["acc_val"], sh, atol=1e-6)
+            assert b["n_candidates"] == len(c)
+            srv.release(rh)
+            srv.release(rd)
+        assert not srv._held
+        # bad ids: positions 5 and 77 out of range
+        q, c, t = reqs[1]
+        c = np.resize(c, max(len(c), 100)).astype(np.uint32)
+        bad = c.copy()
+        bad[[5, 77]] = [n_obj, 0xFFFFFFFF]
+        rb = srv.submit_device(q, up(bad), t)
+        rg = srv.submit_device(q, up(c), t)
+        res_b, res_g = srv.wait(rb), srv.wait(rg)
+        assert res_b["status"] == -5 and res_g["status"] == 0
+        ok = np.setdiff1d(np.arange(len(c)), [5, 77])
+        acc, sh = oracle_request(index, q, c[ok], t)
+        np.testing.assert_array_equal(res_b["acc_idx"], ok[acc])
+        np.testing.assert_allclose(res_b["acc_val"], sh, atol=1e-6)
+        acc, _ = oracle_request(index, q, c, t)
+        np.testing.assert_array_equal(res_g["acc_idx"], acc)
+        # a later request is clean
+        rn = srv.submit_device(q, up(c), t)
+        assert srv.wait(rn)["status"] == 0
+        with pytest.raises(P.BayesLSHError):
+            srv.submit_device(n_obj, dev[0], 0.8)                             # query out of range
+        with pytest.raises(TypeError):
+            srv.submit_device(0, dev[0].view(torch.int32), 0.8)
     finally:
         srv.close()
         ctx.close()
