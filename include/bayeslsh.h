@@ -431,8 +431,10 @@ int bayeslsh_server_submit(blsh_server *srv, uint32_t query, const uint32_t *can
 /* As bayeslsh_server_submit for candidate ids already in device memory (for
  * instance from bayeslsh_band_candidates): nothing is copied on the host; the
  * server copies them device to device into its arena when it admits the
- * request, so cand_dev must stay valid and unchanged until the request is
- * finished (poll/wait report it).  Ids are checked on the device only: a
+ * request, on its own stream, which does not wait for the caller's streams:
+ * the ids must be written (synchronised) before the call, and cand_dev must
+ * stay valid and unchanged until the request is finished (poll/wait report
+ * it).  Ids are checked on the device only: a
  * candidate with an id >= n_obj is never accepted, the other candidates are
  * verified as usual, and the request finishes with status BLSH_EBADID (its
  * accepted list still holds the valid candidates' results).  A query id >=

@@ -538,7 +538,9 @@ class Server:
 
     def submit_device(self, query: int, cand: torch.Tensor, t: float) -> int:
         """Candidate ids already on the device (uint32 tensor): no host copy.
-        The tensor is held until release()."""
+        The server's stream does not wait for the caller's: the tensor's
+        values must be complete (synchronised) before the call.  The tensor
+        is held until release()."""
         _dev(cand, torch.uint32, "cand")
         rid = C.c_int64()
         _check(_lib().bayeslsh_server_submit_device(self.handle, int(query), _p(cand), int(cand.numel()), float(t),

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbayeslsh.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["api.hip", "verify.hip", "sigs.hip", "batched.hip", "banding.hip", "tables.cpp", "server.cpp"]
+SOURCES = ["api.hip", "verify.hip", "sigs.hip", "batched.hip", "banding.hip", "serving.hip", "tables.cpp", "server.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
 # hipcc-only: no packed FP32 instructions in device code
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

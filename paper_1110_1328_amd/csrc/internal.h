@@ -108,6 +108,21 @@ int get_table(blsh_ctx *ctx, const TableKey &key, std::shared_ptr<HostTable> *ho
               hipStream_t stream);
 int ensure_workspace(blsh_ctx *ctx, size_t bytes);
 
+// Device-to-device copy of one request's candidate ids into the serving arena
+// (ids src[0, n) to arena[dst, dst + n)).
+struct CopyJob {
+  const uint32_t *src;
+  int64_t dst;
+  int64_t n;
+};
+constexpr int kCopyJobs = 64;
+// Enqueue the copies jobs[0, n_jobs) (n_jobs <= kCopyJobs) as one launch.
+int gather_copy(const CopyJob *jobs, int n_jobs, uint32_t *arena, hipStream_t s);
+// Radix sort of n (position, value) pairs by the low key_bits bits of the
+// position.  tmp == nullptr: only sets *tmp_bytes (rocPRIM's convention).
+int sort_accepted(const uint64_t *key_in, const float *val_in, uint64_t *key_out, float *val_out, int64_t n,
+                  int key_bits, void *tmp, size_t *tmp_bytes, hipStream_t s);
+
 // Launch helper with optional event bracketing.
 struct LaunchScope {
   blsh_ctx *ctx;

@@ -106,6 +106,8 @@ struct Iteration {
   uint64_t *d_acc_idx = nullptr;
   float *d_acc_val = nullptr;
   int64_t *d_n_acc = nullptr;
+  uint64_t *d_sidx = nullptr;         // accepted pairs sorted by arena position
+  float *d_sval = nullptr;
   int64_t acc_cap = 0;
   std::vector<uint64_t> h_idx;
   std::vector<float> h_val;
@@ -120,6 +122,10 @@ struct blsh_server {
   blsh_sigs index{};
   blsh_server_config cfg{};
   hipStream_t stream{};
+  hipStream_t post{};                 // sorts a finished iteration's pairs while the next one runs
+  void *d_sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  int key_bits = 1;                   // arena positions < 2^key_bits
   uint32_t *d_arena = nullptr;
   Arena arena;
   Iteration iters[2];
@@ -145,6 +151,8 @@ void iteration_free(Iteration &it) {
   if (it.d_acc_idx) hipFree(it.d_acc_idx);
   if (it.d_acc_val) hipFree(it.d_acc_val);
   if (it.d_n_acc) hipFree(it.d_n_acc);
+  if (it.d_sidx) hipFree(it.d_sidx);
+  if (it.d_sval) hipFree(it.d_sval);
   if (it.done) hipEventDestroy(it.done);
 }
 
@@ -232,19 +240,27 @@ int finish_iteration(blsh_server *S, Iteration &it, bool other_busy) {
   it.h_idx.resize(size_t(n));
   it.h_val.resize(size_t(n));
   if (n) {
-    if (hipMemcpy(it.h_idx.data(), it.d_acc_idx, size_t(n) * 8, hipMemcpyDeviceToHost) != hipSuccess) return BLSH_EDEVICE;
-    if (hipMemcpy(it.h_val.data(), it.d_acc_val, size_t(n) * 4, hipMemcpyDeviceToHost) != hipSuccess) return BLSH_EDEVICE;
+    // the iteration's event has completed, so its pairs are ready for the other stream
+    size_t tb = S->sort_tmp_bytes;
+    if (int rc = sort_accepted(it.d_acc_idx, it.d_acc_val, it.d_sidx, it.d_sval, n, S->key_bits, S->d_sort_tmp, &tb,
+                               S->post))
+      return rc;
+    if (hipMemcpyAsync(it.h_idx.data(), it.d_sidx, size_t(n) * 8, hipMemcpyDeviceToHost, S->post) != hipSuccess ||
+        hipMemcpyAsync(it.h_val.data(), it.d_sval, size_t(n) * 4, hipMemcpyDeviceToHost, S->post) != hipSuccess ||
+        hipStreamSynchronize(S->post) != hipSuccess)
+      return BLSH_EDEVICE;
   }
-  // distribute by arena position: slices are disjoint ranges
-  std::vector<std::pair<int64_t, size_t>> starts;
-  for (size_t i = 0; i < it.slices.size(); ++i) starts.push_back({it.slices[i].r->arena_off + it.slices[i].begin, i});
-  std::sort(starts.begin(), starts.end());
-  for (int64_t e = 0; e < n; ++e) {
-    const int64_t pos = int64_t(it.h_idx[e]);
-    auto ub = std::upper_bound(starts.begin(), starts.end(), std::make_pair(pos, size_t(-1)));
-    const Slice &sl = it.slices[std::prev(ub)->second];
-    sl.r->acc_idx.push_back(uint64_t(pos - sl.r->arena_off));
-    sl.r->acc_val.push_back(it.h_val[e]);
+  // slices are disjoint ranges of arena positions: each takes its range of the sorted pairs
+  for (const Slice &sl : it.slices) {
+    const uint64_t off = uint64_t(sl.r->arena_off), lo = off + uint64_t(sl.begin), hi = lo + uint64_t(sl.len);
+    const auto b = std::lower_bound(it.h_idx.begin(), it.h_idx.end(), lo);
+    const auto e = std::lower_bound(b, it.h_idx.end(), hi);
+    std::vector<uint64_t> &ri = sl.r->acc_idx;
+    const size_t at = ri.size();
+    ri.resize(at + size_t(e - b));
+    for (auto p = b; p != e; ++p) ri[at + size_t(p - b)] = *p - off;
+    sl.r->acc_val.insert(sl.r->acc_val.end(), it.h_val.begin() + (b - it.h_idx.begin()),
+                         it.h_val.begin() + (e - it.h_idx.begin()));
   }
   for (const Slice &sl : it.slices) sl.r->finished += sl.len;
   return BLSH_OK;
@@ -274,16 +290,20 @@ void scheduler(blsh_server *S) {
       }
       if (!S->pending.empty()) ++S->deferred;
     }
+    // host ids: one copy each; device ids: one gather launch per kCopyJobs requests
+    std::vector<CopyJob> jobs;
     for (Request *r : admitted) {
-      const hipError_t e =
-          r->n == 0 ? hipSuccess
-          : r->d_src ? hipMemcpyAsync(S->d_arena + r->arena_off, r->d_src, size_t(r->n) * 4, hipMemcpyDeviceToDevice,
-                                      S->stream)
-                     : hipMemcpyAsync(S->d_arena + r->arena_off, r->cand.data(), size_t(r->n) * 4,
-                                      hipMemcpyHostToDevice, S->stream);
-      if (e != hipSuccess) S->fatal = BLSH_EDEVICE;
+      if (r->n && r->d_src) {
+        jobs.push_back({r->d_src, r->arena_off, r->n});
+      } else if (r->n && hipMemcpyAsync(S->d_arena + r->arena_off, r->cand.data(), size_t(r->n) * 4,
+                                        hipMemcpyHostToDevice, S->stream) != hipSuccess) {
+        S->fatal = BLSH_EDEVICE;
+      }
       act.push_back(r);
     }
+    for (size_t i = 0; i < jobs.size(); i += kCopyJobs)
+      if (gather_copy(jobs.data() + i, int(std::min<size_t>(kCopyJobs, jobs.size() - i)), S->d_arena, S->stream))
+        S->fatal = BLSH_EDEVICE;
     // launch the next iteration, then retire the previous one
     Iteration &nx = S->iters[cur];
     int rc = BLSH_OK;
@@ -345,8 +365,22 @@ int bayeslsh_server_create(blsh_ctx *ctx, const blsh_sigs *index, const blsh_ser
   BLSH_HIP(hipSetDevice(ctx->device));
   BLSH_HIP(hipMemset(ctx->d_status, 0, 4));   // the server owns the context from here on
   BLSH_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+  if (hipStreamCreateWithFlags(&S->post, hipStreamNonBlocking) != hipSuccess) {
+    hipStreamDestroy(S->stream);
+    return fail(BLSH_EDEVICE, "stream");
+  }
   const int64_t words = int64_t(cfg->mem_budget_bytes / 4);
+  while (S->key_bits < 64 && (int64_t(1) << S->key_bits) < words) ++S->key_bits;
+  if (sort_accepted(nullptr, nullptr, nullptr, nullptr, cfg->max_batch_candidates, S->key_bits, nullptr,
+                    &S->sort_tmp_bytes, S->post) != BLSH_OK ||
+      hipMalloc(&S->d_sort_tmp, std::max<size_t>(S->sort_tmp_bytes, 256)) != hipSuccess) {
+    hipStreamDestroy(S->post);
+    hipStreamDestroy(S->stream);
+    return fail(BLSH_ENOMEM, "sort buffer");
+  }
   if (hipMalloc(&S->d_arena, size_t(words) * 4) != hipSuccess) {
+    hipFree(S->d_sort_tmp);
+    hipStreamDestroy(S->post);
     hipStreamDestroy(S->stream);
     return fail(BLSH_ENOMEM, "arena of %zu bytes", cfg->mem_budget_bytes);
   }
@@ -358,9 +392,13 @@ int bayeslsh_server_create(blsh_ctx *ctx, const blsh_sigs *index, const blsh_ser
         hipMalloc(&it.d_acc_idx, size_t(cfg->max_batch_candidates) * 8) != hipSuccess ||
         hipMalloc(&it.d_acc_val, size_t(cfg->max_batch_candidates) * 4) != hipSuccess ||
         hipMalloc(&it.d_n_acc, 256) != hipSuccess ||
+        hipMalloc(&it.d_sidx, size_t(cfg->max_batch_candidates) * 8) != hipSuccess ||
+        hipMalloc(&it.d_sval, size_t(cfg->max_batch_candidates) * 4) != hipSuccess ||
         hipEventCreateWithFlags(&it.done, hipEventDisableTiming) != hipSuccess) {
       for (auto &j : S->iters) iteration_free(j);
       hipFree(S->d_arena);
+      hipFree(S->d_sort_tmp);
+      hipStreamDestroy(S->post);
       hipStreamDestroy(S->stream);
       return fail(BLSH_ENOMEM, "iteration buffers");
     }
@@ -487,8 +525,11 @@ void bayeslsh_server_destroy(blsh_server *srv) {
   if (srv->th.joinable()) srv->th.join();
   hipSetDevice(srv->ctx->device);
   hipStreamSynchronize(srv->stream);
+  hipStreamSynchronize(srv->post);
   for (auto &it : srv->iters) iteration_free(it);
   if (srv->d_arena) hipFree(srv->d_arena);
+  if (srv->d_sort_tmp) hipFree(srv->d_sort_tmp);
+  hipStreamDestroy(srv->post);
   hipStreamDestroy(srv->stream);
   delete srv;
 }

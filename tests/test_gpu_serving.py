@@ -157,3 +157,26 @@ def test_serving_device_submit_equals_host_and_oracle(index):
     finally:
         srv.close()
         ctx.close()
+
+
+def test_serving_device_submit_many_per_admission(index):
+    """More device-submitted requests admitted at once than one copy launch
+    takes (64): every request still equals the oracle."""
+    print("serving device submit, 150 at once", flush=True)
+    ctx = P.bayeslsh_create(0)
+    S = sigs_tensor(index, P.COSINE, P.WORD_MAJOR)
+    srv = P.Server(ctx, S, mem_budget_bytes=16 << 20, max_active=256, k=32, max_batch_candidates=1 << 20)
+    try:
+        reqs = make_requests(index.shape[0], 150, 8, lo=0, hi=3.8)
+        dev = [up(c) for _, c, _ in reqs]
+        torch.cuda.synchronize()
+        ids = [srv.submit_device(q, d, t) for (q, _, t), d in zip(reqs, dev)]
+        for rid, (q, c, t) in zip(ids, reqs):
+            res = srv.wait(rid)
+            assert res["status"] == 0
+            acc, sh = oracle_request(index, q, c, t)
+            np.testing.assert_array_equal(res["acc_idx"], acc)
+            np.testing.assert_allclose(res["acc_val"], sh, atol=1e-6)
+    finally:
+        srv.close()
+        ctx.close()
