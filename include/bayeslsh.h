@@ -411,8 +411,8 @@ typedef struct {
 
 /* Result of a finished request.  The arrays are owned by the server and stay
  * valid until bayeslsh_server_release.  acc_idx are positions in the
- * request's candidate list (sorted order is not guaranteed).  Times are
- * seconds on the server's clock (bayeslsh_server_clock). */
+ * request's candidate list, in increasing order.  Times are seconds on the
+ * server's clock (bayeslsh_server_clock). */
 typedef struct {
   int64_t n_candidates;
   int64_t n_accepted;

@@ -552,10 +552,10 @@ class Server:
     def _result(r: "A.RequestResult"):
         import numpy as np
         n = r.n_accepted
-        idx = np.ctypeslib.as_array(r.acc_idx_host, shape=(n,)).copy() if n else np.zeros(0, np.uint64)
+        # positions come in increasing order
+        idx = np.ctypeslib.as_array(r.acc_idx_host, shape=(n,)).astype(np.int64) if n else np.zeros(0, np.int64)
         val = np.ctypeslib.as_array(r.acc_val_host, shape=(n,)).copy() if n else np.zeros(0, np.float32)
-        o = np.argsort(idx, kind="stable")
-        return dict(n_candidates=r.n_candidates, acc_idx=idx[o].astype(np.int64), acc_val=val[o],
+        return dict(n_candidates=r.n_candidates, acc_idx=idx, acc_val=val,
                     submit=r.submit_time_s, admit=r.admit_time_s, done=r.done_time_s, status=r.status)
 
     def poll(self, rid: int):
