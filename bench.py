@@ -353,45 +353,37 @@ def run_serving(args, torch, P):
         run.server_s = max(o["done"] for o in out) - min(o["submit"] for o in out)
         return el, lat, out
 
-    run(None)                                            # warm (graphs, tables)
-    el, lat, out0 = run(None)
-    sat_qps = nq / el
-    res = {"saturated": {"queries_per_s": sat_qps, "pairs_per_s": total / el,
-                         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                         "client_submit_s": run.submit_s, "elapsed_s": el, "server_span_s": run.server_s,
-                         "server_pairs_per_s": total / run.server_s}}
-    log("saturated: %.0f q/s, %.3g pairs/s" % (sat_qps, total / el))
-    for rho in (0.5, 0.8, 0.95):
-        gaps = np.cumsum(np.random.default_rng(int(rho * 100)).exponential(1.0 / (rho * sat_qps), nq))
-        el, lat, out = run(gaps)
-        same = all(np.array_equal(a["acc_idx"], b["acc_idx"]) and np.array_equal(a["acc_val"], b["acc_val"])
-                   for a, b in zip(out0, out))
-        res["rho_%.2f" % rho] = {"queries_per_s": nq / el, "pairs_per_s": total / el,
-                                 "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "same_results": same}
-        log("rho %.2f: p50 %.2f ms p99 %.2f ms" % (rho, res["rho_%.2f" % rho]["p50_ms"], res["rho_%.2f" % rho]["p99_ms"]))
+    def stats(el, lat, out, ref):
+        d = {"queries_per_s": nq / el, "pairs_per_s": total / el, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+             "p99_ms": float(np.percentile(lat, 99) * 1e3), "client_submit_s": run.submit_s, "elapsed_s": el,
+             "server_span_s": run.server_s, "server_pairs_per_s": total / run.server_s}
+        if ref is not None:
+            d["same_results"] = all(np.array_equal(a["acc_idx"], b["acc_idx"]) and
+                                    np.array_equal(a["acc_val"], b["acc_val"]) for a, b in zip(ref, out))
+        return d
+
+    res, out0 = {}, None
+    if args.serving_legs == "all":
+        run(None)                                        # warm (graphs, tables)
+        el, lat, out0 = run(None)
+        sat_qps = nq / el
+        res["saturated"] = stats(el, lat, out0, None)
+        log("saturated: %.0f q/s, %.3g pairs/s" % (sat_qps, total / el))
+        for rho in (0.5, 0.8, 0.95):
+            gaps = np.cumsum(np.random.default_rng(int(rho * 100)).exponential(1.0 / (rho * sat_qps), nq))
+            key = "rho_%.2f" % rho
+            res[key] = stats(*run(gaps), out0)
+            log("rho %.2f: p50 %.2f ms p99 %.2f ms" % (rho, res[key]["p50_ms"], res[key]["p99_ms"]))
     # the same requests with candidate ids already resident on the device
     dcand = up(torch, cand)
     run(None)
     el, lat, out = run(None)
     dev_qps = nq / el
-    same = all(np.array_equal(a["acc_idx"], b["acc_idx"]) and np.array_equal(a["acc_val"], b["acc_val"])
-               for a, b in zip(out0, out))
-    res["device_saturated"] = {"queries_per_s": dev_qps, "pairs_per_s": total / el,
-                               "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                               "p99_ms": float(np.percentile(lat, 99) * 1e3), "same_results": same,
-                               "client_submit_s": run.submit_s, "elapsed_s": el, "server_span_s": run.server_s,
-                               "server_pairs_per_s": total / run.server_s}
+    res["device_saturated"] = stats(el, lat, out, out0)
     log("device submit, saturated: %.0f q/s, %.3g pairs/s (server span %.1f ms: %.3g pairs/s)" % (
         dev_qps, total / el, run.server_s * 1e3, total / run.server_s))
     gaps = np.cumsum(np.random.default_rng(95).exponential(1.0 / (0.95 * dev_qps), nq))
-    el, lat, out = run(gaps)
-    same = all(np.array_equal(a["acc_idx"], b["acc_idx"]) and np.array_equal(a["acc_val"], b["acc_val"])
-               for a, b in zip(out0, out))
-    res["device_rho_0.95"] = {"queries_per_s": nq / el, "pairs_per_s": total / el,
-                              "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                              "p99_ms": float(np.percentile(lat, 99) * 1e3), "same_results": same,
-                              "client_submit_s": run.submit_s, "elapsed_s": el, "server_span_s": run.server_s}
+    res["device_rho_0.95"] = stats(*run(gaps), out0 if out0 is not None else out)
     log("device submit, rho 0.95: p50 %.2f ms p99 %.2f ms" % (res["device_rho_0.95"]["p50_ms"],
                                                                res["device_rho_0.95"]["p99_ms"]))
     dcand = None
@@ -399,10 +391,13 @@ def run_serving(args, torch, P):
     srv.close()
     ctx.close()
     return {"metric": "serving: candidate pairs verified/sec and query latency", "unit": "pairs/s",
-            "value": res["saturated"]["pairs_per_s"], "n_gpus": 1, "data": "synthetic", "dtype": "u32",
+            "value": res["saturated" if "saturated" in res else "device_saturated"]["pairs_per_s"], "n_gpus": 1,
+            "data": "synthetic", "dtype": "u32",
             "config": {"workload": "serving: %d queries against 1M x 1024-bit dense cosine index, candidates "
                                    "10^U(3,6) per query (1%% from the query's mixture component), t=0.8, k=32, "
-                                   "max_active=128, 8M candidates per iteration, 2 GiB arena" % nq, "n_candidates": total,
+                                   "max_active=128, 8M candidates per iteration, 2 GiB arena%s" % (
+                                       nq, "" if args.serving_legs == "all" else "; device-memory submissions only"),
+                       "n_candidates": total,
                        "mean_candidates": float(lens.mean())},
             "latency": res, "server_stats": st}
 
@@ -586,6 +581,8 @@ def main():
                          "Algorithm 1 over all ~2e9 candidates; sweep: the paper's experiments on the tf-idf "
                          "workload (pruning curve, gamma/delta/epsilon, BayesLSH vs Lite by threshold)")
     ap.add_argument("--queries", type=int, default=10000, help="serving: number of queries")
+    ap.add_argument("--serving-legs", choices=["all", "device"], default="all",
+                    help="serving: all legs, or only the device-memory submissions (for a kernel trace)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,

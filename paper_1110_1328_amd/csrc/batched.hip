@@ -14,8 +14,9 @@
 //   wave's own region of the measure's survivor queue (ballot compaction, no
 //   atomics); when the region is full it simply continues in registers.
 // Phase 2 (k_batch_phase2): persistent blocks drain the survivor queues with
-//   every lane busy: one lane per SRP survivor, one group of k/4 lanes per
-//   minhash survivor, running the remaining levels.
+//   every lane busy: one lane per SRP survivor (the words of the next levels
+//   loaded ahead), one group of k/4 lanes per minhash survivor, running the
+//   remaining levels; a block takes the regions it drains as one list.
 //
 // Accepted pairs are staged in slices (as in the single-call paths) and
 // appended to the caller's list by k_batch_flush at the end of the batch.
@@ -453,42 +454,108 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase1(const BatchBlock *__re
 // ---------------------------------------------------------------------------
 // phase 2: spilled survivors
 // ---------------------------------------------------------------------------
+// Block b drains the regions of phase-1 waves b, b + grid, ... taken together
+// as one list: a region holds few survivors, and each survivor is a chain of
+// dependent level loads, so passes over the concatenation overlap the chains
+// of all its regions.  Item i of that list: its wave and its entry there.
+__device__ inline bool region_item(const uint32_t *count, int64_t n_waves, int64_t i, int64_t &w_out,
+                                   int64_t &k_out) {
+  int64_t acc = 0;
+  for (int64_t w = blockIdx.x; w < n_waves; w += gridDim.x) {
+    const int64_t n = count[w];
+    if (i < acc + n) {
+      w_out = w;
+      k_out = i - acc;
+      return true;
+    }
+    acc += n;
+  }
+  return false;
+}
+
+__device__ inline int64_t block_region_total(const uint32_t *count, int64_t n_waves) {
+  int64_t t = 0;
+  for (int64_t w = blockIdx.x; w < n_waves; w += gridDim.x) t += count[w];
+  return t;
+}
+
+// SRP words of level j of q and y (k = 16: the word holding the level)
+template <int K>
+struct LevelWords {
+  uint32_t q[K == 64 ? 2 : 1], y[K == 64 ? 2 : 1];
+};
+template <int K>
+__device__ inline void load_level(const SigView &s, uint32_t q, uint32_t y, int j, LevelWords<K> &w) {
+  auto word = [&](uint32_t id, int i) -> uint32_t {
+    return s.word_major ? s.data[size_t(i) * s.n_obj + id] : s.data[size_t(id) * s.row_words + i];
+  };
+  if constexpr (K == 64) {
+    w.q[0] = word(q, 2 * j);
+    w.q[1] = word(q, 2 * j + 1);
+    w.y[0] = word(y, 2 * j);
+    w.y[1] = word(y, 2 * j + 1);
+  } else {
+    const int i = K == 32 ? j : j >> 1;
+    w.q[0] = word(q, i);
+    w.y[0] = word(y, i);
+  }
+}
+template <int K>
+__device__ inline uint32_t level_agree(const LevelWords<K> &w, int j) {
+  if constexpr (K == 64) return 64u - __popc(w.q[0] ^ w.y[0]) - __popc(w.q[1] ^ w.y[1]);
+  else if constexpr (K == 32) return 32u - __popc(w.q[0] ^ w.y[0]);
+  else return 16u - __popc(((w.q[0] ^ w.y[0]) >> ((j & 1) * 16)) & 0xFFFFu);
+}
+
+// SRP levels whose words are loaded before the first of them is decided: four
+// shorten the chain of a deep survivor (dense serving 50 -> 41 ms); at k = 64
+// a level is already two words per side and the loads past the decision cost
+// more than they save.
+template <int K>
+constexpr int phase2_ahead() { return K == 64 ? 1 : 4; }
+
 template <int KJ, int KC>
 __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__restrict__ Bp) {
   constexpr int G = KJ / 4;
+  constexpr int AHEAD = phase2_ahead<KC>();
   const BatchBlock &B = *Bp;
-  // block b drains the regions of phase-1 waves b, b + grid, ...
   const int64_t R = B.spill_region;
   // SRP survivors: one lane each
-  for (int64_t w = blockIdx.x; w < B.spill_waves; w += gridDim.x) {
-    const int64_t n = B.spill_count[BLSH_COSINE][w];
-    const uint4 *slice = B.spill[BLSH_COSINE] + w * R;
+  {
     const SigView &S = B.sig[BLSH_COSINE];
-    for (int64_t i0 = 0; i0 < n; i0 += kBBlock) {
-      const int64_t i = i0 + threadIdx.x;
-      bool act = i < n;
+    const uint32_t *cnt = B.spill_count[BLSH_COSINE];
+    const int64_t total = block_region_total(cnt, B.spill_waves);
+    for (int64_t i0 = 0; i0 < total; i0 += kBBlock) {
+      int64_t w = 0, k = 0;
+      const bool act = region_item(cnt, B.spill_waves, i0 + threadIdx.x, w, k);
       int64_t pos = 0;
-      uint32_t m = 0, q = 0, yv = 0;
-      int j = 0, L = 0, words = 0;
-      const uint32_t *tab = nullptr;
+      uint32_t m = 0;
       uint8_t code = 0;
       bool emit = false;
       if (act) {
-        const uint4 e = slice[i];
+        const uint4 e = B.spill[BLSH_COSINE][w * R + k];
         pos = int64_t(uint64_t(e.x) | (uint64_t(e.y) << 32));
         const BatchList Ls = B.lists[e.z];
-        tab = B.tables[Ls.table];
-        L = B.n_levels[Ls.table];
-        words = int(tab[2]);
+        const uint32_t *tab = B.tables[Ls.table];
+        const int L = B.n_levels[Ls.table];
+        const int words = int(tab[2]);
         m = e.w & 0xFFFFu;
-        j = int(e.w >> 16);
-        q = Ls.query;
-        yv = B.cand[pos];
-        for (; j < L; ++j) {
-          m += srp_level_word_agree<KC>(S, q, yv, j);
-          if (int(m) < int(tab[kTabMinOff + j])) { code = uint8_t((BLSH_PRUNED << 6) | j); break; }
-          if (accept_bit(tab, words, j, int(m))) { code = uint8_t((BLSH_ACCEPT_CONC << 6) | j); emit = true; break; }
-          if (j == L - 1) { code = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); emit = true; break; }
+        const uint32_t q = Ls.query, yv = B.cand[pos];
+        bool done = false;
+        for (int j0 = int(e.w >> 16); j0 < L && !done; j0 += AHEAD) {
+          LevelWords<KC> lw[AHEAD];
+#pragma unroll
+          for (int d = 0; d < AHEAD; ++d)
+            if (j0 + d < L) load_level<KC>(S, q, yv, j0 + d, lw[d]);
+#pragma unroll
+          for (int d = 0; d < AHEAD; ++d) {
+            const int j = j0 + d;
+            if (done || j >= L) break;
+            m += level_agree<KC>(lw[d], j);
+            if (int(m) < int(tab[kTabMinOff + j])) { code = uint8_t((BLSH_PRUNED << 6) | j); done = true; }
+            else if (accept_bit(tab, words, j, int(m))) { code = uint8_t((BLSH_ACCEPT_CONC << 6) | j); emit = true; done = true; }
+            else if (j == L - 1) { code = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); emit = true; done = true; }
+          }
         }
         B.code[pos] = code;
         if (B.m_dbg) B.m_dbg[pos] = uint16_t(m);
@@ -498,21 +565,21 @@ __global__ __launch_bounds__(kBBlock) void k_batch_phase2(const BatchBlock *__re
     }
   }
   // minhash survivors: one group of G lanes each
-  for (int64_t w = blockIdx.x; w < B.spill_waves; w += gridDim.x) {
-    const int64_t n = B.spill_count[BLSH_JACCARD][w];
-    const uint4 *slice = B.spill[BLSH_JACCARD] + w * R;
+  {
     const SigView &S = B.sig[BLSH_JACCARD];
+    const uint32_t *cnt = B.spill_count[BLSH_JACCARD];
+    const int64_t total = block_region_total(cnt, B.spill_waves);
     constexpr int PER_BLOCK = kBBlock / G;
     const int g = threadIdx.x / G, r = threadIdx.x % G;
-    for (int64_t i0 = 0; i0 < n; i0 += PER_BLOCK) {
-      const int64_t i = i0 + g;
-      const bool act = i < n;
+    for (int64_t i0 = 0; i0 < total; i0 += PER_BLOCK) {
+      int64_t w = 0, k = 0;
+      const bool act = region_item(cnt, B.spill_waves, i0 + g, w, k);
       int64_t pos = 0;
       uint32_t m = 0, q = 0, yv = 0;
       int j = 0, L = 0, words = 0;
       const uint32_t *tab = nullptr;
       if (act) {
-        const uint4 e = slice[i];
+        const uint4 e = B.spill[BLSH_JACCARD][w * R + k];
         pos = int64_t(uint64_t(e.x) | (uint64_t(e.y) << 32));
         const BatchList Ls = B.lists[e.z];
         tab = B.tables[Ls.table];

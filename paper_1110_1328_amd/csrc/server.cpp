@@ -291,23 +291,24 @@ void scheduler(blsh_server *S) {
       if (!S->pending.empty()) ++S->deferred;
     }
     // host ids: one copy each; device ids: one gather launch per kCopyJobs requests
+    // (S->fatal is shared with the submitting threads: errors go through rc, set under the lock below)
+    int rc = BLSH_OK;
     std::vector<CopyJob> jobs;
     for (Request *r : admitted) {
       if (r->n && r->d_src) {
         jobs.push_back({r->d_src, r->arena_off, r->n});
       } else if (r->n && hipMemcpyAsync(S->d_arena + r->arena_off, r->cand.data(), size_t(r->n) * 4,
                                         hipMemcpyHostToDevice, S->stream) != hipSuccess) {
-        S->fatal = BLSH_EDEVICE;
+        rc = BLSH_EDEVICE;
       }
       act.push_back(r);
     }
-    for (size_t i = 0; i < jobs.size(); i += kCopyJobs)
+    for (size_t i = 0; i < jobs.size() && rc == BLSH_OK; i += kCopyJobs)
       if (gather_copy(jobs.data() + i, int(std::min<size_t>(kCopyJobs, jobs.size() - i)), S->d_arena, S->stream))
-        S->fatal = BLSH_EDEVICE;
+        rc = BLSH_EDEVICE;
     // launch the next iteration, then retire the previous one
     Iteration &nx = S->iters[cur];
-    int rc = BLSH_OK;
-    if (!nx.busy) rc = launch_iteration(S, nx, act);
+    if (rc == BLSH_OK && !nx.busy) rc = launch_iteration(S, nx, act);
     Iteration &pv = S->iters[cur ^ 1];
     if (rc == BLSH_OK) rc = finish_iteration(S, pv, nx.busy);
     if (rc == BLSH_OK && !nx.busy) rc = finish_iteration(S, nx, false);   // nothing new was launched: drain
