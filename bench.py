@@ -402,6 +402,82 @@ def run_serving(args, torch, P):
             "latency": res, "server_stats": st}
 
 
+def run_sigs(args, torch, P):
+    """Signature generation (untimed in every verification step), each call
+    timed with HIP events on its stream, median of 5 after a warm-up:
+    - dense SRP of the 1M x 256 mixture against 1024 Gaussian planes on the
+      FP32 matrix cores: 2 d n_bits flops per row, against the 157.3 TFLOP/s
+      dense FP32 MFMA peak;
+    - sparse SRP of the 100k-document tf-idf corpus at 2048 bits, plane entries
+      drawn on the fly (Philox-4x32-10 + Box-Muller, FP64 accumulation):
+      n_bits Gaussians per nonzero;
+    - 256 minhashes of the 1M planted-group sets: one multiply-mod and min per
+      (element, hash)."""
+    from synth import generators as G
+    ctx = P.bayeslsh_create(0)
+    s = torch.cuda.current_stream()
+
+    def timed(fn, reps=5):
+        fn()
+        P.bayeslsh_sync(ctx, s)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(reps):
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        P.bayeslsh_sync(ctx, s)
+        return float(np.median(ts)), float(min(ts))
+
+    log("dense mixture (1M x 256), 1024 planes")
+    mix = G.dense_mixture(seed=G.SEED_BASE + 4)
+    planes = up(torch, G.gaussian_planes(256, 1024, G.SEED_BASE + 204))
+    xd = up(torch, mix.x)
+    n_d = mix.x.shape[0]
+    out_d = torch.empty(n_d * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
+    dense_ms, dense_min = timed(lambda: P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), planes, 1024, 0,
+                                                            P.OBJECT_MAJOR, out_d, s))
+    flops = 2.0 * n_d * 256 * 1024
+    tflops = flops / (dense_ms * 1e-3) / 1e12
+    log("dense SRP: %.3f ms, %.1f TFLOP/s" % (dense_ms, tflops))
+    del xd, out_d
+    log("tf-idf corpus (100k documents)")
+    corpus = G.tfidf_corpus(seed=G.SEED_BASE + 2)
+    nnz = len(corpus.indices)
+    vec = P.csr_vectors(up(torch, corpus.offsets), up(torch, corpus.indices), up(torch, corpus.values), corpus.dim)
+    out_s = torch.empty(corpus.n * (N_BITS // 32), dtype=torch.int32, device="cuda").view(torch.uint32)
+    sparse_ms, sparse_min = timed(lambda: P.bayeslsh_srp_sigs(ctx, vec, None, N_BITS, SRP_SEED, P.OBJECT_MAJOR,
+                                                              out_s, s))
+    log("sparse SRP: %.3f ms, %.3g Gaussians/s" % (sparse_ms, nnz * N_BITS / (sparse_ms * 1e-3)))
+    del vec, out_s
+    log("planted-group sets (1M), 256 minhashes")
+    sets = G.jaccard_sets_large(seed=G.SEED_BASE + 5)
+    a, b = G.minhash_coeffs(256, G.SEED_BASE + 205)
+    sv = P.set_vectors(up(torch, sets.offsets), up(torch, sets.elems), sets.vocab)
+    da, db = up(torch, a), up(torch, b)
+    out_m = torch.empty(sets.n * 256, dtype=torch.int32, device="cuda").view(torch.uint32)
+    mh_ms, mh_min = timed(lambda: P.bayeslsh_minhash_sigs(ctx, sv, da, db, out_m, s))
+    n_el = len(sets.elems)
+    log("minhash: %.3f ms, %.3g hash evaluations/s" % (mh_ms, n_el * 256 / (mh_ms * 1e-3)))
+    ctx.close()
+    return {"metric": "signature generation: dense SRP on the FP32 matrix cores", "value": tflops,
+            "unit": "TFLOP/s", "n_gpus": 1, "ms_per_step": dense_ms, "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "signature generation: dense SRP 1M x 256 fp32 rows x 1024 planes; sparse SRP "
+                                   "100k tf-idf documents x 2048 bits (planes on the fly); 256 minhashes of 1M sets"},
+            "roofline": {"bound": "mfma", "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s",
+                         "frac": tflops / 157.3, "traffic": None, "kernel": "k_srp_dense_mfma<256>",
+                         "flops_per_launch": flops},
+            "dense_srp": {"ms": dense_ms, "min_ms": dense_min, "rows": n_d, "dim": 256, "n_bits": 1024,
+                          "tflops": tflops},
+            "sparse_srp": {"ms": sparse_ms, "min_ms": sparse_min, "rows": corpus.n, "nnz": nnz, "n_bits": N_BITS,
+                           "gaussians_per_s": nnz * N_BITS / (sparse_ms * 1e-3)},
+            "minhash": {"ms": mh_ms, "min_ms": mh_min, "sets": sets.n, "elements": n_el, "n_hashes": 256,
+                        "hash_evals_per_s": n_el * 256 / (mh_ms * 1e-3)}}
+
+
 def run_dense(args, torch, P):
     """Dense cosine estimation: 1M x 256 Gaussian-mixture vectors, 1024 SRP bits
     (object-major rows + prefix array) for verification; candidates from GPU LSH
@@ -574,12 +650,13 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="time a plain 1 GiB device copy and exit")
     ap.add_argument("--layout", choices=["prefix", "word-major"], default="prefix",
                     help="SRP layout verified: object-major 128-bit rows (prefix) or word-major slabs of all bits")
-    ap.add_argument("--workload", choices=["lite", "batched", "serving", "dense", "sweep"], default="lite",
+    ap.add_argument("--workload", choices=["lite", "batched", "serving", "dense", "sweep", "sigs"], default="lite",
                     help="lite: the cosine BayesLSH-Lite line (default); batched: 4096 mixed query lists in one "
                          "graph launch vs the exhaustive batched comparator; serving: Poisson arrivals against the "
                          "dense cosine index, p50/p99 latency; dense: GPU LSH banding of 1M dense vectors then "
                          "Algorithm 1 over all ~2e9 candidates; sweep: the paper's experiments on the tf-idf "
-                         "workload (pruning curve, gamma/delta/epsilon, BayesLSH vs Lite by threshold)")
+                         "workload (pruning curve, gamma/delta/epsilon, BayesLSH vs Lite by threshold); sigs: "
+                         "signature generation (dense SRP on MFMA, sparse SRP, minhash)")
     ap.add_argument("--queries", type=int, default=10000, help="serving: number of queries")
     ap.add_argument("--serving-legs", choices=["all", "device"], default="all",
                     help="serving: all legs, or only the device-memory submissions (for a kernel trace)")
@@ -606,6 +683,9 @@ def main():
         return
     if args.workload == "sweep":
         print(json.dumps(run_sweep(args, torch, P)), flush=True)
+        return
+    if args.workload == "sigs":
+        print(json.dumps(run_sigs(args, torch, P)), flush=True)
         return
     log("generating workload")
     corpus, x, y = build_workload(args.small)
