@@ -141,12 +141,16 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // X: [n_rows][D] fp32, R: [D][n_bits] fp32.  Block = 4 waves = 128 rows; the
 // D dimension is split between the two half-waves: lanes 0..31 cover
 // d in [0, D/2) and lanes 32..63 cover [D/2, D), so that each lane's A
-// operands are one contiguous half-row of X.
+// operands are one contiguous half-row of X.  The 32-plane slices of R are
+// double-buffered in LDS: the next slice is read into registers before the
+// current one's MFMA loop and written to the other buffer after it, so one
+// barrier per slice remains and the reads overlap the matrix work.
 template <int D>
-__global__ __launch_bounds__(256) void k_srp_dense_mfma(const float *X, int64_t n_rows, const float *R,
+__global__ __launch_bounds__(256, 2) void k_srp_dense_mfma(const float *X, int64_t n_rows, const float *R,
                                                         int32_t n_bits, int32_t word_major, uint32_t *out) {
   constexpr int HD = D / 2;
-  __shared__ float sR[D * 32];  // one 32-plane slice: sR[d*32 + j] = R[d][col0 + j]
+  constexpr int PER = D * 32 / 256;   // slice entries per thread
+  __shared__ float sR[2][D * 32];     // 32-plane slices: sR[b][d*32 + j] = R[d][col0 + j]
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
   const int h = lane >> 5, i = lane & 31;
@@ -168,17 +172,28 @@ __global__ __launch_bounds__(256) void k_srp_dense_mfma(const float *X, int64_t 
   // row held in the result word by this lane (lanes 0..31): t = lane
   const int t = lane & 31;
   const int my_v = 4 * (t >> 3) + (t & 3), my_h = (t >> 2) & 1;
-  for (int tile = 0; tile < W; ++tile) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < D * 32; idx += 256) {
-      const int d = idx >> 5, j = idx & 31;
-      sR[idx] = R[size_t(d) * n_bits + tile * 32 + j];
+  float st[PER];
+  auto fetch = [&](int tile) {   // entry idx = threadIdx.x + 256 u of the slice: d = idx / 32, j = idx % 32
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = int(threadIdx.x) + 256 * u;
+      st[u] = R[size_t(idx >> 5) * n_bits + tile * 32 + (idx & 31)];
     }
-    __syncthreads();
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) sR[b][int(threadIdx.x) + 256 * u] = st[u];
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int tile = 0; tile < W; ++tile) {
+    const int b = tile & 1;
+    if (tile + 1 < W) fetch(tile + 1);
     floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < HD; ++s) {
-      const float bv = sR[(h * HD + s) * 32 + i];
+      const float bv = sR[b][(h * HD + s) * 32 + i];
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[s], bv, acc, 0, 0, 0);
     }
     uint32_t word = 0;
@@ -192,6 +207,10 @@ __global__ __launch_bounds__(256) void k_srp_dense_mfma(const float *X, int64_t 
       if (word_major) out[size_t(tile) * n_rows + r] = word;
       else out[size_t(r) * W + tile] = word;
     }
+    // buffer b ^ 1 was last read in the previous slice, before the barrier
+    // that ended it; the barrier below orders these writes before its reads
+    if (tile + 1 < W) stash(b ^ 1);
+    __syncthreads();
   }
 }
 

@@ -79,7 +79,7 @@ def test_sparse_srp_signatures_flip_rule(ctx, n_bits, layout):
 
 
 @pytest.mark.parametrize("d,n_bits,layout", [(256, 1024, P.WORD_MAJOR), (64, 64, P.OBJECT_MAJOR),
-                                             (128, 256, P.OBJECT_MAJOR)])
+                                             (128, 256, P.OBJECT_MAJOR), (32, 32, P.OBJECT_MAJOR)])
 def test_dense_srp_mfma_flip_rule(ctx, d, n_bits, layout):
     _flush("dense srp sigs: d=%d bits=%d" % (d, n_bits))
     mix = G.dense_mixture(n=5000 + 37, d=d, n_comp=50, seed=G.SEED_BASE + 31)   # ragged row tail
