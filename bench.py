@@ -5,8 +5,10 @@ compare with the same output, on one MI355X.
 Workload (default): the cosine BayesLSH-Lite configuration -- 100,000 sparse
 tf-idf vectors (dimension 2^20, Poisson(100) nonzeros, Zipf(1.1) terms, 5%
 planted near-duplicates), 2048 sign-random-projection bits per vector,
-candidates from 16-band x 10-bit LSH banding on an independent projection,
-t = 0.7, epsilon = 0.03, h = 128, k = 32, exact cosine on survivors.
+candidates from 16-band x 10-bit LSH banding on an independent projection
+(on the device, each bucket's pairs in 16 x 16 tiles of its members; timed
+apart from the step), t = 0.7, epsilon = 0.03, h = 128, k = 32, exact cosine
+on survivors.
 
 One step = one bayeslsh_lite_verify call over all candidates with signatures
 and candidates resident in HBM and the posterior table cached.  The
@@ -61,6 +63,31 @@ def build_workload(small: bool):
         corpus = G.tfidf_corpus(seed=G.SEED_BASE + 2)
         x, y = G.sparse_band_candidates(corpus, n_bands=16, band_bits=10, seed=G.SEED_BASE + 102)
     return corpus, x, y
+
+
+def lite_candidates(torch, P, ctx, corpus, small):
+    """The 16-band LSH candidates of the tf-idf corpus, generated on the device:
+    the band keys are the sign bits of the independent Gaussian projection that
+    build_workload bands (10 bits a band; 8 for the small corpus), and
+    bayeslsh_band_candidates lists each bucket's pairs in 16 x 16 tiles of its
+    members (first-band dedupe), the order the compare kernel reads best.  The
+    candidate set is the one build_workload lists.  Returns device x, y, the
+    count and the time of a second, timed banding call in ms."""
+    from synth import generators as G
+    bb = 8 if small else 10
+    words = G.sparse_band_bits(corpus, n_bands=16, band_bits=bb, seed=G.SEED_BASE + 102)
+    S_band = P.Signatures(up(torch, words.reshape(-1)), P.COSINE, P.OBJECT_MAJOR, corpus.n, words.shape[1] * 32)
+    cap = 1 << 27
+    xo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
+    yo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_band_candidates(ctx, S_band, 16, bb, cap, x_out=xo, y_out=yo, order_tile=16)   # sizes its buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, n, trunc = P.bayeslsh_band_candidates(ctx, S_band, 16, bb, cap, x_out=xo, y_out=yo, order_tile=16)
+    band_ms = (time.perf_counter() - t0) * 1e3
+    if trunc:
+        raise RuntimeError("banding: %d candidates exceed the %d-entry buffers" % (n, cap))
+    return xo[:n], yo[:n], n, band_ms
 
 
 def cpu_baseline(corpus, x, y, gpu_codes):
@@ -688,12 +715,14 @@ def main():
         print(json.dumps(run_sigs(args, torch, P)), flush=True)
         return
     log("generating workload")
-    corpus, x, y = build_workload(args.small)
-    n = len(x)
-    log("corpus %d docs, %d nnz; %d candidates" % (corpus.n, len(corpus.indices), n))
+    from synth import generators as G
+    corpus = G.tfidf_corpus(n_docs=20_000, seed=G.SEED_BASE + 2) if args.small else G.tfidf_corpus(seed=G.SEED_BASE + 2)
     ctx = P.bayeslsh_create(0)
+    xd, yd, n, band_ms = lite_candidates(torch, P, ctx, corpus, args.small)
+    x = xd.view(torch.int32).cpu().numpy().view(np.uint32)      # host copies for the oracle baseline
+    y = yd.view(torch.int32).cpu().numpy().view(np.uint32)
+    log("corpus %d docs, %d nnz; %d candidates (GPU banding, %.1f ms)" % (corpus.n, len(corpus.indices), n, band_ms))
     vec = P.csr_vectors(up(torch, corpus.offsets), up(torch, corpus.indices), up(torch, corpus.values), corpus.dim)
-    xd, yd = up(torch, x), up(torch, y)
     W = N_BITS // 32
     sig_wm = torch.empty(corpus.n * W, dtype=torch.int32, device="cuda").view(torch.uint32)
     sig_om = torch.empty(corpus.n * W, dtype=torch.int32, device="cuda").view(torch.uint32)
@@ -801,9 +830,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": ("cosine BayesLSH-Lite: %d sparse tf-idf vectors (dim 2^20, Poisson(100) nnz, Zipf(1.1), 5%% "
-                         "planted near-duplicates), 2048 SRP bits, 16-band LSH candidates, t=0.7, eps=0.03, h=128, "
-                         "k=32, exact FP64-accumulated cosine on survivors" % corpus.n),
+                         "planted near-duplicates), 2048 SRP bits, 16-band LSH candidates (GPU banding, 16 x 16 "
+                         "tiles per bucket), t=0.7, eps=0.03, h=128, k=32, exact FP64-accumulated cosine on "
+                         "survivors" % corpus.n),
             "n_candidates": n,
+            "banding_ms": band_ms,
             "survivors_after_h": n_surv,
             "accepted": int(len(ia)),
             "pruned_at_level": [int(np.sum((dec == 0) & (lvl == j))) for j in range(H // K)],

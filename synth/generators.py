@@ -341,13 +341,26 @@ def sparse_band_candidates(corpus: SparseCorpus, n_bands=16, band_bits=10, seed=
     return band_candidates(_sparse_project(corpus, n_bands * band_bits, seed), n_bands, band_bits)
 
 
+def sparse_band_bits(corpus: SparseCorpus, n_bands=16, band_bits=10, seed=SEED_BASE + 102) -> np.ndarray:
+    """The sign bits that sparse_band_candidates bands, packed 32 to a uint32
+    word, least significant bit first: bit b * band_bits + t of an object is
+    the sign of its projection on plane b * band_bits + t (the rest of the
+    last word is zero).  Shape [n, ceil(n_bands * band_bits / 32)]."""
+    nb = n_bands * band_bits
+    proj = _sparse_project(corpus, nb, seed)
+    w = (nb + 31) // 32
+    bits = np.zeros((corpus.n, w * 32), np.uint64)
+    bits[:, :nb] = proj >= 0
+    return (bits.reshape(corpus.n, w, 32) << np.arange(32, dtype=np.uint64)).sum(2).astype(np.uint32)
+
+
 def dense_band_candidates(x: np.ndarray, n_bands=16, band_bits=12, seed=SEED_BASE + 104, max_bucket=None):
     g = _rng(seed).standard_normal((x.shape[1], n_bands * band_bits))
     proj = x.astype(np.float64) @ g
     return band_candidates(proj, n_bands, band_bits, max_bucket)
 
 
-__all__ += ["sparse_band_candidates", "dense_band_candidates"]
+__all__ += ["sparse_band_candidates", "sparse_band_bits", "dense_band_candidates"]
 
 
 # ----------------------------------------------------------------------------

@@ -107,3 +107,22 @@ def test_band_candidates_structure():
     s = set(pairs.tolist())
     hit = [min(d, int(corpus.dup_source[d])) * corpus.n + max(d, int(corpus.dup_source[d])) in s for d in dups]
     assert np.mean(hit) > 0.8
+
+
+def test_sparse_band_bits_match_the_banded_candidates():
+    """The packed band bits hold the signs the candidate generator bands:
+    every pair listed shares a band key under them, and every pair sharing a
+    key is listed (brute force over all pairs of a small corpus)."""
+    corpus = G.tfidf_corpus(n_docs=300, dim=1 << 14, mean_nnz=30, dup_frac=0.1, seed=G.SEED_BASE + 43)
+    nb, bb = 6, 5
+    words = G.sparse_band_bits(corpus, n_bands=nb, band_bits=bb, seed=G.SEED_BASE + 44)
+    assert words.shape == (corpus.n, 1) and words.dtype == np.uint32
+    bits = (words[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1
+    bits = bits.reshape(corpus.n, 32).astype(bool)
+    assert not bits[:, nb * bb:].any()                  # padding past the last band is zero
+    keys = np.stack([(bits[:, b * bb:(b + 1) * bb] << np.arange(bb)).sum(1) for b in range(nb)], 1)
+    i, j = np.triu_indices(corpus.n, 1)
+    share = (keys[i] == keys[j]).any(1)
+    want = set((i[share].astype(np.int64) * corpus.n + j[share]).tolist())
+    x, y = G.sparse_band_candidates(corpus, n_bands=nb, band_bits=bb, seed=G.SEED_BASE + 44)
+    assert set((x.astype(np.int64) * corpus.n + y).tolist()) == want and len(x) == len(want)
