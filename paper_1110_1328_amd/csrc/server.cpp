@@ -209,23 +209,32 @@ int launch_iteration(blsh_server *S, Iteration &it, std::vector<Request *> &act)
 // hold a bad id; which request it belongs to is read from this iteration's own
 // codes.  It is cleared only when no other iteration is in flight, so an error
 // raised by the overlapping iteration is seen when that one finishes.
+// Device-to-host read on the server's second stream (non-blocking), so that
+// the scheduler never waits on work of the null stream.
+int read_back(blsh_server *S, void *dst, const void *src, size_t bytes) {
+  if (hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, S->post) != hipSuccess ||
+      hipStreamSynchronize(S->post) != hipSuccess)
+    return BLSH_EDEVICE;
+  return BLSH_OK;
+}
+
 int check_device_ids(blsh_server *S, Iteration &it, bool other_busy) {
   bool dev = false;
   for (const Slice &sl : it.slices) dev |= sl.r->d_src != nullptr;
   if (!dev) return BLSH_OK;
   int32_t st = 0;
-  if (hipMemcpy(&st, S->ctx->d_status, 4, hipMemcpyDeviceToHost) != hipSuccess) return BLSH_EDEVICE;
+  if (read_back(S, &st, S->ctx->d_status, 4)) return BLSH_EDEVICE;
   if (st == BLSH_OK) return BLSH_OK;
   std::vector<uint8_t> code;
   for (const Slice &sl : it.slices) {
     if (!sl.r->d_src || sl.r->bad_id) continue;
     code.resize(size_t(sl.len));
-    if (hipMemcpy(code.data(), it.d_code + sl.r->arena_off + sl.begin, size_t(sl.len), hipMemcpyDeviceToHost) !=
-        hipSuccess)
-      return BLSH_EDEVICE;
+    if (read_back(S, code.data(), it.d_code + sl.r->arena_off + sl.begin, size_t(sl.len))) return BLSH_EDEVICE;
     sl.r->bad_id = std::find(code.begin(), code.end(), uint8_t(0xFF)) != code.end();
   }
-  if (!other_busy && hipMemset(S->ctx->d_status, 0, 4) != hipSuccess) return BLSH_EDEVICE;
+  if (!other_busy && (hipMemsetAsync(S->ctx->d_status, 0, 4, S->post) != hipSuccess ||
+                      hipStreamSynchronize(S->post) != hipSuccess))
+    return BLSH_EDEVICE;
   return BLSH_OK;
 }
 
@@ -235,7 +244,7 @@ int finish_iteration(blsh_server *S, Iteration &it, bool other_busy) {
   if (hipEventSynchronize(it.done) != hipSuccess) return BLSH_EDEVICE;
   if (int rc = check_device_ids(S, it, other_busy)) return rc;
   int64_t n = 0;
-  if (hipMemcpy(&n, it.d_n_acc, 8, hipMemcpyDeviceToHost) != hipSuccess) return BLSH_EDEVICE;
+  if (read_back(S, &n, it.d_n_acc, 8)) return BLSH_EDEVICE;
   if (n > it.acc_cap) return BLSH_ETRUNCATED;
   it.h_idx.resize(size_t(n));
   it.h_val.resize(size_t(n));
