@@ -26,7 +26,7 @@ turns each integral into a binomial lower tail, which is summed here in log
 space so that ratios of very small tails (m << n/2) neither underflow nor
 cancel.  B(a, b) cancels in every ratio.
 
-Readings of the paper taken here (each is listed in the design doc):
+Readings of the paper taken here:
   * Jaccard MAP is the Beta mode (m+alpha-1)/(n+alpha+beta-2), clamped to
     [0, 1]; the text derives the mode but the printed formula has -1 in the
     denominator.

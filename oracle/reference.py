@@ -10,7 +10,7 @@ pair exactly as the paper states them:
         prune   if Pr[S >= t | M(m,n)] < epsilon
         stop    if Pr[|S - S_hat| < delta | M(m,n)] >= 1 - gamma   (Algorithm 1 only)
 
-Readings where the paper is silent (listed in the design doc): the hash range of
+Readings where the paper is silent: the hash range of
 each step is [n, n+k) (the printed sum has k+1 terms); Algorithm 1 has no hash
 budget, so a pair still undecided after the last available hash is emitted
 with its estimate ("accepted at n_max"); Algorithm 2 checks pruning at

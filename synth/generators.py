@@ -1,8 +1,8 @@
 """Seeded workload generators (numpy only).
 
 Every generator is a pure function of its arguments and seed.  Shapes and
-distributions follow the workloads described in DESIGN.md ("Input recipe"),
-which stand in for the paper's datasets (Section 5, Table 1): binary sets
+distributions follow the benchmark workloads, which stand in for the paper's
+datasets (Section 5, Table 1): binary sets
 for Jaccard similarity, sparse tf-idf vectors and dense embeddings for
 cosine similarity, and LSH-banded candidate pairs (Section 2, candidate
 generation).  The random draws a hash family needs (minhash coefficients,
