@@ -438,9 +438,11 @@ int bayeslsh_server_submit(blsh_server *srv, uint32_t query, const uint32_t *can
  * candidate with an id >= n_obj is never accepted, the other candidates are
  * verified as usual, and the request finishes with status BLSH_EBADID (its
  * accepted list still holds the valid candidates' results).  A query id >=
- * n_obj is rejected here (BLSH_EINVAL); requests larger than the arena:
- * BLSH_ENOMEM.  Any pending status of `ctx` is cleared when the server is
- * created. */
+ * n_obj is rejected here (BLSH_EINVAL), and so is a cand_dev that is not
+ * device memory of the server's GPU holding n_cand ids (host, managed or
+ * another GPU's memory, or a range past the end of its allocation); requests
+ * larger than the arena: BLSH_ENOMEM.  Any pending status of `ctx` is cleared
+ * when the server is created. */
 int bayeslsh_server_submit_device(blsh_server *srv, uint32_t query, const uint32_t *cand_dev, int64_t n_cand,
                                   double t, int64_t *request_id);
 /* BLSH_OK (finished; *out filled), BLSH_EAGAIN (pending) or an error. */

@@ -453,6 +453,22 @@ int bayeslsh_server_submit_device(blsh_server *srv, uint32_t query, const uint32
   if (!(t > 0 && t < 1)) return fail(BLSH_EINVAL, "t must be in (0,1)");
   if (n_cand > srv->arena.cap) return fail(BLSH_ENOMEM, "request of %lld candidates exceeds the memory budget", (long long)n_cand);
   if (int64_t(query) >= srv->index.n_obj) return fail(BLSH_EINVAL, "query id %u >= n_obj", query);
+  if (n_cand > 0) {
+    // the admission kernel reads cand_dev directly: it must be device memory of
+    // the server's GPU that holds all n_cand ids (anything else would fault there)
+    hipPointerAttribute_t at{};
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    void *p = const_cast<uint32_t *>(cand_dev);
+    const bool ok = hipPointerGetAttributes(&at, p) == hipSuccess && at.type == hipMemoryTypeDevice &&
+                    at.device == srv->ctx->device && hipMemGetAddressRange(&base, &size, p) == hipSuccess &&
+                    uintptr_t(p) + uint64_t(n_cand) * 4 <= uintptr_t(base) + size;
+    if (!ok) {
+      (void)hipGetLastError();   // a failed query leaves the runtime's last error set
+      return fail(BLSH_EINVAL, "cand_dev is not device memory of the server's GPU holding %lld ids",
+                  (long long)n_cand);
+    }
+  }
   auto r = std::make_unique<Request>();
   r->query = query;
   r->t = t;

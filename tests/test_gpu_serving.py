@@ -180,3 +180,33 @@ def test_serving_device_submit_many_per_admission(index):
     finally:
         srv.close()
         ctx.close()
+
+
+def test_serving_device_submit_rejects_non_device_ranges(index):
+    """bayeslsh_server_submit_device checks its pointer on the host: host
+    memory, and a device range past the end of its allocation, are refused
+    (BLSH_EINVAL) before anything reads them; a valid request still runs."""
+    import ctypes as C
+    from paper_1110_1328_amd import api as A
+    print("serving device submit: pointer checks", flush=True)
+    ctx = P.bayeslsh_create(0)
+    S = sigs_tensor(index, P.COSINE, P.WORD_MAJOR)
+    srv = P.Server(ctx, S, mem_budget_bytes=64 << 20, max_active=4, k=32, max_batch_candidates=1 << 16)
+    try:
+        lib = A._lib()
+        rid = C.c_int64(-1)
+        host = np.arange(64, dtype=np.uint32)
+        rc = lib.bayeslsh_server_submit_device(srv.handle, 1, host.ctypes.data_as(C.c_void_p), 64, 0.8, C.byref(rid))
+        assert rc == -1 and rid.value == -1
+        small = up(np.arange(16, dtype=np.uint32))     # a 64-byte tensor: its allocation is far below 32 MB
+        rc = lib.bayeslsh_server_submit_device(srv.handle, 1, C.c_void_p(small.data_ptr()), 8 << 20, 0.8,
+                                               C.byref(rid))
+        assert rc == -1 and rid.value == -1
+        q, c, t = make_requests(index.shape[0], 1, 9)[0]
+        res = srv.wait(srv.submit_device(q, up(c), t))
+        acc, _ = oracle_request(index, q, c, t)
+        assert res["status"] == 0
+        np.testing.assert_array_equal(res["acc_idx"], acc)
+    finally:
+        srv.close()
+        ctx.close()
