@@ -311,7 +311,7 @@ int bayeslsh_exact_similarity(blsh_ctx *ctx, const blsh_candidates *cand, const 
  * call waits for `stream`.  More pairs than capacity: the first `capacity` are
  * written and BLSH_ETRUNCATED is returned; order_tile other than 0 or 16
  * gives BLSH_EINVAL.  Uses the context workspace (about 8 * n_obj * (n_bands
- * + 6) bytes) and, with tiles, a context buffer of 16 bytes per tile of the
+ * + 6) bytes) and, with tiles, a context buffer of 48 bytes per tile of the
  * largest band. */
 int bayeslsh_band_candidates(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t n_bands, int32_t band_bits,
                              int32_t max_bucket, int32_t order_tile, uint32_t *x_out, uint32_t *y_out,

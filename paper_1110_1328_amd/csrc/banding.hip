@@ -173,6 +173,7 @@ struct TileArgs {
   const int64_t *toff;       // first tile of each bucket
   int64_t n_buckets, n_tiles;
   int64_t *tcnt;             // count pass: kept pairs per tile
+  uint64_t *tmask;           // count pass writes, emit pass reads: the tile's 4 keep ballots
   const int64_t *tcoff;      // emit pass: their exclusive prefix
   const int64_t *base;       // emit pass: output offset of this band
   uint32_t *x_out, *y_out;
@@ -180,7 +181,9 @@ struct TileArgs {
 };
 
 // One wave per tile: lane l holds the tile's pair positions 4l .. 4l + 3
-// (row-major), so lanes, then a lane's four slots, are in output order.
+// (row-major), so lanes, then a lane's four slots, are in output order.  The
+// count pass runs the earlier-band test and keeps its four ballots per tile;
+// the emit pass reads them back instead of testing again.
 template <bool EMIT>
 __global__ __launch_bounds__(kBandBlock) void k_band_tiles(TileArgs a) {
   const int lane = lane_id();
@@ -210,28 +213,44 @@ __global__ __launch_bounds__(kBandBlock) void k_band_tiles(TileArgs a) {
     const int64_t ar = ta * kTile + (4 * lane) / kTile;   // the lane's row (same for its 4 slots)
     bool keep[4];
     uint32_t xs = 0, ys[4] = {0, 0, 0, 0};
+    uint64_t mask[4];
+    if constexpr (!EMIT) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t cr = tb * kTile + (4 * lane + i) % kTile;
-      keep[i] = ar < cr && cr < len;
-      if (keep[i]) {
-        xs = a.sids[p0 + ar];
-        ys[i] = a.sids[p0 + cr];
-        const uint32_t *kx = a.keys_om + size_t(xs) * a.n_bands;
-        const uint32_t *ky = a.keys_om + size_t(ys[i]) * a.n_bands;
-        for (int j = 0; j < a.band; ++j)   // collided in an earlier band: emitted there
-          if (kx[j] == ky[j]) { keep[i] = false; break; }
+      for (int i = 0; i < 4; ++i) {
+        const int64_t cr = tb * kTile + (4 * lane + i) % kTile;
+        keep[i] = ar < cr && cr < len;
+        if (keep[i]) {
+          xs = a.sids[p0 + ar];
+          ys[i] = a.sids[p0 + cr];
+          const uint32_t *kx = a.keys_om + size_t(xs) * a.n_bands;
+          const uint32_t *ky = a.keys_om + size_t(ys[i]) * a.n_bands;
+          for (int j = 0; j < a.band; ++j)   // collided in an earlier band: emitted there
+            if (kx[j] == ky[j]) { keep[i] = false; break; }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mask[i] = __ballot(keep[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        mask[i] = a.tmask[4 * t + i];
+        keep[i] = (mask[i] >> lane) & 1u;
+        if (keep[i]) {
+          const int64_t cr = tb * kTile + (4 * lane + i) % kTile;
+          xs = a.sids[p0 + ar];
+          ys[i] = a.sids[p0 + cr];
+        }
       }
     }
-    uint64_t mask[4];
-    int64_t total = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      mask[i] = __ballot(keep[i]);
-      total += __popcll(mask[i]);
-    }
     if (!EMIT) {
-      if (lane == 0) a.tcnt[t] = total;
+      int64_t total = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) total += __popcll(mask[i]);
+      if (lane == 0) {
+        a.tcnt[t] = total;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a.tmask[4 * t + i] = mask[i];
+      }
     } else {
       int64_t rank = 0;
 #pragma unroll
@@ -352,11 +371,12 @@ int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t r
       if (rocprim::exclusive_scan(nullptr, tile_tmp, (const int64_t *)nullptr, (int64_t *)nullptr, int64_t(0),
                                   size_t(n_tiles), rocprim::plus<int64_t>(), s) != hipSuccess)
         return fail(BLSH_EDEVICE, "banding: temporary storage query failed");
-      const size_t tb = align256(size_t(n_tiles) * 8);
-      if ((rc = ensure_tile_buf(ctx, 2 * tb + tile_tmp))) return rc;
+      const size_t tb = align256(size_t(n_tiles) * 8), mb = align256(size_t(n_tiles) * 32);
+      if ((rc = ensure_tile_buf(ctx, 2 * tb + mb + tile_tmp))) return rc;
       int64_t *tcnt = static_cast<int64_t *>(ctx->tile_buf);
       int64_t *tcoff = reinterpret_cast<int64_t *>(static_cast<char *>(ctx->tile_buf) + tb);
-      void *ttmp = static_cast<char *>(ctx->tile_buf) + 2 * tb;
+      uint64_t *tmask = reinterpret_cast<uint64_t *>(static_cast<char *>(ctx->tile_buf) + 2 * tb);
+      void *ttmp = static_cast<char *>(ctx->tile_buf) + 2 * tb + mb;
       TileArgs ta{};
       ta.sids = sids;
       ta.keys_om = keys_om;
@@ -368,6 +388,7 @@ int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t r
       ta.n_buckets = n_buckets;
       ta.n_tiles = n_tiles;
       ta.tcnt = tcnt;
+      ta.tmask = tmask;
       ta.tcoff = tcoff;
       ta.base = base;
       ta.x_out = x_out;
