@@ -134,6 +134,45 @@ def test_verify_pairs_bit_exact(ctx, measure, k):
     assert len(set(want["decision"].tolist())) == 3
 
 
+# (n_hashes, k, t, epsilon, delta, gamma); t = None: near the low end for the measure
+DEGENERATE = [
+    (32, 32, 0.7, 0.03, 0.05, 0.03),       # a single level: n_max = k
+    (64, 64, 0.8, 0.03, 0.05, 0.03),       # a single level at k = 64
+    (256, 32, 0.99, 0.03, 0.05, 0.03),     # threshold near 1
+    (256, 32, None, 0.03, 0.05, 0.03),     # threshold near the low end
+    (256, 16, 0.7, 1e-4, 0.05, 1e-4),      # tiny epsilon and gamma
+    (256, 64, 0.7, 0.5, 0.2, 0.5),         # large epsilon, delta and gamma
+]
+
+
+@pytest.mark.parametrize("measure", [P.JACCARD, P.COSINE])
+@pytest.mark.parametrize("case", range(len(DEGENERATE)))
+def test_degenerate_parameters(ctx, measure, case):
+    """A single level, thresholds near the ends of the range and extreme
+    epsilon / delta / gamma: decisions, levels and m bit-exact against the
+    oracle, accepted estimates within 1e-6."""
+    n_hashes, k, t, eps, delta, gamma = DEGENERATE[case]
+    if t is None:
+        t = 0.05 if measure == P.JACCARD else 0.52
+    npairs = 3000 + 7
+    _flush("degenerate measure=%d case=%d" % (measure, case))
+    sig = _calib_pairs(measure, npairs, n_hashes, 300 + case + 10 * measure)
+    rng = np.random.default_rng(8 + case)
+    x = np.arange(0, 2 * npairs, 2, dtype=np.uint32)
+    y = x + 1
+    sw = rng.random(npairs) < 0.3
+    y[sw] = rng.integers(0, 2 * npairs, sw.sum()).astype(np.uint32)
+    y[:3] = x[:3]
+    want = R.verify(x, y, measure, sig, k, n_hashes // k, t, eps, delta, gamma)
+    layouts = [P.OBJECT_MAJOR] if measure == P.JACCARD else [P.WORD_MAJOR, P.OBJECT_MAJOR]
+    for layout in layouts:
+        res = P.make_result(npairs, npairs, m_debug=True)
+        P.bayeslsh_verify(ctx, P.pairs(up(x), up(y)), sigs_tensor(sig, measure, layout), t, eps, delta, gamma,
+                          (1.0, 1.0), k, res)
+        P.bayeslsh_sync(ctx)
+        assert_same_as_oracle(decode_result(res, npairs), want)
+
+
 @pytest.mark.parametrize("k", [16, 32, 64])
 @pytest.mark.parametrize("lite", [False, True])
 def test_layouts_and_candidate_orders(ctx, k, lite):
