@@ -221,3 +221,20 @@ def test_exhaustive_batched_equals_batched(ctx, workload, k):
     P.bayeslsh_exhaustive_batched(ctx, lists, cand, Sj, Sc, EPS, DELTA, GAMMA, (1, 1), k, res)
     P.bayeslsh_sync(ctx)
     check(decode_result(res, n), want)
+
+
+def test_batched_extreme_thresholds(ctx, workload):
+    """Per-list thresholds near both ends of each measure's range (and one in
+    the middle) in one batch: every list equals the oracle at its own t."""
+    print("batched extreme thresholds", flush=True)
+    rng = np.random.default_rng(77)
+    w = dict(workload)
+    low = np.where(w["meas"] == 0, 0.05, 0.52)
+    pick = rng.integers(0, 3, len(w["lens"]))
+    w["ts"] = np.where(pick == 0, low, np.where(pick == 1, 0.99, 0.7))
+    want = oracle_batched(w, 32)
+    for layout in (P.OBJECT_MAJOR, PREFIX):
+        kk, got = run_batched(ctx, w, 32, layout=layout)
+        assert kk == (32, 32)
+        check(got, want)
+    assert len(set(want["decision"].tolist())) == 3
