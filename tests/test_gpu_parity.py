@@ -335,6 +335,30 @@ def test_lite_cosine_sparse(ctx):
     assert got["n_accepted"] > 10 and (want["decision"] == R.DEC_LITE).sum() > got["n_accepted"]
 
 
+@pytest.mark.parametrize("h,k", [(32, 32), (256, 32), (128, 64), (64, 16)])
+def test_lite_hash_budgets(ctx, h, k):
+    """Lite with one level before the exact similarity (h = k), with every
+    stored hash (h = n_max) and other (h, k) pairs, on word-major slabs and on
+    object-major rows (the 128-bit prefix path when h >= 128)."""
+    _flush("lite budgets h=%d k=%d" % (h, k))
+    corpus = G.tfidf_corpus(n_docs=2000, dim=1 << 16, mean_nnz=50, dup_frac=0.1, seed=G.SEED_BASE + 45)
+    x, y = G.sparse_band_candidates(corpus, n_bands=8, band_bits=5, seed=G.SEED_BASE + 46)
+    n = len(x)
+    proj = R.srp_sparse_projections(corpus.offsets, corpus.indices, corpus.values, 256, 98,
+                                    np.arange(corpus.n, dtype=np.int64))
+    sig = R.bits_from_projections(proj)
+    want = R.verify(x, y, P.COSINE, sig, k, h // k, T, EPS, 0, 0, lite=True)
+    want = R.lite_finish(want, lambda a, b: R.exact_cosine_csr(corpus.offsets, corpus.indices, corpus.values, a, b),
+                         x, y, T)
+    vec = csr_device(corpus)
+    for layout in (P.WORD_MAJOR, P.OBJECT_MAJOR):
+        res = P.make_result(n, n, m_debug=True)
+        P.bayeslsh_lite_verify(ctx, P.pairs(up(x), up(y)), sigs_tensor(sig, P.COSINE, layout), vec,
+                               T, EPS, (1, 1), h, k, res)
+        P.bayeslsh_sync(ctx)
+        assert_same_as_oracle(decode_result(res, n), want, lite_exact=want["exact"])
+
+
 def test_lite_jaccard_sets_and_dense_cosine(ctx):
     _flush("lite jaccard sets + dense cosine")
     sets = G.jaccard_sets(n_sets=600, vocab=20000, n_groups=40, seed=G.SEED_BASE + 51)
