@@ -271,6 +271,100 @@ __global__ __launch_bounds__(kBandBlock) void k_band_tiles(TileArgs a) {
   }
 }
 
+// The count pass for key rows whose length is a multiple of 4, up to band 16:
+// each wave step takes two tiles, decodes both and issues both tiles' id and
+// key loads before using any (a tile alone is a chain of dependent loads:
+// tile offsets, member ids, key rows), comparing earlier-band keys 16 bytes
+// at a time.  Same counts and ballots as k_band_tiles<false>.
+struct TileAt {
+  int64_t len, p0, ar, tb;
+  bool ok;
+};
+
+__device__ inline TileAt tile_at(const TileArgs &a, int64_t t, int lane) {
+  TileAt r{0, 0, 0, 0, t < a.n_tiles};
+  if (!r.ok) return r;
+  int64_t lo = 0, hi = a.n_buckets - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (a.toff[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int64_t lt = t - a.toff[lo];
+  r.len = a.blen[lo];
+  const int64_t nt = (r.len + kTile - 1) / kTile;
+  auto S = [nt](int64_t q) { return q * nt - q * (q - 1) / 2; };
+  const double q2 = double(2 * nt + 1);
+  int64_t ta = int64_t((q2 - sqrt(max(0.0, q2 * q2 - 8.0 * double(lt)))) / 2.0);
+  ta = max<int64_t>(0, min(ta, nt - 1));
+  while (ta > 0 && S(ta) > lt) --ta;
+  while (ta + 1 < nt && S(ta + 1) <= lt) ++ta;
+  r.tb = ta + (lt - S(ta));
+  r.p0 = a.bpos[lo];
+  r.ar = ta * kTile + (4 * lane) / kTile;
+  return r;
+}
+
+__global__ __launch_bounds__(kBandBlock) void k_band_count_pairs(TileArgs a) {
+  const int lane = lane_id();
+  const int64_t waves = int64_t(gridDim.x) * (kBandBlock / kWave);
+  const int64_t w0 = int64_t(blockIdx.x) * (kBandBlock / kWave) +
+                     int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
+  const int nq = (a.band + 3) >> 2;
+  for (int64_t t0 = 2 * w0; t0 < a.n_tiles; t0 += 2 * waves) {
+    TileAt T[2] = {tile_at(a, t0, lane), tile_at(a, t0 + 1, lane)};
+    bool keep[2][4];
+    uint32_t xs[2] = {0, 0}, ys[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (T[u].ok && T[u].ar < T[u].len) xs[u] = a.sids[T[u].p0 + T[u].ar];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t cr = T[u].tb * kTile + (4 * lane + i) % kTile;
+        keep[u][i] = T[u].ok && T[u].ar < cr && cr < T[u].len;
+        ys[u][i] = keep[u][i] ? a.sids[T[u].p0 + cr] : 0u;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < nq) {
+        uint4 kx[2], ky[2][4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          kx[u] = reinterpret_cast<const uint4 *>(a.keys_om + size_t(xs[u]) * a.n_bands)[q];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            ky[u][i] = reinterpret_cast<const uint4 *>(a.keys_om + size_t(ys[u][i]) * a.n_bands)[q];
+        }
+        const int j = 4 * q;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint4 x = kx[u], y = ky[u][i];
+            if ((x.x == y.x && j < a.band) || (x.y == y.y && j + 1 < a.band) || (x.z == y.z && j + 2 < a.band) ||
+                (x.w == y.w && j + 3 < a.band))
+              keep[u][i] = false;
+          }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      uint64_t mask[4];
+      int64_t total = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        mask[i] = __ballot(keep[u][i]);
+        total += __popcll(mask[i]);
+      }
+      if (T[u].ok && lane == 0) {
+        a.tcnt[t0 + u] = total;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a.tmask[4 * (t0 + u) + i] = mask[i];
+      }
+    }
+  }
+}
+
 // base += (pairs of this band) = row_off[n-1] + row_count[n-1]
 __global__ void k_band_advance(int64_t *base, const int64_t *row_off, const int64_t *row_count, int64_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && n > 0) *base += row_off[n - 1] + row_count[n - 1];
@@ -396,7 +490,10 @@ int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t r
       ta.capacity = capacity;
       const unsigned tile_blocks =
           unsigned(std::min<int64_t>(int64_t(ctx->n_cu) * 8, (n_tiles + kBandBlock / kWave - 1) / (kBandBlock / kWave)));
-      hipLaunchKernelGGL(k_band_tiles<false>, dim3(tile_blocks), dim3(kBandBlock), 0, s, ta);
+      if ((n_bands & 3) == 0 && j <= 16)
+        hipLaunchKernelGGL(k_band_count_pairs, dim3(tile_blocks), dim3(kBandBlock), 0, s, ta);
+      else
+        hipLaunchKernelGGL(k_band_tiles<false>, dim3(tile_blocks), dim3(kBandBlock), 0, s, ta);
       size_t t4 = tile_tmp;
       if (rocprim::exclusive_scan(ttmp, t4, tcnt, tcoff, int64_t(0), size_t(n_tiles), rocprim::plus<int64_t>(), s) !=
           hipSuccess)
