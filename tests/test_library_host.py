@@ -116,3 +116,15 @@ def test_fit_prior_matches_oracle(lib):
         assert a == pytest.approx(wa, rel=1e-12) and b == pytest.approx(wb, rel=1e-12)
     with pytest.raises(BayesLSHError):
         P.bayeslsh_fit_prior([0.3, 1.5])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits (status 2) with a
+    message before anything touches a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
