@@ -335,7 +335,7 @@ def run_serving(args, torch, P):
     """Poisson arrivals of query objects against the dense cosine index
     (candidate counts 10^U(3,6), t = 0.8): first all at once (saturated rate),
     then at rho x that rate for rho in {0.5, 0.8, 0.95}; latency = arrival to
-    host-visible result.  Then the same requests submitted from device memory
+    host-visible result; then all at once from 4 client threads.  Then the same requests submitted from device memory
     (candidate ids resident on the GPU, no host copy of them): saturated and at
     rho = 0.95 of that rate.  Rates are given twice: over the client's elapsed
     time (which includes the Python client's submission and per-request result
@@ -380,6 +380,30 @@ def run_serving(args, torch, P):
         run.server_s = max(o["done"] for o in out) - min(o["submit"] for o in out)
         return el, lat, out
 
+    def run_clients(n_clients):
+        """All requests at once from n_clients threads (request i from thread
+        i mod n_clients); each submits its share, then waits for it."""
+        import threading
+        out = [None] * nq
+        t0 = time.perf_counter()
+
+        def client(c):
+            mine = range(c, nq, n_clients)
+            ids = [srv.submit(int(q[i]), cand[off[i]:off[i + 1]], 0.8) for i in mine]
+            for i, r in zip(mine, ids):
+                out[i] = srv.wait(r)
+                srv.release(r)
+
+        th = [threading.Thread(target=client, args=(c,)) for c in range(n_clients)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        el = time.perf_counter() - t0
+        run.submit_s = None
+        run.server_s = max(o["done"] for o in out) - min(o["submit"] for o in out)
+        return el, np.array([o["done"] - o["submit"] for o in out]), out
+
     def stats(el, lat, out, ref):
         d = {"queries_per_s": nq / el, "pairs_per_s": total / el, "p50_ms": float(np.percentile(lat, 50) * 1e3),
              "p99_ms": float(np.percentile(lat, 99) * 1e3), "client_submit_s": run.submit_s, "elapsed_s": el,
@@ -401,6 +425,10 @@ def run_serving(args, torch, P):
             key = "rho_%.2f" % rho
             res[key] = stats(*run(gaps), out0)
             log("rho %.2f: p50 %.2f ms p99 %.2f ms" % (rho, res[key]["p50_ms"], res[key]["p99_ms"]))
+        # the same requests from 4 client threads at once (ids in host memory)
+        res["saturated_4_clients"] = stats(*run_clients(4), out0)
+        log("4 clients, saturated: %.0f q/s, %.3g pairs/s" % (res["saturated_4_clients"]["queries_per_s"],
+                                                             res["saturated_4_clients"]["pairs_per_s"]))
     # the same requests with candidate ids already resident on the device
     dcand = up(torch, cand)
     run(None)

@@ -428,14 +428,15 @@ int bayeslsh_server_submit(blsh_server *srv, uint32_t query, const uint32_t *can
   if (!(t > 0 && t < 1)) return fail(BLSH_EINVAL, "t must be in (0,1)");
   if (n_cand > srv->arena.cap) return fail(BLSH_ENOMEM, "request of %lld candidates exceeds the memory budget", (long long)n_cand);
   if (int64_t(query) >= srv->index.n_obj) return fail(BLSH_EINVAL, "query id %u >= n_obj", query);
-  for (int64_t i = 0; i < n_cand; ++i)
-    if (int64_t(cand_host[i]) >= srv->index.n_obj)
-      return fail(BLSH_EINVAL, "candidate %lld: id %u >= n_obj", (long long)i, cand_host[i]);
   auto r = std::make_unique<Request>();
   r->query = query;
   r->t = t;
   r->n = n_cand;
+  // copy first, then check the copy while it is still in cache (one pass over the caller's memory)
   r->cand.assign(cand_host, cand_host + n_cand);
+  for (int64_t i = 0; i < n_cand; ++i)
+    if (int64_t(r->cand[size_t(i)]) >= srv->index.n_obj)
+      return fail(BLSH_EINVAL, "candidate %lld: id %u >= n_obj", (long long)i, r->cand[size_t(i)]);
   std::lock_guard<std::mutex> lk(srv->mu);
   if (srv->fatal != BLSH_OK) return fail(srv->fatal, "server failed earlier");
   r->id = srv->next_id++;
