@@ -180,6 +180,38 @@ struct TileArgs {
   int64_t capacity;
 };
 
+struct TileAt {
+  int64_t len, p0, ar, tb;
+  bool ok;
+};
+
+// Tile t of the band: its bucket (the last b with toff[b] <= t), the bucket's
+// length and first sorted position, the tile's column index tb and the
+// lane's row ar (tile (ta, tb), tb >= ta: rows before ta hold
+// S(ta) = ta nt - ta (ta - 1) / 2 tiles).  ok = false past the last tile.
+__device__ inline TileAt tile_at(const TileArgs &a, int64_t t, int lane) {
+  TileAt r{0, 0, 0, 0, t < a.n_tiles};
+  if (!r.ok) return r;
+  int64_t lo = 0, hi = a.n_buckets - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (a.toff[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int64_t lt = t - a.toff[lo];
+  r.len = a.blen[lo];
+  const int64_t nt = (r.len + kTile - 1) / kTile;
+  auto S = [nt](int64_t q) { return q * nt - q * (q - 1) / 2; };
+  const double q2 = double(2 * nt + 1);
+  int64_t ta = int64_t((q2 - sqrt(max(0.0, q2 * q2 - 8.0 * double(lt)))) / 2.0);
+  ta = max<int64_t>(0, min(ta, nt - 1));
+  while (ta > 0 && S(ta) > lt) --ta;
+  while (ta + 1 < nt && S(ta + 1) <= lt) ++ta;
+  r.tb = ta + (lt - S(ta));
+  r.p0 = a.bpos[lo];
+  r.ar = ta * kTile + (4 * lane) / kTile;
+  return r;
+}
+
 // One wave per tile: lane l holds the tile's pair positions 4l .. 4l + 3
 // (row-major), so lanes, then a lane's four slots, are in output order.  The
 // count pass runs the earlier-band test and keeps its four ballots per tile;
@@ -192,25 +224,9 @@ __global__ __launch_bounds__(kBandBlock) void k_band_tiles(TileArgs a) {
                      int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
   const int64_t out0 = EMIT ? *a.base : 0;
   for (int64_t t = w0; t < a.n_tiles; t += waves) {
-    // bucket: the last b with toff[b] <= t
-    int64_t lo = 0, hi = a.n_buckets - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) / 2;
-      if (a.toff[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    const int64_t lt = t - a.toff[lo];
-    const int64_t len = a.blen[lo];
-    const int64_t nt = (len + kTile - 1) / kTile;
-    // tile (ta, tb), tb >= ta: rows before ta hold S(ta) = ta nt - ta (ta - 1) / 2 tiles
-    auto S = [nt](int64_t r) { return r * nt - r * (r - 1) / 2; };
-    const double q2 = double(2 * nt + 1);
-    int64_t ta = int64_t((q2 - sqrt(max(0.0, q2 * q2 - 8.0 * double(lt)))) / 2.0);
-    ta = max<int64_t>(0, min(ta, nt - 1));
-    while (ta > 0 && S(ta) > lt) --ta;
-    while (ta + 1 < nt && S(ta + 1) <= lt) ++ta;
-    const int64_t tb = ta + (lt - S(ta));
-    const int64_t p0 = a.bpos[lo];
-    const int64_t ar = ta * kTile + (4 * lane) / kTile;   // the lane's row (same for its 4 slots)
+    const TileAt T = tile_at(a, t, lane);
+    const int64_t len = T.len, tb = T.tb, p0 = T.p0;
+    const int64_t ar = T.ar;   // the lane's row (same for its 4 slots)
     bool keep[4];
     uint32_t xs = 0, ys[4] = {0, 0, 0, 0};
     uint64_t mask[4];
@@ -276,34 +292,6 @@ __global__ __launch_bounds__(kBandBlock) void k_band_tiles(TileArgs a) {
 // key loads before using any (a tile alone is a chain of dependent loads:
 // tile offsets, member ids, key rows), comparing earlier-band keys 16 bytes
 // at a time.  Same counts and ballots as k_band_tiles<false>.
-struct TileAt {
-  int64_t len, p0, ar, tb;
-  bool ok;
-};
-
-__device__ inline TileAt tile_at(const TileArgs &a, int64_t t, int lane) {
-  TileAt r{0, 0, 0, 0, t < a.n_tiles};
-  if (!r.ok) return r;
-  int64_t lo = 0, hi = a.n_buckets - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) / 2;
-    if (a.toff[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  const int64_t lt = t - a.toff[lo];
-  r.len = a.blen[lo];
-  const int64_t nt = (r.len + kTile - 1) / kTile;
-  auto S = [nt](int64_t q) { return q * nt - q * (q - 1) / 2; };
-  const double q2 = double(2 * nt + 1);
-  int64_t ta = int64_t((q2 - sqrt(max(0.0, q2 * q2 - 8.0 * double(lt)))) / 2.0);
-  ta = max<int64_t>(0, min(ta, nt - 1));
-  while (ta > 0 && S(ta) > lt) --ta;
-  while (ta + 1 < nt && S(ta + 1) <= lt) ++ta;
-  r.tb = ta + (lt - S(ta));
-  r.p0 = a.bpos[lo];
-  r.ar = ta * kTile + (4 * lane) / kTile;
-  return r;
-}
-
 __global__ __launch_bounds__(kBandBlock) void k_band_count_pairs(TileArgs a) {
   const int lane = lane_id();
   const int64_t waves = int64_t(gridDim.x) * (kBandBlock / kWave);
