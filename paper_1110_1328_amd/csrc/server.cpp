@@ -203,12 +203,6 @@ int launch_iteration(blsh_server *S, Iteration &it, std::vector<Request *> &act)
   return BLSH_OK;
 }
 
-// Device-submitted ids are checked by the kernels only: a bad id gets code
-// 0xFF and raises the context's status word (first error wins).  The word is
-// shared by both in-flight iterations, so it only says that some iteration may
-// hold a bad id; which request it belongs to is read from this iteration's own
-// codes.  It is cleared only when no other iteration is in flight, so an error
-// raised by the overlapping iteration is seen when that one finishes.
 // Device-to-host read on the server's second stream (non-blocking), so that
 // the scheduler never waits on work of the null stream.
 int read_back(blsh_server *S, void *dst, const void *src, size_t bytes) {
@@ -218,6 +212,13 @@ int read_back(blsh_server *S, void *dst, const void *src, size_t bytes) {
   return BLSH_OK;
 }
 
+// Device-submitted ids are checked by the kernels only: a bad id gets code
+// 0xFF (no Algorithm 1 code reaches it: decisions 0-2 use at most 0xBF) and
+// raises the context's status word (first error wins).  The word is shared by
+// both in-flight iterations, so it only says that some iteration may hold a
+// bad id; which request it belongs to is read from this iteration's own
+// codes.  It is cleared only when no other iteration is in flight, so an error
+// raised by the overlapping iteration is seen when that one finishes.
 int check_device_ids(blsh_server *S, Iteration &it, bool other_busy) {
   bool dev = false;
   for (const Slice &sl : it.slices) dev |= sl.r->d_src != nullptr;
