@@ -76,10 +76,13 @@ __device__ inline void srp_gauss4(uint32_t term, uint32_t q, uint32_t k0, uint32
   const double u0 = (double(w.x) + 0.5) / two32, u1 = (double(w.y) + 0.5) / two32;
   const double u2 = (double(w.z) + 0.5) / two32, u3 = (double(w.w) + 0.5) / two32;
   const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
-  g[0] = double(float(r0 * cos(two_pi * u1)));
-  g[1] = double(float(r0 * sin(two_pi * u1)));
-  g[2] = double(float(r1 * cos(two_pi * u3)));
-  g[3] = double(float(r1 * sin(two_pi * u3)));
+  double s1, c1, s3, c3;   // one argument reduction for each sine-cosine pair
+  sincos(two_pi * u1, &s1, &c1);
+  sincos(two_pi * u3, &s3, &c3);
+  g[0] = double(float(r0 * c1));
+  g[1] = double(float(r0 * s1));
+  g[2] = double(float(r1 * c3));
+  g[3] = double(float(r1 * s3));
 }
 
 template <int G>
