@@ -463,9 +463,10 @@ def run_sigs(args, torch, P):
     - dense SRP of the 1M x 256 mixture against 1024 Gaussian planes on the
       FP32 matrix cores: 2 d n_bits flops per row, against the 157.3 TFLOP/s
       dense FP32 MFMA peak;
-    - sparse SRP of the 100k-document tf-idf corpus at 2048 bits, plane entries
-      drawn on the fly (Philox-4x32-10 + Box-Muller, FP64 accumulation):
-      n_bits Gaussians per nonzero;
+    - sparse SRP of the 100k-document tf-idf corpus at 2048 bits (plane
+      entries from Philox-4x32-10 + Box-Muller, drawn once per term into a
+      table since terms repeat; FP64 accumulation): n_bits entries applied
+      per nonzero;
     - 256 minhashes of the 1M planted-group sets: one multiply-mod and min per
       (element, hash)."""
     from synth import generators as G
@@ -521,7 +522,8 @@ def run_sigs(args, torch, P):
             "unit": "TFLOP/s", "n_gpus": 1, "ms_per_step": dense_ms, "higher_is_better": True, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "signature generation: dense SRP 1M x 256 fp32 rows x 1024 planes; sparse SRP "
-                                   "100k tf-idf documents x 2048 bits (planes on the fly); 256 minhashes of 1M sets"},
+                                   "100k tf-idf documents x 2048 bits (plane entries drawn once per term); 256 "
+                                   "minhashes of 1M sets"},
             "roofline": {"bound": "mfma", "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s",
                          "frac": tflops / 157.3, "traffic": None, "kernel": "k_srp_dense_mfma<256>",
                          "flops_per_launch": flops},

@@ -258,7 +258,12 @@ int bayeslsh_minhash_sigs(blsh_ctx *ctx, const blsh_vectors *sets, const uint32_
  *     g(term, h) = float(z), z from Box-Muller in FP64 on the Philox-4x32-10
  *     words of counter (term, h/4, 0, 0) and key (seed lo32, seed hi32),
  *     u_i = (w_i + 0.5)/2^32, (z0,z1) = BoxMuller(u0,u1), (z2,z3) = BoxMuller(u2,u3),
- *     entry = z_{h mod 4}; projections accumulated in FP64.
+ *     entry = z_{h mod 4}; projections accumulated in FP64.  The call reads
+ *     the nonzero count (offsets[n_obj]) back, waiting for `stream`; when it
+ *     exceeds 2 * dim and dim * n_bits * 4 bytes fit in 16 GiB, the entries of
+ *     every term < dim are drawn once into a table in the context workspace
+ *     and read from there (the same values; an index >= dim, outside the
+ *     CSR contract, is drawn as it occurs rather than read past the table).
  * n_bits must be a multiple of 32 (DENSE: of 64). */
 int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *planes, int32_t n_bits,
                       uint64_t seed, blsh_layout layout, uint32_t *bits_out, void *stream);

@@ -15,7 +15,8 @@ int launch_zero(blsh_ctx *ctx, int64_t *p, hipStream_t s);
 int launch_minhash(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *elems, int64_t n_sets, const uint32_t *a,
                    const uint32_t *b, int n_hashes, uint32_t *out, hipStream_t s);
 int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *indices, const float *values,
-                      int64_t n_rows, int n_bits, uint64_t seed, bool word_major, uint32_t *out, hipStream_t s);
+                      int64_t n_rows, int64_t dim, int n_bits, uint64_t seed, bool word_major, uint32_t *out,
+                      hipStream_t s);
 int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim, const float *R, int n_bits,
                      bool word_major, uint32_t *out, hipStream_t s);
 
@@ -584,7 +585,7 @@ int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *plan
     if (!vecs->offsets || !vecs->indices || !vecs->values) return fail(BLSH_EINVAL, "CSR SRP needs offsets/indices/values");
     if (planes) return fail(BLSH_EINVAL, "CSR SRP generates its planes: pass planes = NULL");
     if (n_bits > 2048) return fail(BLSH_EINVAL, "CSR SRP: n_bits must be <= 2048");
-    return launch_srp_sparse(ctx, vecs->offsets, vecs->indices, vecs->values, vecs->n_obj, n_bits, seed,
+    return launch_srp_sparse(ctx, vecs->offsets, vecs->indices, vecs->values, vecs->n_obj, vecs->dim, n_bits, seed,
                              layout == BLSH_WORD_MAJOR, bits_out, s);
   }
   return fail(BLSH_EINVAL, "SRP needs DENSE or CSR vectors");

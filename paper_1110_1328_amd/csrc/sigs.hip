@@ -93,10 +93,29 @@ __device__ inline uint32_t group_or(uint32_t v) {
   return v;
 }
 
-template <int QPL>  // quads (4 hashes) per lane
+// Plane entries of every coordinate term < dim, float table[term][n_bits]: one
+// thread per (term, quad of hashes).  Used when each term occurs in several
+// rows, so that an entry is drawn once instead of once per occurrence.
+__global__ __launch_bounds__(256) void k_srp_table(int64_t dim, int32_t n_bits, uint32_t k0, uint32_t k1,
+                                                   float *table) {
+  const int Q = n_bits / 4;
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= dim * Q) return;
+  const int64_t term = i / Q;
+  const int q = int(i % Q);
+  double g[4];
+  srp_gauss4(uint32_t(term), uint32_t(q), k0, k1, g);
+  *reinterpret_cast<float4 *>(table + size_t(term) * n_bits + 4 * q) =
+      make_float4(float(g[0]), float(g[1]), float(g[2]), float(g[3]));
+}
+
+// TABLE: entries of terms < dim come from the table (the same values the
+// generator gives, since every entry is rounded to fp32), others are drawn.
+template <int QPL, bool TABLE>  // quads (4 hashes) per lane
 __global__ __launch_bounds__(256) void k_srp_sparse(const int64_t *offsets, const uint32_t *indices,
                                                     const float *values, int64_t n_rows, int32_t n_bits,
-                                                    uint32_t k0, uint32_t k1, int32_t word_major, uint32_t *out) {
+                                                    uint32_t k0, uint32_t k1, int32_t word_major, uint32_t *out,
+                                                    const float *table, int64_t dim) {
   const int lane = lane_id();
   const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (row >= n_rows) return;  // wave-uniform
@@ -115,7 +134,12 @@ __global__ __launch_bounds__(256) void k_srp_sparse(const int64_t *offsets, cons
       const int q = lane + kWave * i;
       if (q < Q) {
         double g[4];
-        srp_gauss4(term, uint32_t(q), k0, k1, g);
+        if (TABLE && int64_t(term) < dim) {
+          const float4 t4 = *reinterpret_cast<const float4 *>(table + size_t(term) * n_bits + 4 * q);
+          g[0] = t4.x; g[1] = t4.y; g[2] = t4.z; g[3] = t4.w;
+        } else {
+          srp_gauss4(term, uint32_t(q), k0, k1, g);
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[i][c] += v * g[c];
       }
@@ -231,13 +255,32 @@ int launch_minhash(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *elems,
   return fail(BLSH_EINVAL, "minhash: n_hashes %d > 1024", n_hashes);
 }
 
+constexpr size_t kSrpTableMaxBytes = size_t(16) << 30;
+
 int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *indices, const float *values,
-                      int64_t n_rows, int n_bits, uint64_t seed, bool word_major, uint32_t *out, hipStream_t s) {
+                      int64_t n_rows, int64_t dim, int n_bits, uint64_t seed, bool word_major, uint32_t *out,
+                      hipStream_t s) {
   const int qpl = (n_bits / 4 + kWave - 1) / kWave;
+  if (qpl > 8) return fail(BLSH_EINVAL, "srp (sparse): n_bits %d > 2048", n_bits);
   const int64_t nb = (n_rows + 3) / 4;
   const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+  // a table of plane entries pays when terms repeat: more nonzeros than twice the dimension
+  int64_t nnz = 0;
+  BLSH_HIP(hipMemcpyAsync(&nnz, offsets + n_rows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BLSH_HIP(hipStreamSynchronize(s));
+  const size_t table_bytes = size_t(std::max<int64_t>(dim, 0)) * size_t(n_bits) * sizeof(float);
+  const bool use_table = dim > 0 && nnz > 2 * dim && table_bytes <= kSrpTableMaxBytes;
+  float *table = nullptr;
+  if (use_table) {
+    if (int rc = ensure_workspace(ctx, table_bytes)) return rc;
+    table = static_cast<float *>(ctx->ws);
+  }
   LaunchScope ls(ctx, s, "srp_sparse");
-#define BLSH_SP(N) if (qpl <= N) { hipLaunchKernelGGL(k_srp_sparse<N>, dim3(nb), dim3(256), 0, s, offsets, indices, values, n_rows, n_bits, k0, k1, int(word_major), out); return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE; }
+  if (use_table) {
+    const int64_t items = dim * (n_bits / 4);
+    hipLaunchKernelGGL(k_srp_table, dim3(unsigned((items + 255) / 256)), dim3(256), 0, s, dim, n_bits, k0, k1, table);
+  }
+#define BLSH_SP(N) if (qpl <= N) { if (use_table) hipLaunchKernelGGL((k_srp_sparse<N, true>), dim3(nb), dim3(256), 0, s, offsets, indices, values, n_rows, n_bits, k0, k1, int(word_major), out, table, dim); else hipLaunchKernelGGL((k_srp_sparse<N, false>), dim3(nb), dim3(256), 0, s, offsets, indices, values, n_rows, n_bits, k0, k1, int(word_major), out, table, dim); return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE; }
   BLSH_SP(1) BLSH_SP(2) BLSH_SP(4) BLSH_SP(8)
 #undef BLSH_SP
   return fail(BLSH_EINVAL, "srp (sparse): n_bits %d > 2048", n_bits);

@@ -78,6 +78,36 @@ def test_sparse_srp_signatures_flip_rule(ctx, n_bits, layout):
     assert diff.sum() <= max(1, 1e-6 * diff.size)
 
 
+@pytest.mark.parametrize("n_bits,layout", [(2048, P.OBJECT_MAJOR), (96, P.WORD_MAJOR)])
+def test_sparse_srp_plane_table_matches_on_the_fly(ctx, n_bits, layout):
+    """With more nonzeros than twice the dimension the plane entries come from
+    a table drawn once per term: bit-identical to drawing them per nonzero
+    (the same CSR data declared with a dimension too large for a table), and
+    the flip rule against the oracle."""
+    _flush("sparse srp plane table: %d bits layout %d" % (n_bits, layout))
+    corpus = G.tfidf_corpus(n_docs=1500, dim=1 << 12, mean_nnz=40, seed=G.SEED_BASE + 23)
+    assert len(corpus.indices) > 2 * corpus.dim
+    seed = 0x2222_3333_4444
+    W = n_bits // 32
+    off, idx, val = up(corpus.offsets), up(corpus.indices.astype(np.uint32)), up(corpus.values)
+    outs = []
+    for dim in (corpus.dim, 1 << 40):   # table; drawn per nonzero
+        out = torch.empty(corpus.n * W, dtype=torch.int32, device="cuda").view(torch.uint32)
+        P.bayeslsh_srp_sigs(ctx, P.csr_vectors(off, idx, val, dim), None, n_bits, seed, layout, out)
+        P.bayeslsh_sync(ctx)
+        outs.append(down(out))
+    np.testing.assert_array_equal(outs[0], outs[1])
+    got = outs[0].reshape((W, corpus.n) if layout == P.WORD_MAJOR else (corpus.n, W))
+    if layout == P.WORD_MAJOR:
+        got = got.T
+    proj = R.srp_sparse_projections(corpus.offsets, corpus.indices, corpus.values, n_bits, seed,
+                                    np.arange(corpus.n, dtype=np.int64))
+    want = R.bits_from_projections(proj)
+    diff = np.unpackbits((got ^ want).view(np.uint8), bitorder="little").reshape(corpus.n, n_bits).astype(bool)
+    assert np.all(np.abs(proj[diff]) < 1e-5), np.abs(proj[diff]).max()
+    assert diff.sum() <= max(1, 1e-6 * diff.size)
+
+
 @pytest.mark.parametrize("d,n_bits,layout", [(256, 1024, P.WORD_MAJOR), (64, 64, P.OBJECT_MAJOR),
                                              (128, 256, P.OBJECT_MAJOR), (32, 32, P.OBJECT_MAJOR)])
 def test_dense_srp_mfma_flip_rule(ctx, d, n_bits, layout):
