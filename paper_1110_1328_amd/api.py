@@ -441,10 +441,11 @@ def bayeslsh_exact_similarity(ctx: Context, cand: Candidates, vecs: Vectors, out
 
 def bayeslsh_band_candidates(ctx: Context, band_sigs: Signatures, n_bands: int, band_bits: int, capacity: int,
                              max_bucket: int = 0, x_out: torch.Tensor = None, y_out: torch.Tensor = None,
-                             stream=None, order_tile: int = 0):
+                             stream=None, order_tile: int = 16):
     """LSH banding on the device.  Returns (x, y, n_pairs, truncated): uint32
     device tensors of `capacity` entries, the first min(n_pairs, capacity) valid.
-    order_tile: 0 (row-major pairs per bucket) or 16 (16 x 16 tiles)."""
+    order_tile: 16 (16 x 16 tiles of each bucket's members, the default: the
+    faster order to band and to verify) or 0 (row-major pairs per bucket)."""
     if x_out is None:
         x_out = torch.empty(max(capacity, 1), dtype=torch.int32, device="cuda").view(torch.uint32)
     if y_out is None:
