@@ -721,6 +721,28 @@ def test_exact_similarity_matches_oracle(ctx):
     assert np.isfinite(o[0]) and np.isnan(o[1])
 
 
+def test_exact_similarity_long_rows(ctx):
+    """Rows longer than one wave's LDS stage (512 entries): the longer row is
+    searched in memory instead; CSR cosine and set Jaccard against the oracle."""
+    _flush("exact similarity, long rows")
+    rng = np.random.default_rng(34)
+    corpus = G.tfidf_corpus(n_docs=300, dim=1 << 16, mean_nnz=800, dup_frac=0.1, seed=G.SEED_BASE + 44)
+    lens = np.diff(corpus.offsets)
+    assert (lens > 512).mean() > 0.9
+    sets = G.jaccard_sets(n_sets=300, vocab=50000, median=900.0, n_groups=20, seed=G.SEED_BASE + 45)
+    assert (np.diff(sets.offsets) > 512).mean() > 0.5
+    cases = [(csr_device(corpus), corpus.n,
+              lambda x, y: R.exact_cosine_csr(corpus.offsets, corpus.indices, corpus.values, x, y)),
+             (sets_device(sets), sets.n, lambda x, y: R.exact_jaccard(sets.offsets, sets.elems, x, y))]
+    for vecs, n_obj, ref in cases:
+        x = rng.integers(0, n_obj, 2003).astype(np.uint32)
+        y = rng.integers(0, n_obj, 2003).astype(np.uint32)
+        x[:10] = y[:10]
+        got = down(P.bayeslsh_exact_similarity(ctx, P.pairs(up(x), up(y)), vecs))[:len(x)]
+        P.bayeslsh_sync(ctx)
+        np.testing.assert_allclose(got, ref(x, y), atol=1e-6, rtol=0)
+
+
 def test_learned_prior_pipeline(ctx):
     """Section 4.1's learned prior end to end on the Jaccard workload: exact
     similarities of a random sample of candidate pairs on the GPU, the
