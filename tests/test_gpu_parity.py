@@ -46,14 +46,17 @@ def run_verify(ctx, cand, sigs, t=T, k=32, prior=(1.0, 1.0), cap=None, m_debug=T
 # ---------------------------------------------------------------------------
 # signatures
 # ---------------------------------------------------------------------------
-def test_minhash_signatures_bit_exact(ctx):
-    _flush("minhash sigs: 400 sets x 256 hashes")
+@pytest.mark.parametrize("n_hashes", [256, 32, 100, 512, 1024])
+def test_minhash_signatures_bit_exact(ctx, n_hashes):
+    """Every hashes-per-lane variant (1, 2, 4, 8, 16), a count that is not a
+    multiple of the wave (100), against the oracle bit for bit."""
+    _flush("minhash sigs: 400 sets x %d hashes" % n_hashes)
     sets = G.jaccard_sets(n_sets=400, vocab=100_000, n_groups=20, seed=G.SEED_BASE + 11)
-    a, b = G.minhash_coeffs(256, G.SEED_BASE + 12)
-    out = torch.empty(sets.n * 256, dtype=torch.int32, device="cuda").view(torch.uint32)
+    a, b = G.minhash_coeffs(n_hashes, G.SEED_BASE + 12)
+    out = torch.empty(sets.n * n_hashes, dtype=torch.int32, device="cuda").view(torch.uint32)
     P.bayeslsh_minhash_sigs(ctx, sets_device(sets), up(a), up(b), out)
     P.bayeslsh_sync(ctx)
-    got = down(out).reshape(sets.n, 256)
+    got = down(out).reshape(sets.n, n_hashes)
     want = R.minhash_signatures(sets.offsets, sets.elems, a, b)
     np.testing.assert_array_equal(got, want)
 
