@@ -61,7 +61,8 @@ def test_minhash_signatures_bit_exact(ctx, n_hashes):
     np.testing.assert_array_equal(got, want)
 
 
-@pytest.mark.parametrize("n_bits,layout", [(2048, P.WORD_MAJOR), (128, P.OBJECT_MAJOR), (96, P.WORD_MAJOR)])
+@pytest.mark.parametrize("n_bits,layout", [(2048, P.WORD_MAJOR), (128, P.OBJECT_MAJOR), (96, P.WORD_MAJOR),
+                                           (512, P.OBJECT_MAJOR), (1024, P.WORD_MAJOR)])
 def test_sparse_srp_signatures_flip_rule(ctx, n_bits, layout):
     _flush("sparse srp sigs: %d bits layout %d" % (n_bits, layout))
     corpus = G.tfidf_corpus(n_docs=300, dim=1 << 20, seed=G.SEED_BASE + 21)
