@@ -6,7 +6,7 @@
  *   - the problem statement and output guarantees (Section 1),
  *   - Algorithm 1 (BayesLSH: prune, else estimate until concentrated) and
  *     Algorithm 2 (BayesLSH-Lite: prune with at most h hashes, then exact
- *     similarity) of Section 3,
+ *     similarity) of Section 4,
  *   - the Jaccard (minhash, Beta prior; Section 4.1) and cosine (sign random
  *     projections, uniform prior on r; Section 4.2) instantiations,
  *   - the precomputation of minimum matches and the cache of concentration
@@ -235,7 +235,13 @@ int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *tuning_host);
  * r = 1 - theta/pi.  lite != 0 skips the concentration bits.  Either output
  * pointer may be NULL.  min_margin_host (optional) receives the smallest
  * distance of an evaluated probability from its threshold.  Host-only: ctx may
- * be NULL (no GPU needed; the table is then built without caching). */
+ * be NULL (no GPU needed; the table is then built without caching).
+ * Near ties are refused: when some evaluated probability lies within 1e-9 of
+ * its threshold (epsilon, or 1 - gamma), the decision at that (n, m) is not
+ * fixed by FP64 evaluation, and the call returns BLSH_EINVAL with a message
+ * naming the test and (n, m).  Every verification entry point (Algorithm 1,
+ * Lite, exhaustive, batched, serving) builds its table through the same code
+ * and refuses such a parameter set the same way, before enqueuing anything. */
 int bayeslsh_posterior_table(blsh_ctx *ctx, blsh_measure measure, double t, double epsilon, double delta,
                              double gamma, blsh_prior prior, int32_t k, int32_t n_levels, int32_t lite,
                              int32_t *min_matches_host, uint32_t *accept_host, double *min_margin_host);

@@ -7,7 +7,7 @@ the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import it.  The product path never calls it and shares no code with it.
 
 Modules
-  posterior  -- posterior quantities of Section 3 (prune probability,
+  posterior  -- posterior quantities of Section 4 (prune probability,
                 MAP estimate, concentration probability) for the Jaccard
                 (Section 4.1) and cosine (Section 4.2) instantiations, in FP64.
   hashes     -- the two LSH families of Section 4: minhash and sign random

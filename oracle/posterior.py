@@ -1,12 +1,12 @@
 """Posterior quantities of BayesLSH in FP64 (oracle; test infrastructure only).
 
 After comparing n hashes of a pair and seeing m agreements (the event
-M(m, n)), the likelihood is Binomial(n, S) (Section 3, eqn likelihood).
+M(m, n)), the likelihood is Binomial(n, S) (Section 4, eqn likelihood).
 BayesLSH needs three numbers from the posterior p(S | M(m, n)):
 
-  prune probability   Pr[S >= t | M(m,n)]             (Section 3, eqn pruneProb)
-  MAP estimate        S_hat = argmax_s p(s | M(m,n))    (Section 3, eqn map)
-  concentration       Pr[|S - S_hat| < delta | M(m,n)]  (Section 3, eqn concentrateProb)
+  prune probability   Pr[S >= t | M(m,n)]             (Section 4, eqn pruneProb)
+  MAP estimate        S_hat = argmax_s p(s | M(m,n))    (Section 4, eqn map)
+  concentration       Pr[|S - S_hat| < delta | M(m,n)]  (Section 4, eqn concentrateProb)
 
 Jaccard (Section 4.1): prior Beta(alpha, beta), posterior
 Beta(m + alpha, n - m + beta); the prune probability is 1 - I_t(a, b) and the

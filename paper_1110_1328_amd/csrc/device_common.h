@@ -157,7 +157,7 @@ __device__ inline double cos_quarter(double x) {
   return c;
 }
 
-// S_hat for an emitted pair (Section 3 eqn map; Section 4.1 Beta mode; Section 4.2 r2c(m/n)).
+// S_hat for an emitted pair (Section 4 eqn map; Section 4.1 Beta mode; Section 4.2 r2c(m/n)).
 __device__ inline float map_estimate(int measure, int m, int n, double alpha, double beta) {
   if (measure == BLSH_JACCARD) {
     double s = (m + alpha - 1.0) / (n + alpha + beta - 2.0);

@@ -44,8 +44,16 @@ struct HostTable {
   int k = 0, n_levels = 0, n_max = 0, words = 0;
   std::vector<int32_t> min_matches;   // [n_levels]
   std::vector<uint32_t> accept;       // [n_levels][words]
+  // smallest |probability - threshold| over every evaluated test, and where
+  // (n, m, kind: 0 prune, 1 concentration)
   double min_margin = 1.0;
+  int margin_n = 0, margin_m = 0, margin_kind = 0;
 };
+
+// A table whose smallest margin is below this is refused (BLSH_EINVAL): the
+// host quadrature, the binomial sums and any other correct evaluation agree
+// far more closely than this, so above it every decision is unique.
+constexpr double kTieMargin = 1e-9;
 
 // Device image of a table, read by every verify kernel into LDS.
 // Layout of the device buffer (32-bit words):

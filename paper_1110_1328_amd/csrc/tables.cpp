@@ -209,8 +209,18 @@ struct Cosine {
   }
 };
 
+// Where a level's smallest margin was found: |probability - threshold| at
+// (n, m), for the prune test (kind 0) or the concentration test (kind 1).
+struct Margin {
+  double v = 1.0;
+  int n = 0, m = 0, kind = 0;
+  void take(double d, int n_, int m_, int kind_) {
+    if (d < v) { v = d; n = n_; m = m_; kind = kind_; }
+  }
+};
+
 template <class Model>
-void build_level(const Model &mdl, const TableKey &key, int j, HostTable *out, double *margin) {
+void build_level(const Model &mdl, const TableKey &key, int j, HostTable *out, Margin *margin) {
   const int n = (j + 1) * key.k;
   // minMatches(n): binary search for the first m with prune_prob >= epsilon.
   int lo = 0, hi = n + 1;  // answer in [lo, hi]; hi = n+1 means "always prune"
@@ -220,13 +230,13 @@ void build_level(const Model &mdl, const TableKey &key, int j, HostTable *out, d
   }
   const int mm = lo;
   out->min_matches[j] = mm;
-  double mg = 1.0;
-  if (mm <= n) mg = std::min(mg, std::fabs(mdl.prune_prob(mm, n) - key.epsilon));
-  if (mm > 0 && mm - 1 <= n) mg = std::min(mg, std::fabs(mdl.prune_prob(mm - 1, n) - key.epsilon));
+  Margin mg;
+  if (mm <= n) mg.take(std::fabs(mdl.prune_prob(mm, n) - key.epsilon), n, mm, 0);
+  if (mm > 0 && mm - 1 <= n) mg.take(std::fabs(mdl.prune_prob(mm - 1, n) - key.epsilon), n, mm - 1, 0);
   if (!key.lite) {
     for (int m = mm; m <= n; ++m) {
       const double c = mdl.concentration(m, n);
-      mg = std::min(mg, std::fabs(c - (1.0 - key.gamma)));
+      mg.take(std::fabs(c - (1.0 - key.gamma)), n, m, 1);
       if (c >= 1.0 - key.gamma) out->accept[size_t(j) * out->words + (m >> 5)] |= 1u << (m & 31);
     }
   }
@@ -235,7 +245,7 @@ void build_level(const Model &mdl, const TableKey &key, int j, HostTable *out, d
 
 template <class Model>
 void build_all(const Model &mdl, const TableKey &key, HostTable *out) {
-  std::vector<double> margins(key.n_levels, 1.0);
+  std::vector<Margin> margins(key.n_levels);
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   nt = std::min<unsigned>(nt, key.n_levels);
   std::vector<std::thread> th;
@@ -244,7 +254,13 @@ void build_all(const Model &mdl, const TableKey &key, HostTable *out) {
       for (int j = int(w); j < key.n_levels; j += int(nt)) build_level(mdl, key, j, out, &margins[j]);
     });
   for (auto &x : th) x.join();
-  out->min_margin = *std::min_element(margins.begin(), margins.end());
+  const Margin *lo = &margins[0];
+  for (const Margin &m : margins)
+    if (m.v < lo->v) lo = &m;
+  out->min_margin = lo->v;
+  out->margin_n = lo->n;
+  out->margin_m = lo->m;
+  out->margin_kind = lo->kind;
 }
 
 }  // namespace
@@ -265,6 +281,17 @@ int build_table(const TableKey &key, HostTable *out) {
     Cosine mdl{key.t, key.delta};
     build_all(mdl, key, out);
   }
+  // A probability this close to its threshold could fall on either side of it
+  // under another (equally valid) evaluation of the posterior: the decision at
+  // that (n, m) is not determined, so the parameter set is refused rather
+  // than answered one way silently.
+  if (out->min_margin < kTieMargin)
+    return fail(BLSH_EINVAL,
+                "posterior table: %s at n=%d, m=%d lies within %.3g of its threshold (%s = %.17g); decisions "
+                "there are not determined in FP64 -- change the parameters slightly",
+                out->margin_kind == 0 ? "Pr[S >= t | M(m,n)]" : "Pr[|S - S_hat| < delta | M(m,n)]", out->margin_n,
+                out->margin_m, out->min_margin, out->margin_kind == 0 ? "epsilon" : "1 - gamma",
+                out->margin_kind == 0 ? key.epsilon : 1.0 - key.gamma);
   return BLSH_OK;
 }
 

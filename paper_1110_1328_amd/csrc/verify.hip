@@ -489,10 +489,16 @@ __global__ __launch_bounds__(kBlock) void k_exact(VerifyArgs a) {
 }
 
 // Algorithm 1 for the SRP candidates queued after the 128-hash prefix: one
-// lane per queued pair, from its next level on.  On object-major rows a step
-// loads the next two 16-byte chunks of both sides, every load issued before
-// any is used, so one round trip serves 256 / K levels; on word-major slabs,
-// where every word is a gather of its own, a step loads one level's words.
+// lane per queued pair, from its next level on.  Layouts (LM):
+//   kTailWM     word-major slabs, where every word is a gather of its own: a
+//               step loads one level's words;
+//   kTailRow16  object-major rows of a multiple of 4 words, 16-byte aligned: a
+//               step loads the next two 16-byte chunks of both sides, every
+//               load issued before any is used, so one round trip serves
+//               256 / K levels;
+//   kTailRow4   other object-major rows (a caller's prefix array beside rows
+//               that a 16-byte load cannot start, e.g. 160 or 192 hashes): the
+//               same 8-word step read one word at a time, never past the row.
 // minMatches and the accept bits sit in LDS (the decision of a level costs no
 // memory round trip).
 // Agreeing hashes of level q of the 8 loaded words (q < 256 / K; q is a
@@ -504,8 +510,11 @@ __device__ inline uint32_t agree_at(const uint32_t (&d)[8], int q) {
   else return 16u - __popc((d[q >> 1] >> ((q & 1) * 16)) & 0xFFFFu);
 }
 
-template <int K, bool WM>
+constexpr int kTailWM = 0, kTailRow16 = 1, kTailRow4 = 2;
+
+template <int K, int LM>
 __global__ __launch_bounds__(kBlock) void k_verify_tail(VerifyArgs a) {
+  constexpr bool WM = LM == kTailWM;
   extern __shared__ uint32_t s_acc[];   // n_levels * words accept-bit words
   __shared__ int s_min[kMaxLevels];
   const int L = a.n_levels;
@@ -563,6 +572,16 @@ __global__ __launch_bounds__(kBlock) void k_verify_tail(VerifyArgs a) {
           }
 #pragma unroll
           for (int u = 0; u < kStepWords; ++u) d[u] = hx[u] ^ hy[u];
+        } else if constexpr (LM == kTailRow4) {
+          const uint32_t *rx = a.sig + size_t(x) * a.row_words + w0, *ry = a.sig + size_t(y) * a.row_words + w0;
+          uint32_t hx[8], hy[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            hx[u] = u < avail ? rx[u] : 0u;
+            hy[u] = u < avail ? ry[u] : 0u;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) d[u] = hx[u] ^ hy[u];
         } else {
           const u32x4 hx0 = *reinterpret_cast<const u32x4 *>(a.sig + size_t(x) * a.row_words + w0);
           const u32x4 hy0 = *reinterpret_cast<const u32x4 *>(a.sig + size_t(y) * a.row_words + w0);
@@ -969,15 +988,19 @@ int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStrea
 }
 
 // words: accept-bit words per level of the launch's table (LDS of the tail).
+// Object-major rows take 16-byte chunk loads only when every row starts on a
+// 16-byte boundary and holds a whole number of chunks.
 int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, int words, hipStream_t s) {
   const int64_t nb = round_up(int64_t(ctx->n_cu) * 16, kSlices);
   const size_t lds = size_t(a.n_levels) * words * 4;
+  const bool row16 = a.row_words % 4 == 0 && (uintptr_t(a.sig) & 15) == 0;
   LaunchScope ls(ctx, s, "verify_tail");
-#define BLSH_T(KK)                                                                                    \
-  if (k == KK) {                                                                                      \
-    if (word_major) hipLaunchKernelGGL((k_verify_tail<KK, true>), dim3(nb), dim3(kBlock), lds, s, a);  \
-    else hipLaunchKernelGGL((k_verify_tail<KK, false>), dim3(nb), dim3(kBlock), lds, s, a);           \
-    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                                  \
+#define BLSH_T(KK)                                                                                          \
+  if (k == KK) {                                                                                            \
+    if (word_major) hipLaunchKernelGGL((k_verify_tail<KK, kTailWM>), dim3(nb), dim3(kBlock), lds, s, a);     \
+    else if (row16) hipLaunchKernelGGL((k_verify_tail<KK, kTailRow16>), dim3(nb), dim3(kBlock), lds, s, a);  \
+    else hipLaunchKernelGGL((k_verify_tail<KK, kTailRow4>), dim3(nb), dim3(kBlock), lds, s, a);             \
+    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                                        \
   }
   BLSH_T(16) BLSH_T(32) BLSH_T(64)
 #undef BLSH_T

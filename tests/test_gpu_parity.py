@@ -256,6 +256,33 @@ def test_layouts_and_candidate_orders(ctx, k, lite):
             assert_same_as_oracle(got, want, lite_exact=want["exact"] if lite else None)
 
 
+@pytest.mark.parametrize("n_hashes,k", [(160, 32), (192, 64), (224, 16), (224, 32), (416, 32)])
+def test_tail_on_rows_of_odd_word_counts(ctx, n_hashes, k):
+    """Object-major SRP rows whose length is not a multiple of 4 words (160,
+    192, 224, 416 hashes) beside a separate 128-bit prefix array: the levels
+    past the prefix are read one word at a time, never past a row (the last
+    object is in the candidate set, so its row ends the buffer), aligned and
+    at a 4-byte offset; the oracle's decisions, levels, m and S_hat."""
+    _flush("tail on %d-hash rows, k=%d" % (n_hashes, k))
+    n_obj = 3001
+    W = n_hashes // 32
+    sig = _calib_pairs(P.COSINE, (n_obj + 1) // 2, n_hashes, 900 + n_hashes + k, lo=0.75)[:n_obj]
+    rng = np.random.default_rng(n_hashes + k)
+    x = np.concatenate([np.arange(0, n_obj - 1, 2), rng.integers(0, n_obj, 5000)]).astype(np.uint32)
+    y = np.concatenate([np.arange(1, n_obj, 2), rng.integers(0, n_obj, 5000)]).astype(np.uint32)
+    x[-1], y[-1] = n_obj - 1, n_obj - 2
+    want = R.verify(x, y, P.COSINE, sig, k, n_hashes // k, T, EPS, DELTA, GAMMA)
+    assert np.sum(want["level"] >= 128 // k) > 100   # the tail has work
+    pfx = up(np.ascontiguousarray(sig[:, :4]))
+    rows = up(np.ascontiguousarray(sig))
+    buf = torch.zeros(n_obj * W + 1, dtype=torch.int32, device="cuda")
+    buf[1:] = rows.view(torch.int32)
+    for data in (rows, buf[1:].view(torch.uint32)):
+        S = P.Signatures(data, P.COSINE, P.OBJECT_MAJOR, n_obj, n_hashes, prefix=pfx)
+        res = run_verify(ctx, P.pairs(up(x), up(y)), S, k=k)
+        assert_same_as_oracle(decode_result(res, len(x)), want)
+
+
 def test_verify_jaccard_workload_all_pairs(ctx):
     """The Jaccard workload at full size: 2000 sets, all 1,999,000 pairs, 256
     minhashes, k = 32, t = 0.7, Beta(1,1); explicit pairs give the same result."""
@@ -689,6 +716,54 @@ def test_invalid_arguments_rejected(ctx):
     with pytest.raises(P.BayesLSHError):   # Lite budget not a multiple of k
         P.bayeslsh_lite_verify(ctx, P.pairs(x, x), S, P.dense_vectors(torch.zeros(10, 8, device="cuda")), T, EPS,
                                (1, 1), 48, 32, res)
+
+
+def test_near_tie_parameters_refused(ctx):
+    """Section 4.3's table decisions are unique only away from ties: epsilon
+    placed exactly on the oracle's Pr[S >= t | M(m, n)] at (n, m) = (64, 45)
+    (cosine, t = 0.8), or 1 - gamma on its concentration at (96, 90)
+    (Jaccard, t = 0.7), is refused with BLSH_EINVAL naming (n, m) by
+    Algorithm 1, Lite, the exhaustive comparator and the batched call, with
+    nothing enqueued (the outputs keep their sentinel); nudged by 1e-6 the
+    same calls run."""
+    n = 64
+    sig = _calib_pairs(P.COSINE, n // 2, 256, 14)
+    S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
+    x = up(np.arange(0, n, 2, dtype=np.uint32))
+    y = up(np.arange(1, n, 2, dtype=np.uint32))
+    cand = P.pairs(x, y)
+    eps_tie = O.prune_prob(1, 45, 64, 0.8)
+    dvec = P.dense_vectors(torch.ones(n, 8, device="cuda"))
+    calls = {
+        "verify": lambda r, e: P.bayeslsh_verify(ctx, cand, S, 0.8, e, DELTA, GAMMA, (1, 1), 32, r),
+        "lite": lambda r, e: P.bayeslsh_lite_verify(ctx, cand, S, dvec, 0.8, e, (1, 1), 128, 32, r),
+        "exhaustive": lambda r, e: P.bayeslsh_exhaustive_verify(ctx, cand, S, None, 0.8, e, DELTA, GAMMA, (1, 1),
+                                                                32, 0, P.REPLAY, r),
+    }
+    for name, call in calls.items():
+        res = P.make_result(n // 2, n)
+        res.code.fill_(0xEE)
+        with pytest.raises(P.BayesLSHError) as e:
+            call(res, eps_tie)
+        assert e.value.code == -1 and "n=64, m=45" in str(e.value), (name, str(e.value))
+        P.bayeslsh_sync(ctx)
+        assert bool((res.code == 0xEE).all()), name
+        call(res, eps_tie + 1e-6)
+        P.bayeslsh_sync(ctx)
+        assert not bool((res.code == 0xEE).any()), name
+    # the batched call, Jaccard list with 1 - gamma on a concentration value
+    gamma_tie = 1.0 - O.concentration(0, 90, 96, DELTA)
+    jsig = _calib_pairs(P.JACCARD, n // 2, 256, 15)
+    SJ = sigs_tensor(jsig, P.JACCARD, P.OBJECT_MAJOR)
+    lists = P.list_descs(np.array([0], np.int32), np.array([0.7]), np.array([0], np.uint32),
+                         np.array([0], np.int64), np.array([n - 1], np.int64))
+    cand_ids = up(np.arange(1, n, dtype=np.uint32))
+    res = P.make_result(n - 1, n)
+    with pytest.raises(P.BayesLSHError) as e:
+        P.bayeslsh_verify_batched(ctx, lists, cand_ids, SJ, None, EPS, DELTA, gamma_tie, (1, 1), (32, 32), res)
+    assert e.value.code == -1 and "n=96, m=90" in str(e.value), str(e.value)
+    P.bayeslsh_verify_batched(ctx, lists, cand_ids, SJ, None, EPS, DELTA, gamma_tie + 1e-6, (1, 1), (32, 32), res)
+    P.bayeslsh_sync(ctx)
 
 
 def test_exact_similarity_matches_oracle(ctx):

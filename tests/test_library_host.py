@@ -128,3 +128,41 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+@pytest.mark.parametrize("measure,t,k,L,n,m,kind", [
+    (0, 0.7, 32, 8, 32, 18, "prune"),         # epsilon placed on Pr[S >= t | M(18, 32)]
+    (0, 0.7, 32, 8, 128, 80, "prune"),
+    (1, 0.8, 32, 8, 64, 45, "prune"),
+    (0, 0.7, 32, 8, 96, 90, "concentration"),  # 1 - gamma placed on Pr[|S - S_hat| < delta | M(90, 96)]
+    (1, 0.7, 32, 4, 128, 120, "concentration"),
+])
+def test_posterior_table_refuses_near_ties(lib, measure, t, k, L, n, m, kind):
+    """Section 4.3's precomputed decisions are unique only when no posterior
+    probability sits on its threshold.  A parameter set that puts epsilon (or
+    1 - gamma) exactly on a probability the oracle computes at some (n, m) is
+    refused with BLSH_EINVAL naming that (n, m), rather than decided one way
+    by rounding; a nearby parameter set (threshold moved by 1e-6) builds."""
+    import paper_1110_1328_amd as P
+    from paper_1110_1328_amd.api import BayesLSHError
+    eps, delta, gamma = 0.03, 0.05, 0.03
+    if kind == "prune":
+        eps = O.prune_prob(measure, m, n, t)
+        assert 1e-6 < eps < 0.5
+    else:
+        c = O.concentration(measure, m, n, delta)
+        gamma = 1.0 - c
+        assert 1e-6 < gamma < 0.5
+        # the pair must reach the concentration test there (not pruned first)
+        assert O.prune_prob(measure, m, n, t) >= eps
+    with pytest.raises(BayesLSHError) as e:
+        P.bayeslsh_posterior_table(None, measure, t, eps, delta, gamma, (1.0, 1.0), k, L, False)
+    assert e.value.code == -1
+    msg = str(e.value)
+    assert "n=%d, m=%d" % (n, m) in msg, msg
+    if kind == "prune":
+        eps += 1e-6
+    else:
+        gamma += 1e-6
+    _, _, margin = P.bayeslsh_posterior_table(None, measure, t, eps, delta, gamma, (1.0, 1.0), k, L, False)
+    assert margin > 1e-9

@@ -395,6 +395,66 @@ def test_mle_estimate():
     np.testing.assert_allclose(out["shat"], want)
 
 
+def _bit_rows(n_bits, agree_counts):
+    """Object 0 = all-zero bits; object i+1 agrees with it on exactly
+    agree_counts[i] of the first n_bits bits (packed LSB-first words)."""
+    words = n_bits // 32
+    rows = np.zeros((len(agree_counts) + 1, words), np.uint32)
+    for i, m in enumerate(agree_counts):
+        bits = np.zeros(n_bits, np.uint8)
+        bits[m:] = 1                     # the last n_bits - m bits disagree
+        rows[i + 1] = np.packbits(bits.reshape(words, 32)[:, ::-1], axis=1).view(">u4").ravel()
+    return rows
+
+
+def test_mle_cosine_branch_hand_values():
+    """Cosine LSH Approx (Section 3 estimator through the Section 4.2 map
+    r -> cos(pi (1 - r))): at m/n = 1, 3/4, 1/2, 1/4 and 0 the estimate is
+    cos 0 = 1, cos(pi/4) = sqrt(2)/2, cos(pi/2) = 0, cos(3 pi/4) = -sqrt(2)/2
+    and cos(pi) = -1 (values of the cosine, not retyped from the oracle's
+    expression); emission is inclusive at t (checked on the Jaccard branch,
+    where 3/4 is exact)."""
+    n = 64
+    rows = _bit_rows(n, [64, 48, 32, 16, 0])
+    x = np.zeros(5, np.uint32)
+    y = np.arange(1, 6, dtype=np.uint32)
+    assert np.array_equal(R.counts_all(x, y, 1, rows, n), [64, 48, 32, 16, 0])
+    out = R.mle(x, y, 1, rows, n, 0.7)
+    h = np.sqrt(2.0) / 2.0
+    np.testing.assert_allclose(out["shat"], [1.0, h, 0.0, -h, -1.0], atol=1e-15)
+    assert out["accepted"].tolist() == [True, True, False, False, False]
+    # inclusive threshold: 48/64 = 0.75 exactly, t = 0.75 accepts (a strict
+    # rule would reject it)
+    jac = np.zeros((2, n), np.uint32)
+    jac[1, 48:] = 7
+    o = R.mle(np.array([0], np.uint32), np.array([1], np.uint32), 0, jac, n, 0.75)
+    assert o["shat"][0] == 0.75 and bool(o["accepted"][0])
+
+
+def test_mle_cosine_branch_recovers_the_angle():
+    """Sign random projections agree with probability 1 - theta/pi (Section
+    4.2), so the cosine estimate over many hashes approaches cos(theta): two
+    unit vectors at a chosen angle, 2^16 Gaussian planes drawn here with
+    numpy (not the oracle's generator), bits packed LSB-first.  A reading such
+    as cos(pi r) would return -cos(theta) and fail."""
+    rng = np.random.default_rng(11)
+    d, n = 32, 1 << 16
+    for theta in (0.3, 1.0, 2.2):
+        u = rng.standard_normal(d)
+        u /= np.linalg.norm(u)
+        w = rng.standard_normal(d)
+        w -= (w @ u) * u
+        w /= np.linalg.norm(w)
+        v = np.cos(theta) * u + np.sin(theta) * w
+        planes = rng.standard_normal((d, n))
+        bits = np.stack([(u @ planes) >= 0, (v @ planes) >= 0]).astype(np.uint8)
+        rows = np.packbits(bits.reshape(2, n // 32, 32)[:, :, ::-1], axis=2).view(">u4").reshape(2, n // 32)
+        rows = rows.astype(np.uint32)
+        o = R.mle(np.array([0], np.uint32), np.array([1], np.uint32), 1, rows, n, 0.5)
+        # std of m/n <= 0.002 at n = 2^16; through cos that is <= pi * 0.002
+        assert abs(o["shat"][0] - np.cos(theta)) < 0.03, (theta, o["shat"][0])
+
+
 # ---------------------------------------------------------------------------
 # Learned prior (Section 4.1): method of moments, and the posterior with real
 # Beta parameters
