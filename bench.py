@@ -2,20 +2,23 @@
 """Benchmark: candidate pairs verified per second, BayesLSH vs exhaustive hash
 compare with the same output, on one MI355X.
 
-Workload (default): the cosine BayesLSH-Lite configuration -- 100,000 sparse
-tf-idf vectors (dimension 2^20, Poisson(100) nonzeros, Zipf(1.1) terms, 5%
-planted near-duplicates), 2048 sign-random-projection bits per vector,
-candidates from 16-band x 10-bit LSH banding on an independent projection
-(on the device, each bucket's pairs in 16 x 16 tiles of its members; timed
-apart from the step), t = 0.7, epsilon = 0.03, h = 128, k = 32, exact cosine
-on survivors.
+Workload (default): dense cosine estimation, the largest workload one GPU
+holds -- 1M x 256 unit vectors from a 1000-component Gaussian mixture, 1024
+sign-random-projection bits per vector (FP32 MFMA projection), candidates
+from GPU LSH banding (16 bands x 12 bits of an independent 192-bit
+projection, each bucket's pairs in 16 x 16 tiles of its members; about 2.4e9
+pairs; timed apart from the step), Algorithm 1 at t = 0.8, epsilon = gamma =
+0.03, delta = 0.05, k = 32.
 
-One step = one bayeslsh_lite_verify call over all candidates with signatures
-and candidates resident in HBM and the posterior table cached.  The
-exhaustive comparator (bayeslsh_exhaustive_verify, mode REPLAY_LITE: all 2048
-bits of both object-major rows, then the same decision sequence replayed and
-the same exact-similarity kernel) is timed the same way and its output is
-checked to be identical.
+One step = one bayeslsh_verify call over all candidates with signatures and
+candidates resident in HBM and the posterior table cached.  The exhaustive
+comparator (bayeslsh_exhaustive_verify, mode REPLAY: all 1024 bits of both
+object-major rows, then the same decision sequence replayed) is timed the same
+way and its output is checked to be identical.  The line carries the roofline
+of the dominant kernel (algorithmic bytes over its HIP-event duration), the
+oracle timed on the host over a seeded sample, and the sample's parity.  The
+cosine BayesLSH-Lite workload (100k sparse tf-idf vectors, ~8e7 candidates)
+follows under its own key.
 
 Prints one JSON line (stdout).  Progress goes to stderr.
 """
@@ -36,6 +39,14 @@ METRIC = "candidate pairs verified/sec, BayesLSH vs exhaustive hash compare, sam
 T, EPS, H, K, N_BITS = 0.7, 0.03, 128, 32, 2048
 SRP_SEED = 0x5EED_1110_1328
 HBM_PEAK_GBS = 8000.0
+# the paper's own speedups, for context only (other hardware, whole pipeline
+# including candidate generation, real datasets)
+PAPER_CONTEXT = {
+    "speedup_over_baselines": "2x-20x in most comparisons (abstract; Section 5)",
+    "speedup_over_lsh_approx": "tf-idf cosine 2.0x-3.0x, binary Jaccard 2.8x-4.2x, binary cosine 1.2x "
+                               "(Table 2, time summed over thresholds)",
+    "hardware": "single-threaded C/C++, dual-socket dual-core 2.3 GHz Opteron, 8 GB RAM (Section 5)",
+}
 
 
 def log(msg):
@@ -90,13 +101,14 @@ def lite_candidates(torch, P, ctx, corpus, small):
     return xo[:n], yo[:n], n, band_ms
 
 
-def cpu_baseline(corpus, x, y, gpu_codes):
+def cpu_baseline(corpus, x, y, gpu_codes, gpu_m, gpu_acc):
     """The oracle (plain C loop of Algorithm 2 + FP64 exact cosine), timed over the
     whole candidate set on the host's cores, on signatures the oracle computes
     itself (the first h bits of every object; not timed, as the GPU's signature
-    generation is not in its step either).  Also compares its decisions with the
-    GPU codes on every candidate whose two objects have no near-zero projection
-    (only there can an FP32-vs-FP64 rounding flip a signature bit)."""
+    generation is not in its step either).  Also compares its output with the
+    GPU's on every candidate whose two objects have no near-zero projection
+    (only there can an FP32-vs-FP64 rounding flip a signature bit): decision,
+    level and m exact, the accepted set equal, exact cosines within 1e-6."""
     from oracle import reference as R
     from oracle import posterior as OP
     rows = np.arange(corpus.n, dtype=np.int64)
@@ -115,10 +127,20 @@ def cpu_baseline(corpus, x, y, gpu_codes):
     fragile = np.any(np.abs(proj) < 1e-5, axis=1)
     ok = ~(fragile[x] | fragile[y])
     g = gpu_codes
+    acc_idx, acc_val = gpu_acc
+    gpu_accepted = np.zeros(len(x), bool)
+    gpu_accepted[acc_idx] = True
+    gpu_val = np.full(len(x), np.nan)
+    gpu_val[acc_idx] = acc_val
+    both = ok & gpu_accepted & res["accepted"]
     parity = dict(compared=int(ok.sum()), skipped_fragile=int((~ok).sum()),
                   decision_mismatches=int(np.sum((g[ok] >> 6) != res["decision"][ok])),
-                  level_mismatches=int(np.sum((g[ok] & 63) != res["level"][ok])))
-    return dict(value=len(x) / dt, unit="pairs/s", cores=threads, kind="oracle",
+                  level_mismatches=int(np.sum((g[ok] & 63) != res["level"][ok])),
+                  m_mismatches=int(np.sum(gpu_m[ok] != res["m"][ok])),
+                  accepted_set_mismatches=int(np.sum(gpu_accepted[ok] != res["accepted"][ok])),
+                  accepted_compared=int(both.sum()),
+                  max_abs_exact_cosine_error=float(np.max(np.abs(gpu_val[both] - res["exact"][both]), initial=0.0)))
+    return dict(value=len(x) / dt, unit="pairs/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
                 sample="all %d candidates of the workload, median of 3 runs (%.2f s each)" % (len(x), dt)), parity, res
 
 
@@ -535,17 +557,68 @@ def run_sigs(args, torch, P):
                         "hash_evals_per_s": n_el * 256 / (mh_ms * 1e-3)}}
 
 
+DENSE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "verify_dense_1m_traffic.txt")
+DENSE_KERNEL_SOURCES = ("paper_1110_1328_amd/csrc/verify.hip", "paper_1110_1328_amd/csrc/device_common.h")
+# the verification call's kernels, by the names their launches are profiled under
+DENSE_KERNELS = ("verify_bits_prefix", "verify_tail", "acc_flush")
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def kernel_profile(P, ctx, stream, fn, steps, names):
+    """Average duration and launches per step of each named kernel, from HIP
+    events recorded around every launch on its stream (a pass of its own, so
+    that event creation stays out of the timed steps)."""
+    P.bayeslsh_profile_enable(ctx, True)
+    P.bayeslsh_profile_reset(ctx)
+    for _ in range(steps):
+        fn()
+    P.bayeslsh_sync(ctx, stream)
+    out = {}
+    for nm in names:
+        ms, nl = P.bayeslsh_profile_read(ctx, nm)
+        out[nm] = {"avg_ms": ms / max(nl, 1), "launches_per_step": nl / steps, "ms_per_step": ms / steps}
+    P.bayeslsh_profile_enable(ctx, False)
+    return out
+
+
+def measured_traffic_of(path, sources, key):
+    """A value from a committed counter summary, or None when the kernel sources
+    hash differently from when the counters were taken."""
+    import hashlib
+    try:
+        kv = dict(l.split() for l in open(path) if l.strip())
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return int(float(kv[key])) if kv.get("kernel_source_sha256") == h.hexdigest() and key in kv else None
+
+
 def run_dense(args, torch, P):
-    """Dense cosine estimation: 1M x 256 Gaussian-mixture vectors, 1024 SRP bits
-    (object-major rows + prefix array) for verification; candidates from GPU LSH
-    banding (16 bands x 12 bits of an independent 192-bit projection, each
-    bucket's pairs listed by 16 x 16 tiles of its members); then
-    Algorithm 1 (t = 0.8, eps = gamma = 0.03, delta = 0.05, k = 32, n_max = 1024)
-    over every candidate, against the exhaustive REPLAY comparator (object-major
-    rows) with the same output.  A random sample of the candidates is checked
-    against the oracle on the GPU's own signatures."""
+    """Dense cosine estimation, the largest single-GPU workload: 1M x 256
+    Gaussian-mixture vectors, 1024 SRP bits (object-major rows + the 16 B/object
+    prefix array) for verification; candidates from GPU LSH banding (16 bands x
+    12 bits of an independent 192-bit projection, each bucket's pairs listed by
+    16 x 16 tiles of its members); one step = Algorithm 1 (t = 0.8, eps = gamma =
+    0.03, delta = 0.05, k = 32, n_max = 1024) over every candidate, against the
+    exhaustive REPLAY comparator (object-major rows) with the same output.  A
+    seeded sample of the candidates is checked against the oracle on the GPU's
+    own signatures (decision, level and m exact, S_hat within 1e-6), and the
+    oracle's Algorithm 1 is timed over that sample on the host's cores."""
     from synth import generators as G
     from oracle import reference as R
+    from oracle import posterior as OP
     t, eps, delta, gamma, k = 0.8, 0.03, 0.05, 0.03, 32
     ctx = P.bayeslsh_create(0)
     log("dense index (1M x 256, 1024 verification bits)")
@@ -557,7 +630,7 @@ def run_dense(args, torch, P):
     xd = up(torch, mix.x)
     P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), band_planes, 192, 0, P.OBJECT_MAJOR, band_sig)
     P.bayeslsh_sync(ctx)
-    del xd
+    del xd, mix
     S_band = P.Signatures(band_sig, P.COSINE, P.OBJECT_MAJOR, n_obj, 192)
     cap = int(2.6e9)
     xo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
@@ -573,51 +646,149 @@ def run_dense(args, torch, P):
     cand = P.pairs(xo[:n], yo[:n])
     acc_cap = 1 << 28
     res = P.make_result(n, acc_cap)
-    res_ex = P.make_result(n, acc_cap)
     stream = torch.cuda.current_stream()
 
-    def timed(fn, steps):
-        fn()
-        P.bayeslsh_sync(ctx, stream)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t1
-        P.bayeslsh_sync(ctx, stream)
-        return el * 1e3 / steps
+    def step():
+        P.bayeslsh_verify(ctx, cand, S_pfx, t, eps, delta, gamma, (1, 1), k, res, stream)
 
-    ms = timed(lambda: P.bayeslsh_verify(ctx, cand, S_pfx, t, eps, delta, gamma, (1, 1), k, res, stream), 5)
-    log("BayesLSH: %.3f ms (%.3g pairs/s)" % (ms, n / ms * 1e3))
-    ms_ex = timed(lambda: P.bayeslsh_exhaustive_verify(ctx, cand, S_om, None, t, eps, delta, gamma, (1, 1), k, 0,
-                                                       P.REPLAY, res_ex, stream), 2)
-    log("exhaustive: %.3f ms" % ms_ex)
+    for _ in range(args.warmup):
+        step()
+    P.bayeslsh_sync(ctx, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    P.bayeslsh_sync(ctx, stream)
+    log("BayesLSH: %.3f ms/step (%.3g pairs/s)" % (ms, n / ms * 1e3))
+    prof = kernel_profile(P, ctx, stream, step, min(args.steps, 10), DENSE_KERNELS)
+    log("kernels: %s" % ", ".join("%s %.3f ms x %.0f" % (k_, v["avg_ms"], v["launches_per_step"])
+                                  for k_, v in prof.items()))
+
+    # the exhaustive comparator: every candidate compares all 1024 bits, then the
+    # decision sequence is replayed -> the same output
+    res_ex = P.make_result(n, acc_cap)
+
+    def step_ex():
+        P.bayeslsh_exhaustive_verify(ctx, cand, S_om, None, t, eps, delta, gamma, (1, 1), k, 0, P.REPLAY, res_ex,
+                                     stream)
+
+    step_ex()
+    P.bayeslsh_sync(ctx, stream)
+    torch.cuda.synchronize()
+    ex_steps = max(2, args.steps // 10)
+    t1 = time.perf_counter()
+    for _ in range(ex_steps):
+        step_ex()
+    torch.cuda.synchronize()
+    ms_ex = (time.perf_counter() - t1) * 1e3 / ex_steps
+    P.bayeslsh_sync(ctx, stream)
+    log("exhaustive: %.3f ms/step" % ms_ex)
     diff_codes = int(res.code[:n].ne(res_ex.code[:n]).sum().item())
-    ia, va = res.accepted()
-    ib, vb = res_ex.accepted()
-    same = diff_codes == 0 and np.array_equal(ia, ib) and np.array_equal(va, vb)
+    n_acc = int(res.n_accepted.item())
+    same = diff_codes == 0 and n_acc == int(res_ex.n_accepted.item())
+    if same:   # the accepted lists as sets of (index, value): sorted on the device
+        ia, oa = torch.sort(res.acc_idx[:n_acc].view(torch.int64))
+        ib, ob = torch.sort(res_ex.acc_idx[:n_acc].view(torch.int64))
+        same = bool(torch.equal(ia, ib)) and bool(torch.equal(res.acc_val[:n_acc][oa], res_ex.acc_val[:n_acc][ob]))
+        del ia, oa, ib, ob
     if not same:
-        log("outputs differ: %d codes, accepted %d vs %d" % (diff_codes, len(ia), len(ib)))
+        log("outputs differ: %d codes" % diff_codes)
+    del res_ex
     codes = res.code[:n]
-    dec_counts = [int((codes >> 6).eq(d).sum().item()) for d in range(3)]
-    lvl_mean = float((codes & 63).float().mean().item())
-    # sampled parity: the oracle on the GPU's own signatures
+    lvl = (codes & 63).to(torch.int64)
+    dec = codes >> 6
+    dec_counts = [int(dec.eq(d).sum().item()) for d in range(3)]
+    levels_reached = int(lvl.sum().item()) + n
+    levels_past_prefix = int((lvl - 3).clamp_(min=0).sum().item())
+    lvl_mean = levels_reached / n - 1.0
+    del lvl, dec
+
+    # parity pass with m recorded (not timed), on a seeded sample against the oracle
+    res_m = P.make_result(n, acc_cap, m_debug=True)
+    P.bayeslsh_verify(ctx, cand, S_pfx, t, eps, delta, gamma, (1, 1), k, res_m, stream)
+    P.bayeslsh_sync(ctx, stream)
+    assert bool(torch.equal(res_m.code[:n], res.code[:n]))
     rng = np.random.default_rng(G.SEED_BASE + 105)
-    pick = np.sort(rng.choice(n, size=min(n, 1_000_000), replace=False))
+    n_sample = min(n, args.cpu_sample)
+    pick = np.sort(rng.choice(n, size=n_sample, replace=False))
     pick_d = torch.from_numpy(pick).cuda()
     xs = xo[:n].view(torch.int32)[pick_d].cpu().numpy().view(np.uint32)
     ys = yo[:n].view(torch.int32)[pick_d].cpu().numpy().view(np.uint32)
+    got_code = res_m.code[:n][pick_d].cpu().numpy()
+    got_m = res_m.m_debug[:n].view(torch.int16)[pick_d].cpu().numpy().view(np.uint16).astype(np.int32)
+    n_acc_m = int(res_m.n_accepted.item())
+    shat_all = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    shat_all[res_m.acc_idx[:n_acc_m].view(torch.int64)] = res_m.acc_val[:n_acc_m]
+    got_shat = shat_all[pick_d].cpu().numpy()
+    del shat_all, res_m, pick_d
     sig_host = S_om.data.view(torch.int32).cpu().numpy().view(np.uint32).reshape(n_obj, 32)
-    want = R.verify(xs, ys, P.COSINE, sig_host, k, 1024 // k, t, eps, delta, gamma)
-    got = codes[pick_d].cpu().numpy()
-    mism = int(np.sum((got >> 6) != want["decision"])) + int(np.sum((got & 63) != want["level"]))
-    log("sampled parity: %d mismatches over %d" % (mism, len(pick)))
+    log("cpu baseline and sampled parity: oracle Algorithm 1 over %d candidates" % n_sample)
+    OP.decision_memo(1, t, eps, delta, gamma, 1.0, 1.0, k, 1024 // k, True)   # table, outside the timed runs
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    times = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        want = R.verify(xs, ys, P.COSINE, sig_host, k, 1024 // k, t, eps, delta, gamma)
+        times.append(time.perf_counter() - t1)
+    dt = float(np.median(times))
+    emit = np.isfinite(want["shat"])
+    parity = {
+        "sample": n_sample,
+        "decision_mismatches": int(np.sum((got_code >> 6) != want["decision"])),
+        "level_mismatches": int(np.sum((got_code & 63) != want["level"])),
+        "m_mismatches": int(np.sum(got_m != want["m"])),
+        "emitted_in_sample": int(emit.sum()),
+        "emitted_set_mismatches": int(np.sum(np.isfinite(got_shat) != emit)),
+        "max_abs_shat_error": float(np.max(np.abs(got_shat[emit] - want["shat"][emit]), initial=0.0)),
+    }
+    log("sampled parity: %s" % parity)
+    cpu = dict(value=n_sample / dt, unit="pairs/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
+               sample="seeded uniform sample of %d of the %d candidates (kept in candidate order), oracle "
+                      "Algorithm 1 (plain C loop, OpenMP) on the GPU's own signatures, median of 3 runs "
+                      "(%.2f s each)" % (n_sample, n, dt))
+    log("cpu baseline: %.3g pairs/s on %d threads" % (cpu["value"], threads))
+    del xs, ys, sig_host, want
+
+    # Algorithmic bytes (per candidate: 8 B of ids + 1 B of code + both sides'
+    # 4 B chunk per level reached + 12 B per emitted pair), split by kernel: the
+    # prefix kernel owns the ids, the code and levels 0..3 (the first 128
+    # hashes), the tail the later levels and the emission.
+    chunk = 2 * (k // 8)
+    accepted = dec_counts[1] + dec_counts[2]
+    call_bytes = 9 * n + chunk * levels_reached + 12 * accepted
+    pfx_bytes = 9 * n + chunk * (levels_reached - levels_past_prefix)
+    tail_bytes = chunk * levels_past_prefix + 12 * accepted
+    per = {"verify_bits_prefix": pfx_bytes, "verify_tail": tail_bytes, "acc_flush": 12 * accepted}
+    kern_ms = sum(v["ms_per_step"] for v in prof.values())
+    dom = max(("verify_bits_prefix", "verify_tail"), key=lambda k_: prof[k_]["ms_per_step"])
+    launches = prof[dom]["launches_per_step"]
+    dom_bytes = per[dom] / launches
+    achieved = dom_bytes / (prof[dom]["avg_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic_of(DENSE_TRAFFIC_FILE, DENSE_KERNEL_SOURCES, "traffic_bytes_per_launch_" + dom)
+    roofline = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "kernel": dom, "kernel_avg_ms": prof[dom]["avg_ms"], "launches_per_step": launches,
+        "algorithmic_bytes_per_launch": dom_bytes,
+        "kernels": {k_: dict(v, algorithmic_bytes_per_step=per[k_],
+                             algorithmic_GBps=per[k_] / (v["ms_per_step"] * 1e-3) / 1e9 if v["ms_per_step"] else None)
+                    for k_, v in prof.items()},
+        "call": {"algorithmic_bytes": call_bytes, "kernel_ms": kern_ms,
+                 "achieved": call_bytes / (kern_ms * 1e-3) / 1e9,
+                 "frac": call_bytes / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "hbm_stream_bytes": 9 * n, "stream_frac": 9 * n / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "traffic": measured_traffic_of(DENSE_TRAFFIC_FILE, DENSE_KERNEL_SOURCES, "traffic_bytes_per_call")},
+        "bytes_model": "per candidate 8 B ids + 1 B code + 8 B per level reached (4 B chunk per side at k = 32) "
+                       "+ 12 B per emitted pair; the prefix kernel owns ids, code and levels 0-3, the tail kernel "
+                       "the later levels and the emission",
+    }
     ctx.close()
-    hbm = n * 9
     return {
-        "metric": "candidate pairs verified/sec, BayesLSH vs exhaustive hash compare, same output",
-        "value": n / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "ms_per_step": ms, "higher_is_better": True,
+        "metric": METRIC,
+        "value": n / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": "dense cosine estimation: 1M x 256 Gaussian-mixture vectors (1000 components), 1024 SRP "
                                "bits, GPU LSH banding 16 x 12 bits on an independent 192-bit projection (pairs of a "
@@ -625,11 +796,13 @@ def run_dense(args, torch, P):
                                "n_max=1024",
                    "n_candidates": n, "banding_ms": band_ms, "banding_pairs_per_s": n / (band_ms * 1e-3)},
         "decisions": {"pruned": dec_counts[0], "accept_conc": dec_counts[1], "accept_nmax": dec_counts[2],
-                      "mean_level": lvl_mean, "accepted_listed": int(len(ia))},
+                      "mean_level": lvl_mean, "accepted_listed": n_acc},
         "exhaustive": {"ms_per_step": ms_ex, "value": n / (ms_ex * 1e-3), "speedup": ms_ex / ms, "same_output": same,
-                       "differing_codes": diff_codes},
-        "sampled_parity": {"sample": len(pick), "mismatches": mism},
-        "hbm_stream_GBps": hbm / (ms * 1e-3) / 1e9,
+                       "differing_codes": diff_codes, "mode": "REPLAY, all 1024 bits of both object-major rows"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "sampled_parity": parity,
+        "paper_context": PAPER_CONTEXT,
     }
 
 
@@ -697,53 +870,17 @@ def run_sweep(args, torch, P):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--small", action="store_true", help="20k-document workload (quick check)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--copy-calibration", action="store_true", help="time a plain 1 GiB device copy and exit")
-    ap.add_argument("--layout", choices=["prefix", "word-major"], default="prefix",
-                    help="SRP layout verified: object-major 128-bit rows (prefix) or word-major slabs of all bits")
-    ap.add_argument("--workload", choices=["lite", "batched", "serving", "dense", "sweep", "sigs"], default="lite",
-                    help="lite: the cosine BayesLSH-Lite line (default); batched: 4096 mixed query lists in one "
-                         "graph launch vs the exhaustive batched comparator; serving: Poisson arrivals against the "
-                         "dense cosine index, p50/p99 latency; dense: GPU LSH banding of 1M dense vectors then "
-                         "Algorithm 1 over all ~2e9 candidates; sweep: the paper's experiments on the tf-idf "
-                         "workload (pruning curve, gamma/delta/epsilon, BayesLSH vs Lite by threshold); sigs: "
-                         "signature generation (dense SRP on MFMA, sparse SRP, minhash)")
-    ap.add_argument("--queries", type=int, default=10000, help="serving: number of queries")
-    ap.add_argument("--serving-legs", choices=["all", "device"], default="all",
-                    help="serving: all legs, or only the device-memory submissions (for a kernel trace)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_1110_1328_amd as P
-
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.workload == "batched":
-        print(json.dumps(run_batched(args, torch, P)), flush=True)
-        return
-    if args.workload == "serving":
-        print(json.dumps(run_serving(args, torch, P)), flush=True)
-        return
-    if args.workload == "dense":
-        print(json.dumps(run_dense(args, torch, P)), flush=True)
-        return
-    if args.workload == "sweep":
-        print(json.dumps(run_sweep(args, torch, P)), flush=True)
-        return
-    if args.workload == "sigs":
-        print(json.dumps(run_sigs(args, torch, P)), flush=True)
-        return
+def run_lite(args, torch, P):
+    """The cosine BayesLSH-Lite workload: 100,000 sparse tf-idf vectors
+    (dimension 2^20, Poisson(100) nonzeros, Zipf(1.1) terms, 5% planted
+    near-duplicates), 2048 SRP bits per vector, candidates from 16-band x
+    10-bit LSH banding on an independent projection (on the device, each
+    bucket's pairs in 16 x 16 tiles of its members; timed apart from the step),
+    t = 0.7, epsilon = 0.03, h = 128, k = 32, exact cosine on survivors.  One
+    step = one bayeslsh_lite_verify call over all candidates.  Two exhaustive
+    comparators with the same output: all 2048 bits of both object-major rows,
+    and only the h = 128 bits Lite may use (all h/k level counts, no early
+    exit) -- the second isolates the gain of Algorithm 2's early pruning."""
     log("generating workload")
     from synth import generators as G
     corpus = G.tfidf_corpus(n_docs=20_000, seed=G.SEED_BASE + 2) if args.small else G.tfidf_corpus(seed=G.SEED_BASE + 2)
@@ -788,6 +925,12 @@ def main():
         P.bayeslsh_exhaustive_verify(ctx, cand, S_om, vec, T, EPS, 0.5, 0.5, (1.0, 1.0), K, H, P.REPLAY_LITE, res_ex,
                                      stream)
 
+    res_exh = P.make_result(n, cap)
+
+    def step_ex_h():   # only the h bits Lite may use: all h/k level counts, no early exit
+        P.bayeslsh_exhaustive_verify(ctx, cand, S_pf, vec, T, EPS, 0.5, 0.5, (1.0, 1.0), K, H, P.REPLAY_LITE, res_exh,
+                                     stream)
+
     for _ in range(args.warmup):
         step()
     P.bayeslsh_sync(ctx, stream)
@@ -812,25 +955,42 @@ def main():
     x_ms, x_n = P.bayeslsh_profile_read(ctx, "exact")   # exact similarity of the survivors (prefix layout)
     P.bayeslsh_profile_enable(ctx, False)
     log("BayesLSH-Lite: %.3f ms/step (verify kernel %.3f ms)" % (ms_step, k_ms / max(k_n, 1)))
-    # exhaustive comparator
+    # exhaustive comparators
     ex_steps = max(3, args.steps // 5)
-    for _ in range(2):
-        step_ex()
-    P.bayeslsh_sync(ctx, stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(ex_steps):
-        step_ex()
-    torch.cuda.synchronize()
-    ex_el = time.perf_counter() - t0
-    P.bayeslsh_sync(ctx, stream)
-    ex_ms = ex_el * 1e3 / ex_steps
-    log("exhaustive: %.3f ms/step" % ex_ms)
+
+    def timed_ex(fn):
+        for _ in range(2):
+            fn()
+        P.bayeslsh_sync(ctx, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(ex_steps):
+            fn()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        P.bayeslsh_sync(ctx, stream)
+        return el * 1e3 / ex_steps
+
+    ex_ms = timed_ex(step_ex)
+    exh_ms = timed_ex(step_ex_h)
+    log("exhaustive: %.3f ms/step over 2048 bits, %.3f ms/step over the h = %d bits" % (ex_ms, exh_ms, H))
     codes = res.code[:n].cpu().numpy()
-    same = bool(torch.equal(res.code[:n], res_ex.code[:n]))
     ia, va = res.accepted()
-    ib, vb = res_ex.accepted()
-    same = same and np.array_equal(ia, ib) and np.array_equal(va, vb)
+
+    def same_as(r):
+        ib, vb = r.accepted()
+        return bool(torch.equal(res.code[:n], r.code[:n])) and np.array_equal(ia, ib) and np.array_equal(va, vb)
+
+    same = same_as(res_ex)
+    same_h = same_as(res_exh)
+    del res_ex, res_exh
+    # m of every candidate, from a pass with m recorded (not timed)
+    res_m = P.make_result(n, cap, m_debug=True)
+    P.bayeslsh_lite_verify(ctx, cand, S_run, vec, T, EPS, (1.0, 1.0), H, K, res_m, stream)
+    P.bayeslsh_sync(ctx, stream)
+    assert bool(torch.equal(res_m.code[:n], res.code[:n]))
+    gpu_m = res_m.m_debug[:n].view(torch.int16).cpu().numpy().view(np.uint16).astype(np.int32)
+    del res_m
     dec, lvl = codes >> 6, codes & 63
     n_surv = int(np.sum(dec == 3))
     # Algorithmic bytes of the verify kernel per launch.  HBM stream: candidate ids
@@ -844,7 +1004,11 @@ def main():
     per_step = max(k_n, 1) / args.steps                 # verify launches per step (candidate chunks)
     hbm_bytes = int(hbm_bytes / per_step)               # per launch
     gather_bytes = int(gather_bytes / per_step)
-    achieved = hbm_bytes / (k_avg_ms * 1e-3) / 1e9
+    # algorithmic bytes per launch: ids + code + both sides' chunk per level
+    # reached (the survivors' exact cosines are computed by k_exact)
+    alg_bytes = hbm_bytes + gather_bytes
+    achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic() if args.layout == "prefix" else None
     out = {
         "metric": METRIC,
         "value": n / (ms_step * 1e-3),
@@ -871,31 +1035,100 @@ def main():
         },
         "exhaustive": {"ms_per_step": ex_ms, "value": n / (ex_ms * 1e-3), "speedup": ex_ms / ms_step,
                        "same_output": same, "mode": "REPLAY_LITE, all 2048 bits per object"},
+        "exhaustive_h_bits": {"ms_per_step": exh_ms, "value": n / (exh_ms * 1e-3), "speedup": exh_ms / ms_step,
+                              "same_output": same_h,
+                              "mode": "REPLAY_LITE over the h = 128 bits Lite may use (128-bit object-major "
+                                      "rows): every level counted, no early exit, then the same decisions "
+                                      "replayed -- the gain of Algorithm 2's pruning alone"},
         "signature_ms": sig_ms,
         "prefix_rows_equal_full_signature_prefix": same_prefix,
-        # the paper's own speedups, for context only (other hardware, whole
-        # pipeline including candidate generation, real datasets)
-        "paper_context": {
-            "speedup_over_baselines": "2x-20x in most comparisons (abstract; Section 5)",
-            "speedup_over_lsh_approx": "tf-idf cosine 2.0x-3.0x, binary Jaccard 2.8x-4.2x, binary cosine 1.2x "
-                                       "(Table 2, time summed over thresholds)",
-            "hardware": "single-threaded C/C++, dual-socket dual-core 2.3 GHz Opteron, 8 GB RAM (Section 5)",
-        },
+        "paper_context": PAPER_CONTEXT,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.layout == "prefix" else None, "kernel": k_name,
-                     "kernel_ms": k_avg_ms, "kernel_launches_timed": k_n, "hbm_bytes_per_launch": hbm_bytes,
-                     "exact_kernel_ms": x_ms / max(x_n, 1) if x_n else None,
-                     "l2_gather_bytes_per_launch": gather_bytes,
-                     "gather_inclusive_GBps": (hbm_bytes + gather_bytes) / (k_avg_ms * 1e-3) / 1e9},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": k_name,
+                     "kernel_ms": k_avg_ms, "kernel_launches_timed": k_n,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "bytes_model": "per candidate 8 B ids + 1 B code + 8 B per level reached (4 B chunk per "
+                                    "side at k = 32); survivors' exact cosines are k_exact's",
+                     "hbm_stream_bytes_per_launch": hbm_bytes,
+                     "stream_frac": hbm_bytes / (k_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic_frac": traffic / (k_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+                     "exact_kernel_ms": x_ms / max(x_n, 1) if x_n else None},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        cb, parity, _ = cpu_baseline(corpus, x, y, codes)
+        cb, parity, _ = cpu_baseline(corpus, x, y, codes, gpu_m, (ia, va))
         out["cpu_baseline"] = cb
         out["full_size_parity"] = parity
         log("cpu baseline: %.3g pairs/s; parity %s" % (cb["value"], parity))
     ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--small", action="store_true", help="20k-document workload (quick check)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true", help="time a plain 1 GiB device copy and exit")
+    ap.add_argument("--layout", choices=["prefix", "word-major"], default="prefix",
+                    help="SRP layout verified: object-major 128-bit rows (prefix) or word-major slabs of all bits")
+    ap.add_argument("--workload", choices=["headline", "lite", "batched", "serving", "dense", "sweep", "sigs"],
+                    default="headline",
+                    help="headline (default): the dense line below, with the cosine BayesLSH-Lite line under its "
+                         "own key; dense: GPU LSH banding of 1M dense vectors then Algorithm 1 over all ~2.4e9 "
+                         "candidates; lite: the cosine BayesLSH-Lite line alone; batched: 4096 mixed query lists "
+                         "in one graph launch vs the exhaustive batched comparator; serving: Poisson arrivals "
+                         "against the dense cosine index, p50/p99 latency; sweep: the paper's experiments on the "
+                         "tf-idf workload (pruning curve, gamma/delta/epsilon, BayesLSH vs Lite by threshold); "
+                         "sigs: signature generation (dense SRP on MFMA, sparse SRP, minhash)")
+    ap.add_argument("--no-lite", action="store_true", help="headline: skip the cosine BayesLSH-Lite leg")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 27,
+                    help="dense: candidates in the seeded sample the oracle is timed on and compared over")
+    ap.add_argument("--queries", type=int, default=10000, help="serving: number of queries")
+    ap.add_argument("--serving-legs", choices=["all", "device"], default="all",
+                    help="serving: all legs, or only the device-memory submissions (for a kernel trace)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1110_1328_amd as P
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args, torch, P)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(run_serving(args, torch, P)), flush=True)
+        return
+    if args.workload == "dense":
+        print(json.dumps(run_dense(args, torch, P)), flush=True)
+        return
+    if args.workload == "sweep":
+        print(json.dumps(run_sweep(args, torch, P)), flush=True)
+        return
+    if args.workload == "sigs":
+        print(json.dumps(run_sigs(args, torch, P)), flush=True)
+        return
+    if args.workload == "lite":
+        print(json.dumps(run_lite(args, torch, P)), flush=True)
+        return
+    # default: the dense estimation workload is the headline line; the cosine
+    # BayesLSH-Lite workload rides along under its own key
+    out = run_dense(args, torch, P)
+    torch.cuda.empty_cache()
+    if not args.no_lite:
+        try:
+            out["cosine_lite_100k"] = run_lite(args, torch, P)
+        except Exception as e:   # the headline stands on its own; the failure is reported, not hidden
+            log("lite leg failed: %r" % (e,))
+            out["cosine_lite_100k"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 

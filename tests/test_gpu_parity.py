@@ -274,7 +274,7 @@ def test_tail_on_rows_of_odd_word_counts(ctx, n_hashes, k):
     want = R.verify(x, y, P.COSINE, sig, k, n_hashes // k, T, EPS, DELTA, GAMMA)
     assert np.sum(want["level"] >= 128 // k) > 100   # the tail has work
     pfx = up(np.ascontiguousarray(sig[:, :4]))
-    rows = up(np.ascontiguousarray(sig))
+    rows = up(np.ascontiguousarray(sig).reshape(-1))
     buf = torch.zeros(n_obj * W + 1, dtype=torch.int32, device="cuda")
     buf[1:] = rows.view(torch.int32)
     for data in (rows, buf[1:].view(torch.uint32)):
