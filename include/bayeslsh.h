@@ -289,6 +289,26 @@ int bayeslsh_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs 
                     double epsilon, double delta, double gamma, blsh_prior prior, int32_t k,
                     blsh_result *res, void *stream);
 
+/* Algorithm 1 as bayeslsh_verify (same arguments, constraints and output),
+ * for callers that cannot allocate device memory while they call: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * The call allocates nothing (no hipMalloc or hipFree, no allocating library
+ * routine): every buffer beyond the caller's inputs and outputs -- the slice
+ * counters, the decision-table image, the survivor queue and the accepted-pair
+ * staging -- lives in a fixed device array of the library, 16.7 MiB, one per
+ * GPU (held until the process ends), sized for one launch of 2^20 candidates;
+ * a longer call runs as several launches, so no input size exceeds it.  The
+ * array keeps the last call's contents; a call clears what it relies on, on
+ * `stream`, before its first launch.  Calls that overlap on one GPU -- from
+ * any context or stream -- share the array and race: the caller serialises
+ * them.  A parameter set seen for the first time has its table built on the
+ * host (host memory only) and its image copied into the array on `stream`.
+ * Errors: as bayeslsh_verify; BLSH_EINVAL for a context on a device numbered
+ * 64 or above (no scratch array is kept there). */
+int bayeslsh_verify_noalloc(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, double t,
+                            double epsilon, double delta, double gamma, blsh_prior prior, int32_t k,
+                            blsh_result *res, void *stream);
+
 /* Algorithm 2 (BayesLSH-Lite).  Prune as above using at most h hashes
  * (h % k == 0, h <= n_max); survivors get their exact similarity from `exact`
  * (cosine: DENSE or CSR, sums in FP64; Jaccard: SETS) and are emitted iff

@@ -90,6 +90,9 @@ PROTOTYPES = [
     ("bayeslsh_verify", C.c_int,
      [p, C.POINTER(Candidates), C.POINTER(Sigs), C.c_double, C.c_double, C.c_double, C.c_double, Prior, C.c_int32,
       C.POINTER(Result), p]),
+    ("bayeslsh_verify_noalloc", C.c_int,
+     [p, C.POINTER(Candidates), C.POINTER(Sigs), C.c_double, C.c_double, C.c_double, C.c_double, Prior, C.c_int32,
+      C.POINTER(Result), p]),
     ("bayeslsh_lite_verify", C.c_int,
      [p, C.POINTER(Candidates), C.POINTER(Sigs), C.POINTER(Vectors), C.c_double, C.c_double, Prior, C.c_int32,
       C.c_int32, C.POINTER(Result), p]),

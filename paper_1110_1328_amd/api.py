@@ -417,6 +417,17 @@ def bayeslsh_verify(ctx: Context, cand: Candidates, sigs: Signatures, t, epsilon
     return res
 
 
+def bayeslsh_verify_noalloc(ctx: Context, cand: Candidates, sigs: Signatures, t, epsilon, delta, gamma,
+                            prior=(1.0, 1.0), k=32, res: Result = None, stream=None):
+    """bayeslsh_verify without device allocation inside the call (its scratch is
+    the library's fixed per-GPU array); same output."""
+    _check_result_size(res, cand)
+    cs, ss, rs = cand.struct(), sigs.struct(), res.struct()
+    _check(_lib().bayeslsh_verify_noalloc(ctx.handle, C.byref(cs), C.byref(ss), t, epsilon, delta, gamma,
+                                          _prior(prior), k, C.byref(rs), _stream(stream)))
+    return res
+
+
 def bayeslsh_lite_verify(ctx: Context, cand: Candidates, sigs: Signatures, exact: Vectors, t, epsilon,
                          prior=(1.0, 1.0), h=128, k=32, res: Result = None, stream=None):
     _check_result_size(res, cand)

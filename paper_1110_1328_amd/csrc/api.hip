@@ -71,24 +71,27 @@ int get_table(blsh_ctx *ctx, const TableKey &key, std::shared_ptr<HostTable> *ho
   } else {
     ht = it->second;
   }
+  if (ht->image.empty()) {   // the device image of the table, kept with it
+    std::vector<uint32_t> &img = ht->image;
+    img.assign(kTabAccOff + size_t(ht->n_levels) * ht->words, 0u);
+    img[0] = uint32_t(ht->k);
+    img[1] = uint32_t(ht->n_levels);
+    img[2] = uint32_t(ht->words);
+    img[3] = uint32_t(key.measure);
+    std::memcpy(&img[4], &key.alpha, 8);
+    std::memcpy(&img[6], &key.beta, 8);
+    std::memcpy(&img[8], &key.t, 8);
+    for (int j = 0; j < ht->n_levels; ++j) img[kTabMinOff + j] = uint32_t(ht->min_matches[j]);
+    std::memcpy(&img[kTabAccOff], ht->accept.data(), ht->accept.size() * 4);
+  }
   if (host) *host = ht;
   if (dev) {
     auto dt = ctx->dev_tables.find(key);
     if (dt == ctx->dev_tables.end()) {
-      std::vector<uint32_t> img(kTabAccOff + size_t(ht->n_levels) * ht->words, 0u);
-      img[0] = uint32_t(ht->k);
-      img[1] = uint32_t(ht->n_levels);
-      img[2] = uint32_t(ht->words);
-      img[3] = uint32_t(key.measure);
-      std::memcpy(&img[4], &key.alpha, 8);
-      std::memcpy(&img[6], &key.beta, 8);
-      std::memcpy(&img[8], &key.t, 8);
-      for (int j = 0; j < ht->n_levels; ++j) img[kTabMinOff + j] = uint32_t(ht->min_matches[j]);
-      std::memcpy(&img[kTabAccOff], ht->accept.data(), ht->accept.size() * 4);
       DevTable d;
-      d.words = img.size();
+      d.words = ht->image.size();
       BLSH_HIP(hipMalloc(&d.ptr, d.words * 4));
-      BLSH_HIP(hipMemcpy(d.ptr, img.data(), d.words * 4, hipMemcpyHostToDevice));
+      BLSH_HIP(hipMemcpy(d.ptr, ht->image.data(), d.words * 4, hipMemcpyHostToDevice));
       dt = ctx->dev_tables.emplace(key, d).first;
     }
     *dev = dt->second.ptr;
@@ -274,6 +277,72 @@ static int get_workspace(blsh_ctx *ctx, int64_t chunk, bool queue, bool with_m, 
   return BLSH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point (bayeslsh_verify_noalloc): one
+// fixed array per GPU for everything one launch of at most kNaChunk
+// candidates needs beyond the caller's inputs and outputs -- the slice
+// counters, the decision-table image, the survivor queue (index and m | level
+// per entry) and the accepted-pair staging.  A longer call runs as several
+// such launches.  Every call on a GPU uses that GPU's copy and leaves its
+// contents behind; a call clears the counters it relies on before its first
+// launch, so calls that overlap on one GPU race.
+//
+// In host code `scratch` is a host-side stand-in, not a device address:
+// bayeslsh_create looks up each device's address once (hipGetSymbolAddress,
+// that device current) and every use goes through that pointer.
+// ---------------------------------------------------------------------------
+static constexpr size_t align256c(size_t b) { return (b + 255) & ~size_t(255); }
+static constexpr int64_t kNaChunk = int64_t(1) << 20;
+static constexpr int64_t kNaQueueCap = (kNaChunk + 1024 + kSlices - 1) / kSlices + 256;
+static constexpr int64_t kNaStageCap = (kNaChunk + kSlices - 1) / kSlices;
+static constexpr size_t kNaCntBytes = align256c(kSliceBufWords * sizeof(int64_t));
+static constexpr size_t kNaTabBytes = size_t(40) << 10;   // tables of up to 64 levels of 4096 hashes: 33 KB
+static constexpr size_t kNaQBytes = align256c(size_t(kSlices) * kNaQueueCap * 4);
+static constexpr size_t kNaStBytes = align256c(size_t(kSlices) * kNaStageCap * 4);
+static constexpr size_t kScratchBytes = kNaCntBytes + kNaTabBytes + 2 * kNaQBytes + 2 * kNaStBytes;
+static_assert(kScratchBytes <= (size_t(24) << 20), "scratch stays modest");
+static_assert((kTabAccOff + size_t(kMaxLevels) * ((64 * kMaxLevels + 1 + 31) / 32)) * 4 <= kNaTabBytes,
+              "the largest table image fits its region");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kScratchDevices];
+
+// Address of this file's scratch array on `device` (which must be current);
+// looked up once per device.
+static int scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) return BLSH_OK;   // the allocation-free entry point refuses it
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch[device]) return BLSH_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(BLSH_EDEVICE, "scratch address lookup on device %d failed: %s", device, hipGetErrorString(e));
+  g_scratch[device] = ptr;
+  return BLSH_OK;
+}
+
+// The workspace of one launch, carved from the device's scratch array.
+static int scratch_workspace(blsh_ctx *ctx, Workspace *w, uint32_t **table) {
+  void *base = ctx->device >= 0 && ctx->device < kScratchDevices ? g_scratch[ctx->device] : nullptr;
+  if (!base) return fail(BLSH_EDEVICE, "no scratch array on device %d", ctx->device);
+  char *p = static_cast<char *>(base);
+  w->cnt = reinterpret_cast<int64_t *>(p);
+  p += kNaCntBytes;
+  *table = reinterpret_cast<uint32_t *>(p);
+  p += kNaTabBytes;
+  w->q_rel = reinterpret_cast<uint32_t *>(p);
+  w->q_m = reinterpret_cast<uint32_t *>(p + kNaQBytes);
+  w->q_cap = kNaQueueCap;
+  p += 2 * kNaQBytes;
+  w->st_rel = reinterpret_cast<uint32_t *>(p);
+  w->st_val = reinterpret_cast<float *>(p + kNaStBytes);
+  w->st_cap = kNaStageCap;
+  return BLSH_OK;
+}
+
 static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
   a.ex_kind = v->kind;
   a.ex_dense = v->dense;
@@ -284,9 +353,13 @@ static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
 }
 
 // Shared driver of verify / lite / exhaustive.
+// noalloc: Algorithm 1 only; every buffer beyond the caller's comes from the
+// device's scratch array (launches of at most kNaChunk candidates), the table
+// image is copied into it, and nothing is allocated.
 static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, const blsh_vectors *exact,
                       double t, double eps, double delta, double gamma, blsh_prior prior, int k, int h,
-                      int exhaustive_mode /* -1: early-exit path */, blsh_result *res, void *stream) {
+                      int exhaustive_mode /* -1: early-exit path */, blsh_result *res, void *stream,
+                      bool noalloc = false) {
   if (!ctx) return fail(BLSH_EINVAL, "null context");
   const bool lite = exhaustive_mode == -1 ? (exact != nullptr) : exhaustive_mode == BLSH_REPLAY_LITE;
   const bool tab_lite = lite || exhaustive_mode == BLSH_MLE;  // no concentration bits needed
@@ -317,7 +390,19 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   TableKey key{int(sigs->measure), t, eps, tab_lite ? 0.0 : delta, tab_lite ? 0.0 : gamma, prior.alpha, prior.beta, k,
                n_levels, tab_lite ? 1 : 0};
   const uint32_t *dtab = nullptr;
-  if ((rc = get_table(ctx, key, nullptr, &dtab, s))) return rc;
+  Workspace w{};
+  uint32_t *na_table = nullptr;
+  std::shared_ptr<HostTable> na_host;
+  if (noalloc) {
+    if ((rc = scratch_workspace(ctx, &w, &na_table))) return rc;
+    if ((rc = get_table(ctx, key, &na_host, nullptr, s))) return rc;
+    if (na_host->image.size() * 4 > kNaTabBytes)
+      return fail(BLSH_EINVAL, "table of %zu bytes exceeds the %zu-byte scratch region", na_host->image.size() * 4,
+                  kNaTabBytes);
+    dtab = na_table;
+  } else if ((rc = get_table(ctx, key, nullptr, &dtab, s))) {
+    return rc;
+  }
 
   VerifyArgs a{};
   fill_cand(a, cand);
@@ -359,9 +444,15 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   const bool queued = (lite && !fused_exact) || tail;
   // launches are chunked so that no grid exceeds 2^32 work-items (the
   // dispatch's grid size): the comparator runs up to 64 lanes per candidate
-  const int64_t chunk = std::min<int64_t>(n_cand, exh ? kExhChunk : kChunk);
-  Workspace w{};
-  if ((rc = get_workspace(ctx, chunk, queued, tail, &w))) return rc;
+  const int64_t chunk = std::min<int64_t>(n_cand, noalloc ? kNaChunk : exh ? kExhChunk : kChunk);
+  if (noalloc) {
+    // the table image, then every counter of the single-call paths cleared
+    // (the array keeps whatever the last call on this GPU left there)
+    BLSH_HIP(hipMemcpyAsync(na_table, na_host->image.data(), na_host->image.size() * 4, hipMemcpyHostToDevice, s));
+    if ((rc = launch_zero_slices(ctx, w.cnt, s))) return fail(rc, "launch failed");
+  } else if ((rc = get_workspace(ctx, chunk, queued, tail, &w))) {
+    return rc;
+  }
   a.q_rel = w.q_rel;
   a.q_m = w.q_m;
   a.q_cnt = w.cnt + size_t(2) * kSlices * kCntStride;
@@ -371,29 +462,32 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   a.st_cap = w.st_cap;
   if (lite) fill_exact(a, exact);
   // the counters of the next set are zero unless an earlier call stopped
-  // before its last flush
-  if (ctx->slices_dirty) {
+  // before its last flush (the allocation-free path cleared its own above and
+  // starts from set 0)
+  if (!noalloc && ctx->slices_dirty) {
     if ((rc = launch_zero_slices(ctx, w.cnt, s))) return fail(rc, "launch failed");
     ctx->slices_dirty = false;
   }
-  auto set_cnt = [&](int set) { return w.cnt + size_t(set) * kSlices * kCntStride; };
-  auto set_total = [&](int set) { return w.cnt + (size_t(3) * kSlices + set) * kCntStride; };
+  int na_set = 0;
+  int &set = noalloc ? na_set : ctx->slice_set;
+  auto set_cnt = [&](int st) { return w.cnt + size_t(st) * kSlices * kCntStride; };
+  auto set_total = [&](int st) { return w.cnt + (size_t(3) * kSlices + st) * kCntStride; };
   for (int64_t c0 = 0; c0 < n_cand; c0 += chunk) {
     a.c_begin = c0;
     a.c_end = std::min(n_cand, c0 + chunk);
-    const int cur = ctx->slice_set, nxt = cur ^ 1;
+    const int cur = set, nxt = cur ^ 1;
     a.acc_cnt = set_cnt(cur);
     a.acc_total = set_total(cur);
     const bool wm = sigs->measure == BLSH_COSINE && sigs->layout == BLSH_WORD_MAJOR;
-    ctx->slices_dirty = true;
+    if (!noalloc) ctx->slices_dirty = true;
     rc = exh ? launch_exhaustive(ctx, a, k, s) : launch_verify(ctx, a, k, lite, wm, s);
     if (!rc && tail) rc = launch_verify_tail(ctx, a, k, wm, (n_levels * k + 1 + 31) / 32, s);
     if (!rc && queued && !tail) rc = launch_exact(ctx, a, a.c_end - a.c_begin, s);
     if (!rc) rc = launch_acc_flush(ctx, a, set_cnt(nxt), set_total(nxt), a.c_end == n_cand, s);
     if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;
-    ctx->slice_set = nxt;
+    set = nxt;
   }
-  ctx->slices_dirty = false;
+  if (!noalloc) ctx->slices_dirty = false;
   return BLSH_OK;
 }
 
@@ -413,6 +507,7 @@ int bayeslsh_create(blsh_ctx **out, int device) {
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(BLSH_EDEVICE, "no HIP device");
   if (device < 0 || device >= n) return fail(BLSH_EINVAL, "device %d out of range", device);
   BLSH_HIP(hipSetDevice(device));
+  if (int rc = scratch_init(device)) return rc;
   auto *c = new (std::nothrow) blsh_ctx();
   if (!c) return fail(BLSH_ENOMEM, "host allocation failed");
   c->device = device;
@@ -594,6 +689,15 @@ int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *plan
 int bayeslsh_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, double t, double epsilon,
                     double delta, double gamma, blsh_prior prior, int32_t k, blsh_result *res, void *stream) {
   return run_verify(ctx, cand, sigs, nullptr, t, epsilon, delta, gamma, prior, k, 0, -1, res, stream);
+}
+
+int bayeslsh_verify_noalloc(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, double t,
+                            double epsilon, double delta, double gamma, blsh_prior prior, int32_t k,
+                            blsh_result *res, void *stream) {
+  if (ctx && (ctx->device < 0 || ctx->device >= kScratchDevices))
+    return fail(BLSH_EINVAL, "bayeslsh_verify_noalloc: device %d has no scratch array (devices 0..%d)", ctx->device,
+                kScratchDevices - 1);
+  return run_verify(ctx, cand, sigs, nullptr, t, epsilon, delta, gamma, prior, k, 0, -1, res, stream, true);
 }
 
 int bayeslsh_lite_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, const blsh_vectors *exact,

@@ -48,6 +48,7 @@ struct HostTable {
   // (n, m, kind: 0 prune, 1 concentration)
   double min_margin = 1.0;
   int margin_n = 0, margin_m = 0, margin_kind = 0;
+  std::vector<uint32_t> image;        // the device image (layout below), built once
 };
 
 // A table whose smallest margin is below this is refused (BLSH_EINVAL): the
