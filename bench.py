@@ -560,7 +560,8 @@ def run_sigs(args, torch, P):
 DENSE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "verify_dense_1m_traffic.txt")
 DENSE_KERNEL_SOURCES = ("paper_1110_1328_amd/csrc/verify.hip", "paper_1110_1328_amd/csrc/device_common.h")
 # the verification call's kernels, by the names their launches are profiled under
-DENSE_KERNELS = ("verify_bits_prefix", "verify_tail", "acc_flush")
+TILE_KERNELS = ("verify_tiles", "verify_rows", "acc_flush")
+PAIR_KERNELS = ("verify_bits_prefix", "verify_tail", "acc_flush")
 
 
 def cpu_model():
@@ -605,22 +606,52 @@ def measured_traffic_of(path, sources, key):
     return int(float(kv[key])) if kv.get("kernel_source_sha256") == h.hexdigest() and key in kv else None
 
 
+def timed_steps(torch, P, ctx, stream, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    P.bayeslsh_sync(ctx, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / steps
+    P.bayeslsh_sync(ctx, stream)
+    return ms
+
+
+def same_output(torch, n, ra, rb):
+    """Codes equal and accepted lists equal as sets of (index, value), on the device."""
+    diff = int(ra.code[:n].ne(rb.code[:n]).sum().item())
+    na, nb = int(ra.n_accepted.item()), int(rb.n_accepted.item())
+    same = diff == 0 and na == nb
+    if same:
+        ia, oa = torch.sort(ra.acc_idx[:na].view(torch.int64))
+        ib, ob = torch.sort(rb.acc_idx[:nb].view(torch.int64))
+        same = bool(torch.equal(ia, ib)) and bool(torch.equal(ra.acc_val[:na][oa], rb.acc_val[:nb][ob]))
+    return same, diff
+
+
 def run_dense(args, torch, P):
     """Dense cosine estimation, the largest single-GPU workload: 1M x 256
-    Gaussian-mixture vectors, 1024 SRP bits (object-major rows + the 16 B/object
-    prefix array) for verification; candidates from GPU LSH banding (16 bands x
-    12 bits of an independent 192-bit projection, each bucket's pairs listed by
-    16 x 16 tiles of its members); one step = Algorithm 1 (t = 0.8, eps = gamma =
-    0.03, delta = 0.05, k = 32, n_max = 1024) over every candidate, against the
-    exhaustive REPLAY comparator (object-major rows) with the same output.  A
-    seeded sample of the candidates is checked against the oracle on the GPU's
-    own signatures (decision, level and m exact, S_hat within 1e-6), and the
-    oracle's Algorithm 1 is timed over that sample on the host's cores."""
+    Gaussian-mixture vectors, 1024 SRP bits (object-major rows) for
+    verification; candidates from GPU LSH banding (16 bands x 12 bits of an
+    independent 192-bit projection; each bucket's pairs by 16 x 16 tiles of its
+    members, ~2.4e9 pairs).  One step = Algorithm 1 (t = 0.8, eps = gamma =
+    0.03, delta = 0.05, k = 32, n_max = 1024) over every candidate, the
+    candidates handed over as bucket tiles (bayeslsh_band_tiles); the same
+    candidates as explicit id pairs (bayeslsh_band_candidates, with the 16 B
+    prefix array) are timed beside it and must give the same output, and so
+    must the exhaustive REPLAY comparator (all 1024 bits of both object-major
+    rows).  A seeded sample of the candidates is checked against the oracle on
+    the GPU's own signatures (decision, level and m exact, S_hat within 1e-6),
+    and the oracle's Algorithm 1 is timed over that sample on the host."""
     from synth import generators as G
     from oracle import reference as R
     from oracle import posterior as OP
     t, eps, delta, gamma, k = 0.8, 0.03, 0.05, 0.03, 32
     ctx = P.bayeslsh_create(0)
+    stream = torch.cuda.current_stream()
     log("dense index (1M x 256, 1024 verification bits)")
     mix, (S_pfx,) = dense_index(torch, P, ctx, (P.OBJECT_MAJOR,), prefix=True)
     n_obj = mix.x.shape[0]
@@ -632,67 +663,68 @@ def run_dense(args, torch, P):
     P.bayeslsh_sync(ctx)
     del xd, mix
     S_band = P.Signatures(band_sig, P.COSINE, P.OBJECT_MAJOR, n_obj, 192)
+
+    # the candidates as bucket tiles (banding once to size its buffers, then timed)
+    tile_cap = 1 << 25
+    mem = torch.empty(16 * n_obj, dtype=torch.int32, device="cuda").view(torch.uint32)
+    tl = torch.empty(tile_cap * 8, dtype=torch.int64, device="cuda")
+    P.bayeslsh_band_tiles(ctx, S_band, 16, 12, tile_cap, members_out=mem, tiles_out=tl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, n_tiles, n, trunc = P.bayeslsh_band_tiles(ctx, S_band, 16, 12, tile_cap, members_out=mem, tiles_out=tl)
+    band_tiles_ms = (time.perf_counter() - t0) * 1e3
+    assert not trunc, n_tiles
+    log("banding as tiles: %d candidates in %d tiles, %.1f ms" % (n, n_tiles, band_tiles_ms))
+    # and as explicit id pairs
     cap = int(2.6e9)
     xo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
     yo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
-    # banding once to size its buffers, then timed
     P.bayeslsh_band_candidates(ctx, S_band, 16, 12, cap, x_out=xo, y_out=yo, order_tile=16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, _, n, trunc = P.bayeslsh_band_candidates(ctx, S_band, 16, 12, cap, x_out=xo, y_out=yo, order_tile=16)
+    _, _, n_p, trunc = P.bayeslsh_band_candidates(ctx, S_band, 16, 12, cap, x_out=xo, y_out=yo, order_tile=16)
     band_ms = (time.perf_counter() - t0) * 1e3
-    assert not trunc, n
-    log("banding: %d candidates in %.1f ms" % (n, band_ms))
-    cand = P.pairs(xo[:n], yo[:n])
+    assert not trunc and n_p == n, (n_p, n)
+    log("banding as pairs: %d candidates in %.1f ms" % (n, band_ms))
     acc_cap = 1 << 28
+
+    # headline: Algorithm 1 over the tiles
+    cand_t = P.tiles(mem, tl, n_tiles, n)
     res = P.make_result(n, acc_cap)
-    stream = torch.cuda.current_stream()
 
     def step():
-        P.bayeslsh_verify(ctx, cand, S_pfx, t, eps, delta, gamma, (1, 1), k, res, stream)
+        P.bayeslsh_verify(ctx, cand_t, S_om, t, eps, delta, gamma, (1, 1), k, res, stream)
 
-    for _ in range(args.warmup):
-        step()
-    P.bayeslsh_sync(ctx, stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t1) * 1e3 / args.steps
-    P.bayeslsh_sync(ctx, stream)
-    log("BayesLSH: %.3f ms/step (%.3g pairs/s)" % (ms, n / ms * 1e3))
-    prof = kernel_profile(P, ctx, stream, step, min(args.steps, 10), DENSE_KERNELS)
+    ms = timed_steps(torch, P, ctx, stream, step, args.steps, args.warmup)
+    log("BayesLSH over tiles: %.3f ms/step (%.3g pairs/s)" % (ms, n / ms * 1e3))
+    prof = kernel_profile(P, ctx, stream, step, min(args.steps, 10), TILE_KERNELS)
     log("kernels: %s" % ", ".join("%s %.3f ms x %.0f" % (k_, v["avg_ms"], v["launches_per_step"])
                                   for k_, v in prof.items()))
+
+    # the same candidates as id pairs (prefix array + tail)
+    cand_p = P.pairs(xo[:n], yo[:n])
+    res_p = P.make_result(n, acc_cap)
+
+    def step_p():
+        P.bayeslsh_verify(ctx, cand_p, S_pfx, t, eps, delta, gamma, (1, 1), k, res_p, stream)
+
+    ms_p = timed_steps(torch, P, ctx, stream, step_p, max(3, args.steps // 2), 2)
+    prof_p = kernel_profile(P, ctx, stream, step_p, min(args.steps, 5), PAIR_KERNELS)
+    same_p, diff_p = same_output(torch, n, res, res_p)
+    log("BayesLSH over id pairs: %.3f ms/step; same output as tiles: %s" % (ms_p, same_p))
+    del res_p
 
     # the exhaustive comparator: every candidate compares all 1024 bits, then the
     # decision sequence is replayed -> the same output
     res_ex = P.make_result(n, acc_cap)
 
     def step_ex():
-        P.bayeslsh_exhaustive_verify(ctx, cand, S_om, None, t, eps, delta, gamma, (1, 1), k, 0, P.REPLAY, res_ex,
+        P.bayeslsh_exhaustive_verify(ctx, cand_p, S_om, None, t, eps, delta, gamma, (1, 1), k, 0, P.REPLAY, res_ex,
                                      stream)
 
-    step_ex()
-    P.bayeslsh_sync(ctx, stream)
-    torch.cuda.synchronize()
-    ex_steps = max(2, args.steps // 10)
-    t1 = time.perf_counter()
-    for _ in range(ex_steps):
-        step_ex()
-    torch.cuda.synchronize()
-    ms_ex = (time.perf_counter() - t1) * 1e3 / ex_steps
-    P.bayeslsh_sync(ctx, stream)
+    ms_ex = timed_steps(torch, P, ctx, stream, step_ex, max(2, args.steps // 10), 1)
     log("exhaustive: %.3f ms/step" % ms_ex)
-    diff_codes = int(res.code[:n].ne(res_ex.code[:n]).sum().item())
-    n_acc = int(res.n_accepted.item())
-    same = diff_codes == 0 and n_acc == int(res_ex.n_accepted.item())
-    if same:   # the accepted lists as sets of (index, value): sorted on the device
-        ia, oa = torch.sort(res.acc_idx[:n_acc].view(torch.int64))
-        ib, ob = torch.sort(res_ex.acc_idx[:n_acc].view(torch.int64))
-        same = bool(torch.equal(ia, ib)) and bool(torch.equal(res.acc_val[:n_acc][oa], res_ex.acc_val[:n_acc][ob]))
-        del ia, oa, ib, ob
+    same, diff_codes = same_output(torch, n, res, res_ex)
     if not same:
         log("outputs differ: %d codes" % diff_codes)
     del res_ex
@@ -703,11 +735,12 @@ def run_dense(args, torch, P):
     levels_reached = int(lvl.sum().item()) + n
     levels_past_prefix = int((lvl - 3).clamp_(min=0).sum().item())
     lvl_mean = levels_reached / n - 1.0
+    n_acc = int(res.n_accepted.item())
     del lvl, dec
 
     # parity pass with m recorded (not timed), on a seeded sample against the oracle
     res_m = P.make_result(n, acc_cap, m_debug=True)
-    P.bayeslsh_verify(ctx, cand, S_pfx, t, eps, delta, gamma, (1, 1), k, res_m, stream)
+    P.bayeslsh_verify(ctx, cand_t, S_om, t, eps, delta, gamma, (1, 1), k, res_m, stream)
     P.bayeslsh_sync(ctx, stream)
     assert bool(torch.equal(res_m.code[:n], res.code[:n]))
     rng = np.random.default_rng(G.SEED_BASE + 105)
@@ -736,6 +769,7 @@ def run_dense(args, torch, P):
     emit = np.isfinite(want["shat"])
     parity = {
         "sample": n_sample,
+        "path": "bucket tiles (the headline call)",
         "decision_mismatches": int(np.sum((got_code >> 6) != want["decision"])),
         "level_mismatches": int(np.sum((got_code & 63) != want["level"])),
         "m_mismatches": int(np.sum(got_m != want["m"])),
@@ -751,18 +785,29 @@ def run_dense(args, torch, P):
     log("cpu baseline: %.3g pairs/s on %d threads" % (cpu["value"], threads))
     del xs, ys, sig_host, want
 
-    # Algorithmic bytes (per candidate: 8 B of ids + 1 B of code + both sides'
-    # 4 B chunk per level reached + 12 B per emitted pair), split by kernel: the
-    # prefix kernel owns the ids, the code and levels 0..3 (the first 128
-    # hashes), the tail the later levels and the emission.
+    # Algorithmic bytes.  Per candidate: 1 B of code, both sides' 4 B chunk per
+    # level reached (8 B), 12 B per emitted pair; the candidate ids: 8 B per
+    # pair for id pairs, for tiles the 64 B descriptor and 32 member ids (4 B)
+    # per tile.  Tiles: the tile kernel owns the ids, the code and level 0, the
+    # row kernel the later levels and the emission; id pairs: the prefix kernel
+    # owns ids, code and levels 0-3, the tail the rest.
     chunk = 2 * (k // 8)
     accepted = dec_counts[1] + dec_counts[2]
-    call_bytes = 9 * n + chunk * levels_reached + 12 * accepted
-    pfx_bytes = 9 * n + chunk * (levels_reached - levels_past_prefix)
-    tail_bytes = chunk * levels_past_prefix + 12 * accepted
-    per = {"verify_bits_prefix": pfx_bytes, "verify_tail": tail_bytes, "acc_flush": 12 * accepted}
+    id_bytes_t = n_tiles * (64 + 32 * 4)
+    call_bytes = id_bytes_t + n + chunk * levels_reached + 12 * accepted
+    per = {"verify_tiles": id_bytes_t + n + chunk * n,
+           "verify_rows": chunk * (levels_reached - n) + 12 * accepted,
+           "acc_flush": 12 * accepted}
+    per_p = {"verify_bits_prefix": 9 * n + chunk * (levels_reached - levels_past_prefix),
+             "verify_tail": chunk * levels_past_prefix + 12 * accepted, "acc_flush": 12 * accepted}
+
+    def with_bytes(pr, bb):
+        return {k_: dict(v, algorithmic_bytes_per_step=bb[k_],
+                         algorithmic_GBps=bb[k_] / (v["ms_per_step"] * 1e-3) / 1e9 if v["ms_per_step"] else None)
+                for k_, v in pr.items()}
+
     kern_ms = sum(v["ms_per_step"] for v in prof.values())
-    dom = max(("verify_bits_prefix", "verify_tail"), key=lambda k_: prof[k_]["ms_per_step"])
+    dom = max(("verify_tiles", "verify_rows"), key=lambda k_: prof[k_]["ms_per_step"])
     launches = prof[dom]["launches_per_step"]
     dom_bytes = per[dom] / launches
     achieved = dom_bytes / (prof[dom]["avg_ms"] * 1e-3) / 1e9
@@ -770,19 +815,17 @@ def run_dense(args, torch, P):
     roofline = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,
+        "traffic_frac": traffic / (prof[dom]["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
         "kernel": dom, "kernel_avg_ms": prof[dom]["avg_ms"], "launches_per_step": launches,
         "algorithmic_bytes_per_launch": dom_bytes,
-        "kernels": {k_: dict(v, algorithmic_bytes_per_step=per[k_],
-                             algorithmic_GBps=per[k_] / (v["ms_per_step"] * 1e-3) / 1e9 if v["ms_per_step"] else None)
-                    for k_, v in prof.items()},
+        "kernels": with_bytes(prof, per),
         "call": {"algorithmic_bytes": call_bytes, "kernel_ms": kern_ms,
                  "achieved": call_bytes / (kern_ms * 1e-3) / 1e9,
                  "frac": call_bytes / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                 "hbm_stream_bytes": 9 * n, "stream_frac": 9 * n / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                  "traffic": measured_traffic_of(DENSE_TRAFFIC_FILE, DENSE_KERNEL_SOURCES, "traffic_bytes_per_call")},
-        "bytes_model": "per candidate 8 B ids + 1 B code + 8 B per level reached (4 B chunk per side at k = 32) "
-                       "+ 12 B per emitted pair; the prefix kernel owns ids, code and levels 0-3, the tail kernel "
-                       "the later levels and the emission",
+        "bytes_model": "per candidate 1 B code + 8 B per level reached (4 B chunk per side at k = 32) + 12 B per "
+                       "emitted pair, plus 64 B descriptor + 32 x 4 B member ids per tile; the tile kernel owns "
+                       "ids, code and level 0, the row kernel the later levels and the emission",
     }
     ctx.close()
     return {
@@ -791,14 +834,21 @@ def run_dense(args, torch, P):
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": "dense cosine estimation: 1M x 256 Gaussian-mixture vectors (1000 components), 1024 SRP "
-                               "bits, GPU LSH banding 16 x 12 bits on an independent 192-bit projection (pairs of a "
-                               "bucket in 16 x 16 tiles), Algorithm 1 t=0.8, eps=gamma=0.03, delta=0.05, k=32, "
-                               "n_max=1024",
-                   "n_candidates": n, "banding_ms": band_ms, "banding_pairs_per_s": n / (band_ms * 1e-3)},
+                               "bits, GPU LSH banding 16 x 12 bits on an independent 192-bit projection, candidates "
+                               "handed over as 16 x 16 bucket tiles, Algorithm 1 t=0.8, eps=gamma=0.03, "
+                               "delta=0.05, k=32, n_max=1024",
+                   "n_candidates": n, "n_tiles": n_tiles, "banding_tiles_ms": band_tiles_ms,
+                   "banding_pairs_ms": band_ms, "banding_pairs_per_s": n / (band_tiles_ms * 1e-3)},
         "decisions": {"pruned": dec_counts[0], "accept_conc": dec_counts[1], "accept_nmax": dec_counts[2],
                       "mean_level": lvl_mean, "accepted_listed": n_acc},
+        "id_pairs": {"ms_per_step": ms_p, "value": n / (ms_p * 1e-3), "same_output_as_tiles": same_p,
+                     "differing_codes": diff_p,
+                     "note": "the same candidates as 8 B id pairs (bayeslsh_band_candidates) with the 16 B/object "
+                             "prefix array: one 16-byte gather per side per candidate, survivors to the tail kernel",
+                     "kernels": with_bytes(prof_p, per_p)},
         "exhaustive": {"ms_per_step": ms_ex, "value": n / (ms_ex * 1e-3), "speedup": ms_ex / ms, "same_output": same,
-                       "differing_codes": diff_codes, "mode": "REPLAY, all 1024 bits of both object-major rows"},
+                       "differing_codes": diff_codes,
+                       "mode": "REPLAY over id pairs, all 1024 bits of both object-major rows"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sampled_parity": parity,

@@ -24,11 +24,14 @@ int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStrea
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s);
 int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, int words, hipStream_t s);
 int launch_zero_slices(blsh_ctx *ctx, int64_t *cnt, hipStream_t s);
+int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s);
+int launch_verify_rows(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals,
+                       hipStream_t s);
 int launch_acc_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t *nxt_cnt, int64_t *nxt_total, bool last,
                      hipStream_t s);
 int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t row_words, bool word_major,
                     int32_t n_bands, int32_t band_bits, int32_t max_bucket, int32_t tile, uint32_t *x_out,
-                    uint32_t *y_out, int64_t capacity, int64_t *n_pairs, hipStream_t s);
+                    uint32_t *y_out, int64_t capacity, int64_t *n_pairs, hipStream_t s, const BandTilesOut *to);
 int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, const uint32_t *cand, int64_t n_cand,
                    const blsh_sigs *jac, const blsh_sigs *cos, double eps, double delta, double gamma,
                    blsh_prior prior, int32_t kj, int32_t kc, blsh_result *res, int32_t *k_used, hipStream_t s,
@@ -81,7 +84,19 @@ int get_table(blsh_ctx *ctx, const TableKey &key, std::shared_ptr<HostTable> *ho
     std::memcpy(&img[4], &key.alpha, 8);
     std::memcpy(&img[6], &key.beta, 8);
     std::memcpy(&img[8], &key.t, 8);
-    for (int j = 0; j < ht->n_levels; ++j) img[kTabMinOff + j] = uint32_t(ht->min_matches[j]);
+    bool intervals = true;
+    for (int j = 0; j < ht->n_levels; ++j) {
+      const int n = (j + 1) * ht->k, mm = ht->min_matches[j];
+      img[kTabMinOff + j] = uint32_t(mm);
+      // the accept set above min_matches: [lo, n] when it is an interval
+      auto bit = [&](int m) { return (ht->accept[size_t(j) * ht->words + (m >> 5)] >> (m & 31)) & 1u; };
+      int lo = n + 1;
+      for (int m = n; m >= mm && m >= 0 && bit(m); --m) lo = m;
+      for (int m = mm; m < lo; ++m)
+        if (bit(m)) intervals = false;
+      img[kTabAloOff + j] = uint32_t(lo);
+    }
+    img[kTabFlagOff] = intervals ? 1u : 0u;
     std::memcpy(&img[kTabAccOff], ht->accept.data(), ht->accept.size() * 4);
   }
   if (host) *host = ht;
@@ -188,6 +203,14 @@ static int check_cand(const blsh_candidates *c, int64_t *n_cand) {
       if (c->all_n < 0 || c->all_n > (1ll << 31)) return fail(BLSH_EINVAL, "candidates: all_n out of range");
       *n_cand = c->all_n * (c->all_n - 1) / 2;
       if (c->all_n < 2) *n_cand = 0;
+      return BLSH_OK;
+    case BLSH_TILES:
+      if (c->n_tiles < 0 || c->n_cand < 0 || c->n_members < 0) return fail(BLSH_EINVAL, "candidates: negative tile sizes");
+      if (c->n_tiles > 0 && (!c->tiles || !c->members || c->n_members == 0))
+        return fail(BLSH_EINVAL, "candidates: null tiles or members");
+      if (c->n_cand > c->n_tiles * 256) return fail(BLSH_EINVAL, "candidates: n_cand exceeds 256 per tile");
+      if (uintptr_t(c->tiles) & 7) return fail(BLSH_EINVAL, "candidates: tiles must be 8-byte aligned");
+      *n_cand = c->n_cand;
       return BLSH_OK;
     default:
       return fail(BLSH_EINVAL, "candidates: bad kind %d", int(c->kind));
@@ -353,6 +376,65 @@ static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
 }
 
 // Shared driver of verify / lite / exhaustive.
+// Algorithm 1 over BLSH_TILES candidates: launches of at most kTilesChunk
+// tiles, each [k_verify_tiles (level 0; survivors queued with their ids),
+// k_verify_rows (the survivors over whole rows), k_acc_flush].  Workspace:
+// kSlices survivor slices of 16-byte entries, each sized for the most a
+// launch puts in it (a wave takes one tile, 256 candidates at most, and wave
+// w uses slice w % kSlices), and the accepted-pair staging.
+static constexpr int64_t kTilesChunk = int64_t(1) << 19;
+
+static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, int k, int n_max, int n_levels,
+                     bool intervals, hipStream_t s) {
+  const int64_t S = kSlices;
+  const int64_t chunk = std::min<int64_t>(cand->n_tiles, kTilesChunk);
+  const int64_t waves = (chunk + 3) / 4 * 4;
+  const int64_t q_cap = (waves + S - 1) / S * 256;
+  const int64_t stage = ctx->tuning.acc_stage_cap > 0 ? int64_t(ctx->tuning.acc_stage_cap) : kStageDefault;
+  const int64_t st_cap = (std::min<int64_t>(chunk * 256, stage) + S - 1) / S;
+  const size_t q_bytes = align256(size_t(S) * q_cap * 16);
+  const size_t st_bytes = align256(size_t(S) * st_cap * 4);
+  int rc = ensure_workspace(ctx, q_bytes + 2 * st_bytes);
+  if (rc) return rc;
+  char *p = static_cast<char *>(ctx->ws);
+  int64_t *cnt = ctx->d_slices;
+  a.q_ent = reinterpret_cast<u32x4 *>(p);
+  a.q_cap = q_cap;
+  a.q_cnt = cnt + size_t(2) * kSlices * kCntStride;
+  a.st_rel = reinterpret_cast<uint32_t *>(p + q_bytes);
+  a.st_val = reinterpret_cast<float *>(p + q_bytes + st_bytes);
+  a.st_cap = st_cap;
+  a.tiles = cand->tiles;
+  a.members = cand->members;
+  a.n_members = cand->n_members;
+  a.n_cand = cand->n_cand;
+  a.c_begin = 0;
+  a.pfx = nullptr;
+  if (ctx->slices_dirty) {
+    if ((rc = launch_zero_slices(ctx, cnt, s))) return fail(rc, "launch failed");
+    ctx->slices_dirty = false;
+  }
+  const int words = (n_levels * k + 1 + 31) / 32;
+  auto set_cnt = [&](int st) { return cnt + size_t(st) * kSlices * kCntStride; };
+  auto set_total = [&](int st) { return cnt + (size_t(3) * kSlices + st) * kCntStride; };
+  for (int64_t t0 = 0; t0 < cand->n_tiles; t0 += chunk) {
+    a.t_begin = t0;
+    a.t_end = std::min(cand->n_tiles, t0 + chunk);
+    a.c_begin_dev = &cand->tiles[t0].first;
+    const int cur = ctx->slice_set, nxt = cur ^ 1;
+    a.acc_cnt = set_cnt(cur);
+    a.acc_total = set_total(cur);
+    ctx->slices_dirty = true;
+    rc = launch_verify_tiles(ctx, a, k, s);
+    if (!rc) rc = launch_verify_rows(ctx, a, k, n_max, words, intervals, s);
+    if (!rc) rc = launch_acc_flush(ctx, a, set_cnt(nxt), set_total(nxt), a.t_end == cand->n_tiles, s);
+    if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;
+    ctx->slice_set = nxt;
+  }
+  ctx->slices_dirty = false;
+  return BLSH_OK;
+}
+
 // noalloc: Algorithm 1 only; every buffer beyond the caller's comes from the
 // device's scratch array (launches of at most kNaChunk candidates), the table
 // image is copied into it, and nothing is allocated.
@@ -376,6 +458,13 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
     if ((rc = check_exact(exact, sigs->measure, sigs->n_obj))) return rc;
   }
   const bool exh = exhaustive_mode >= 0;
+  if (cand->kind == BLSH_TILES) {
+    if (exh || lite || noalloc) return fail(BLSH_EINVAL, "BLSH_TILES candidates: Algorithm 1 (bayeslsh_verify) only");
+    if (sigs->measure != BLSH_COSINE) return fail(BLSH_EINVAL, "BLSH_TILES candidates: SRP signatures only");
+    if (sigs->layout != BLSH_OBJECT_MAJOR || (uintptr_t(sigs->data) & 15) || row_words % 4)
+      return fail(BLSH_EINVAL, "BLSH_TILES candidates: object-major rows of a multiple of 128 hashes, 16-byte aligned");
+    if (n_max % 128 || n_max > 2048) return fail(BLSH_EINVAL, "BLSH_TILES candidates: n_max must be a multiple of 128 <= 2048");
+  }
   if (exh) {
     if (sigs->measure == BLSH_COSINE) {
       if (sigs->layout != BLSH_OBJECT_MAJOR) return fail(BLSH_EINVAL, "exhaustive: SRP signatures must be OBJECT_MAJOR");
@@ -400,7 +489,7 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
       return fail(BLSH_EINVAL, "table of %zu bytes exceeds the %zu-byte scratch region", na_host->image.size() * 4,
                   kNaTabBytes);
     dtab = na_table;
-  } else if ((rc = get_table(ctx, key, nullptr, &dtab, s))) {
+  } else if ((rc = get_table(ctx, key, &na_host, &dtab, s))) {
     return rc;
   }
 
@@ -432,7 +521,10 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   a.mode = exh ? exhaustive_mode : 0;
   a.count_levels = n_max / k;
   a.t = t;
-  if (n_cand == 0) return launch_zero(ctx, res->n_accepted, s) ? fail(BLSH_EDEVICE, "launch failed") : BLSH_OK;
+  if (n_cand == 0 || (cand->kind == BLSH_TILES && cand->n_tiles == 0))
+    return launch_zero(ctx, res->n_accepted, s) ? fail(BLSH_EDEVICE, "launch failed") : BLSH_OK;
+  if (cand->kind == BLSH_TILES)
+    return run_tiles(ctx, cand, a, k, n_max, n_levels, (na_host->image[kTabFlagOff] & 1u) != 0, s);
   // SRP Algorithm 1 with a prefix view: candidates undecided after the first
   // 128 hashes are queued and finished by a second kernel with every lane busy
   const bool tail = !exh && !lite && sigs->measure == BLSH_COSINE && a.pfx != nullptr && 128 / k < n_levels;
@@ -813,7 +905,35 @@ int bayeslsh_band_candidates(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t 
   if (capacity > 0 && (!x_out || !y_out)) return fail(BLSH_EINVAL, "banding: null outputs");
   return band_candidates(ctx, g->data, g->n_obj, g->n_hashes / 32, g->layout == BLSH_WORD_MAJOR, n_bands, band_bits,
                          max_bucket, order_tile, x_out, y_out, capacity, n_pairs_host,
-                         static_cast<hipStream_t>(stream));
+                         static_cast<hipStream_t>(stream), nullptr);
+}
+
+int bayeslsh_band_tiles(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t n_bands, int32_t band_bits,
+                        int32_t max_bucket, uint32_t *members_out, int64_t members_capacity, blsh_tile *tiles_out,
+                        int64_t tiles_capacity, int64_t *n_tiles_host, int64_t *n_pairs_host, void *stream) {
+  if (!ctx) return fail(BLSH_EINVAL, "null context");
+  if (!n_pairs_host || !n_tiles_host) return fail(BLSH_EINVAL, "n_tiles_host / n_pairs_host: null");
+  *n_pairs_host = 0;
+  *n_tiles_host = 0;
+  const blsh_sigs *g = band_sigs;
+  if (!g || !g->data) return fail(BLSH_EINVAL, "band signatures: null");
+  if (g->measure != BLSH_COSINE) return fail(BLSH_EINVAL, "banding takes sign-random-projection bits");
+  if (g->layout != BLSH_OBJECT_MAJOR && g->layout != BLSH_WORD_MAJOR) return fail(BLSH_EINVAL, "bad layout");
+  if (g->n_obj <= 0 || g->n_obj > 0xFFFFFFFFll) return fail(BLSH_EINVAL, "band signatures: n_obj out of range");
+  if (g->n_hashes <= 0 || g->n_hashes % 32) return fail(BLSH_EINVAL, "band signatures: n_hashes must be a multiple of 32");
+  if (band_bits < 1 || band_bits > 32 || n_bands < 1 || n_bands > 64)
+    return fail(BLSH_EINVAL, "banding: 1 <= band_bits <= 32 and 1 <= n_bands <= 64");
+  if (int64_t(n_bands) * band_bits > g->n_hashes)
+    return fail(BLSH_EINVAL, "banding: n_bands * band_bits (%d) > n_hashes (%d)", n_bands * band_bits, g->n_hashes);
+  if (max_bucket < 0 || tiles_capacity < 0) return fail(BLSH_EINVAL, "banding: negative max_bucket or capacity");
+  if (!members_out || members_capacity < int64_t(n_bands) * g->n_obj)
+    return fail(BLSH_EINVAL, "banding tiles: members_out must hold n_bands * n_obj = %lld ids",
+                (long long)(int64_t(n_bands) * g->n_obj));
+  if (tiles_capacity > 0 && !tiles_out) return fail(BLSH_EINVAL, "banding tiles: null tiles_out");
+  if (uintptr_t(tiles_out) & 7) return fail(BLSH_EINVAL, "banding tiles: tiles_out must be 8-byte aligned");
+  BandTilesOut to{members_out, members_capacity, tiles_out, tiles_capacity, n_tiles_host};
+  return band_candidates(ctx, g->data, g->n_obj, g->n_hashes / 32, g->layout == BLSH_WORD_MAJOR, n_bands, band_bits,
+                         max_bucket, 16, nullptr, nullptr, 0, n_pairs_host, static_cast<hipStream_t>(stream), &to);
 }
 
 int bayeslsh_fit_prior(const double *sim_host, int64_t r, blsh_prior *prior_out, int32_t *uniform_host) {

@@ -353,6 +353,43 @@ __global__ __launch_bounds__(kBandBlock) void k_band_count_pairs(TileArgs a) {
   }
 }
 
+// Bit j of the low 16 bits of x moved to bit 4j.
+__device__ inline uint64_t spread4(uint64_t x) {
+  x &= 0xFFFFull;
+  x = (x | (x << 24)) & 0x000000FF000000FFull;
+  x = (x | (x << 12)) & 0x000F000F000F000Full;
+  x = (x | (x << 6)) & 0x0303030303030303ull;
+  x = (x | (x << 3)) & 0x1111111111111111ull;
+  return x;
+}
+
+// Tile descriptors of a band (one thread per tile): the tile's first
+// candidate index (the band's running pair count plus the tile's offset), the
+// positions of its row and column members in the members array (the band's
+// sorted ids start at member_base), their counts, and the keep mask in
+// row-major bit order (the count pass's ballot i holds position 4l + i at bit
+// l: word w of the mask takes lanes 16w .. 16w+15 of the four ballots,
+// interleaved).
+__global__ __launch_bounds__(kBandBlock) void k_band_tile_desc(TileArgs a, int64_t member_base, blsh_tile *out,
+                                                               int64_t out_base, int64_t out_cap) {
+  const int64_t t = int64_t(blockIdx.x) * kBandBlock + threadIdx.x;
+  if (t >= a.n_tiles || out_base + t >= out_cap) return;
+  const TileAt T = tile_at(a, t, 0);
+  const int64_t ta = T.ar / kTile;
+  blsh_tile d;
+  d.first = *a.base + a.tcoff[t];
+  d.row0 = member_base + T.p0 + ta * kTile;
+  d.col0 = member_base + T.p0 + T.tb * kTile;
+  d.n_rows = uint32_t(min<int64_t>(kTile, T.len - ta * kTile));
+  d.n_cols = uint32_t(min<int64_t>(kTile, T.len - T.tb * kTile));
+  const uint64_t b0 = a.tmask[4 * t], b1 = a.tmask[4 * t + 1], b2 = a.tmask[4 * t + 2], b3 = a.tmask[4 * t + 3];
+#pragma unroll
+  for (int w = 0; w < 4; ++w)
+    d.keep[w] = spread4(b0 >> (16 * w)) | (spread4(b1 >> (16 * w)) << 1) | (spread4(b2 >> (16 * w)) << 2) |
+                (spread4(b3 >> (16 * w)) << 3);
+  out[out_base + t] = d;
+}
+
 // base += (pairs of this band) = row_off[n-1] + row_count[n-1]
 __global__ void k_band_advance(int64_t *base, const int64_t *row_off, const int64_t *row_count, int64_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && n > 0) *base += row_off[n - 1] + row_count[n - 1];
@@ -378,8 +415,9 @@ static int ensure_tile_buf(blsh_ctx *ctx, size_t bytes) {
 
 int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t row_words, bool word_major,
                     int32_t n_bands, int32_t band_bits, int32_t max_bucket, int32_t tile, uint32_t *x_out,
-                    uint32_t *y_out, int64_t capacity, int64_t *n_pairs, hipStream_t s) {
+                    uint32_t *y_out, int64_t capacity, int64_t *n_pairs, hipStream_t s, const BandTilesOut *to) {
   if (tile != 0 && tile != kTile) return fail(BLSH_EINVAL, "banding: order_tile must be 0 or %d", kTile);
+  int64_t tiles_total = 0;   // tiles output: descriptors written so far (all bands)
   const size_t n = size_t(n_obj);
   // rocPRIM temporary storage sizes
   size_t sort_tmp = 0, scan_tmp = 0, flag_tmp = 0;
@@ -486,7 +524,16 @@ int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t r
       if (rocprim::exclusive_scan(ttmp, t4, tcnt, tcoff, int64_t(0), size_t(n_tiles), rocprim::plus<int64_t>(), s) !=
           hipSuccess)
         return fail(BLSH_EDEVICE, "banding: scan failed");
-      hipLaunchKernelGGL(k_band_tiles<true>, dim3(tile_blocks), dim3(kBandBlock), 0, s, ta);
+      if (to) {   // tiles instead of pairs: this band's members and tile descriptors
+        if (int64_t(j + 1) * n_obj <= to->member_cap)
+          BLSH_HIP(hipMemcpyAsync(to->members + size_t(j) * n, sids, n * 4, hipMemcpyDeviceToDevice, s));
+        const unsigned db = unsigned((n_tiles + kBandBlock - 1) / kBandBlock);
+        hipLaunchKernelGGL(k_band_tile_desc, dim3(db), dim3(kBandBlock), 0, s, ta, int64_t(j) * n_obj, to->tiles,
+                           tiles_total, to->tile_cap);
+        tiles_total += n_tiles;
+      } else {
+        hipLaunchKernelGGL(k_band_tiles<true>, dim3(tile_blocks), dim3(kBandBlock), 0, s, ta);
+      }
       hipLaunchKernelGGL(k_band_advance, dim3(1), dim3(64), 0, s, base, tcoff, tcnt, n_tiles);
       continue;
     }
@@ -516,6 +563,13 @@ int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t r
   BLSH_HIP(hipMemcpyAsync(n_pairs, base, 8, hipMemcpyDeviceToHost, s));
   BLSH_HIP(hipStreamSynchronize(s));
   if (hipGetLastError() != hipSuccess) return fail(BLSH_EDEVICE, "banding: launch failed");
+  if (to) {
+    *to->n_tiles = tiles_total;
+    if (tiles_total > to->tile_cap)
+      return fail(BLSH_ETRUNCATED, "banding: %lld tiles, capacity %lld", (long long)tiles_total,
+                  (long long)to->tile_cap);
+    return BLSH_OK;
+  }
   return *n_pairs > capacity ? fail(BLSH_ETRUNCATED, "banding: %lld pairs, capacity %lld", (long long)*n_pairs,
                                     (long long)capacity)
                              : BLSH_OK;

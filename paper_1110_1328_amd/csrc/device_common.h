@@ -70,7 +70,20 @@ struct VerifyArgs {
   int32_t mode;                          // 0 replay, 1 replay-lite, 2 mle
   int32_t count_levels;                  // levels compared in full (n_max/k)
   double t;
+  // BLSH_TILES: the launch runs tiles [t_begin, t_end); its candidates start at
+  // *c_begin_dev (tiles[t_begin].first, read on the device; queue and staging
+  // indices are relative to it); n_cand bounds every candidate index written
+  const blsh_tile *tiles;
+  const uint32_t *members;
+  int64_t n_members;
+  int64_t t_begin, t_end;
+  const int64_t *c_begin_dev;
+  int64_t n_cand;
+  u32x4 *q_ent;                          // survivor entries {candidate - c_begin, x, y, 0}
 };
+
+// First candidate of the launch: a host value, or for tiles a device value.
+__device__ inline int64_t launch_c_begin(const VerifyArgs &a) { return a.c_begin_dev ? *a.c_begin_dev : a.c_begin; }
 
 __device__ inline int lane_id() { return __lane_id(); }
 
@@ -198,8 +211,8 @@ __device__ inline void emit_direct(const VerifyArgs &a, bool pred, uint64_t idx,
 
 // Wave-level compaction of (idx, val) into the wave's staging slice (the
 // caller's list for entries past the slice's capacity); called in converged
-// control flow by every active lane.
-__device__ inline void emit_accepted(const VerifyArgs &a, bool pred, uint64_t idx, float val) {
+// control flow by every active lane.  c_begin: the launch's first candidate.
+__device__ inline void emit_accepted_from(const VerifyArgs &a, bool pred, uint64_t idx, float val, int64_t c_begin) {
   const uint64_t mask = __ballot(pred);
   if (mask == 0) return;
   {
@@ -211,12 +224,16 @@ __device__ inline void emit_accepted(const VerifyArgs &a, bool pred, uint64_t id
     base = __shfl(base, leader);
     const unsigned long long pos = base + lanes_below(mask);
     if (pred && int64_t(pos) < a.st_cap) {
-      a.st_rel[size_t(s) * a.st_cap + pos] = uint32_t(idx - uint64_t(a.c_begin));
+      a.st_rel[size_t(s) * a.st_cap + pos] = uint32_t(idx - uint64_t(c_begin));
       a.st_val[size_t(s) * a.st_cap + pos] = val;
       pred = false;
     }
   }
   emit_direct(a, pred, idx, val);
+}
+
+__device__ inline void emit_accepted(const VerifyArgs &a, bool pred, uint64_t idx, float val) {
+  emit_accepted_from(a, pred, idx, val, a.c_begin);
 }
 
 // Position of a wave's `total` new entries in its survivor-queue slice (valid

@@ -60,10 +60,16 @@ constexpr double kTieMargin = 1e-9;
 // Layout of the device buffer (32-bit words):
 //   [0] k  [1] n_levels  [2] words  [3] measure
 //   [4..5] alpha (double)  [6..7] beta (double)  [8..9] t (double)
+//   [10] flags: bit 0 set when every level's accept set, restricted to
+//        m >= min_matches, is an interval [min_accept, n] (or empty)
 //   [16 .. 16+64)        min_matches
-//   [80 .. 80+L*words)   accept bits
+//   [80 .. 80+64)        min_accept (n+1 when nothing is accepted; meaningful
+//                        when flag bit 0 is set)
+//   [144 .. 144+L*words) accept bits
+constexpr int kTabFlagOff = 10;
 constexpr int kTabMinOff = 16;
-constexpr int kTabAccOff = 16 + kMaxLevels;
+constexpr int kTabAloOff = 16 + kMaxLevels;
+constexpr int kTabAccOff = 16 + 2 * kMaxLevels;
 
 int build_table(const TableKey &key, HostTable *out);  // host FP64, tables.cpp
 
@@ -116,6 +122,16 @@ namespace blsh {
 int get_table(blsh_ctx *ctx, const TableKey &key, std::shared_ptr<HostTable> *host, const uint32_t **dev,
               hipStream_t stream);
 int ensure_workspace(blsh_ctx *ctx, size_t bytes);
+
+// Tiles output of the banding (bayeslsh_band_tiles): each band's sorted
+// member ids at members[band * n_obj ...] and the tile descriptors of all bands.
+struct BandTilesOut {
+  uint32_t *members;
+  int64_t member_cap;
+  blsh_tile *tiles;
+  int64_t tile_cap;
+  int64_t *n_tiles;   // host
+};
 
 // Device-to-device copy of one request's candidate ids into the serving arena
 // (ids src[0, n) to arena[dst, dst + n)).

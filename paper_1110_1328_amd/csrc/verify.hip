@@ -643,6 +643,229 @@ __global__ __launch_bounds__(kBlock) void k_exact_pairs(VerifyArgs a, double *ou
 }
 
 // ---------------------------------------------------------------------------
+// Bucket tiles (BLSH_TILES, SRP): one wave per 16 x 16 tile of a bucket's
+// member pairs.  Lanes 0..15 load the ids of the tile's row members and lanes
+// 16..31 those of its column members (consecutive positions of the band's
+// sorted ids), then each of these lanes the first level's words of its object
+// (one cache line per object, 32 per tile instead of two gathers per pair).
+// Lane l owns the tile positions p = 4l .. 4l+3 (row l/4, columns 4(l%4) ..
+// 4(l%4)+3) and takes both sides' words from the loading lanes by lane
+// permutation.  Level 0 is decided here; the candidates it does not prune go,
+// with their two ids, to the survivor queue, where k_verify_rows runs
+// Algorithm 1 on them from level 0 over whole rows.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kNoObject = 0xFFFFFFFFu;   // lane holds no (valid) object
+
+// Wave-level compaction of a lane's P survivor entries (bit p of `want`) into
+// the tiles survivor queue, one atomic per wave.
+template <int P>
+__device__ inline void push_entries(const VerifyArgs &a, uint32_t want, const u32x4 *e) {
+  uint64_t mask[P];
+  uint32_t total = 0;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    mask[p] = __ballot((want >> p) & 1u);
+    total += uint32_t(__popcll(mask[p]));
+  }
+  if (total == 0) return;
+  const int s = wave_slice();
+  int64_t base = queue_reserve(a, s, total, 0);
+  u32x4 *q = a.q_ent + size_t(s) * a.q_cap;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if ((want >> p) & 1u) {
+      const int64_t pos = base + lanes_below(mask[p]);
+      if (pos < a.q_cap) q[pos] = e[p];
+      else raise_status(a.status, BLSH_EDEVICE);
+    }
+    base += __popcll(mask[p]);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
+  const int lane = lane_id();
+  const int64_t t = a.t_begin + xcd_tile(blockIdx.x, gridDim.x) * (kBlock / kWave) +
+                    __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+  if (t >= a.t_end) return;   // whole wave
+  const blsh_tile *T = a.tiles + t;
+  const int64_t cb = *a.c_begin_dev;
+  const int64_t first = T->first;
+  const uint64_t keep0 = T->keep[0], keep1 = T->keep[1], keep2 = T->keep[2], keep3 = T->keep[3];
+  const int min0 = int(a.table[kTabMinOff]);
+
+  const int n_rows = int(T->n_rows), n_cols = int(T->n_cols);
+  // the tile's 32 objects: id and level-0 words (K = 64: two words); an id
+  // >= n_obj is a bad id (BLSH_EBADID), a position outside members[] a
+  // malformed tile (BLSH_EINVAL); either leaves the lane without an object
+  uint32_t id = kNoObject, w0 = 0, w1 = 0;
+  if (lane < 32) {
+    const bool row = lane < 16;
+    const int o = lane & 15;
+    const int64_t pos = (row ? T->row0 : T->col0) + o;
+    if (o < (row ? n_rows : n_cols)) {
+      if (pos >= 0 && pos < a.n_members) {
+        const uint32_t v = a.members[pos];
+        if (v < a.n_obj) {
+          id = v;
+          if constexpr (K == 64) {
+            const uint2 h = *reinterpret_cast<const uint2 *>(a.sig + size_t(v) * a.row_words);
+            w0 = h.x;
+            w1 = h.y;
+          } else {
+            w0 = a.sig[size_t(v) * a.row_words];
+          }
+        } else {
+          raise_status(a.status, BLSH_EBADID);
+        }
+      } else {
+        raise_status(a.status, BLSH_EINVAL);
+      }
+    }
+  }
+  const int r = lane >> 2, c0 = 16 + 4 * (lane & 3);
+  const uint32_t xid = __shfl(id, r), xw0 = __shfl(w0, r);
+  const uint32_t xw1 = K == 64 ? __shfl(w1, r) : 0u;
+  uint32_t yid[4], yw0[4], yw1[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    yid[i] = __shfl(id, c0 + i);
+    yw0[i] = __shfl(w0, c0 + i);
+    yw1[i] = K == 64 ? __shfl(w1, c0 + i) : 0u;
+  }
+  // this lane's positions 4l .. 4l+3: bits of keep word l/16; their numbers
+  // follow the set bits of every earlier position
+  const int kw = lane >> 4, sh = 4 * (lane & 15);
+  const uint64_t mine = kw == 0 ? keep0 : kw == 1 ? keep1 : kw == 2 ? keep2 : keep3;
+  const int before = (kw > 0 ? __popcll(keep0) : 0) + (kw > 1 ? __popcll(keep1) : 0) + (kw > 2 ? __popcll(keep2) : 0);
+  const uint32_t kb = uint32_t(mine >> sh) & 0xFu;
+  int64_t rank = first + before + __popcll(sh ? (mine & ((1ull << sh) - 1ull)) : 0ull);
+  uint32_t want = 0;
+  u32x4 ent[4];
+  bool malformed = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ent[i] = u32x4{0u, 0u, 0u, 0u};
+    if (!((kb >> i) & 1u)) continue;
+    const int64_t c = rank++;
+    if (c < 0 || c >= a.n_cand) {   // numbering outside the call's candidates: skipped
+      malformed = true;
+      continue;
+    }
+    if (xid == kNoObject || yid[i] == kNoObject) {
+      a.code[c] = 0xFF;
+      if (r >= n_rows || c0 - 16 + i >= n_cols) malformed = true;   // a position past the tile's members
+      continue;
+    }
+    uint32_t m;
+    if constexpr (K == 16) m = 16u - __popc((xw0 ^ yw0[i]) & 0xFFFFu);
+    else if constexpr (K == 32) m = 32u - __popc(xw0 ^ yw0[i]);
+    else m = 64u - __popc(xw0 ^ yw0[i]) - __popc(xw1 ^ yw1[i]);
+    a.code[c] = uint8_t(BLSH_PRUNED << 6);   // level 0; survivors are overwritten by the row kernel
+    if (a.m_dbg) a.m_dbg[c] = uint16_t(m);
+    if (int(m) >= min0) {
+      want |= 1u << i;
+      ent[i] = u32x4{uint32_t(c - cb), xid, yid[i], 0u};
+    }
+  }
+  if (malformed) raise_status(a.status, BLSH_EINVAL);
+  push_entries<4>(a, want, ent);
+}
+
+// Algorithm 1 over whole rows for the queued survivors of the tiles: a group
+// of G = n_max / 128 lanes per survivor, lane r of the group holding words
+// 4r .. 4r+3 of both rows (one 128-byte line per side and 8 lanes), so that
+// the group's loads coalesce.  Each lane counts the agreements of its 128/K
+// levels, a prefix across the group gives m at every level, and each lane
+// finds the first of its levels that decides (prune below min_matches;
+// accept at or above min_accept, or by the accept bits when a level's accept
+// set is not an interval; n_max); the group takes the earliest.  minMatches
+// and min_accept of a lane's levels are held in registers.
+template <int K, int G>
+__global__ __launch_bounds__(kBlock) void k_verify_rows(VerifyArgs a) {
+  constexpr int LPL = 128 / K;      // levels per lane
+  constexpr int PPW = kWave / G;    // survivors per wave step
+  extern __shared__ uint32_t s_acc[];   // accept bits (tables with non-interval accept sets)
+  const int L = a.n_levels;
+  const int words = int(a.table[2]);
+  const bool intervals = a.table[kTabFlagOff] & 1u;
+  if (!intervals)
+    for (int i = threadIdx.x; i < L * words; i += kBlock) s_acc[i] = a.table[kTabAccOff + i];
+  __syncthreads();
+  const int lane = lane_id(), r = lane % G, g = lane / G;
+  int mn[LPL], alo[LPL];
+#pragma unroll
+  for (int q = 0; q < LPL; ++q) {
+    const int j = r * LPL + q;
+    mn[q] = j < L ? int(a.table[kTabMinOff + j]) : 0;
+    alo[q] = j < L ? int(a.table[kTabAloOff + j]) : 0x7fffffff;
+  }
+  const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
+  const int64_t cb = *a.c_begin_dev;
+  // the grid is a multiple of kSlices blocks: block b serves queue slice
+  // b % kSlices together with the other blocks of that slice
+  const int sl = int(blockIdx.x % kSlices);
+  const int64_t n = min(a.q_cnt[sl * kCntStride], a.q_cap);
+  const u32x4 *ent = a.q_ent + size_t(sl) * a.q_cap;
+  const int64_t w_in = int64_t(blockIdx.x / kSlices) * (kBlock / kWave) + (threadIdx.x >> 6);
+  const int64_t w_all = int64_t(gridDim.x / kSlices) * (kBlock / kWave);
+  for (int64_t i0 = w_in * PPW; i0 < n; i0 += w_all * PPW) {   // wave-uniform bound
+    const int64_t i = i0 + g;
+    const bool act = i < n;
+    u32x4 e = u32x4{0u, 0u, 0u, 0u};
+    uint32_t d[4] = {0u, 0u, 0u, 0u};
+    if (act) {
+      e = ent[i];
+      const u32x4 hx = *reinterpret_cast<const u32x4 *>(a.sig + size_t(e.y) * a.row_words + 4 * r);
+      const u32x4 hy = *reinterpret_cast<const u32x4 *>(a.sig + size_t(e.z) * a.row_words + 4 * r);
+      d[0] = hx.x ^ hy.x; d[1] = hx.y ^ hy.y; d[2] = hx.z ^ hy.z; d[3] = hx.w ^ hy.w;
+    }
+    uint32_t cnt[LPL], tot = 0;
+#pragma unroll
+    for (int q = 0; q < LPL; ++q) {
+      if constexpr (K == 16) cnt[q] = 16u - __popc((d[q >> 1] >> ((q & 1) * 16)) & 0xFFFFu);
+      else if constexpr (K == 32) cnt[q] = 32u - __popc(d[q]);
+      else cnt[q] = 64u - __popc(d[2 * q]) - __popc(d[2 * q + 1]);
+      tot += cnt[q];
+    }
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, G);
+      if (r >= o) incl += v;
+    }
+    uint32_t run = incl - tot;
+    // first deciding level of this lane: key = level << 20 | decision << 16 | m
+    uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+    for (int q = 0; q < LPL; ++q) {
+      run += cnt[q];
+      const int j = r * LPL + q;
+      if (key == 0xFFFFFFFFu && j < L) {
+        const int m = int(run);
+        int dec = -1;
+        if (m < mn[q]) dec = BLSH_PRUNED;
+        else if (intervals ? m >= alo[q] : ((s_acc[j * words + (m >> 5)] >> (m & 31)) & 1u)) dec = BLSH_ACCEPT_CONC;
+        else if (j == L - 1) dec = BLSH_ACCEPT_NMAX;
+        if (dec >= 0) key = (uint32_t(j) << 20) | (uint32_t(dec) << 16) | uint32_t(m);
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) key = min(key, uint32_t(__shfl_xor(key, o)));
+    const int j = int(key >> 20), dec = int((key >> 16) & 3u), m = int(key & 0xFFFFu);
+    const int64_t c = cb + int64_t(e.x);
+    const bool lead = act && r == 0;
+    if (lead) {
+      a.code[c] = uint8_t((dec << 6) | j);
+      if (a.m_dbg) a.m_dbg[c] = uint16_t(m);
+    }
+    const bool emit = lead && dec != BLSH_PRUNED;
+    const float v = emit ? map_estimate(a.measure, m, (j + 1) * K, alpha, beta) : 0.f;
+    emit_accepted_from(a, emit, uint64_t(c), v, cb);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Exhaustive comparator
 // ---------------------------------------------------------------------------
 // Decision replay over cumulative counts: returns true when level j with m
@@ -845,11 +1068,14 @@ __global__ void k_zero_slices(int64_t *cnt) {
 // set (nxt_cnt, *nxt_total): block 0 clears its counts and stores the new
 // running count there, or 0 and *n_acc on the call's last launch.  Block s
 // also clears queue count s.
+// kFlushParts blocks share a slice, each copying a contiguous part of it.
+constexpr int kFlushParts = 8;
+
 __global__ __launch_bounds__(kBlock) void k_acc_flush(VerifyArgs a, int64_t *nxt_cnt, int64_t *nxt_total, int last) {
   static_assert(kSlices == kBlock, "one staging slice per thread of a block");
   __shared__ int64_t s_cnt[kSlices];
   __shared__ int64_t s_base, s_total;
-  const int t = threadIdx.x, sl = blockIdx.x;
+  const int t = threadIdx.x, sl = blockIdx.x % kSlices, part = blockIdx.x / kSlices;
   int64_t c = min(a.acc_cnt[size_t(t) * kCntStride], a.st_cap);
   // inclusive scan of the slice counts across the block (wave scan, then
   // the four wave totals)
@@ -872,19 +1098,22 @@ __global__ __launch_bounds__(kBlock) void k_acc_flush(VerifyArgs a, int64_t *nxt
   const int64_t base = s_base + s_cnt[sl];
   const uint32_t *rel = a.st_rel + size_t(sl) * a.st_cap;
   const float *val = a.st_val + size_t(sl) * a.st_cap;
+  const int64_t cb = launch_c_begin(a);
+  const int64_t per = (n + kFlushParts - 1) / kFlushParts;
+  const int64_t i1 = min(n, (part + 1) * per);
   bool trunc = false;
-  for (int64_t i = t; i < n; i += kBlock) {
+  for (int64_t i = part * per + t; i < i1; i += kBlock) {
     const int64_t pos = base + i;
     if (pos < a.acc_cap) {
-      a.acc_idx[pos] = uint64_t(a.c_begin) + rel[i];
+      a.acc_idx[pos] = uint64_t(cb) + rel[i];
       a.acc_val[pos] = val[i];
     } else {
       trunc = true;
     }
   }
   if (trunc) raise_status(a.status, BLSH_ETRUNCATED);
-  if (t == 0 && a.q_cnt) a.q_cnt[size_t(sl) * kCntStride] = 0;
-  if (sl == 0) {
+  if (part == 0 && t == 0 && a.q_cnt) a.q_cnt[size_t(sl) * kCntStride] = 0;
+  if (sl == 0 && part == 0) {
     nxt_cnt[size_t(t) * kCntStride] = 0;
     if (t == 0) {
       const int64_t total = s_base + s_total;
@@ -1007,6 +1236,39 @@ int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_majo
   return fail(BLSH_EINVAL, "unsupported k=%d", k);
 }
 
+// Tiles: the level-0 pass over tiles [a.t_begin, a.t_end), one wave each.
+int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s) {
+  const int64_t nt = a.t_end - a.t_begin;
+  if (nt <= 0) return BLSH_OK;
+  const int64_t nb = blocks_for(nt, kBlock / kWave);
+  LaunchScope ls(ctx, s, "verify_tiles");
+  if (k == 16) hipLaunchKernelGGL((k_verify_tiles<16>), dim3(nb), dim3(kBlock), 0, s, a);
+  else if (k == 32) hipLaunchKernelGGL((k_verify_tiles<32>), dim3(nb), dim3(kBlock), 0, s, a);
+  else if (k == 64) hipLaunchKernelGGL((k_verify_tiles<64>), dim3(nb), dim3(kBlock), 0, s, a);
+  else return fail(BLSH_EINVAL, "unsupported k=%d", k);
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+}
+
+// Tiles: Algorithm 1 over whole rows for the queued survivors; G = n_max/128
+// lanes per survivor; accept bits in LDS only for non-interval tables.
+int launch_verify_rows(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals,
+                       hipStream_t s) {
+  const int64_t nb = round_up(int64_t(ctx->n_cu) * 16, kSlices);
+  const size_t lds = intervals ? 0 : size_t(a.n_levels) * words * 4;
+  const int G = n_max / 128;
+  LaunchScope ls(ctx, s, "verify_rows");
+#define BLSH_R(KK, GG)                                                                     \
+  if (k == KK && G == GG) {                                                                \
+    hipLaunchKernelGGL((k_verify_rows<KK, GG>), dim3(nb), dim3(kBlock), lds, s, a);        \
+    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                       \
+  }
+  BLSH_R(16, 1) BLSH_R(16, 2) BLSH_R(16, 4) BLSH_R(16, 8) BLSH_R(16, 16)
+  BLSH_R(32, 1) BLSH_R(32, 2) BLSH_R(32, 4) BLSH_R(32, 8) BLSH_R(32, 16)
+  BLSH_R(64, 1) BLSH_R(64, 2) BLSH_R(64, 4) BLSH_R(64, 8) BLSH_R(64, 16)
+#undef BLSH_R
+  return fail(BLSH_EINVAL, "tiles: unsupported k=%d, n_max=%d", k, n_max);
+}
+
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s) {
   const int64_t n = a.c_end - a.c_begin;
   if (n <= 0) return BLSH_OK;
@@ -1025,7 +1287,7 @@ int launch_zero_slices(blsh_ctx *ctx, int64_t *cnt, hipStream_t s) {
 int launch_acc_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t *nxt_cnt, int64_t *nxt_total, bool last,
                      hipStream_t s) {
   LaunchScope ls(ctx, s, "acc_flush");
-  hipLaunchKernelGGL(k_acc_flush, dim3(kSlices), dim3(kBlock), 0, s, a, nxt_cnt, nxt_total, int(last));
+  hipLaunchKernelGGL(k_acc_flush, dim3(kSlices * kFlushParts), dim3(kBlock), 0, s, a, nxt_cnt, nxt_total, int(last));
   return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
