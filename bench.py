@@ -560,7 +560,7 @@ def run_sigs(args, torch, P):
 DENSE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "verify_dense_1m_traffic.txt")
 DENSE_KERNEL_SOURCES = ("paper_1110_1328_amd/csrc/verify.hip", "paper_1110_1328_amd/csrc/device_common.h")
 # the verification call's kernels, by the names their launches are profiled under
-TILE_KERNELS = ("verify_tiles", "verify_rows", "acc_flush")
+TILE_KERNELS = ("verify_tiles", "tiles_flush")
 PAIR_KERNELS = ("verify_bits_prefix", "verify_tail", "acc_flush")
 
 
@@ -666,12 +666,11 @@ def run_dense(args, torch, P):
 
     # the candidates as bucket tiles (banding once to size its buffers, then timed)
     tile_cap = 1 << 25
-    mem = torch.empty(16 * n_obj, dtype=torch.int32, device="cuda").view(torch.uint32)
-    tl = torch.empty(tile_cap * 8, dtype=torch.int64, device="cuda")
-    P.bayeslsh_band_tiles(ctx, S_band, 16, 12, tile_cap, members_out=mem, tiles_out=tl)
+    tl = torch.empty(tile_cap * 24, dtype=torch.int64, device="cuda")
+    P.bayeslsh_band_tiles(ctx, S_band, 16, 12, tile_cap, tiles_out=tl)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, _, n_tiles, n, trunc = P.bayeslsh_band_tiles(ctx, S_band, 16, 12, tile_cap, members_out=mem, tiles_out=tl)
+    _, n_tiles, n, trunc = P.bayeslsh_band_tiles(ctx, S_band, 16, 12, tile_cap, tiles_out=tl)
     band_tiles_ms = (time.perf_counter() - t0) * 1e3
     assert not trunc, n_tiles
     log("banding as tiles: %d candidates in %d tiles, %.1f ms" % (n, n_tiles, band_tiles_ms))
@@ -689,7 +688,7 @@ def run_dense(args, torch, P):
     acc_cap = 1 << 28
 
     # headline: Algorithm 1 over the tiles
-    cand_t = P.tiles(mem, tl, n_tiles, n)
+    cand_t = P.tiles(tl, n_tiles, n)
     res = P.make_result(n, acc_cap)
 
     def step():
@@ -793,11 +792,9 @@ def run_dense(args, torch, P):
     # owns ids, code and levels 0-3, the tail the rest.
     chunk = 2 * (k // 8)
     accepted = dec_counts[1] + dec_counts[2]
-    id_bytes_t = n_tiles * (64 + 32 * 4)
+    id_bytes_t = n_tiles * 192
     call_bytes = id_bytes_t + n + chunk * levels_reached + 12 * accepted
-    per = {"verify_tiles": id_bytes_t + n + chunk * n,
-           "verify_rows": chunk * (levels_reached - n) + 12 * accepted,
-           "acc_flush": 12 * accepted}
+    per = {"verify_tiles": id_bytes_t + n + chunk * levels_reached + 12 * accepted, "tiles_flush": 12 * accepted}
     per_p = {"verify_bits_prefix": 9 * n + chunk * (levels_reached - levels_past_prefix),
              "verify_tail": chunk * levels_past_prefix + 12 * accepted, "acc_flush": 12 * accepted}
 
@@ -807,7 +804,7 @@ def run_dense(args, torch, P):
                 for k_, v in pr.items()}
 
     kern_ms = sum(v["ms_per_step"] for v in prof.values())
-    dom = max(("verify_tiles", "verify_rows"), key=lambda k_: prof[k_]["ms_per_step"])
+    dom = "verify_tiles"
     launches = prof[dom]["launches_per_step"]
     dom_bytes = per[dom] / launches
     achieved = dom_bytes / (prof[dom]["avg_ms"] * 1e-3) / 1e9
@@ -824,8 +821,8 @@ def run_dense(args, torch, P):
                  "frac": call_bytes / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                  "traffic": measured_traffic_of(DENSE_TRAFFIC_FILE, DENSE_KERNEL_SOURCES, "traffic_bytes_per_call")},
         "bytes_model": "per candidate 1 B code + 8 B per level reached (4 B chunk per side at k = 32) + 12 B per "
-                       "emitted pair, plus 64 B descriptor + 32 x 4 B member ids per tile; the tile kernel owns "
-                       "ids, code and level 0, the row kernel the later levels and the emission",
+                       "emitted pair, plus the 192 B descriptor (member ids included) per tile; the tile kernel "
+                       "does all of it, the flush copies the staged accepted pairs to the caller's list",
     }
     ctx.close()
     return {

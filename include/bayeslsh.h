@@ -84,14 +84,15 @@ typedef enum {
 
 /* One 16 x 16 tile of an LSH bucket's member pairs (Section 2 banding, written
  * by bayeslsh_band_tiles).  Position p = 16 r + c (r, c in [0, 16)) stands for
- * the pair (members[row0 + r], members[col0 + c]); it is a candidate iff bit
- * p % 64 of keep[p / 64] is set, and the candidates of the tile are numbered
- * first, first + 1, ... in increasing p.  64 bytes. */
+ * the pair (ids[r], ids[16 + c]): row r's member and column c's member; it is
+ * a candidate iff bit p % 64 of keep[p / 64] is set, and the candidates of the
+ * tile are numbered first, first + 1, ... in increasing p.  192 bytes. */
 typedef struct {
-  int64_t first;          /* candidate index of the tile's first candidate      */
-  int64_t row0, col0;     /* positions in members[] of tile row 0 and column 0   */
-  uint32_t n_rows, n_cols; /* members on the tile's rows / columns, 1..16        */
-  uint64_t keep[4];       /* the candidate positions (row-major bit mask)        */
+  int64_t first;           /* candidate index of the tile's first candidate         */
+  uint32_t n_rows, n_cols; /* members on the tile's rows / columns, 1..16           */
+  uint64_t keep[4];        /* the candidate positions (row-major bit mask)          */
+  uint32_t ids[32];        /* object ids: rows 0..15, then columns 0..15            */
+  uint32_t reserved[4];
 } blsh_tile;
 
 /* Vector kinds for exact similarity (Alg. 2) and signature generation. */
@@ -135,9 +136,7 @@ typedef struct {
   int64_t n_cand;                /* QUERY_LISTS: offsets[n_lists] (host copy of the total);
                                     TILES: the number of candidates the tiles hold */
   int64_t all_n;                 /* ALL_PAIRS                 */
-  const uint32_t *members;       /* TILES: [n_members] object ids the tiles point into */
-  int64_t n_members;
-  const blsh_tile *tiles;        /* TILES: [n_tiles], in increasing `first` order */
+  const blsh_tile *tiles;        /* TILES: [n_tiles], 16-byte aligned */
   int64_t n_tiles;
 } blsh_candidates;
 
@@ -306,13 +305,12 @@ int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *plan
  * signatures must be OBJECT_MAJOR with n_hashes % 4 == 0.
  * BLSH_TILES candidates (SRP only): OBJECT_MAJOR rows, 16-byte aligned, of a
  * multiple of 128 hashes, n_max a multiple of 128 up to 2048.  A wave takes a
- * tile: it loads the 32 members' first-level words once and decides level 0
- * for the tile's pairs; the pairs it does not prune are finished over whole
- * rows (one 128-byte line per side per 128 hashes).  Malformed tiles are
- * reported at the next bayeslsh_sync: candidate numbers outside [0, n_cand)
- * are skipped, and pairs at positions outside members[] or past the tile's
- * n_rows / n_cols get code 0xFF (BLSH_EINVAL); a member id >= n_obj gives its
- * pairs code 0xFF (BLSH_EBADID). */
+ * tile: it stages the first n_max hashes of its 32 members in LDS (one load
+ * per 128-byte line), decides level 0 for the tile's pairs and finishes the
+ * pairs level 0 does not prune from those rows.  Malformed tiles are reported
+ * at the next bayeslsh_sync: candidate numbers outside [0, n_cand) are
+ * skipped and positions past the tile's n_rows / n_cols get code 0xFF
+ * (BLSH_EINVAL); a member id >= n_obj gives its pairs code 0xFF (BLSH_EBADID). */
 int bayeslsh_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, double t,
                     double epsilon, double delta, double gamma, blsh_prior prior, int32_t k,
                     blsh_result *res, void *stream);
@@ -378,22 +376,20 @@ int bayeslsh_band_candidates(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t 
 
 /* LSH banding (Section 2) as bucket tiles: the candidates of
  * bayeslsh_band_candidates with order_tile = 16 -- the same pairs with the same
- * candidate indices -- handed over as each band's sorted member ids and one
- * blsh_tile per 16 x 16 tile of a bucket's member pairs, instead of one id pair
- * per candidate (about 0.3 B instead of 8 B per candidate).
- *   members_out  device uint32[n_bands * n_obj]: band j's members at
- *                [j n_obj, (j+1) n_obj), bucket by bucket (keys increasing),
- *                members by increasing id (capacity below that: BLSH_EINVAL);
- *   tiles_out    device blsh_tile[tiles_capacity], band by band, buckets by
- *                increasing key, tile rows then tile columns;
+ * candidate indices -- handed over as one blsh_tile per 16 x 16 tile of a
+ * bucket's member pairs (the tile's 32 member ids, its keep mask and the index
+ * of its first candidate) instead of one id pair per candidate: 192 bytes per
+ * up to 256 candidates instead of 8 bytes per candidate.
+ *   tiles_out    device blsh_tile[tiles_capacity], 16-byte aligned: band by
+ *                band, buckets by increasing key, tile rows then tile columns;
  *   *n_tiles_host, *n_pairs_host  tiles and candidates; the call waits for
  *                `stream`.  More tiles than the capacity: the first
  *                tiles_capacity are written, BLSH_ETRUNCATED.
- * Pass the outputs as a BLSH_TILES candidate set (members, n_members =
- * n_bands * n_obj, tiles, n_tiles, n_cand = *n_pairs_host). */
+ * Pass the outputs as a BLSH_TILES candidate set (tiles, n_tiles, n_cand =
+ * *n_pairs_host). */
 int bayeslsh_band_tiles(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t n_bands, int32_t band_bits,
-                        int32_t max_bucket, uint32_t *members_out, int64_t members_capacity, blsh_tile *tiles_out,
-                        int64_t tiles_capacity, int64_t *n_tiles_host, int64_t *n_pairs_host, void *stream);
+                        int32_t max_bucket, blsh_tile *tiles_out, int64_t tiles_capacity, int64_t *n_tiles_host,
+                        int64_t *n_pairs_host, void *stream);
 
 /* Learned Jaccard prior (Section 4.1): Beta(alpha, beta) fitted to a random
  * sample of candidate-pair similarities s_1..s_r (host array) by the method

@@ -34,15 +34,15 @@ class Sigs(C.Structure):
 class Candidates(C.Structure):
     _fields_ = [("kind", C.c_int), ("x", p), ("y", p), ("n_pairs", C.c_int64), ("query", p), ("offsets", p),
                 ("cand", p), ("n_lists", C.c_int64), ("n_cand", C.c_int64), ("all_n", C.c_int64),
-                ("members", p), ("n_members", C.c_int64), ("tiles", p), ("n_tiles", C.c_int64)]
+                ("tiles", p), ("n_tiles", C.c_int64)]
 
 
 class Tile(C.Structure):
-    _fields_ = [("first", C.c_int64), ("row0", C.c_int64), ("col0", C.c_int64), ("n_rows", C.c_uint32),
-                ("n_cols", C.c_uint32), ("keep", C.c_uint64 * 4)]
+    _fields_ = [("first", C.c_int64), ("n_rows", C.c_uint32), ("n_cols", C.c_uint32), ("keep", C.c_uint64 * 4),
+                ("ids", C.c_uint32 * 32), ("reserved", C.c_uint32 * 4)]
 
 
-TILE_BYTES = 64
+TILE_BYTES = 192
 assert C.sizeof(Tile) == TILE_BYTES
 
 
@@ -110,8 +110,8 @@ PROTOTYPES = [
     ("bayeslsh_fit_prior", C.c_int, [p, C.c_int64, C.POINTER(Prior), C.POINTER(C.c_int32)]),
     ("bayeslsh_band_candidates", C.c_int, [p, C.POINTER(Sigs), C.c_int32, C.c_int32, C.c_int32, C.c_int32, p, p, C.c_int64,
                                            C.POINTER(C.c_int64), p]),
-    ("bayeslsh_band_tiles", C.c_int, [p, C.POINTER(Sigs), C.c_int32, C.c_int32, C.c_int32, p, C.c_int64, p,
-                                      C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64), p]),
+    ("bayeslsh_band_tiles", C.c_int, [p, C.POINTER(Sigs), C.c_int32, C.c_int32, C.c_int32, p, C.c_int64,
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64), p]),
     ("bayeslsh_verify_batched", C.c_int,
      [p, C.POINTER(ListDesc), C.c_int64, p, C.c_int64, C.POINTER(Sigs), C.POINTER(Sigs), C.c_double, C.c_double,
       C.c_double, Prior, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Result), p]),

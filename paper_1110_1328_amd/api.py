@@ -106,7 +106,6 @@ class Candidates:
     cand: torch.Tensor = None
     n_cand: int = 0
     all_n: int = 0
-    members: torch.Tensor = None
     tiles: torch.Tensor = None
     n_tiles: int = 0
 
@@ -120,7 +119,7 @@ class Candidates:
 
     def struct(self):
         return _cached(self, self._build, self.kind, self.x, self.y, self.query, self.offsets, self.cand, self.n_cand,
-                       self.all_n, self.members, self.tiles, self.n_tiles)
+                       self.all_n, self.tiles, self.n_tiles)
 
     def _build(self):
         c = A.Candidates()
@@ -138,22 +137,20 @@ class Candidates:
             c.query, c.offsets, c.cand = _p(self.query), _p(self.offsets), _p(self.cand)
             c.n_lists, c.n_cand = self.query.numel(), self.n_cand
         elif self.kind == TILES:
-            _dev(self.members, torch.uint32, "members")
             if self.tiles.device.type != "cuda" or not self.tiles.is_contiguous():
                 raise ValueError("tiles: contiguous device tensor expected")
             if self.tiles.numel() * self.tiles.element_size() < self.n_tiles * A.TILE_BYTES:
                 raise ValueError("tiles: tensor smaller than n_tiles descriptors")
-            c.members, c.n_members = _p(self.members), self.members.numel()
             c.tiles, c.n_tiles, c.n_cand = _p(self.tiles), self.n_tiles, self.n_cand
         else:
             c.all_n = self.all_n
         return c
 
 
-def tiles(members: torch.Tensor, tiles_buf: torch.Tensor, n_tiles: int, n_cand: int) -> Candidates:
-    """BLSH_TILES candidates from bayeslsh_band_tiles' outputs (tiles_buf: a
-    device byte or int64 tensor holding n_tiles 64-byte descriptors)."""
-    return Candidates(TILES, members=members, tiles=tiles_buf, n_tiles=int(n_tiles), n_cand=int(n_cand))
+def tiles(tiles_buf: torch.Tensor, n_tiles: int, n_cand: int) -> Candidates:
+    """BLSH_TILES candidates from bayeslsh_band_tiles' output (tiles_buf: a
+    device tensor holding n_tiles 192-byte descriptors, 16-byte aligned)."""
+    return Candidates(TILES, tiles=tiles_buf, n_tiles=int(n_tiles), n_cand=int(n_cand))
 
 
 def pairs(x: torch.Tensor, y: torch.Tensor) -> Candidates:
@@ -493,30 +490,24 @@ def bayeslsh_band_candidates(ctx: Context, band_sigs: Signatures, n_bands: int, 
 
 
 def bayeslsh_band_tiles(ctx: Context, band_sigs: Signatures, n_bands: int, band_bits: int, tile_capacity: int,
-                        max_bucket: int = 0, members_out: torch.Tensor = None, tiles_out: torch.Tensor = None,
-                        stream=None):
+                        max_bucket: int = 0, tiles_out: torch.Tensor = None, stream=None):
     """LSH banding as bucket tiles (the order_tile = 16 candidates, same
-    numbering).  Returns (members, tiles, n_tiles, n_pairs, truncated):
-    members a uint32 device tensor of n_bands * n_obj ids, tiles an int64 device
-    tensor of tile_capacity 64-byte descriptors (8 int64 each); pass
-    tiles(members, tiles, n_tiles, n_pairs) to bayeslsh_verify."""
-    n_mem = n_bands * band_sigs.n_obj
-    if members_out is None:
-        members_out = torch.empty(max(n_mem, 1), dtype=torch.int32, device="cuda").view(torch.uint32)
+    numbering).  Returns (tiles, n_tiles, n_pairs, truncated): tiles an int64
+    device tensor of tile_capacity 192-byte descriptors (24 int64 each); pass
+    tiles(tiles, n_tiles, n_pairs) to bayeslsh_verify."""
+    words = A.TILE_BYTES // 8
     if tiles_out is None:
-        tiles_out = torch.empty(max(tile_capacity, 1) * (A.TILE_BYTES // 8), dtype=torch.int64, device="cuda")
-    _dev(members_out, torch.uint32, "members_out")
+        tiles_out = torch.empty(max(tile_capacity, 1) * words, dtype=torch.int64, device="cuda")
     if tiles_out.numel() * tiles_out.element_size() < tile_capacity * A.TILE_BYTES:
         raise ValueError("tiles_out smaller than tile_capacity descriptors")
     st = band_sigs.struct()
     nt, npairs = C.c_int64(0), C.c_int64(0)
-    rc = _lib().bayeslsh_band_tiles(ctx.handle, C.byref(st), n_bands, band_bits, max_bucket, _p(members_out),
-                                    members_out.numel(), _p(tiles_out), tile_capacity, C.byref(nt), C.byref(npairs),
-                                    _stream(stream))
+    rc = _lib().bayeslsh_band_tiles(ctx.handle, C.byref(st), n_bands, band_bits, max_bucket, _p(tiles_out),
+                                    tile_capacity, C.byref(nt), C.byref(npairs), _stream(stream))
     if rc == A.ETRUNCATED:
-        return members_out, tiles_out, nt.value, npairs.value, True
+        return tiles_out, nt.value, npairs.value, True
     _check(rc)
-    return members_out, tiles_out, nt.value, npairs.value, False
+    return tiles_out, nt.value, npairs.value, False
 
 
 def bayeslsh_fit_prior(sims) -> tuple:

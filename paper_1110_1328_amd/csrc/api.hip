@@ -24,8 +24,10 @@ int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStrea
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s);
 int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, int words, hipStream_t s);
 int launch_zero_slices(blsh_ctx *ctx, int64_t *cnt, hipStream_t s);
-int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s);
-int launch_verify_rows(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals,
+int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals,
+                        int64_t grid_waves, hipStream_t s);
+int tiles_grid_waves(blsh_ctx *ctx, int k, int n_max, bool intervals, size_t lds, int64_t *waves);
+int launch_tiles_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t grid_waves, int64_t *off, bool last,
                        hipStream_t s);
 int launch_acc_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t *nxt_cnt, int64_t *nxt_total, bool last,
                      hipStream_t s);
@@ -205,11 +207,9 @@ static int check_cand(const blsh_candidates *c, int64_t *n_cand) {
       if (c->all_n < 2) *n_cand = 0;
       return BLSH_OK;
     case BLSH_TILES:
-      if (c->n_tiles < 0 || c->n_cand < 0 || c->n_members < 0) return fail(BLSH_EINVAL, "candidates: negative tile sizes");
-      if (c->n_tiles > 0 && (!c->tiles || !c->members || c->n_members == 0))
-        return fail(BLSH_EINVAL, "candidates: null tiles or members");
-      if (c->n_cand > c->n_tiles * 256) return fail(BLSH_EINVAL, "candidates: n_cand exceeds 256 per tile");
-      if (uintptr_t(c->tiles) & 7) return fail(BLSH_EINVAL, "candidates: tiles must be 8-byte aligned");
+      if (c->n_tiles < 0 || c->n_cand < 0) return fail(BLSH_EINVAL, "candidates: negative tile sizes");
+      if (c->n_tiles > 0 && !c->tiles) return fail(BLSH_EINVAL, "candidates: null tiles");
+      if (uintptr_t(c->tiles) & 15) return fail(BLSH_EINVAL, "candidates: tiles must be 16-byte aligned");
       *n_cand = c->n_cand;
       return BLSH_OK;
     default:
@@ -377,61 +377,48 @@ static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
 
 // Shared driver of verify / lite / exhaustive.
 // Algorithm 1 over BLSH_TILES candidates: launches of at most kTilesChunk
-// tiles, each [k_verify_tiles (level 0; survivors queued with their ids),
-// k_verify_rows (the survivors over whole rows), k_acc_flush].  Workspace:
-// kSlices survivor slices of 16-byte entries, each sized for the most a
-// launch puts in it (a wave takes one tile, 256 candidates at most, and wave
-// w uses slice w % kSlices), and the accepted-pair staging.
-static constexpr int64_t kTilesChunk = int64_t(1) << 19;
+// tiles (their candidates, at most 256 each, stay below 2^32 relative to the
+// launch's first), each [k_verify_tiles, k_tiles_scan, k_tiles_copy].  The
+// tile kernel runs on a persistent grid, each wave with a staging region of
+// its own (no atomics; kTilesStage entries in all); the running accepted count
+// sits in the context's counter buffer.
+static constexpr int64_t kTilesChunk = int64_t(1) << 20;
+static constexpr int64_t kTilesStage = int64_t(1) << 25;
 
 static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, int k, int n_max, int n_levels,
                      bool intervals, hipStream_t s) {
-  const int64_t S = kSlices;
-  const int64_t chunk = std::min<int64_t>(cand->n_tiles, kTilesChunk);
-  const int64_t waves = (chunk + 3) / 4 * 4;
-  const int64_t q_cap = (waves + S - 1) / S * 256;
-  const int64_t stage = ctx->tuning.acc_stage_cap > 0 ? int64_t(ctx->tuning.acc_stage_cap) : kStageDefault;
-  const int64_t st_cap = (std::min<int64_t>(chunk * 256, stage) + S - 1) / S;
-  const size_t q_bytes = align256(size_t(S) * q_cap * 16);
-  const size_t st_bytes = align256(size_t(S) * st_cap * 4);
-  int rc = ensure_workspace(ctx, q_bytes + 2 * st_bytes);
+  const int words = (n_levels * k + 1 + 31) / 32;
+  int64_t waves = 0;
+  int rc = tiles_grid_waves(ctx, k, n_max, intervals, size_t(n_levels) * words * 4, &waves);
   if (rc) return rc;
+  const int64_t stage = ctx->tuning.acc_stage_cap > 0 ? int64_t(ctx->tuning.acc_stage_cap) : kTilesStage;
+  const int64_t st_cap = std::max<int64_t>(1, stage / waves);   // entries per wave region
+  const size_t st_bytes = align256(size_t(waves) * st_cap * 4);
+  const size_t cnt_bytes = align256(size_t(waves) * 4), off_bytes = align256(size_t(waves) * 8);
+  if ((rc = ensure_workspace(ctx, 2 * st_bytes + cnt_bytes + off_bytes))) return rc;
   char *p = static_cast<char *>(ctx->ws);
-  int64_t *cnt = ctx->d_slices;
-  a.q_ent = reinterpret_cast<u32x4 *>(p);
-  a.q_cap = q_cap;
-  a.q_cnt = cnt + size_t(2) * kSlices * kCntStride;
-  a.st_rel = reinterpret_cast<uint32_t *>(p + q_bytes);
-  a.st_val = reinterpret_cast<float *>(p + q_bytes + st_bytes);
+  a.st_rel = reinterpret_cast<uint32_t *>(p);
+  a.st_val = reinterpret_cast<float *>(p + st_bytes);
   a.st_cap = st_cap;
+  a.wst_cnt = reinterpret_cast<uint32_t *>(p + 2 * st_bytes);
+  int64_t *off = reinterpret_cast<int64_t *>(p + 2 * st_bytes + cnt_bytes);
   a.tiles = cand->tiles;
-  a.members = cand->members;
-  a.n_members = cand->n_members;
   a.n_cand = cand->n_cand;
   a.c_begin = 0;
   a.pfx = nullptr;
-  if (ctx->slices_dirty) {
-    if ((rc = launch_zero_slices(ctx, cnt, s))) return fail(rc, "launch failed");
-    ctx->slices_dirty = false;
-  }
-  const int words = (n_levels * k + 1 + 31) / 32;
-  auto set_cnt = [&](int st) { return cnt + size_t(st) * kSlices * kCntStride; };
-  auto set_total = [&](int st) { return cnt + (size_t(3) * kSlices + st) * kCntStride; };
-  for (int64_t t0 = 0; t0 < cand->n_tiles; t0 += chunk) {
+  a.st_raw = 1;
+  // the running accepted count: the context's counter of staging set 0
+  a.acc_total = ctx->d_slices + (size_t(3) * kSlices) * kCntStride;
+  if ((rc = launch_zero(ctx, a.acc_total, s))) return fail(rc, "launch failed");
+  ctx->slices_dirty = true;   // the single-call paths clear their counters before their next use
+  for (int64_t t0 = 0; t0 < cand->n_tiles; t0 += kTilesChunk) {
     a.t_begin = t0;
-    a.t_end = std::min(cand->n_tiles, t0 + chunk);
+    a.t_end = std::min(cand->n_tiles, t0 + kTilesChunk);
     a.c_begin_dev = &cand->tiles[t0].first;
-    const int cur = ctx->slice_set, nxt = cur ^ 1;
-    a.acc_cnt = set_cnt(cur);
-    a.acc_total = set_total(cur);
-    ctx->slices_dirty = true;
-    rc = launch_verify_tiles(ctx, a, k, s);
-    if (!rc) rc = launch_verify_rows(ctx, a, k, n_max, words, intervals, s);
-    if (!rc) rc = launch_acc_flush(ctx, a, set_cnt(nxt), set_total(nxt), a.t_end == cand->n_tiles, s);
+    rc = launch_verify_tiles(ctx, a, k, n_max, words, intervals, waves, s);
+    if (!rc) rc = launch_tiles_flush(ctx, a, waves, off, a.t_end == cand->n_tiles, s);
     if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;
-    ctx->slice_set = nxt;
   }
-  ctx->slices_dirty = false;
   return BLSH_OK;
 }
 
@@ -909,8 +896,8 @@ int bayeslsh_band_candidates(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t 
 }
 
 int bayeslsh_band_tiles(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t n_bands, int32_t band_bits,
-                        int32_t max_bucket, uint32_t *members_out, int64_t members_capacity, blsh_tile *tiles_out,
-                        int64_t tiles_capacity, int64_t *n_tiles_host, int64_t *n_pairs_host, void *stream) {
+                        int32_t max_bucket, blsh_tile *tiles_out, int64_t tiles_capacity, int64_t *n_tiles_host,
+                        int64_t *n_pairs_host, void *stream) {
   if (!ctx) return fail(BLSH_EINVAL, "null context");
   if (!n_pairs_host || !n_tiles_host) return fail(BLSH_EINVAL, "n_tiles_host / n_pairs_host: null");
   *n_pairs_host = 0;
@@ -926,12 +913,9 @@ int bayeslsh_band_tiles(blsh_ctx *ctx, const blsh_sigs *band_sigs, int32_t n_ban
   if (int64_t(n_bands) * band_bits > g->n_hashes)
     return fail(BLSH_EINVAL, "banding: n_bands * band_bits (%d) > n_hashes (%d)", n_bands * band_bits, g->n_hashes);
   if (max_bucket < 0 || tiles_capacity < 0) return fail(BLSH_EINVAL, "banding: negative max_bucket or capacity");
-  if (!members_out || members_capacity < int64_t(n_bands) * g->n_obj)
-    return fail(BLSH_EINVAL, "banding tiles: members_out must hold n_bands * n_obj = %lld ids",
-                (long long)(int64_t(n_bands) * g->n_obj));
   if (tiles_capacity > 0 && !tiles_out) return fail(BLSH_EINVAL, "banding tiles: null tiles_out");
-  if (uintptr_t(tiles_out) & 7) return fail(BLSH_EINVAL, "banding tiles: tiles_out must be 8-byte aligned");
-  BandTilesOut to{members_out, members_capacity, tiles_out, tiles_capacity, n_tiles_host};
+  if (uintptr_t(tiles_out) & 15) return fail(BLSH_EINVAL, "banding tiles: tiles_out must be 16-byte aligned");
+  BandTilesOut to{tiles_out, tiles_capacity, n_tiles_host};
   return band_candidates(ctx, g->data, g->n_obj, g->n_hashes / 32, g->layout == BLSH_WORD_MAJOR, n_bands, band_bits,
                          max_bucket, 16, nullptr, nullptr, 0, n_pairs_host, static_cast<hipStream_t>(stream), &to);
 }

@@ -364,22 +364,19 @@ __device__ inline uint64_t spread4(uint64_t x) {
 }
 
 // Tile descriptors of a band (one thread per tile): the tile's first
-// candidate index (the band's running pair count plus the tile's offset), the
-// positions of its row and column members in the members array (the band's
-// sorted ids start at member_base), their counts, and the keep mask in
-// row-major bit order (the count pass's ballot i holds position 4l + i at bit
-// l: word w of the mask takes lanes 16w .. 16w+15 of the four ballots,
-// interleaved).
-__global__ __launch_bounds__(kBandBlock) void k_band_tile_desc(TileArgs a, int64_t member_base, blsh_tile *out,
-                                                               int64_t out_base, int64_t out_cap) {
+// candidate index (the band's running pair count plus the tile's offset), its
+// row and column counts and member ids (the band's sorted ids), and the keep
+// mask in row-major bit order (the count pass's ballot i holds position
+// 4l + i at bit l: word w of the mask takes lanes 16w .. 16w+15 of the four
+// ballots, interleaved).
+__global__ __launch_bounds__(kBandBlock) void k_band_tile_desc(TileArgs a, blsh_tile *out, int64_t out_base,
+                                                               int64_t out_cap) {
   const int64_t t = int64_t(blockIdx.x) * kBandBlock + threadIdx.x;
   if (t >= a.n_tiles || out_base + t >= out_cap) return;
   const TileAt T = tile_at(a, t, 0);
   const int64_t ta = T.ar / kTile;
   blsh_tile d;
   d.first = *a.base + a.tcoff[t];
-  d.row0 = member_base + T.p0 + ta * kTile;
-  d.col0 = member_base + T.p0 + T.tb * kTile;
   d.n_rows = uint32_t(min<int64_t>(kTile, T.len - ta * kTile));
   d.n_cols = uint32_t(min<int64_t>(kTile, T.len - T.tb * kTile));
   const uint64_t b0 = a.tmask[4 * t], b1 = a.tmask[4 * t + 1], b2 = a.tmask[4 * t + 2], b3 = a.tmask[4 * t + 3];
@@ -387,6 +384,11 @@ __global__ __launch_bounds__(kBandBlock) void k_band_tile_desc(TileArgs a, int64
   for (int w = 0; w < 4; ++w)
     d.keep[w] = spread4(b0 >> (16 * w)) | (spread4(b1 >> (16 * w)) << 1) | (spread4(b2 >> (16 * w)) << 2) |
                 (spread4(b3 >> (16 * w)) << 3);
+  for (int i = 0; i < kTile; ++i) {
+    d.ids[i] = i < int(d.n_rows) ? a.sids[T.p0 + ta * kTile + i] : 0xFFFFFFFFu;
+    d.ids[kTile + i] = i < int(d.n_cols) ? a.sids[T.p0 + T.tb * kTile + i] : 0xFFFFFFFFu;
+  }
+  for (int i = 0; i < 4; ++i) d.reserved[i] = 0;
   out[out_base + t] = d;
 }
 
@@ -524,12 +526,10 @@ int band_candidates(blsh_ctx *ctx, const uint32_t *sig, int64_t n_obj, int32_t r
       if (rocprim::exclusive_scan(ttmp, t4, tcnt, tcoff, int64_t(0), size_t(n_tiles), rocprim::plus<int64_t>(), s) !=
           hipSuccess)
         return fail(BLSH_EDEVICE, "banding: scan failed");
-      if (to) {   // tiles instead of pairs: this band's members and tile descriptors
-        if (int64_t(j + 1) * n_obj <= to->member_cap)
-          BLSH_HIP(hipMemcpyAsync(to->members + size_t(j) * n, sids, n * 4, hipMemcpyDeviceToDevice, s));
+      if (to) {   // tiles instead of pairs: this band's tile descriptors
         const unsigned db = unsigned((n_tiles + kBandBlock - 1) / kBandBlock);
-        hipLaunchKernelGGL(k_band_tile_desc, dim3(db), dim3(kBandBlock), 0, s, ta, int64_t(j) * n_obj, to->tiles,
-                           tiles_total, to->tile_cap);
+        hipLaunchKernelGGL(k_band_tile_desc, dim3(db), dim3(kBandBlock), 0, s, ta, to->tiles, tiles_total,
+                           to->tile_cap);
         tiles_total += n_tiles;
       } else {
         hipLaunchKernelGGL(k_band_tiles<true>, dim3(tile_blocks), dim3(kBandBlock), 0, s, ta);

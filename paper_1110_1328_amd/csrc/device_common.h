@@ -71,15 +71,18 @@ struct VerifyArgs {
   int32_t count_levels;                  // levels compared in full (n_max/k)
   double t;
   // BLSH_TILES: the launch runs tiles [t_begin, t_end); its candidates start at
-  // *c_begin_dev (tiles[t_begin].first, read on the device; queue and staging
-  // indices are relative to it); n_cand bounds every candidate index written
+  // *c_begin_dev (tiles[t_begin].first, read on the device; staging indices
+  // are relative to it); n_cand bounds every candidate index written
   const blsh_tile *tiles;
-  const uint32_t *members;
-  int64_t n_members;
   int64_t t_begin, t_end;
   const int64_t *c_begin_dev;
   int64_t n_cand;
-  u32x4 *q_ent;                          // survivor entries {candidate - c_begin, x, y, 0}
+  // staging values are raw (m | n << 16, as the float's bits): the flush
+  // computes S_hat from them (tiles path)
+  int32_t st_raw;
+  // tiles path: the staging holds one region of st_cap entries per wave of the
+  // persistent grid, filled in order; wave w leaves its count in wst_cnt[w]
+  uint32_t *wst_cnt;
 };
 
 // First candidate of the launch: a host value, or for tiles a device value.
@@ -161,12 +164,17 @@ __device__ inline bool fetch_candidate(const VerifyArgs &a, int64_t c, uint32_t 
 
 // cos(x) for x in [0, pi/2] from its Taylor series through x^24 (truncation
 // below (pi/2)^26 / 26! < 2e-21), in Horner form: a few registers, no range
-// reduction.
+// reduction.  The factors 1/((2i-1) 2i) are compile-time constants, so each
+// term is one multiply and one fused multiply-add (no FP64 division).
 __device__ inline double cos_quarter(double x) {
   const double x2 = x * x;
   double c = 1.0;
 #pragma unroll
-  for (int i = 12; i >= 1; --i) c = 1.0 - c * x2 / double((2 * i - 1) * (2 * i));
+  for (int i = 12; i >= 1; --i) {
+    constexpr double one = 1.0;
+    const double inv = one / double((2 * i - 1) * (2 * i));   // folded: i is a constant after unrolling
+    c = __builtin_fma(-c * x2, inv, 1.0);
+  }
   return c;
 }
 
@@ -318,6 +326,32 @@ __device__ inline uint32_t group_sum(uint32_t v) {
   if constexpr (G >= 8) v += dpp<kDppHalfMirror>(v);
   if constexpr (G >= 16) v += dpp<kDppRowMirror>(v);
   return v;
+}
+
+// Minimum over aligned groups of G lanes (G in {1,2,4,8,16}); every lane of
+// the group receives it.  All lanes of the wave must be active.
+template <int G>
+__device__ inline uint32_t group_min(uint32_t v) {
+  if constexpr (G >= 2) v = min(v, dpp<kDppQuadXor1>(v));
+  if constexpr (G >= 4) v = min(v, dpp<kDppQuadXor2>(v));
+  if constexpr (G >= 8) v = min(v, dpp<kDppHalfMirror>(v));
+  if constexpr (G >= 16) v = min(v, dpp<kDppRowMirror>(v));
+  return v;
+}
+
+// Exclusive prefix sum within aligned groups of G lanes (G in {1,2,4,8,16}),
+// lane r of a group receiving the sum of lanes 0 .. r-1 (row shifts within
+// rows of 16 lanes; a lane adds a shifted value only from its own group).
+// All lanes of the wave must be active.
+template <int G>
+__device__ inline uint32_t group_excl_scan(uint32_t v) {
+  const int r = int(__lane_id()) & (G - 1);
+  uint32_t incl = v;
+  if constexpr (G >= 2) { const uint32_t u = uint32_t(__builtin_amdgcn_update_dpp(0, int(incl), 0x111, 0xF, 0xF, true)); if (r >= 1) incl += u; }
+  if constexpr (G >= 4) { const uint32_t u = uint32_t(__builtin_amdgcn_update_dpp(0, int(incl), 0x112, 0xF, 0xF, true)); if (r >= 2) incl += u; }
+  if constexpr (G >= 8) { const uint32_t u = uint32_t(__builtin_amdgcn_update_dpp(0, int(incl), 0x114, 0xF, 0xF, true)); if (r >= 4) incl += u; }
+  if constexpr (G >= 16) { const uint32_t u = uint32_t(__builtin_amdgcn_update_dpp(0, int(incl), 0x118, 0xF, 0xF, true)); if (r >= 8) incl += u; }
+  return incl - v;
 }
 
 // Broadcast lane (group base + S) within aligned groups of G lanes (G <= 16).

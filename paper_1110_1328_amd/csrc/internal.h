@@ -123,11 +123,9 @@ int get_table(blsh_ctx *ctx, const TableKey &key, std::shared_ptr<HostTable> *ho
               hipStream_t stream);
 int ensure_workspace(blsh_ctx *ctx, size_t bytes);
 
-// Tiles output of the banding (bayeslsh_band_tiles): each band's sorted
-// member ids at members[band * n_obj ...] and the tile descriptors of all bands.
+// Tiles output of the banding (bayeslsh_band_tiles): the tile descriptors of
+// all bands.
 struct BandTilesOut {
-  uint32_t *members;
-  int64_t member_cap;
   blsh_tile *tiles;
   int64_t tile_cap;
   int64_t *n_tiles;   // host

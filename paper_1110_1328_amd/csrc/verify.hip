@@ -28,6 +28,9 @@
 // Survivor queues and the accepted-pair staging are split into slices whose
 // counters sit on separate cache lines (device-common helpers): one counter
 // for a whole launch would serialise every wave's atomic.
+#include <map>
+#include <mutex>
+
 #include "device_common.h"
 
 namespace blsh {
@@ -643,226 +646,298 @@ __global__ __launch_bounds__(kBlock) void k_exact_pairs(VerifyArgs a, double *ou
 }
 
 // ---------------------------------------------------------------------------
-// Bucket tiles (BLSH_TILES, SRP): one wave per 16 x 16 tile of a bucket's
-// member pairs.  Lanes 0..15 load the ids of the tile's row members and lanes
-// 16..31 those of its column members (consecutive positions of the band's
-// sorted ids), then each of these lanes the first level's words of its object
-// (one cache line per object, 32 per tile instead of two gathers per pair).
-// Lane l owns the tile positions p = 4l .. 4l+3 (row l/4, columns 4(l%4) ..
-// 4(l%4)+3) and takes both sides' words from the loading lanes by lane
-// permutation.  Level 0 is decided here; the candidates it does not prune go,
-// with their two ids, to the survivor queue, where k_verify_rows runs
-// Algorithm 1 on them from level 0 over whole rows.
+// Bucket tiles (BLSH_TILES, SRP): a wave takes one 16 x 16 tile of a bucket's
+// member pairs at a time.
+//   stage   the first n_max hashes (NW words) of the tile's 32 members go to
+//           the wave's LDS: 16-byte chunks, consecutive lanes on consecutive
+//           chunks of a row, so each 128-byte line is one load -- 32 lines per
+//           tile instead of two gathers per pair;
+//   level 0 lane l owns positions p = 4l .. 4l+3 (row l/4, columns 4(l%4) ..
+//           4(l%4)+3) and decides level 0 from the staged first words; the
+//           positions it does not prune are listed in LDS;
+//   rest    groups of P2 lanes take the listed pairs, each lane WPL words of
+//           both rows from LDS (128/K levels per 4 words), count agreements
+//           per level, prefix them across the group and find the first level
+//           that decides (prune below minMatches; accept at or above the
+//           minimum accepting m, or by the accept bits when a level's accept
+//           set is not an interval; n_max); the group takes the earliest.
+// Waves are persistent; the waves of an XCD sweep contiguous windows of tiles
+// together, so a bucket's rows stay in that XCD's L2 while its tiles pass.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kNoObject = 0xFFFFFFFFu;   // lane holds no (valid) object
+constexpr uint32_t kNoObject = 0xFFFFFFFFu;
+constexpr int kTileWords = int(sizeof(blsh_tile) / 4);   // 48: the descriptor, one dword per lane
+static_assert(sizeof(blsh_tile) == 192, "tile descriptor layout");
 
-// Wave-level compaction of a lane's P survivor entries (bit p of `want`) into
-// the tiles survivor queue, one atomic per wave.
-template <int P>
-__device__ inline void push_entries(const VerifyArgs &a, uint32_t want, const u32x4 *e) {
-  uint64_t mask[P];
-  uint32_t total = 0;
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    mask[p] = __ballot((want >> p) & 1u);
-    total += uint32_t(__popcll(mask[p]));
-  }
-  if (total == 0) return;
-  const int s = wave_slice();
-  int64_t base = queue_reserve(a, s, total, 0);
-  u32x4 *q = a.q_ent + size_t(s) * a.q_cap;
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    if ((want >> p) & 1u) {
-      const int64_t pos = base + lanes_below(mask[p]);
-      if (pos < a.q_cap) q[pos] = e[p];
-      else raise_status(a.status, BLSH_EDEVICE);
-    }
-    base += __popcll(mask[p]);
-  }
-}
+// LDS of one wave: the tile's rows (padded by 4 words so that the groups'
+// 16-byte reads of different rows spread over the banks), the listed pairs
+// (rank << 8 | position) and the tile's codes by rank.
+template <int NW>
+struct TileLds {
+  uint32_t rows[32][NW + 4];
+  uint16_t list[256 + kWave];   // entries 256.. take the stores of lanes with nothing to list
+  uint8_t code[256 + kWave];    // by rank; 256.. as for list
+};
 
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
-  const int lane = lane_id();
-  const int64_t t = a.t_begin + xcd_tile(blockIdx.x, gridDim.x) * (kBlock / kWave) +
-                    __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
-  if (t >= a.t_end) return;   // whole wave
-  const blsh_tile *T = a.tiles + t;
-  const int64_t cb = *a.c_begin_dev;
-  const int64_t first = T->first;
-  const uint64_t keep0 = T->keep[0], keep1 = T->keep[1], keep2 = T->keep[2], keep3 = T->keep[3];
-  const int min0 = int(a.table[kTabMinOff]);
-
-  const int n_rows = int(T->n_rows), n_cols = int(T->n_cols);
-  // the tile's 32 objects: id and level-0 words (K = 64: two words); an id
-  // >= n_obj is a bad id (BLSH_EBADID), a position outside members[] a
-  // malformed tile (BLSH_EINVAL); either leaves the lane without an object
-  uint32_t id = kNoObject, w0 = 0, w1 = 0;
-  if (lane < 32) {
-    const bool row = lane < 16;
-    const int o = lane & 15;
-    const int64_t pos = (row ? T->row0 : T->col0) + o;
-    if (o < (row ? n_rows : n_cols)) {
-      if (pos >= 0 && pos < a.n_members) {
-        const uint32_t v = a.members[pos];
-        if (v < a.n_obj) {
-          id = v;
-          if constexpr (K == 64) {
-            const uint2 h = *reinterpret_cast<const uint2 *>(a.sig + size_t(v) * a.row_words);
-            w0 = h.x;
-            w1 = h.y;
-          } else {
-            w0 = a.sig[size_t(v) * a.row_words];
-          }
-        } else {
-          raise_status(a.status, BLSH_EBADID);
-        }
-      } else {
-        raise_status(a.status, BLSH_EINVAL);
-      }
-    }
-  }
-  const int r = lane >> 2, c0 = 16 + 4 * (lane & 3);
-  const uint32_t xid = __shfl(id, r), xw0 = __shfl(w0, r);
-  const uint32_t xw1 = K == 64 ? __shfl(w1, r) : 0u;
-  uint32_t yid[4], yw0[4], yw1[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    yid[i] = __shfl(id, c0 + i);
-    yw0[i] = __shfl(w0, c0 + i);
-    yw1[i] = K == 64 ? __shfl(w1, c0 + i) : 0u;
-  }
-  // this lane's positions 4l .. 4l+3: bits of keep word l/16; their numbers
-  // follow the set bits of every earlier position
-  const int kw = lane >> 4, sh = 4 * (lane & 15);
-  const uint64_t mine = kw == 0 ? keep0 : kw == 1 ? keep1 : kw == 2 ? keep2 : keep3;
-  const int before = (kw > 0 ? __popcll(keep0) : 0) + (kw > 1 ? __popcll(keep1) : 0) + (kw > 2 ? __popcll(keep2) : 0);
-  const uint32_t kb = uint32_t(mine >> sh) & 0xFu;
-  int64_t rank = first + before + __popcll(sh ? (mine & ((1ull << sh) - 1ull)) : 0ull);
-  uint32_t want = 0;
-  u32x4 ent[4];
-  bool malformed = false;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    ent[i] = u32x4{0u, 0u, 0u, 0u};
-    if (!((kb >> i) & 1u)) continue;
-    const int64_t c = rank++;
-    if (c < 0 || c >= a.n_cand) {   // numbering outside the call's candidates: skipped
-      malformed = true;
-      continue;
-    }
-    if (xid == kNoObject || yid[i] == kNoObject) {
-      a.code[c] = 0xFF;
-      if (r >= n_rows || c0 - 16 + i >= n_cols) malformed = true;   // a position past the tile's members
-      continue;
-    }
-    uint32_t m;
-    if constexpr (K == 16) m = 16u - __popc((xw0 ^ yw0[i]) & 0xFFFFu);
-    else if constexpr (K == 32) m = 32u - __popc(xw0 ^ yw0[i]);
-    else m = 64u - __popc(xw0 ^ yw0[i]) - __popc(xw1 ^ yw1[i]);
-    a.code[c] = uint8_t(BLSH_PRUNED << 6);   // level 0; survivors are overwritten by the row kernel
-    if (a.m_dbg) a.m_dbg[c] = uint16_t(m);
-    if (int(m) >= min0) {
-      want |= 1u << i;
-      ent[i] = u32x4{uint32_t(c - cb), xid, yid[i], 0u};
-    }
-  }
-  if (malformed) raise_status(a.status, BLSH_EINVAL);
-  push_entries<4>(a, want, ent);
-}
-
-// Algorithm 1 over whole rows for the queued survivors of the tiles: a group
-// of G = n_max / 128 lanes per survivor, lane r of the group holding words
-// 4r .. 4r+3 of both rows (one 128-byte line per side and 8 lanes), so that
-// the group's loads coalesce.  Each lane counts the agreements of its 128/K
-// levels, a prefix across the group gives m at every level, and each lane
-// finds the first of its levels that decides (prune below min_matches;
-// accept at or above min_accept, or by the accept bits when a level's accept
-// set is not an interval; n_max); the group takes the earliest.  minMatches
-// and min_accept of a lane's levels are held in registers.
-template <int K, int G>
-__global__ __launch_bounds__(kBlock) void k_verify_rows(VerifyArgs a) {
-  constexpr int LPL = 128 / K;      // levels per lane
-  constexpr int PPW = kWave / G;    // survivors per wave step
-  extern __shared__ uint32_t s_acc[];   // accept bits (tables with non-interval accept sets)
+template <int K, int NW, bool INTERVALS>
+__global__ __launch_bounds__(kBlock, 5) void k_verify_tiles(VerifyArgs a) {
+  constexpr int P2 = NW >= 16 ? NW / 8 : 1;   // lanes per listed pair
+  constexpr int WPL = NW / P2;                // words per lane (4 or 8)
+  constexpr int LPL = WPL * 32 / K;           // levels per lane
+  constexpr int SPI = kWave / P2;             // listed pairs per wave step
+  constexpr int CPO = NW / 4;                 // 16-byte chunks per staged row
+  constexpr int NCH = 32 * CPO;               // chunks per tile
+  constexpr int CPL = (NCH + kWave - 1) / kWave;
+  __shared__ TileLds<NW> lds_all[kBlock / kWave];
+  TileLds<NW> &S = lds_all[threadIdx.x >> 6];
+  extern __shared__ uint32_t s_acc[];         // accept bits (tables with non-interval accept sets)
   const int L = a.n_levels;
   const int words = int(a.table[2]);
-  const bool intervals = a.table[kTabFlagOff] & 1u;
-  if (!intervals)
+  if (!INTERVALS)
     for (int i = threadIdx.x; i < L * words; i += kBlock) s_acc[i] = a.table[kTabAccOff + i];
   __syncthreads();
-  const int lane = lane_id(), r = lane % G, g = lane / G;
-  int mn[LPL], alo[LPL];
-#pragma unroll
-  for (int q = 0; q < LPL; ++q) {
-    const int j = r * LPL + q;
-    mn[q] = j < L ? int(a.table[kTabMinOff + j]) : 0;
-    alo[q] = j < L ? int(a.table[kTabAloOff + j]) : 0x7fffffff;
+  const int lane = lane_id(), q = lane % P2, g = lane / P2;
+  // level j's tests in disagreements D (hashes that differ among the first
+  // (j+1) K, so m = (j+1) K - D): prune iff D > pd[j], accept iff D <= ad[j]
+  // (pd = (j+1) K - minMatches, ad = (j+1) K - min_accept; either may be -1:
+  // always prune / never accept); in LDS, read 4 levels at a time
+  __shared__ int4 s_pd[kMaxLevels / 4], s_ad[kMaxLevels / 4];
+  if (threadIdx.x < kMaxLevels) {
+    const int j = threadIdx.x, n = (j + 1) * K;
+    reinterpret_cast<int *>(s_pd)[j] = j < L ? n - int(a.table[kTabMinOff + j]) : -1;
+    reinterpret_cast<int *>(s_ad)[j] = j < L ? n - int(a.table[kTabAloOff + j]) : -1;
   }
-  const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
+  __syncthreads();
+  const bool last_lane = q == P2 - 1;         // holds level L - 1 as its level LPL - 1
+  const uint32_t min0 = a.table[kTabMinOff];
   const int64_t cb = *a.c_begin_dev;
-  // the grid is a multiple of kSlices blocks: block b serves queue slice
-  // b % kSlices together with the other blocks of that slice
-  const int sl = int(blockIdx.x % kSlices);
-  const int64_t n = min(a.q_cnt[sl * kCntStride], a.q_cap);
-  const u32x4 *ent = a.q_ent + size_t(sl) * a.q_cap;
-  const int64_t w_in = int64_t(blockIdx.x / kSlices) * (kBlock / kWave) + (threadIdx.x >> 6);
-  const int64_t w_all = int64_t(gridDim.x / kSlices) * (kBlock / kWave);
-  for (int64_t i0 = w_in * PPW; i0 < n; i0 += w_all * PPW) {   // wave-uniform bound
-    const int64_t i = i0 + g;
-    const bool act = i < n;
-    u32x4 e = u32x4{0u, 0u, 0u, 0u};
-    uint32_t d[4] = {0u, 0u, 0u, 0u};
-    if (act) {
-      e = ent[i];
-      const u32x4 hx = *reinterpret_cast<const u32x4 *>(a.sig + size_t(e.y) * a.row_words + 4 * r);
-      const u32x4 hy = *reinterpret_cast<const u32x4 *>(a.sig + size_t(e.z) * a.row_words + 4 * r);
-      d[0] = hx.x ^ hy.x; d[1] = hx.y ^ hy.y; d[2] = hx.z ^ hy.z; d[3] = hx.w ^ hy.w;
-    }
-    uint32_t cnt[LPL], tot = 0;
+  const int64_t gw = xcd_tile(blockIdx.x, gridDim.x) * (kBlock / kWave) +
+                     __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+  const int64_t n_waves = int64_t(gridDim.x) * (kBlock / kWave);
+  const uint32_t *tdw = reinterpret_cast<const uint32_t *>(a.tiles);
+  const int r = lane >> 2, cc = 16 + 4 * (lane & 3);   // level 0: row r, staged rows cc .. cc+3
+  // this wave's staging region: accepted pairs (candidate - launch start, raw
+  // m | n << 16) in order; past its end, the caller's list directly
+  uint32_t *w_rel = a.st_rel + size_t(gw) * a.st_cap;
+  float *w_val = a.st_val + size_t(gw) * a.st_cap;
+  int64_t w_cnt = 0;   // wave-uniform
+  // the descriptor, one dword per lane, loaded one tile ahead
+  uint32_t nd = 0;
+  if (a.t_begin + gw < a.t_end && lane < kTileWords) nd = tdw[size_t(a.t_begin + gw) * kTileWords + lane];
+  for (int64_t t = a.t_begin + gw; t < a.t_end; t += n_waves) {   // wave-uniform
+    const uint32_t dw = nd;
+    if (t + n_waves < a.t_end && lane < kTileWords) nd = tdw[size_t(t + n_waves) * kTileWords + lane];
+    const int64_t first = int64_t(uint64_t(uint32_t(__builtin_amdgcn_readlane(int(dw), 0))) |
+                                  (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(dw), 1))) << 32));
+    const int n_rows = __builtin_amdgcn_readlane(int(dw), 2), n_cols = __builtin_amdgcn_readlane(int(dw), 3);
+    // member ids (lanes 0..31) and this lane's four keep bits (positions 4l .. 4l+3)
+    const uint32_t idv = uint32_t(__shfl(int(dw), 12 + (lane & 31)));
+    const uint32_t kb = (uint32_t(__shfl(int(dw), 4 + (lane >> 3))) >> (4 * (lane & 7))) & 0xFu;
+    const bool member = lane < 32 && (lane & 15) < (lane < 16 ? n_rows : n_cols);
+    const uint32_t id = member && idv < a.n_obj ? idv : kNoObject;
+    if (member && idv >= a.n_obj) raise_status(a.status, BLSH_EBADID);
+    // stage the rows (a missing member stages object 0's row, never read)
+    uint32_t oid[CPL];
 #pragma unroll
-    for (int q = 0; q < LPL; ++q) {
-      if constexpr (K == 16) cnt[q] = 16u - __popc((d[q >> 1] >> ((q & 1) * 16)) & 0xFFFFu);
-      else if constexpr (K == 32) cnt[q] = 32u - __popc(d[q]);
-      else cnt[q] = 64u - __popc(d[2 * q]) - __popc(d[2 * q + 1]);
-      tot += cnt[q];
+    for (int u = 0; u < CPL; ++u) {
+      const uint32_t o = uint32_t(__shfl(int(id), min((lane + kWave * u) / CPO, 31)));
+      oid[u] = o == kNoObject ? 0u : o;
     }
-    uint32_t incl = tot;
 #pragma unroll
-    for (int o = 1; o < G; o <<= 1) {
-      const uint32_t v = __shfl_up(incl, o, G);
-      if (r >= o) incl += v;
-    }
-    uint32_t run = incl - tot;
-    // first deciding level of this lane: key = level << 20 | decision << 16 | m
-    uint32_t key = 0xFFFFFFFFu;
-#pragma unroll
-    for (int q = 0; q < LPL; ++q) {
-      run += cnt[q];
-      const int j = r * LPL + q;
-      if (key == 0xFFFFFFFFu && j < L) {
-        const int m = int(run);
-        int dec = -1;
-        if (m < mn[q]) dec = BLSH_PRUNED;
-        else if (intervals ? m >= alo[q] : ((s_acc[j * words + (m >> 5)] >> (m & 31)) & 1u)) dec = BLSH_ACCEPT_CONC;
-        else if (j == L - 1) dec = BLSH_ACCEPT_NMAX;
-        if (dec >= 0) key = (uint32_t(j) << 20) | (uint32_t(dec) << 16) | uint32_t(m);
+    for (int u = 0; u < CPL; ++u) {
+      const int ch = lane + kWave * u;
+      if (NCH % kWave == 0 || ch < NCH) {
+        const int o = ch / CPO, pc = ch % CPO;
+        const u32x4 v = *reinterpret_cast<const u32x4 *>(a.sig + size_t(oid[u]) * a.row_words + 4 * pc);
+        *reinterpret_cast<u32x4 *>(&S.rows[o][4 * pc]) = v;
       }
     }
+    const uint32_t xid = uint32_t(__shfl(int(id), r));
+    uint32_t yid[4];
 #pragma unroll
-    for (int o = 1; o < G; o <<= 1) key = min(key, uint32_t(__shfl_xor(key, o)));
-    const int j = int(key >> 20), dec = int((key >> 16) & 3u), m = int(key & 0xFFFFu);
-    const int64_t c = cb + int64_t(e.x);
-    const bool lead = act && r == 0;
-    if (lead) {
-      a.code[c] = uint8_t((dec << 6) | j);
-      if (a.m_dbg) a.m_dbg[c] = uint16_t(m);
+    for (int i = 0; i < 4; ++i) yid[i] = uint32_t(__shfl(int(id), cc + i));
+    // ranks: kept positions in lower lanes (all slots), then this lane's lower slots
+    int below = 0, count = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint64_t b = __ballot((kb >> i) & 1u);
+      below += int(lanes_below(b));
+      count += __popcll(b);
     }
-    const bool emit = lead && dec != BLSH_PRUNED;
-    const float v = emit ? map_estimate(a.measure, m, (j + 1) * K, alpha, beta) : 0.f;
-    emit_accepted_from(a, emit, uint64_t(c), v, cb);
+    wave_lds_sync();
+    // level 0 for this lane's four positions; codes and m go to LDS by rank
+    const uint32_t xw0 = S.rows[r][0], xw1 = K == 64 ? S.rows[r][1] : 0u;
+    uint32_t surv = 0;
+    bool malformed = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rk = below + __popc(kb & ((1u << i) - 1u));
+      const bool kept = (kb >> i) & 1u;
+      const bool ok = xid != kNoObject && yid[i] != kNoObject;
+      uint32_t m;
+      if constexpr (K == 16) m = 16u - __popc((xw0 ^ S.rows[cc + i][0]) & 0xFFFFu);
+      else if constexpr (K == 32) m = 32u - __popc(xw0 ^ S.rows[cc + i][0]);
+      else m = 64u - __popc(xw0 ^ S.rows[cc + i][0]) - __popc(xw1 ^ S.rows[cc + i][1]);
+      const int slot = kept ? rk : 256 + lane;
+      S.code[slot] = ok ? uint8_t(BLSH_PRUNED << 6) : uint8_t(0xFF);   // survivors: set after their last level
+      if (a.m_dbg && kept && first + rk >= 0 && first + rk < a.n_cand) a.m_dbg[first + rk] = uint16_t(m);
+      malformed |= kept && !ok && (r >= n_rows || cc - 16 + i >= n_cols);   // a position past the tile's members
+      surv |= uint32_t(kept && ok && m >= min0) << i;
+    }
+    if (malformed) raise_status(a.status, BLSH_EINVAL);
+    // the surviving positions (rank << 8 | position), in position order
+    int at = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint64_t b = __ballot((surv >> i) & 1u);
+      at += int(lanes_below(b));
+      total += __popcll(b);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool sv = (surv >> i) & 1u;
+      S.list[sv ? at : 256 + lane] = uint16_t(((below + __popc(kb & ((1u << i) - 1u))) << 8) | (4 * lane + i));
+      at += int(sv);
+    }
+    wave_lds_sync();
+    // the listed pairs over their whole rows
+    for (int base = 0; base < total; base += SPI) {   // wave-uniform
+      const int e = base + g;
+      const bool act = e < total;
+      const uint32_t ent = act ? S.list[e] : 0u;
+      const int p = int(ent & 0xFFu), rk = int(ent >> 8);
+      const uint32_t *xr = &S.rows[p >> 4][q * WPL];
+      const uint32_t *yr = &S.rows[16 + (p & 15)][q * WPL];
+      uint32_t d[WPL];
+#pragma unroll
+      for (int w4 = 0; w4 < WPL; w4 += 4) {
+        const u32x4 hx = *reinterpret_cast<const u32x4 *>(xr + w4);
+        const u32x4 hy = *reinterpret_cast<const u32x4 *>(yr + w4);
+        d[w4] = hx.x ^ hy.x; d[w4 + 1] = hx.y ^ hy.y; d[w4 + 2] = hx.z ^ hy.z; d[w4 + 3] = hx.w ^ hy.w;
+      }
+      // disagreements cumulated over this lane's levels, then over the group's
+      // lower lanes
+      int D[LPL];
+      uint32_t acc = 0;
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) {
+        if constexpr (K == 16) acc += __popc((d[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu);
+        else if constexpr (K == 32) acc += __popc(d[i]);
+        else acc += __popc(d[2 * i]) + __popc(d[2 * i + 1]);
+        D[i] = int(acc);
+      }
+      const int pre = int(group_excl_scan<P2>(acc));
+      int pd[LPL], ad[LPL];
+#pragma unroll
+      for (int i4 = 0; i4 < LPL; i4 += 4) {
+        const int4 vp = s_pd[(q * LPL + i4) / 4], va = s_ad[(q * LPL + i4) / 4];
+        pd[i4] = vp.x; pd[i4 + 1] = vp.y; pd[i4 + 2] = vp.z; pd[i4 + 3] = vp.w;
+        ad[i4] = va.x; ad[i4 + 1] = va.y; ad[i4 + 2] = va.z; ad[i4 + 3] = va.w;
+      }
+      // the first deciding level of this lane (scanned from the last, so the
+      // earliest wins): key = level << 20 | decision << 16 | m
+      uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+      for (int i = LPL - 1; i >= 0; --i) {
+        const int Di = D[i] + pre;
+        const int j = q * LPL + i;
+        const int m = (j + 1) * K - Di;
+        const bool prune = Di > pd[i];
+        bool accept;
+        if constexpr (INTERVALS) accept = Di <= ad[i];
+        else accept = !prune && ((s_acc[j * words + (m >> 5)] >> (m & 31)) & 1u);
+        const bool nmax = i == LPL - 1 && last_lane;
+        const uint32_t dec = prune ? uint32_t(BLSH_PRUNED) : accept ? uint32_t(BLSH_ACCEPT_CONC) : uint32_t(BLSH_ACCEPT_NMAX);
+        key = (prune || accept || nmax) ? ((uint32_t(j) << 20) | (dec << 16) | uint32_t(m)) : key;
+      }
+      key = group_min<P2>(key);
+      const int j = int(key >> 20), dec = int((key >> 16) & 3u), m = int(key & 0xFFFFu);
+      const bool lead = act && q == 0;
+      if (lead) {
+        S.code[rk] = uint8_t((dec << 6) | j);
+        if (a.m_dbg) a.m_dbg[first + rk] = uint16_t(m);
+      }
+      const bool emit = lead && dec != BLSH_PRUNED;
+      const uint64_t em = __ballot(emit);
+      // S_hat is computed from (m, n) when the staging is flushed
+      const int64_t pos = w_cnt + int64_t(lanes_below(em));
+      const bool over = emit && pos >= a.st_cap;
+      if (emit && !over) {
+        w_rel[pos] = uint32_t(first + rk - cb);
+        w_val[pos] = __uint_as_float(uint32_t(m) | (uint32_t((j + 1) * K) << 16));
+      }
+      if (__ballot(over)) {   // the region is full: S_hat here, into the caller's list
+        const float sv = over ? map_estimate(a.measure, m, (j + 1) * K, tab_f64(a.table, 4), tab_f64(a.table, 6)) : 0.f;
+        emit_direct(a, over, uint64_t(first + rk), sv);
+      }
+      w_cnt += __popcll(em);
+    }
+    wave_lds_sync();
+    // the tile's codes (and m) as one run of candidates [first, first + count)
+    if (first < 0 || first + count > a.n_cand) raise_status(a.status, BLSH_EINVAL);   // numbering outside the call
+    for (int i = lane; i < count; i += kWave) {
+      const int64_t c = first + i;
+      if (c >= 0 && c < a.n_cand) a.code[c] = S.code[i];
+    }
+    wave_lds_sync();   // the next tile's staging overwrites these rows and lists
   }
+  if (lane == 0) a.wst_cnt[gw] = uint32_t(min<int64_t>(w_cnt, a.st_cap));
+}
+
+// Tiles path, after each launch: the waves' staging counts, exclusive prefix
+// from the running accepted count (which already holds the pairs that went to
+// the caller's list directly); the running count advances past them, and on
+// the call's last launch becomes *n_acc.  One block.
+__global__ __launch_bounds__(1024) void k_tiles_scan(const uint32_t *cnt, int64_t n_waves, int64_t *off,
+                                                      int64_t *total, int64_t *n_acc, int last) {
+  __shared__ int64_t s_part[1024 / kWave];
+  __shared__ int64_t s_carry;
+  if (threadIdx.x == 0) s_carry = *total;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < n_waves; b0 += 1024) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t v = i < n_waves ? int64_t(cnt[i]) : 0;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t u = __shfl_up(x, o);
+      if (lane_id() >= o) x += u;
+    }
+    if (lane_id() == kWave - 1) s_part[threadIdx.x / kWave] = x;
+    __syncthreads();
+    int64_t before = s_carry;
+    for (int w = 0; w < int(threadIdx.x / kWave); ++w) before += s_part[w];
+    if (i < n_waves) off[i] = before + x - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) s_carry = before + x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *total = s_carry;
+    if (last) *n_acc = s_carry;
+  }
+}
+
+// Tiles path: each wave's staged accepted pairs to the caller's list at its
+// offset, S_hat computed from (m, n); one block per wave region.
+__global__ __launch_bounds__(kBlock) void k_tiles_copy(VerifyArgs a, const int64_t *off) {
+  const int64_t w = blockIdx.x;
+  const int64_t n = a.wst_cnt[w], base = off[w];
+  const int64_t cb = *a.c_begin_dev;
+  const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
+  const uint32_t *rel = a.st_rel + size_t(w) * a.st_cap;
+  const float *val = a.st_val + size_t(w) * a.st_cap;
+  bool trunc = false;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    const int64_t pos = base + i;
+    if (pos < a.acc_cap) {
+      const uint32_t u = __float_as_uint(val[i]);
+      a.acc_idx[pos] = uint64_t(cb) + rel[i];
+      a.acc_val[pos] = map_estimate(a.measure, int(u & 0xFFFFu), int(u >> 16), alpha, beta);
+    } else {
+      trunc = true;
+    }
+  }
+  if (trunc) raise_status(a.status, BLSH_ETRUNCATED);
 }
 
 // ---------------------------------------------------------------------------
@@ -1099,6 +1174,7 @@ __global__ __launch_bounds__(kBlock) void k_acc_flush(VerifyArgs a, int64_t *nxt
   const uint32_t *rel = a.st_rel + size_t(sl) * a.st_cap;
   const float *val = a.st_val + size_t(sl) * a.st_cap;
   const int64_t cb = launch_c_begin(a);
+  const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
   const int64_t per = (n + kFlushParts - 1) / kFlushParts;
   const int64_t i1 = min(n, (part + 1) * per);
   bool trunc = false;
@@ -1106,7 +1182,12 @@ __global__ __launch_bounds__(kBlock) void k_acc_flush(VerifyArgs a, int64_t *nxt
     const int64_t pos = base + i;
     if (pos < a.acc_cap) {
       a.acc_idx[pos] = uint64_t(cb) + rel[i];
-      a.acc_val[pos] = val[i];
+      float v = val[i];
+      if (a.st_raw) {   // S_hat from (m, n), one pair per lane
+        const uint32_t u = __float_as_uint(v);
+        v = map_estimate(a.measure, int(u & 0xFFFFu), int(u >> 16), alpha, beta);
+      }
+      a.acc_val[pos] = v;
     } else {
       trunc = true;
     }
@@ -1236,37 +1317,73 @@ int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_majo
   return fail(BLSH_EINVAL, "unsupported k=%d", k);
 }
 
-// Tiles: the level-0 pass over tiles [a.t_begin, a.t_end), one wave each.
-int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, hipStream_t s) {
-  const int64_t nt = a.t_end - a.t_begin;
-  if (nt <= 0) return BLSH_OK;
-  const int64_t nb = blocks_for(nt, kBlock / kWave);
-  LaunchScope ls(ctx, s, "verify_tiles");
-  if (k == 16) hipLaunchKernelGGL((k_verify_tiles<16>), dim3(nb), dim3(kBlock), 0, s, a);
-  else if (k == 32) hipLaunchKernelGGL((k_verify_tiles<32>), dim3(nb), dim3(kBlock), 0, s, a);
-  else if (k == 64) hipLaunchKernelGGL((k_verify_tiles<64>), dim3(nb), dim3(kBlock), 0, s, a);
-  else return fail(BLSH_EINVAL, "unsupported k=%d", k);
-  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+// Tiles: the persistent tile kernel over tiles [a.t_begin, a.t_end); NW =
+// n_max / 32 words staged per member; accept bits in LDS only for tables whose
+// accept sets are not intervals.
+// The persistent grid of a tile-kernel variant: as many blocks as stay
+// resident on the device at once (occupancy queried once per variant).
+template <typename F>
+static int64_t resident_blocks(blsh_ctx *ctx, F kernel, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, size_t>, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  const auto key = std::make_pair(reinterpret_cast<const void *>(kernel), lds);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    it = cache.emplace(key, per_cu).first;
+  }
+  return int64_t(it->second) * ctx->n_cu;
 }
 
-// Tiles: Algorithm 1 over whole rows for the queued survivors; G = n_max/128
-// lanes per survivor; accept bits in LDS only for non-interval tables.
-int launch_verify_rows(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals,
-                       hipStream_t s) {
-  const int64_t nb = round_up(int64_t(ctx->n_cu) * 16, kSlices);
-  const size_t lds = intervals ? 0 : size_t(a.n_levels) * words * 4;
-  const int G = n_max / 128;
-  LaunchScope ls(ctx, s, "verify_rows");
-#define BLSH_R(KK, GG)                                                                     \
-  if (k == KK && G == GG) {                                                                \
-    hipLaunchKernelGGL((k_verify_rows<KK, GG>), dim3(nb), dim3(kBlock), lds, s, a);        \
-    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                       \
+// Waves of the persistent tile grid for (k, n_max) (the staging holds one
+// region per wave).
+int tiles_grid_waves(blsh_ctx *ctx, int k, int n_max, bool intervals, size_t lds, int64_t *waves) {
+  const int NW = n_max / 32;
+#define BLSH_TG(KK, WW)                                                                                     \
+  if (k == KK && NW == WW) {                                                                                \
+    *waves = (intervals ? resident_blocks(ctx, k_verify_tiles<KK, WW, true>, 0)                             \
+                        : resident_blocks(ctx, k_verify_tiles<KK, WW, false>, lds)) * (kBlock / kWave);    \
+    return BLSH_OK;                                                                                         \
   }
-  BLSH_R(16, 1) BLSH_R(16, 2) BLSH_R(16, 4) BLSH_R(16, 8) BLSH_R(16, 16)
-  BLSH_R(32, 1) BLSH_R(32, 2) BLSH_R(32, 4) BLSH_R(32, 8) BLSH_R(32, 16)
-  BLSH_R(64, 1) BLSH_R(64, 2) BLSH_R(64, 4) BLSH_R(64, 8) BLSH_R(64, 16)
-#undef BLSH_R
+  BLSH_TG(16, 4) BLSH_TG(16, 8) BLSH_TG(16, 16) BLSH_TG(16, 32) BLSH_TG(16, 64)
+  BLSH_TG(32, 4) BLSH_TG(32, 8) BLSH_TG(32, 16) BLSH_TG(32, 32) BLSH_TG(32, 64)
+  BLSH_TG(64, 4) BLSH_TG(64, 8) BLSH_TG(64, 16) BLSH_TG(64, 32) BLSH_TG(64, 64)
+#undef BLSH_TG
   return fail(BLSH_EINVAL, "tiles: unsupported k=%d, n_max=%d", k, n_max);
+}
+
+// grid_waves: from tiles_grid_waves (every wave of the grid writes its count).
+int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals,
+                        int64_t grid_waves, hipStream_t s) {
+  const int64_t nb = grid_waves / (kBlock / kWave);
+  const size_t lds = intervals ? 0 : size_t(a.n_levels) * words * 4;
+  const int NW = n_max / 32;
+  LaunchScope ls(ctx, s, "verify_tiles");
+#define BLSH_TT(KK, WW)                                                                              \
+  if (k == KK && NW == WW) {                                                                         \
+    if (intervals) hipLaunchKernelGGL((k_verify_tiles<KK, WW, true>), dim3(nb), dim3(kBlock), 0, s, a); \
+    else hipLaunchKernelGGL((k_verify_tiles<KK, WW, false>), dim3(nb), dim3(kBlock), lds, s, a);      \
+    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                                 \
+  }
+  BLSH_TT(16, 4) BLSH_TT(16, 8) BLSH_TT(16, 16) BLSH_TT(16, 32) BLSH_TT(16, 64)
+  BLSH_TT(32, 4) BLSH_TT(32, 8) BLSH_TT(32, 16) BLSH_TT(32, 32) BLSH_TT(32, 64)
+  BLSH_TT(64, 4) BLSH_TT(64, 8) BLSH_TT(64, 16) BLSH_TT(64, 32) BLSH_TT(64, 64)
+#undef BLSH_TT
+  return fail(BLSH_EINVAL, "tiles: unsupported k=%d, n_max=%d", k, n_max);
+}
+
+// Tiles path, after each launch: offsets of the waves' staged pairs, then the
+// copy to the caller's list.
+int launch_tiles_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t grid_waves, int64_t *off, bool last,
+                       hipStream_t s) {
+  LaunchScope ls(ctx, s, "tiles_flush");
+  hipLaunchKernelGGL(k_tiles_scan, dim3(1), dim3(1024), 0, s, a.wst_cnt, grid_waves, off, a.acc_total, a.n_acc,
+                     int(last));
+  hipLaunchKernelGGL(k_tiles_copy, dim3(grid_waves), dim3(kBlock), 0, s, a, off);
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s) {

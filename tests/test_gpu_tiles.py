@@ -36,14 +36,18 @@ def _bits(mix, n_bits, seed):
     return G.pack_bits((mix.x.astype(np.float64) @ planes >= 0).astype(np.uint8))
 
 
-def expand(members, tiles_i64, n_tiles):
+TW = 24   # int64 words per 192-byte tile descriptor
+
+
+def expand(tiles_i64, n_tiles):
     """Host expansion of tile descriptors into (x, y) in candidate order; also
     checks that each tile numbers its candidates right after the previous one."""
-    d = tiles_i64[: n_tiles * 8].reshape(n_tiles, 8)
-    first, row0, col0 = d[:, 0], d[:, 1], d[:, 2]
-    n_rows = (d[:, 3] & 0xFFFFFFFF).astype(np.int64)
-    n_cols = ((d[:, 3] >> 32) & 0xFFFFFFFF).astype(np.int64)
-    keep = d[:, 4:8].view(np.uint64)
+    d = tiles_i64[: n_tiles * TW].reshape(n_tiles, TW)
+    first = d[:, 0]
+    n_rows = (d[:, 1] & 0xFFFFFFFF).astype(np.int64)
+    n_cols = ((d[:, 1] >> 32) & 0xFFFFFFFF).astype(np.int64)
+    keep = np.ascontiguousarray(d[:, 2:6]).view(np.uint64)
+    ids = np.ascontiguousarray(d[:, 6:22]).view(np.uint32).reshape(n_tiles, 32)
     bits = np.unpackbits(keep.view(np.uint8).reshape(n_tiles, 32), axis=1, bitorder="little").astype(bool)
     counts = bits.sum(axis=1)
     assert np.array_equal(first, np.concatenate([[0], np.cumsum(counts)[:-1]]))
@@ -51,13 +55,13 @@ def expand(members, tiles_i64, n_tiles):
     t_idx, p = np.nonzero(bits)
     r, c = p // 16, p % 16
     assert np.all(r < n_rows[t_idx]) and np.all(c < n_cols[t_idx])
-    return members[row0[t_idx] + r], members[col0[t_idx] + c]
+    return ids[t_idx, r], ids[t_idx, 16 + c]
 
 
 def band_tiles(ctx, S, nb, b, max_bucket=0, cap=1 << 16):
-    mem, tl, nt, npairs, trunc = P.bayeslsh_band_tiles(ctx, S, nb, b, cap, max_bucket=max_bucket)
+    tl, nt, npairs, trunc = P.bayeslsh_band_tiles(ctx, S, nb, b, cap, max_bucket=max_bucket)
     assert not trunc
-    return mem, tl, nt, npairs
+    return tl, nt, npairs
 
 
 @pytest.mark.parametrize("nb,b,max_bucket", [(8, 8, 0), (5, 11, 0), (3, 5, 40), (20, 3, 40), (4, 16, 0)])
@@ -71,9 +75,9 @@ def test_band_tiles_list_the_oracle_pairs(ctx, mix, nb, b, max_bucket):
     wx, wy = R.band_candidates(bits, nb, b, max_bucket, tile=16)
     assert len(wx) > 1000
     for layout in (P.OBJECT_MAJOR, P.WORD_MAJOR):
-        mem, tl, nt, npairs = band_tiles(ctx, sigs_tensor(bits, P.COSINE, layout), nb, b, max_bucket)
+        tl, nt, npairs = band_tiles(ctx, sigs_tensor(bits, P.COSINE, layout), nb, b, max_bucket)
         assert npairs == len(wx)
-        gx, gy = expand(down(mem), tl.cpu().numpy(), nt)
+        gx, gy = expand(tl.cpu().numpy(), nt)
         np.testing.assert_array_equal(gx, wx)
         np.testing.assert_array_equal(gy, wy)
 
@@ -97,7 +101,7 @@ def test_tiles_verify_matches_oracle(ctx, mix, banded, k, n_max, t):
     print("tiles verify k=%d n_max=%d t=%.1f" % (k, n_max, t), flush=True)
     band, (wx, wy) = banded
     sig = _bits(mix, n_max, G.SEED_BASE + 64 + n_max)
-    mem, tl, nt, npairs = band_tiles(ctx, sigs_tensor(band, P.COSINE, P.OBJECT_MAJOR), 16, 6)
+    tl, nt, npairs = band_tiles(ctx, sigs_tensor(band, P.COSINE, P.OBJECT_MAJOR), 16, 6)
     assert npairs == len(wx)
     want = R.verify(wx, wy, P.COSINE, sig, k, n_max // k, t, EPS, DELTA, GAMMA)
     # pruned and concentrated everywhere; accepted at n_max too except where
@@ -105,7 +109,7 @@ def test_tiles_verify_matches_oracle(ctx, mix, banded, k, n_max, t):
     assert {0, 1} <= set(want["decision"].tolist())
     S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
     res = P.make_result(npairs, npairs, m_debug=True)
-    P.bayeslsh_verify(ctx, P.tiles(mem, tl, nt, npairs), S, t, EPS, DELTA, GAMMA, (1, 1), k, res)
+    P.bayeslsh_verify(ctx, P.tiles(tl, nt, npairs), S, t, EPS, DELTA, GAMMA, (1, 1), k, res)
     P.bayeslsh_sync(ctx)
     got = decode_result(res, npairs)
     assert_same_as_oracle(got, want)
@@ -117,73 +121,119 @@ def test_tiles_verify_matches_oracle(ctx, mix, banded, k, n_max, t):
     np.testing.assert_array_equal(got["acc_val"], gp["acc_val"])
 
 
-def _tile(first, row0, col0, n_rows, n_cols, positions):
+def _tile(first, row_ids, col_ids, positions):
+    n_rows, n_cols = len(row_ids), len(col_ids)
     keep = np.zeros(4, np.uint64)
     for p_ in positions:
         keep[p_ // 64] |= np.uint64(1) << np.uint64(p_ % 64)
-    return np.array([first, row0, col0, n_rows | (n_cols << 32)] + list(keep.view(np.int64)), np.int64)
+    ids = np.full(32, 0xFFFFFFFF, np.uint32)
+    ids[:n_rows] = row_ids
+    ids[16:16 + n_cols] = col_ids
+    head = np.array([first, n_rows | (n_cols << 32)], np.int64)
+    return np.concatenate([head, keep.view(np.int64), ids.view(np.int64), np.zeros(2, np.int64)])
 
 
 def test_tiles_by_hand_and_malformed(ctx):
-    """Hand-made tiles: partial rows and columns, sparse keep masks, several
-    launches' worth of tiles; then a member id >= n_obj (code 0xFF,
-    BLSH_EBADID), a position past the members array and numbering past n_cand
-    (BLSH_EINVAL), an empty tile list."""
+    """Hand-made tiles: partial rows and columns, sparse keep masks, more tiles
+    than one launch of the persistent grid takes at once; then a member id >=
+    n_obj (code 0xFF, BLSH_EBADID), a position past n_rows and numbering past
+    n_cand (BLSH_EINVAL), an empty tile list."""
     rng = np.random.default_rng(8)
     n_obj, n_max, k = 500, 256, 32
     sig = G.pack_bits(G.calibration_bits(n_obj // 2, n_max, rng.uniform(0.6, 1.0, n_obj // 2), 81))
-    members = rng.permutation(n_obj).astype(np.uint32)
     tiles, xs, ys, first = [], [], [], 0
-    for _ in range(700):
+    for _ in range(9000):
         nr, nc = int(rng.integers(1, 17)), int(rng.integers(1, 17))
-        r0, c0 = int(rng.integers(0, n_obj - 16)), int(rng.integers(0, n_obj - 16))
+        rows = rng.integers(0, n_obj, nr).astype(np.uint32)
+        cols = rng.integers(0, n_obj, nc).astype(np.uint32)
         pos = sorted(int(16 * r + c) for r in range(nr) for c in range(nc) if rng.random() < 0.7)
         if not pos:
             continue
-        tiles.append(_tile(first, r0, c0, nr, nc, pos))
-        xs += [members[r0 + q // 16] for q in pos]
-        ys += [members[c0 + q % 16] for q in pos]
+        tiles.append(_tile(first, rows, cols, pos))
+        xs += [rows[q // 16] for q in pos]
+        ys += [cols[q % 16] for q in pos]
         first += len(pos)
     x, y = np.array(xs, np.uint32), np.array(ys, np.uint32)
     S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
     want = R.verify(x, y, P.COSINE, sig, k, n_max // k, 0.7, EPS, DELTA, GAMMA)
-    tl = up(np.stack(tiles))
-    mem = up(members)
+    tl = up(np.stack(tiles).reshape(-1))
     res = P.make_result(first, first, m_debug=True)
-    P.bayeslsh_verify(ctx, P.tiles(mem, tl.view(-1), len(tiles), first), S, 0.7, EPS, DELTA, GAMMA, (1, 1), k, res)
+    P.bayeslsh_verify(ctx, P.tiles(tl, len(tiles), first), S, 0.7, EPS, DELTA, GAMMA, (1, 1), k, res)
     P.bayeslsh_sync(ctx)
     assert_same_as_oracle(decode_result(res, first), want)
 
-    def run_one(tile, members_arr, n_cand):
+    def run_one(tile, n_cand):
         r = P.make_result(max(n_cand, 1), 16)
         r.code.fill_(0xEE)
-        P.bayeslsh_verify(ctx, P.tiles(up(members_arr), up(tile[None, :]).view(-1), 1, n_cand), S, 0.7, EPS, DELTA,
-                          GAMMA, (1, 1), k, r)
+        P.bayeslsh_verify(ctx, P.tiles(up(tile), 1, n_cand), S, 0.7, EPS, DELTA, GAMMA, (1, 1), k, r)
         with pytest.raises(P.BayesLSHError) as e:
             P.bayeslsh_sync(ctx)
         return e.value.code, r.code[:n_cand].cpu().numpy()
 
-    bad_mem = members.copy()
-    bad_mem[3] = n_obj + 5                                   # row member 3 is a bad id
-    code, got = run_one(_tile(0, 0, 8, 4, 4, [16 * r + c for r in range(4) for c in range(4)]), bad_mem, 16)
+    rows = np.arange(4, dtype=np.uint32)
+    cols = np.arange(8, 12, dtype=np.uint32)
+    bad_rows = rows.copy()
+    bad_rows[3] = n_obj + 5                                             # row member 3 is a bad id
+    code, got = run_one(_tile(0, bad_rows, cols, [16 * r + c for r in range(4) for c in range(4)]), 16)
     assert code == -5 and np.all(got[12:16] == 0xFF) and np.all(got[:12] != 0xFF)   # BLSH_EBADID
-    code, got = run_one(_tile(0, n_obj - 2, 0, 4, 4, [0, 1, 16, 17, 32]), members, 5)   # rows past members[]
+    code, got = run_one(_tile(0, rows[:2], cols[:2], [0, 1, 16, 17, 34]), 5)          # position past n_rows
     assert code == -1 and got[4] == 0xFF and np.all(got[:4] != 0xFF)
-    code, got = run_one(_tile(0, 0, 8, 2, 2, [0, 1, 16, 17, 34]), members, 5)           # position past n_rows
-    assert code == -1 and got[4] == 0xFF
-    code, got = run_one(_tile(3, 0, 8, 2, 2, [0, 1, 16, 17]), members, 5)               # numbering past n_cand
+    code, got = run_one(_tile(3, rows[:2], cols[:2], [0, 1, 16, 17]), 5)              # numbering past n_cand
     assert code == -1 and np.all(got[3:5] != 0xEE) and np.all(got[:3] == 0xEE)
     r = P.make_result(1, 1)
     r.n_accepted.fill_(9)
-    P.bayeslsh_verify(ctx, P.tiles(mem, tl.view(-1), 0, 0), S, 0.7, EPS, DELTA, GAMMA, (1, 1), k, r)
+    P.bayeslsh_verify(ctx, P.tiles(tl, 0, 0), S, 0.7, EPS, DELTA, GAMMA, (1, 1), k, r)
     P.bayeslsh_sync(ctx)
     assert int(r.n_accepted.item()) == 0
 
 
+def test_tiles_numbered_past_two_to_the_31_and_32(ctx):
+    """Tiles whose candidates are numbered beyond 2^31 and 2^32 (a result of
+    4.3e9 candidates, most of them outside these tiles): codes, m and accepted
+    indices land at those numbers, equal to the oracle's output for the same
+    pairs."""
+    rng = np.random.default_rng(9)
+    n_obj, n_max, k = 600, 512, 32
+    sig = G.pack_bits(G.calibration_bits(n_obj // 2, n_max, rng.uniform(0.6, 1.0, n_obj // 2), 91))
+    S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
+    n_cand = (1 << 32) + 5000
+    # three full tiles (768 numbers) from each start: straddling 2^31 and 2^32, disjoint
+    starts = [(1 << 31) - 300, (1 << 31) + 1000, (1 << 32) - 400, (1 << 32) + 1000]
+    tiles, xs, ys, idx = [], [], [], []
+    for st in starts:
+        for u in range(3):
+            rows = np.sort(rng.choice(n_obj, 16, replace=False)).astype(np.uint32)
+            cols = np.sort(rng.choice(n_obj, 16, replace=False)).astype(np.uint32)
+            pos = list(range(256))
+            first = st + 256 * u
+            tiles.append(_tile(first, rows, cols, pos))
+            xs += [rows[q // 16] for q in pos]
+            ys += [cols[q % 16] for q in pos]
+            idx += list(range(first, first + 256))
+    x, y, idx = np.array(xs, np.uint32), np.array(ys, np.uint32), np.array(idx, np.int64)
+    want = R.verify(x, y, P.COSINE, sig, k, n_max // k, 0.7, EPS, DELTA, GAMMA)
+    res = P.make_result(n_cand, 1 << 16, m_debug=True)
+    res.code.fill_(0xEE)
+    P.bayeslsh_verify(ctx, P.tiles(up(np.stack(tiles).reshape(-1)), len(tiles), n_cand), S, 0.7, EPS, DELTA, GAMMA,
+                      (1, 1), k, res)
+    P.bayeslsh_sync(ctx)
+    idx_d = torch.from_numpy(idx).cuda()
+    code = res.code[idx_d].cpu().numpy()
+    m = res.m_debug.view(torch.int16)[idx_d].cpu().numpy().view(np.uint16).astype(np.int32)
+    np.testing.assert_array_equal(code >> 6, want["decision"])
+    np.testing.assert_array_equal(code & 63, want["level"])
+    np.testing.assert_array_equal(m, want["m"])
+    ai, av = res.accepted()
+    emit = (want["decision"] == 1) | (want["decision"] == 2)
+    np.testing.assert_array_equal(ai, idx[emit])
+    np.testing.assert_allclose(av, want["shat"][emit], atol=1e-6, rtol=0)
+    assert int((res.code == 0xEE).sum().item()) == n_cand - len(idx)   # nothing else written
+
+
 def test_tiles_rejected_where_unsupported(ctx, mix, banded):
     band = banded[0]
-    mem, tl, nt, npairs = band_tiles(ctx, sigs_tensor(band, P.COSINE, P.OBJECT_MAJOR), 16, 6)
-    cand = P.tiles(mem, tl, nt, npairs)
+    tl, nt, npairs = band_tiles(ctx, sigs_tensor(band, P.COSINE, P.OBJECT_MAJOR), 16, 6)
+    cand = P.tiles(tl, nt, npairs)
     res = P.make_result(npairs, 16)
     sig = _bits(mix, 256, 5)
     for S in (sigs_tensor(sig, P.COSINE, P.WORD_MAJOR), sigs_tensor(_bits(mix, 96, 6), P.COSINE, P.OBJECT_MAJOR),
@@ -196,6 +246,6 @@ def test_tiles_rejected_where_unsupported(ctx, mix, banded):
         P.bayeslsh_lite_verify(ctx, cand, S, P.dense_vectors(up(mix.x)), 0.7, EPS, (1, 1), 128, 32, res)
     with pytest.raises(P.BayesLSHError):
         P.bayeslsh_verify_noalloc(ctx, cand, S, 0.7, EPS, DELTA, GAMMA, (1, 1), 32, res)
-    with pytest.raises(P.BayesLSHError):    # members buffer smaller than n_bands * n_obj
-        P.bayeslsh_band_tiles(ctx, sigs_tensor(band, P.COSINE, P.OBJECT_MAJOR), 16, 6, 16,
-                              members_out=mem[:100])
+    with pytest.raises(P.BayesLSHError):    # tiles must be 16-byte aligned
+        P.bayeslsh_verify(ctx, P.tiles(tl.view(torch.int32)[1:], nt, npairs), S, 0.7, EPS, DELTA, GAMMA, (1, 1), 32,
+                          res)
