@@ -308,9 +308,10 @@ int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *plan
  * tile: it stages the first n_max hashes of its 32 members in LDS (one load
  * per 128-byte line), decides level 0 for the tile's pairs and finishes the
  * pairs level 0 does not prune from those rows.  Malformed tiles are reported
- * at the next bayeslsh_sync: candidate numbers outside [0, n_cand) are
- * skipped and positions past the tile's n_rows / n_cols get code 0xFF
- * (BLSH_EINVAL); a member id >= n_obj gives its pairs code 0xFF (BLSH_EBADID). */
+ * at the next bayeslsh_sync: a tile whose candidate numbers run outside
+ * [0, n_cand) is skipped (nothing of it written), and positions past the
+ * tile's n_rows / n_cols get code 0xFF (BLSH_EINVAL); a member id >= n_obj
+ * gives its pairs code 0xFF (BLSH_EBADID). */
 int bayeslsh_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, double t,
                     double epsilon, double delta, double gamma, blsh_prior prior, int32_t k,
                     blsh_result *res, void *stream);

@@ -679,7 +679,7 @@ struct TileLds {
 };
 
 template <int K, int NW, bool INTERVALS>
-__global__ __launch_bounds__(kBlock, 5) void k_verify_tiles(VerifyArgs a) {
+__global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
   constexpr int P2 = NW >= 16 ? NW / 8 : 1;   // lanes per listed pair
   constexpr int WPL = NW / P2;                // words per lane (4 or 8)
   constexpr int LPL = WPL * 32 / K;           // levels per lane
@@ -735,21 +735,23 @@ __global__ __launch_bounds__(kBlock, 5) void k_verify_tiles(VerifyArgs a) {
     const bool member = lane < 32 && (lane & 15) < (lane < 16 ? n_rows : n_cols);
     const uint32_t id = member && idv < a.n_obj ? idv : kNoObject;
     if (member && idv >= a.n_obj) raise_status(a.status, BLSH_EBADID);
-    // stage the rows (a missing member stages object 0's row, never read)
+    // stage the rows (a missing member stages object 0's row, never read):
+    // every chunk's load is issued before the first is stored
+    const uint32_t idz = id == kNoObject ? 0u : id;
     uint32_t oid[CPL];
 #pragma unroll
+    for (int u = 0; u < CPL; ++u) oid[u] = uint32_t(__shfl(int(idz), min((lane + kWave * u) / CPO, 31)));
+    u32x4 chunk[CPL];
+#pragma unroll
     for (int u = 0; u < CPL; ++u) {
-      const uint32_t o = uint32_t(__shfl(int(id), min((lane + kWave * u) / CPO, 31)));
-      oid[u] = o == kNoObject ? 0u : o;
+      const int ch = lane + kWave * u;
+      if (NCH % kWave == 0 || ch < NCH)
+        chunk[u] = *reinterpret_cast<const u32x4 *>(a.sig + uint64_t(oid[u]) * uint32_t(a.row_words) + 4 * (ch % CPO));
     }
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
       const int ch = lane + kWave * u;
-      if (NCH % kWave == 0 || ch < NCH) {
-        const int o = ch / CPO, pc = ch % CPO;
-        const u32x4 v = *reinterpret_cast<const u32x4 *>(a.sig + size_t(oid[u]) * a.row_words + 4 * pc);
-        *reinterpret_cast<u32x4 *>(&S.rows[o][4 * pc]) = v;
-      }
+      if (NCH % kWave == 0 || ch < NCH) *reinterpret_cast<u32x4 *>(&S.rows[ch / CPO][4 * (ch % CPO)]) = chunk[u];
     }
     const uint32_t xid = uint32_t(__shfl(int(id), r));
     uint32_t yid[4];
@@ -764,9 +766,13 @@ __global__ __launch_bounds__(kBlock, 5) void k_verify_tiles(VerifyArgs a) {
       count += __popcll(b);
     }
     wave_lds_sync();
-    // level 0 for this lane's four positions; codes and m go to LDS by rank
+    if (first < 0 || first + count > a.n_cand) {   // numbering outside the call's candidates: the tile is skipped
+      if (lane == 0) raise_status(a.status, BLSH_EINVAL);
+      continue;
+    }
+    // level 0 for this lane's four positions; codes go to LDS by rank
     const uint32_t xw0 = S.rows[r][0], xw1 = K == 64 ? S.rows[r][1] : 0u;
-    uint32_t surv = 0;
+    uint32_t surv = 0, mm[4];
     bool malformed = false;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -777,13 +783,17 @@ __global__ __launch_bounds__(kBlock, 5) void k_verify_tiles(VerifyArgs a) {
       if constexpr (K == 16) m = 16u - __popc((xw0 ^ S.rows[cc + i][0]) & 0xFFFFu);
       else if constexpr (K == 32) m = 32u - __popc(xw0 ^ S.rows[cc + i][0]);
       else m = 64u - __popc(xw0 ^ S.rows[cc + i][0]) - __popc(xw1 ^ S.rows[cc + i][1]);
-      const int slot = kept ? rk : 256 + lane;
-      S.code[slot] = ok ? uint8_t(BLSH_PRUNED << 6) : uint8_t(0xFF);   // survivors: set after their last level
-      if (a.m_dbg && kept && first + rk >= 0 && first + rk < a.n_cand) a.m_dbg[first + rk] = uint16_t(m);
+      mm[i] = m;
+      S.code[kept ? rk : 256 + lane] = ok ? uint8_t(BLSH_PRUNED << 6) : uint8_t(0xFF);   // survivors: set later
       malformed |= kept && !ok && (r >= n_rows || cc - 16 + i >= n_cols);   // a position past the tile's members
       surv |= uint32_t(kept && ok && m >= min0) << i;
     }
     if (malformed) raise_status(a.status, BLSH_EINVAL);
+    if (a.m_dbg) {   // m of the pairs level 0 decides (survivors: after their last level)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if ((kb >> i) & 1u) a.m_dbg[first + below + __popc(kb & ((1u << i) - 1u))] = uint16_t(mm[i]);
+    }
     // the surviving positions (rank << 8 | position), in position order
     int at = 0, total = 0;
 #pragma unroll
@@ -872,12 +882,8 @@ __global__ __launch_bounds__(kBlock, 5) void k_verify_tiles(VerifyArgs a) {
       w_cnt += __popcll(em);
     }
     wave_lds_sync();
-    // the tile's codes (and m) as one run of candidates [first, first + count)
-    if (first < 0 || first + count > a.n_cand) raise_status(a.status, BLSH_EINVAL);   // numbering outside the call
-    for (int i = lane; i < count; i += kWave) {
-      const int64_t c = first + i;
-      if (c >= 0 && c < a.n_cand) a.code[c] = S.code[i];
-    }
+    // the tile's codes as one run of candidates [first, first + count)
+    for (int i = lane; i < count; i += kWave) a.code[first + i] = S.code[i];
     wave_lds_sync();   // the next tile's staging overwrites these rows and lists
   }
   if (lane == 0) a.wst_cnt[gw] = uint32_t(min<int64_t>(w_cnt, a.st_cap));
