@@ -836,31 +836,46 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
         D[i] = int(acc);
       }
       const int pre = int(group_excl_scan<P2>(acc));
-      int pd[LPL], ad[LPL];
-#pragma unroll
-      for (int i4 = 0; i4 < LPL; i4 += 4) {
-        const int4 vp = s_pd[(q * LPL + i4) / 4], va = s_ad[(q * LPL + i4) / 4];
-        pd[i4] = vp.x; pd[i4 + 1] = vp.y; pd[i4 + 2] = vp.z; pd[i4 + 3] = vp.w;
-        ad[i4] = va.x; ad[i4 + 1] = va.y; ad[i4 + 2] = va.z; ad[i4 + 3] = va.w;
-      }
       // the first deciding level of this lane (scanned from the last, so the
-      // earliest wins): key = level << 20 | decision << 16 | m
+      // earliest wins): key = level << 20 | D.  With interval accept sets a
+      // level continues iff ad < D <= pd, one unsigned test of D - (ad + 1)
+      // against pd - ad; the decision itself is read off (j, D) afterwards.
       uint32_t key = 0xFFFFFFFFu;
+      if constexpr (INTERVALS) {
+        uint32_t lo[LPL], w[LPL];
 #pragma unroll
-      for (int i = LPL - 1; i >= 0; --i) {
-        const int Di = D[i] + pre;
-        const int j = q * LPL + i;
-        const int m = (j + 1) * K - Di;
-        const bool prune = Di > pd[i];
-        bool accept;
-        if constexpr (INTERVALS) accept = Di <= ad[i];
-        else accept = !prune && ((s_acc[j * words + (m >> 5)] >> (m & 31)) & 1u);
-        const bool nmax = i == LPL - 1 && last_lane;
-        const uint32_t dec = prune ? uint32_t(BLSH_PRUNED) : accept ? uint32_t(BLSH_ACCEPT_CONC) : uint32_t(BLSH_ACCEPT_NMAX);
-        key = (prune || accept || nmax) ? ((uint32_t(j) << 20) | (dec << 16) | uint32_t(m)) : key;
+        for (int i4 = 0; i4 < LPL; i4 += 4) {
+          const int4 vp = s_pd[(q * LPL + i4) / 4], va = s_ad[(q * LPL + i4) / 4];
+          lo[i4] = uint32_t(va.x + 1); lo[i4 + 1] = uint32_t(va.y + 1);
+          lo[i4 + 2] = uint32_t(va.z + 1); lo[i4 + 3] = uint32_t(va.w + 1);
+          w[i4] = uint32_t(vp.x - va.x); w[i4 + 1] = uint32_t(vp.y - va.y);
+          w[i4 + 2] = uint32_t(vp.z - va.z); w[i4 + 3] = uint32_t(vp.w - va.w);
+        }
+        const uint32_t kb0 = uint32_t(q * LPL) << 20;
+#pragma unroll
+        for (int i = LPL - 1; i >= 0; --i) {
+          const uint32_t Di = uint32_t(D[i] + pre);
+          const bool decide = Di - lo[i] >= w[i] || (i == LPL - 1 && last_lane);
+          key = decide ? kb0 + (uint32_t(i) << 20) + Di : key;
+        }
+      } else {
+#pragma unroll
+        for (int i = LPL - 1; i >= 0; --i) {
+          const int Di = D[i] + pre;
+          const int j = q * LPL + i;
+          const int m = (j + 1) * K - Di;
+          const bool prune = Di > reinterpret_cast<const int *>(s_pd)[j];
+          const bool accept = !prune && ((s_acc[j * words + (m >> 5)] >> (m & 31)) & 1u);
+          key = (prune || accept || (i == LPL - 1 && last_lane)) ? ((uint32_t(j) << 20) | uint32_t(Di)) : key;
+        }
       }
       key = group_min<P2>(key);
-      const int j = int(key >> 20), dec = int((key >> 16) & 3u), m = int(key & 0xFFFFu);
+      const int j = int(key >> 20), Dj = int(key & 0xFFFFFu), m = (j + 1) * K - Dj;
+      int dec;
+      if (Dj > reinterpret_cast<const int *>(s_pd)[j]) dec = BLSH_PRUNED;
+      else if (INTERVALS ? Dj <= reinterpret_cast<const int *>(s_ad)[j] : ((s_acc[j * words + (m >> 5)] >> (m & 31)) & 1u))
+        dec = BLSH_ACCEPT_CONC;
+      else dec = BLSH_ACCEPT_NMAX;
       const bool lead = act && q == 0;
       if (lead) {
         S.code[rk] = uint8_t((dec << 6) | j);
