@@ -557,7 +557,7 @@ def run_sigs(args, torch, P):
                         "hash_evals_per_s": n_el * 256 / (mh_ms * 1e-3)}}
 
 
-DENSE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "verify_dense_1m_traffic.txt")
+DENSE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "verify_tiles_dense_1m_traffic.txt")
 DENSE_KERNEL_SOURCES = ("paper_1110_1328_amd/csrc/verify.hip", "paper_1110_1328_amd/csrc/device_common.h")
 # the verification call's kernels, by the names their launches are profiled under
 TILE_KERNELS = ("verify_tiles", "tiles_flush")
@@ -742,9 +742,12 @@ def run_dense(args, torch, P):
     P.bayeslsh_verify(ctx, cand_t, S_om, t, eps, delta, gamma, (1, 1), k, res_m, stream)
     P.bayeslsh_sync(ctx, stream)
     assert bool(torch.equal(res_m.code[:n], res.code[:n]))
+    # stratified sample: one candidate drawn uniformly from each of n_sample
+    # equal strata of the candidate numbering (already in candidate order)
     rng = np.random.default_rng(G.SEED_BASE + 105)
     n_sample = min(n, args.cpu_sample)
-    pick = np.sort(rng.choice(n, size=n_sample, replace=False))
+    stride = n // n_sample
+    pick = np.arange(n_sample, dtype=np.int64) * stride + rng.integers(0, stride, size=n_sample, dtype=np.int64)
     pick_d = torch.from_numpy(pick).cuda()
     xs = xo[:n].view(torch.int32)[pick_d].cpu().numpy().view(np.uint32)
     ys = yo[:n].view(torch.int32)[pick_d].cpu().numpy().view(np.uint32)
@@ -778,7 +781,7 @@ def run_dense(args, torch, P):
     }
     log("sampled parity: %s" % parity)
     cpu = dict(value=n_sample / dt, unit="pairs/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
-               sample="seeded uniform sample of %d of the %d candidates (kept in candidate order), oracle "
+               sample="seeded stratified sample of %d of the %d candidates (one uniform draw per stratum), oracle "
                       "Algorithm 1 (plain C loop, OpenMP) on the GPU's own signatures, median of 3 runs "
                       "(%.2f s each)" % (n_sample, n, dt))
     log("cpu baseline: %.3g pairs/s on %d threads" % (cpu["value"], threads))
@@ -823,6 +826,10 @@ def run_dense(args, torch, P):
         "bytes_model": "per candidate 1 B code + 8 B per level reached (4 B chunk per side at k = 32) + 12 B per "
                        "emitted pair, plus the 192 B descriptor (member ids included) per tile; the tile kernel "
                        "does all of it, the flush copies the staged accepted pairs to the caller's list",
+        "note": "frac counts each candidate's level chunks as if read for it alone; the tile kernel reads a "
+                "tile's 32 rows once into LDS for its 256 positions, so the counted HBM traffic (traffic, "
+                "traffic_frac) is a fraction of the algorithmic bytes and the kernel is bound by instruction "
+                "issue rather than by HBM",
     }
     ctx.close()
     return {
@@ -1131,7 +1138,7 @@ def main():
                          "tf-idf workload (pruning curve, gamma/delta/epsilon, BayesLSH vs Lite by threshold); "
                          "sigs: signature generation (dense SRP on MFMA, sparse SRP, minhash)")
     ap.add_argument("--no-lite", action="store_true", help="headline: skip the cosine BayesLSH-Lite leg")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 27,
+    ap.add_argument("--cpu-sample", type=int, default=1 << 29,
                     help="dense: candidates in the seeded sample the oracle is timed on and compared over")
     ap.add_argument("--queries", type=int, default=10000, help="serving: number of queries")
     ap.add_argument("--serving-legs", choices=["all", "device"], default="all",
