@@ -275,7 +275,9 @@ def run_batched(args, torch, P):
     k_used = P.bayeslsh_verify_batched(ctx, lists, cand_d, S_j, S_c, eps, delta, gamma, (1, 1), 0, res, stream)
     P.bayeslsh_sync(ctx, stream)
     tune = P.bayeslsh_get_tuning(ctx)
-    log("autotuned: k=%s inreg=%d blocks/CU=%d" % (k_used, tune["last_batch_inreg"], tune["last_batch_blocks_per_cu"]))
+    log("autotuned: k=%s tiles srp %d / minhash %d, inreg=%d blocks/CU=%d" % (
+        k_used, tune["last_batch_srp_tile"], tune["last_batch_mh_tile"], tune["last_batch_inreg"],
+        tune["last_batch_blocks_per_cu"]))
 
     def timed(fn, steps):
         for _ in range(2):
@@ -294,6 +296,21 @@ def run_batched(args, torch, P):
     ms = timed(lambda: P.bayeslsh_verify_batched(ctx, lists, cand_d, S_j, S_c, eps, delta, gamma, (1, 1), k_used,
                                                  res, stream), steps)
     log("batched: %.3f ms" % ms)
+    # every phase-1 tile shape at the tuned k, in-register depth and blocks per
+    # CU (the autotuner's choice among them is the one timed above)
+    shapes = {}
+    r2 = P.make_result(n, cap)
+    for ts in (128, 256, 512):
+        for tm in (64, 128):
+            P.bayeslsh_set_tuning(ctx, batch_inreg=tune["last_batch_inreg"],
+                                  batch_blocks_per_cu=tune["last_batch_blocks_per_cu"], batch_srp_tile=ts,
+                                  batch_mh_tile=tm)
+            t_ms = timed(lambda: P.bayeslsh_verify_batched(ctx, lists, cand_d, S_j, S_c, eps, delta, gamma, (1, 1),
+                                                           k_used, r2, stream), 3)
+            shapes["srp%d_mh%d" % (ts, tm)] = {"ms": t_ms, "same_codes": bool(torch.equal(r2.code[:n], res.code[:n]))}
+    P.bayeslsh_set_tuning(ctx)
+    del r2
+    log("tile shapes: %s" % ", ".join("%s %.3f ms" % (kk, v["ms"]) for kk, v in shapes.items()))
     # the same batch split by measure, at every k (where the time goes)
     split = {}
     r2 = P.make_result(n, cap)
@@ -343,7 +360,9 @@ def run_batched(args, torch, P):
                                "vectors, 1024 SRP bits (word-major + 128-bit prefix array; the comparator reads object-major rows); eps=0.03, delta=0.05, gamma=0.03",
                    "n_candidates": n, "n_jaccard": int(len(cj)), "n_cosine": int(len(cc)),
                    "k_jaccard": k_used[0], "k_cosine": k_used[1], "inreg_levels": tune["last_batch_inreg"],
-                   "blocks_per_cu": tune["last_batch_blocks_per_cu"]},
+                   "blocks_per_cu": tune["last_batch_blocks_per_cu"], "srp_tile": tune["last_batch_srp_tile"],
+                   "minhash_tile": tune["last_batch_mh_tile"]},
+        "tile_shapes": shapes,
         "decisions": {"pruned": int(np.sum(dec == 0)), "accept_conc": int(np.sum(dec == 1)),
                       "accept_nmax": int(np.sum(dec == 2)), "accepted_listed": int(len(ia))},
         "exhaustive": {"ms_per_step": ms_ex, "value": n / (ms_ex * 1e-3), "speedup": ms_ex / ms,

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define BAYESLSH_VERSION 2
+#define BAYESLSH_VERSION 3
 
 typedef enum {
   BLSH_OK = 0,
@@ -210,6 +210,11 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
  *           undecided candidates are compacted into a survivor queue.
  *   batch_blocks_per_cu: blocks per CU of the batched tile kernel (4 waves
  *           each; every wave runs a contiguous range of tiles).
+ *   batch_srp_tile: consecutive candidates of one cosine list per wave tile of
+ *           the batched tile kernel: 128, 256 or 512 (2, 4 or 8 per lane).
+ *   batch_mh_tile: the same for Jaccard lists: 64 or 128 (1 or 2 per lane).
+ *           Both shapes are otherwise chosen by the autotuner (when the call
+ *           autotunes k) or default to 256 and 64.
  *   batch_spill_cap: entries of each measure's survivor queue, split evenly
  *           into one region per wave of the tile kernel; a survivor that finds
  *           its wave's region full keeps running in registers (same result).
@@ -221,8 +226,8 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
  *           caller's list after each launch; a pair that finds its slice full
  *           goes to the list directly (same output, slower).
  *   last_batch_*: set by the library after each batched call (the autotuned
- *           or given k of each measure, in-register levels and blocks per
- *           CU); ignored by bayeslsh_set_tuning. */
+ *           or given k of each measure, tile shapes, in-register levels and
+ *           blocks per CU); ignored by bayeslsh_set_tuning. */
 typedef struct {
   int32_t gather;
   int32_t batch_inreg;
@@ -233,6 +238,10 @@ typedef struct {
   int32_t batch_spill_cap;   /* batched: survivor-queue entries per measure (0 = min(n_cand, 2^24)) */
   int32_t last_batch_k_cosine;
   int32_t acc_stage_cap;     /* accepted-pair staging entries (0 = 2^24 single-call, 2^20 batched) */
+  int32_t batch_srp_tile;    /* 0, 128, 256 or 512 */
+  int32_t batch_mh_tile;     /* 0, 64 or 128 */
+  int32_t last_batch_srp_tile;
+  int32_t last_batch_mh_tile;
 } blsh_tuning;
 int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *tuning_host);
 int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *tuning_host);

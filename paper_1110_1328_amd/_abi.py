@@ -60,7 +60,9 @@ class Tuning(C.Structure):
     _fields_ = [("gather", C.c_int32), ("batch_inreg", C.c_int32), ("batch_blocks_per_cu", C.c_int32),
                 ("last_batch_k_jaccard", C.c_int32), ("last_batch_inreg", C.c_int32),
                 ("last_batch_blocks_per_cu", C.c_int32), ("batch_spill_cap", C.c_int32),
-                ("last_batch_k_cosine", C.c_int32), ("acc_stage_cap", C.c_int32)]
+                ("last_batch_k_cosine", C.c_int32), ("acc_stage_cap", C.c_int32),
+                ("batch_srp_tile", C.c_int32), ("batch_mh_tile", C.c_int32),
+                ("last_batch_srp_tile", C.c_int32), ("last_batch_mh_tile", C.c_int32)]
 
 
 class ListDesc(C.Structure):

@@ -695,11 +695,17 @@ int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
     return fail(BLSH_EINVAL, "tuning.batch_blocks_per_cu must be in [0, 32]");
   if (t->batch_spill_cap < 0) return fail(BLSH_EINVAL, "tuning.batch_spill_cap < 0");
   if (t->acc_stage_cap < 0) return fail(BLSH_EINVAL, "tuning.acc_stage_cap < 0");
+  if (t->batch_srp_tile != 0 && t->batch_srp_tile != 128 && t->batch_srp_tile != 256 && t->batch_srp_tile != 512)
+    return fail(BLSH_EINVAL, "tuning.batch_srp_tile must be 0, 128, 256 or 512");
+  if (t->batch_mh_tile != 0 && t->batch_mh_tile != 64 && t->batch_mh_tile != 128)
+    return fail(BLSH_EINVAL, "tuning.batch_mh_tile must be 0, 64 or 128");
   ctx->tuning.gather = t->gather;
   ctx->tuning.acc_stage_cap = t->acc_stage_cap;
   ctx->tuning.batch_spill_cap = t->batch_spill_cap;
   ctx->tuning.batch_inreg = t->batch_inreg;
   ctx->tuning.batch_blocks_per_cu = t->batch_blocks_per_cu;
+  ctx->tuning.batch_srp_tile = t->batch_srp_tile;
+  ctx->tuning.batch_mh_tile = t->batch_mh_tile;
   return BLSH_OK;
 }
 

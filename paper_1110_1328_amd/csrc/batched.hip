@@ -2,9 +2,10 @@
 // graph-launched pair of persistent kernels (Algorithm 1 per candidate).
 //
 // Phase 1 (k_batch_phase1, one launch per measure): the batch is cut into
-//   wave tiles -- 256 consecutive candidates of one SRP list (4 per lane) or
-//   64 of one minhash list (lane l owns candidate l, a group of k/4 lanes
-//   compares each candidate's k hashes) -- and every wave of the fixed grid
+//   wave tiles -- 128, 256 or 512 consecutive candidates of one SRP list (2, 4
+//   or 8 per lane) or 64 or 128 of one minhash list (lane l owns candidates l
+//   and 64 + l, a group of k/4 lanes compares each candidate's k hashes), the
+//   shape per measure chosen by the autotuner -- and every wave of the fixed grid
 //   runs one contiguous range of tiles (no work counter, no block barrier),
 //   each XCD an eighth of every list (L2 locality of sorted ids).  The
 //   query's hashes are wave-uniform.  Each list carries its own measure and
@@ -23,8 +24,8 @@
 //
 // The kernels read all their arguments from one device-resident BatchBlock,
 // so the graph that holds [reset, phase 1 x 2, phase 2, flush] is captured
-// once per (k pair, grid) and replayed for any batch: each call only refreshes
-// the block.
+// once per (k pair, tile shapes, grid) and replayed for any batch: each call
+// only refreshes the block and the tile prefix sums.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -38,8 +39,11 @@ namespace blsh {
 
 constexpr int kMaxBatchTables = 64;
 constexpr int kBBlock = 256;
-constexpr int kSrpTile = 256;      // phase 1: candidates per SRP wave tile (64 lanes x 4)
-constexpr int kMhTile = 64;        // phase 1: candidates per minhash wave tile (one per lane)
+// phase 1 wave tiles (the autotuner picks one shape per measure):
+// SRP 128, 256 or 512 consecutive candidates (2, 4 or 8 per lane), minhash 64
+// or 128 (1 or 2 per lane)
+constexpr int kSrpTileDefault = 256;
+constexpr int kMhTileDefault = 64;
 constexpr int kExSrpTile = 1024;   // comparator: candidates per SRP block tile
 constexpr int kExMhTile = 256;     // comparator: candidates per minhash block tile
 constexpr int kXcds = 8;           // phase 1: list tiles split in kXcds position ranges, one per XCD
@@ -211,11 +215,10 @@ __device__ inline uint32_t prefix_agree(const uint32_t *d, int j) {
   else return 16u - __popc((d[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu);
 }
 
-// 256 consecutive candidates of one SRP list: candidate base + 64 p + lane.
-template <int K>
+// 64 P consecutive candidates of one SRP list: candidate base + 64 p + lane.
+template <int K, int P>
 __device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_id, int64_t base,
                          const uint32_t *tab, int L, int64_t wave, uint32_t &n_spill) {
-  constexpr int P = kSrpTile / kWave;
   constexpr int PL = 128 / K;          // levels held by a 128-bit prefix
   const SigView S = B.sig[BLSH_COSINE];
   const int words = int(ld_uniform(tab + 2));
@@ -320,75 +323,107 @@ __device__ void srp_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_
   }
 }
 
-// 64 consecutive candidates of one minhash list: lane l owns candidate base + l;
-// the group of G = k/4 lanes holding a candidate compares the k hashes of each
-// of its G members in turn (lane r holds hashes 4r..4r+3 of the level), with
-// the group's rows loaded before any comparison.
-template <int K>
+// 64 P consecutive candidates of one minhash list: lane l owns candidates
+// base + 64 p + l; the group of G = k/4 lanes holding a candidate compares the
+// k hashes of each of its G members in turn (lane r holds hashes 4r..4r+3 of
+// the level), with the rows of a pass loaded for all P candidates before any
+// comparison.
+template <int K, int P>
 __device__ void minhash_tile(const BatchBlock &B, const BatchList &Ls, int32_t list_id, int64_t base,
                              const uint32_t *tab, int L, int64_t wave, uint32_t &n_spill) {
   constexpr int G = K / 4;
-  constexpr int CH = G < 8 ? G : 8;      // rows in flight per pass
+  constexpr int CH = G < 8 ? G : 8;      // rows in flight per pass and candidate
   const SigView S = B.sig[BLSH_JACCARD];
   const int words = int(ld_uniform(tab + 2));
   const int64_t end = Ls.offset + Ls.length;
   const int lane = lane_id(), r = lane & (G - 1);
-  const int64_t c = base + lane;
   const uint32_t q = Ls.query;
   const bool q_ok = q < S.n_obj;
-  const bool in = c < end;
-  uint32_t y = 0;
-  bool alive = false, bad = false;
-  if (in) {
-    y = __builtin_nontemporal_load(B.cand + c);
-    if (q_ok && y < S.n_obj) alive = true; else bad = true;
+  uint32_t y[P], m[P], alive = 0, bad = 0, in = 0, emit = 0;
+  uint8_t code[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t c = base + p * kWave + lane;
+    y[p] = 0;
+    m[p] = 0;
+    code[p] = 0;
+    if (c < end) {
+      in |= 1u << p;
+      y[p] = __builtin_nontemporal_load(B.cand + c);
+      if (q_ok && y[p] < S.n_obj) alive |= 1u << p; else bad |= 1u << p;
+    }
   }
-  uint32_t m = 0;
-  uint8_t code = 0;
-  bool emit = false;
   auto level = [&](int j) {
     // a lane whose candidate is decided (or invalid) reads the query's row
-    const uint32_t yv = alive ? y : q;
-    uint32_t ys[G];
-    group_bcast_all<G>(yv, ys, std::make_integer_sequence<int, G>{});
+    uint32_t ys[P][G];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      group_bcast_all<G>((alive >> p) & 1u ? y[p] : q, ys[p], std::make_integer_sequence<int, G>{});
     const size_t col = size_t(j) * K + 4 * r;
     const uint4 hq = *reinterpret_cast<const uint4 *>(S.data + size_t(q) * S.row_words + col);
-    uint32_t own = 0;
+    uint32_t own[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) own[p] = 0;
 #pragma unroll
     for (int s0 = 0; s0 < G; s0 += CH) {
-      uint4 hy[CH];
+      uint4 hy[P][CH];
 #pragma unroll
-      for (int s = 0; s < CH; ++s)
-        hy[s] = *reinterpret_cast<const uint4 *>(S.data + size_t(ys[s0 + s]) * S.row_words + col);
+      for (int p = 0; p < P; ++p)
 #pragma unroll
-      for (int s = 0; s < CH; ++s) {
-        uint32_t cnt = uint32_t(hq.x == hy[s].x) + uint32_t(hq.y == hy[s].y) + uint32_t(hq.z == hy[s].z) +
-                       uint32_t(hq.w == hy[s].w);
-        cnt = group_sum<G>(cnt);
-        if (r == s0 + s) own = cnt;
-      }
+        for (int s = 0; s < CH; ++s)
+          hy[p][s] = *reinterpret_cast<const uint4 *>(S.data + size_t(ys[p][s0 + s]) * S.row_words + col);
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+          uint32_t cnt = uint32_t(hq.x == hy[p][s].x) + uint32_t(hq.y == hy[p][s].y) +
+                         uint32_t(hq.z == hy[p][s].z) + uint32_t(hq.w == hy[p][s].w);
+          cnt = group_sum<G>(cnt);
+          if (r == s0 + s) own[p] = cnt;
+        }
     }
-    if (alive) {
-      m += own;
-      if (int(m) < int(ld_uniform(tab + kTabMinOff + j))) { code = uint8_t((BLSH_PRUNED << 6) | j); alive = false; }
-      else if (accept_bit(tab, words, j, int(m))) { code = uint8_t((BLSH_ACCEPT_CONC << 6) | j); alive = false; emit = true; }
-      else if (j == L - 1) { code = uint8_t((BLSH_ACCEPT_NMAX << 6) | j); alive = false; emit = true; }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      if (!((alive >> p) & 1u)) continue;
+      m[p] += own[p];
+      const int mp = int(m[p]);
+      if (mp < int(ld_uniform(tab + kTabMinOff + j))) {
+        code[p] = uint8_t((BLSH_PRUNED << 6) | j);
+        alive &= ~(1u << p);
+      } else if (accept_bit(tab, words, j, mp)) {
+        code[p] = uint8_t((BLSH_ACCEPT_CONC << 6) | j);
+        alive &= ~(1u << p);
+        emit |= 1u << p;
+      } else if (j == L - 1) {
+        code[p] = uint8_t((BLSH_ACCEPT_NMAX << 6) | j);
+        alive &= ~(1u << p);
+        emit |= 1u << p;
+      }
     }
   };
   const int J = min(L, B.inreg_levels);
-  for (int j = 0; j < J && __ballot(alive); ++j) level(j);
+  for (int j = 0; j < J && __ballot(alive != 0); ++j) level(j);
   if (J < L) {
-    const uint4 e = spill_entry(c, uint32_t(list_id), m, uint32_t(J));
-    if (spill_tile<1>(B, BLSH_JACCARD, wave, n_spill, alive ? 1u : 0u, &e)) alive = false;
+    uint4 e[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) e[p] = spill_entry(base + p * kWave + lane, uint32_t(list_id), m[p], uint32_t(J));
+    alive &= ~spill_tile<P>(B, BLSH_JACCARD, wave, n_spill, alive, e);
   }
-  for (int j = J; j < L && __ballot(alive); ++j) level(j);
+  for (int j = J; j < L && __ballot(alive != 0); ++j) level(j);
   if (bad) raise_status(B.status, BLSH_EBADID);
-  if (in) {
-    B.code[c] = bad ? uint8_t(0xFF) : code;
-    if (B.m_dbg) B.m_dbg[c] = uint16_t(m);
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if (!((in >> p) & 1u)) continue;
+    const int64_t c = base + p * kWave + lane;
+    B.code[c] = (bad >> p) & 1u ? uint8_t(0xFF) : code[p];
+    if (B.m_dbg) B.m_dbg[c] = uint16_t(m[p]);
   }
-  const float v = emit ? map_estimate(BLSH_JACCARD, int(m), ((code & 63) + 1) * K, B.alpha, B.beta) : 0.f;
-  emit_block(B, emit, c, v);
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const bool e = (emit >> p) & 1u;
+    const float v = e ? map_estimate(BLSH_JACCARD, int(m[p]), ((code[p] & 63) + 1) * K, B.alpha, B.beta) : 0.f;
+    emit_block(B, e, base + p * kWave + lane, v);
+  }
 }
 
 // Index of the list holding tile t (the last l with prefix[l] <= t).
@@ -401,10 +436,12 @@ __device__ inline int64_t list_of_tile(const int64_t *prefix, int64_t n_lists, i
   return lo;
 }
 
-// The tiles [t0, t1) of slice x, run in order by one wave.
-template <int KJ, int KC>
+// The tiles [t0, t1) of slice x, run in order by one wave (lists of measure
+// MEAS, 64 P candidates per tile).
+template <int MEAS, int K, int P>
 __device__ inline void phase1_range(const BatchBlock &B, int x, const int64_t *prefix, int64_t t0, int64_t t1,
-                                    int64_t wave, uint32_t &n_spill_j, uint32_t &n_spill_c) {
+                                    int64_t wave, uint32_t &n_spill) {
+  constexpr int64_t tsz = int64_t(P) * kWave;
   int64_t l = list_of_tile(prefix, B.n_lists, t0);
   int64_t first = ld_uniform(prefix + l), next = ld_uniform(prefix + l + 1);
   for (int64_t t = t0; t < t1; ++t) {
@@ -416,12 +453,11 @@ __device__ inline void phase1_range(const BatchBlock &B, int x, const int64_t *p
     const BatchList Ls = ld_list(B.lists + l);
     const uint32_t *tab = ld_uniform(B.tables + Ls.table);
     const int L = ld_uniform(B.n_levels + Ls.table);
-    const int64_t tsz = Ls.measure == BLSH_COSINE ? kSrpTile : kMhTile;
     const int64_t tile = (int64_t(x) * ((Ls.length + tsz - 1) / tsz)) / kXcds + (t - first);
-    if (Ls.measure == BLSH_COSINE)
-      srp_tile<KC>(B, Ls, int32_t(l), Ls.offset + tile * kSrpTile, tab, L, wave, n_spill_c);
+    if constexpr (MEAS == BLSH_COSINE)
+      srp_tile<K, P>(B, Ls, int32_t(l), Ls.offset + tile * tsz, tab, L, wave, n_spill);
     else
-      minhash_tile<KJ>(B, Ls, int32_t(l), Ls.offset + tile * kMhTile, tab, L, wave, n_spill_j);
+      minhash_tile<K, P>(B, Ls, int32_t(l), Ls.offset + tile * tsz, tab, L, wave, n_spill);
   }
 }
 
@@ -430,25 +466,25 @@ __device__ inline void phase1_range(const BatchBlock &B, int x, const int64_t *p
 // (by position) of every list's tiles: lists hold sorted candidate ids, so an
 // XCD touches about an eighth of the signature rows and its L2 holds them.
 // Within an XCD every wave runs a contiguous range of that XCD's tiles.  One
-// launch runs the lists of one measure (`meas`), so the streaming minhash rows
+// launch runs the lists of one measure (MEAS), so the streaming minhash rows
 // do not evict the SRP rows from L2.
-template <int KJ, int KC>
-__global__ __launch_bounds__(kBBlock) void k_batch_phase1(const BatchBlock *__restrict__ Bp, int meas) {
+template <int MEAS, int K, int P>
+__global__ __launch_bounds__(kBBlock) void k_batch_phase1(const BatchBlock *__restrict__ Bp) {
   const BatchBlock &B = *Bp;
   const int x = int(blockIdx.x) % kXcds;
   const int64_t nbx = (int64_t(gridDim.x) - x + kXcds - 1) / kXcds;      // blocks on this XCD (grid >= kXcds)
   const int64_t wx = int64_t(blockIdx.x / kXcds) * (kBBlock / kWave) +
                      int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
   const int64_t Wx = nbx * (kBBlock / kWave);
-  const int64_t *prefix = B.tile_prefix + int64_t(meas * kXcds + x) * (B.n_lists + 1);
+  const int64_t *prefix = B.tile_prefix + int64_t(MEAS * kXcds + x) * (B.n_lists + 1);
   const int64_t Tx = ld_uniform(prefix + B.n_lists);
   const int64_t t0 = wx * Tx / Wx, t1 = (wx + 1) * Tx / Wx;
   const int64_t wave = int64_t(blockIdx.x) * (kBBlock / kWave) +
                        int64_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave));
-  uint32_t n_spill_j = 0, n_spill_c = 0;
-  if (t0 < t1) phase1_range<KJ, KC>(B, x, prefix, t0, t1, wave, n_spill_j, n_spill_c);
+  uint32_t n_spill = 0;
+  if (t0 < t1) phase1_range<MEAS, K, P>(B, x, prefix, t0, t1, wave, n_spill);
   if (lane_id() == 0)   // every wave of the grid reports its fill, 0 included
-    B.spill_count[meas][wave] = meas == BLSH_COSINE ? n_spill_c : n_spill_j;
+    B.spill_count[MEAS][wave] = n_spill;
 }
 
 // ---------------------------------------------------------------------------
@@ -875,13 +911,15 @@ struct BatchState {
   bool staged_valid = false;
   hipStream_t cap_stream{};
   struct GraphKey {
-    int mode, kj, kc, grid1, grid2;
+    int mode, kj, kc, ts, tm, grid1, grid2;
     bool operator<(const GraphKey &o) const {
-      return std::tie(mode, kj, kc, grid1, grid2) < std::tie(o.mode, o.kj, o.kc, o.grid1, o.grid2);
+      return std::tie(mode, kj, kc, ts, tm, grid1, grid2) < std::tie(o.mode, o.kj, o.kc, o.ts, o.tm, o.grid1, o.grid2);
     }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
-  struct Choice { int kj, kc, inreg, bpc; };
+  // k per measure, SRP / minhash tile (candidates per wave tile), in-register
+  // levels, blocks per CU
+  struct Choice { int kj, kc, ts, tm, inreg, bpc; };
   std::map<std::vector<int64_t>, Choice> tuned;
 };
 
@@ -972,35 +1010,47 @@ static int grow_spill(BatchState *b, int64_t cap) {
   return BLSH_OK;
 }
 
+template <int KC>
+static void launch_phase1_srp(const BatchBlock *blk, int ts, int grid1, hipStream_t s) {
+  if (ts == 128) hipLaunchKernelGGL((k_batch_phase1<BLSH_COSINE, KC, 2>), dim3(grid1), dim3(kBBlock), 0, s, blk);
+  else if (ts == 512) hipLaunchKernelGGL((k_batch_phase1<BLSH_COSINE, KC, 8>), dim3(grid1), dim3(kBBlock), 0, s, blk);
+  else hipLaunchKernelGGL((k_batch_phase1<BLSH_COSINE, KC, 4>), dim3(grid1), dim3(kBBlock), 0, s, blk);
+}
+
+template <int KJ>
+static void launch_phase1_mh(const BatchBlock *blk, int tm, int grid1, hipStream_t s) {
+  if (tm == 128) hipLaunchKernelGGL((k_batch_phase1<BLSH_JACCARD, KJ, 2>), dim3(grid1), dim3(kBBlock), 0, s, blk);
+  else hipLaunchKernelGGL((k_batch_phase1<BLSH_JACCARD, KJ, 1>), dim3(grid1), dim3(kBBlock), 0, s, blk);
+}
+
 template <int KJ, int KC>
-static void launch_batch_kernels(BatchState *b, int mode, int grid1, int grid2, hipStream_t s) {
+static void launch_batch_kernels(BatchState *b, const BatchState::GraphKey &gk, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kSlices), 0, s, b->d_block);
-  if (mode == 1) {
-    hipLaunchKernelGGL((k_batch_exhaustive<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block);
+  if (gk.mode == 1) {
+    hipLaunchKernelGGL((k_batch_exhaustive<KJ, KC>), dim3(gk.grid1), dim3(kBBlock), 0, s, b->d_block);
   } else {
-    hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block, int(BLSH_COSINE));
-    hipLaunchKernelGGL((k_batch_phase1<KJ, KC>), dim3(grid1), dim3(kBBlock), 0, s, b->d_block, int(BLSH_JACCARD));
-    hipLaunchKernelGGL((k_batch_phase2<KJ, KC>), dim3(grid2), dim3(kBBlock), 0, s, b->d_block);
+    launch_phase1_srp<KC>(b->d_block, gk.ts, gk.grid1, s);
+    launch_phase1_mh<KJ>(b->d_block, gk.tm, gk.grid1, s);
+    hipLaunchKernelGGL((k_batch_phase2<KJ, KC>), dim3(gk.grid2), dim3(kBBlock), 0, s, b->d_block);
   }
   hipLaunchKernelGGL(k_batch_flush, dim3(kSlices), dim3(kBBlock), 0, s, b->d_block);
 }
 
 template <int KJ>
-static void launch_batch_kernels_kc(BatchState *b, int kc, int mode, int grid1, int grid2, hipStream_t s) {
-  if (kc == 16) launch_batch_kernels<KJ, 16>(b, mode, grid1, grid2, s);
-  else if (kc == 32) launch_batch_kernels<KJ, 32>(b, mode, grid1, grid2, s);
-  else launch_batch_kernels<KJ, 64>(b, mode, grid1, grid2, s);
+static void launch_batch_kernels_kc(BatchState *b, const BatchState::GraphKey &gk, hipStream_t s) {
+  if (gk.kc == 16) launch_batch_kernels<KJ, 16>(b, gk, s);
+  else if (gk.kc == 32) launch_batch_kernels<KJ, 32>(b, gk, s);
+  else launch_batch_kernels<KJ, 64>(b, gk, s);
 }
 
-static int get_graph(BatchState *b, int mode, int kj, int kc, int grid1, int grid2, hipGraphExec_t *out) {
-  BatchState::GraphKey key{mode, kj, kc, grid1, grid2};
+static int get_graph(BatchState *b, const BatchState::GraphKey &key, hipGraphExec_t *out) {
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) { *out = it->second; return BLSH_OK; }
   hipGraph_t g;
   BLSH_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-  if (kj == 16) launch_batch_kernels_kc<16>(b, kc, mode, grid1, grid2, b->cap_stream);
-  else if (kj == 32) launch_batch_kernels_kc<32>(b, kc, mode, grid1, grid2, b->cap_stream);
-  else launch_batch_kernels_kc<64>(b, kc, mode, grid1, grid2, b->cap_stream);
+  if (key.kj == 16) launch_batch_kernels_kc<16>(b, key, b->cap_stream);
+  else if (key.kj == 32) launch_batch_kernels_kc<32>(b, key, b->cap_stream);
+  else launch_batch_kernels_kc<64>(b, key, b->cap_stream);
   BLSH_HIP(hipStreamEndCapture(b->cap_stream, &g));
   hipGraphExec_t ex;
   hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -1040,11 +1090,9 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
   // --- work decomposition (does not depend on k) ---
   if ((rc = grow_lists(b, n_lists))) return rc;
   if (b->staged_valid) BLSH_HIP(hipEventSynchronize(b->staged));   // previous call's staging copies are done
-  const int64_t srp_tile = mode ? kExSrpTile : kSrpTile, mh_tile = mode ? kExMhTile : kMhTile;
-  // tile prefix sums: one array (comparator) or one per (measure, XCD slice)
+  // list descriptors; the tile prefix sums depend on the tile shapes and are
+  // built by prepare()
   const int n_slices = mode ? 1 : 2 * kXcds;
-  int64_t tiles = 0;
-  for (int x = 0; x < n_slices; ++x) b->h_prefix[int64_t(x) * (n_lists + 1)] = 0;
   for (int64_t i = 0; i < n_lists; ++i) {
     const blsh_list_desc &d = lists[i];
     BatchList &bl = b->h_lists[i];
@@ -1054,30 +1102,48 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     bl.measure = d.measure;
     bl.table = int32_t(std::lower_bound(ts.begin(), ts.end(), d.t) - ts.begin()) * 2 + (d.measure == BLSH_COSINE);
     bl.pad = 0;
-    const int64_t tsz = d.measure == BLSH_COSINE ? srp_tile : mh_tile;
-    const int64_t nt = (d.length + tsz - 1) / tsz;
-    tiles += nt;
-    for (int x = 0; x < n_slices; ++x) {
-      int64_t *px = b->h_prefix + int64_t(x) * (n_lists + 1);
-      if (mode) {
-        px[i + 1] = px[i] + nt;
-      } else {
-        const int me = x / kXcds, xs = x % kXcds;
-        px[i + 1] = px[i] + (me == d.measure ? (int64_t(xs + 1) * nt) / kXcds - (int64_t(xs) * nt) / kXcds : 0);
+  }
+  // tile prefix sums for SRP / minhash tiles of srp_tile / mh_tile candidates:
+  // one array (comparator) or one per (measure, XCD slice)
+  int64_t tiles = 0;
+  auto build_prefix = [&](int64_t srp_tile, int64_t mh_tile) {
+    tiles = 0;
+    for (int x = 0; x < n_slices; ++x) b->h_prefix[int64_t(x) * (n_lists + 1)] = 0;
+    for (int64_t i = 0; i < n_lists; ++i) {
+      const blsh_list_desc &d = lists[i];
+      const int64_t tsz = d.measure == BLSH_COSINE ? srp_tile : mh_tile;
+      const int64_t nt = (d.length + tsz - 1) / tsz;
+      tiles += nt;
+      for (int x = 0; x < n_slices; ++x) {
+        int64_t *px = b->h_prefix + int64_t(x) * (n_lists + 1);
+        if (mode) {
+          px[i + 1] = px[i] + nt;
+        } else {
+          const int me = x / kXcds, xs = x % kXcds;
+          px[i + 1] = px[i] + (me == d.measure ? (int64_t(xs + 1) * nt) / kXcds - (int64_t(xs) * nt) / kXcds : 0);
+        }
       }
     }
-  }
+  };
+  int64_t prefix_shape[2] = {-1, -1};   // tile shapes of the prefix sums last uploaded in this call
   const int64_t spill_cap = ctx->tuning.batch_spill_cap > 0
                                 ? int64_t(ctx->tuning.batch_spill_cap)
                                 : std::max<int64_t>(1024, std::min<int64_t>(n_cand, int64_t(1) << 24));
   if ((rc = grow_spill(b, spill_cap))) return rc;
 
-  auto prepare = [&](int kkj, int kkc, int inreg, int grid1) -> int {
+  auto prepare = [&](int kkj, int kkc, int64_t srp_tile, int64_t mh_tile, int inreg, int grid1) -> int {
     const int kk[2] = {kkj, kkc};
-    // the pinned staging block is read by the copy enqueued by the previous
-    // prepare (the autotuner enqueues several per call): wait for that copy
-    // before rewriting the block
+    // the pinned staging (block, prefix sums) is read by the copies enqueued by
+    // the previous prepare (the autotuner enqueues several per call): wait for
+    // those copies before rewriting it
     BLSH_HIP(hipEventSynchronize(b->staged));
+    if (prefix_shape[0] != srp_tile || prefix_shape[1] != mh_tile) {
+      build_prefix(srp_tile, mh_tile);
+      BLSH_HIP(hipMemcpyAsync(b->d_prefix, b->h_prefix, n_slices * (n_lists + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
+      prefix_shape[0] = srp_tile;
+      prefix_shape[1] = mh_tile;
+    }
     BatchBlock &B = *b->h_block;
     std::memset(&B, 0, sizeof(B));
     B.lists = b->d_lists;
@@ -1133,28 +1199,31 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     return BLSH_OK;
   };
   BLSH_HIP(hipMemcpyAsync(b->d_lists, b->h_lists, n_lists * sizeof(BatchList), hipMemcpyHostToDevice, s));
-  BLSH_HIP(hipMemcpyAsync(b->d_prefix, b->h_prefix, n_slices * (n_lists + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
-                          s));
 
   auto run = [&](const BatchState::Choice &c) -> int {
     const int grid1 = std::max(kXcds, ctx->n_cu * c.bpc);   // phase 1 needs a block on every XCD slice
     int r2 = grow_spill_counts(b, int64_t(grid1) * (kBBlock / kWave));
     if (r2) return r2;
-    if ((r2 = prepare(c.kj, c.kc, c.inreg, grid1))) return r2;
+    const int ts = mode ? kExSrpTile : c.ts, tm = mode ? kExMhTile : c.tm;
+    if ((r2 = prepare(c.kj, c.kc, ts, tm, c.inreg, grid1))) return r2;
     const int grid2 = std::max(1, ctx->n_cu * 4);
     hipGraphExec_t ex;
-    if ((r2 = get_graph(b, mode, c.kj, c.kc, grid1, grid2, &ex))) return r2;
+    if ((r2 = get_graph(b, BatchState::GraphKey{mode, c.kj, c.kc, ts, tm, grid1, grid2}, &ex))) return r2;
     LaunchScope ls(ctx, s, mode ? "batched_exhaustive_graph" : "batched_graph");
     BLSH_HIP(hipGraphLaunch(ex, s));
     return BLSH_OK;
   };
 
   // k of a measure no list uses is irrelevant: 32
-  BatchState::Choice ch{kj ? kj : 32, kc ? kc : 32, 2, 8};
+  BatchState::Choice ch{kj ? kj : 32, kc ? kc : 32, kSrpTileDefault, kMhTileDefault, 2, 8};
+  const int fixed_tile[2] = {ctx->tuning.batch_mh_tile, ctx->tuning.batch_srp_tile};
+  if (fixed_tile[0] > 0) ch.tm = fixed_tile[0];
+  if (fixed_tile[1] > 0) ch.ts = fixed_tile[1];
   if ((kj == 0 || kc == 0) && mode == 0) {
     // autotune (cached per context and batch shape): each free k in turn with
     // the other fixed (the two measures' tiles share the grid but not their
-    // work), then in-register levels x blocks per CU at the chosen pair
+    // work), then each used measure's tile shape at its k, then in-register
+    // levels x blocks per CU at the chosen shapes
     std::vector<int64_t> key{n_lists, n_cand >> 16, int64_t(need[0]), int64_t(need[1]), n_max[0], n_max[1],
                              int64_t(ts.size()), kj, kc};
     auto it = b->tuned.find(key);
@@ -1194,6 +1263,22 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
         }
         ch = pick;
       }
+      for (int me = 0; me < 2; ++me) {
+        if (!need[me] || fixed_tile[me] > 0) continue;
+        static constexpr int kSrpShapes[] = {128, 256, 512}, kMhShapes[] = {64, 128};
+        const int *shapes = me ? kSrpShapes : kMhShapes;
+        const int n_shapes = me ? 3 : 2;
+        float best = 1e30f;
+        BatchState::Choice pick = ch;
+        for (int i = 0; i < n_shapes; ++i) {
+          BatchState::Choice c = ch;
+          (me ? c.ts : c.tm) = shapes[i];
+          float ms = 0.f;
+          if ((rc = time_of(c, &ms))) return rc;
+          if (ms < best) { best = ms; pick = c; }
+        }
+        ch = pick;
+      }
       float best = 1e30f;
       BatchState::Choice pick = ch;
       for (int inreg : {1, 2, 4, kMaxLevels})   // kMaxLevels: every level in registers, no queue
@@ -1211,12 +1296,16 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
   }
   if (ctx->tuning.batch_inreg > 0) ch.inreg = ctx->tuning.batch_inreg;
   if (ctx->tuning.batch_blocks_per_cu > 0) ch.bpc = ctx->tuning.batch_blocks_per_cu;
+  if (fixed_tile[0] > 0) ch.tm = fixed_tile[0];
+  if (fixed_tile[1] > 0) ch.ts = fixed_tile[1];
   if ((rc = run(ch))) return rc;
   if (k_used) { k_used[0] = ch.kj; k_used[1] = ch.kc; }
   ctx->tuning.last_batch_k_jaccard = ch.kj;
   ctx->tuning.last_batch_k_cosine = ch.kc;
   ctx->tuning.last_batch_inreg = ch.inreg;
   ctx->tuning.last_batch_blocks_per_cu = ch.bpc;
+  ctx->tuning.last_batch_srp_tile = mode ? kExSrpTile : ch.ts;
+  ctx->tuning.last_batch_mh_tile = mode ? kExMhTile : ch.tm;
   return BLSH_OK;
 }
 

@@ -121,6 +121,36 @@ def test_batched_matches_oracle(ctx, workload, k):
     assert len(set(want["decision"].tolist())) == 3
 
 
+@pytest.mark.parametrize("k", [16, 32, 64])
+def test_batched_tile_shapes_match_oracle(ctx, workload, k):
+    """Every phase-1 tile shape: SRP wave tiles of 128, 256 and 512 candidates
+    (2, 4, 8 per lane), minhash tiles of 64 and 128 (1, 2 per lane), each with
+    survivors queued after one level and with every level in registers; the
+    output is the oracle's list by list."""
+    print("batched tile shapes k=%d" % k, flush=True)
+    want = oracle_batched(workload, k)
+    try:
+        for ts in (128, 256, 512):
+            for tm in (64, 128):
+                for inreg in (1, 64):
+                    P.bayeslsh_set_tuning(ctx, batch_inreg=inreg, batch_blocks_per_cu=2, batch_srp_tile=ts,
+                                          batch_mh_tile=tm)
+                    _, got = run_batched(ctx, workload, k, layout=P.OBJECT_MAJOR if ts == 256 else P.WORD_MAJOR)
+                    t = P.bayeslsh_get_tuning(ctx)
+                    assert (t["last_batch_srp_tile"], t["last_batch_mh_tile"]) == (ts, tm)
+                    check(got, want)
+    finally:
+        P.bayeslsh_set_tuning(ctx)
+
+
+def test_batched_tile_shape_rejected(ctx):
+    for kw in ({"batch_srp_tile": 64}, {"batch_srp_tile": 1024}, {"batch_mh_tile": 32}, {"batch_mh_tile": 256}):
+        with pytest.raises(P.BayesLSHError) as e:
+            P.bayeslsh_set_tuning(ctx, **kw)
+        assert e.value.code == -1
+    P.bayeslsh_set_tuning(ctx)
+
+
 def test_batched_spill_overflow_and_layout(ctx, workload):
     """A survivor queue far too small: survivors that find it full keep going in
     registers; object-major cosine signatures give the same output."""
@@ -175,6 +205,7 @@ def test_batched_autotune(ctx, workload):
     assert kk[0] in (16, 32, 64) and kk[1] in (16, 32, 64)
     t = P.bayeslsh_get_tuning(ctx)
     assert (t["last_batch_k_jaccard"], t["last_batch_k_cosine"]) == kk and t["last_batch_inreg"] in (1, 2, 4, 64)
+    assert t["last_batch_srp_tile"] in (128, 256, 512) and t["last_batch_mh_tile"] in (64, 128)
     check(got, oracle_batched(workload, kk))
     kk2, _ = run_batched(ctx, workload, 0)   # cached choice: same k
     assert kk2 == kk
