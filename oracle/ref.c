@@ -11,7 +11,9 @@
  *   srp_gauss         standard normal plane entry g(term, bit) for the sign
  *                     random projection family (Section 4.2): Box-Muller in
  *                     FP64 on two Philox words, rounded to float.
- *   srp_sparse_proj   r_b . x in FP64 for sparse rows (Section 4.2).
+ *   srp_sparse_proj   r_b . x in FP64 for sparse rows (Section 4.2), optionally
+ *                     with every plane entry stored in 2 bytes (Section 4.3).
+ *   q16_encode/decode the 2-byte storage of a plane entry (Section 4.3).
  *   minhash           min over the set of (a_h e + b_h) mod (2^31-1)  (Section 4.1).
  *   verify            Algorithm 1 (BayesLSH) / Algorithm 2 (BayesLSH-Lite) per pair,
  *                     reading per-(m,n) decisions memoised by the Python oracle.
@@ -66,17 +68,45 @@ float srp_gauss(uint64_t seed, uint32_t term, uint32_t bit) {
     return (float)z;
 }
 
-/* proj[r][b] = sum over the row's nonzeros of value * g(term, b), in FP64. */
+/* 2-byte storage of a Gaussian sample (Section 4.3, cheaper storage of hash
+ * functions): x in (-8, 8) is kept as the integer floor((x + 8) 2^16 / 16);
+ * values outside the interval saturate to the end codes.  The stored code is
+ * read back as the midpoint of its interval of width 16 / 2^16, so the error
+ * is at most half that width. */
+uint16_t q16_encode(double x) {
+    double c = floor((x + 8.0) * (65536.0 / 16.0));
+    if (c < 0.0) c = 0.0;
+    if (c > 65535.0) c = 65535.0;
+    return (uint16_t)c;
+}
+
+double q16_decode(uint16_t code) {
+    return ((double)code + 0.5) * (16.0 / 65536.0) - 8.0;
+}
+
+void q16_encode_array(const double *x, int64_t n, uint16_t *out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = q16_encode(x[i]);
+}
+
+void q16_decode_array(const uint16_t *c, int64_t n, double *out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = q16_decode(c[i]);
+}
+
+/* proj[r][b] = sum over the row's nonzeros of value * g(term, b), in FP64;
+ * with q16 != 0 each entry g is replaced by its 2-byte code read back. */
 void srp_sparse_proj(const int64_t *offsets, const uint32_t *indices, const float *values,
                      const int64_t *rows, int64_t n_rows, int32_t n_bits, uint64_t seed,
-                     double *proj) {
+                     int32_t q16, double *proj) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < n_rows; ++r) {
         int64_t i = rows[r];
         for (int32_t b = 0; b < n_bits; ++b) {
             double acc = 0.0;
-            for (int64_t e = offsets[i]; e < offsets[i + 1]; ++e)
-                acc += (double)values[e] * (double)srp_gauss(seed, indices[e], (uint32_t)b);
+            for (int64_t e = offsets[i]; e < offsets[i + 1]; ++e) {
+                double g = (double)srp_gauss(seed, indices[e], (uint32_t)b);
+                if (q16) g = q16_decode(q16_encode(g));
+                acc += (double)values[e] * g;
+            }
             proj[r * (int64_t)n_bits + b] = acc;
         }
     }

@@ -48,7 +48,9 @@ def lib():
         L.philox4x32_10.argtypes = [p, p, p]
         L.srp_gauss.argtypes = [u64, C.c_uint32, C.c_uint32]
         L.srp_gauss.restype = C.c_float
-        L.srp_sparse_proj.argtypes = [p, p, p, p, i64, i32, u64, p]
+        L.srp_sparse_proj.argtypes = [p, p, p, p, i64, i32, u64, i32, p]
+        L.q16_encode_array.argtypes = [p, i64, p]
+        L.q16_decode_array.argtypes = [p, i64, p]
         L.minhash.argtypes = [p, p, p, i64, p, p, i32, p]
         L.verify.argtypes = [i32, p, p, i64, i64, i32, p, i32, i32, i32, i32, p, p, p, p, p]
         L.count_all.argtypes = [p, p, i64, i32, p, i32, i32, p]
@@ -119,13 +121,33 @@ def srp_gauss(seed: int, term: int, bit: int) -> float:
     return float(lib().srp_gauss(seed, term, bit))
 
 
-def srp_sparse_projections(offsets, indices, values, n_bits, seed, rows) -> np.ndarray:
+def srp_sparse_projections(offsets, indices, values, n_bits, seed, rows, q16=False) -> np.ndarray:
+    """r_b . x in FP64 for sparse rows (Section 4.2); q16: every plane entry
+    taken through its 2-byte storage (Section 4.3) first."""
     offsets = _c(offsets, np.int64)
     indices = _c(indices, np.uint32)
     values = _c(values, np.float32)
     rows = _c(rows, np.int64)
     out = np.empty((len(rows), n_bits), np.float64)
-    lib().srp_sparse_proj(_ptr(offsets), _ptr(indices), _ptr(values), _ptr(rows), len(rows), n_bits, seed, _ptr(out))
+    lib().srp_sparse_proj(_ptr(offsets), _ptr(indices), _ptr(values), _ptr(rows), len(rows), n_bits, seed,
+                          int(bool(q16)), _ptr(out))
+    return out
+
+
+def q16_encode(x) -> np.ndarray:
+    """2-byte code of Gaussian samples (Section 4.3): floor((x + 8) 2^16 / 16),
+    saturating outside (-8, 8)."""
+    x = _c(np.atleast_1d(x), np.float64)
+    out = np.empty(len(x), np.uint16)
+    lib().q16_encode_array(_ptr(x), len(x), _ptr(out))
+    return out
+
+
+def q16_decode(codes) -> np.ndarray:
+    """The value a 2-byte code stands for: the midpoint of its interval."""
+    c = _c(np.atleast_1d(codes), np.uint16)
+    out = np.empty(len(c), np.float64)
+    lib().q16_decode_array(_ptr(c), len(c), _ptr(out))
     return out
 
 

@@ -285,6 +285,62 @@ def test_gaussian_plane_entries_are_standard_normal():
     assert R.srp_gauss(99, 7, 5) == np.float32(z1)
 
 
+def test_q16_codes_are_the_midpoints_of_a_uniform_grid():
+    """2-byte plane storage (Section 4.3), all 65,536 codes: the values read
+    back form a uniform grid of 2^16 cells over (-8, 8), one value at the
+    middle of each cell, symmetric about 0; every value encodes to its own
+    code; each cell's lower edge belongs to it and its upper edge to the next
+    (the floor of the printed encoding); samples outside (-8, 8) saturate."""
+    codes = np.arange(1 << 16, dtype=np.uint16)
+    d = R.q16_decode(codes)
+    step = 2.0 ** -12                       # 16 / 2^16
+    assert np.all(np.diff(d) == step)
+    assert d[0] == -8 + step / 2 and d[-1] == 8 - step / 2
+    assert np.all(d + d[::-1] == 0)
+    np.testing.assert_array_equal(R.q16_encode(d), codes)
+    lo = -8.0 + codes.astype(np.float64) * step
+    np.testing.assert_array_equal(R.q16_encode(lo), codes)
+    hi = lo + (step - 2.0 ** -32)           # just below the upper edge (exact, also after the shift by 8)
+    np.testing.assert_array_equal(R.q16_encode(hi), codes)
+    np.testing.assert_array_equal(R.q16_encode(lo[1:] - 2.0 ** -32), codes[:-1])
+    np.testing.assert_array_equal(R.q16_encode([-1e9, -8.5, -8.0, 8.0 - 1e-9, 8.0, 1e9]),
+                                  [0, 0, 0, 65535, 65535, 65535])
+
+
+def test_q16_error_bound_and_the_printed_claim():
+    """Read back at the cell midpoint the error is at most half a cell,
+    2^-13 = 1.22e-4, and that bound is reached; it exceeds the 1e-4 the
+    paper prints for the encoding.  A generated plane entry never leaves
+    (-8, 8): the smallest uniform Box-Muller sees is 0.5 / 2^32."""
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-8, 8, 1 << 20)
+    err = np.abs(R.q16_decode(R.q16_encode(x)) - x)
+    assert err.max() <= 2.0 ** -13
+    assert err.max() > 0.999 * 2.0 ** -13 > 1e-4
+    assert math.sqrt(-2 * math.log(0.5 / 2 ** 32)) < 7.0
+    g = np.array([R.srp_gauss(31, t, b) for t in range(40) for b in range(256)])
+    assert np.all(np.abs(R.q16_decode(R.q16_encode(g)) - g) <= 2.0 ** -13)
+
+
+def test_q16_sparse_projection():
+    """Projections over 2-byte plane entries: a numpy recomputation from the
+    entries read back, and within sum |x_i| 2^-13 of the fp32-entry ones."""
+    corpus = G.tfidf_corpus(n_docs=40, dim=1 << 12, mean_nnz=30, seed=22)
+    rows = np.arange(corpus.n, dtype=np.int64)
+    nb = 64
+    proj = R.srp_sparse_projections(corpus.offsets, corpus.indices, corpus.values, nb, 78, rows)
+    projq = R.srp_sparse_projections(corpus.offsets, corpus.indices, corpus.values, nb, 78, rows, q16=True)
+    for r in rows[:3]:
+        idx, val = corpus.row(r)
+        g = np.array([[R.srp_gauss(78, int(t), b) for b in range(nb)] for t in idx], np.float64)
+        gq = R.q16_decode(R.q16_encode(g.ravel())).reshape(g.shape)
+        assert np.any(gq != g)
+        np.testing.assert_allclose(projq[r], val.astype(np.float64) @ gq, rtol=1e-12, atol=1e-14)
+    l1 = np.array([np.abs(corpus.row(r)[1].astype(np.float64)).sum() for r in rows])
+    assert np.all(np.abs(projq - proj) <= l1[:, None] * 2.0 ** -13 + 1e-12)
+    assert np.any(projq != proj)
+
+
 def test_sparse_projection_and_angle_agreement():
     """r . x in FP64 equals a numpy recomputation from the plane entries, and the
     sign bits agree with probability 1 - theta/pi (Section 4.2)."""
