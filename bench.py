@@ -548,7 +548,17 @@ def run_sigs(args, torch, P):
     sparse_ms, sparse_min = timed(lambda: P.bayeslsh_srp_sigs(ctx, vec, None, N_BITS, SRP_SEED, P.OBJECT_MAJOR,
                                                               out_s, s))
     log("sparse SRP: %.3f ms, %.3g Gaussians/s" % (sparse_ms, nnz * N_BITS / (sparse_ms * 1e-3)))
-    del vec, out_s
+    # the same with every plane entry stored in 2 bytes (Section 4.3): the table
+    # of codes is half the bytes; bits differ only where |r . x| is within the
+    # storage error of 0
+    out_q = torch.empty_like(out_s)
+    q16_ms, q16_min = timed(lambda: P.bayeslsh_srp_sigs(ctx, vec, None, N_BITS, SRP_SEED, P.OBJECT_MAJOR,
+                                                        out_q, s, flags=P.SRP_PLANES_Q16))
+    x = out_q.view(torch.int32) ^ out_s.view(torch.int32)
+    flipped = sum(int(((x >> b) & 1).sum().item()) for b in range(32))
+    log("sparse SRP, 2-byte plane entries: %.3f ms; %d of %d bits differ from the fp32-entry signatures"
+        % (q16_ms, flipped, corpus.n * N_BITS))
+    del vec, out_s, out_q, x
     log("planted-group sets (1M), 256 minhashes")
     sets = G.jaccard_sets_large(seed=G.SEED_BASE + 5)
     a, b = G.minhash_coeffs(256, G.SEED_BASE + 205)
@@ -572,6 +582,9 @@ def run_sigs(args, torch, P):
                           "tflops": tflops},
             "sparse_srp": {"ms": sparse_ms, "min_ms": sparse_min, "rows": corpus.n, "nnz": nnz, "n_bits": N_BITS,
                            "gaussians_per_s": nnz * N_BITS / (sparse_ms * 1e-3)},
+            "sparse_srp_q16": {"ms": q16_ms, "min_ms": q16_min, "gaussians_per_s": nnz * N_BITS / (q16_ms * 1e-3),
+                               "bits_differing_from_fp32_entries": flipped,
+                               "note": "plane entries as 2-byte codes (Section 4.3), table of dim x n_bits codes"},
             "minhash": {"ms": mh_ms, "min_ms": mh_min, "sets": sets.n, "elements": n_el, "n_hashes": 256,
                         "hash_evals_per_s": n_el * 256 / (mh_ms * 1e-3)}}
 

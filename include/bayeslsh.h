@@ -283,6 +283,20 @@ int bayeslsh_posterior_table(blsh_ctx *ctx, blsh_measure measure, double t, doub
 int bayeslsh_minhash_sigs(blsh_ctx *ctx, const blsh_vectors *sets, const uint32_t *a, const uint32_t *b,
                           int32_t n_hashes, uint32_t *sigs_out, void *stream);
 
+/* Flags of bayeslsh_srp_sigs. */
+enum {
+  /* Cheaper storage of hash functions (Section 4.3): every generated plane
+   * entry g (CSR vectors) is kept as the 2-byte code
+   * c = floor((g + 8) * 2^16 / 16), clamped to [0, 65535], and used as the
+   * middle of its cell, (c + 0.5) * 16 / 2^16 - 8, so |used - g| <= 2^-13
+   * (about 1.22e-4; the paper prints 1e-4 for this encoding, which its cell
+   * width of 2.44e-4 does not allow).  A generated entry never leaves
+   * (-6.8, 6.8), so no entry saturates.  The plane table, when one is built,
+   * holds the codes: 2 bytes per entry instead of 4.  The signature bits can
+   * differ from the unflagged ones only where |r . x| <= 2^-13 sum |x_i|. */
+  BLSH_SRP_PLANES_Q16 = 1
+};
+
 /* Sign random projections (Section 4.2): bit h of object i is 1 iff r_h . x_i >= 0,
  * packed LSB-first (hash h -> word h/32, bit h%32) in `layout`.
  *   DENSE vectors: planes = float R[dim][n_bits] (device); projections by an
@@ -293,13 +307,15 @@ int bayeslsh_minhash_sigs(blsh_ctx *ctx, const blsh_vectors *sets, const uint32_
  *     u_i = (w_i + 0.5)/2^32, (z0,z1) = BoxMuller(u0,u1), (z2,z3) = BoxMuller(u2,u3),
  *     entry = z_{h mod 4}; projections accumulated in FP64.  The call reads
  *     the nonzero count (offsets[n_obj]) back, waiting for `stream`; when it
- *     exceeds 2 * dim and dim * n_bits * 4 bytes fit in 16 GiB, the entries of
- *     every term < dim are drawn once into a table in the context workspace
- *     and read from there (the same values; an index >= dim, outside the
- *     CSR contract, is drawn as it occurs rather than read past the table).
- * n_bits must be a multiple of 32 (DENSE: of 64). */
+ *     exceeds 2 * dim and dim * n_bits * 4 bytes (2 with BLSH_SRP_PLANES_Q16)
+ *     fit in 16 GiB, the entries of every term < dim are drawn once into a
+ *     table in the context workspace and read from there (the same values;
+ *     an index >= dim, outside the CSR contract, is drawn as it occurs rather
+ *     than read past the table).
+ * flags: 0 or BLSH_SRP_PLANES_Q16 (CSR only; with DENSE vectors it is
+ * BLSH_EINVAL).  n_bits must be a multiple of 32 (DENSE: of 64). */
 int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *planes, int32_t n_bits,
-                      uint64_t seed, blsh_layout layout, uint32_t *bits_out, void *stream);
+                      uint64_t seed, blsh_layout layout, int32_t flags, uint32_t *bits_out, void *stream);
 
 /* ---------------- verification ---------------- */
 

@@ -18,6 +18,7 @@ OBJECT_MAJOR, WORD_MAJOR = 0, 1
 PAIRS, QUERY_LISTS, ALL_PAIRS, TILES = 0, 1, 2, 3
 DENSE, CSR, SETS = 0, 1, 2
 REPLAY, REPLAY_LITE, MLE = 0, 1, 2
+SRP_PLANES_Q16 = 1
 
 p = C.c_void_p
 
@@ -98,7 +99,7 @@ PROTOTYPES = [
      [p, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, Prior, C.c_int32, C.c_int32, C.c_int32, p, p,
       C.POINTER(C.c_double)]),
     ("bayeslsh_minhash_sigs", C.c_int, [p, C.POINTER(Vectors), p, p, C.c_int32, p, p]),
-    ("bayeslsh_srp_sigs", C.c_int, [p, C.POINTER(Vectors), p, C.c_int32, C.c_uint64, C.c_int, p, p]),
+    ("bayeslsh_srp_sigs", C.c_int, [p, C.POINTER(Vectors), p, C.c_int32, C.c_uint64, C.c_int, C.c_int32, p, p]),
     ("bayeslsh_verify", C.c_int,
      [p, C.POINTER(Candidates), C.POINTER(Sigs), C.c_double, C.c_double, C.c_double, C.c_double, Prior, C.c_int32,
       C.POINTER(Result), p]),

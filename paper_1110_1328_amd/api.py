@@ -14,7 +14,8 @@ import torch
 
 from . import _abi as A
 from ._abi import (ACCEPT_CONC, ACCEPT_NMAX, ALL_PAIRS, COSINE, CSR, DENSE, JACCARD, LITE_EXACT, MLE,  # noqa: F401
-                   OBJECT_MAJOR, PAIRS, PRUNED, QUERY_LISTS, REPLAY, REPLAY_LITE, SETS, TILES, WORD_MAJOR)
+                   OBJECT_MAJOR, PAIRS, PRUNED, QUERY_LISTS, REPLAY, REPLAY_LITE, SETS, SRP_PLANES_Q16, TILES,
+                   WORD_MAJOR)
 
 
 class BayesLSHError(RuntimeError):
@@ -394,14 +395,15 @@ def bayeslsh_minhash_sigs(ctx: Context, sets: Vectors, a: torch.Tensor, b: torch
 
 
 def bayeslsh_srp_sigs(ctx: Context, vecs: Vectors, planes, n_bits: int, seed: int, layout: int, out: torch.Tensor,
-                      stream=None):
+                      stream=None, flags: int = 0):
+    """flags: 0 or SRP_PLANES_Q16 (generated plane entries in 2 bytes)."""
     _dev(out, torch.uint32, "bits_out")
     if planes is not None:
         _dev(planes, torch.float32, "planes")
     if out.numel() < vecs.n_obj * (n_bits // 32):
         raise ValueError("bits_out too small")
     v = vecs.struct()
-    _check(_lib().bayeslsh_srp_sigs(ctx.handle, C.byref(v), _p(planes), n_bits, seed, layout, _p(out),
+    _check(_lib().bayeslsh_srp_sigs(ctx.handle, C.byref(v), _p(planes), n_bits, seed, layout, flags, _p(out),
                                     _stream(stream)))
     return out
 

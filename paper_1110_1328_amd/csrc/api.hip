@@ -15,8 +15,8 @@ int launch_zero(blsh_ctx *ctx, int64_t *p, hipStream_t s);
 int launch_minhash(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *elems, int64_t n_sets, const uint32_t *a,
                    const uint32_t *b, int n_hashes, uint32_t *out, hipStream_t s);
 int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *indices, const float *values,
-                      int64_t n_rows, int64_t dim, int n_bits, uint64_t seed, bool word_major, uint32_t *out,
-                      hipStream_t s);
+                      int64_t n_rows, int64_t dim, int n_bits, uint64_t seed, bool word_major, bool q16,
+                      uint32_t *out, hipStream_t s);
 int launch_srp_dense(blsh_ctx *ctx, const float *X, int64_t n_rows, int64_t dim, const float *R, int n_bits,
                      bool word_major, uint32_t *out, hipStream_t s);
 
@@ -749,8 +749,10 @@ int bayeslsh_minhash_sigs(blsh_ctx *ctx, const blsh_vectors *sets, const uint32_
 }
 
 int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *planes, int32_t n_bits, uint64_t seed,
-                      blsh_layout layout, uint32_t *bits_out, void *stream) {
+                      blsh_layout layout, int32_t flags, uint32_t *bits_out, void *stream) {
   if (!ctx || !vecs || !bits_out) return fail(BLSH_EINVAL, "null argument");
+  if (flags & ~int32_t(BLSH_SRP_PLANES_Q16)) return fail(BLSH_EINVAL, "unknown SRP flags 0x%x", unsigned(flags));
+  const bool q16 = (flags & BLSH_SRP_PLANES_Q16) != 0;
   if (n_bits <= 0 || n_bits % 32) return fail(BLSH_EINVAL, "n_bits must be a positive multiple of 32");
   if (layout != BLSH_OBJECT_MAJOR && layout != BLSH_WORD_MAJOR) return fail(BLSH_EINVAL, "bad layout");
   if (vecs->n_obj <= 0) return BLSH_OK;
@@ -758,6 +760,7 @@ int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *plan
   if (vecs->kind == BLSH_DENSE) {
     if (!vecs->dense || !planes) return fail(BLSH_EINVAL, "dense SRP needs vectors and planes");
     if (uintptr_t(vecs->dense) & 15) return fail(BLSH_EINVAL, "dense vectors must be 16-byte aligned");
+    if (q16) return fail(BLSH_EINVAL, "BLSH_SRP_PLANES_Q16 applies to generated (CSR) planes only");
     return launch_srp_dense(ctx, vecs->dense, vecs->n_obj, vecs->dim, planes, n_bits, layout == BLSH_WORD_MAJOR,
                             bits_out, s);
   }
@@ -766,7 +769,7 @@ int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *plan
     if (planes) return fail(BLSH_EINVAL, "CSR SRP generates its planes: pass planes = NULL");
     if (n_bits > 2048) return fail(BLSH_EINVAL, "CSR SRP: n_bits must be <= 2048");
     return launch_srp_sparse(ctx, vecs->offsets, vecs->indices, vecs->values, vecs->n_obj, vecs->dim, n_bits, seed,
-                             layout == BLSH_WORD_MAJOR, bits_out, s);
+                             layout == BLSH_WORD_MAJOR, q16, bits_out, s);
   }
   return fail(BLSH_EINVAL, "SRP needs DENSE or CSR vectors");
 }

@@ -6,11 +6,15 @@
 //   k_srp_sparse       one wave per sparse row, lanes over groups of 4 hashes; plane
 //                      entries come from Philox-4x32-10 + Box-Muller (FP64), the
 //                      projections accumulate in FP64, and the sign bits are packed
-//                      32 to a word with DPP (Section 4.2).
+//                      32 to a word with DPP (Section 4.2).  Optionally every entry
+//                      is stored in 2 bytes (Section 4.3): a table of codes then
+//                      takes half the bytes of the fp32 one.
 //   k_srp_dense_mfma   dense rows times a Gaussian plane matrix on the matrix cores
 //                      (v_mfma_f32_32x32x2f32); each wave keeps 32 rows of X in
 //                      registers, the block stages a 32-plane slice of R in LDS, and
 //                      the sign of every accumulator is packed with a wave ballot.
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace blsh {
@@ -85,6 +89,17 @@ __device__ inline void srp_gauss4(uint32_t term, uint32_t q, uint32_t k0, uint32
   g[3] = double(float(r1 * s3));
 }
 
+// 2-byte storage of a plane entry (Section 4.3): g in (-8, 8) becomes the
+// integer floor((g + 8) 2^16 / 16), saturating outside; the code is read back
+// as the middle of its cell of width 2^-12 (error at most 2^-13).  Both steps
+// are exact in FP64 for every fp32 entry.
+__device__ inline uint32_t q16_code(double g) {
+  const double c = floor((g + 8.0) * 4096.0);
+  return uint32_t(fmin(fmax(c, 0.0), 65535.0));
+}
+
+__device__ inline double q16_value(uint32_t code) { return (double(code) + 0.5) * (1.0 / 4096.0) - 8.0; }
+
 template <int G>
 __device__ inline uint32_t group_or(uint32_t v) {
   if constexpr (G >= 2) v |= dpp<kDppQuadXor1>(v);
@@ -93,11 +108,13 @@ __device__ inline uint32_t group_or(uint32_t v) {
   return v;
 }
 
-// Plane entries of every coordinate term < dim, float table[term][n_bits]: one
-// thread per (term, quad of hashes).  Used when each term occurs in several
-// rows, so that an entry is drawn once instead of once per occurrence.
+// Plane entries of every coordinate term < dim, table[term][n_bits] of fp32
+// (Q16: of 2-byte codes): one thread per (term, quad of hashes).  Used when
+// each term occurs in several rows, so that an entry is drawn once instead of
+// once per occurrence.
+template <bool Q16>
 __global__ __launch_bounds__(256) void k_srp_table(int64_t dim, int32_t n_bits, uint32_t k0, uint32_t k1,
-                                                   float *table) {
+                                                   void *table) {
   const int Q = n_bits / 4;
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= dim * Q) return;
@@ -105,20 +122,50 @@ __global__ __launch_bounds__(256) void k_srp_table(int64_t dim, int32_t n_bits, 
   const int q = int(i % Q);
   double g[4];
   srp_gauss4(uint32_t(term), uint32_t(q), k0, k1, g);
-  *reinterpret_cast<float4 *>(table + size_t(term) * n_bits + 4 * q) =
-      make_float4(float(g[0]), float(g[1]), float(g[2]), float(g[3]));
+  const size_t at = size_t(term) * n_bits + 4 * q;
+  if constexpr (Q16) {
+    const uint2 w = make_uint2(q16_code(g[0]) | q16_code(g[1]) << 16, q16_code(g[2]) | q16_code(g[3]) << 16);
+    *reinterpret_cast<uint2 *>(static_cast<uint16_t *>(table) + at) = w;
+  } else {
+    *reinterpret_cast<float4 *>(static_cast<float *>(table) + at) =
+        make_float4(float(g[0]), float(g[1]), float(g[2]), float(g[3]));
+  }
+}
+
+// The four entries of hashes 4q..4q+3 at `term`, read from the table row or
+// drawn (terms >= dim); Q16: as their 2-byte codes read back.
+template <bool Q16>
+__device__ inline void srp_entry4(const void *table, int64_t dim, int32_t n_bits, uint32_t term, int q, uint32_t k0,
+                                  uint32_t k1, double g[4]) {
+  srp_gauss4(term, uint32_t(q), k0, k1, g);
+  if constexpr (Q16) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g[c] = q16_value(q16_code(g[c]));
+  }
+  (void)table; (void)dim; (void)n_bits;
 }
 
 // TABLE: entries of terms < dim come from the table (the same values the
-// generator gives, since every entry is rounded to fp32), others are drawn.
-template <int QPL, bool TABLE>  // quads (4 hashes) per lane
+// generator gives, since every entry is rounded to fp32, or the same codes),
+// others are drawn.  Q16: every entry is the value its 2-byte code stands for.
+// With a table the row's nonzeros are taken U at a time: the U table rows are
+// requested before any is used, so that U dependent fetches overlap (a batch
+// with a term outside the table leaves the rest of the row to the loop that
+// takes one nonzero at a time).
+// A wave takes one row and 64 QPL consecutive quads of its hashes (a slice;
+// rows of more hashes take several waves).
+template <int QPL, bool TABLE, bool Q16>  // quads (4 hashes) per lane
 __global__ __launch_bounds__(256) void k_srp_sparse(const int64_t *offsets, const uint32_t *indices,
                                                     const float *values, int64_t n_rows, int32_t n_bits,
-                                                    uint32_t k0, uint32_t k1, int32_t word_major, uint32_t *out,
-                                                    const float *table, int64_t dim) {
+                                                    int32_t n_slices, uint32_t k0, uint32_t k1, int32_t word_major,
+                                                    uint32_t *out, const void *table, int64_t dim) {
+  constexpr int U = TABLE ? (Q16 ? 4 : 2) : 1;
+  using Entry = typename std::conditional<Q16, uint2, float4>::type;
   const int lane = lane_id();
-  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t wid = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t row = wid / n_slices;
   if (row >= n_rows) return;  // wave-uniform
+  const int q0 = int(wid % n_slices) * kWave * QPL;   // first quad of the slice
   const int Q = n_bits / 4, W = n_bits / 32;
   double acc[QPL][4];
 #pragma unroll
@@ -126,28 +173,75 @@ __global__ __launch_bounds__(256) void k_srp_sparse(const int64_t *offsets, cons
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[i][c] = 0.0;
   const int64_t s = offsets[row], e = offsets[row + 1];
-  for (int64_t t = s; t < e; ++t) {
+  auto fma4 = [&](int i, double v, const double g[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[i][c] += v * g[c];
+  };
+  auto decode = [&](const Entry &x, double g[4]) {
+    if constexpr (Q16) {
+      g[0] = q16_value(x.x & 0xFFFFu); g[1] = q16_value(x.x >> 16);
+      g[2] = q16_value(x.y & 0xFFFFu); g[3] = q16_value(x.y >> 16);
+    } else {
+      g[0] = x.x; g[1] = x.y; g[2] = x.z; g[3] = x.w;
+    }
+  };
+  int64_t t = s;
+  if constexpr (TABLE) {
+    for (; t + U <= e; t += U) {
+      uint32_t term[U];
+      double v[U];
+      bool in_table = true;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        term[u] = indices[t + u];
+        v[u] = values[t + u];
+        in_table = in_table && int64_t(term[u]) < dim;
+      }
+      if (!in_table) break;   // a term outside the table: the rest of the row one nonzero at a time
+      Entry ent[U][QPL];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+          const int q = q0 + lane + kWave * i;
+          if (q < Q)
+            ent[u][i] = *reinterpret_cast<const Entry *>(static_cast<const typename std::conditional<
+                            Q16, uint16_t, float>::type *>(table) + size_t(term[u]) * n_bits + 4 * q);
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+          const int q = q0 + lane + kWave * i;
+          if (q < Q) {
+            double g[4];
+            decode(ent[u][i], g);
+            fma4(i, v[u], g);
+          }
+        }
+    }
+  }
+  for (; t < e; ++t) {
     const uint32_t term = indices[t];
     const double v = values[t];
 #pragma unroll
     for (int i = 0; i < QPL; ++i) {
-      const int q = lane + kWave * i;
+      const int q = q0 + lane + kWave * i;
       if (q < Q) {
         double g[4];
         if (TABLE && int64_t(term) < dim) {
-          const float4 t4 = *reinterpret_cast<const float4 *>(table + size_t(term) * n_bits + 4 * q);
-          g[0] = t4.x; g[1] = t4.y; g[2] = t4.z; g[3] = t4.w;
+          decode(*reinterpret_cast<const Entry *>(static_cast<const typename std::conditional<
+                     Q16, uint16_t, float>::type *>(table) + size_t(term) * n_bits + 4 * q), g);
         } else {
-          srp_gauss4(term, uint32_t(q), k0, k1, g);
+          srp_entry4<Q16>(table, dim, n_bits, term, q, k0, k1, g);
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[i][c] += v * g[c];
+        fma4(i, v, g);
       }
     }
   }
 #pragma unroll
   for (int i = 0; i < QPL; ++i) {
-    const int q = lane + kWave * i;
+    const int q = q0 + lane + kWave * i;
     uint32_t nib = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) nib |= uint32_t(acc[i][c] >= 0.0) << c;
@@ -258,30 +352,46 @@ int launch_minhash(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *elems,
 constexpr size_t kSrpTableMaxBytes = size_t(16) << 30;
 
 int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *indices, const float *values,
-                      int64_t n_rows, int64_t dim, int n_bits, uint64_t seed, bool word_major, uint32_t *out,
-                      hipStream_t s) {
-  const int qpl = (n_bits / 4 + kWave - 1) / kWave;
-  if (qpl > 8) return fail(BLSH_EINVAL, "srp (sparse): n_bits %d > 2048", n_bits);
-  const int64_t nb = (n_rows + 3) / 4;
+                      int64_t n_rows, int64_t dim, int n_bits, uint64_t seed, bool word_major, bool q16,
+                      uint32_t *out, hipStream_t s) {
+  // quads per lane: up to 4 (1024 hashes per wave); longer rows in slices of 1024
+  const int quads = n_bits / 4;
+  const int qpl_all = (quads + kWave - 1) / kWave;
+  if (qpl_all > 8) return fail(BLSH_EINVAL, "srp (sparse): n_bits %d > 2048", n_bits);
+  const int qpl = std::min(qpl_all, 4);
+  const int n_slices = (qpl_all + qpl - 1) / qpl;
+  const int64_t nb = (n_rows * n_slices + 3) / 4;
   const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
   // a table of plane entries pays when terms repeat: more nonzeros than twice the dimension
   int64_t nnz = 0;
   BLSH_HIP(hipMemcpyAsync(&nnz, offsets + n_rows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   BLSH_HIP(hipStreamSynchronize(s));
-  const size_t table_bytes = size_t(std::max<int64_t>(dim, 0)) * size_t(n_bits) * sizeof(float);
+  const size_t entry_bytes = q16 ? sizeof(uint16_t) : sizeof(float);
+  const size_t table_bytes = size_t(std::max<int64_t>(dim, 0)) * size_t(n_bits) * entry_bytes;
   const bool use_table = dim > 0 && nnz > 2 * dim && table_bytes <= kSrpTableMaxBytes;
-  float *table = nullptr;
+  void *table = nullptr;
   if (use_table) {
     if (int rc = ensure_workspace(ctx, table_bytes)) return rc;
-    table = static_cast<float *>(ctx->ws);
+    table = ctx->ws;
   }
   LaunchScope ls(ctx, s, "srp_sparse");
   if (use_table) {
     const int64_t items = dim * (n_bits / 4);
-    hipLaunchKernelGGL(k_srp_table, dim3(unsigned((items + 255) / 256)), dim3(256), 0, s, dim, n_bits, k0, k1, table);
+    const dim3 g(unsigned((items + 255) / 256));
+    if (q16) hipLaunchKernelGGL(k_srp_table<true>, g, dim3(256), 0, s, dim, n_bits, k0, k1, table);
+    else hipLaunchKernelGGL(k_srp_table<false>, g, dim3(256), 0, s, dim, n_bits, k0, k1, table);
   }
-#define BLSH_SP(N) if (qpl <= N) { if (use_table) hipLaunchKernelGGL((k_srp_sparse<N, true>), dim3(nb), dim3(256), 0, s, offsets, indices, values, n_rows, n_bits, k0, k1, int(word_major), out, table, dim); else hipLaunchKernelGGL((k_srp_sparse<N, false>), dim3(nb), dim3(256), 0, s, offsets, indices, values, n_rows, n_bits, k0, k1, int(word_major), out, table, dim); return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE; }
-  BLSH_SP(1) BLSH_SP(2) BLSH_SP(4) BLSH_SP(8)
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, offsets, indices, values, n_rows, n_bits, n_slices, k0, k1,
+                       int(word_major), out, static_cast<const void *>(table), dim);
+    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
+  };
+#define BLSH_SP(N)                                                           \
+  if (qpl <= N) {                                                            \
+    if (use_table) return q16 ? go(k_srp_sparse<N, true, true>) : go(k_srp_sparse<N, true, false>); \
+    return q16 ? go(k_srp_sparse<N, false, true>) : go(k_srp_sparse<N, false, false>);              \
+  }
+  BLSH_SP(1) BLSH_SP(2) BLSH_SP(4)
 #undef BLSH_SP
   return fail(BLSH_EINVAL, "srp (sparse): n_bits %d > 2048", n_bits);
 }
