@@ -897,8 +897,12 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
       w_cnt += __popcll(em);
     }
     wave_lds_sync();
-    // the tile's codes as one run of candidates [first, first + count)
-    for (int i = lane; i < count; i += kWave) a.code[first + i] = S.code[i];
+    // the tile's codes as one run of candidates [first, first + count), count <= 256
+#pragma unroll
+    for (int u = 0; u < 256 / kWave; ++u) {
+      const int i = lane + kWave * u;
+      if (i < count) a.code[first + i] = S.code[i];
+    }
     wave_lds_sync();   // the next tile's staging overwrites these rows and lists
   }
   if (lane == 0) a.wst_cnt[gw] = uint32_t(min<int64_t>(w_cnt, a.st_cap));
