@@ -108,17 +108,32 @@ __device__ inline uint32_t group_or(uint32_t v) {
   return v;
 }
 
-// Plane entries of every coordinate term < dim, table[term][n_bits] of fp32
-// (Q16: of 2-byte codes): one thread per (term, quad of hashes).  Used when
-// each term occurs in several rows, so that an entry is drawn once instead of
-// once per occurrence.
+// used[term] = 1 for every term < dim that some nonzero holds (used[] zeroed
+// before).
+__global__ __launch_bounds__(256) void k_srp_mark(const uint32_t *indices, int64_t nnz, int64_t dim,
+                                                  uint8_t *used) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < nnz; i += int64_t(gridDim.x) * 256) {
+    const uint32_t t = indices[i];
+    if (int64_t(t) < dim) used[t] = 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u8(uint8_t *p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) p[i] = 0;
+}
+
+// Plane entries of the terms < dim that occur (used[term] != 0),
+// table[term][n_bits] of fp32 (Q16: of 2-byte codes): one thread per (term,
+// quad of hashes).  Used when each term occurs in several rows, so that an
+// entry is drawn once instead of once per occurrence.
 template <bool Q16>
 __global__ __launch_bounds__(256) void k_srp_table(int64_t dim, int32_t n_bits, uint32_t k0, uint32_t k1,
-                                                   void *table) {
+                                                   const uint8_t *used, void *table) {
   const int Q = n_bits / 4;
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= dim * Q) return;
   const int64_t term = i / Q;
+  if (!used[term]) return;
   const int q = int(i % Q);
   double g[4];
   srp_gauss4(uint32_t(term), uint32_t(q), k0, k1, g);
@@ -370,16 +385,23 @@ int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *ind
   const size_t table_bytes = size_t(std::max<int64_t>(dim, 0)) * size_t(n_bits) * entry_bytes;
   const bool use_table = dim > 0 && nnz > 2 * dim && table_bytes <= kSrpTableMaxBytes;
   void *table = nullptr;
+  uint8_t *used = nullptr;   // one byte per term after the table
   if (use_table) {
-    if (int rc = ensure_workspace(ctx, table_bytes)) return rc;
+    if (int rc = ensure_workspace(ctx, table_bytes + size_t(dim))) return rc;
     table = ctx->ws;
+    used = static_cast<uint8_t *>(ctx->ws) + table_bytes;
   }
   LaunchScope ls(ctx, s, "srp_sparse");
   if (use_table) {
+    // draw the entries of the terms that occur
+    const unsigned gz = unsigned(std::min<int64_t>((dim + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_fill_u8, dim3(gz), dim3(256), 0, s, used, dim);
+    const unsigned gm = unsigned(std::min<int64_t>((nnz + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_srp_mark, dim3(gm), dim3(256), 0, s, indices, nnz, dim, used);
     const int64_t items = dim * (n_bits / 4);
     const dim3 g(unsigned((items + 255) / 256));
-    if (q16) hipLaunchKernelGGL(k_srp_table<true>, g, dim3(256), 0, s, dim, n_bits, k0, k1, table);
-    else hipLaunchKernelGGL(k_srp_table<false>, g, dim3(256), 0, s, dim, n_bits, k0, k1, table);
+    if (q16) hipLaunchKernelGGL(k_srp_table<true>, g, dim3(256), 0, s, dim, n_bits, k0, k1, used, table);
+    else hipLaunchKernelGGL(k_srp_table<false>, g, dim3(256), 0, s, dim, n_bits, k0, k1, used, table);
   }
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, offsets, indices, values, n_rows, n_bits, n_slices, k0, k1,
