@@ -215,6 +215,10 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
  *   batch_mh_tile: the same for Jaccard lists: 64 or 128 (1 or 2 per lane).
  *           Both shapes are otherwise chosen by the autotuner (when the call
  *           autotunes k) or default to 256 and 64.
+ *   tiles_accept_bitmask: 1 = the BLSH_TILES kernel tests acceptance with
+ *           the per-level accept bitmask even when every level's accept set
+ *           is an interval [min accept, n] (which it then tests with two
+ *           bounds); the same output, for checking the bitmask path.
  *   batch_spill_cap: entries of each measure's survivor queue, split evenly
  *           into one region per wave of the tile kernel; a survivor that finds
  *           its wave's region full keeps running in registers (same result).
@@ -242,6 +246,7 @@ typedef struct {
   int32_t batch_mh_tile;     /* 0, 64 or 128 */
   int32_t last_batch_srp_tile;
   int32_t last_batch_mh_tile;
+  int32_t tiles_accept_bitmask;   /* 0 or 1 */
 } blsh_tuning;
 int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *tuning_host);
 int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *tuning_host);

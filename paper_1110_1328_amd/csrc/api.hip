@@ -510,8 +510,10 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   a.t = t;
   if (n_cand == 0 || (cand->kind == BLSH_TILES && cand->n_tiles == 0))
     return launch_zero(ctx, res->n_accepted, s) ? fail(BLSH_EDEVICE, "launch failed") : BLSH_OK;
-  if (cand->kind == BLSH_TILES)
-    return run_tiles(ctx, cand, a, k, n_max, n_levels, (na_host->image[kTabFlagOff] & 1u) != 0, s);
+  if (cand->kind == BLSH_TILES) {
+    const bool intervals = (na_host->image[kTabFlagOff] & 1u) != 0 && !ctx->tuning.tiles_accept_bitmask;
+    return run_tiles(ctx, cand, a, k, n_max, n_levels, intervals, s);
+  }
   // SRP Algorithm 1 with a prefix view: candidates undecided after the first
   // 128 hashes are queued and finished by a second kernel with every lane busy
   const bool tail = !exh && !lite && sigs->measure == BLSH_COSINE && a.pfx != nullptr && 128 / k < n_levels;
@@ -699,6 +701,8 @@ int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
     return fail(BLSH_EINVAL, "tuning.batch_srp_tile must be 0, 128, 256 or 512");
   if (t->batch_mh_tile != 0 && t->batch_mh_tile != 64 && t->batch_mh_tile != 128)
     return fail(BLSH_EINVAL, "tuning.batch_mh_tile must be 0, 64 or 128");
+  if (t->tiles_accept_bitmask < 0 || t->tiles_accept_bitmask > 1)
+    return fail(BLSH_EINVAL, "tuning.tiles_accept_bitmask must be 0 or 1");
   ctx->tuning.gather = t->gather;
   ctx->tuning.acc_stage_cap = t->acc_stage_cap;
   ctx->tuning.batch_spill_cap = t->batch_spill_cap;
@@ -706,6 +710,7 @@ int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
   ctx->tuning.batch_blocks_per_cu = t->batch_blocks_per_cu;
   ctx->tuning.batch_srp_tile = t->batch_srp_tile;
   ctx->tuning.batch_mh_tile = t->batch_mh_tile;
+  ctx->tuning.tiles_accept_bitmask = t->tiles_accept_bitmask;
   return BLSH_OK;
 }
 

@@ -96,8 +96,9 @@ def test_tiles_verify_matches_oracle(ctx, mix, banded, k, n_max, t):
     """Algorithm 1 over the tiles of a banding of the mixture (16 bands x 6
     bits, buckets of a few to a few hundred members, keep masks with holes),
     on an independent n_max-bit projection, every group width of the row
-    kernel (n_max / 128 = 1 .. 16 lanes) and every k: the oracle's output on
-    the oracle's banding pairs, and the PAIRS path's output."""
+    kernel (n_max / 128 = 1 .. 16 lanes), every k and both acceptance tests
+    (interval bounds, accept bitmask): the oracle's output on the oracle's
+    banding pairs, and the PAIRS path's output."""
     print("tiles verify k=%d n_max=%d t=%.1f" % (k, n_max, t), flush=True)
     band, (wx, wy) = banded
     sig = _bits(mix, n_max, G.SEED_BASE + 64 + n_max)
@@ -108,11 +109,17 @@ def test_tiles_verify_matches_oracle(ctx, mix, banded, k, n_max, t):
     # every pair concentrates first (2048 hashes; t = 0.9)
     assert {0, 1} <= set(want["decision"].tolist())
     S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
-    res = P.make_result(npairs, npairs, m_debug=True)
-    P.bayeslsh_verify(ctx, P.tiles(tl, nt, npairs), S, t, EPS, DELTA, GAMMA, (1, 1), k, res)
-    P.bayeslsh_sync(ctx)
-    got = decode_result(res, npairs)
-    assert_same_as_oracle(got, want)
+    # acceptance tested with the two bounds of each level's accept interval,
+    # then with the accept bitmask (the path for tables whose accept sets are
+    # not intervals): the same output
+    for bitmask in (1, 0):
+        P.bayeslsh_set_tuning(ctx, tiles_accept_bitmask=bitmask)
+        res = P.make_result(npairs, npairs, m_debug=True)
+        P.bayeslsh_verify(ctx, P.tiles(tl, nt, npairs), S, t, EPS, DELTA, GAMMA, (1, 1), k, res)
+        P.bayeslsh_sync(ctx)
+        got = decode_result(res, npairs)
+        assert_same_as_oracle(got, want)
+    P.bayeslsh_set_tuning(ctx)
     res_p = P.make_result(npairs, npairs, m_debug=True)
     P.bayeslsh_verify(ctx, P.pairs(up(wx), up(wy)), S, t, EPS, DELTA, GAMMA, (1, 1), k, res_p)
     P.bayeslsh_sync(ctx)
