@@ -179,6 +179,22 @@ typedef struct blsh_ctx blsh_ctx;
 int bayeslsh_create(blsh_ctx **out, int device);
 void bayeslsh_destroy(blsh_ctx *ctx);
 
+/* Caller control of the context workspace (the device memory that
+ * verification, Lite, the comparator, banding and the sparse SRP plane table
+ * use beyond the caller's inputs and outputs).  bayeslsh_reserve_workspace
+ * makes it at least `bytes` now (allocating synchronises the device once).
+ * With fixed != 0 later calls never grow it: a call that needs more returns
+ * BLSH_ENOMEM before launching any kernel or writing any output (a table
+ * image may already have been uploaded to the cache), and the sparse SRP draws its plane
+ * entries per nonzero instead of building a table that does not fit (the
+ * same signatures).  fixed = 0 restores growth on demand.  A caller that
+ * wants no allocation after setup runs its largest call once, reads the size
+ * with bayeslsh_workspace_bytes and reserves it fixed.  The batched state,
+ * the banding tile buffer and the posterior-table images are allocated
+ * apart from the workspace (the first call of each kind). */
+int bayeslsh_reserve_workspace(blsh_ctx *ctx, size_t bytes, int32_t fixed);
+int bayeslsh_workspace_bytes(blsh_ctx *ctx, size_t *bytes_host);
+
 /* Wait for `stream`, then return (and clear) the first error a kernel of this
  * context raised since the last sync: BLSH_ETRUNCATED, BLSH_EBADID, BLSH_EINVAL
  * (empty set in bayeslsh_minhash_sigs), or BLSH_OK. */

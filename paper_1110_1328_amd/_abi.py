@@ -88,6 +88,8 @@ class RequestResult(C.Structure):
 PROTOTYPES = [
     ("bayeslsh_create", C.c_int, [C.POINTER(p), C.c_int]),
     ("bayeslsh_destroy", None, [p]),
+    ("bayeslsh_reserve_workspace", C.c_int, [p, C.c_size_t, C.c_int32]),
+    ("bayeslsh_workspace_bytes", C.c_int, [p, C.POINTER(C.c_size_t)]),
     ("bayeslsh_sync", C.c_int, [p, p]),
     ("bayeslsh_last_error", C.c_char_p, []),
     ("bayeslsh_version", C.c_int, []),

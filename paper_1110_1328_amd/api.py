@@ -318,6 +318,16 @@ def bayeslsh_get_tuning(ctx: Context) -> dict:
     return {name: getattr(t, name) for name, _ in A.Tuning._fields_}
 
 
+def bayeslsh_reserve_workspace(ctx: Context, n_bytes: int, fixed: bool = False):
+    _check(_lib().bayeslsh_reserve_workspace(ctx.handle, int(n_bytes), int(bool(fixed))))
+
+
+def bayeslsh_workspace_bytes(ctx: Context) -> int:
+    n = C.c_size_t()
+    _check(_lib().bayeslsh_workspace_bytes(ctx.handle, C.byref(n)))
+    return n.value
+
+
 LIST_DTYPE = None
 
 

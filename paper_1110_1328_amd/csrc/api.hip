@@ -119,6 +119,9 @@ int get_table(blsh_ctx *ctx, const TableKey &key, std::shared_ptr<HostTable> *ho
 
 int ensure_workspace(blsh_ctx *ctx, size_t bytes) {
   if (ctx->ws_bytes >= bytes) return BLSH_OK;
+  if (ctx->ws_fixed)
+    return fail(BLSH_ENOMEM, "the call needs %zu bytes of workspace; the context's is fixed at %zu", bytes,
+                ctx->ws_bytes);
   BLSH_HIP(hipDeviceSynchronize());
   if (ctx->ws) hipFree(ctx->ws);
   ctx->ws = nullptr;
@@ -616,6 +619,20 @@ int bayeslsh_create(blsh_ctx **out, int device) {
     return fail(BLSH_EDEVICE, "counter init failed");
   }
   *out = c;
+  return BLSH_OK;
+}
+
+int bayeslsh_reserve_workspace(blsh_ctx *ctx, size_t bytes, int32_t fixed) {
+  if (!ctx) return fail(BLSH_EINVAL, "null context");
+  ctx->ws_fixed = false;
+  if (int rc = ensure_workspace(ctx, bytes)) return rc;
+  ctx->ws_fixed = fixed != 0;
+  return BLSH_OK;
+}
+
+int bayeslsh_workspace_bytes(blsh_ctx *ctx, size_t *bytes_host) {
+  if (!ctx || !bytes_host) return fail(BLSH_EINVAL, "null argument");
+  *bytes_host = ctx->ws_bytes;
   return BLSH_OK;
 }
 

@@ -104,6 +104,7 @@ struct blsh_ctx {
   // survivor workspace
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  bool ws_fixed = false;   // set by bayeslsh_reserve_workspace: calls never grow ws
   // banding: per-tile counts and offsets of the tiled emission order
   void *tile_buf = nullptr;
   size_t tile_bytes = 0;

@@ -383,7 +383,10 @@ int launch_srp_sparse(blsh_ctx *ctx, const int64_t *offsets, const uint32_t *ind
   BLSH_HIP(hipStreamSynchronize(s));
   const size_t entry_bytes = q16 ? sizeof(uint16_t) : sizeof(float);
   const size_t table_bytes = size_t(std::max<int64_t>(dim, 0)) * size_t(n_bits) * entry_bytes;
-  const bool use_table = dim > 0 && nnz > 2 * dim && table_bytes <= kSrpTableMaxBytes;
+  // (a context whose workspace is fixed too small for the table draws the
+  // entries per nonzero instead: the same values)
+  const bool use_table = dim > 0 && nnz > 2 * dim && table_bytes <= kSrpTableMaxBytes &&
+                         (!ctx->ws_fixed || table_bytes + size_t(dim) <= ctx->ws_bytes);
   void *table = nullptr;
   uint8_t *used = nullptr;   // one byte per term after the table
   if (use_table) {

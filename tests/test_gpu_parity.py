@@ -852,3 +852,73 @@ def test_learned_prior_pipeline(ctx):
     S = P.Signatures(out, P.JACCARD, P.OBJECT_MAJOR, sets.n, 256)
     res = run_verify(ctx, P.all_pairs(sets.n), S, prior=(alpha, beta))
     assert_same_as_oracle(decode_result(res, len(want["decision"])), want)
+
+
+def test_fixed_workspace(ctx):
+    """A context workspace reserved and fixed: calls that fit run without
+    growing it (and give the output of a growing context); a call that needs
+    more returns BLSH_ENOMEM before enqueuing anything (its outputs untouched);
+    the sparse SRP with a workspace too small for its plane table draws the
+    entries per nonzero, giving the table path's bits."""
+    _flush("fixed workspace")
+    c2 = P.bayeslsh_create(0)
+    try:
+        rng = np.random.default_rng(41)
+        sig = G.pack_bits(G.calibration_bits(2000, 512, rng.uniform(0.5, 1.0, 2000), 42))
+        S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
+        n = 300_000
+        x = rng.integers(0, 4000, n).astype(np.uint32)
+        y = (x ^ 1).astype(np.uint32)
+        y[::3] = rng.integers(0, 4000, len(y[::3]))
+        cand = P.pairs(up(x), up(y))
+        ref = P.make_result(n, n, m_debug=True)
+        P.bayeslsh_verify(ctx, cand, S, 0.7, 0.03, 0.05, 0.03, (1, 1), 32, ref)
+        P.bayeslsh_sync(ctx)
+        want = decode_result(ref, n)
+        # warm up, read the size, freeze it: the same call runs again without growing
+        res = P.make_result(n, n, m_debug=True)
+        P.bayeslsh_verify(c2, cand, S, 0.7, 0.03, 0.05, 0.03, (1, 1), 32, res)
+        P.bayeslsh_sync(c2)
+        size = P.bayeslsh_workspace_bytes(c2)
+        assert size > 0
+        P.bayeslsh_reserve_workspace(c2, size, fixed=True)
+        res = P.make_result(n, n, m_debug=True)
+        P.bayeslsh_verify(c2, cand, S, 0.7, 0.03, 0.05, 0.03, (1, 1), 32, res)
+        P.bayeslsh_sync(c2)
+        assert P.bayeslsh_workspace_bytes(c2) == size
+        got = decode_result(res, n)
+        np.testing.assert_array_equal(got["code"], want["code"])
+        np.testing.assert_array_equal(got["acc_idx"], want["acc_idx"])
+        np.testing.assert_array_equal(got["acc_val"], want["acc_val"])
+        # a call that needs more than the fixed size: refused, nothing written
+        big = 40 * n
+        xb = np.resize(x, big)
+        yb = np.resize(y, big)
+        res_b = P.make_result(big, 16)
+        res_b.code.fill_(0xEE)
+        with pytest.raises(P.BayesLSHError) as e:
+            P.bayeslsh_verify(c2, P.pairs(up(xb), up(yb)), S, 0.7, 0.03, 0.05, 0.03, (1, 1), 32, res_b)
+        assert e.value.code == -2 and "workspace" in str(e.value)
+        P.bayeslsh_sync(c2)
+        assert bool((res_b.code == 0xEE).all())
+        assert P.bayeslsh_workspace_bytes(c2) == size
+        # the sparse SRP: table path (growing context) vs per-nonzero (fixed, too small)
+        corpus = G.tfidf_corpus(n_docs=1500, dim=1 << 12, mean_nnz=40, seed=G.SEED_BASE + 27)
+        assert len(corpus.indices) > 2 * corpus.dim
+        W = 2048 // 32
+        outs = []
+        for cc in (ctx, c2):
+            out = torch.empty(corpus.n * W, dtype=torch.int32, device="cuda").view(torch.uint32)
+            P.bayeslsh_srp_sigs(cc, csr_device(corpus), None, 2048, 0x77, P.OBJECT_MAJOR, out)
+            P.bayeslsh_sync(cc)
+            outs.append(down(out))
+        np.testing.assert_array_equal(outs[0], outs[1])
+        assert P.bayeslsh_workspace_bytes(c2) == size
+        # unfixed: grows again
+        P.bayeslsh_reserve_workspace(c2, 0, fixed=False)
+        P.bayeslsh_verify(c2, P.pairs(up(xb), up(yb)), S, 0.7, 0.03, 0.05, 0.03, (1, 1), 32,
+                          P.make_result(big, big))
+        P.bayeslsh_sync(c2)
+        assert P.bayeslsh_workspace_bytes(c2) > size
+    finally:
+        c2.close()

@@ -93,6 +93,9 @@ def test_calls_without_a_context_fail_cleanly(lib):
     assert b"context" in lib.bayeslsh_last_error()
     assert lib.bayeslsh_sync(None, None) == -1
     assert lib.bayeslsh_minhash_sigs(None, None, None, None, 0, None, None) == -1
+    assert lib.bayeslsh_reserve_workspace(None, 1 << 20, 1) == -1
+    n = C.c_size_t()
+    assert lib.bayeslsh_workspace_bytes(None, C.byref(n)) == -1
     h = C.c_void_p()
     rc = lib.bayeslsh_create(C.byref(h), 0)
     if rc == 0:   # a GPU is visible
