@@ -844,6 +844,17 @@ def run_dense(args, torch, P):
     dom_bytes = per[dom] / launches
     achieved = dom_bytes / (prof[dom]["avg_ms"] * 1e-3) / 1e9
     traffic = measured_traffic_of(DENSE_TRAFFIC_FILE, DENSE_KERNEL_SOURCES, "traffic_bytes_per_launch_" + dom)
+
+    def issue_of(kernel_ms):
+        """VALU issue utilisation: the kernel's VALU instructions per launch (SQ
+        counters, committed with the traffic) over what 256 CUs issue at one
+        wave instruction per cycle at 2.4 GHz in the launch's live duration."""
+        valu = measured_traffic_of(DENSE_TRAFFIC_FILE, DENSE_KERNEL_SOURCES, "valu_insts_per_launch_" + dom)
+        if valu is None:
+            return None
+        cap = 256 * 2.4e9 * kernel_ms * 1e-3
+        return {"valu_insts_per_launch": valu, "valu_issue_capacity_per_launch": cap, "valu_busy_frac": valu / cap,
+                "valu_insts_per_tile": valu / (n_tiles / launches), "source": "SQ_INSTS_VALU, " + os.path.relpath(DENSE_TRAFFIC_FILE, ROOT)}
     roofline = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,
@@ -858,10 +869,11 @@ def run_dense(args, torch, P):
         "bytes_model": "per candidate 1 B code + 8 B per level reached (4 B chunk per side at k = 32) + 12 B per "
                        "emitted pair, plus the 192 B descriptor (member ids included) per tile; the tile kernel "
                        "does all of it, the flush copies the staged accepted pairs to the caller's list",
+        "issue": issue_of(prof[dom]["avg_ms"]),
         "note": "frac counts each candidate's level chunks as if read for it alone; the tile kernel reads a "
                 "tile's 32 rows once into LDS for its 256 positions, so the counted HBM traffic (traffic, "
                 "traffic_frac) is a fraction of the algorithmic bytes and the kernel is bound by instruction "
-                "issue rather than by HBM",
+                "issue rather than by HBM (issue.valu_busy_frac)",
     }
     ctx.close()
     return {
