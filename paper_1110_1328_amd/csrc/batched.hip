@@ -1225,7 +1225,7 @@ int verify_batched(blsh_ctx *ctx, const blsh_list_desc *lists, int64_t n_lists, 
     // work), then each used measure's tile shape at its k, then in-register
     // levels x blocks per CU at the chosen shapes
     std::vector<int64_t> key{n_lists, n_cand >> 16, int64_t(need[0]), int64_t(need[1]), n_max[0], n_max[1],
-                             int64_t(ts.size()), kj, kc};
+                             int64_t(ts.size()), kj, kc, fixed_tile[0], fixed_tile[1]};
     auto it = b->tuned.find(key);
     if (it != b->tuned.end()) {
       ch = it->second;
