@@ -380,11 +380,11 @@ static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
 
 // Shared driver of verify / lite / exhaustive.
 // Algorithm 1 over BLSH_TILES candidates: launches of at most kTilesChunk
-// tiles (their candidates, at most 256 each, stay below 2^32 relative to the
-// launch's first), each [k_verify_tiles, k_tiles_scan, k_tiles_copy].  The
-// tile kernel runs on a persistent grid, each wave with a staging region of
-// its own (no atomics; kTilesStage entries in all); the running accepted count
-// sits in the context's counter buffer.
+// tiles, each [k_verify_tiles, k_tiles_scan, k_tiles_copy].  The tile kernel
+// runs on a persistent grid, each wave with a staging region of its own (no
+// atomics; kTilesStage entries in all, each the candidate's absolute index and
+// its raw (m, n), so tiles may come in any order of their numbering); the
+// running accepted count sits in the context's counter buffer.
 static constexpr int64_t kTilesChunk = int64_t(1) << 20;
 static constexpr int64_t kTilesStage = int64_t(1) << 25;
 
@@ -396,15 +396,15 @@ static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, i
   if (rc) return rc;
   const int64_t stage = ctx->tuning.acc_stage_cap > 0 ? int64_t(ctx->tuning.acc_stage_cap) : kTilesStage;
   const int64_t st_cap = std::max<int64_t>(1, stage / waves);   // entries per wave region
-  const size_t st_bytes = align256(size_t(waves) * st_cap * 4);
+  const size_t idx_bytes = align256(size_t(waves) * st_cap * 8), val_bytes = align256(size_t(waves) * st_cap * 4);
   const size_t cnt_bytes = align256(size_t(waves) * 4), off_bytes = align256(size_t(waves) * 8);
-  if ((rc = ensure_workspace(ctx, 2 * st_bytes + cnt_bytes + off_bytes))) return rc;
+  if ((rc = ensure_workspace(ctx, idx_bytes + val_bytes + cnt_bytes + off_bytes))) return rc;
   char *p = static_cast<char *>(ctx->ws);
-  a.st_rel = reinterpret_cast<uint32_t *>(p);
-  a.st_val = reinterpret_cast<float *>(p + st_bytes);
+  a.st_idx = reinterpret_cast<uint64_t *>(p);
+  a.st_val = reinterpret_cast<float *>(p + idx_bytes);
   a.st_cap = st_cap;
-  a.wst_cnt = reinterpret_cast<uint32_t *>(p + 2 * st_bytes);
-  int64_t *off = reinterpret_cast<int64_t *>(p + 2 * st_bytes + cnt_bytes);
+  a.wst_cnt = reinterpret_cast<uint32_t *>(p + idx_bytes + val_bytes);
+  int64_t *off = reinterpret_cast<int64_t *>(p + idx_bytes + val_bytes + cnt_bytes);
   a.tiles = cand->tiles;
   a.n_cand = cand->n_cand;
   a.c_begin = 0;
@@ -417,7 +417,6 @@ static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, i
   for (int64_t t0 = 0; t0 < cand->n_tiles; t0 += kTilesChunk) {
     a.t_begin = t0;
     a.t_end = std::min(cand->n_tiles, t0 + kTilesChunk);
-    a.c_begin_dev = &cand->tiles[t0].first;
     rc = launch_verify_tiles(ctx, a, k, n_max, words, intervals, waves, s);
     if (!rc) rc = launch_tiles_flush(ctx, a, waves, off, a.t_end == cand->n_tiles, s);
     if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;

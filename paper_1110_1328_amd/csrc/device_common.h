@@ -70,23 +70,20 @@ struct VerifyArgs {
   int32_t mode;                          // 0 replay, 1 replay-lite, 2 mle
   int32_t count_levels;                  // levels compared in full (n_max/k)
   double t;
-  // BLSH_TILES: the launch runs tiles [t_begin, t_end); its candidates start at
-  // *c_begin_dev (tiles[t_begin].first, read on the device; staging indices
-  // are relative to it); n_cand bounds every candidate index written
+  // BLSH_TILES: the launch runs tiles [t_begin, t_end) (in any order of their
+  // numbering); n_cand bounds every candidate index written
   const blsh_tile *tiles;
   int64_t t_begin, t_end;
-  const int64_t *c_begin_dev;
   int64_t n_cand;
   // staging values are raw (m | n << 16, as the float's bits): the flush
   // computes S_hat from them (tiles path)
   int32_t st_raw;
   // tiles path: the staging holds one region of st_cap entries per wave of the
-  // persistent grid, filled in order; wave w leaves its count in wst_cnt[w]
+  // persistent grid, filled in order -- the candidate index (absolute, 8 B)
+  // in st_idx and the raw value in st_val; wave w leaves its count in wst_cnt[w]
+  uint64_t *st_idx;
   uint32_t *wst_cnt;
 };
-
-// First candidate of the launch: a host value, or for tiles a device value.
-__device__ inline int64_t launch_c_begin(const VerifyArgs &a) { return a.c_begin_dev ? *a.c_begin_dev : a.c_begin; }
 
 __device__ inline int lane_id() { return __lane_id(); }
 

@@ -709,15 +709,14 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
   __syncthreads();
   const bool last_lane = q == P2 - 1;         // holds level L - 1 as its level LPL - 1
   const uint32_t min0 = a.table[kTabMinOff];
-  const int64_t cb = *a.c_begin_dev;
   const int64_t gw = xcd_tile(blockIdx.x, gridDim.x) * (kBlock / kWave) +
                      __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
   const int64_t n_waves = int64_t(gridDim.x) * (kBlock / kWave);
   const uint32_t *tdw = reinterpret_cast<const uint32_t *>(a.tiles);
   const int r = lane >> 2, cc = 16 + 4 * (lane & 3);   // level 0: row r, staged rows cc .. cc+3
-  // this wave's staging region: accepted pairs (candidate - launch start, raw
+  // this wave's staging region: accepted pairs (candidate index, raw
   // m | n << 16) in order; past its end, the caller's list directly
-  uint32_t *w_rel = a.st_rel + size_t(gw) * a.st_cap;
+  uint64_t *w_idx = a.st_idx + size_t(gw) * a.st_cap;
   float *w_val = a.st_val + size_t(gw) * a.st_cap;
   int64_t w_cnt = 0;   // wave-uniform
   // the descriptor, one dword per lane, loaded one tile ahead
@@ -887,7 +886,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
       const int64_t pos = w_cnt + int64_t(lanes_below(em));
       const bool over = emit && pos >= a.st_cap;
       if (emit && !over) {
-        w_rel[pos] = uint32_t(first + rk - cb);
+        w_idx[pos] = uint64_t(first + rk);
         w_val[pos] = __uint_as_float(uint32_t(m) | (uint32_t((j + 1) * K) << 16));
       }
       if (__ballot(over)) {   // the region is full: S_hat here, into the caller's list
@@ -947,16 +946,15 @@ __global__ __launch_bounds__(1024) void k_tiles_scan(const uint32_t *cnt, int64_
 __global__ __launch_bounds__(kBlock) void k_tiles_copy(VerifyArgs a, const int64_t *off) {
   const int64_t w = blockIdx.x;
   const int64_t n = a.wst_cnt[w], base = off[w];
-  const int64_t cb = *a.c_begin_dev;
   const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
-  const uint32_t *rel = a.st_rel + size_t(w) * a.st_cap;
+  const uint64_t *idx = a.st_idx + size_t(w) * a.st_cap;
   const float *val = a.st_val + size_t(w) * a.st_cap;
   bool trunc = false;
   for (int64_t i = threadIdx.x; i < n; i += kBlock) {
     const int64_t pos = base + i;
     if (pos < a.acc_cap) {
       const uint32_t u = __float_as_uint(val[i]);
-      a.acc_idx[pos] = uint64_t(cb) + rel[i];
+      a.acc_idx[pos] = idx[i];
       a.acc_val[pos] = map_estimate(a.measure, int(u & 0xFFFFu), int(u >> 16), alpha, beta);
     } else {
       trunc = true;
@@ -1198,7 +1196,7 @@ __global__ __launch_bounds__(kBlock) void k_acc_flush(VerifyArgs a, int64_t *nxt
   const int64_t base = s_base + s_cnt[sl];
   const uint32_t *rel = a.st_rel + size_t(sl) * a.st_cap;
   const float *val = a.st_val + size_t(sl) * a.st_cap;
-  const int64_t cb = launch_c_begin(a);
+  const int64_t cb = a.c_begin;
   const double alpha = tab_f64(a.table, 4), beta = tab_f64(a.table, 6);
   const int64_t per = (n + kFlushParts - 1) / kFlushParts;
   const int64_t i1 = min(n, (part + 1) * per);

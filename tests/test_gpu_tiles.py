@@ -194,11 +194,13 @@ def test_tiles_by_hand_and_malformed(ctx):
     assert int(r.n_accepted.item()) == 0
 
 
-def test_tiles_numbered_past_two_to_the_31_and_32(ctx):
+@pytest.mark.parametrize("order", ["ascending", "descending", "shuffled"])
+def test_tiles_numbered_past_two_to_the_31_and_32(ctx, order):
     """Tiles whose candidates are numbered beyond 2^31 and 2^32 (a result of
-    4.3e9 candidates, most of them outside these tiles): codes, m and accepted
-    indices land at those numbers, equal to the oracle's output for the same
-    pairs."""
+    4.3e9 candidates, most of them outside these tiles), handed over in
+    ascending, descending or shuffled order of their numbering (one launch
+    holds them all): codes, m and accepted indices land at those numbers,
+    equal to the oracle's output for the same pairs."""
     rng = np.random.default_rng(9)
     n_obj, n_max, k = 600, 512, 32
     sig = G.pack_bits(G.calibration_bits(n_obj // 2, n_max, rng.uniform(0.6, 1.0, n_obj // 2), 91))
@@ -219,10 +221,15 @@ def test_tiles_numbered_past_two_to_the_31_and_32(ctx):
             idx += list(range(first, first + 256))
     x, y, idx = np.array(xs, np.uint32), np.array(ys, np.uint32), np.array(idx, np.int64)
     want = R.verify(x, y, P.COSINE, sig, k, n_max // k, 0.7, EPS, DELTA, GAMMA)
+    tiles = np.stack(tiles)
+    if order == "descending":
+        tiles = tiles[::-1]
+    elif order == "shuffled":
+        tiles = tiles[np.random.default_rng(10).permutation(len(tiles))]
     res = P.make_result(n_cand, 1 << 16, m_debug=True)
     res.code.fill_(0xEE)
-    P.bayeslsh_verify(ctx, P.tiles(up(np.stack(tiles).reshape(-1)), len(tiles), n_cand), S, 0.7, EPS, DELTA, GAMMA,
-                      (1, 1), k, res)
+    P.bayeslsh_verify(ctx, P.tiles(up(np.ascontiguousarray(tiles).reshape(-1)), len(tiles), n_cand), S, 0.7, EPS,
+                      DELTA, GAMMA, (1, 1), k, res)
     P.bayeslsh_sync(ctx)
     idx_d = torch.from_numpy(idx).cuda()
     code = res.code[idx_d].cpu().numpy()
