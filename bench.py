@@ -145,7 +145,8 @@ def cpu_baseline(corpus, x, y, gpu_codes, gpu_m, gpu_acc):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "verify_bits_prefix_cosine_lite_100k_traffic.txt")
-KERNEL_SOURCES = ("paper_1110_1328_amd/csrc/verify.hip", "paper_1110_1328_amd/csrc/device_common.h")
+KERNEL_SOURCES = ("paper_1110_1328_amd/csrc/verify.hip", "paper_1110_1328_amd/csrc/device_common.h",
+                  "paper_1110_1328_amd/csrc/api.hip")
 
 
 def measured_traffic():
@@ -590,7 +591,10 @@ def run_sigs(args, torch, P):
 
 
 DENSE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "verify_tiles_dense_1m_traffic.txt")
-DENSE_KERNEL_SOURCES = ("paper_1110_1328_amd/csrc/verify.hip", "paper_1110_1328_amd/csrc/device_common.h")
+# the kernels' sources and the host code that cuts a call into launches (the
+# counters are per launch)
+DENSE_KERNEL_SOURCES = ("paper_1110_1328_amd/csrc/verify.hip", "paper_1110_1328_amd/csrc/device_common.h",
+                        "paper_1110_1328_amd/csrc/api.hip")
 # the verification call's kernels, by the names their launches are profiled under
 TILE_KERNELS = ("verify_tiles", "tiles_flush")
 PAIR_KERNELS = ("verify_bits_prefix", "verify_tail", "acc_flush")

@@ -385,8 +385,8 @@ static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
 // atomics; kTilesStage entries in all, each the candidate's absolute index and
 // its raw (m, n), so tiles may come in any order of their numbering); the
 // running accepted count sits in the context's counter buffer.
-static constexpr int64_t kTilesChunk = int64_t(1) << 20;
-static constexpr int64_t kTilesStage = int64_t(1) << 25;
+static constexpr int64_t kTilesChunk = int64_t(1) << 22;
+static constexpr int64_t kTilesStage = int64_t(1) << 27;
 
 static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, int k, int n_max, int n_levels,
                      bool intervals, hipStream_t s) {
@@ -394,7 +394,10 @@ static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, i
   int64_t waves = 0;
   int rc = tiles_grid_waves(ctx, k, n_max, intervals, size_t(n_levels) * words * 4, &waves);
   if (rc) return rc;
-  const int64_t stage = ctx->tuning.acc_stage_cap > 0 ? int64_t(ctx->tuning.acc_stage_cap) : kTilesStage;
+  // (no more entries than the call has candidates; a wave whose region fills
+  // emits directly)
+  const int64_t stage = ctx->tuning.acc_stage_cap > 0 ? int64_t(ctx->tuning.acc_stage_cap)
+                                                      : std::min<int64_t>(kTilesStage, cand->n_cand);
   const int64_t st_cap = std::max<int64_t>(1, stage / waves);   // entries per wave region
   const size_t idx_bytes = align256(size_t(waves) * st_cap * 8), val_bytes = align256(size_t(waves) * st_cap * 4);
   const size_t cnt_bytes = align256(size_t(waves) * 4), off_bytes = align256(size_t(waves) * 8);
