@@ -349,8 +349,10 @@ int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *plan
  * k in {16, 32, 64}; n_max % k == 0; n_max/k <= 64.  SRP signatures may be
  * OBJECT_MAJOR or WORD_MAJOR (WORD_MAJOR is the fast layout); minhash
  * signatures must be OBJECT_MAJOR with n_hashes % 4 == 0.
- * BLSH_TILES candidates (SRP only): OBJECT_MAJOR rows, 16-byte aligned, of a
- * multiple of 128 hashes, n_max a multiple of 128 up to 2048.  A wave takes a
+ * BLSH_TILES candidates (SRP, this entry point only: Lite, the comparators and
+ * the allocation-free entry point refuse them with BLSH_EINVAL): OBJECT_MAJOR
+ * rows, 16-byte aligned, of a multiple of 128 hashes, n_max a multiple of 128
+ * up to 2048; tiles may come in any order of their numbering.  A wave takes a
  * tile: it stages the first n_max hashes of its 32 members in LDS (one load
  * per 128-byte line), decides level 0 for the tile's pairs and finishes the
  * pairs level 0 does not prune from those rows.  Malformed tiles are reported
@@ -376,6 +378,8 @@ int bayeslsh_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs 
  * any context or stream -- share the array and race: the caller serialises
  * them.  A parameter set seen for the first time has its table built on the
  * host (host memory only) and its image copied into the array on `stream`.
+ * Candidate kinds: PAIRS, QUERY_LISTS and ALL_PAIRS; BLSH_TILES is refused
+ * (BLSH_EINVAL: its per-wave staging is sized by the call).
  * Errors: as bayeslsh_verify; BLSH_EINVAL for a context on a device numbered
  * 64 or above (no scratch array is kept there). */
 int bayeslsh_verify_noalloc(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sigs *sigs, double t,
