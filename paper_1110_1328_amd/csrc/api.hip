@@ -24,9 +24,10 @@ int launch_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t max_items, hipStrea
 int launch_exact_pairs(blsh_ctx *ctx, const VerifyArgs &a, double *out, hipStream_t s);
 int launch_verify_tail(blsh_ctx *ctx, const VerifyArgs &a, int k, bool word_major, int words, hipStream_t s);
 int launch_zero_slices(blsh_ctx *ctx, int64_t *cnt, hipStream_t s);
-int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals,
+int launch_tiles_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t grid_waves, hipStream_t s);
+int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals, bool lite,
                         int64_t grid_waves, hipStream_t s);
-int tiles_grid_waves(blsh_ctx *ctx, int k, int n_max, bool intervals, size_t lds, int64_t *waves);
+int tiles_grid_waves(blsh_ctx *ctx, int k, int n_max, bool intervals, bool lite, size_t lds, int64_t *waves);
 int launch_tiles_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t grid_waves, int64_t *off, bool last,
                        hipStream_t s);
 int launch_acc_flush(blsh_ctx *ctx, const VerifyArgs &a, int64_t *nxt_cnt, int64_t *nxt_total, bool last,
@@ -387,40 +388,51 @@ static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
 // running accepted count sits in the context's counter buffer.
 static constexpr int64_t kTilesChunk = int64_t(1) << 22;
 static constexpr int64_t kTilesStage = int64_t(1) << 27;
+static constexpr int64_t kTilesStageLite = int64_t(1) << 24;   // 20 B per entry
 
 static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, int k, int n_max, int n_levels,
-                     bool intervals, hipStream_t s) {
+                     bool intervals, bool lite, hipStream_t s) {
   const int words = (n_levels * k + 1 + 31) / 32;
   int64_t waves = 0;
-  int rc = tiles_grid_waves(ctx, k, n_max, intervals, size_t(n_levels) * words * 4, &waves);
+  int rc = tiles_grid_waves(ctx, k, n_max, intervals, lite, size_t(n_levels) * words * 4, &waves);
   if (rc) return rc;
   // (no more entries than the call has candidates; a wave whose region fills
-  // emits directly)
+  // emits directly.  Lite: every position of every tile a wave takes in a
+  // launch fits its region, so the launch is sized by the staging.)
   const int64_t stage = ctx->tuning.acc_stage_cap > 0 ? int64_t(ctx->tuning.acc_stage_cap)
-                                                      : std::min<int64_t>(kTilesStage, cand->n_cand);
-  const int64_t st_cap = std::max<int64_t>(1, stage / waves);   // entries per wave region
+                                                      : std::min<int64_t>(lite ? kTilesStageLite : kTilesStage,
+                                                                          cand->n_cand);
+  int64_t st_cap = std::max<int64_t>(1, stage / waves);   // entries per wave region
+  int64_t chunk = kTilesChunk;
+  if (lite) {
+    st_cap = std::max<int64_t>(256, st_cap / 256 * 256);
+    chunk = std::min<int64_t>(kTilesChunk, waves * (st_cap / 256));
+  }
   const size_t idx_bytes = align256(size_t(waves) * st_cap * 8), val_bytes = align256(size_t(waves) * st_cap * 4);
+  const size_t xy_bytes = lite ? align256(size_t(waves) * st_cap * 8) : 0;
   const size_t cnt_bytes = align256(size_t(waves) * 4), off_bytes = align256(size_t(waves) * 8);
-  if ((rc = ensure_workspace(ctx, idx_bytes + val_bytes + cnt_bytes + off_bytes))) return rc;
+  if ((rc = ensure_workspace(ctx, idx_bytes + val_bytes + xy_bytes + cnt_bytes + off_bytes))) return rc;
   char *p = static_cast<char *>(ctx->ws);
   a.st_idx = reinterpret_cast<uint64_t *>(p);
   a.st_val = reinterpret_cast<float *>(p + idx_bytes);
+  a.st_xy = lite ? reinterpret_cast<uint2 *>(p + idx_bytes + val_bytes) : nullptr;
   a.st_cap = st_cap;
-  a.wst_cnt = reinterpret_cast<uint32_t *>(p + idx_bytes + val_bytes);
-  int64_t *off = reinterpret_cast<int64_t *>(p + idx_bytes + val_bytes + cnt_bytes);
+  a.wst_cnt = reinterpret_cast<uint32_t *>(p + idx_bytes + val_bytes + xy_bytes);
+  int64_t *off = reinterpret_cast<int64_t *>(p + idx_bytes + val_bytes + xy_bytes + cnt_bytes);
   a.tiles = cand->tiles;
   a.n_cand = cand->n_cand;
   a.c_begin = 0;
   a.pfx = nullptr;
-  a.st_raw = 1;
+  a.st_raw = lite ? 0 : 1;
   // the running accepted count: the context's counter of staging set 0
   a.acc_total = ctx->d_slices + (size_t(3) * kSlices) * kCntStride;
   if ((rc = launch_zero(ctx, a.acc_total, s))) return fail(rc, "launch failed");
   ctx->slices_dirty = true;   // the single-call paths clear their counters before their next use
-  for (int64_t t0 = 0; t0 < cand->n_tiles; t0 += kTilesChunk) {
+  for (int64_t t0 = 0; t0 < cand->n_tiles; t0 += chunk) {
     a.t_begin = t0;
-    a.t_end = std::min(cand->n_tiles, t0 + kTilesChunk);
-    rc = launch_verify_tiles(ctx, a, k, n_max, words, intervals, waves, s);
+    a.t_end = std::min(cand->n_tiles, t0 + chunk);
+    rc = launch_verify_tiles(ctx, a, k, n_max, words, intervals, lite, waves, s);
+    if (!rc && lite) rc = launch_tiles_exact(ctx, a, waves, s);
     if (!rc) rc = launch_tiles_flush(ctx, a, waves, off, a.t_end == cand->n_tiles, s);
     if (rc) return rc == BLSH_EDEVICE ? fail(rc, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : rc;
   }
@@ -451,7 +463,9 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
   }
   const bool exh = exhaustive_mode >= 0;
   if (cand->kind == BLSH_TILES) {
-    if (exh || lite || noalloc) return fail(BLSH_EINVAL, "BLSH_TILES candidates: Algorithm 1 (bayeslsh_verify) only");
+    if (exh || noalloc)
+      return fail(BLSH_EINVAL, "BLSH_TILES candidates: bayeslsh_verify and bayeslsh_lite_verify only");
+    if (lite && (h % 128 || h > 2048)) return fail(BLSH_EINVAL, "BLSH_TILES candidates, Lite: h must be a multiple of 128 <= 2048");
     if (sigs->measure != BLSH_COSINE) return fail(BLSH_EINVAL, "BLSH_TILES candidates: SRP signatures only");
     if (sigs->layout != BLSH_OBJECT_MAJOR || (uintptr_t(sigs->data) & 15) || row_words % 4)
       return fail(BLSH_EINVAL, "BLSH_TILES candidates: object-major rows of a multiple of 128 hashes, 16-byte aligned");
@@ -517,7 +531,9 @@ static int run_verify(blsh_ctx *ctx, const blsh_candidates *cand, const blsh_sig
     return launch_zero(ctx, res->n_accepted, s) ? fail(BLSH_EDEVICE, "launch failed") : BLSH_OK;
   if (cand->kind == BLSH_TILES) {
     const bool intervals = (na_host->image[kTabFlagOff] & 1u) != 0 && !ctx->tuning.tiles_accept_bitmask;
-    return run_tiles(ctx, cand, a, k, n_max, n_levels, intervals, s);
+    if (lite) fill_exact(a, exact);
+    // the rows are staged up to the last level: n_max, or h for Lite
+    return run_tiles(ctx, cand, a, k, lite ? h : n_max, n_levels, intervals || lite, lite, s);
   }
   // SRP Algorithm 1 with a prefix view: candidates undecided after the first
   // 128 hashes are queued and finished by a second kernel with every lane busy

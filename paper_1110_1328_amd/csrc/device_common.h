@@ -83,6 +83,8 @@ struct VerifyArgs {
   // in st_idx and the raw value in st_val; wave w leaves its count in wst_cnt[w]
   uint64_t *st_idx;
   uint32_t *wst_cnt;
+  // tiles path, Lite: the staged pairs' ids (x, y) beside st_idx
+  uint2 *st_xy;
 };
 
 __device__ inline int lane_id() { return __lane_id(); }

@@ -678,7 +678,11 @@ struct TileLds {
   uint8_t code[256 + kWave];    // by rank; 256.. as for list
 };
 
-template <int K, int NW, bool INTERVALS>
+// LITE (Algorithm 2): the table has no accept sets, so a listed pair is
+// pruned at some level or reaches the last one (n = h); those get the Lite
+// code and go to the wave's staging region with their ids, for k_tiles_exact.
+// The host sizes a Lite launch so that no region can fill.
+template <int K, int NW, bool INTERVALS, bool LITE>
 __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
   constexpr int P2 = NW >= 16 ? NW / 8 : 1;   // lanes per listed pair
   constexpr int WPL = NW / P2;                // words per lane (4 or 8)
@@ -874,7 +878,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
       if (Dj > reinterpret_cast<const int *>(s_pd)[j]) dec = BLSH_PRUNED;
       else if (INTERVALS ? Dj <= reinterpret_cast<const int *>(s_ad)[j] : ((s_acc[j * words + (m >> 5)] >> (m & 31)) & 1u))
         dec = BLSH_ACCEPT_CONC;
-      else dec = BLSH_ACCEPT_NMAX;
+      else dec = LITE ? BLSH_LITE_EXACT : BLSH_ACCEPT_NMAX;
       const bool lead = act && q == 0;
       if (lead) {
         S.code[rk] = uint8_t((dec << 6) | j);
@@ -882,16 +886,27 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
       }
       const bool emit = lead && dec != BLSH_PRUNED;
       const uint64_t em = __ballot(emit);
-      // S_hat is computed from (m, n) when the staging is flushed
       const int64_t pos = w_cnt + int64_t(lanes_below(em));
-      const bool over = emit && pos >= a.st_cap;
-      if (emit && !over) {
-        w_idx[pos] = uint64_t(first + rk);
-        w_val[pos] = __uint_as_float(uint32_t(m) | (uint32_t((j + 1) * K) << 16));
-      }
-      if (__ballot(over)) {   // the region is full: S_hat here, into the caller's list
-        const float sv = over ? map_estimate(a.measure, m, (j + 1) * K, tab_f64(a.table, 4), tab_f64(a.table, 6)) : 0.f;
-        emit_direct(a, over, uint64_t(first + rk), sv);
+      if constexpr (LITE) {
+        // the pair's ids for its exact similarity (every lane takes part in the shuffles)
+        const uint32_t ix = uint32_t(__shfl(int(id), p >> 4)), iy = uint32_t(__shfl(int(id), 16 + (p & 15)));
+        if (emit && pos < a.st_cap) {   // (the host sizes the launch so that it always is)
+          w_idx[pos] = uint64_t(first + rk);
+          a.st_xy[size_t(gw) * a.st_cap + pos] = make_uint2(ix, iy);
+        } else if (emit) {
+          raise_status(a.status, BLSH_EINVAL);
+        }
+      } else {
+        // S_hat is computed from (m, n) when the staging is flushed
+        const bool over = emit && pos >= a.st_cap;
+        if (emit && !over) {
+          w_idx[pos] = uint64_t(first + rk);
+          w_val[pos] = __uint_as_float(uint32_t(m) | (uint32_t((j + 1) * K) << 16));
+        }
+        if (__ballot(over)) {   // the region is full: S_hat here, into the caller's list
+          const float sv = over ? map_estimate(a.measure, m, (j + 1) * K, tab_f64(a.table, 4), tab_f64(a.table, 6)) : 0.f;
+          emit_direct(a, over, uint64_t(first + rk), sv);
+        }
       }
       w_cnt += __popcll(em);
     }
@@ -941,8 +956,51 @@ __global__ __launch_bounds__(1024) void k_tiles_scan(const uint32_t *cnt, int64_
   }
 }
 
+// Tiles path, Lite: the exact similarity of every pair a wave of the tile
+// kernel staged (Algorithm 2's final step); those with s > t are compacted to
+// the front of the region with s as their value, and the region's count
+// becomes theirs.  One block per region, its waves taking the pairs in rounds
+// of one pair each: every entry of a round is read before any is written, and
+// a round writes only slots below its own entries, so the compaction never
+// overwrites an entry not yet read.
+__global__ __launch_bounds__(kBlock) void k_tiles_exact(VerifyArgs a) {
+  __shared__ uint32_t s_idx[kBlock / kWave][kExactLds];
+  __shared__ float s_val[kBlock / kWave][kExactLds];
+  __shared__ int s_kept;
+  const int64_t w = blockIdx.x;
+  const int wv = threadIdx.x >> 6;
+  const int64_t n = a.wst_cnt[w];
+  uint64_t *idx = a.st_idx + size_t(w) * a.st_cap;
+  float *val = a.st_val + size_t(w) * a.st_cap;
+  const uint2 *xy = a.st_xy + size_t(w) * a.st_cap;
+  if (threadIdx.x == 0) s_kept = 0;
+  __syncthreads();
+  for (int64_t r0 = 0; r0 < n; r0 += kBlock / kWave) {   // uniform over the block
+    const int64_t e = r0 + wv;
+    const bool has = e < n;
+    uint64_t c = 0;
+    uint2 p = make_uint2(0, 0);
+    if (has) {
+      c = idx[e];
+      p = xy[e];
+    }
+    __syncthreads();
+    if (has) {
+      const double sim = exact_wave(a, p.x, p.y, s_idx[wv], s_val[wv]);
+      if (lane_id() == 0 && sim > a.t) {
+        const int slot = atomicAdd(&s_kept, 1);
+        idx[slot] = c;
+        val[slot] = float(sim);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.wst_cnt[w] = uint32_t(s_kept);
+}
+
 // Tiles path: each wave's staged accepted pairs to the caller's list at its
-// offset, S_hat computed from (m, n); one block per wave region.
+// offset, S_hat computed from (m, n) (Lite: the exact similarity staged);
+// one block per wave region.
 __global__ __launch_bounds__(kBlock) void k_tiles_copy(VerifyArgs a, const int64_t *off) {
   const int64_t w = blockIdx.x;
   const int64_t n = a.wst_cnt[w], base = off[w];
@@ -955,7 +1013,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles_copy(VerifyArgs a, const int64
     if (pos < a.acc_cap) {
       const uint32_t u = __float_as_uint(val[i]);
       a.acc_idx[pos] = idx[i];
-      a.acc_val[pos] = map_estimate(a.measure, int(u & 0xFFFFu), int(u >> 16), alpha, beta);
+      a.acc_val[pos] = a.st_raw ? map_estimate(a.measure, int(u & 0xFFFFu), int(u >> 16), alpha, beta) : val[i];
     } else {
       trunc = true;
     }
@@ -1363,13 +1421,14 @@ static int64_t resident_blocks(blsh_ctx *ctx, F kernel, size_t lds) {
 
 // Waves of the persistent tile grid for (k, n_max) (the staging holds one
 // region per wave).
-int tiles_grid_waves(blsh_ctx *ctx, int k, int n_max, bool intervals, size_t lds, int64_t *waves) {
+int tiles_grid_waves(blsh_ctx *ctx, int k, int n_max, bool intervals, bool lite, size_t lds, int64_t *waves) {
   const int NW = n_max / 32;
-#define BLSH_TG(KK, WW)                                                                                     \
-  if (k == KK && NW == WW) {                                                                                \
-    *waves = (intervals ? resident_blocks(ctx, k_verify_tiles<KK, WW, true>, 0)                             \
-                        : resident_blocks(ctx, k_verify_tiles<KK, WW, false>, lds)) * (kBlock / kWave);    \
-    return BLSH_OK;                                                                                         \
+#define BLSH_TG(KK, WW)                                                                                        \
+  if (k == KK && NW == WW) {                                                                                   \
+    *waves = (lite ? resident_blocks(ctx, k_verify_tiles<KK, WW, true, true>, 0)                               \
+              : intervals ? resident_blocks(ctx, k_verify_tiles<KK, WW, true, false>, 0)                       \
+                          : resident_blocks(ctx, k_verify_tiles<KK, WW, false, false>, lds)) * (kBlock / kWave); \
+    return BLSH_OK;                                                                                            \
   }
   BLSH_TG(16, 4) BLSH_TG(16, 8) BLSH_TG(16, 16) BLSH_TG(16, 32) BLSH_TG(16, 64)
   BLSH_TG(32, 4) BLSH_TG(32, 8) BLSH_TG(32, 16) BLSH_TG(32, 32) BLSH_TG(32, 64)
@@ -1379,23 +1438,32 @@ int tiles_grid_waves(blsh_ctx *ctx, int k, int n_max, bool intervals, size_t lds
 }
 
 // grid_waves: from tiles_grid_waves (every wave of the grid writes its count).
-int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals,
+// lite: Algorithm 2 (its table's accept sets are empty, so intervals).
+int launch_verify_tiles(blsh_ctx *ctx, const VerifyArgs &a, int k, int n_max, int words, bool intervals, bool lite,
                         int64_t grid_waves, hipStream_t s) {
   const int64_t nb = grid_waves / (kBlock / kWave);
-  const size_t lds = intervals ? 0 : size_t(a.n_levels) * words * 4;
+  const size_t lds = intervals || lite ? 0 : size_t(a.n_levels) * words * 4;
   const int NW = n_max / 32;
   LaunchScope ls(ctx, s, "verify_tiles");
-#define BLSH_TT(KK, WW)                                                                              \
-  if (k == KK && NW == WW) {                                                                         \
-    if (intervals) hipLaunchKernelGGL((k_verify_tiles<KK, WW, true>), dim3(nb), dim3(kBlock), 0, s, a); \
-    else hipLaunchKernelGGL((k_verify_tiles<KK, WW, false>), dim3(nb), dim3(kBlock), lds, s, a);      \
-    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                                 \
+#define BLSH_TT(KK, WW)                                                                                      \
+  if (k == KK && NW == WW) {                                                                                 \
+    if (lite) hipLaunchKernelGGL((k_verify_tiles<KK, WW, true, true>), dim3(nb), dim3(kBlock), 0, s, a);      \
+    else if (intervals) hipLaunchKernelGGL((k_verify_tiles<KK, WW, true, false>), dim3(nb), dim3(kBlock), 0, s, a); \
+    else hipLaunchKernelGGL((k_verify_tiles<KK, WW, false, false>), dim3(nb), dim3(kBlock), lds, s, a);     \
+    return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;                                         \
   }
   BLSH_TT(16, 4) BLSH_TT(16, 8) BLSH_TT(16, 16) BLSH_TT(16, 32) BLSH_TT(16, 64)
   BLSH_TT(32, 4) BLSH_TT(32, 8) BLSH_TT(32, 16) BLSH_TT(32, 32) BLSH_TT(32, 64)
   BLSH_TT(64, 4) BLSH_TT(64, 8) BLSH_TT(64, 16) BLSH_TT(64, 32) BLSH_TT(64, 64)
 #undef BLSH_TT
   return fail(BLSH_EINVAL, "tiles: unsupported k=%d, n_max=%d", k, n_max);
+}
+
+// Tiles path, Lite: the staged pairs' exact similarities, one block per region.
+int launch_tiles_exact(blsh_ctx *ctx, const VerifyArgs &a, int64_t grid_waves, hipStream_t s) {
+  LaunchScope ls(ctx, s, "tiles_exact");
+  hipLaunchKernelGGL(k_tiles_exact, dim3(grid_waves), dim3(kBlock), 0, s, a);
+  return hipGetLastError() == hipSuccess ? BLSH_OK : BLSH_EDEVICE;
 }
 
 // Tiles path, after each launch: offsets of the waves' staged pairs, then the

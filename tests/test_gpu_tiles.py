@@ -256,10 +256,43 @@ def test_tiles_rejected_where_unsupported(ctx, mix, banded):
             P.bayeslsh_verify(ctx, cand, S, 0.7, EPS, DELTA, GAMMA, (1, 1), 32, res)
         assert e.value.code == -1
     S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
+    with pytest.raises(P.BayesLSHError):   # Lite over tiles: h a multiple of 128
+        P.bayeslsh_lite_verify(ctx, cand, S, P.dense_vectors(up(mix.x)), 0.7, EPS, (1, 1), 64, 32, res)
     with pytest.raises(P.BayesLSHError):
-        P.bayeslsh_lite_verify(ctx, cand, S, P.dense_vectors(up(mix.x)), 0.7, EPS, (1, 1), 128, 32, res)
+        P.bayeslsh_exhaustive_verify(ctx, cand, S, None, 0.7, EPS, DELTA, GAMMA, (1, 1), 32, 0, P.REPLAY, res)
     with pytest.raises(P.BayesLSHError):
         P.bayeslsh_verify_noalloc(ctx, cand, S, 0.7, EPS, DELTA, GAMMA, (1, 1), 32, res)
     with pytest.raises(P.BayesLSHError):    # tiles must be 16-byte aligned
         P.bayeslsh_verify(ctx, P.tiles(tl.view(torch.int32)[1:], nt, npairs), S, 0.7, EPS, DELTA, GAMMA, (1, 1), 32,
                           res)
+
+
+@pytest.mark.parametrize("k,h,t", [(32, 128, 0.7), (16, 256, 0.8), (64, 512, 0.7)])
+def test_tiles_lite_matches_oracle(ctx, mix, banded, k, h, t):
+    """Algorithm 2 (BayesLSH-Lite) over the tiles: prune tests on the first h
+    hashes, then the exact cosine of the mixture rows for the survivors,
+    emitted iff s > t: the oracle's decisions, levels, m and exact values on
+    the oracle's banding pairs, and the PAIRS Lite path's output."""
+    print("tiles lite k=%d h=%d t=%.1f" % (k, h, t), flush=True)
+    band, (wx, wy) = banded
+    sig = _bits(mix, 1024, G.SEED_BASE + 65)
+    tl, nt, npairs = band_tiles(ctx, sigs_tensor(band, P.COSINE, P.OBJECT_MAJOR), 16, 6)
+    want = R.verify(wx, wy, P.COSINE, sig, k, h // k, t, EPS, 0, 0, lite=True)
+    exact_fn = lambda a_, b_: R.exact_cosine_dense(mix.x, a_, b_)
+    want = R.lite_finish(want, exact_fn, wx, wy, t)
+    assert {0, 3} <= set(want["decision"].tolist())
+    S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
+    vec = P.dense_vectors(up(mix.x))
+    res = P.make_result(npairs, npairs, m_debug=True)
+    P.bayeslsh_lite_verify(ctx, P.tiles(tl, nt, npairs), S, vec, t, EPS, (1, 1), h, k, res)
+    P.bayeslsh_sync(ctx)
+    got = decode_result(res, npairs)
+    assert_same_as_oracle(got, want, lite_exact=want["exact"])
+    assert got["n_accepted"] > 10
+    res_p = P.make_result(npairs, npairs, m_debug=True)
+    P.bayeslsh_lite_verify(ctx, P.pairs(up(wx), up(wy)), S, vec, t, EPS, (1, 1), h, k, res_p)
+    P.bayeslsh_sync(ctx)
+    gp = decode_result(res_p, npairs)
+    np.testing.assert_array_equal(got["code"], gp["code"])
+    np.testing.assert_array_equal(got["acc_idx"], gp["acc_idx"])
+    np.testing.assert_array_equal(got["acc_val"], gp["acc_val"])
