@@ -81,9 +81,11 @@ def lite_candidates(torch, P, ctx, corpus, small):
     the band keys are the sign bits of the independent Gaussian projection that
     build_workload bands (10 bits a band; 8 for the small corpus), and
     bayeslsh_band_candidates lists each bucket's pairs in 16 x 16 tiles of its
-    members (first-band dedupe), the order the compare kernel reads best.  The
-    candidate set is the one build_workload lists.  Returns device x, y, the
-    count and the time of a second, timed banding call in ms."""
+    members (first-band dedupe), the order the compare kernel reads best; and
+    the same candidates, numbered alike, as bucket tiles (bayeslsh_band_tiles).
+    The candidate set is the one build_workload lists.  Returns device x, y,
+    the count, the time of a second, timed banding call in ms, then the tiles,
+    their count and the timed tile banding call in ms."""
     from synth import generators as G
     bb = 8 if small else 10
     words = G.sparse_band_bits(corpus, n_bands=16, band_bits=bb, seed=G.SEED_BASE + 102)
@@ -98,7 +100,16 @@ def lite_candidates(torch, P, ctx, corpus, small):
     band_ms = (time.perf_counter() - t0) * 1e3
     if trunc:
         raise RuntimeError("banding: %d candidates exceed the %d-entry buffers" % (n, cap))
-    return xo[:n], yo[:n], n, band_ms
+    tile_cap = 1 << 21
+    tl = torch.empty(tile_cap * 24, dtype=torch.int64, device="cuda")
+    P.bayeslsh_band_tiles(ctx, S_band, 16, bb, tile_cap, tiles_out=tl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, nt, n_t, trunc = P.bayeslsh_band_tiles(ctx, S_band, 16, bb, tile_cap, tiles_out=tl)
+    band_t_ms = (time.perf_counter() - t0) * 1e3
+    if trunc or n_t != n:
+        raise RuntimeError("banding into tiles: %d candidates in %d tiles (pairs: %d)" % (n_t, nt, n))
+    return xo[:n], yo[:n], n, band_ms, tl, nt, band_t_ms
 
 
 def cpu_baseline(corpus, x, y, gpu_codes, gpu_m, gpu_acc):
@@ -982,15 +993,19 @@ def run_lite(args, torch, P):
     step = one bayeslsh_lite_verify call over all candidates.  Two exhaustive
     comparators with the same output: all 2048 bits of both object-major rows,
     and only the h = 128 bits Lite may use (all h/k level counts, no early
-    exit) -- the second isolates the gain of Algorithm 2's early pruning."""
+    exit) -- the second isolates the gain of Algorithm 2's early pruning.  The
+    same candidates as bucket tiles (bayeslsh_band_tiles, 16 x 16 member tiles
+    over the 128-bit object-major rows) are timed beside the step and must give
+    the same output."""
     log("generating workload")
     from synth import generators as G
     corpus = G.tfidf_corpus(n_docs=20_000, seed=G.SEED_BASE + 2) if args.small else G.tfidf_corpus(seed=G.SEED_BASE + 2)
     ctx = P.bayeslsh_create(0)
-    xd, yd, n, band_ms = lite_candidates(torch, P, ctx, corpus, args.small)
+    xd, yd, n, band_ms, tl, n_tiles, band_t_ms = lite_candidates(torch, P, ctx, corpus, args.small)
     x = xd.view(torch.int32).cpu().numpy().view(np.uint32)      # host copies for the oracle baseline
     y = yd.view(torch.int32).cpu().numpy().view(np.uint32)
-    log("corpus %d docs, %d nnz; %d candidates (GPU banding, %.1f ms)" % (corpus.n, len(corpus.indices), n, band_ms))
+    log("corpus %d docs, %d nnz; %d candidates (GPU banding: %.1f ms as pairs, %.1f ms as %d tiles)"
+        % (corpus.n, len(corpus.indices), n, band_ms, band_t_ms, n_tiles))
     vec = P.csr_vectors(up(torch, corpus.offsets), up(torch, corpus.indices), up(torch, corpus.values), corpus.dim)
     W = N_BITS // 32
     sig_wm = torch.empty(corpus.n * W, dtype=torch.int32, device="cuda").view(torch.uint32)
@@ -1015,13 +1030,25 @@ def run_lite(args, torch, P):
     same_prefix = bool(torch.equal(sig_pf.view(torch.int32).view(corpus.n, H // 32),
                                    sig_om.view(torch.int32).view(corpus.n, N_BITS // 32)[:, : H // 32]))
     cand = P.pairs(xd, yd)
+    # the step runs over id pairs (Lite reads 128 bits: one 16-byte gather per
+    # side); the same candidates as bucket tiles over the 128-bit object-major
+    # rows are timed beside it (same output)
+    tiles = False
+    with_tiles = args.layout == "prefix"
+    cand_t = P.tiles(tl, n_tiles, n)
+    main_cand = cand
     cap = max(1 << 20, n // 100)
     res = P.make_result(n, cap)
     res_ex = P.make_result(n, cap)
     stream = torch.cuda.current_stream()
 
     def step():
-        P.bayeslsh_lite_verify(ctx, cand, S_run, vec, T, EPS, (1.0, 1.0), H, K, res, stream)
+        P.bayeslsh_lite_verify(ctx, main_cand, S_run, vec, T, EPS, (1.0, 1.0), H, K, res, stream)
+
+    res_p = P.make_result(n, cap)
+
+    def step_tiles():
+        P.bayeslsh_lite_verify(ctx, cand_t, S_run, vec, T, EPS, (1.0, 1.0), H, K, res_p, stream)
 
     def step_ex():
         P.bayeslsh_exhaustive_verify(ctx, cand, S_om, vec, T, EPS, 0.5, 0.5, (1.0, 1.0), K, H, P.REPLAY_LITE, res_ex,
@@ -1051,12 +1078,34 @@ def run_lite(args, torch, P):
     for _ in range(args.steps):
         step()
     P.bayeslsh_sync(ctx, stream)
-    k_ms, k_n = P.bayeslsh_profile_read(ctx, "verify_bits")
+    k_ms, k_n = P.bayeslsh_profile_read(ctx, "verify_tiles" if tiles else "verify_bits")
     k_name = ("k_verify_bits, object-major 128-bit rows (one 16-byte gather per side); Lite survivors queued "
               "for k_exact" if args.layout == "prefix" else "k_verify_bits, word-major slabs, fused Lite exact")
-    x_ms, x_n = P.bayeslsh_profile_read(ctx, "exact")   # exact similarity of the survivors (prefix layout)
+    x_ms, x_n = P.bayeslsh_profile_read(ctx, "exact")   # exact similarity of the survivors
+    f_ms, f_n = P.bayeslsh_profile_read(ctx, "flush")
     P.bayeslsh_profile_enable(ctx, False)
     log("BayesLSH-Lite: %.3f ms/step (verify kernel %.3f ms)" % (ms_step, k_ms / max(k_n, 1)))
+    # the same candidates as bucket tiles: the 32 rows of a tile staged once
+    ms_tiles, kt_ms, kt_n = None, 0.0, 0
+    if with_tiles:
+        for _ in range(2):
+            step_tiles()
+        P.bayeslsh_sync(ctx, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step_tiles()
+        torch.cuda.synchronize()
+        ms_tiles = (time.perf_counter() - t0) * 1e3 / args.steps
+        P.bayeslsh_sync(ctx, stream)
+        P.bayeslsh_profile_enable(ctx, True)
+        P.bayeslsh_profile_reset(ctx)
+        step_tiles()
+        P.bayeslsh_sync(ctx, stream)
+        kt_ms, kt_n = P.bayeslsh_profile_read(ctx, "verify_tiles")
+        P.bayeslsh_profile_enable(ctx, False)
+        log("BayesLSH-Lite over bucket tiles: %.3f ms/step (k_verify_tiles %.3f ms x %d)"
+            % (ms_tiles, kt_ms / max(kt_n, 1), kt_n))
     # exhaustive comparators
     ex_steps = max(3, args.steps // 5)
 
@@ -1085,10 +1134,11 @@ def run_lite(args, torch, P):
 
     same = same_as(res_ex)
     same_h = same_as(res_exh)
-    del res_ex, res_exh
+    same_p = same_as(res_p) if with_tiles else None
+    del res_ex, res_exh, res_p
     # m of every candidate, from a pass with m recorded (not timed)
     res_m = P.make_result(n, cap, m_debug=True)
-    P.bayeslsh_lite_verify(ctx, cand, S_run, vec, T, EPS, (1.0, 1.0), H, K, res_m, stream)
+    P.bayeslsh_lite_verify(ctx, main_cand, S_run, vec, T, EPS, (1.0, 1.0), H, K, res_m, stream)
     P.bayeslsh_sync(ctx, stream)
     assert bool(torch.equal(res_m.code[:n], res.code[:n]))
     gpu_m = res_m.m_debug[:n].view(torch.int16).cpu().numpy().view(np.uint16).astype(np.int32)
@@ -1100,7 +1150,8 @@ def run_lite(args, torch, P):
     # (2 x k/8 B per level reached) come from a 1.6 MB array (prefix layout) or
     # 400 KB slabs (word-major) that stay in L2; the exact cosine of the rare
     # survivors reads their two sparse rows (~2 x 100 x 8 B).
-    hbm_bytes = n * 9
+    # (tiles: the 192 B descriptor per tile instead of 8 B of ids per candidate)
+    hbm_bytes = n_tiles * 192 + n if tiles else n * 9
     gather_bytes = int(np.sum(lvl.astype(np.int64) + 1)) * 2 * (K // 8)
     k_avg_ms = k_ms / max(k_n, 1)
     per_step = max(k_n, 1) / args.steps                 # verify launches per step (candidate chunks)
@@ -1130,11 +1181,17 @@ def run_lite(args, torch, P):
                          "tiles per bucket), t=0.7, eps=0.03, h=128, k=32, exact FP64-accumulated cosine on "
                          "survivors" % corpus.n),
             "n_candidates": n,
-            "banding_ms": band_ms,
+            "n_tiles": n_tiles if tiles else None,
+            "banding_ms": band_t_ms if tiles else band_ms,
+            "banding_pairs_ms": band_ms,
             "survivors_after_h": n_surv,
             "accepted": int(len(ia)),
             "pruned_at_level": [int(np.sum((dec == 0) & (lvl == j))) for j in range(H // K)],
         },
+        "bucket_tiles": {"ms_per_step": ms_tiles, "value": n / (ms_tiles * 1e-3) if ms_tiles else None,
+                         "same_output": same_p, "n_tiles": n_tiles, "banding_ms": band_t_ms,
+                         "kernel": "k_verify_tiles (Lite) + k_tiles_exact + flush",
+                         "verify_kernel_ms": kt_ms / max(kt_n, 1), "launches": kt_n},
         "exhaustive": {"ms_per_step": ex_ms, "value": n / (ex_ms * 1e-3), "speedup": ex_ms / ms_step,
                        "same_output": same, "mode": "REPLAY_LITE, all 2048 bits per object"},
         "exhaustive_h_bits": {"ms_per_step": exh_ms, "value": n / (exh_ms * 1e-3), "speedup": exh_ms / ms_step,
@@ -1149,12 +1206,16 @@ def run_lite(args, torch, P):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": k_name,
                      "kernel_ms": k_avg_ms, "kernel_launches_timed": k_n,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "bytes_model": "per candidate 8 B ids + 1 B code + 8 B per level reached (4 B chunk per "
-                                    "side at k = 32); survivors' exact cosines are k_exact's",
+                     "bytes_model": ("per tile the 192 B descriptor, per candidate 1 B code + 8 B per level "
+                                     "reached (4 B chunk per side at k = 32); survivors' exact cosines are "
+                                     "k_tiles_exact's" if tiles else
+                                     "per candidate 8 B ids + 1 B code + 8 B per level reached (4 B chunk per "
+                                     "side at k = 32)"),
                      "hbm_stream_bytes_per_launch": hbm_bytes,
                      "stream_frac": hbm_bytes / (k_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "traffic_frac": traffic / (k_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
-                     "exact_kernel_ms": x_ms / max(x_n, 1) if x_n else None},
+                     "exact_kernel_ms": x_ms / max(x_n, 1) if x_n else None,
+                     "flush_kernel_ms": f_ms / max(f_n, 1) if f_n else None},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle)")

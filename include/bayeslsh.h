@@ -349,10 +349,13 @@ int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *plan
  * k in {16, 32, 64}; n_max % k == 0; n_max/k <= 64.  SRP signatures may be
  * OBJECT_MAJOR or WORD_MAJOR (WORD_MAJOR is the fast layout); minhash
  * signatures must be OBJECT_MAJOR with n_hashes % 4 == 0.
- * BLSH_TILES candidates (SRP, this entry point only: Lite, the comparators and
- * the allocation-free entry point refuse them with BLSH_EINVAL): OBJECT_MAJOR
- * rows, 16-byte aligned, of a multiple of 128 hashes, n_max a multiple of 128
- * up to 2048; tiles may come in any order of their numbering.  A wave takes a
+ * BLSH_TILES candidates (SRP; also bayeslsh_lite_verify, with h a multiple of
+ * 128; the comparators and the allocation-free entry point refuse them with
+ * BLSH_EINVAL): OBJECT_MAJOR rows, 16-byte aligned, of a multiple of 128
+ * hashes, n_max a multiple of 128 up to 2048; tiles may come in any order of
+ * their numbering.  Lite over tiles stages every position of a launch's tiles
+ * for the exact similarity: up to 20 bytes of workspace per candidate, at
+ * most 2.7 GB (longer calls run as several launches).  A wave takes a
  * tile: it stages the first n_max hashes of its 32 members in LDS (one load
  * per 128-byte line), decides level 0 for the tile's pairs and finishes the
  * pairs level 0 does not prune from those rows.  Malformed tiles are reported

@@ -388,7 +388,7 @@ static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
 // running accepted count sits in the context's counter buffer.
 static constexpr int64_t kTilesChunk = int64_t(1) << 22;
 static constexpr int64_t kTilesStage = int64_t(1) << 27;
-static constexpr int64_t kTilesStageLite = int64_t(1) << 24;   // 20 B per entry
+static constexpr int64_t kTilesStageLite = int64_t(1) << 27;   // 20 B per entry
 
 static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, int k, int n_max, int n_levels,
                      bool intervals, bool lite, hipStream_t s) {
