@@ -783,6 +783,14 @@ def run_dense(args, torch, P):
     lvl_mean = levels_reached / n - 1.0
     n_acc = int(res.n_accepted.item())
     del lvl, dec
+    # decisions by level (index j: taken after (j + 1) k hashes): a histogram of
+    # the code bytes, in chunks of 2^30 candidates
+    hist = torch.zeros(256, dtype=torch.int64, device="cuda")
+    for c0 in range(0, n, 1 << 30):
+        hist += torch.bincount(codes[c0:c0 + (1 << 30)].to(torch.int32), minlength=256)
+    hist = hist.cpu().numpy()
+    by_level = {name: hist[64 * d: 64 * d + 1024 // k].tolist()
+                for d, name in ((0, "pruned"), (1, "accept_conc"), (2, "accept_nmax"))}
 
     # parity pass with m recorded (not timed), on a seeded sample against the oracle
     res_m = P.make_result(n, acc_cap, m_debug=True)
@@ -903,7 +911,7 @@ def run_dense(args, torch, P):
                    "n_candidates": n, "n_tiles": n_tiles, "banding_tiles_ms": band_tiles_ms,
                    "banding_pairs_ms": band_ms, "banding_pairs_per_s": n / (band_tiles_ms * 1e-3)},
         "decisions": {"pruned": dec_counts[0], "accept_conc": dec_counts[1], "accept_nmax": dec_counts[2],
-                      "mean_level": lvl_mean, "accepted_listed": n_acc},
+                      "mean_level": lvl_mean, "accepted_listed": n_acc, "by_level": by_level},
         "id_pairs": {"ms_per_step": ms_p, "value": n / (ms_p * 1e-3), "same_output_as_tiles": same_p,
                      "differing_codes": diff_p,
                      "note": "the same candidates as 8 B id pairs (bayeslsh_band_candidates) with the 16 B/object "

@@ -713,6 +713,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
   __syncthreads();
   const bool last_lane = q == P2 - 1;         // holds level L - 1 as its level LPL - 1
   const uint32_t min0 = a.table[kTabMinOff];
+  // level 1's prune test in the first pass (none with a single level), after
+  // level 0's accept test: ad0 = K - min_accept of level 0
+  const uint32_t min1 = L > 1 ? a.table[kTabMinOff + 1] : 0u;
+  const int ad0 = reinterpret_cast<const int *>(s_ad)[0];
   const int64_t gw = xcd_tile(blockIdx.x, gridDim.x) * (kBlock / kWave) +
                      __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
   const int64_t n_waves = int64_t(gridDim.x) * (kBlock / kWave);
@@ -773,8 +777,11 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
       if (lane == 0) raise_status(a.status, BLSH_EINVAL);
       continue;
     }
-    // level 0 for this lane's four positions; codes go to LDS by rank
-    const uint32_t xw0 = S.rows[r][0], xw1 = K == 64 ? S.rows[r][1] : 0u;
+    // levels 0 and 1 for this lane's four positions (2K <= 128 hashes: the
+    // first 4 words of each row, one LDS read): a pair pruned at level 0, or
+    // at level 1 without level 0 having accepted it, is decided here; the rest
+    // is listed.  Codes go to LDS by rank.
+    const u32x4 xw = *reinterpret_cast<const u32x4 *>(&S.rows[r][0]);
     uint32_t surv = 0, mm[4];
     bool malformed = false;
 #pragma unroll
@@ -782,14 +789,26 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
       const int rk = below + __popc(kb & ((1u << i) - 1u));
       const bool kept = (kb >> i) & 1u;
       const bool ok = xid != kNoObject && yid[i] != kNoObject;
-      uint32_t m;
-      if constexpr (K == 16) m = 16u - __popc((xw0 ^ S.rows[cc + i][0]) & 0xFFFFu);
-      else if constexpr (K == 32) m = 32u - __popc(xw0 ^ S.rows[cc + i][0]);
-      else m = 64u - __popc(xw0 ^ S.rows[cc + i][0]) - __popc(xw1 ^ S.rows[cc + i][1]);
-      mm[i] = m;
-      S.code[kept ? rk : 256 + lane] = ok ? uint8_t(BLSH_PRUNED << 6) : uint8_t(0xFF);   // survivors: set later
+      const u32x4 yw = *reinterpret_cast<const u32x4 *>(&S.rows[cc + i][0]);
+      uint32_t m0, m1;
+      if constexpr (K == 16) {
+        const uint32_t d = xw.x ^ yw.x;
+        m0 = 16u - __popc(d & 0xFFFFu);
+        m1 = 16u - __popc(d >> 16);
+      } else if constexpr (K == 32) {
+        m0 = 32u - __popc(xw.x ^ yw.x);
+        m1 = 32u - __popc(xw.y ^ yw.y);
+      } else {
+        m0 = 64u - __popc(xw.x ^ yw.x) - __popc(xw.y ^ yw.y);
+        m1 = 64u - __popc(xw.z ^ yw.z) - __popc(xw.w ^ yw.w);
+      }
+      const bool s0 = kept && ok && m0 >= min0;
+      const bool acc0 = INTERVALS ? int(K - m0) <= ad0 : ((s_acc[m0 >> 5] >> (m0 & 31)) & 1u) != 0;
+      const bool p1 = s0 && !acc0 && m0 + m1 < min1;
+      mm[i] = p1 ? m0 + m1 : m0;
+      S.code[kept ? rk : 256 + lane] = ok ? uint8_t((BLSH_PRUNED << 6) | (p1 ? 1 : 0)) : uint8_t(0xFF);   // survivors: set later
       malformed |= kept && !ok && (r >= n_rows || cc - 16 + i >= n_cols);   // a position past the tile's members
-      surv |= uint32_t(kept && ok && m >= min0) << i;
+      surv |= uint32_t(s0 && !p1) << i;
     }
     if (malformed) raise_status(a.status, BLSH_EINVAL);
     if (a.m_dbg) {   // m of the pairs level 0 decides (survivors: after their last level)

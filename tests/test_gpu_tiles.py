@@ -296,3 +296,38 @@ def test_tiles_lite_matches_oracle(ctx, mix, banded, k, h, t):
     np.testing.assert_array_equal(got["code"], gp["code"])
     np.testing.assert_array_equal(got["acc_idx"], gp["acc_idx"])
     np.testing.assert_array_equal(got["acc_val"], gp["acc_val"])
+
+
+@pytest.mark.parametrize("k", [32, 64])
+def test_tiles_level0_accept_before_level1_prune(ctx, k):
+    """The tile kernel decides levels 0 and 1 in its first pass.  A pair that
+    agrees on every hash of level 0 is accepted there (the table concentrates
+    at m = n = k) even when it disagrees on every hash of level 1, which would
+    prune it at level 1 had level 0 not ended its loop (Algorithm 1 tests
+    acceptance before going on).  One tile: row 0 an all-zero object, columns
+    objects with chosen disagreement counts in levels 0 and 1: the oracle's
+    decisions, levels and m."""
+    n_max, t = 512, 0.8
+    words = n_max // 32
+    rng = np.random.default_rng(17)
+    combos = [(0, k), (0, k), (0, k // 2), (1, k), (2, k), (k // 4, k), (0, 0), (3, 0), (k // 2, 0), (1, 1),
+              (0, k - 1), (k - 1, k), (5, 5), (0, 3), (2, k - 2)]
+    sig = np.zeros((len(combos) + 1, words), np.uint32)
+    for j, (d0, d1) in enumerate(combos, start=1):
+        bits = np.zeros(n_max, np.uint8)
+        bits[rng.choice(k, d0, replace=False)] = 1            # level 0 disagreements
+        bits[k + rng.choice(k, d1, replace=False)] = 1        # level 1 disagreements
+        bits[2 * k:] = rng.integers(0, 2, n_max - 2 * k) * (rng.random(n_max - 2 * k) < 0.1)
+        sig[j] = G.pack_bits(bits[None, :])[0]
+    m_cols = len(combos)
+    tile = _tile(0, np.array([0], np.uint32), np.arange(1, m_cols + 1, dtype=np.uint32), list(range(m_cols)))
+    x = np.zeros(m_cols, np.uint32)
+    y = np.arange(1, m_cols + 1, dtype=np.uint32)
+    want = R.verify(x, y, P.COSINE, sig, k, n_max // k, t, EPS, DELTA, GAMMA)
+    # the case under test is there: accepted at level 0 with level 1 all disagreeing
+    assert want["decision"][0] == 1 and want["level"][0] == 0
+    S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
+    res = P.make_result(m_cols, m_cols, m_debug=True)
+    P.bayeslsh_verify(ctx, P.tiles(up(tile), 1, m_cols), S, t, EPS, DELTA, GAMMA, (1, 1), k, res)
+    P.bayeslsh_sync(ctx)
+    assert_same_as_oracle(decode_result(res, m_cols), want)
