@@ -1,0 +1,140 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the bench
+times, on seeded samples of the outputs that the oracle computes one by one.
+
+- Dense estimation: 1M x 256 Gaussian-mixture vectors, 1024 SRP bits, GPU LSH
+  banding 16 x 12 bits of an independent 192-bit projection (2.4e9 candidates)
+  handed over as bucket tiles, Algorithm 1 at t = 0.8, eps = gamma = 0.03,
+  delta = 0.05, k = 32.  A stratified sample of 2^21 candidates (their ids
+  from the same banding listed as id pairs, numbered alike) against the
+  oracle on the GPU's own signatures: decision, level, m and S_hat; the id-pair
+  path gives the same codes for every candidate.
+- Cosine Lite: 100,000 tf-idf documents, 128 SRP bits, 16-band x 10-bit GPU
+  banding (80.7M candidates), Algorithm 2 at t = 0.7, eps = 0.03, k = 32,
+  h = 128.  A stratified sample of 2^20 candidates against the oracle's
+  Algorithm 2 on the GPU's signatures and its FP64 exact cosines.
+
+The oracle takes the GPU's signature bits as input (signature generation is
+checked separately under the sign-flip rule), so every sampled output is
+compared exactly."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1110_1328_amd as P
+from oracle import reference as R
+from synth import generators as G
+
+from gpu_util import csr_device, down, up
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    c = P.bayeslsh_create(0)
+    yield c
+    c.close()
+
+
+def _sample(n, n_sample, seed):
+    """One uniform draw from each of n_sample equal strata of [0, n)."""
+    rng = np.random.default_rng(seed)
+    stride = n // n_sample
+    return np.arange(n_sample, dtype=np.int64) * stride + rng.integers(0, stride, n_sample)
+
+
+def _gather_u32(t, idx):
+    return down(t.view(torch.int32)[torch.from_numpy(idx).cuda()].view(torch.uint32))
+
+
+def _results_at(res, idx, n):
+    d = torch.from_numpy(idx).cuda()
+    code = res.code[:n][d].cpu().numpy()
+    m = res.m_debug[:n].view(torch.int16)[d].cpu().numpy().view(np.uint16).astype(np.int32)
+    na = int(res.n_accepted.item())
+    assert na <= res.acc_idx.numel()
+    val = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    val[res.acc_idx[:na].view(torch.int64)] = res.acc_val[:na]
+    return code, m, val[d].cpu().numpy()
+
+
+def _check(code, m, val, want, val_key, tol):
+    np.testing.assert_array_equal(code >> 6, want["decision"])
+    np.testing.assert_array_equal(code & 63, want["level"])
+    np.testing.assert_array_equal(m, want["m"])
+    emit = np.isfinite(want[val_key]) & (want["accepted"] if "accepted" in want else True)
+    np.testing.assert_array_equal(np.isfinite(val), emit)
+    assert np.max(np.abs(val[emit] - want[val_key][emit]), initial=0.0) <= tol
+
+
+def test_dense_estimation_full_size(ctx):
+    print("full size: dense estimation, 1M objects", flush=True)
+    t, eps, delta, gamma, k = 0.8, 0.03, 0.05, 0.03, 32
+    mix = G.dense_mixture(seed=G.SEED_BASE + 4)
+    n_obj = mix.x.shape[0]
+    xd = up(mix.x)
+    planes = up(G.gaussian_planes(256, 1024, G.SEED_BASE + 204))
+    sig = torch.empty(n_obj * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), planes, 1024, 0, P.OBJECT_MAJOR, sig)
+    band = torch.empty(n_obj * 6, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(G.gaussian_planes(256, 192, G.SEED_BASE + 104)), 192, 0,
+                        P.OBJECT_MAJOR, band)
+    P.bayeslsh_sync(ctx)
+    del xd, mix
+    S_band = P.Signatures(band, P.COSINE, P.OBJECT_MAJOR, n_obj, 192)
+    tl, nt, n, trunc = P.bayeslsh_band_tiles(ctx, S_band, 16, 12, 1 << 25)
+    assert not trunc and n > 2_000_000_000
+    S = P.Signatures(sig, P.COSINE, P.OBJECT_MAJOR, n_obj, 1024)
+    res = P.make_result(n, 1 << 28, m_debug=True)
+    P.bayeslsh_verify(ctx, P.tiles(tl, nt, n), S, t, eps, delta, gamma, (1, 1), k, res)
+    P.bayeslsh_sync(ctx)
+    cap = n + 1024
+    xo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
+    yo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
+    _, _, n_p, trunc = P.bayeslsh_band_candidates(ctx, S_band, 16, 12, cap, x_out=xo, y_out=yo, order_tile=16)
+    assert not trunc and n_p == n
+    # every candidate: the id-pair path's codes equal the tiles'
+    res_p = P.make_result(n, 1 << 28)
+    P.bayeslsh_verify(ctx, P.pairs(xo[:n], yo[:n]), S, t, eps, delta, gamma, (1, 1), k, res_p)
+    P.bayeslsh_sync(ctx)
+    assert bool(torch.equal(res.code[:n], res_p.code[:n]))
+    assert int(res.n_accepted.item()) == int(res_p.n_accepted.item())
+    del res_p
+    # a stratified sample against the oracle
+    idx = _sample(n, 1 << 21, 4101)
+    xs, ys = _gather_u32(xo, idx), _gather_u32(yo, idx)
+    code, m, val = _results_at(res, idx, n)
+    sig_h = down(sig).reshape(n_obj, 32)
+    want = R.verify(xs, ys, P.COSINE, sig_h, k, 1024 // k, t, eps, delta, gamma)
+    _check(code, m, val, want, "shat", 1e-6)
+    assert (want["decision"] == 0).any() and (want["decision"] == 1).any() and (want["decision"] == 2).any()
+
+
+def test_cosine_lite_full_size(ctx):
+    print("full size: cosine Lite, 100k documents", flush=True)
+    t, eps, h, k = 0.7, 0.03, 128, 32
+    corpus = G.tfidf_corpus(seed=G.SEED_BASE + 2)
+    vec = csr_device(corpus)
+    sig = torch.empty(corpus.n * (h // 32), dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, vec, None, h, 0x5EED_1110_1328, P.OBJECT_MAJOR, sig)
+    words = G.sparse_band_bits(corpus, n_bands=16, band_bits=10, seed=G.SEED_BASE + 102)
+    S_band = P.Signatures(up(words.reshape(-1)), P.COSINE, P.OBJECT_MAJOR, corpus.n, words.shape[1] * 32)
+    cap = 1 << 27
+    xo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
+    yo = torch.empty(cap, dtype=torch.int32, device="cuda").view(torch.uint32)
+    _, _, n, trunc = P.bayeslsh_band_candidates(ctx, S_band, 16, 10, cap, x_out=xo, y_out=yo, order_tile=16)
+    assert not trunc and n > 80_000_000
+    S = P.Signatures(sig, P.COSINE, P.OBJECT_MAJOR, corpus.n, h)
+    res = P.make_result(n, 1 << 22, m_debug=True)
+    P.bayeslsh_lite_verify(ctx, P.pairs(xo[:n], yo[:n]), S, vec, t, eps, (1, 1), h, k, res)
+    P.bayeslsh_sync(ctx)
+    idx = _sample(n, 1 << 20, 4102)
+    xs, ys = _gather_u32(xo, idx), _gather_u32(yo, idx)
+    code, m, val = _results_at(res, idx, n)
+    sig_h = down(sig).reshape(corpus.n, h // 32)
+    want = R.verify(xs, ys, P.COSINE, sig_h, k, h // k, t, eps, 0, 0, lite=True)
+    want = R.lite_finish(want, lambda a, b: R.exact_cosine_csr(corpus.offsets, corpus.indices, corpus.values, a, b),
+                         xs, ys, t)
+    _check(code, m, val, want, "exact", 1e-6)
+    assert (want["decision"] == 0).any() and (want["decision"] == 3).any() and want["accepted"].any()
