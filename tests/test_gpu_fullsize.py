@@ -12,6 +12,10 @@ times, on seeded samples of the outputs that the oracle computes one by one.
   banding (80.7M candidates), Algorithm 2 at t = 0.7, eps = 0.03, k = 32,
   h = 128.  A stratified sample of 2^20 candidates against the oracle's
   Algorithm 2 on the GPU's signatures and its FP64 exact cosines.
+- Batched: 4096 query lists (about 4.4e8 candidates) over the 1M-set minhash
+  index and the dense SRP index (word-major slabs plus the prefix array), k and
+  launch shapes autotuned.  A stratified sample of 2^20 candidates against the
+  oracle at each measure's chosen k and each list's threshold.
 
 The oracle takes the GPU's signature bits as input (signature generation is
 checked separately under the sign-flip rule), so every sampled output is
@@ -138,3 +142,90 @@ def test_cosine_lite_full_size(ctx):
                          xs, ys, t)
     _check(code, m, val, want, "exact", 1e-6)
     assert (want["decision"] == 0).any() and (want["decision"] == 3).any() and want["accepted"].any()
+
+
+def _related(labels):
+    """related(q): the other objects with q's label (label < 0: none)."""
+    order = np.argsort(labels, kind="stable")
+    lab = labels[order]
+    starts = np.searchsorted(lab, labels, side="left")
+    ends = np.searchsorted(lab, labels, side="right")
+
+    def related(q):
+        if labels[q] < 0:
+            return np.zeros(0, np.int64)
+        m = order[starts[q]:ends[q]]
+        return m[m != q]
+    return related
+
+
+def test_batched_full_size(ctx):
+    """The batched workload (4096 lists, lengths 10^U(2,6), measure ~
+    Bernoulli(1/2), t in {0.5, 0.7, 0.9}; 1M minhash sets and the 1M x 1024-bit
+    SRP index as word-major slabs plus the 128-bit prefix array), k and the
+    launch shapes autotuned as the bench runs it: a stratified sample of 2^20
+    candidates against the oracle at the chosen k of each measure and the
+    list's threshold (decision, level, m, S_hat)."""
+    print("full size: batched, 4096 lists", flush=True)
+    eps, delta, gamma = 0.03, 0.05, 0.03
+    sets = G.jaccard_sets_large(seed=G.SEED_BASE + 5)
+    a, b = G.minhash_coeffs(256, G.SEED_BASE + 205)
+    sig_j = torch.empty(sets.n * 256, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_minhash_sigs(ctx, P.set_vectors(up(sets.offsets), up(sets.elems), sets.vocab), up(a), up(b), sig_j)
+    S_j = P.Signatures(sig_j, P.JACCARD, P.OBJECT_MAJOR, sets.n, 256)
+    mix = G.dense_mixture(seed=G.SEED_BASE + 4)
+    n_c = mix.x.shape[0]
+    xd = up(mix.x)
+    planes = G.gaussian_planes(256, 1024, G.SEED_BASE + 204)
+    pfx = torch.empty(n_c * 4, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(np.ascontiguousarray(planes[:, :128])), 128, 0,
+                        P.OBJECT_MAJOR, pfx)
+    sig_wm = torch.empty(n_c * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(planes), 1024, 0, P.WORD_MAJOR, sig_wm)
+    sig_om = torch.empty(n_c * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(planes), 1024, 0, P.OBJECT_MAJOR, sig_om)
+    P.bayeslsh_sync(ctx)
+    del xd
+    S_c = P.Signatures(sig_wm, P.COSINE, P.WORD_MAJOR, n_c, 1024, prefix=pfx)
+    n_lists = 4096
+    rng = np.random.default_rng(G.SEED_BASE + 3)
+    meas = rng.integers(0, 2, n_lists).astype(np.int32)
+    ts = rng.choice([0.5, 0.7, 0.9], n_lists)
+    qj, oj, cj = G.member_lists(int(np.sum(meas == 0)), sets.n, 2, 6, _related(sets.group), seed=G.SEED_BASE + 31)
+    qc, oc, cc = G.member_lists(int(np.sum(meas == 1)), n_c, 2, 6, _related(mix.comp), seed=G.SEED_BASE + 32)
+    cand = np.concatenate([cj, cc])
+    query = np.empty(n_lists, np.uint32)
+    offset = np.empty(n_lists, np.int64)
+    length = np.empty(n_lists, np.int64)
+    ij, ic = np.flatnonzero(meas == 0), np.flatnonzero(meas == 1)
+    query[ij], offset[ij], length[ij] = qj, oj[:-1], np.diff(oj)
+    query[ic], offset[ic], length[ic] = qc, oc[:-1] + len(cj), np.diff(oc)
+    lists = P.list_descs(meas, ts, query, offset, length)
+    n = len(cand)
+    assert n > 400_000_000
+    res = P.make_result(n, 1 << 24, m_debug=True)
+    kk = P.bayeslsh_verify_batched(ctx, lists, up(cand), S_j, S_c, eps, delta, gamma, (1, 1), 0, res)
+    P.bayeslsh_sync(ctx)
+    idx = _sample(n, 1 << 20, 4103)
+    code, m, val = _results_at(res, idx, n)
+    # each sampled candidate's list: lists are stored by position (the Jaccard
+    # lists first), so sort the list starts
+    order = np.argsort(offset, kind="stable")
+    li = order[np.searchsorted(offset[order], idx, side="right") - 1]
+    assert np.all((offset[li] <= idx) & (idx < offset[li] + length[li]))
+    sigs_h = {0: down(sig_j).reshape(sets.n, 256), 1: down(sig_om).reshape(n_c, 32)}
+    n_hash = {0: 256, 1: 1024}
+    checked = 0
+    seen = set()
+    for me in (0, 1):
+        for t in (0.5, 0.7, 0.9):
+            sel = np.flatnonzero((meas[li] == me) & (ts[li] == t))
+            if not len(sel):
+                continue
+            k = int(kk[me])
+            want = R.verify(query[li[sel]], cand[idx[sel]], me, sigs_h[me], k, n_hash[me] // k, t, eps, delta, gamma)
+            _check(code[sel], m[sel], val[sel], want, "shat", 1e-6)
+            checked += len(sel)
+            seen.update(np.unique(want["decision"]).tolist())
+    assert checked == len(idx)
+    assert {0, 1, 2} <= seen
