@@ -159,6 +159,26 @@ def _related(labels):
     return related
 
 
+def _dense_index(ctx):
+    """The dense cosine index: 1M x 256 mixture vectors, 1024 SRP bits as
+    word-major slabs plus the 128-bit prefix array (what the batched and
+    serving paths read), and the same bits object-major for the oracle."""
+    mix = G.dense_mixture(seed=G.SEED_BASE + 4)
+    n_c = mix.x.shape[0]
+    xd = up(mix.x)
+    planes = G.gaussian_planes(256, 1024, G.SEED_BASE + 204)
+    pfx = torch.empty(n_c * 4, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(np.ascontiguousarray(planes[:, :128])), 128, 0,
+                        P.OBJECT_MAJOR, pfx)
+    sig_wm = torch.empty(n_c * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(planes), 1024, 0, P.WORD_MAJOR, sig_wm)
+    sig_om = torch.empty(n_c * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
+    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(planes), 1024, 0, P.OBJECT_MAJOR, sig_om)
+    P.bayeslsh_sync(ctx)
+    del xd
+    return mix, P.Signatures(sig_wm, P.COSINE, P.WORD_MAJOR, n_c, 1024, prefix=pfx), sig_om
+
+
 def test_batched_full_size(ctx):
     """The batched workload (4096 lists, lengths 10^U(2,6), measure ~
     Bernoulli(1/2), t in {0.5, 0.7, 0.9}; 1M minhash sets and the 1M x 1024-bit
@@ -173,20 +193,8 @@ def test_batched_full_size(ctx):
     sig_j = torch.empty(sets.n * 256, dtype=torch.int32, device="cuda").view(torch.uint32)
     P.bayeslsh_minhash_sigs(ctx, P.set_vectors(up(sets.offsets), up(sets.elems), sets.vocab), up(a), up(b), sig_j)
     S_j = P.Signatures(sig_j, P.JACCARD, P.OBJECT_MAJOR, sets.n, 256)
-    mix = G.dense_mixture(seed=G.SEED_BASE + 4)
+    mix, S_c, sig_om = _dense_index(ctx)
     n_c = mix.x.shape[0]
-    xd = up(mix.x)
-    planes = G.gaussian_planes(256, 1024, G.SEED_BASE + 204)
-    pfx = torch.empty(n_c * 4, dtype=torch.int32, device="cuda").view(torch.uint32)
-    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(np.ascontiguousarray(planes[:, :128])), 128, 0,
-                        P.OBJECT_MAJOR, pfx)
-    sig_wm = torch.empty(n_c * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
-    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(planes), 1024, 0, P.WORD_MAJOR, sig_wm)
-    sig_om = torch.empty(n_c * 32, dtype=torch.int32, device="cuda").view(torch.uint32)
-    P.bayeslsh_srp_sigs(ctx, P.dense_vectors(xd), up(planes), 1024, 0, P.OBJECT_MAJOR, sig_om)
-    P.bayeslsh_sync(ctx)
-    del xd
-    S_c = P.Signatures(sig_wm, P.COSINE, P.WORD_MAJOR, n_c, 1024, prefix=pfx)
     n_lists = 4096
     rng = np.random.default_rng(G.SEED_BASE + 3)
     meas = rng.integers(0, 2, n_lists).astype(np.int32)
@@ -229,3 +237,49 @@ def test_batched_full_size(ctx):
             seen.update(np.unique(want["decision"]).tolist())
     assert checked == len(idx)
     assert {0, 1, 2} <= seen
+
+
+def test_serving_full_size(ctx):
+    """The serving workload: 10,000 queries against the dense index, candidate
+    counts 10^U(3,6) (about 1.4e9 candidates), t = 0.8, k = 32, all submitted
+    at once to a server with a 2 GiB admission budget, 128 active requests and
+    2^23-candidate batches.  For a stratified sample of 2^20 candidates: in its
+    request's accepted list iff the oracle emits S_hat for it, with the same
+    value to 1e-6."""
+    print("full size: serving, 10000 queries", flush=True)
+    t, eps, delta, gamma = 0.8, 0.03, 0.05, 0.03
+    mix, S, sig_om = _dense_index(ctx)
+    n_obj = mix.x.shape[0]
+    nq = 10000
+    rng = np.random.default_rng(G.SEED_BASE + 6)
+    queries = rng.integers(0, n_obj, nq).astype(np.uint32)
+    q, off, cand = G.member_lists(nq, n_obj, 3, 6, _related(mix.comp), seed=G.SEED_BASE + 61, queries=queries)
+    total = int(off[-1])
+    assert total > 1_000_000_000
+    idx = _sample(total, 1 << 20, 4104)
+    req = np.searchsorted(off, idx, side="right") - 1
+    bounds = np.searchsorted(req, np.arange(nq + 1))
+    got_acc = np.zeros(len(idx), bool)
+    got_val = np.full(len(idx), np.nan, np.float32)
+    srv = P.Server(ctx, S, mem_budget_bytes=2 << 30, max_active=128, k=32, max_batch_candidates=1 << 23)
+    try:
+        ids = [srv.submit(int(q[i]), cand[off[i]:off[i + 1]], t) for i in range(nq)]
+        for i, rid in enumerate(ids):
+            r = srv.wait(rid)
+            assert r["status"] == 0 and r["n_candidates"] == off[i + 1] - off[i]
+            srv.release(rid)
+            acc = r["acc_idx"]
+            assert np.all(np.diff(acc) > 0) and (len(acc) == 0 or acc[-1] < r["n_candidates"])
+            lo, hi = bounds[i], bounds[i + 1]
+            local = idx[lo:hi] - off[i]
+            pos = np.minimum(np.searchsorted(acc, local), max(len(acc) - 1, 0))
+            hit = (acc[pos] == local) if len(acc) else np.zeros(hi - lo, bool)
+            got_acc[lo:hi] = hit
+            got_val[lo:hi][hit] = r["acc_val"][pos[hit]]
+    finally:
+        srv.close()
+    want = R.verify(q[req], cand[idx], P.COSINE, down(sig_om).reshape(n_obj, 32), 32, 32, t, eps, delta, gamma)
+    emit = np.isfinite(want["shat"])
+    np.testing.assert_array_equal(got_acc, emit)
+    assert np.max(np.abs(got_val[emit] - want["shat"][emit]), initial=0.0) <= 1e-6
+    assert emit.any() and not emit.all()
