@@ -669,21 +669,32 @@ constexpr int kTileWords = int(sizeof(blsh_tile) / 4);   // 48: the descriptor, 
 static_assert(sizeof(blsh_tile) == 192, "tile descriptor layout");
 
 // LDS of one wave: the tile's rows (padded by 4 words so that the groups'
-// 16-byte reads of different rows spread over the banks), the listed pairs
-// (rank << 8 | position) and the tile's codes by rank.
+// 16-byte reads of different rows spread over the banks) and the listed pairs
+// (rank << 8 | position).
 template <int NW>
 struct TileLds {
   uint32_t rows[32][NW + 4];
   uint16_t list[256 + kWave];   // entries 256.. take the stores of lanes with nothing to list
-  uint8_t code[256 + kWave];    // by rank; 256.. as for list
 };
+
+// *(T *)((char *)base + off): a 32-bit byte offset from a wave-uniform base
+// (one address register per lane instead of a 64-bit sum)
+template <class T>
+__device__ inline T &at_byte(T *base, uint32_t off) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
+}
 
 // LITE (Algorithm 2): the table has no accept sets, so a listed pair is
 // pruned at some level or reaches the last one (n = h); those get the Lite
 // code and go to the wave's staging region with their ids, for k_tiles_exact.
 // The host sizes a Lite launch so that no region can fill.
+// Occupancy: a wave waits for its staging loads on every tile, and resident
+// waves cover those waits; interval tables at K >= 32 and up to 1024 bits
+// are held to 80 registers, six waves per SIMD (measured best: five and seven
+// were slower, the latter from the extra instructions of the tighter limit).
 template <int K, int NW, bool INTERVALS, bool LITE>
-__global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) void k_verify_tiles(VerifyArgs a) {
   constexpr int P2 = NW >= 16 ? NW / 8 : 1;   // lanes per listed pair
   constexpr int WPL = NW / P2;                // words per lane (4 or 8)
   constexpr int LPL = WPL * 32 / K;           // levels per lane
@@ -691,6 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
   constexpr int CPO = NW / 4;                 // 16-byte chunks per staged row
   constexpr int NCH = 32 * CPO;               // chunks per tile
   constexpr int CPL = (NCH + kWave - 1) / kWave;
+  static_assert(kWave % CPO == 0, "a lane's chunks sit at one offset within their rows");
   __shared__ TileLds<NW> lds_all[kBlock / kWave];
   TileLds<NW> &S = lds_all[threadIdx.x >> 6];
   extern __shared__ uint32_t s_acc[];         // accept bits (tables with non-interval accept sets)
@@ -703,12 +715,18 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
   // level j's tests in disagreements D (hashes that differ among the first
   // (j+1) K, so m = (j+1) K - D): prune iff D > pd[j], accept iff D <= ad[j]
   // (pd = (j+1) K - minMatches, ad = (j+1) K - min_accept; either may be -1:
-  // always prune / never accept); in LDS, read 4 levels at a time
+  // always prune / never accept); in LDS, read 4 levels at a time.  With
+  // interval accept sets a level continues iff ad < D <= pd, one unsigned
+  // test of D - lo against w (lo = ad + 1, w = pd - ad), also in LDS.
   __shared__ int4 s_pd[kMaxLevels / 4], s_ad[kMaxLevels / 4];
+  __shared__ uint4 s_lo[kMaxLevels / 4], s_w[kMaxLevels / 4];
   if (threadIdx.x < kMaxLevels) {
     const int j = threadIdx.x, n = (j + 1) * K;
-    reinterpret_cast<int *>(s_pd)[j] = j < L ? n - int(a.table[kTabMinOff + j]) : -1;
-    reinterpret_cast<int *>(s_ad)[j] = j < L ? n - int(a.table[kTabAloOff + j]) : -1;
+    const int pd = j < L ? n - int(a.table[kTabMinOff + j]) : -1, ad = j < L ? n - int(a.table[kTabAloOff + j]) : -1;
+    reinterpret_cast<int *>(s_pd)[j] = pd;
+    reinterpret_cast<int *>(s_ad)[j] = ad;
+    reinterpret_cast<uint32_t *>(s_lo)[j] = uint32_t(ad + 1);
+    reinterpret_cast<uint32_t *>(s_w)[j] = uint32_t(pd - ad);
   }
   __syncthreads();
   const bool last_lane = q == P2 - 1;         // holds level L - 1 as its level LPL - 1
@@ -744,26 +762,27 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
     if (member && idv >= a.n_obj) raise_status(a.status, BLSH_EBADID);
     // stage the rows (a missing member stages object 0's row, never read):
     // every chunk's load is issued before the first is stored
+    // (chunk lane + 64 u is chunk lane % CPO of row lane / CPO + u 64 / CPO:
+    // one address register per lane, the rest immediate offsets)
     const uint32_t idz = id == kNoObject ? 0u : id;
     uint32_t oid[CPL];
 #pragma unroll
-    for (int u = 0; u < CPL; ++u) oid[u] = uint32_t(__shfl(int(idz), min((lane + kWave * u) / CPO, 31)));
+    for (int u = 0; u < CPL; ++u)   // lanes past the last chunk read a lane they do not use
+      oid[u] = uint32_t(__builtin_amdgcn_ds_bpermute(4 * (lane / CPO) + 4 * u * (kWave / CPO), int(idz)));
+    const uint32_t *sig_l = a.sig + 4 * (lane % CPO);
     u32x4 chunk[CPL];
 #pragma unroll
-    for (int u = 0; u < CPL; ++u) {
-      const int ch = lane + kWave * u;
-      if (NCH % kWave == 0 || ch < NCH)
-        chunk[u] = *reinterpret_cast<const u32x4 *>(a.sig + uint64_t(oid[u]) * uint32_t(a.row_words) + 4 * (ch % CPO));
-    }
+    for (int u = 0; u < CPL; ++u)
+      if (NCH % kWave == 0 || lane + kWave * u < NCH)
+        chunk[u] = *reinterpret_cast<const u32x4 *>(sig_l + uint64_t(oid[u]) * uint32_t(a.row_words));
 #pragma unroll
-    for (int u = 0; u < CPL; ++u) {
-      const int ch = lane + kWave * u;
-      if (NCH % kWave == 0 || ch < NCH) *reinterpret_cast<u32x4 *>(&S.rows[ch / CPO][4 * (ch % CPO)]) = chunk[u];
-    }
-    const uint32_t xid = uint32_t(__shfl(int(id), r));
+    for (int u = 0; u < CPL; ++u)
+      if (NCH % kWave == 0 || lane + kWave * u < NCH)
+        *reinterpret_cast<u32x4 *>(&S.rows[lane / CPO + u * (kWave / CPO)][4 * (lane % CPO)]) = chunk[u];
+    const uint32_t xid = uint32_t(__builtin_amdgcn_ds_bpermute(4 * r, int(id)));
     uint32_t yid[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) yid[i] = uint32_t(__shfl(int(id), cc + i));
+    for (int i = 0; i < 4; ++i) yid[i] = uint32_t(__builtin_amdgcn_ds_bpermute(4 * cc + 4 * i, int(id)));
     // ranks: kept positions in lower lanes (all slots), then this lane's lower slots
     int below = 0, count = 0;
 #pragma unroll
@@ -779,8 +798,10 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
     }
     // levels 0 and 1 for this lane's four positions (2K <= 128 hashes: the
     // first 4 words of each row, one LDS read): a pair pruned at level 0, or
-    // at level 1 without level 0 having accepted it, is decided here; the rest
-    // is listed.  Codes go to LDS by rank.
+    // at level 1 without level 0 having accepted it, is decided here and its
+    // code written; the rest is listed and written once decided.  The tile's
+    // candidates are the run [first, first + count), by rank.
+    uint8_t *const cb = a.code + first;
     const u32x4 xw = *reinterpret_cast<const u32x4 *>(&S.rows[r][0]);
     uint32_t surv = 0, mm[4];
     bool malformed = false;
@@ -806,7 +827,8 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
       const bool acc0 = INTERVALS ? int(K - m0) <= ad0 : ((s_acc[m0 >> 5] >> (m0 & 31)) & 1u) != 0;
       const bool p1 = s0 && !acc0 && m0 + m1 < min1;
       mm[i] = p1 ? m0 + m1 : m0;
-      S.code[kept ? rk : 256 + lane] = ok ? uint8_t((BLSH_PRUNED << 6) | (p1 ? 1 : 0)) : uint8_t(0xFF);   // survivors: set later
+      if (kept && !(s0 && !p1))
+        at_byte(cb, uint32_t(rk)) = ok ? uint8_t((BLSH_PRUNED << 6) | (p1 ? 1 : 0)) : uint8_t(0xFF);
       malformed |= kept && !ok && (r >= n_rows || cc - 16 + i >= n_cols);   // a position past the tile's members
       surv |= uint32_t(s0 && !p1) << i;
     }
@@ -859,19 +881,21 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
       }
       const int pre = int(group_excl_scan<P2>(acc));
       // the first deciding level of this lane (scanned from the last, so the
-      // earliest wins): key = level << 20 | D.  With interval accept sets a
-      // level continues iff ad < D <= pd, one unsigned test of D - (ad + 1)
-      // against pd - ad; the decision itself is read off (j, D) afterwards.
+      // earliest wins): key = level << 20 | D; the decision itself is read
+      // off (j, D) afterwards.
       uint32_t key = 0xFFFFFFFFu;
       if constexpr (INTERVALS) {
+        // this lane's bounds, read on every step rather than held in registers
+        // through the tile (the opaque index keeps the reads in the loop):
+        // fewer live registers, more resident waves
+        int bi = q * LPL / 4;
+        asm volatile("" : "+v"(bi));
         uint32_t lo[LPL], w[LPL];
 #pragma unroll
         for (int i4 = 0; i4 < LPL; i4 += 4) {
-          const int4 vp = s_pd[(q * LPL + i4) / 4], va = s_ad[(q * LPL + i4) / 4];
-          lo[i4] = uint32_t(va.x + 1); lo[i4 + 1] = uint32_t(va.y + 1);
-          lo[i4 + 2] = uint32_t(va.z + 1); lo[i4 + 3] = uint32_t(va.w + 1);
-          w[i4] = uint32_t(vp.x - va.x); w[i4 + 1] = uint32_t(vp.y - va.y);
-          w[i4 + 2] = uint32_t(vp.z - va.z); w[i4 + 3] = uint32_t(vp.w - va.w);
+          const uint4 vl = s_lo[bi + i4 / 4], vw = s_w[bi + i4 / 4];
+          lo[i4] = vl.x; lo[i4 + 1] = vl.y; lo[i4 + 2] = vl.z; lo[i4 + 3] = vl.w;
+          w[i4] = vw.x; w[i4 + 1] = vw.y; w[i4 + 2] = vw.z; w[i4 + 3] = vw.w;
         }
         const uint32_t kb0 = uint32_t(q * LPL) << 20;
 #pragma unroll
@@ -900,7 +924,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
       else dec = LITE ? BLSH_LITE_EXACT : BLSH_ACCEPT_NMAX;
       const bool lead = act && q == 0;
       if (lead) {
-        S.code[rk] = uint8_t((dec << 6) | j);
+        at_byte(cb, uint32_t(rk)) = uint8_t((dec << 6) | j);
         if (a.m_dbg) a.m_dbg[first + rk] = uint16_t(m);
       }
       const bool emit = lead && dec != BLSH_PRUNED;
@@ -928,13 +952,6 @@ __global__ __launch_bounds__(kBlock) void k_verify_tiles(VerifyArgs a) {
         }
       }
       w_cnt += __popcll(em);
-    }
-    wave_lds_sync();
-    // the tile's codes as one run of candidates [first, first + count), count <= 256
-#pragma unroll
-    for (int u = 0; u < 256 / kWave; ++u) {
-      const int i = lane + kWave * u;
-      if (i < count) a.code[first + i] = S.code[i];
     }
     wave_lds_sync();   // the next tile's staging overwrites these rows and lists
   }
