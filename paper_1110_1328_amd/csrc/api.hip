@@ -404,6 +404,8 @@ static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, i
                                                                           cand->n_cand);
   int64_t st_cap = std::max<int64_t>(1, stage / waves);   // entries per wave region
   int64_t chunk = kTilesChunk;
+  if (lite && ctx->tuning.acc_stage_cap <= 0)   // room for every position of the call's tiles, if it fits
+    st_cap = std::min<int64_t>(kTilesStageLite / waves, 256 * ((cand->n_tiles + waves - 1) / waves));
   if (lite) {
     st_cap = std::max<int64_t>(256, st_cap / 256 * 256);
     chunk = std::min<int64_t>(kTilesChunk, waves * (st_cap / 256));
