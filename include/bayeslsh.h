@@ -354,8 +354,8 @@ int bayeslsh_srp_sigs(blsh_ctx *ctx, const blsh_vectors *vecs, const float *plan
  * BLSH_EINVAL): OBJECT_MAJOR rows, 16-byte aligned, of a multiple of 128
  * hashes, n_max a multiple of 128 up to 2048; tiles may come in any order of
  * their numbering.  Lite over tiles stages every position of a launch's tiles
- * for the exact similarity: up to 20 bytes of workspace per candidate, at
- * most 2.7 GB (longer calls run as several launches).  A wave takes a
+ * for the exact similarity: 20 bytes of workspace per tile position (5 KiB
+ * per tile), at most 2.7 GB (longer calls run as several launches).  A wave takes a
  * tile: it stages the first n_max hashes of its 32 members in LDS (one load
  * per 128-byte line), decides level 0 for the tile's pairs and finishes the
  * pairs level 0 does not prune from those rows.  Malformed tiles are reported
