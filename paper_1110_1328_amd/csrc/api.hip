@@ -423,6 +423,10 @@ static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, i
   int64_t *off = reinterpret_cast<int64_t *>(p + idx_bytes + val_bytes + xy_bytes + cnt_bytes);
   a.tiles = cand->tiles;
   a.n_cand = cand->n_cand;
+  {
+    const uint64_t bytes = uint64_t(a.n_obj) * uint64_t(a.row_words) * 4u;
+    a.sig_buf_bytes = a.n_obj <= (int64_t(1) << 24) && bytes < (uint64_t(1) << 32) ? uint32_t(bytes) : 0u;
+  }
   a.c_begin = 0;
   a.pfx = nullptr;
   a.st_raw = lite ? 0 : 1;

@@ -85,6 +85,10 @@ struct VerifyArgs {
   uint32_t *wst_cnt;
   // tiles path, Lite: the staged pairs' ids (x, y) beside st_idx
   uint2 *st_xy;
+  // tiles path: the signature array's size in bytes when a row's offset fits
+  // 32 bits through a 24-bit multiply (n_obj <= 2^24, size < 2^32): the rows
+  // are then read as a buffer with 32-bit offsets; else 0
+  uint32_t sig_buf_bytes;
 };
 
 __device__ inline int lane_id() { return __lane_id(); }

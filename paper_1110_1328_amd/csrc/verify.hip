@@ -739,6 +739,10 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
                      __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
   const int64_t n_waves = int64_t(gridDim.x) * (kBlock / kWave);
   const uint32_t *tdw = reinterpret_cast<const uint32_t *>(a.tiles);
+  // the signature rows as a buffer (gfx9 raw buffer, 32-bit data format word);
+  // offsets past its size read zeros
+  const __amdgpu_buffer_rsrc_t sig_rsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(a.sig), 0, int(a.sig_buf_bytes), 0x00020000);
   const int r = lane >> 2, cc = 16 + 4 * (lane & 3);   // level 0: row r, staged rows cc .. cc+3
   // this wave's staging region: accepted pairs (candidate index, raw
   // m | n << 16) in order; past its end, the caller's list directly
@@ -769,12 +773,22 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
 #pragma unroll
     for (int u = 0; u < CPL; ++u)   // lanes past the last chunk read a lane they do not use
       oid[u] = uint32_t(__builtin_amdgcn_ds_bpermute(4 * (lane / CPO) + 4 * u * (kWave / CPO), int(idz)));
-    const uint32_t *sig_l = a.sig + 4 * (lane % CPO);
     u32x4 chunk[CPL];
+    if (a.sig_buf_bytes) {   // wave-uniform: one 24-bit multiply-add per chunk
+      const uint32_t row_bytes = uint32_t(a.row_words) * 4u, lane_off = 16u * uint32_t(lane % CPO);
 #pragma unroll
-    for (int u = 0; u < CPL; ++u)
-      if (NCH % kWave == 0 || lane + kWave * u < NCH)
-        chunk[u] = *reinterpret_cast<const u32x4 *>(sig_l + uint64_t(oid[u]) * uint32_t(a.row_words));
+      for (int u = 0; u < CPL; ++u)
+        if (NCH % kWave == 0 || lane + kWave * u < NCH) {
+          const auto v = __builtin_amdgcn_raw_buffer_load_b128(sig_rsrc, __umul24(oid[u], row_bytes) + lane_off, 0, 0);
+          chunk[u] = u32x4{v[0], v[1], v[2], v[3]};
+        }
+    } else {
+      const uint32_t *sig_l = a.sig + 4 * (lane % CPO);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (NCH % kWave == 0 || lane + kWave * u < NCH)
+          chunk[u] = *reinterpret_cast<const u32x4 *>(sig_l + uint64_t(oid[u]) * uint32_t(a.row_words));
+    }
 #pragma unroll
     for (int u = 0; u < CPL; ++u)
       if (NCH % kWave == 0 || lane + kWave * u < NCH)

@@ -244,6 +244,58 @@ def test_tiles_numbered_past_two_to_the_31_and_32(ctx, order):
     assert int((res.code == 0xEE).sum().item()) == n_cand - len(idx)   # nothing else written
 
 
+
+def test_tiles_member_ids_past_two_to_the_24(ctx):
+    """An index of 2^24 + 300 objects (128-bit rows): the tile kernel reads
+    rows through 32-bit buffer offsets only while n_obj <= 2^24 and the rows
+    fit 4 GiB, else through 64-bit addresses.  Tiles mixing members below and
+    above 2^24 take the second way; the same tiles over an index of the low
+    objects only take the first; both equal the oracle."""
+    rng = np.random.default_rng(12)
+    n_small, n_max, k = 600, 128, 32
+    sig = G.pack_bits(G.calibration_bits(n_small // 2, n_max, rng.uniform(0.6, 1.0, n_small // 2), 121))
+    lo, hi = np.arange(300), np.arange(300, 600)
+    big = (1 << 24) + 300
+    ids = np.concatenate([lo, hi - 300 + (1 << 24)]).astype(np.uint32)   # object i of sig at ids[i]
+    words = torch.zeros(big * 4, dtype=torch.int32, device="cuda")
+    words.view(big, 4)[torch.from_numpy(ids.astype(np.int64)).cuda()] = torch.from_numpy(sig.view(np.int32)).cuda()
+    S_big = P.Signatures(words.view(torch.uint32), P.COSINE, P.OBJECT_MAJOR, big, n_max)
+    tiles, xs, ys, first = [], [], [], 0
+    for _ in range(40):
+        rows = rng.choice(n_small, 16, replace=False)
+        cols = rng.choice(n_small, 16, replace=False)
+        pos = [q for q in range(256) if rng.random() < 0.8]
+        tiles.append(_tile(first, ids[rows], ids[cols], pos))
+        xs += [rows[q // 16] for q in pos]
+        ys += [cols[q % 16] for q in pos]
+        first += len(pos)
+    x, y = np.array(xs, np.uint32), np.array(ys, np.uint32)
+    want = R.verify(x, y, P.COSINE, sig, k, n_max // k, 0.7, EPS, DELTA, GAMMA)
+    res = P.make_result(first, first, m_debug=True)
+    P.bayeslsh_verify(ctx, P.tiles(up(np.stack(tiles).reshape(-1)), len(tiles), first), S_big, 0.7, EPS, DELTA,
+                      GAMMA, (1, 1), k, res)
+    P.bayeslsh_sync(ctx)
+    assert_same_as_oracle(decode_result(res, first), want)
+    # the low half alone, as an index of 300 objects (buffer offsets)
+    low_tiles, lx, ly, first = [], [], [], 0
+    for _ in range(40):
+        rows = rng.choice(300, 16, replace=False)
+        cols = rng.choice(300, 16, replace=False)
+        pos = [q for q in range(256) if rng.random() < 0.8]
+        low_tiles.append(_tile(first, ids[rows], ids[cols], pos))
+        lx += [rows[q // 16] for q in pos]
+        ly += [cols[q % 16] for q in pos]
+        first += len(pos)
+    S_low = sigs_tensor(sig[:300], P.COSINE, P.OBJECT_MAJOR)
+    want = R.verify(np.array(lx, np.uint32), np.array(ly, np.uint32), P.COSINE, sig, k, n_max // k, 0.7, EPS, DELTA,
+                    GAMMA)
+    res = P.make_result(first, first, m_debug=True)
+    P.bayeslsh_verify(ctx, P.tiles(up(np.stack(low_tiles).reshape(-1)), len(low_tiles), first), S_low, 0.7, EPS,
+                      DELTA, GAMMA, (1, 1), k, res)
+    P.bayeslsh_sync(ctx)
+    assert_same_as_oracle(decode_result(res, first), want)
+    del words
+
 def test_tiles_rejected_where_unsupported(ctx, mix, banded):
     band = banded[0]
     tl, nt, npairs = band_tiles(ctx, sigs_tensor(band, P.COSINE, P.OBJECT_MAJOR), 16, 6)
