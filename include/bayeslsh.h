@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define BAYESLSH_VERSION 3
+#define BAYESLSH_VERSION 4
 
 typedef enum {
   BLSH_OK = 0,
@@ -247,7 +247,10 @@ int bayeslsh_profile_read(blsh_ctx *ctx, const char *name_substr, double *total_
  *           goes to the list directly (same output, slower).
  *   last_batch_*: set by the library after each batched call (the autotuned
  *           or given k of each measure, tile shapes, in-register levels and
- *           blocks per CU); ignored by bayeslsh_set_tuning. */
+ *           blocks per CU); ignored by bayeslsh_set_tuning.
+ *   tiles_per_launch: BLSH_TILES calls run as launches of at most this many
+ *           tiles (0 = 2^22; 1 .. 2^22), each followed by the copy of its
+ *           staged accepted pairs to the caller's list; same output. */
 typedef struct {
   int32_t gather;
   int32_t batch_inreg;
@@ -263,6 +266,7 @@ typedef struct {
   int32_t last_batch_srp_tile;
   int32_t last_batch_mh_tile;
   int32_t tiles_accept_bitmask;   /* 0 or 1 */
+  int32_t tiles_per_launch;       /* 0 = 2^22 */
 } blsh_tuning;
 int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *tuning_host);
 int bayeslsh_get_tuning(blsh_ctx *ctx, blsh_tuning *tuning_host);

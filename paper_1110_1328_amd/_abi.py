@@ -64,7 +64,7 @@ class Tuning(C.Structure):
                 ("last_batch_k_cosine", C.c_int32), ("acc_stage_cap", C.c_int32),
                 ("batch_srp_tile", C.c_int32), ("batch_mh_tile", C.c_int32),
                 ("last_batch_srp_tile", C.c_int32), ("last_batch_mh_tile", C.c_int32),
-                ("tiles_accept_bitmask", C.c_int32)]
+                ("tiles_accept_bitmask", C.c_int32), ("tiles_per_launch", C.c_int32)]
 
 
 class ListDesc(C.Structure):

@@ -303,12 +303,13 @@ def bayeslsh_profile_read(ctx: Context, name: str):
 
 def bayeslsh_set_tuning(ctx: Context, gather: int = 0, batch_inreg: int = 0, batch_blocks_per_cu: int = 0,
                         batch_spill_cap: int = 0, acc_stage_cap: int = 0, batch_srp_tile: int = 0,
-                        batch_mh_tile: int = 0, tiles_accept_bitmask: int = 0):
+                        batch_mh_tile: int = 0, tiles_accept_bitmask: int = 0, tiles_per_launch: int = 0):
     t = A.Tuning()
     t.gather, t.batch_inreg, t.batch_blocks_per_cu, t.batch_spill_cap = gather, batch_inreg, batch_blocks_per_cu, batch_spill_cap
     t.acc_stage_cap = acc_stage_cap
     t.batch_srp_tile, t.batch_mh_tile = batch_srp_tile, batch_mh_tile
     t.tiles_accept_bitmask = tiles_accept_bitmask
+    t.tiles_per_launch = tiles_per_launch
     _check(_lib().bayeslsh_set_tuning(ctx.handle, C.byref(t)))
 
 

@@ -403,12 +403,12 @@ static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, i
                                                       : std::min<int64_t>(lite ? kTilesStageLite : kTilesStage,
                                                                           cand->n_cand);
   int64_t st_cap = std::max<int64_t>(1, stage / waves);   // entries per wave region
-  int64_t chunk = kTilesChunk;
+  int64_t chunk = ctx->tuning.tiles_per_launch > 0 ? int64_t(ctx->tuning.tiles_per_launch) : kTilesChunk;
   if (lite && ctx->tuning.acc_stage_cap <= 0)   // room for every position of the call's tiles, if it fits
     st_cap = std::min<int64_t>(kTilesStageLite / waves, 256 * ((cand->n_tiles + waves - 1) / waves));
   if (lite) {
     st_cap = std::max<int64_t>(256, st_cap / 256 * 256);
-    chunk = std::min<int64_t>(kTilesChunk, waves * (st_cap / 256));
+    chunk = std::min<int64_t>(chunk, waves * (st_cap / 256));
   }
   const size_t idx_bytes = align256(size_t(waves) * st_cap * 8), val_bytes = align256(size_t(waves) * st_cap * 4);
   const size_t xy_bytes = lite ? align256(size_t(waves) * st_cap * 8) : 0;
@@ -744,6 +744,8 @@ int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
     return fail(BLSH_EINVAL, "tuning.batch_mh_tile must be 0, 64 or 128");
   if (t->tiles_accept_bitmask < 0 || t->tiles_accept_bitmask > 1)
     return fail(BLSH_EINVAL, "tuning.tiles_accept_bitmask must be 0 or 1");
+  if (t->tiles_per_launch < 0 || t->tiles_per_launch > kTilesChunk)
+    return fail(BLSH_EINVAL, "tuning.tiles_per_launch must be in [0, 2^22]");
   ctx->tuning.gather = t->gather;
   ctx->tuning.acc_stage_cap = t->acc_stage_cap;
   ctx->tuning.batch_spill_cap = t->batch_spill_cap;
@@ -752,6 +754,7 @@ int bayeslsh_set_tuning(blsh_ctx *ctx, const blsh_tuning *t) {
   ctx->tuning.batch_srp_tile = t->batch_srp_tile;
   ctx->tuning.batch_mh_tile = t->batch_mh_tile;
   ctx->tuning.tiles_accept_bitmask = t->tiles_accept_bitmask;
+  ctx->tuning.tiles_per_launch = t->tiles_per_launch;
   return BLSH_OK;
 }
 

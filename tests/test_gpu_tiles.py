@@ -194,6 +194,50 @@ def test_tiles_by_hand_and_malformed(ctx):
     assert int(r.n_accepted.item()) == 0
 
 
+
+@pytest.mark.parametrize("per_launch,stage_cap", [(97, 0), (1000, 0), (97, 64)])
+def test_tiles_many_launches(ctx, per_launch, stage_cap):
+    """A call cut into many launches (tiles_per_launch), each launch's staged
+    accepted pairs appended to the caller's list after it; with a tiny staging
+    most pairs go to the list directly from the tile kernel.  Same codes, m
+    and accepted list as one launch, and as the oracle."""
+    rng = np.random.default_rng(13)
+    n_obj, n_max, k = 500, 256, 32
+    sig = G.pack_bits(G.calibration_bits(n_obj // 2, n_max, rng.uniform(0.6, 1.0, n_obj // 2), 131))
+    tiles, xs, ys, first = [], [], [], 0
+    for _ in range(6000):
+        nr, nc = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+        rows = rng.integers(0, n_obj, nr).astype(np.uint32)
+        cols = rng.integers(0, n_obj, nc).astype(np.uint32)
+        pos = sorted(int(16 * r + c) for r in range(nr) for c in range(nc) if rng.random() < 0.7)
+        if not pos:
+            continue
+        tiles.append(_tile(first, rows, cols, pos))
+        xs += [rows[q // 16] for q in pos]
+        ys += [cols[q % 16] for q in pos]
+        first += len(pos)
+    x, y = np.array(xs, np.uint32), np.array(ys, np.uint32)
+    S = sigs_tensor(sig, P.COSINE, P.OBJECT_MAJOR)
+    want = R.verify(x, y, P.COSINE, sig, k, n_max // k, 0.7, EPS, DELTA, GAMMA)
+    cand = P.tiles(up(np.stack(tiles).reshape(-1)), len(tiles), first)
+    one = P.make_result(first, first, m_debug=True)
+    P.bayeslsh_verify(ctx, cand, S, 0.7, EPS, DELTA, GAMMA, (1, 1), k, one)
+    P.bayeslsh_sync(ctx)
+    P.bayeslsh_set_tuning(ctx, tiles_per_launch=per_launch, acc_stage_cap=stage_cap)
+    try:
+        for _ in range(2):   # twice: the second call reuses the staging
+            res = P.make_result(first, first, m_debug=True)
+            P.bayeslsh_verify(ctx, cand, S, 0.7, EPS, DELTA, GAMMA, (1, 1), k, res)
+            P.bayeslsh_sync(ctx)
+            got = decode_result(res, first)
+            assert_same_as_oracle(got, want)
+            ref = decode_result(one, first)
+            np.testing.assert_array_equal(got["code"], ref["code"])
+            np.testing.assert_array_equal(got["m"], ref["m"])
+            np.testing.assert_array_equal(got["acc_val"], ref["acc_val"])
+    finally:
+        P.bayeslsh_set_tuning(ctx)
+
 @pytest.mark.parametrize("order", ["ascending", "descending", "shuffled"])
 def test_tiles_numbered_past_two_to_the_31_and_32(ctx, order):
     """Tiles whose candidates are numbered beyond 2^31 and 2^32 (a result of
@@ -348,6 +392,18 @@ def test_tiles_lite_matches_oracle(ctx, mix, banded, k, h, t):
     np.testing.assert_array_equal(got["code"], gp["code"])
     np.testing.assert_array_equal(got["acc_idx"], gp["acc_idx"])
     np.testing.assert_array_equal(got["acc_val"], gp["acc_val"])
+    # the same call in launches of 7 tiles
+    P.bayeslsh_set_tuning(ctx, tiles_per_launch=7)
+    try:
+        res_m = P.make_result(npairs, npairs, m_debug=True)
+        P.bayeslsh_lite_verify(ctx, P.tiles(tl, nt, npairs), S, vec, t, EPS, (1, 1), h, k, res_m)
+        P.bayeslsh_sync(ctx)
+    finally:
+        P.bayeslsh_set_tuning(ctx)
+    assert nt > 14
+    gm = decode_result(res_m, npairs)
+    for key in ("code", "m", "acc_idx", "acc_val"):
+        np.testing.assert_array_equal(gm[key], got[key])
 
 
 @pytest.mark.parametrize("k", [32, 64])

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, name), name
     # and the binding declares a prototype for each
     assert sorted(n for n, _, _ in _abi.PROTOTYPES) == declared
-    assert lib.bayeslsh_version() == 3
+    assert lib.bayeslsh_version() == 4
 
 
 TABLE_CASES = [
