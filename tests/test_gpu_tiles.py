@@ -238,6 +238,17 @@ def test_tiles_many_launches(ctx, per_launch, stage_cap):
     finally:
         P.bayeslsh_set_tuning(ctx)
 
+
+def test_tiles_per_launch_rejected_out_of_range(ctx):
+    for v in (-1, (1 << 22) + 1):
+        with pytest.raises(P.BayesLSHError) as e:
+            P.bayeslsh_set_tuning(ctx, tiles_per_launch=v)
+        assert e.value.code == -1
+    P.bayeslsh_set_tuning(ctx, tiles_per_launch=1 << 22)
+    assert P.bayeslsh_get_tuning(ctx)["tiles_per_launch"] == 1 << 22
+    P.bayeslsh_set_tuning(ctx)
+
+
 @pytest.mark.parametrize("order", ["ascending", "descending", "shuffled"])
 def test_tiles_numbered_past_two_to_the_31_and_32(ctx, order):
     """Tiles whose candidates are numbered beyond 2^31 and 2^32 (a result of
