@@ -684,6 +684,18 @@ __device__ inline T &at_byte(T *base, uint32_t off) {
   return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
 }
 
+// A field of the kernel's VerifyArgs argument (its first, at offset 0 of
+// the kernel-argument segment) read where it is used, not held in scalar
+// registers through the kernel: for the fields of rare paths (bad ids, the
+// debug array, a full staging region) in a kernel at the scalar register
+// limit, whose spilled scalars would otherwise be reloaded on every tile.
+template <class T>
+__device__ inline T arg_on_use(size_t off) {
+  const auto *kp = (const char __attribute__((address_space(4))) *)__builtin_amdgcn_kernarg_segment_ptr();
+  return *reinterpret_cast<const volatile T __attribute__((address_space(4))) *>(kp + off);
+}
+#define BLSH_ARG_ON_USE(f) arg_on_use<decltype(VerifyArgs::f)>(offsetof(VerifyArgs, f))
+
 // LITE (Algorithm 2): the table has no accept sets, so a listed pair is
 // pruned at some level or reaches the last one (n = h); those get the Lite
 // code and go to the wave's staging region with their ids, for k_tiles_exact.
@@ -763,7 +775,7 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
     const uint32_t kb = (uint32_t(__shfl(int(dw), 4 + (lane >> 3))) >> (4 * (lane & 7))) & 0xFu;
     const bool member = lane < 32 && (lane & 15) < (lane < 16 ? n_rows : n_cols);
     const uint32_t id = member && idv < a.n_obj ? idv : kNoObject;
-    if (member && idv >= a.n_obj) raise_status(a.status, BLSH_EBADID);
+    if (member && idv >= a.n_obj) raise_status(BLSH_ARG_ON_USE(status), BLSH_EBADID);
     // stage the rows (a missing member stages object 0's row, never read):
     // every chunk's load is issued before the first is stored
     // (chunk lane + 64 u is chunk lane % CPO of row lane / CPO + u 64 / CPO:
@@ -807,7 +819,7 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
     }
     wave_lds_sync();
     if (first < 0 || first + count > a.n_cand) {   // numbering outside the call's candidates: the tile is skipped
-      if (lane == 0) raise_status(a.status, BLSH_EINVAL);
+      if (lane == 0) raise_status(BLSH_ARG_ON_USE(status), BLSH_EINVAL);
       continue;
     }
     // levels 0 and 1 for this lane's four positions (2K <= 128 hashes: the
@@ -846,11 +858,11 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
       malformed |= kept && !ok && (r >= n_rows || cc - 16 + i >= n_cols);   // a position past the tile's members
       surv |= uint32_t(s0 && !p1) << i;
     }
-    if (malformed) raise_status(a.status, BLSH_EINVAL);
-    if (a.m_dbg) {   // m of the pairs level 0 decides (survivors: after their last level)
+    if (malformed) raise_status(BLSH_ARG_ON_USE(status), BLSH_EINVAL);
+    if (uint16_t *const m_dbg = BLSH_ARG_ON_USE(m_dbg)) {   // m of the pairs level 0 decides (survivors: after their last level)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        if ((kb >> i) & 1u) a.m_dbg[first + below + __popc(kb & ((1u << i) - 1u))] = uint16_t(mm[i]);
+        if ((kb >> i) & 1u) m_dbg[first + below + __popc(kb & ((1u << i) - 1u))] = uint16_t(mm[i]);
     }
     // the surviving positions (rank << 8 | position), in position order
     int at = 0, total = 0;
@@ -939,7 +951,7 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
       const bool lead = act && q == 0;
       if (lead) {
         at_byte(cb, uint32_t(rk)) = uint8_t((dec << 6) | j);
-        if (a.m_dbg) a.m_dbg[first + rk] = uint16_t(m);
+        if (uint16_t *const m_dbg = BLSH_ARG_ON_USE(m_dbg)) m_dbg[first + rk] = uint16_t(m);
       }
       const bool emit = lead && dec != BLSH_PRUNED;
       const uint64_t em = __ballot(emit);
@@ -951,7 +963,7 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
           w_idx[pos] = uint64_t(first + rk);
           a.st_xy[size_t(gw) * a.st_cap + pos] = make_uint2(ix, iy);
         } else if (emit) {
-          raise_status(a.status, BLSH_EINVAL);
+          raise_status(BLSH_ARG_ON_USE(status), BLSH_EINVAL);
         }
       } else {
         // S_hat is computed from (m, n) when the staging is flushed
@@ -961,8 +973,15 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
           w_val[pos] = __uint_as_float(uint32_t(m) | (uint32_t((j + 1) * K) << 16));
         }
         if (__ballot(over)) {   // the region is full: S_hat here, into the caller's list
-          const float sv = over ? map_estimate(a.measure, m, (j + 1) * K, tab_f64(a.table, 4), tab_f64(a.table, 6)) : 0.f;
-          emit_direct(a, over, uint64_t(first + rk), sv);
+          VerifyArgs r{};   // the fields emit_direct reads, read here
+          r.acc_idx = BLSH_ARG_ON_USE(acc_idx);
+          r.acc_val = BLSH_ARG_ON_USE(acc_val);
+          r.acc_cap = BLSH_ARG_ON_USE(acc_cap);
+          r.acc_total = BLSH_ARG_ON_USE(acc_total);
+          r.status = BLSH_ARG_ON_USE(status);
+          const uint32_t *tab = BLSH_ARG_ON_USE(table);
+          const float sv = over ? map_estimate(BLSH_ARG_ON_USE(measure), m, (j + 1) * K, tab_f64(tab, 4), tab_f64(tab, 6)) : 0.f;
+          emit_direct(r, over, uint64_t(first + rk), sv);
         }
       }
       w_cnt += __popcll(em);
