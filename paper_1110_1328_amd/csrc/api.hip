@@ -389,6 +389,10 @@ static void fill_exact(VerifyArgs &a, const blsh_vectors *v) {
 static constexpr int64_t kTilesChunk = int64_t(1) << 22;
 static constexpr int64_t kTilesStage = int64_t(1) << 27;
 static constexpr int64_t kTilesStageLite = int64_t(1) << 27;   // 20 B per entry
+// (the tile kernel addresses a launch's descriptors and a wave's staging
+// region with 32-bit byte offsets)
+static_assert(kTilesChunk * int64_t(sizeof(blsh_tile)) < (int64_t(1) << 31), "descriptor offsets");
+static_assert(kTilesStage < (int64_t(1) << 29) && kTilesStageLite < (int64_t(1) << 29), "staging offsets");
 
 static int run_tiles(blsh_ctx *ctx, const blsh_candidates *cand, VerifyArgs a, int k, int n_max, int n_levels,
                      bool intervals, bool lite, hipStream_t s) {

@@ -747,10 +747,14 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
   // level 0's accept test: ad0 = K - min_accept of level 0
   const uint32_t min1 = L > 1 ? a.table[kTabMinOff + 1] : 0u;
   const int ad0 = reinterpret_cast<const int *>(s_ad)[0];
-  const int64_t gw = xcd_tile(blockIdx.x, gridDim.x) * (kBlock / kWave) +
-                     __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
-  const int64_t n_waves = int64_t(gridDim.x) * (kBlock / kWave);
-  const uint32_t *tdw = reinterpret_cast<const uint32_t *>(a.tiles);
+  const int gw = int(xcd_tile(blockIdx.x, gridDim.x)) * (kBlock / kWave) +
+                 __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+  const int n_waves = int(gridDim.x) * (kBlock / kWave);
+  // the launch's tiles (at most 2^22, numbered from t_begin) as a buffer of
+  // 192-byte descriptors: 32-bit offsets, one dword per lane
+  const int n_t = int(a.t_end - a.t_begin);
+  const __amdgpu_buffer_rsrc_t tile_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<blsh_tile *>(a.tiles + a.t_begin), 0, n_t * int(sizeof(blsh_tile)), 0x00020000);
   // the signature rows as a buffer (gfx9 raw buffer, 32-bit data format word);
   // offsets past its size read zeros
   const __amdgpu_buffer_rsrc_t sig_rsrc =
@@ -758,15 +762,21 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
   const int r = lane >> 2, cc = 16 + 4 * (lane & 3);   // level 0: row r, staged rows cc .. cc+3
   // this wave's staging region: accepted pairs (candidate index, raw
   // m | n << 16) in order; past its end, the caller's list directly
+  // (a region holds fewer than 2^29 entries: 32-bit counts and byte offsets)
   uint64_t *w_idx = a.st_idx + size_t(gw) * a.st_cap;
   float *w_val = a.st_val + size_t(gw) * a.st_cap;
-  int64_t w_cnt = 0;   // wave-uniform
+  uint2 *w_xy = LITE ? a.st_xy + size_t(gw) * a.st_cap : nullptr;
+  const uint32_t st_cap = uint32_t(a.st_cap);
+  uint32_t w_cnt = 0;   // wave-uniform
   // the descriptor, one dword per lane, loaded one tile ahead
   uint32_t nd = 0;
-  if (a.t_begin + gw < a.t_end && lane < kTileWords) nd = tdw[size_t(a.t_begin + gw) * kTileWords + lane];
-  for (int64_t t = a.t_begin + gw; t < a.t_end; t += n_waves) {   // wave-uniform
+  if (gw < n_t && lane < kTileWords)
+    nd = __builtin_amdgcn_raw_buffer_load_b32(tile_rsrc, 4 * lane, uint32_t(gw) * uint32_t(sizeof(blsh_tile)), 0);
+  for (int t = gw; t < n_t; t += n_waves) {   // wave-uniform
     const uint32_t dw = nd;
-    if (t + n_waves < a.t_end && lane < kTileWords) nd = tdw[size_t(t + n_waves) * kTileWords + lane];
+    if (t + n_waves < n_t && lane < kTileWords)
+      nd = __builtin_amdgcn_raw_buffer_load_b32(tile_rsrc, 4 * lane, uint32_t(t + n_waves) * uint32_t(sizeof(blsh_tile)),
+                                                0);
     const int64_t first = int64_t(uint64_t(uint32_t(__builtin_amdgcn_readlane(int(dw), 0))) |
                                   (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(dw), 1))) << 32));
     const int n_rows = __builtin_amdgcn_readlane(int(dw), 2), n_cols = __builtin_amdgcn_readlane(int(dw), 3);
@@ -955,22 +965,22 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
       }
       const bool emit = lead && dec != BLSH_PRUNED;
       const uint64_t em = __ballot(emit);
-      const int64_t pos = w_cnt + int64_t(lanes_below(em));
+      const uint32_t pos = w_cnt + lanes_below(em);
       if constexpr (LITE) {
         // the pair's ids for its exact similarity (every lane takes part in the shuffles)
         const uint32_t ix = uint32_t(__shfl(int(id), p >> 4)), iy = uint32_t(__shfl(int(id), 16 + (p & 15)));
-        if (emit && pos < a.st_cap) {   // (the host sizes the launch so that it always is)
-          w_idx[pos] = uint64_t(first + rk);
-          a.st_xy[size_t(gw) * a.st_cap + pos] = make_uint2(ix, iy);
+        if (emit && pos < st_cap) {   // (the host sizes the launch so that it always is)
+          at_byte(w_idx, pos * 8u) = uint64_t(first + rk);
+          at_byte(w_xy, pos * 8u) = make_uint2(ix, iy);
         } else if (emit) {
           raise_status(BLSH_ARG_ON_USE(status), BLSH_EINVAL);
         }
       } else {
         // S_hat is computed from (m, n) when the staging is flushed
-        const bool over = emit && pos >= a.st_cap;
+        const bool over = emit && pos >= st_cap;
         if (emit && !over) {
-          w_idx[pos] = uint64_t(first + rk);
-          w_val[pos] = __uint_as_float(uint32_t(m) | (uint32_t((j + 1) * K) << 16));
+          at_byte(w_idx, pos * 8u) = uint64_t(first + rk);
+          at_byte(w_val, pos * 4u) = __uint_as_float(uint32_t(m) | (uint32_t((j + 1) * K) << 16));
         }
         if (__ballot(over)) {   // the region is full: S_hat here, into the caller's list
           VerifyArgs r{};   // the fields emit_direct reads, read here
@@ -984,11 +994,11 @@ __attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) v
           emit_direct(r, over, uint64_t(first + rk), sv);
         }
       }
-      w_cnt += __popcll(em);
+      w_cnt += uint32_t(__popcll(em));
     }
     wave_lds_sync();   // the next tile's staging overwrites these rows and lists
   }
-  if (lane == 0) a.wst_cnt[gw] = uint32_t(min<int64_t>(w_cnt, a.st_cap));
+  if (lane == 0) a.wst_cnt[gw] = min(w_cnt, st_cap);
 }
 
 // Tiles path, after each launch: the waves' staging counts, exclusive prefix
