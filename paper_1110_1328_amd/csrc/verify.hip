@@ -702,11 +702,11 @@ __device__ inline T arg_on_use(size_t off) {
 // The host sizes a Lite launch so that no region can fill.
 // Occupancy: a wave waits for its staging loads on every tile, and resident
 // waves cover those waits; interval tables at K >= 32 and up to 1024 bits
-// are held to 80 registers, six waves per SIMD (measured best: five and seven
-// were slower, the latter from the extra instructions of the tighter limit).
+// are held to 72 registers, seven waves per SIMD (measured best; eight would
+// not fit the LDS, 4 waves' rows and lists per block).
 template <int K, int NW, bool INTERVALS, bool LITE>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 6 : 1))) void k_verify_tiles(VerifyArgs a) {
+__attribute__((amdgpu_waves_per_eu(INTERVALS && K >= 32 && NW <= 32 ? 7 : 1))) void k_verify_tiles(VerifyArgs a) {
   constexpr int P2 = NW >= 16 ? NW / 8 : 1;   // lanes per listed pair
   constexpr int WPL = NW / P2;                // words per lane (4 or 8)
   constexpr int LPL = WPL * 32 / K;           // levels per lane
