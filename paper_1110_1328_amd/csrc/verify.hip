@@ -653,14 +653,16 @@ __global__ __launch_bounds__(kBlock) void k_exact_pairs(VerifyArgs a, double *ou
 //           chunks of a row, so each 128-byte line is one load -- 32 lines per
 //           tile instead of two gathers per pair;
 //   level 0 lane l owns positions p = 4l .. 4l+3 (row l/4, columns 4(l%4) ..
-//           4(l%4)+3) and decides level 0 from the staged first words; the
-//           positions it does not prune are listed in LDS;
+//           4(l%4)+3) and decides level 0, and level 1's prune, from the
+//           staged first words, writing the codes of the pairs it decides;
+//           the positions still open are listed in LDS;
 //   rest    groups of P2 lanes take the listed pairs, each lane WPL words of
 //           both rows from LDS (128/K levels per 4 words), count agreements
 //           per level, prefix them across the group and find the first level
 //           that decides (prune below minMatches; accept at or above the
 //           minimum accepting m, or by the accept bits when a level's accept
-//           set is not an interval; n_max); the group takes the earliest.
+//           set is not an interval; n_max); the group takes the earliest,
+//           writes the pair's code and stages it if accepted.
 // Waves are persistent; the waves of an XCD sweep contiguous windows of tiles
 // together, so a bucket's rows stay in that XCD's L2 while its tiles pass.
 // ---------------------------------------------------------------------------
